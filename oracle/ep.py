@@ -1,0 +1,253 @@
+"""Plain FP64 EP for TV priors: Algorithm 1 and the fast EP-EM of Algorithm 2.
+
+TEST INFRASTRUCTURE ONLY (see oracle/__init__.py).
+
+State (Sec. III-A): five Gaussian approximating factors q_{x,k}, k = 0..4, with
+diagonal covariances, stored as natural parameters per pixel,
+tau_k = 1 / Sigma_{x,k} and eta_k = mu_{x,k} / Sigma_{x,k}.  The global
+approximation is their product (Eq. (Q_x_final)): tau = sum_k tau_k,
+eta = sum_k eta_k, mu_x = eta / tau, v_x = 1 / tau.
+
+Colour classes (Sec. II-B, Fig. 1, Eq. (prior1)), pixel (r, c), row-major,
+0-based, i = left/top pixel of the edge, j = right/bottom pixel:
+  V1: (r, c)-(r, c+1), c even;   V2: (r, c)-(r, c+1), c odd;
+  V3: (r, c)-(r+1, c), r even;   V4: (r, c)-(r+1, c), r odd.
+FREE boundary keeps only edges inside the image; PERIODIC (even sizes) adds the
+wrap edges (r, W-1)-(r, 0) to V2 and (H-1, c)-(0, c) to V4.  A pixel that no
+edge of V_k touches keeps the flat site (tau_k, eta_k) = (0, 0).
+
+One sweep t (readings of the paper's silent points are listed in the design doc):
+  1. likelihood site (Eqs. (tilted_P_1), (update_q0_x)), skipped for H = I,
+     where it is exact and constant, and in sweep 1, where the initial
+     q_{x,0} of the initialisation line stands in for it;
+  2. for k in the block order (default 1, 2, 3, 4): every edge of V_k in
+     parallel -- cavity, tilted moments of u (Eq. (marginal_tilted_un)),
+     Gehre-Jin projection back to (x_i, x_j), site update (Eq. (update_qk_x)),
+     negative-variance clamp, damping;
+  3. EM (Algorithm 2, option 3, Eq. (3rd_alternative_a0)):
+     lambda <- N / a_bar_u, a_bar_u = sum over all edges of the sweep of the
+     tilted E|u_n| at the lambda used in the sweep; N = number of pixels.
+
+Parity pins: tests/test_oracle_ep.py (l2-TV fixed point = dense posterior mean,
+exact single-edge posterior, EM fixed point = marginal-likelihood maximiser on a
+single edge, symmetry invariants, colour-class structure) and
+tests/test_oracle_brute.py (3x3 brute-force posterior marginals).
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+from typing import Optional, Sequence
+
+import numpy as np
+
+from . import operators as ops
+from .tilted import tilted
+
+SITE_INIT_PREC = 1e-8     # 1 / 1e8: initial TV-site variance 1e8
+PREC_FLOOR = 1e-8         # clamp: site variance negative or above 1e8 -> 1e8
+
+
+def colour_classes(h: int, w: int, boundary: str = "free"):
+    """Edge lists (i, j) of flat pixel indices for V1..V4 (index 0..3)."""
+    if boundary not in ("free", "periodic"):
+        raise ValueError(boundary)
+    if boundary == "periodic" and (h % 2 or w % 2):
+        raise ValueError("periodic boundary needs even image sizes")
+    idx = np.arange(h * w).reshape(h, w)
+    out = []
+    for parity in (0, 1):              # horizontal: V1 (c even), V2 (c odd)
+        i_list, j_list = [], []
+        for c in range(parity, w, 2):
+            if c + 1 < w:
+                i_list.append(idx[:, c]); j_list.append(idx[:, c + 1])
+            elif boundary == "periodic":
+                i_list.append(idx[:, c]); j_list.append(idx[:, 0])
+        out.append((np.concatenate(i_list) if i_list else np.zeros(0, int),
+                    np.concatenate(j_list) if j_list else np.zeros(0, int)))
+    for parity in (0, 1):              # vertical: V3 (r even), V4 (r odd)
+        i_list, j_list = [], []
+        for r in range(parity, h, 2):
+            if r + 1 < h:
+                i_list.append(idx[r, :]); j_list.append(idx[r + 1, :])
+            elif boundary == "periodic":
+                i_list.append(idx[r, :]); j_list.append(idx[0, :])
+        out.append((np.concatenate(i_list) if i_list else np.zeros(0, int),
+                    np.concatenate(j_list) if j_list else np.zeros(0, int)))
+    return out
+
+
+@dataclass
+class EPState:
+    tau: np.ndarray                 # (5, N)
+    eta: np.ndarray                 # (5, N)
+    lam: float                      # l1: lambda; l2: beta
+    E: Optional[np.ndarray] = None  # last tilted mean of the likelihood site (CG warm start)
+    clamp_count: int = 0
+    cg_iters: int = 0
+    history: list = field(default_factory=list)
+
+
+class EPProblem:
+    """Everything Algorithm 1 takes as input (y, H, xi, theta) plus the readings'
+    knobs: damping, boundary, block order, prior, variance estimator."""
+
+    def __init__(self, y, op: ops.Operator, xi, lam, damping=0.5, prior="l1",
+                 boundary="free", order: Sequence[int] = (1, 2, 3, 4),
+                 estimator="spectral", cg_rtol=1e-12):
+        self.op = op
+        self.h, self.w = op.shape
+        self.N = self.h * self.w
+        self.xi = float(xi)
+        self.lam0 = float(lam)
+        self.damping = float(damping)
+        self.prior = prior
+        self.boundary = boundary
+        self.order = tuple(order)
+        self.estimator = estimator
+        self.cg_rtol = cg_rtol
+        self.y = y
+        self.hty = op.Hty(y)
+        self.edges = colour_classes(self.h, self.w, boundary)
+        self.covered = np.zeros((4, self.N), dtype=bool)
+        for k in range(4):
+            i, j = self.edges[k]
+            self.covered[k, i] = True
+            self.covered[k, j] = True
+
+
+def problem_from_synthetic(p, prior="l1", estimator="spectral", boundary=None, order=(1, 2, 3, 4),
+                           lam=None, damping=None):
+    """Build an EPProblem from a synthetic.Problem."""
+    op = ops.Operator(p.op, p.shape, taps=p.taps, mask=p.mask)
+    return EPProblem(p.y, op, p.xi, p.lam0 if lam is None else lam,
+                     damping=p.damping if damping is None else damping, prior=prior,
+                     boundary=p.boundary if boundary is None else boundary, order=order,
+                     estimator=estimator)
+
+
+def init_cold(pb: EPProblem) -> EPState:
+    """Initialisation line of Algorithm 1: q_{x,0} = N(H^T y, xi I) (= N(y, xi I)
+    when y lives in pixel space), TV sites with variance 1e8 where covered."""
+    N = pb.N
+    tau = np.zeros((5, N))
+    eta = np.zeros((5, N))
+    tau[0] = 1.0 / pb.xi
+    eta[0] = (pb.hty if pb.op.kind != ops.IDENTITY else np.asarray(pb.y, dtype=np.float64)).ravel() / pb.xi
+    for k in range(4):
+        tau[k + 1, pb.covered[k]] = SITE_INIT_PREC
+    return EPState(tau=tau, eta=eta, lam=pb.lam0)
+
+
+def marginals(st: EPState):
+    """Eq. (Q_x_final): global precision/mean from the sum of all five sites."""
+    tau = st.tau.sum(axis=0)
+    eta = st.eta.sum(axis=0)
+    return eta / tau, 1.0 / tau
+
+
+def cavity(st: EPState, k: int):
+    """Natural parameters of Q^{\\k} = Q / q_{x,k}: leave-one-out sums (Sec. III-B)."""
+    others = [l for l in range(5) if l != k]
+    return st.tau[others].sum(axis=0), st.eta[others].sum(axis=0)
+
+
+def likelihood_site_update(pb: EPProblem, st: EPState):
+    """Update q_{x,0} (Eqs. (tilted_P_1) and (update_q0_x)), clamp, damp."""
+    tau_c, eta_c = cavity(st, 0)
+    shape = (pb.h, pb.w)
+    b = (pb.hty / pb.xi) + eta_c.reshape(shape)
+    x0 = st.E
+    if x0 is None:
+        x0 = marginals(st)[0].reshape(shape)
+    E, it = ops.solve_tilted_mean(pb.op, pb.xi, tau_c.reshape(shape), b, x0=x0, rtol=pb.cg_rtol)
+    st.E = E
+    st.cg_iters = it
+    V = ops.tilted_variance(pb.op, pb.xi, tau_c.reshape(shape), pb.estimator).ravel()
+    E = E.ravel()
+    tau_new = 1.0 / V - tau_c
+    clamp = tau_new < PREC_FLOOR
+    st.clamp_count += int(clamp.sum())
+    tau_new = np.where(clamp, PREC_FLOOR, tau_new)
+    eta_new = (tau_new + tau_c) * E - eta_c
+    a = pb.damping
+    st.tau[0] = a * tau_new + (1.0 - a) * st.tau[0]
+    st.eta[0] = a * eta_new + (1.0 - a) * st.eta[0]
+
+
+def tv_block_update(pb: EPProblem, st: EPState, k: int) -> float:
+    """Update q_{x,k} for every edge of V_k in parallel (k = 1..4).
+    Returns the sum over the block's edges of the tilted E|u_n|."""
+    i, j = pb.edges[k - 1]
+    if i.size == 0:
+        return 0.0
+    tau_c, eta_c = cavity(st, k)
+    ci = 1.0 / tau_c[i]
+    cj = 1.0 / tau_c[j]
+    mi = eta_c[i] * ci
+    mj = eta_c[j] * cj
+    m = mi - mj
+    s = ci + cj
+    m_bar, S_bar, e_abs = tilted(pb.prior, m, s, st.lam)
+    # Gehre-Jin projection of the tilted moments of u back to (x_i, x_j)
+    Ei = mi + (m_bar - m) / s * ci
+    Ej = mj - (m_bar - m) / s * cj
+    Vi = ci + (S_bar - s) / (s * s) * ci * ci
+    Vj = cj + (S_bar - s) / (s * s) * cj * cj
+    a = pb.damping
+    for idx, Ep, Vp, cp in ((i, Ei, Vi, ci), (j, Ej, Vj, cj)):
+        tau_new = 1.0 / Vp - 1.0 / cp
+        clamp = tau_new < PREC_FLOOR
+        st.clamp_count += int(clamp.sum())
+        tau_new = np.where(clamp, PREC_FLOOR, tau_new)
+        eta_new = (tau_new + 1.0 / cp) * Ep - eta_c[idx]
+        st.tau[k, idx] = a * tau_new + (1.0 - a) * st.tau[k, idx]
+        st.eta[k, idx] = a * eta_new + (1.0 - a) * st.eta[k, idx]
+    return float(e_abs.sum())
+
+
+def sweep(pb: EPProblem, st: EPState, t: int, em: bool) -> float:
+    """Sweep t (1-based).  Returns a_bar_u of the sweep."""
+    if pb.op.kind != ops.IDENTITY and t > 1:
+        likelihood_site_update(pb, st)
+    a_bar = 0.0
+    for k in pb.order:
+        a_bar += tv_block_update(pb, st, k)
+    if em:
+        if pb.prior != "l1":
+            raise ValueError("EM is defined for the l1-TV prior only")
+        st.lam = pb.N / a_bar
+    return a_bar
+
+
+def solve(pb: EPProblem, sweeps: int, em: bool, tol: Optional[float] = None,
+          state: Optional[EPState] = None, record=False):
+    """Run up to ``sweeps`` sweeps.  With ``tol`` set, stop at the first sweep
+    whose changes satisfy the convergence rule:
+        max|mu_t - mu_{t-1}| <= tol * (max y - min y),
+        max|v_t / v_{t-1} - 1| <= 10 tol,
+        |lambda_t / lambda_{t-1} - 1| <= tol (EM only).
+    Returns (mu, v, state, info)."""
+    st = init_cold(pb) if state is None else state
+    yr = np.asarray(pb.hty if pb.op.kind == ops.DFT else pb.y, dtype=np.float64)
+    yrange = float(yr.max() - yr.min()) or 1.0
+    mu_prev, v_prev = marginals(st)
+    done = 0
+    converged = False
+    for t in range(1, sweeps + 1):
+        lam_prev = st.lam
+        a_bar = sweep(pb, st, t, em)
+        done = t
+        mu, v = marginals(st)
+        dmu = float(np.max(np.abs(mu - mu_prev))) / yrange
+        dv = float(np.max(np.abs(v / v_prev - 1.0)))
+        dl = abs(st.lam / lam_prev - 1.0)
+        if record:
+            st.history.append({"t": t, "lam": st.lam, "a_bar": a_bar, "dmu": dmu, "dv": dv,
+                               "cg": st.cg_iters})
+        mu_prev, v_prev = mu, v
+        if tol is not None and dmu <= tol and dv <= 10 * tol and (not em or dl <= tol):
+            converged = True
+            break
+    mu, v = marginals(st)
+    info = {"sweeps": done, "lam": st.lam, "converged": converged, "clamp_count": st.clamp_count}
+    return mu.reshape(pb.h, pb.w), v.reshape(pb.h, pb.w), st, info

@@ -1,0 +1,182 @@
+"""Degradation operators H, H^T, H^T H and the likelihood-site variance (FP64).
+
+TEST INFRASTRUCTURE ONLY (see oracle/__init__.py).
+
+Sec. II-A, Eq. (1): y = H x + n, n ~ N(0, xi I).  Three operators:
+
+* identity (denoising, case (i));
+* periodic 2-D convolution with centred taps k of odd size (deconvolution,
+  case (ii)): (H x)(r, c) = sum_{a,b} k(a, b) x(r - a + kh//2, c - b + kw//2),
+  indices modulo the image size;  H^T is the matching correlation;
+* masked orthonormal 2-D DFT (compressive sensing, case (iii) replaced by a
+  Fourier sensing matrix): observations are the masked complex coefficients of
+  F x.  Treating (Re, Im) of each kept coefficient as two real observations of
+  variance xi gives H^T H x = Re(F^H P F x) and H^T y = Re(F^H P y).
+
+The blur H and H^T are written as sums of shifted copies (their definition);
+H^T H and its spectrum use the FFT (a library primitive), and tests check the
+two forms against each other.
+
+Eq. (tilted_P_1) needs diag((H^T H / xi + diag(tau_c))^{-1}).  The paper notes
+it is exact when H^T H is diagonal and otherwise names Monte Carlo estimators
+(RBMC).  Two estimators are provided:
+
+* "exact":    the dense inverse (tiny images only);
+* "spectral": replace the cavity precision by its mean d (a scalar), where the
+              inverse is circulant and its diagonal is the constant
+              c = mean_w 1 / (|H(w)|^2 / xi + d); the site precision is then the
+              constant gamma = 1/c - d, and the tilted variance at pixel p is
+              1 / (gamma + tau_c[p]).  Exact when tau_c is constant.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+IDENTITY = "identity"
+BLUR = "blur"
+DFT = "dft"
+
+
+class Operator:
+    def __init__(self, kind, shape, taps=None, mask=None):
+        self.kind = kind
+        self.shape = tuple(shape)
+        self.taps = None if taps is None else np.asarray(taps, dtype=np.float64)
+        self.mask = None if mask is None else np.asarray(mask).astype(bool)
+        if kind == BLUR:
+            kh, kw = self.taps.shape
+            if kh % 2 == 0 or kw % 2 == 0:
+                raise ValueError("blur taps must have odd sizes")
+        if kind == DFT and self.mask.shape != self.shape:
+            raise ValueError("mask shape mismatch")
+        self._spec = None
+
+    # ---------------- definition forms ----------------
+    def H(self, x):
+        """Forward operator on a real image.  DFT: returns the complex masked
+        spectrum (h, w) with zeros off the mask."""
+        if self.kind == IDENTITY:
+            return x.copy()
+        if self.kind == BLUR:
+            kh, kw = self.taps.shape
+            out = np.zeros_like(x)
+            for a in range(kh):
+                for b in range(kw):
+                    out += self.taps[a, b] * np.roll(x, (a - kh // 2, b - kw // 2), axis=(0, 1))
+            return out
+        X = np.fft.fft2(x, norm="ortho")
+        return np.where(self.mask, X, 0.0)
+
+    def Ht(self, v):
+        """Adjoint: real image."""
+        if self.kind == IDENTITY:
+            return np.asarray(v, dtype=np.float64).copy()
+        if self.kind == BLUR:
+            kh, kw = self.taps.shape
+            out = np.zeros_like(v)
+            for a in range(kh):
+                for b in range(kw):
+                    out += self.taps[a, b] * np.roll(v, (-(a - kh // 2), -(b - kw // 2)), axis=(0, 1))
+            return out
+        V = np.where(self.mask, v, 0.0)
+        return np.real(np.fft.ifft2(V, norm="ortho"))
+
+    # ---------------- spectral forms ----------------
+    def spectrum(self):
+        """Eigenvalues |H(w)|^2 of the circulant H^T H, shape (h, w)."""
+        if self._spec is not None:
+            return self._spec
+        h, w = self.shape
+        if self.kind == IDENTITY:
+            spec = np.ones((h, w))
+        elif self.kind == BLUR:
+            kh, kw = self.taps.shape
+            pad = np.zeros((h, w))
+            for a in range(kh):
+                for b in range(kw):
+                    pad[(a - kh // 2) % h, (b - kw // 2) % w] += self.taps[a, b]
+            spec = np.abs(np.fft.fft2(pad)) ** 2
+        else:
+            m = self.mask.astype(np.float64)
+            # P(-w): index (-r mod h, -c mod w)
+            m_neg = np.roll(m[::-1, ::-1], (1, 1), axis=(0, 1))
+            spec = 0.5 * (m + m_neg)
+        self._spec = spec
+        return spec
+
+    def HtH(self, x):
+        """H^T H x through the spectrum (FFT); tests pin it to Ht(H(x))."""
+        if self.kind == IDENTITY:
+            return x.copy()
+        return np.real(np.fft.ifft2(np.fft.fft2(x) * self.spectrum()))
+
+    def Hty(self, y):
+        return self.Ht(y)
+
+    def dense_HtH(self):
+        """Explicit N x N matrix of H^T H (tiny images only)."""
+        h, w = self.shape
+        n = h * w
+        A = np.zeros((n, n))
+        e = np.zeros((h, w))
+        for p in range(n):
+            e.flat[p] = 1.0
+            A[:, p] = self.Ht(self.H(e)).ravel()
+            e.flat[p] = 0.0
+        return A
+
+
+def solve_tilted_mean(op: Operator, xi, tau_c, b, x0=None, rtol=1e-12, maxiter=5000):
+    """E = (H^T H / xi + diag(tau_c))^{-1} b by preconditioned conjugate
+    gradients (the paper's suggestion for the mean of Eq. (tilted_P_1)).
+
+    The preconditioner is the circulant (H^T H / xi + mean(tau_c) I)^{-1}; it
+    changes the iteration count, not the solution.  Returns (E, iterations)."""
+    h, w = op.shape
+    if op.kind == IDENTITY:
+        return b / (1.0 / xi + tau_c), 0
+    spec = op.spectrum()
+    dbar = float(np.mean(tau_c))
+    pre = 1.0 / (spec / xi + dbar)
+
+    def A(v):
+        return op.HtH(v) / xi + tau_c * v
+
+    def M(v):
+        return np.real(np.fft.ifft2(np.fft.fft2(v) * pre))
+
+    x = np.zeros((h, w)) if x0 is None else np.array(x0, dtype=np.float64)
+    r = b - A(x)
+    bn = np.linalg.norm(b)
+    if bn == 0.0:
+        return np.zeros((h, w)), 0
+    z = M(r)
+    p = z.copy()
+    rz = float(np.vdot(r, z))
+    it = 0
+    while np.linalg.norm(r) > rtol * bn and it < maxiter:
+        q = A(p)
+        alpha = rz / float(np.vdot(p, q))
+        x += alpha * p
+        r -= alpha * q
+        z = M(r)
+        rz_new = float(np.vdot(r, z))
+        p = z + (rz_new / rz) * p
+        rz = rz_new
+        it += 1
+    return x, it
+
+
+def tilted_variance(op: Operator, xi, tau_c, estimator="spectral"):
+    """Diagonal of (H^T H / xi + diag(tau_c))^{-1}."""
+    if op.kind == IDENTITY:
+        return 1.0 / (1.0 / xi + tau_c)
+    if estimator == "exact":
+        A = op.dense_HtH() / xi + np.diag(tau_c.ravel())
+        return np.diag(np.linalg.inv(A)).reshape(op.shape).copy()
+    if estimator == "spectral":
+        d = float(np.mean(tau_c))
+        c = float(np.mean(1.0 / (op.spectrum() / xi + d)))
+        gamma = 1.0 / c - d
+        return 1.0 / (gamma + tau_c)
+    raise ValueError(f"unknown estimator {estimator!r}")
