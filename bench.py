@@ -1,0 +1,160 @@
+"""Benchmark: EP factor-updates/s on one MI355X, plus seconds to convergence.
+
+A step is one EP-EM sweep of the whole hot path over one image: the
+likelihood-site update (CG solve with H^T H applications, spectral variance,
+damped site update) for non-identity operators, the fused sweep over the four
+colour classes (cavity, tilted moments, site update, damping, clamp), and the
+EM update of lambda.  value = factor updates (edges per sweep x sweeps) per
+second of wall time over the K timed sweeps, inputs already resident on the GPU.
+
+Workloads (synthetic, seeded; see the design doc for the recipe):
+  deconv2048  2048^2 deconvolution, 9x9 Gaussian blur sigma_b = 2 (periodic),
+              sigma = 0.01, EM from lambda = 1, damping 0.5     [default]
+  denoise128  128^2 denoising, sigma = 0.1, lambda = 10 fixed, damping 0.5
+  denoise4096 4096^2 denoising, sigma = 0.1, EM (an HBM-resident probe of the sweep)
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+SWEEP_BYTES_PER_PX = 72        # 5 sites (tau, eta) read + 4 written, float32
+
+
+def make_workload(name):
+    import synthetic as syn
+    if name == "deconv2048":
+        return syn.config4_test(seed=0, size=2048), True
+    if name == "denoise128":
+        return syn.config0(), False
+    if name == "denoise4096":
+        rng = syn.rng_for(5, 0)
+        return syn.make_denoise(4096, 4096, 960, 0.1, rng, mode="paint", lam0=1.0, sweeps=50,
+                                em=True, name="denoise4096"), True
+    raise SystemExit(f"unknown workload {name}")
+
+
+def edges(h, w):
+    return h * (w - 1) + (h - 1) * w
+
+
+def cpu_baseline(p, em, sweeps):
+    """The FP64 oracle on a bounded sample of the same workload: its first
+    `sweeps` sweeps, single-threaded."""
+    from threadpoolctl import threadpool_limits
+    from oracle import ep as oep
+    with threadpool_limits(limits=1):
+        pb = oep.problem_from_synthetic(p)
+        t0 = time.perf_counter()
+        oep.solve(pb, sweeps, em)
+        dt = time.perf_counter() - t0
+    h, w = p.shape
+    return {"value": edges(h, w) * sweeps / dt, "unit": "factor-updates/s", "cores": 1,
+            "kind": "oracle", "sample": f"first {sweeps} sweeps of the same {h}x{w} workload, "
+                                        f"{dt:.1f} s, numpy FP64 single thread"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="deconv2048")
+    ap.add_argument("--tol", type=float, default=1e-5)
+    ap.add_argument("--max-sweeps", type=int, default=2000)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sweeps", type=int, default=2)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(see DESIGN.md for how the sweep would shard)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2110_01585_amd import Context, spec_from_synthetic
+    from paper_2110_01585_amd import _native
+
+    p, em = make_workload(args.workload)
+    h, w = p.shape
+    print(f"[bench] workload {args.workload} {h}x{w} op={p.op} em={em}", file=sys.stderr, flush=True)
+    dev = torch.device("cuda:0")
+    ctx = Context([spec_from_synthetic(p)], device=dev)
+    y = torch.tensor(p.y, dtype=torch.float32, device=dev).contiguous()
+    ctx.ep_tv_set_observation([y])
+    ctx.ep_tv_run(args.warmup, em)
+    torch.cuda.synchronize()
+
+    # timed region: K sweeps from a cold start
+    ctx.ep_tv_init_cold()
+    ctx.ep_tv_set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.ep_tv_run(args.steps, em)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    tm = ctx.ep_tv_get_timing()
+    ctx.ep_tv_set_timing(False)
+    st = ctx.ep_tv_get_stats()[0]
+    dt = t1 - t0
+    E = edges(h, w)
+    value = E * args.steps / dt
+    print(f"[bench] {args.steps} sweeps in {dt*1e3:.1f} ms; sweep kernel {tm['sweep_ms']:.2f} ms / "
+          f"{tm['sweep_launches']}, likelihood {tm['lik_ms']:.2f} ms / {tm['lik_updates']}",
+          file=sys.stderr, flush=True)
+
+    # roofline of the sweep kernel (algorithmic bytes: every site read once, TV sites written once)
+    sweep_avg_s = tm["sweep_ms"] / max(tm["sweep_launches"], 1) / 1e3
+    sweep_bytes = SWEEP_BYTES_PER_PX * h * w
+    achieved = sweep_bytes / sweep_avg_s / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": "k_tv_sweep", "bytes_per_launch": sweep_bytes,
+                "avg_launch_us": round(sweep_avg_s * 1e6, 2)}
+
+    # seconds to converged from a cold start (y resident on the GPU)
+    ctx.ep_tv_init_cold()
+    torch.cuda.synchronize()
+    mu = torch.empty(h, w, device=dev)
+    var = torch.empty(h, w, device=dev)
+    t2 = time.perf_counter()
+    rc, stats = ctx.ep_tv_solve(args.max_sweeps, args.tol, em, [mu], [var])
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    conv = {"s_to_converged_cold": round(t3 - t2, 4), "sweeps_cold": stats[0]["sweeps"],
+            "converged_cold": stats[0]["converged"], "tol": args.tol,
+            "lambda_final": stats[0]["lambda"]}
+    print(f"[bench] cold solve: {conv}", file=sys.stderr, flush=True)
+    ctx.close()
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        print("[bench] timing the oracle on the host", file=sys.stderr, flush=True)
+        cpu = cpu_baseline(p, em, args.cpu_sweeps)
+
+    line = {
+        "metric": "EP factor-updates/s + s to converged 2048^2 deconv, warm-start vs plain, 1 GPU",
+        "value": value, "unit": "factor-updates/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": dt * 1e3 / args.steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": args.workload, "height": h, "width": w, "op": p.op, "em": em,
+                   "edges_per_sweep": E, "damping": p.damping, "xi": p.xi},
+        "roofline": roofline, "cpu_baseline": cpu, "convergence": conv,
+        "timing_ms": {"sweep": tm["sweep_ms"], "likelihood": tm["lik_ms"],
+                      "hth_apply": tm["apply_ms"]},
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,208 @@
+/*
+ * ep_tv.h -- C ABI of the MI355X (gfx950) EP-TV image-restoration library.
+ *
+ * What it computes (Yao, McLaughlin, Altmann, "Fast Scalable Image Restoration
+ * using Total Variation Priors and Expectation Propagation", arXiv 2110.01585):
+ * Gaussian approximations Q(x) = N(mu, diag v) of the posterior of an image x
+ * observed as y = H x + n, n ~ N(0, xi I) (Sec. II-A, Eq. (1)), under the
+ * anisotropic l1-TV prior prod exp(-lambda |x_i - x_j|) over 4-neighbour pairs
+ * (Sec. II-B, Eq. (L1_TV)).  EP keeps five diagonal Gaussian factors
+ * (Sec. III-A): q_{x,0} for the likelihood and q_{x,k}, k = 1..4, one per colour
+ * class V_k of pixel pairs (Fig. 1, Eq. (prior1)).  One sweep is Algorithm 1's
+ * loop body: likelihood-site update (Eqs. (tilted_P_1), (update_q0_x)), then for
+ * each V_k all pairs in parallel (Eqs. (marginal_tilted_un), (update_qk_x)), with
+ * damping and the negative-variance clamp (Sec. III-C).  With EM on, lambda is
+ * replaced after every sweep by N / a_bar_u (Algorithm 2, Eq.
+ * (3rd_alternative_a0)), N = number of pixels.
+ *
+ * Conventions shared by every entry point:
+ *  - Return value: int32 status, 0 = OK, > 0 = warning, < 0 = error (EP_TV_*).
+ *    No C++ exception crosses this boundary.  After an error, ep_tv_last_error()
+ *    on the same context returns a message.
+ *  - "device pointer" = memory on the GPU the context was created on (e.g. a
+ *    torch tensor's data_ptr()); "host pointer" = ordinary CPU memory.
+ *  - The caller owns every buffer it passes.  The library never frees caller
+ *    memory and never keeps a caller pointer beyond the call, except the
+ *    workspace given to ep_tv_create, which must stay alive and untouched by the
+ *    caller until ep_tv_destroy.
+ *  - Images are row-major, dense, float32: pixel (r, c) of an H x W image is
+ *    element r * W + c.  Pixel arrays passed per instance are given as a host
+ *    array of n_problems device pointers.
+ *  - All GPU work is enqueued on the HIP stream given to ep_tv_create.  Calls
+ *    documented as "asynchronous" return before the GPU has finished; calls
+ *    that return host-visible results synchronise that stream.
+ *  - A context is not thread-safe; use one per host thread.
+ */
+#ifndef EP_TV_H
+#define EP_TV_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  EP_TV_OK = 0,
+  EP_TV_W_NOT_CONVERGED = 1,   /* ep_tv_solve hit max_sweeps before the tolerance */
+  EP_TV_W_WARM_FALLBACK = 2,   /* a warm start was rejected and a cold start used */
+  EP_TV_E_ARG = -1,            /* invalid argument (sizes, xi <= 0, damping, NULL) */
+  EP_TV_E_OOM = -2,            /* workspace smaller than ep_tv_workspace_bytes() */
+  EP_TV_E_HIP = -3,            /* a HIP runtime call failed */
+  EP_TV_E_NONFINITE = -4,      /* NaN/Inf detected in the EP state */
+  EP_TV_E_STATE = -5           /* call out of order (e.g. solve before observation) */
+};
+
+/* Degradation operator H (Sec. II-A, cases (i)-(iii)). */
+enum {
+  EP_TV_OP_IDENTITY = 0,       /* denoising: H = I */
+  EP_TV_OP_BLUR_PERIODIC = 1,  /* deconvolution: periodic 2-D convolution with given taps */
+  EP_TV_OP_DFT_MASK = 2        /* CS: subset of orthonormal 2-D DFT coefficients */
+};
+
+/* Image boundary for the pixel-pair graph.  FREE: pairs inside the image only;
+ * PERIODIC: wrap-around pairs added (requires even height and width). */
+enum { EP_TV_BND_FREE = 0, EP_TV_BND_PERIODIC = 1 };
+
+/* One restoration problem.  Host pointers inside are read (copied) by
+ * ep_tv_create only. */
+typedef struct {
+  int32_t height, width;       /* image size, each in [1, 16384] */
+  int32_t op;                  /* EP_TV_OP_* */
+  int32_t boundary;            /* EP_TV_BND_* */
+  const float* blur_taps;      /* host, blur_h * blur_w row-major, odd sizes <= 17, centred:
+                                  (Hx)(r,c) = sum_ab taps[a][b] x(r-a+blur_h/2, c-b+blur_w/2) */
+  int32_t blur_h, blur_w;
+  const uint8_t* dft_mask;     /* host, height*width, nonzero = coefficient observed; the DC
+                                  coefficient is always treated as observed */
+  double noise_var;            /* xi > 0, variance of each real observation (CS: of Re and Im) */
+  double lambda0;              /* > 0: lambda (fixed, or the EM starting value) */
+  double damping;              /* in (0, 1]: weight of the new site value in the damped update */
+} ep_tv_problem;
+
+/* Per-instance statistics (host struct filled by ep_tv_solve / ep_tv_get_stats). */
+typedef struct {
+  int32_t sweeps_done;         /* sweeps run on this instance since the last (re)initialisation */
+  int32_t cg_iters_last;       /* CG iterations of the last likelihood-site update */
+  int32_t cg_iters_total;      /* CG iterations since the last (re)initialisation */
+  int32_t clamp_count;         /* site updates whose precision was clamped (Sec. III-C) */
+  int32_t status;              /* EP_TV_OK, EP_TV_W_NOT_CONVERGED or an error code */
+  int32_t converged;           /* 1 once the convergence rule of ep_tv_solve held */
+  double lambda;               /* current lambda */
+  double a_bar_u;              /* sum over the last sweep's edges of the tilted E|u| */
+  double max_dmu_rel;          /* last sweep: max |mu_t - mu_{t-1}| / (max y - min y) */
+  double max_dv_rel;           /* last sweep: max |v_t / v_{t-1} - 1| */
+  double elapsed_ms;           /* wall time of the ep_tv_solve call (same for all instances) */
+} ep_tv_stats;
+
+typedef struct ep_tv_ctx ep_tv_ctx;
+
+/* Library version string (static storage). */
+const char* ep_tv_version(void);
+
+/* Bytes of device workspace a context for these problems needs (host out-param).
+ * p: host array of n_problems descriptors, n_problems in [1, 4096]. */
+int ep_tv_workspace_bytes(const ep_tv_problem* p, int32_t n_problems, size_t* bytes);
+
+/* Create a context for n_problems independent instances solved together (one
+ * batch; each instance keeps its own lambda, convergence flag and statistics).
+ * d_workspace: device pointer, >= ep_tv_workspace_bytes() bytes, 256-byte aligned,
+ *   owned by the caller, used exclusively by this context until ep_tv_destroy.
+ * hip_stream: hipStream_t to enqueue on (NULL = default stream).
+ * out: receives the context.  Validates every descriptor (EP_TV_E_ARG). */
+int ep_tv_create(const ep_tv_problem* p, int32_t n_problems, void* d_workspace,
+                 size_t ws_bytes, void* hip_stream, ep_tv_ctx** out);
+
+/* Set the observations and (re)initialise every instance cold, as in the
+ * initialisation line of Algorithm 1: q_{x,0} = N(H^T y, xi I) (for H = I or
+ * blur, y itself), TV sites with variance 1e8 where a pair of V_k covers the
+ * pixel, flat (0, 0) elsewhere; lambda = lambda0.  Asynchronous.
+ * d_y: host array of n_problems device pointers.  IDENTITY/BLUR: height*width
+ *   floats.  DFT_MASK: height*width complex values as interleaved (re, im)
+ *   float pairs, the orthonormal 2-D DFT coefficients of x plus noise; entries
+ *   off the mask are ignored.  The data is copied; the caller may reuse y. */
+int ep_tv_set_observation(ep_tv_ctx* ctx, const float* const* d_y);
+
+/* Re-run the cold initialisation with the stored observations.  Asynchronous. */
+int ep_tv_init_cold(ep_tv_ctx* ctx);
+
+/* Run n_sweeps sweeps of Algorithm 1 on every active instance; with em_enabled,
+ * lambda <- N / a_bar_u after every sweep (the fast EP-EM of Algorithm 2, one EP
+ * iteration per EM iteration).  Asynchronous; no host synchronisation. */
+int ep_tv_run(ep_tv_ctx* ctx, int32_t n_sweeps, int32_t em_enabled);
+
+/* One iteration of Algorithm 2: n_ep_sweeps sweeps of Algorithm 1 at the
+ * current lambda, then lambda <- N / a_bar_u from the last of those sweeps.
+ * lambda_out: host array of n_problems doubles receiving the new lambdas, or NULL
+ * (then the call is asynchronous). */
+int ep_tv_em_step(ep_tv_ctx* ctx, int32_t n_ep_sweeps, double* lambda_out);
+
+/* Sweep until every instance has converged or max_sweeps sweeps were run, then
+ * write the marginals.  Convergence rule, checked after every sweep on the GPU:
+ *   max|mu_t - mu_{t-1}| <= tol * (max y - min y)  and  max|v_t/v_{t-1} - 1| <= 10 tol
+ *   and, with EM, |lambda_t / lambda_{t-1} - 1| <= tol.
+ * A converged instance is frozen (no further sweeps).  tol <= 0 runs exactly
+ * max_sweeps sweeps.  d_mean, d_var: host arrays of n_problems device pointers
+ * (height*width floats each) or NULL to skip.  stats: host array of n_problems
+ * or NULL.  Synchronises the stream.  Returns EP_TV_W_NOT_CONVERGED if any
+ * instance did not converge (tol > 0), EP_TV_E_NONFINITE on NaN/Inf. */
+int ep_tv_solve(ep_tv_ctx* ctx, int32_t max_sweeps, double tol, int32_t em_enabled,
+                float* const* d_mean, float* const* d_var, ep_tv_stats* stats);
+
+/* Write mu = eta/tau and v = 1/tau of the global approximation (Eq. (Q_x_final))
+ * for every instance.  Asynchronous.  Arguments as in ep_tv_solve. */
+int ep_tv_marginals(ep_tv_ctx* ctx, float* const* d_mean, float* const* d_var);
+
+/* Copy the five sites out (checkpoint).  d_out: host array of n_problems device
+ * pointers, each 10*height*width floats, planar in the order
+ * tau_0, eta_0, tau_1, eta_1, ..., tau_4, eta_4 (natural parameters:
+ * tau = 1/variance, eta = mean/variance).  Asynchronous. */
+int ep_tv_get_sites(ep_tv_ctx* ctx, float* const* d_out);
+
+/* Restore the five sites (resume) in the layout of ep_tv_get_sites, and the
+ * lambdas (host array of n_problems doubles, or NULL to keep them).  Resets the
+ * convergence flags and sweep counters.  Asynchronous. */
+int ep_tv_set_sites(ep_tv_ctx* ctx, const float* const* d_in, const double* lambda);
+
+/* Current per-instance statistics into a host array of n_problems.  Synchronises. */
+int ep_tv_get_stats(ep_tv_ctx* ctx, ep_tv_stats* stats);
+
+/* The tilted-moment step of the TV-site update on its own (Sec. III-C, Eq.
+ * (marginal_tilted_un) with the l1-TV factor of Eq. (L1_TV)), exposed so its
+ * device arithmetic can be checked in isolation.  For each of n differences
+ * u ~ N(u; m[i], s[i]) exp(-lambda |u|) it writes rho[i] = 1 - Var/s[i],
+ * delta[i] = E[u] - m[i] and eabs[i] = E|u|.  All arrays are device pointers of
+ * n floats, s[i] > 0, lambda >= 0.  hip_stream as in ep_tv_create.
+ * Asynchronous. */
+int ep_tv_tilted_moments(int32_t n, const float* d_m, const float* d_s, float lambda,
+                         float* d_rho, float* d_delta, float* d_eabs, void* hip_stream);
+
+/* Kernel timing for measurement.  With timing enabled, HIP events are recorded
+ * on the context's stream around every launch of the fused TV sweep kernel and
+ * around every likelihood-site update (its CG solve and site kernels), and
+ * their durations are accumulated.  ep_tv_set_timing(ctx, 1) also clears the
+ * totals.  ep_tv_get_timing synchronises and fills a host struct. */
+typedef struct {
+  double sweep_ms;             /* total GPU time of TV sweep kernel launches */
+  int32_t sweep_launches;
+  double lik_ms;               /* total GPU time of likelihood-site updates */
+  int32_t lik_updates;
+  double apply_ms;             /* total GPU time of H^T H applications inside CG */
+  int32_t apply_launches;
+} ep_tv_timing;
+
+int ep_tv_set_timing(ep_tv_ctx* ctx, int32_t enable);
+int ep_tv_get_timing(ep_tv_ctx* ctx, ep_tv_timing* out);
+
+/* Message for the last error on this context ("" if none).  Static to the ctx. */
+const char* ep_tv_last_error(const ep_tv_ctx* ctx);
+
+/* Destroy the context.  Frees only what the library allocated for itself. */
+void ep_tv_destroy(ep_tv_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* EP_TV_H */

@@ -215,7 +215,8 @@ def sweep(pb: EPProblem, st: EPState, t: int, em: bool) -> float:
     if em:
         if pb.prior != "l1":
             raise ValueError("EM is defined for the l1-TV prior only")
-        st.lam = pb.N / a_bar
+        if a_bar > 0.0:              # an image without edges has nothing to re-estimate
+            st.lam = pb.N / a_bar
     return a_bar
 
 

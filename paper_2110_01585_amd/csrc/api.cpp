@@ -1,0 +1,604 @@
+// Host side of the C ABI declared in include/ep_tv.h: argument validation,
+// workspace layout, the tile list, and the per-sweep launch schedule.
+#include "../../include/ep_tv.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "ep_tv_internal.h"
+#include "lik.h"
+
+using namespace eptv;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+struct InstHost {
+  ep_tv_problem p{};
+  std::vector<float> taps;
+  std::vector<uint8_t> mask;
+  int pitch = 0;
+  long long off = 0;
+  int strips = 0, chunks = 0, chunk_rows = 0, tile0 = 0, ntiles = 0;
+};
+
+struct Layout {
+  long long plane = 0;       // elements per plane (all instances)
+  int ntiles = 0;
+  size_t S0 = 0, SB[2][4]{}, ypix = 0, inst = 0, st = 0, tiles = 0;
+  size_t part_e = 0, part_m = 0, part_v = 0, part_c = 0, part_f = 0, tab0 = 0, tab1 = 0;
+  LikLayout lik;
+  size_t total = 0;
+};
+
+int pick_chunk_rows(int H, int W) {
+  if (const char* e = std::getenv("EPTV_CHUNK_ROWS")) {
+    int v = std::atoi(e);
+    if (v >= 2 && v % 2 == 0) return v;
+  }
+  const long long strips = (W + kStripInt - 1) / kStripInt;
+  int ch = 32;
+  while (ch > 8 && strips * ((H + ch - 1) / ch) < 4096) ch /= 2;
+  return ch;
+}
+
+const char* validate(const ep_tv_problem& p) {
+  if (p.height < 1 || p.width < 1 || p.height > 16384 || p.width > 16384)
+    return "height and width must be in [1, 16384]";
+  if (p.op < EP_TV_OP_IDENTITY || p.op > EP_TV_OP_DFT_MASK) return "unknown operator";
+  if (p.boundary != EP_TV_BND_FREE && p.boundary != EP_TV_BND_PERIODIC) return "unknown boundary";
+  if (p.boundary == EP_TV_BND_PERIODIC && (p.height % 2 || p.width % 2 || p.height < 2 || p.width < 2))
+    return "periodic boundary needs even height and width";
+  if (!(p.noise_var > 0.0) || !std::isfinite(p.noise_var)) return "noise_var must be > 0";
+  if (!(p.lambda0 > 0.0) || !std::isfinite(p.lambda0)) return "lambda0 must be > 0";
+  if (!(p.damping > 0.0 && p.damping <= 1.0)) return "damping must be in (0, 1]";
+  if (p.op == EP_TV_OP_BLUR_PERIODIC) {
+    if (!p.blur_taps) return "blur operator needs blur_taps";
+    if (p.blur_h < 1 || p.blur_w < 1 || p.blur_h % 2 == 0 || p.blur_w % 2 == 0 ||
+        p.blur_h > kMaxTaps || p.blur_w > kMaxTaps)
+      return "blur taps must have odd sizes <= 17";
+    if (p.blur_h > p.height || p.blur_w > p.width) return "blur kernel larger than the image";
+  }
+  if (p.op == EP_TV_OP_DFT_MASK) {
+    if (!p.dft_mask) return "DFT operator needs dft_mask";
+    if (!fft_size_ok(p.height) || !fft_size_ok(p.width))
+      return "DFT operator needs power-of-two sizes in [4, 4096]";
+  }
+  return nullptr;
+}
+
+void make_layout(std::vector<InstHost>& ih, Layout& L) {
+  long long off = 0;
+  int tiles = 0;
+  for (auto& h : ih) {
+    const int H = h.p.height, W = h.p.width;
+    h.pitch = (int)align_up((size_t)W + 1, 64);   // +1: a lane's pixel pair never leaves the row
+    h.off = off;
+    off += (long long)h.pitch * H;
+    off = (long long)align_up((size_t)off, 64);
+    h.chunk_rows = pick_chunk_rows(H, W);
+    h.strips = (W + kStripInt - 1) / kStripInt;
+    h.chunks = (H + h.chunk_rows - 1) / h.chunk_rows;
+    h.tile0 = tiles;
+    h.ntiles = h.strips * h.chunks;
+    tiles += h.ntiles;
+  }
+  L.plane = std::max<long long>(off, 64);
+  L.ntiles = tiles;
+  const int n = (int)ih.size();
+  size_t cur = 0;
+  auto take = [&](size_t bytes) {
+    size_t at = cur;
+    cur = align_up(cur + bytes, kAlign);
+    return at;
+  };
+  L.S0 = take(sizeof(float2) * (size_t)L.plane);
+  for (int b = 0; b < 2; ++b)
+    for (int k = 0; k < 4; ++k) L.SB[b][k] = take(sizeof(float2) * (size_t)L.plane);
+  L.ypix = take(sizeof(float) * (size_t)L.plane);
+  L.inst = take(sizeof(InstDev) * n);
+  L.st = take(sizeof(InstState) * n);
+  L.tiles = take(sizeof(int4) * (size_t)std::max(tiles, 1));
+  L.part_e = take(sizeof(double) * (size_t)std::max(tiles, 1));
+  L.part_m = take(sizeof(float) * (size_t)std::max(tiles, 1));
+  L.part_v = take(sizeof(float) * (size_t)std::max(tiles, 1));
+  L.part_c = take(sizeof(unsigned) * (size_t)std::max(tiles, 1));
+  L.part_f = take(sizeof(unsigned) * (size_t)std::max(tiles, 1));
+  L.tab0 = take(sizeof(float*) * n);
+  L.tab1 = take(sizeof(float*) * n);
+  std::vector<LikInstInfo> li(n);
+  for (int i = 0; i < n; ++i) {
+    li[i].op = ih[i].p.op;
+    li[i].H = ih[i].p.height;
+    li[i].W = ih[i].p.width;
+  }
+  lik_layout(li.data(), n, L.plane, take, L.lik);
+  L.total = cur;
+}
+
+}  // namespace
+
+struct ep_tv_ctx {
+  int n = 0;
+  std::vector<InstHost> ih;
+  Layout L;
+  hipStream_t stream = nullptr;
+  char* ws = nullptr;
+  float2* S0 = nullptr;
+  float2* SB[2][4]{};
+  int cur = 0;   // which TV-site buffer holds the current state
+  float* ypix = nullptr;
+  InstDev* d_inst = nullptr;
+  InstState* d_st = nullptr;
+  int4* d_tiles = nullptr;
+  SweepArgs sa{};
+  float** d_tab0 = nullptr;
+  float** d_tab1 = nullptr;
+  LikCtx lik;
+  bool has_obs = false;
+  bool any_lik = false;
+  std::vector<InstState> host_st;
+  std::vector<float*> tab_host0, tab_host1;
+  double last_elapsed_ms = 0.0;
+  std::string err;
+  // measurement: event pairs around sweep launches and likelihood updates
+  bool timing = false;
+  std::vector<hipEvent_t> ev_pool;
+  std::vector<std::pair<int, int>> ev_sweep, ev_lik;   // indices into ev_pool
+  size_t ev_used = 0;
+};
+
+struct CurSites {
+  float2* S[5];
+};
+
+static CurSites cur_sites(const ep_tv_ctx* c) {
+  CurSites r;
+  r.S[0] = c->S0;
+  for (int k = 0; k < 4; ++k) r.S[k + 1] = c->SB[c->cur][k];
+  return r;
+}
+
+static hipEvent_t next_event(ep_tv_ctx* c, int& idx) {
+  if (c->ev_used == c->ev_pool.size()) {
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    c->ev_pool.push_back(e);
+  }
+  idx = (int)c->ev_used;
+  return c->ev_pool[c->ev_used++];
+}
+
+static void timing_clear(ep_tv_ctx* c) {
+  c->ev_sweep.clear();
+  c->ev_lik.clear();
+  c->ev_used = 0;
+}
+
+static int fail(ep_tv_ctx* c, int code, const std::string& msg) {
+  if (c) c->err = msg;
+  return code;
+}
+
+static int hip_check(ep_tv_ctx* c, hipError_t e, const char* what) {
+  if (e == hipSuccess) return EP_TV_OK;
+  return fail(c, EP_TV_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIPCHK(c, expr)                              \
+  do {                                               \
+    int _rc = hip_check((c), (expr), #expr);         \
+    if (_rc != EP_TV_OK) return _rc;                 \
+  } while (0)
+
+extern "C" {
+
+const char* ep_tv_version(void) { return "eptv-gfx950 0.1"; }
+
+int ep_tv_workspace_bytes(const ep_tv_problem* p, int32_t n, size_t* bytes) {
+  if (!p || !bytes || n < 1 || n > 4096) return EP_TV_E_ARG;
+  std::vector<InstHost> ih(n);
+  for (int i = 0; i < n; ++i) {
+    if (validate(p[i])) return EP_TV_E_ARG;
+    ih[i].p = p[i];
+  }
+  Layout L;
+  make_layout(ih, L);
+  *bytes = L.total;
+  return EP_TV_OK;
+}
+
+int ep_tv_create(const ep_tv_problem* p, int32_t n, void* d_ws, size_t ws_bytes, void* stream,
+                 ep_tv_ctx** out) {
+  if (!out) return EP_TV_E_ARG;
+  *out = nullptr;
+  if (!p || n < 1 || n > 4096 || !d_ws) return EP_TV_E_ARG;
+  if (reinterpret_cast<uintptr_t>(d_ws) % kAlign) return EP_TV_E_ARG;
+  ep_tv_ctx* c = new ep_tv_ctx();
+  c->n = n;
+  c->ih.resize(n);
+  for (int i = 0; i < n; ++i) {
+    if (const char* m = validate(p[i])) {
+      delete c;
+      return EP_TV_E_ARG;
+    }
+    c->ih[i].p = p[i];
+    if (p[i].op == EP_TV_OP_BLUR_PERIODIC) {
+      c->ih[i].taps.assign(p[i].blur_taps, p[i].blur_taps + (size_t)p[i].blur_h * p[i].blur_w);
+      c->ih[i].p.blur_taps = nullptr;
+    }
+    if (p[i].op == EP_TV_OP_DFT_MASK) {
+      c->ih[i].mask.assign(p[i].dft_mask, p[i].dft_mask + (size_t)p[i].height * p[i].width);
+      c->ih[i].mask[0] = 1;   // DC always observed
+      c->ih[i].p.dft_mask = nullptr;
+    }
+    if (p[i].op != EP_TV_OP_IDENTITY) c->any_lik = true;
+  }
+  make_layout(c->ih, c->L);
+  if (ws_bytes < c->L.total) {
+    delete c;
+    return EP_TV_E_OOM;
+  }
+  c->stream = reinterpret_cast<hipStream_t>(stream);
+  c->ws = reinterpret_cast<char*>(d_ws);
+  c->S0 = reinterpret_cast<float2*>(c->ws + c->L.S0);
+  for (int b = 0; b < 2; ++b)
+    for (int k = 0; k < 4; ++k) c->SB[b][k] = reinterpret_cast<float2*>(c->ws + c->L.SB[b][k]);
+  c->ypix = reinterpret_cast<float*>(c->ws + c->L.ypix);
+  c->d_inst = reinterpret_cast<InstDev*>(c->ws + c->L.inst);
+  c->d_st = reinterpret_cast<InstState*>(c->ws + c->L.st);
+  c->d_tiles = reinterpret_cast<int4*>(c->ws + c->L.tiles);
+  c->d_tab0 = reinterpret_cast<float**>(c->ws + c->L.tab0);
+  c->d_tab1 = reinterpret_cast<float**>(c->ws + c->L.tab1);
+  SweepArgs& a = c->sa;
+  a.S0 = c->S0;
+  a.inst = c->d_inst;
+  a.st = c->d_st;
+  a.tiles = c->d_tiles;
+  a.ntiles = c->L.ntiles;
+  a.part_eabs = reinterpret_cast<double*>(c->ws + c->L.part_e);
+  a.part_dmu = reinterpret_cast<float*>(c->ws + c->L.part_m);
+  a.part_dv = reinterpret_cast<float*>(c->ws + c->L.part_v);
+  a.part_clamp = reinterpret_cast<unsigned*>(c->ws + c->L.part_c);
+  a.part_flags = reinterpret_cast<unsigned*>(c->ws + c->L.part_f);
+
+  std::vector<InstDev> idev(n);
+  std::vector<int4> tiles;
+  tiles.reserve(c->L.ntiles);
+  for (int i = 0; i < n; ++i) {
+    const InstHost& h = c->ih[i];
+    InstDev& d = idev[i];
+    std::memset(&d, 0, sizeof(d));
+    d.H = h.p.height; d.W = h.p.width; d.pitch = h.pitch; d.bnd = h.p.boundary;
+    d.off = h.off; d.op = h.p.op; d.strips = h.strips; d.chunks = h.chunks; d.tile0 = h.tile0;
+    d.ntiles = h.ntiles; d.chunk_rows = h.chunk_rows; d.npix = h.p.height * h.p.width;
+    d.xi = (float)h.p.noise_var; d.inv_xi = (float)(1.0 / h.p.noise_var);
+    d.alpha = (float)h.p.damping;
+    for (int s = 0; s < h.strips; ++s)
+      for (int ch = 0; ch < h.chunks; ++ch) tiles.push_back(make_int4(i, s, ch, 0));
+  }
+  int rc = hip_check(c, hipMemcpyAsync(c->d_inst, idev.data(), sizeof(InstDev) * n,
+                                       hipMemcpyHostToDevice, c->stream), "copy instances");
+  if (rc == EP_TV_OK && !tiles.empty())
+    rc = hip_check(c, hipMemcpyAsync(c->d_tiles, tiles.data(), sizeof(int4) * tiles.size(),
+                                     hipMemcpyHostToDevice, c->stream), "copy tiles");
+  if (rc == EP_TV_OK) {
+    std::vector<LikInstInfo> li(n);
+    for (int i = 0; i < n; ++i) {
+      li[i].op = c->ih[i].p.op;
+      li[i].H = c->ih[i].p.height;
+      li[i].W = c->ih[i].p.width;
+      li[i].pitch = c->ih[i].pitch;
+      li[i].off = c->ih[i].off;
+      li[i].xi = c->ih[i].p.noise_var;
+      li[i].damping = c->ih[i].p.damping;
+      li[i].taps = c->ih[i].taps.empty() ? nullptr : c->ih[i].taps.data();
+      li[i].th = c->ih[i].p.blur_h;
+      li[i].tw = c->ih[i].p.blur_w;
+      li[i].mask = c->ih[i].mask.empty() ? nullptr : c->ih[i].mask.data();
+      li[i].tile0 = c->ih[i].tile0;
+      li[i].ntiles = c->ih[i].ntiles;
+    }
+    std::string e;
+    if (lik_create(c->lik, li.data(), n, c->ws, c->L.lik, c->L.plane, c->d_inst, c->d_st,
+                   c->d_tiles, c->L.ntiles, c->ypix, c->stream, e) != hipSuccess)
+      rc = fail(c, EP_TV_E_HIP, "likelihood-site setup: " + e);
+  }
+  if (rc == EP_TV_OK) rc = hip_check(c, hipStreamSynchronize(c->stream), "create sync");
+  if (rc != EP_TV_OK) {
+    delete c;
+    return rc;
+  }
+  c->host_st.resize(n);
+  *out = c;
+  return EP_TV_OK;
+}
+
+static int reset_states(ep_tv_ctx* c) {
+  for (int i = 0; i < c->n; ++i) {
+    InstState& s = c->host_st[i];
+    std::memset(&s, 0, sizeof(s));
+    s.lam = s.lam_prev = c->ih[i].p.lambda0;
+    s.active = 1u;
+  }
+  HIPCHK(c, hipMemcpyAsync(c->d_st, c->host_st.data(), sizeof(InstState) * c->n,
+                           hipMemcpyHostToDevice, c->stream));
+  return EP_TV_OK;
+}
+
+int ep_tv_init_cold(ep_tv_ctx* c) {
+  if (!c) return EP_TV_E_ARG;
+  if (!c->has_obs) return fail(c, EP_TV_E_STATE, "no observation set");
+  int rc = reset_states(c);
+  if (rc) return rc;
+  HIPCHK(c, launch_yrange(c->ypix, c->d_inst, c->d_st, c->n, c->stream));
+  c->cur = 0;
+  HIPCHK(c, launch_init_cold(cur_sites(c).S, c->ypix, c->d_inst, c->d_st, c->d_tiles, c->L.ntiles,
+                             c->stream));
+  HIPCHK(c, lik_reset(c->lik, c->stream));
+  return EP_TV_OK;
+}
+
+int ep_tv_set_observation(ep_tv_ctx* c, const float* const* d_y) {
+  if (!c || !d_y) return EP_TV_E_ARG;
+  for (int i = 0; i < c->n; ++i) {
+    if (!d_y[i]) return fail(c, EP_TV_E_ARG, "null observation pointer");
+    const InstHost& h = c->ih[i];
+    if (h.p.op == EP_TV_OP_DFT_MASK) continue;
+    HIPCHK(c, hipMemcpy2DAsync(c->ypix + h.off, sizeof(float) * h.pitch, d_y[i],
+                               sizeof(float) * h.p.width, sizeof(float) * h.p.width, h.p.height,
+                               hipMemcpyDeviceToDevice, c->stream));
+  }
+  HIPCHK(c, lik_set_observation(c->lik, d_y, c->stream));
+  c->has_obs = true;
+  return ep_tv_init_cold(c);
+}
+
+static int one_sweep(ep_tv_ctx* c, int em, bool delta, double tol) {
+  const bool tm = c->timing && c->ev_used + 4 <= 8192;
+  int i0 = 0, i1 = 0;
+  if (c->any_lik) {
+    if (tm) HIPCHK(c, hipEventRecord(next_event(c, i0), c->stream));
+    HIPCHK(c, lik_update(c->lik, cur_sites(c).S, c->stream));
+    if (tm) {
+      HIPCHK(c, hipEventRecord(next_event(c, i1), c->stream));
+      c->ev_lik.emplace_back(i0, i1);
+    }
+  }
+  if (tm) HIPCHK(c, hipEventRecord(next_event(c, i0), c->stream));
+  SweepArgs& a = c->sa;
+  float2* const* in = c->SB[c->cur];
+  float2* const* out = c->SB[c->cur ^ 1];
+  a.I1 = in[0]; a.I2 = in[1]; a.I3 = in[2]; a.I4 = in[3];
+  a.O1 = out[0]; a.O2 = out[1]; a.O3 = out[2]; a.O4 = out[3];
+  HIPCHK(c, launch_tv_sweep(a, delta, c->stream));
+  c->cur ^= 1;
+  if (tm) {
+    HIPCHK(c, hipEventRecord(next_event(c, i1), c->stream));
+    c->ev_sweep.emplace_back(i0, i1);
+  }
+  HIPCHK(c, launch_finalize(c->d_inst, c->d_st, c->n, c->sa, em, tol, c->stream));
+  return EP_TV_OK;
+}
+
+int ep_tv_run(ep_tv_ctx* c, int32_t n_sweeps, int32_t em) {
+  if (!c || n_sweeps < 0) return EP_TV_E_ARG;
+  if (!c->has_obs) return fail(c, EP_TV_E_STATE, "no observation set");
+  for (int t = 0; t < n_sweeps; ++t) {
+    int rc = one_sweep(c, em ? 1 : 0, false, 0.0);
+    if (rc) return rc;
+  }
+  return EP_TV_OK;
+}
+
+static int pull_states(ep_tv_ctx* c) {
+  HIPCHK(c, hipMemcpyAsync(c->host_st.data(), c->d_st, sizeof(InstState) * c->n,
+                           hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return EP_TV_OK;
+}
+
+int ep_tv_em_step(ep_tv_ctx* c, int32_t n_ep, double* lambda_out) {
+  if (!c || n_ep < 1) return EP_TV_E_ARG;
+  if (!c->has_obs) return fail(c, EP_TV_E_STATE, "no observation set");
+  for (int t = 0; t < n_ep; ++t) {
+    int rc = one_sweep(c, t == n_ep - 1 ? 1 : 0, false, 0.0);
+    if (rc) return rc;
+  }
+  if (lambda_out) {
+    int rc = pull_states(c);
+    if (rc) return rc;
+    for (int i = 0; i < c->n; ++i) lambda_out[i] = c->host_st[i].lam;
+  }
+  return EP_TV_OK;
+}
+
+static int set_tab(ep_tv_ctx* c, float* const* host, float** dev, std::vector<float*>& keep) {
+  keep.assign(host, host + c->n);
+  HIPCHK(c, hipMemcpyAsync(dev, keep.data(), sizeof(float*) * c->n, hipMemcpyHostToDevice,
+                           c->stream));
+  return EP_TV_OK;
+}
+
+int ep_tv_marginals(ep_tv_ctx* c, float* const* d_mean, float* const* d_var) {
+  if (!c) return EP_TV_E_ARG;
+  if (!c->has_obs) return fail(c, EP_TV_E_STATE, "no observation set");
+  if (!d_mean && !d_var) return EP_TV_OK;
+  if (d_mean) {
+    int rc = set_tab(c, d_mean, c->d_tab0, c->tab_host0);
+    if (rc) return rc;
+  }
+  if (d_var) {
+    int rc = set_tab(c, d_var, c->d_tab1, c->tab_host1);
+    if (rc) return rc;
+  }
+  HIPCHK(c, launch_marginals(cur_sites(c).S, c->d_inst, c->d_tiles, c->L.ntiles, d_mean ? c->d_tab0 : nullptr,
+                             d_var ? c->d_tab1 : nullptr, c->stream));
+  return EP_TV_OK;
+}
+
+static void fill_stats(ep_tv_ctx* c, ep_tv_stats* s) {
+  for (int i = 0; i < c->n; ++i) {
+    const InstState& h = c->host_st[i];
+    ep_tv_stats& o = s[i];
+    o.sweeps_done = (int32_t)h.sweeps;
+    o.cg_iters_last = h.cg_last;
+    o.cg_iters_total = h.cg_total;
+    o.clamp_count = (int32_t)h.clamps;
+    o.converged = h.converged;
+    o.status = (h.flags & FLAG_NONFINITE) ? EP_TV_E_NONFINITE
+               : (h.converged ? EP_TV_OK : EP_TV_W_NOT_CONVERGED);
+    o.lambda = h.lam;
+    o.a_bar_u = h.abar;
+    o.max_dmu_rel = h.dmu;
+    o.max_dv_rel = h.dv;
+    o.elapsed_ms = c->last_elapsed_ms;
+  }
+}
+
+int ep_tv_solve(ep_tv_ctx* c, int32_t max_sweeps, double tol, int32_t em, float* const* d_mean,
+                float* const* d_var, ep_tv_stats* stats) {
+  if (!c || max_sweeps < 0) return EP_TV_E_ARG;
+  if (!c->has_obs) return fail(c, EP_TV_E_STATE, "no observation set");
+  const auto t0 = std::chrono::steady_clock::now();
+  const bool use_tol = tol > 0.0;
+  const int check_every = 8;
+  int rc = EP_TV_OK;
+  for (int t = 0; t < max_sweeps; ++t) {
+    rc = one_sweep(c, em ? 1 : 0, true, use_tol ? tol : 0.0);
+    if (rc) return rc;
+    if (use_tol && ((t + 1) % check_every == 0)) {
+      rc = pull_states(c);
+      if (rc) return rc;
+      bool any = false;
+      for (int i = 0; i < c->n; ++i) any = any || c->host_st[i].active;
+      if (!any) break;
+    }
+  }
+  rc = ep_tv_marginals(c, d_mean, d_var);
+  if (rc) return rc;
+  rc = pull_states(c);
+  if (rc) return rc;
+  c->last_elapsed_ms =
+      std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  if (stats) fill_stats(c, stats);
+  bool nonfinite = false, notconv = false;
+  for (int i = 0; i < c->n; ++i) {
+    nonfinite = nonfinite || (c->host_st[i].flags & FLAG_NONFINITE);
+    notconv = notconv || !c->host_st[i].converged;
+  }
+  if (nonfinite) return fail(c, EP_TV_E_NONFINITE, "non-finite EP state");
+  if (use_tol && notconv) return EP_TV_W_NOT_CONVERGED;
+  return EP_TV_OK;
+}
+
+int ep_tv_get_sites(ep_tv_ctx* c, float* const* d_out) {
+  if (!c || !d_out) return EP_TV_E_ARG;
+  int rc = set_tab(c, d_out, c->d_tab0, c->tab_host0);
+  if (rc) return rc;
+  HIPCHK(c, launch_sites_io(cur_sites(c).S, c->d_inst, c->d_tiles, c->L.ntiles, c->d_tab0, 1,
+                            c->stream));
+  return EP_TV_OK;
+}
+
+int ep_tv_set_sites(ep_tv_ctx* c, const float* const* d_in, const double* lambda) {
+  if (!c || !d_in) return EP_TV_E_ARG;
+  if (!c->has_obs) return fail(c, EP_TV_E_STATE, "no observation set");
+  int rc = pull_states(c);
+  if (rc) return rc;
+  for (int i = 0; i < c->n; ++i) {
+    InstState& s = c->host_st[i];
+    if (lambda) {
+      if (!(lambda[i] > 0.0)) return fail(c, EP_TV_E_ARG, "lambda must be > 0");
+      s.lam = s.lam_prev = lambda[i];
+    }
+    s.active = 1u;
+    s.converged = 0;
+    s.sweeps = 0u;
+    s.clamps = 0u;
+    s.flags = 0u;
+    s.cg_total = 0;
+  }
+  HIPCHK(c, hipMemcpyAsync(c->d_st, c->host_st.data(), sizeof(InstState) * c->n,
+                           hipMemcpyHostToDevice, c->stream));
+  rc = set_tab(c, const_cast<float* const*>(d_in), c->d_tab0, c->tab_host0);
+  if (rc) return rc;
+  HIPCHK(c, launch_sites_io(cur_sites(c).S, c->d_inst, c->d_tiles, c->L.ntiles, c->d_tab0, 0,
+                            c->stream));
+  HIPCHK(c, lik_resume(c->lik, c->stream));
+  return EP_TV_OK;
+}
+
+int ep_tv_get_stats(ep_tv_ctx* c, ep_tv_stats* stats) {
+  if (!c || !stats) return EP_TV_E_ARG;
+  int rc = pull_states(c);
+  if (rc) return rc;
+  fill_stats(c, stats);
+  return EP_TV_OK;
+}
+
+int ep_tv_tilted_moments(int32_t n, const float* d_m, const float* d_s, float lambda, float* d_rho,
+                         float* d_delta, float* d_eabs, void* stream) {
+  if (n < 0 || (n > 0 && (!d_m || !d_s || !d_rho || !d_delta || !d_eabs)) || !(lambda >= 0.f))
+    return EP_TV_E_ARG;
+  if (launch_tilted(n, d_m, d_s, lambda, d_rho, d_delta, d_eabs,
+                    reinterpret_cast<hipStream_t>(stream)) != hipSuccess)
+    return EP_TV_E_HIP;
+  return EP_TV_OK;
+}
+
+int ep_tv_set_timing(ep_tv_ctx* c, int32_t enable) {
+  if (!c) return EP_TV_E_ARG;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  timing_clear(c);
+  lik_timing(c->lik, enable != 0, true);
+  c->timing = enable != 0;
+  return EP_TV_OK;
+}
+
+int ep_tv_get_timing(ep_tv_ctx* c, ep_tv_timing* out) {
+  if (!c || !out) return EP_TV_E_ARG;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  std::memset(out, 0, sizeof(*out));
+  for (auto& pr : c->ev_sweep) {
+    float ms = 0.f;
+    HIPCHK(c, hipEventElapsedTime(&ms, c->ev_pool[pr.first], c->ev_pool[pr.second]));
+    out->sweep_ms += ms;
+    out->sweep_launches += 1;
+  }
+  for (auto& pr : c->ev_lik) {
+    float ms = 0.f;
+    HIPCHK(c, hipEventElapsedTime(&ms, c->ev_pool[pr.first], c->ev_pool[pr.second]));
+    out->lik_ms += ms;
+    out->lik_updates += 1;
+  }
+  double ams = 0.0;
+  int an = 0;
+  HIPCHK(c, lik_timing_read(c->lik, ams, an));
+  out->apply_ms = ams;
+  out->apply_launches = an;
+  return EP_TV_OK;
+}
+
+const char* ep_tv_last_error(const ep_tv_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+void ep_tv_destroy(ep_tv_ctx* c) {
+  if (!c) return;
+  if (c->stream || true) (void)hipStreamSynchronize(c->stream);
+  lik_destroy(c->lik);
+  for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
+  delete c;
+}
+
+}  // extern "C"

@@ -1,0 +1,243 @@
+// Element-wise and reduction kernels around the sweep: cold initialisation
+// (initialisation line of Algorithm 1), per-instance finalisation of a sweep
+// (EM update lambda = N / a_bar_u of Algorithm 2 and the convergence rule),
+// the gather of the global approximation (Eq. (Q_x_final)), site checkpoint
+// copies and the observation range.
+//
+// Element-wise kernels walk the same tile list as the sweep (one tile = the
+// 124 interior columns of a strip times one chunk of rows), one block per tile.
+#include "ep_tv_internal.h"
+
+namespace eptv {
+
+struct TileBox {
+  int c0, c1, r0, r1;
+};
+
+__device__ __forceinline__ TileBox tile_box(const int4 td, const InstDev& I) {
+  TileBox b;
+  b.c0 = td.y * kStripInt;
+  b.c1 = min(b.c0 + kStripInt, I.W);
+  b.r0 = td.z * I.chunk_rows;
+  b.r1 = min(b.r0 + I.chunk_rows, I.H);
+  return b;
+}
+
+// Pixel (r, c) is touched by some pair of colour class k (0-based kk = k-1).
+__device__ __forceinline__ bool covered(int kk, int r, int c, const InstDev& I) {
+  if (I.bnd == BND_PERIODIC) return true;
+  switch (kk) {
+    case 0: return (c & 1) ? true : (c + 1 < I.W);
+    case 1: return (c & 1) ? (c + 1 < I.W) : (c >= 1);
+    case 2: return (r & 1) ? true : (r + 1 < I.H);
+    default: return (r & 1) ? (r + 1 < I.H) : (r >= 1);
+  }
+}
+
+struct SitePtrs {
+  float2* S[5];
+};
+
+__global__ __launch_bounds__(256) void k_init_cold(SitePtrs sp, const float* __restrict__ y_pix,
+                                                   const InstDev* __restrict__ inst,
+                                                   const int4* __restrict__ tiles) {
+  const int4 td = tiles[blockIdx.x];
+  const InstDev I = inst[td.x];
+  const TileBox b = tile_box(td, I);
+  const int cols = b.c1 - b.c0;
+  const int n = cols * (b.r1 - b.r0);
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    const int r = b.r0 + i / cols;
+    const int c = b.c0 + i % cols;
+    const long long p = I.off + (long long)r * I.pitch + c;
+    const float yv = y_pix[p];
+    sp.S[0][p] = make_float2(I.inv_xi, yv * I.inv_xi);
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk)
+      sp.S[kk + 1][p] = covered(kk, r, c, I) ? make_float2(kSiteInitPrec, 0.f) : make_float2(0.f, 0.f);
+  }
+}
+
+hipError_t launch_init_cold(float2* const S[5], const float* y_pix, const InstDev* inst,
+                            InstState* st, const int4* tiles, int ntiles, hipStream_t s) {
+  (void)st;
+  SitePtrs sp;
+  for (int k = 0; k < 5; ++k) sp.S[k] = S[k];
+  if (ntiles == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_init_cold, dim3(ntiles), dim3(256), 0, s, sp, y_pix, inst, tiles);
+  return hipGetLastError();
+}
+
+// One block per instance: deterministic fixed-shape reduction of the sweep's
+// per-tile partials, then lambda / convergence / counters.
+__global__ __launch_bounds__(256) void k_finalize(const InstDev* __restrict__ inst,
+                                                  InstState* __restrict__ st, SweepArgs a, int em,
+                                                  double tol) {
+  __shared__ double se[256];
+  __shared__ float sm[256], sv[256];
+  __shared__ unsigned sc[256], sf[256];
+  const int i = blockIdx.x;
+  const InstDev I = inst[i];
+  InstState& S = st[i];
+  if (!S.active) return;   // frozen before this sweep: nothing ran
+  double e = 0.0;
+  float dm = 0.f, dv = 0.f;
+  unsigned cl = 0u, fl = 0u;
+  for (int t = threadIdx.x; t < I.ntiles; t += blockDim.x) {
+    const int g = I.tile0 + t;
+    e += a.part_eabs[g];
+    dm = fmaxf(dm, a.part_dmu[g]);
+    dv = fmaxf(dv, a.part_dv[g]);
+    cl += a.part_clamp[g];
+    fl |= a.part_flags[g];
+  }
+  se[threadIdx.x] = e; sm[threadIdx.x] = dm; sv[threadIdx.x] = dv; sc[threadIdx.x] = cl;
+  sf[threadIdx.x] = fl;
+  __syncthreads();
+  for (int w = 128; w >= 1; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      se[threadIdx.x] += se[threadIdx.x + w];
+      sm[threadIdx.x] = fmaxf(sm[threadIdx.x], sm[threadIdx.x + w]);
+      sv[threadIdx.x] = fmaxf(sv[threadIdx.x], sv[threadIdx.x + w]);
+      sc[threadIdx.x] += sc[threadIdx.x + w];
+      sf[threadIdx.x] |= sf[threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double abar = se[0];
+    S.abar = abar;
+    S.clamps += sc[0];
+    S.flags |= sf[0];
+    S.sweeps += 1;
+    S.lam_prev = S.lam;
+    if (em && abar > 0.0) S.lam = (double)I.npix / abar;
+    S.dmu = (double)sm[0] / (S.yrange > 0.0 ? S.yrange : 1.0);
+    S.dv = (double)sv[0];
+    if (S.flags & FLAG_NONFINITE) {
+      S.active = 0u;
+    } else if (tol > 0.0) {
+      const double dl = fabs(S.lam / S.lam_prev - 1.0);
+      if (S.dmu <= tol && S.dv <= 10.0 * tol && (!em || dl <= tol)) {
+        S.converged = 1;
+        S.active = 0u;
+      }
+    }
+  }
+}
+
+hipError_t launch_finalize(const InstDev* inst, InstState* st, int n, const SweepArgs& a, int em,
+                           double tol, hipStream_t s) {
+  hipLaunchKernelGGL(k_finalize, dim3(n), dim3(256), 0, s, inst, st, a, em, tol);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void k_marginals(SitePtrs sp, const InstDev* __restrict__ inst,
+                                                   const int4* __restrict__ tiles,
+                                                   float* const* __restrict__ mean_tab,
+                                                   float* const* __restrict__ var_tab) {
+  const int4 td = tiles[blockIdx.x];
+  const InstDev I = inst[td.x];
+  const TileBox b = tile_box(td, I);
+  float* mo = mean_tab ? mean_tab[td.x] : nullptr;
+  float* vo = var_tab ? var_tab[td.x] : nullptr;
+  const int cols = b.c1 - b.c0;
+  const int n = cols * (b.r1 - b.r0);
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    const int r = b.r0 + i / cols;
+    const int c = b.c0 + i % cols;
+    const long long p = I.off + (long long)r * I.pitch + c;
+    double t = 0.0, e = 0.0;
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+      const float2 v = sp.S[k][p];
+      t += (double)v.x;
+      e += (double)v.y;
+    }
+    const long long q = (long long)r * I.W + c;
+    if (mo) mo[q] = (float)(e / t);
+    if (vo) vo[q] = (float)(1.0 / t);
+  }
+}
+
+hipError_t launch_marginals(float2* const S[5], const InstDev* inst, const int4* tiles, int ntiles,
+                            float* const* d_mean_tab, float* const* d_var_tab, hipStream_t s) {
+  SitePtrs sp;
+  for (int k = 0; k < 5; ++k) sp.S[k] = S[k];
+  if (ntiles == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_marginals, dim3(ntiles), dim3(256), 0, s, sp, inst, tiles, d_mean_tab,
+                     d_var_tab);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void k_sites_io(SitePtrs sp, const InstDev* __restrict__ inst,
+                                                  const int4* __restrict__ tiles,
+                                                  float* const* __restrict__ tab, int to_user) {
+  const int4 td = tiles[blockIdx.x];
+  const InstDev I = inst[td.x];
+  const TileBox b = tile_box(td, I);
+  float* u = tab[td.x];
+  const long long plane = (long long)I.H * I.W;
+  const int cols = b.c1 - b.c0;
+  const int n = cols * (b.r1 - b.r0);
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    const int r = b.r0 + i / cols;
+    const int c = b.c0 + i % cols;
+    const long long p = I.off + (long long)r * I.pitch + c;
+    const long long q = (long long)r * I.W + c;
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+      if (to_user) {
+        const float2 v = sp.S[k][p];
+        u[(2 * k) * plane + q] = v.x;
+        u[(2 * k + 1) * plane + q] = v.y;
+      } else {
+        sp.S[k][p] = make_float2(u[(2 * k) * plane + q], u[(2 * k + 1) * plane + q]);
+      }
+    }
+  }
+}
+
+hipError_t launch_sites_io(float2* const S[5], const InstDev* inst, const int4* tiles, int ntiles,
+                           float* const* d_tab, int to_user, hipStream_t s) {
+  SitePtrs sp;
+  for (int k = 0; k < 5; ++k) sp.S[k] = S[k];
+  if (ntiles == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_sites_io, dim3(ntiles), dim3(256), 0, s, sp, inst, tiles, d_tab, to_user);
+  return hipGetLastError();
+}
+
+// max - min of the pixel-space observation, one block per instance.
+__global__ __launch_bounds__(1024) void k_yrange(const float* __restrict__ y_pix,
+                                                 const InstDev* __restrict__ inst,
+                                                 InstState* __restrict__ st) {
+  __shared__ float smin[1024], smax[1024];
+  const InstDev I = inst[blockIdx.x];
+  float lo = 3.0e38f, hi = -3.0e38f;
+  const long long n = (long long)I.H * I.W;
+  for (long long i = threadIdx.x; i < n; i += blockDim.x) {
+    const int r = (int)(i / I.W), c = (int)(i % I.W);
+    const float v = y_pix[I.off + (long long)r * I.pitch + c];
+    lo = fminf(lo, v);
+    hi = fmaxf(hi, v);
+  }
+  smin[threadIdx.x] = lo;
+  smax[threadIdx.x] = hi;
+  __syncthreads();
+  for (int w = 512; w >= 1; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      smin[threadIdx.x] = fminf(smin[threadIdx.x], smin[threadIdx.x + w]);
+      smax[threadIdx.x] = fmaxf(smax[threadIdx.x], smax[threadIdx.x + w]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) st[blockIdx.x].yrange = (double)smax[0] - (double)smin[0];
+}
+
+hipError_t launch_yrange(const float* y_pix, const InstDev* inst, InstState* st, int n,
+                         hipStream_t s) {
+  hipLaunchKernelGGL(k_yrange, dim3(n), dim3(1024), 0, s, y_pix, inst, st);
+  return hipGetLastError();
+}
+
+}  // namespace eptv

@@ -1,0 +1,379 @@
+// Fused EP sweep over the four colour classes of pixel pairs (Algorithm 1,
+// inner loop over k = 1..4, with all pairs of a class in parallel).
+//
+// Dependency structure used for the fusion.  V1 (horizontal, left column even)
+// and V2 (horizontal, left column odd) only couple pixels of one row; V3
+// (vertical, top row even) and V4 (vertical, top row odd) only pixels of one
+// column.  The state of a pixel after the four classes therefore depends on
+// pixels at most 2 columns and 2 rows away.  One wave owns a vertical strip of
+// 128 columns (2 per lane; lane l holds columns c0-2+2l and c0-1+2l, so every V1
+// pair is inside a lane) of which the middle 124 are written, and marches down a
+// chunk of rows two at a time:
+//
+//   load rows (r, r+1)  ->  V1 on both rows (lane-local)
+//                       ->  V2 on both rows (pair = lane's right pixel and the
+//                           next lane's left pixel; cavities and results cross
+//                           lanes by shuffles)
+//                       ->  V3 on (r, r+1) (lane-local)
+//                       ->  V4 on (r-1, r) with row r-1 carried from the
+//                           previous step, after which rows r-1 and r are final
+//                           and are stored.
+//
+// A chunk of rows [R0, R1) loads rows R0-2 .. R1+1; halo pixels are recomputed,
+// never stored, so every pixel is written by exactly one wave; all reads come
+// from the previous sweep's buffer and all writes go to the other one.  Each edge's
+// E|u| (for EM) and each clamp are counted by the wave that stores the edge's
+// first (left/top) pixel.  HBM traffic per sweep: 5 sites read (40 B/px) and 4
+// written (32 B/px).
+#include "ep_tv_internal.h"
+#include "tilted.h"
+
+namespace eptv {
+
+struct Px {
+  float t[5];
+  float e[5];
+};
+
+template <int K>
+__device__ __forceinline__ void cavity(const Px& p, float& c, float& m) {
+  // Leave-one-out sums of the other four sites' natural parameters (Q / q_k,
+  // Sec. III-B), accumulated in FP64 so the mean's numerator cannot cancel.
+  double t = 0.0, e = 0.0;
+#pragma unroll
+  for (int l = 0; l < 5; ++l) {
+    if (l != K) {
+      t += (double)p.t[l];
+      e += (double)p.e[l];
+    }
+  }
+  c = frcp((float)t);
+  m = (float)e * c;
+}
+
+struct PairOut {
+  float ti, ei, tj, ej;  // new site (tau, eta) for the two endpoints, clamped
+  bool ki, kj;           // clamped?
+  float eabs;
+};
+
+// Tilted moments of u = x_i - x_j, Gehre-Jin projection onto (x_i, x_j) and
+// the site update of Eq. (update_qk_x) in the equivalent cancellation-free
+// form tau_i = rho / (s - rho c_i), eta_i = tau_i E_i + delta / s (and i<->j,
+// delta -> -delta); variance clamp of Sec. III-C at 1e8.
+__device__ __forceinline__ PairOut pair_core(float ci, float mi, float cj, float mj, float lam) {
+  const float s = ci + cj;
+  const Tilt T = laplace_tilt(mi - mj, s, lam);
+  const float dels = T.delta * frcp(s);
+  const float Ei = mi + dels * ci;
+  const float Ej = mj - dels * cj;
+  PairOut o;
+  o.ti = T.rho * frcp(s - T.rho * ci);
+  o.tj = T.rho * frcp(s - T.rho * cj);
+  o.ki = o.ti < kPrecFloor;
+  o.kj = o.tj < kPrecFloor;
+  o.ti = o.ki ? kPrecFloor : o.ti;
+  o.tj = o.kj ? kPrecFloor : o.tj;
+  o.ei = o.ti * Ei + dels;
+  o.ej = o.tj * Ej - dels;
+  o.eabs = T.eabs;
+  return o;
+}
+
+template <int K>
+__device__ __forceinline__ void damp(Px& p, float tn, float en, float alpha) {
+  p.t[K] = alpha * tn + (1.0f - alpha) * p.t[K];
+  p.e[K] = alpha * en + (1.0f - alpha) * p.e[K];
+}
+
+struct Acc {
+  double eabs;
+  unsigned clamps;
+};
+
+// Pair inside one lane (V1 on a row, V3/V4 on a column).
+template <int K>
+__device__ __forceinline__ void pair_local(Px& P, Px& Q, bool exists, bool cnt_edge, bool cnt_p,
+                                           bool cnt_q, float lam, float alpha, Acc& acc) {
+  float ci, mi, cj, mj;
+  cavity<K>(P, ci, mi);
+  cavity<K>(Q, cj, mj);
+  const PairOut o = pair_core(ci, mi, cj, mj, lam);
+  if (exists) {
+    damp<K>(P, o.ti, o.ei, alpha);
+    damp<K>(Q, o.tj, o.ej, alpha);
+    if (cnt_edge) acc.eabs += (double)o.eabs;
+    acc.clamps += (cnt_p && o.ki ? 1u : 0u) + (cnt_q && o.kj ? 1u : 0u);
+  }
+}
+
+// V2 pair: this lane's right pixel R with the next lane's left pixel.
+// exists: the pair (R, next L) exists (evaluated by the owning lane).
+__device__ __forceinline__ void pair_v2(Px& L, Px& R, bool exists, bool cnt_edge, bool cnt_r,
+                                        bool cnt_l, float lam, float alpha, Acc& acc, int lane) {
+  float cl, ml;
+  cavity<2>(L, cl, ml);
+  const float cj = __shfl_down(cl, 1, kWave);
+  const float mj = __shfl_down(ml, 1, kWave);
+  float ci, mi;
+  cavity<2>(R, ci, mi);
+  const PairOut o = pair_core(ci, mi, cj, mj, lam);
+  // hand the partner's new site back to the lane that owns it
+  const float tj = __shfl_up(o.tj, 1, kWave);
+  const float ej = __shfl_up(o.ej, 1, kWave);
+  const int bits = __shfl_up((exists ? 1 : 0) | (o.kj ? 2 : 0), 1, kWave);
+  if (exists) {
+    damp<2>(R, o.ti, o.ei, alpha);
+    if (cnt_edge) acc.eabs += (double)o.eabs;
+    acc.clamps += (cnt_r && o.ki) ? 1u : 0u;
+  }
+  if (lane > 0 && (bits & 1)) {
+    damp<2>(L, tj, ej, alpha);
+    acc.clamps += (cnt_l && (bits & 2)) ? 1u : 0u;
+  }
+}
+
+__device__ __forceinline__ void set_dummy(Px& p) {
+#pragma unroll
+  for (int l = 0; l < 5; ++l) {
+    p.t[l] = 1.0f;
+    p.e[l] = 0.0f;
+  }
+}
+
+__device__ __forceinline__ void load_row(const SweepArgs& a, long long idx, bool ok, bool okR,
+                                         Px& L, Px& R) {
+  if (ok) {
+    const float2* S[5] = {a.S0, a.I1, a.I2, a.I3, a.I4};
+#pragma unroll
+    for (int l = 0; l < 5; ++l) {
+      const float4 v = *reinterpret_cast<const float4*>(S[l] + idx);
+      L.t[l] = v.x;
+      L.e[l] = v.y;
+      R.t[l] = v.z;
+      R.e[l] = v.w;
+    }
+    if (!okR) set_dummy(R);
+  } else {
+    set_dummy(L);
+    set_dummy(R);
+  }
+}
+
+__device__ __forceinline__ void store_row(const SweepArgs& a, long long idx, bool wL, bool wR,
+                                          const Px& L, const Px& R) {
+  float2* S[4] = {a.O1, a.O2, a.O3, a.O4};
+  if (wL && wR) {
+#pragma unroll
+    for (int l = 0; l < 4; ++l)
+      *reinterpret_cast<float4*>(S[l] + idx) =
+          make_float4(L.t[l + 1], L.e[l + 1], R.t[l + 1], R.e[l + 1]);
+  } else if (wL) {
+#pragma unroll
+    for (int l = 0; l < 4; ++l) S[l][idx] = make_float2(L.t[l + 1], L.e[l + 1]);
+  } else if (wR) {
+#pragma unroll
+    for (int l = 0; l < 4; ++l) S[l][idx + 1] = make_float2(R.t[l + 1], R.e[l + 1]);
+  }
+}
+
+__device__ __forceinline__ void totals(const Px& p, float& mu, float& v) {
+  float t = 0.f, e = 0.f;
+#pragma unroll
+  for (int l = 0; l < 5; ++l) {
+    t += p.t[l];
+    e += p.e[l];
+  }
+  v = 1.0f / t;
+  mu = e * v;
+}
+
+__device__ __forceinline__ int wrap(int i, int n) {
+  int r = i % n;
+  return r < 0 ? r + n : r;
+}
+
+template <bool DELTA>
+__global__ __launch_bounds__(256) void k_tv_sweep(SweepArgs a) {
+  const int wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int tile = xcd_remap(blockIdx.x, gridDim.x) * kWavesPerBlock + wave;
+  if (tile >= a.ntiles) return;
+  const int4 td = a.tiles[tile];
+  const InstDev I = a.inst[td.x];
+  const InstState& ST = a.st[td.x];
+  if (!ST.active) {
+    if (lane == 0) {
+      a.part_eabs[tile] = 0.0;
+      a.part_dmu[tile] = 0.f;
+      a.part_dv[tile] = 0.f;
+      a.part_clamp[tile] = 0u;
+      a.part_flags[tile] = 0u;
+    }
+    return;
+  }
+  const float lam = (float)ST.lam;
+  const float alpha = I.alpha;
+  const bool per = I.bnd == BND_PERIODIC;
+  const int W = I.W, H = I.H;
+  const int c0 = td.y * kStripInt;
+  const int cl = c0 - 2 + 2 * lane;
+  const int cr = cl + 1;
+  bool vL, vR, vN;
+  int gcl;
+  if (per) {
+    vL = vR = vN = true;
+    gcl = wrap(cl, W);
+  } else {
+    vL = cl >= 0 && cl < W;
+    vR = cr >= 0 && cr < W;
+    vN = cl + 2 >= 0 && cl + 2 < W;
+    gcl = cl;
+  }
+  const bool wL = vL && cl >= c0 && cl < c0 + kStripInt && cl < W;
+  const bool wR = vR && cr >= c0 && cr < c0 + kStripInt && cr < W;
+  const bool v1col = vL && vR;
+  const bool v2col = vR && vN && lane < kWave - 1;
+
+  const int R0 = td.z * I.chunk_rows;
+  const int R1 = min(R0 + I.chunk_rows, H);
+
+  Acc acc{0.0, 0u};
+  float dmu = 0.f, dv = 0.f;
+  unsigned flags = 0u;
+  Px aL, aR;                    // row r-1 after V3 (carried)
+  float aomL = 0.f, aovL = 1.f, aomR = 0.f, aovR = 1.f;
+
+  for (int r = R0 - 2; r <= R1; r += 2) {
+    const bool bv = per || (r >= 0 && r < H);
+    const bool cv = per || (r + 1 >= 0 && r + 1 < H);
+    const int gb = per ? wrap(r, H) : r;
+    const int gc = per ? wrap(r + 1, H) : r + 1;
+    const bool bint = r >= R0 && r < R1;
+    const bool cint = r + 1 >= R0 && r + 1 < R1;
+    Px bL, bR, cL, cR;
+    const long long ib = I.off + (long long)gb * I.pitch + gcl;
+    const long long ic = I.off + (long long)gc * I.pitch + gcl;
+    load_row(a, ib, bv && vL, vR, bL, bR);
+    load_row(a, ic, cv && vL, vR, cL, cR);
+    float bomL = 0.f, bovL = 1.f, bomR = 0.f, bovR = 1.f, comL = 0.f, covL = 1.f, comR = 0.f,
+          covR = 1.f;
+    if (DELTA) {
+      totals(bL, bomL, bovL);
+      totals(bR, bomR, bovR);
+      totals(cL, comL, covL);
+      totals(cR, comR, covR);
+    }
+    // V1 on both rows
+    pair_local<1>(bL, bR, bv && v1col, bint && wL, bint && wL, bint && wR, lam, alpha, acc);
+    pair_local<1>(cL, cR, cv && v1col, cint && wL, cint && wL, cint && wR, lam, alpha, acc);
+    // V2 on both rows
+    pair_v2(bL, bR, bv && v2col, bint && wR, bint && wR, bint && wL, lam, alpha, acc, lane);
+    pair_v2(cL, cR, cv && v2col, cint && wR, cint && wR, cint && wL, lam, alpha, acc, lane);
+    // V3 on (r, r+1)
+    {
+      const bool ex = bv && cv && (per || r + 1 < H);
+      pair_local<3>(bL, cL, ex && vL, bint && wL, bint && wL, cint && wL, lam, alpha, acc);
+      pair_local<3>(bR, cR, ex && vR, bint && wR, bint && wR, cint && wR, lam, alpha, acc);
+    }
+    // V4 on (r-1, r), then rows r-1 and r are final
+    if (r > R0 - 2) {
+      const bool av = per || (r - 1 >= 0 && r - 1 < H);
+      const bool aint = r - 1 >= R0 && r - 1 < R1;
+      const bool ex = av && bv;
+      pair_local<4>(aL, bL, ex && vL, aint && wL, aint && wL, bint && wL, lam, alpha, acc);
+      pair_local<4>(aR, bR, ex && vR, aint && wR, aint && wR, bint && wR, lam, alpha, acc);
+      if (aint) {
+        const int ga = per ? wrap(r - 1, H) : r - 1;
+        store_row(a, I.off + (long long)ga * I.pitch + gcl, wL, wR, aL, aR);
+        if (DELTA) {
+          float m1, v1;
+          if (wL) {
+            totals(aL, m1, v1);
+            dmu = fmaxf(dmu, fabsf(m1 - aomL));
+            dv = fmaxf(dv, fabsf(v1 / aovL - 1.f));
+            if (!(fabsf(m1) < 3.0e38f) || !(v1 > 0.f && v1 < 3.0e38f)) flags |= FLAG_NONFINITE;
+          }
+          if (wR) {
+            totals(aR, m1, v1);
+            dmu = fmaxf(dmu, fabsf(m1 - aomR));
+            dv = fmaxf(dv, fabsf(v1 / aovR - 1.f));
+            if (!(fabsf(m1) < 3.0e38f) || !(v1 > 0.f && v1 < 3.0e38f)) flags |= FLAG_NONFINITE;
+          }
+        }
+      }
+    }
+    if (bint) {
+      store_row(a, ib, wL, wR, bL, bR);
+      if (DELTA) {
+        float m1, v1;
+        if (wL) {
+          totals(bL, m1, v1);
+          dmu = fmaxf(dmu, fabsf(m1 - bomL));
+          dv = fmaxf(dv, fabsf(v1 / bovL - 1.f));
+          if (!(fabsf(m1) < 3.0e38f) || !(v1 > 0.f && v1 < 3.0e38f)) flags |= FLAG_NONFINITE;
+        }
+        if (wR) {
+          totals(bR, m1, v1);
+          dmu = fmaxf(dmu, fabsf(m1 - bomR));
+          dv = fmaxf(dv, fabsf(v1 / bovR - 1.f));
+          if (!(fabsf(m1) < 3.0e38f) || !(v1 > 0.f && v1 < 3.0e38f)) flags |= FLAG_NONFINITE;
+        }
+      }
+    }
+    aL = cL;
+    aR = cR;
+    aomL = comL; aovL = covL; aomR = comR; aovR = covR;
+  }
+
+  // wave reductions (fixed order -> deterministic)
+  double e = acc.eabs;
+  unsigned ncl = acc.clamps;
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+    e += __shfl_xor(e, off, kWave);
+    ncl += __shfl_xor(ncl, off, kWave);
+    dmu = fmaxf(dmu, __shfl_xor(dmu, off, kWave));
+    dv = fmaxf(dv, __shfl_xor(dv, off, kWave));
+    flags |= __shfl_xor(flags, off, kWave);
+  }
+  if (lane == 0) {
+    a.part_eabs[tile] = e;
+    a.part_clamp[tile] = ncl;
+    a.part_dmu[tile] = dmu;
+    a.part_dv[tile] = dv;
+    a.part_flags[tile] = flags;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_tilted(int n, const float* __restrict__ m,
+                                                const float* __restrict__ s, float lam,
+                                                float* __restrict__ rho, float* __restrict__ del,
+                                                float* __restrict__ eabs) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const Tilt T = laplace_tilt(m[i], s[i], lam);
+  rho[i] = T.rho;
+  del[i] = T.delta;
+  eabs[i] = T.eabs;
+}
+
+hipError_t launch_tilted(int n, const float* m, const float* s, float lam, float* rho, float* del,
+                         float* eabs, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_tilted, dim3((n + 255) / 256), dim3(256), 0, st, n, m, s, lam, rho, del,
+                     eabs);
+  return hipGetLastError();
+}
+
+hipError_t launch_tv_sweep(const SweepArgs& a, bool want_delta, hipStream_t s) {
+  const int blocks = (a.ntiles + kWavesPerBlock - 1) / kWavesPerBlock;
+  if (blocks == 0) return hipSuccess;
+  if (want_delta)
+    hipLaunchKernelGGL(k_tv_sweep<true>, dim3(blocks), dim3(256), 0, s, a);
+  else
+    hipLaunchKernelGGL(k_tv_sweep<false>, dim3(blocks), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+}  // namespace eptv

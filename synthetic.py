@@ -52,7 +52,6 @@ def piecewise_image(h: int, w: int, n_shapes: int, rng: np.random.Generator,
     """
     s = min(h, w)
     img = np.zeros((h, w), dtype=np.float64)
-    rr, cc = np.mgrid[0:h, 0:w]
     lo, hi = max(1, math.ceil(s / 16)), max(1, math.ceil(s / 4))
     for _ in range(n_shapes):
         is_disk = (mode == "paint") and (rng.random() < disk_fraction)
@@ -61,18 +60,24 @@ def piecewise_image(h: int, w: int, n_shapes: int, rng: np.random.Generator,
             r0 = rng.random() * h
             c0 = rng.random() * w
             rad = rng.uniform(s / 32.0, s / 8.0)
+            ra, rb = max(0, int(math.floor(r0 - rad)) - 1), min(h, int(math.ceil(r0 + rad)) + 1)
+            ca, cb = max(0, int(math.floor(c0 - rad)) - 1), min(w, int(math.ceil(c0 + rad)) + 1)
+            rr, cc = np.mgrid[ra:rb, ca:cb]
             m = (rr + 0.5 - r0) ** 2 + (cc + 0.5 - c0) ** 2 <= rad * rad
+            if mode == "sum":
+                img[ra:rb, ca:cb][m] += val
+            else:
+                img[ra:rb, ca:cb][m] = val
         else:
             hh = int(rng.integers(lo, hi + 1))
             ww = int(rng.integers(lo, hi + 1))
             r0 = int(rng.integers(0, h))
             c0 = int(rng.integers(0, w))
-            m = np.zeros((h, w), dtype=bool)
-            m[r0:min(h, r0 + hh), c0:min(w, c0 + ww)] = True
-        if mode == "sum":
-            img[m] += val
-        else:
-            img[m] = val
+            sl = (slice(r0, min(h, r0 + hh)), slice(c0, min(w, c0 + ww)))
+            if mode == "sum":
+                img[sl] += val
+            else:
+                img[sl] = val
     return img
 
 

@@ -1,0 +1,68 @@
+"""CPU checks of the C-ABI library: it loads, exports every symbol that
+include/ep_tv.h declares, and validates descriptors on the host."""
+import ctypes
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+from paper_2110_01585_amd import _native as N
+from paper_2110_01585_amd import ProblemSpec, ep_tv_workspace_bytes, EPTVError
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ep_tv.h")
+
+
+def _declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"\b(ep_tv_[a-z_]+)\s*\(", src)
+    return sorted(set(names))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = N.lib()
+    declared = _declared()
+    assert len(declared) >= 14
+    for name in declared:
+        assert hasattr(lib, name), name
+        assert name in N.SIGNATURES, f"binding lacks {name}"
+    out = subprocess.run(["nm", "-D", "--defined-only", N.LIB_PATH], capture_output=True, text=True).stdout
+    exported = set(re.findall(r"\bT (ep_tv_\w+)", out))
+    assert set(declared) <= exported
+
+
+def test_version():
+    assert N.lib().ep_tv_version().decode().startswith("eptv-gfx950")
+
+
+def test_workspace_bytes_and_validation():
+    ok = ProblemSpec(128, 128, noise_var=0.01, lambda0=10.0, damping=0.5)
+    b1 = ep_tv_workspace_bytes([ok])
+    b2 = ep_tv_workspace_bytes([ok, ProblemSpec(300, 17)])
+    assert b1 >= 128 * 128 * (5 * 8 + 4) and b2 > b1
+    bad = [ProblemSpec(0, 5), ProblemSpec(5, 5, noise_var=0.0), ProblemSpec(5, 5, lambda0=-1),
+           ProblemSpec(5, 5, damping=0.0), ProblemSpec(5, 5, damping=1.5),
+           ProblemSpec(5, 6, boundary=N.BND_PERIODIC),
+           ProblemSpec(8, 8, op=N.OP_BLUR_PERIODIC, taps=np.ones((4, 3), np.float32)),
+           ProblemSpec(8, 8, op=N.OP_BLUR_PERIODIC),
+           ProblemSpec(12, 8, op=N.OP_DFT_MASK, mask=np.ones((12, 8), np.uint8)),
+           ProblemSpec(8, 8, op=7)]
+    for s in bad:
+        with pytest.raises(EPTVError):
+            ep_tv_workspace_bytes([s])
+
+
+def test_null_arguments_are_rejected():
+    lib = N.lib()
+    out = ctypes.c_size_t(0)
+    assert lib.ep_tv_workspace_bytes(None, 1, ctypes.byref(out)) == N.EP_TV_E_ARG
+    h = ctypes.c_void_p(None)
+    arr = (N.EpTvProblem * 1)()
+    assert lib.ep_tv_create(arr, 1, None, 0, None, ctypes.byref(h)) == N.EP_TV_E_ARG
+    assert lib.ep_tv_run(None, 1, 0) == N.EP_TV_E_ARG
+    assert lib.ep_tv_solve(None, 1, 0.0, 0, None, None, None) == N.EP_TV_E_ARG
+    assert lib.ep_tv_last_error(None) == b"null context"
+    lib.ep_tv_destroy(None)
