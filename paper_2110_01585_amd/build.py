@@ -19,6 +19,7 @@ CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(PKG, "_build")
 LIBDIR = os.path.join(PKG, "lib")
 LIB = os.path.join(LIBDIR, "libeptv.so")
+INCLUDE = os.path.join(os.path.dirname(PKG), "include")
 ARCH = os.environ.get("EPTV_ARCH", "gfx950")
 
 COMMON = ["-fPIC", "-O3", "-std=c++17", f"--offload-arch={ARCH}",
@@ -40,7 +41,7 @@ def sources():
 
 def _compile(src):
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
-    cmd = [_hipcc(), "-c", src, "-o", obj] + COMMON
+    cmd = [_hipcc(), "-c", src, "-o", obj, f"-I{INCLUDE}"] + COMMON
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed on {src}:\n{r.stdout}\n{r.stderr}")

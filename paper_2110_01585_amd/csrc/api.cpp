@@ -1,6 +1,6 @@
 // Host side of the C ABI declared in include/ep_tv.h: argument validation,
 // workspace layout, the tile list, and the per-sweep launch schedule.
-#include "../../include/ep_tv.h"
+#include "ep_tv.h"
 
 #include <hip/hip_runtime.h>
 
@@ -49,7 +49,7 @@ int pick_chunk_rows(int H, int W) {
   }
   const long long strips = (W + kStripInt - 1) / kStripInt;
   int ch = 32;
-  while (ch > 8 && strips * ((H + ch - 1) / ch) < 4096) ch /= 2;
+  while (ch > 8 && strips * ((H + ch - 1) / ch) < 8192) ch /= 2;
   return ch;
 }
 
@@ -272,6 +272,7 @@ int ep_tv_create(const ep_tv_problem* p, int32_t n, void* d_ws, size_t ws_bytes,
   a.part_dv = reinterpret_cast<float*>(c->ws + c->L.part_v);
   a.part_clamp = reinterpret_cast<unsigned*>(c->ws + c->L.part_c);
   a.part_flags = reinterpret_cast<unsigned*>(c->ws + c->L.part_f);
+
 
   std::vector<InstDev> idev(n);
   std::vector<int4> tiles;

@@ -241,3 +241,4 @@ hipError_t launch_yrange(const float* y_pix, const InstDev* inst, InstState* st,
 }
 
 }  // namespace eptv
+

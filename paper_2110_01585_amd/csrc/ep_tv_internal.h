@@ -22,7 +22,7 @@ constexpr int kStripInt = kStripPx - 4;   // interior columns per strip (2-px ha
 constexpr int kWavesPerBlock = 4;
 constexpr float kPrecFloor = 1e-8f;       // clamp: site variance < 0 or > 1e8 -> 1e8
 constexpr float kSiteInitPrec = 1e-8f;    // initial TV-site variance 1e8
-constexpr int kTailDepth = 24;            // Laplace continued-fraction depth (x >= 3)
+constexpr int kTailDepth = 20;            // Laplace continued-fraction depth (x >= 3)
 constexpr float kTailX = 3.0f;
 
 enum { OP_IDENTITY = 0, OP_BLUR = 1, OP_DFT = 2 };
@@ -79,6 +79,7 @@ __device__ __forceinline__ int xcd_remap(int bid, int nb) {
 
 // ---- launchers (defined in the .hip files) ----
 hipError_t launch_tv_sweep(const SweepArgs& a, bool want_delta, hipStream_t s);
+
 hipError_t launch_tilted(int n, const float* m, const float* s, float lam, float* rho, float* del,
                          float* eabs, hipStream_t st);
 hipError_t launch_init_cold(float2* const S[5], const float* y_pix, const InstDev* inst,

@@ -25,6 +25,8 @@
 // E|u| (for EM) and each clamp are counted by the wave that stores the edge's
 // first (left/top) pixel.  HBM traffic per sweep: 5 sites read (40 B/px) and 4
 // written (32 B/px).
+#include <algorithm>
+
 #include "ep_tv_internal.h"
 #include "tilted.h"
 
@@ -141,23 +143,26 @@ __device__ __forceinline__ void set_dummy(Px& p) {
   }
 }
 
-__device__ __forceinline__ void load_row(const SweepArgs& a, long long idx, bool ok, bool okR,
-                                         Px& L, Px& R) {
-  if (ok) {
-    const float2* S[5] = {a.S0, a.I1, a.I2, a.I3, a.I4};
+struct Raw {
+  float4 v[5];  // the five sites of a lane's pixel pair, as loaded
+};
+
+__device__ __forceinline__ void fetch(const SweepArgs& a, long long idx, bool ok, Raw& R) {
+  const float2* S[5] = {a.S0, a.I1, a.I2, a.I3, a.I4};
 #pragma unroll
-    for (int l = 0; l < 5; ++l) {
-      const float4 v = *reinterpret_cast<const float4*>(S[l] + idx);
-      L.t[l] = v.x;
-      L.e[l] = v.y;
-      R.t[l] = v.z;
-      R.e[l] = v.w;
-    }
-    if (!okR) set_dummy(R);
-  } else {
-    set_dummy(L);
-    set_dummy(R);
+  for (int l = 0; l < 5; ++l)
+    R.v[l] = ok ? *reinterpret_cast<const float4*>(S[l] + idx) : make_float4(1.f, 0.f, 1.f, 0.f);
+}
+
+__device__ __forceinline__ void unpack(const Raw& R, bool okR, Px& L, Px& Rt) {
+#pragma unroll
+  for (int l = 0; l < 5; ++l) {
+    L.t[l] = R.v[l].x;
+    L.e[l] = R.v[l].y;
+    Rt.t[l] = R.v[l].z;
+    Rt.e[l] = R.v[l].w;
   }
+  if (!okR) set_dummy(Rt);
 }
 
 __device__ __forceinline__ void store_row(const SweepArgs& a, long long idx, bool wL, bool wR,
@@ -193,25 +198,13 @@ __device__ __forceinline__ int wrap(int i, int n) {
   return r < 0 ? r + n : r;
 }
 
+// One tile (strip x chunk) of one instance; `tile` and every value derived from
+// the tile descriptor are wave-uniform (scalar registers).
 template <bool DELTA>
-__global__ __launch_bounds__(256) void k_tv_sweep(SweepArgs a) {
-  const int wave = threadIdx.x >> 6;
-  const int lane = threadIdx.x & 63;
-  const int tile = xcd_remap(blockIdx.x, gridDim.x) * kWavesPerBlock + wave;
-  if (tile >= a.ntiles) return;
+__device__ __forceinline__ void sweep_tile(const SweepArgs& a, int tile, int lane) {
   const int4 td = a.tiles[tile];
   const InstDev I = a.inst[td.x];
   const InstState& ST = a.st[td.x];
-  if (!ST.active) {
-    if (lane == 0) {
-      a.part_eabs[tile] = 0.0;
-      a.part_dmu[tile] = 0.f;
-      a.part_dv[tile] = 0.f;
-      a.part_clamp[tile] = 0u;
-      a.part_flags[tile] = 0u;
-    }
-    return;
-  }
   const float lam = (float)ST.lam;
   const float alpha = I.alpha;
   const bool per = I.bnd == BND_PERIODIC;
@@ -244,18 +237,25 @@ __global__ __launch_bounds__(256) void k_tv_sweep(SweepArgs a) {
   Px aL, aR;                    // row r-1 after V3 (carried)
   float aomL = 0.f, aovL = 1.f, aomR = 0.f, aovR = 1.f;
 
+  auto row_ok = [&](int r) { return per || (r >= 0 && r < H); };
+  auto row_idx = [&](int r) {
+    const int g = per ? wrap(r, H) : r;
+    return I.off + (long long)g * I.pitch + gcl;
+  };
   for (int r = R0 - 2; r <= R1; r += 2) {
-    const bool bv = per || (r >= 0 && r < H);
-    const bool cv = per || (r + 1 >= 0 && r + 1 < H);
-    const int gb = per ? wrap(r, H) : r;
-    const int gc = per ? wrap(r + 1, H) : r + 1;
+    const bool bv = row_ok(r);
+    const bool cv = row_ok(r + 1);
     const bool bint = r >= R0 && r < R1;
     const bool cint = r + 1 >= R0 && r + 1 < R1;
+    const long long ib = row_idx(r);
     Px bL, bR, cL, cR;
-    const long long ib = I.off + (long long)gb * I.pitch + gcl;
-    const long long ic = I.off + (long long)gc * I.pitch + gcl;
-    load_row(a, ib, bv && vL, vR, bL, bR);
-    load_row(a, ic, cv && vL, vR, cL, cR);
+    {
+      Raw nb, nc;
+      fetch(a, ib, bv && vL, nb);
+      fetch(a, row_idx(r + 1), cv && vL, nc);
+      unpack(nb, vR, bL, bR);
+      unpack(nc, vR, cL, cR);
+    }
     float bomL = 0.f, bovL = 1.f, bomR = 0.f, bovR = 1.f, comL = 0.f, covL = 1.f, comR = 0.f,
           covR = 1.f;
     if (DELTA) {
@@ -284,8 +284,7 @@ __global__ __launch_bounds__(256) void k_tv_sweep(SweepArgs a) {
       pair_local<4>(aL, bL, ex && vL, aint && wL, aint && wL, bint && wL, lam, alpha, acc);
       pair_local<4>(aR, bR, ex && vR, aint && wR, aint && wR, bint && wR, lam, alpha, acc);
       if (aint) {
-        const int ga = per ? wrap(r - 1, H) : r - 1;
-        store_row(a, I.off + (long long)ga * I.pitch + gcl, wL, wR, aL, aR);
+        store_row(a, row_idx(r - 1), wL, wR, aL, aR);
         if (DELTA) {
           float m1, v1;
           if (wL) {
@@ -346,6 +345,28 @@ __global__ __launch_bounds__(256) void k_tv_sweep(SweepArgs a) {
   }
 }
 
+// One wave per tile; consecutive tiles (vertically adjacent chunks of a strip,
+// which share halo rows) are mapped to the same XCD.
+template <bool DELTA>
+__global__ __launch_bounds__(256) void k_tv_sweep(SweepArgs a) {
+  const int wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int tile = xcd_remap(blockIdx.x, gridDim.x) * kWavesPerBlock + wave;
+  if (tile >= a.ntiles) return;
+  const int4 td = a.tiles[tile];
+  if (!a.st[td.x].active) {
+    if (lane == 0) {
+      a.part_eabs[tile] = 0.0;
+      a.part_dmu[tile] = 0.f;
+      a.part_dv[tile] = 0.f;
+      a.part_clamp[tile] = 0u;
+      a.part_flags[tile] = 0u;
+    }
+    return;
+  }
+  sweep_tile<DELTA>(a, tile, lane);
+}
+
 __global__ __launch_bounds__(256) void k_tilted(int n, const float* __restrict__ m,
                                                 const float* __restrict__ s, float lam,
                                                 float* __restrict__ rho, float* __restrict__ del,
@@ -377,3 +398,4 @@ hipError_t launch_tv_sweep(const SweepArgs& a, bool want_delta, hipStream_t s) {
 }
 
 }  // namespace eptv
+

@@ -3,10 +3,10 @@
 // (Eq. (L1_TV)), and the site update that follows from the Gehre-Jin pair
 // projection and Eq. (update_qk_x).
 //
-// Precision policy: FP32 throughout, except the far tails of the truncated
-// Gaussian components, where the variance follows from Laplace's continued
-// fraction of the Mills ratio evaluated in FP64 (the direct formula cancels
-// there).  The expressions are arranged so that the quantities the site update
+// Precision: FP32.  In the far tails of the truncated Gaussian components the
+// direct formula for the variance cancels catastrophically; there K and r come
+// from Laplace's continued fraction of the Mills ratio, whose evaluation only
+// adds positive terms.  The expressions are arranged so that the quantities the site update
 // needs -- rho = 1 - S_bar/s and delta = m_bar - m -- never come out of a
 // difference of nearly equal numbers:
 //
@@ -37,15 +37,15 @@ struct Tilt {
 
 // (K, r) of a component whose cut lies x >= kTailX standard deviations beyond
 // its mean, by the bottom-up continued fraction K = 1/(x + L),
-// L = 2/(x + 3/(x + ...)), evaluated in FP64.
-__device__ __forceinline__ void tail_cf(float xf, float& K, float& r) {
-  const double x = (double)xf;
-  double t = 0.0;
+// L = 2/(x + 3/(x + ...)).  Every step adds positive numbers, so the
+// recurrence is stable in FP32 (relative error ~ depth * eps) and, unlike the
+// direct formula, never subtracts nearly equal quantities.
+__device__ __forceinline__ void tail_cf(float x, float& K, float& r) {
+  float t = 0.0f;
 #pragma unroll
-  for (int n = kTailDepth; n >= 2; --n) t = (double)n / (x + t);
-  const double Kd = 1.0 / (x + t);
-  K = (float)Kd;
-  r = (float)(x + Kd);
+  for (int n = kTailDepth; n >= 2; --n) t = (float)n * frcp(x + t);
+  K = frcp(x + t);
+  r = x + K;
 }
 
 __device__ __forceinline__ Tilt laplace_tilt(float m, float s, float lam) {
