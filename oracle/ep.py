@@ -126,13 +126,16 @@ def problem_from_synthetic(p, prior="l1", estimator="spectral", boundary=None, o
 
 
 def init_cold(pb: EPProblem) -> EPState:
-    """Initialisation line of Algorithm 1: q_{x,0} = N(H^T y, xi I) (= N(y, xi I)
-    when y lives in pixel space), TV sites with variance 1e8 where covered."""
+    """Initialisation line of Algorithm 1: q_{x,0} = N(y, xi I) when y lives in
+    pixel space (denoising, deconvolution); for the masked DFT, whose y are
+    Fourier coefficients, the pixel-space back-projection H^T y takes its place.
+    TV sites get variance 1e8 where covered."""
     N = pb.N
     tau = np.zeros((5, N))
     eta = np.zeros((5, N))
     tau[0] = 1.0 / pb.xi
-    eta[0] = (pb.hty if pb.op.kind != ops.IDENTITY else np.asarray(pb.y, dtype=np.float64)).ravel() / pb.xi
+    y0 = pb.hty if pb.op.kind == ops.DFT else np.asarray(pb.y, dtype=np.float64)
+    eta[0] = y0.ravel() / pb.xi
     for k in range(4):
         tau[k + 1, pb.covered[k]] = SITE_INIT_PREC
     return EPState(tau=tau, eta=eta, lam=pb.lam0)
