@@ -79,6 +79,9 @@ typedef struct {
   double noise_var;            /* xi > 0, variance of each real observation (CS: of Re and Im) */
   double lambda0;              /* > 0: lambda (fixed, or the EM starting value) */
   double damping;              /* in (0, 1]: weight of the new site value in the damped update */
+  double cg_tol;               /* CG relative residual ||r||/||b|| for the likelihood site; 0 = 1e-8 */
+  int32_t cg_max_iters;        /* CG iteration cap per likelihood-site update; 0 = 200 */
+  int32_t reserved;            /* must be 0 */
 } ep_tv_problem;
 
 /* Per-instance statistics (host struct filled by ep_tv_solve / ep_tv_get_stats). */
@@ -94,6 +97,9 @@ typedef struct {
   double max_dmu_rel;          /* last sweep: max |mu_t - mu_{t-1}| / (max y - min y) */
   double max_dv_rel;           /* last sweep: max |v_t / v_{t-1} - 1| */
   double elapsed_ms;           /* wall time of the ep_tv_solve call (same for all instances) */
+  double lik_precision;        /* last likelihood-site precision gamma (non-identity operators) */
+  double cavity_precision_mean;/* mean cavity precision d_bar of the last likelihood-site update */
+  double cg_rel_residual;      /* ||r|| / ||b|| at the end of the last CG solve */
 } ep_tv_stats;
 
 typedef struct ep_tv_ctx ep_tv_ctx;

@@ -37,7 +37,8 @@ class EpTvProblem(ctypes.Structure):
                 ("blur_h", ctypes.c_int32), ("blur_w", ctypes.c_int32),
                 ("dft_mask", ctypes.POINTER(ctypes.c_uint8)),
                 ("noise_var", ctypes.c_double), ("lambda0", ctypes.c_double),
-                ("damping", ctypes.c_double)]
+                ("damping", ctypes.c_double), ("cg_tol", ctypes.c_double),
+                ("cg_max_iters", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class EpTvStats(ctypes.Structure):
@@ -46,7 +47,8 @@ class EpTvStats(ctypes.Structure):
                 ("status", ctypes.c_int32), ("converged", ctypes.c_int32),
                 ("lambda_", ctypes.c_double), ("a_bar_u", ctypes.c_double),
                 ("max_dmu_rel", ctypes.c_double), ("max_dv_rel", ctypes.c_double),
-                ("elapsed_ms", ctypes.c_double)]
+                ("elapsed_ms", ctypes.c_double), ("lik_precision", ctypes.c_double),
+                ("cavity_precision_mean", ctypes.c_double), ("cg_rel_residual", ctypes.c_double)]
 
 
 class EpTvTiming(ctypes.Structure):

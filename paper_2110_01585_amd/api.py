@@ -33,20 +33,23 @@ class ProblemSpec:
     damping: float = 0.5
     taps: Optional[np.ndarray] = None
     mask: Optional[np.ndarray] = None
+    cg_tol: float = 0.0          # 0 = library default
+    cg_max_iters: int = 0        # 0 = library default
 
 
 _OPS = {"identity": N.OP_IDENTITY, "blur": N.OP_BLUR_PERIODIC, "dft": N.OP_DFT_MASK}
 _BNDS = {"free": N.BND_FREE, "periodic": N.BND_PERIODIC}
 
 
-def spec_from_synthetic(p, lam0=None, damping=None) -> ProblemSpec:
+def spec_from_synthetic(p, lam0=None, damping=None, cg_tol=0.0, cg_max_iters=0) -> ProblemSpec:
     """ProblemSpec of a synthetic.Problem (same fields, C enums)."""
     h, w = p.shape
     return ProblemSpec(h, w, _OPS[p.op], _BNDS[p.boundary], float(p.xi),
                        float(p.lam0 if lam0 is None else lam0),
                        float(p.damping if damping is None else damping),
                        taps=None if p.taps is None else np.asarray(p.taps, np.float32),
-                       mask=None if p.mask is None else np.asarray(p.mask, np.uint8))
+                       mask=None if p.mask is None else np.asarray(p.mask, np.uint8),
+                       cg_tol=cg_tol, cg_max_iters=cg_max_iters)
 
 
 def _problems(specs: Sequence[ProblemSpec]):
@@ -56,6 +59,7 @@ def _problems(specs: Sequence[ProblemSpec]):
         a = arr[i]
         a.height, a.width, a.op, a.boundary = s.height, s.width, s.op, s.boundary
         a.noise_var, a.lambda0, a.damping = s.noise_var, s.lambda0, s.damping
+        a.cg_tol, a.cg_max_iters, a.reserved = s.cg_tol, s.cg_max_iters, 0
         if s.taps is not None:
             t = np.ascontiguousarray(s.taps, dtype=np.float32)
             keep.append(t)
@@ -198,7 +202,8 @@ class Context:
         return {"sweeps": s.sweeps_done, "cg_last": s.cg_iters_last, "cg_total": s.cg_iters_total,
                 "clamps": s.clamp_count, "status": s.status, "converged": bool(s.converged),
                 "lambda": s.lambda_, "a_bar_u": s.a_bar_u, "dmu": s.max_dmu_rel,
-                "dv": s.max_dv_rel, "elapsed_ms": s.elapsed_ms}
+                "dv": s.max_dv_rel, "elapsed_ms": s.elapsed_ms, "gamma": s.lik_precision,
+                "dbar": s.cavity_precision_mean, "cg_rel_residual": s.cg_rel_residual}
 
     # -- conveniences built only from the entry points above --
     def marginals(self):

@@ -63,6 +63,9 @@ const char* validate(const ep_tv_problem& p) {
   if (!(p.noise_var > 0.0) || !std::isfinite(p.noise_var)) return "noise_var must be > 0";
   if (!(p.lambda0 > 0.0) || !std::isfinite(p.lambda0)) return "lambda0 must be > 0";
   if (!(p.damping > 0.0 && p.damping <= 1.0)) return "damping must be in (0, 1]";
+  if (!(p.cg_tol >= 0.0 && p.cg_tol < 1.0)) return "cg_tol must be in [0, 1)";
+  if (p.cg_max_iters < 0 || p.cg_max_iters > 100000) return "cg_max_iters must be in [0, 100000]";
+  if (p.reserved != 0) return "reserved field must be 0";
   if (p.op == EP_TV_OP_BLUR_PERIODIC) {
     if (!p.blur_taps) return "blur operator needs blur_taps";
     if (p.blur_h < 1 || p.blur_w < 1 || p.blur_h % 2 == 0 || p.blur_w % 2 == 0 ||
@@ -304,6 +307,8 @@ int ep_tv_create(const ep_tv_problem* p, int32_t n, void* d_ws, size_t ws_bytes,
       li[i].off = c->ih[i].off;
       li[i].xi = c->ih[i].p.noise_var;
       li[i].damping = c->ih[i].p.damping;
+      li[i].cg_tol = c->ih[i].p.cg_tol > 0.0 ? c->ih[i].p.cg_tol : kCgTol;
+      li[i].cg_max_iters = c->ih[i].p.cg_max_iters > 0 ? c->ih[i].p.cg_max_iters : kCgMaxIters;
       li[i].taps = c->ih[i].taps.empty() ? nullptr : c->ih[i].taps.data();
       li[i].th = c->ih[i].p.blur_h;
       li[i].tw = c->ih[i].p.blur_w;
@@ -465,6 +470,9 @@ static void fill_stats(ep_tv_ctx* c, ep_tv_stats* s) {
     o.max_dmu_rel = h.dmu;
     o.max_dv_rel = h.dv;
     o.elapsed_ms = c->last_elapsed_ms;
+    o.lik_precision = h.gamma;
+    o.cavity_precision_mean = h.dbar;
+    o.cg_rel_residual = h.cg_bb > 0.0 ? std::sqrt(h.cg_rr / h.cg_bb) : 0.0;
   }
 }
 

@@ -43,8 +43,10 @@ struct InstState {
   double dmu, dv;            // last sweep's relative deltas
   double gamma, dbar;        // likelihood site: spectral precision, mean cavity precision
   double cg_rr, cg_bb;       // CG residual / rhs squared norms
+  double cg_rz, cg_alpha, cg_beta;
   unsigned clamps, flags, active, sweeps;
-  int cg_last, cg_total, converged, pad;
+  int cg_last, cg_total, converged, cg_done;
+  int cg_it, x_valid, pad0, pad1;
 };
 
 enum { FLAG_NONFINITE = 1u };

@@ -4,13 +4,20 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <string>
+#include <vector>
 
 #include "ep_tv_internal.h"
 
 namespace eptv {
 
 constexpr int kMaxTaps = 17;
+constexpr int kLikTW = 64;       // likelihood-kernel tile: 64 columns x 32 rows
+constexpr int kLikTH = 32;
+constexpr int kMaxRadius = kMaxTaps - 1;   // radius of the combined H^T H kernel
+constexpr int kCgMaxIters = 200;
+constexpr double kCgTol = 1e-8;            // relative residual ||r|| / ||b||
 
 inline bool fft_size_ok(int n) { return n >= 4 && n <= 4096 && (n & (n - 1)) == 0; }
 
@@ -18,29 +25,91 @@ struct LikInstInfo {
   int op = 0, H = 0, W = 0, pitch = 0;
   long long off = 0;
   double xi = 1.0, damping = 1.0;
+  double cg_tol = kCgTol;
+  int cg_max_iters = kCgMaxIters;
   const float* taps = nullptr;
   int th = 0, tw = 0;
   const uint8_t* mask = nullptr;
   int tile0 = 0, ntiles = 0;
 };
 
-struct LikLayout {
-  size_t planes[8]{};
-  int nplanes = 0;
-  size_t extra = 0;
+// Device description of one instance with a non-identity operator.
+struct LikInst {
+  int H, W, pitch, op;
+  long long off;             // element offset in the pixel planes
+  int inst;                  // index into InstDev / InstState
+  int tile0, ntiles, tiles_x;
+  int sep, Rr, Rc, kh, kw;   // separable taps?, combined-kernel radii, tap sizes
+  int k_off, gr_off, gc_off; // offsets into the taps buffer
+  float inv_xi, alpha, diagA, pad;   // diagA = sum of squared taps / xi (diagonal of H^T H / xi)
+  double cg_tol2;            // squared relative residual tolerance
+  int cg_max_iters, pad2;
 };
+
+enum {
+  LP_HTY = 0, LP_TAUC, LP_ETAC, LP_B, LP_X, LP_R, LP_P0, LP_P1, LP_Q, LP_SPEC, LP_COUNT
+};
+
+struct LikLayout {
+  size_t planes[LP_COUNT]{};
+  int nplanes = 0;
+  size_t inst = 0, tiles = 0, part0 = 0, part1 = 0, taps = 0, fft = 0;
+  int nlik = 0, ntiles = 0, ntaps = 0;
+  size_t fft_bytes = 0;
+};
+
+// Number of likelihood tiles and taps floats for the layout.
+inline void lik_counts(const LikInstInfo* li, int n, int& nlik, int& ntiles, int& ntaps,
+                       long long& fft_elems) {
+  nlik = 0; ntiles = 0; ntaps = 0; fft_elems = 0;
+  for (int i = 0; i < n; ++i) {
+    if (li[i].op == OP_IDENTITY) continue;
+    ++nlik;
+    ntiles += ((li[i].W + kLikTW - 1) / kLikTW) * ((li[i].H + kLikTH - 1) / kLikTH);
+    if (li[i].op == OP_BLUR) ntaps += li[i].th * li[i].tw + 2 * li[i].th + 2 * li[i].tw;
+    if (li[i].op == OP_DFT) fft_elems = std::max<long long>(fft_elems, (long long)li[i].H * li[i].W);
+  }
+}
 
 template <class Take>
 void lik_layout(const LikInstInfo* li, int n, long long plane, Take&& take, LikLayout& L) {
-  bool any = false;
-  for (int i = 0; i < n; ++i) any = any || li[i].op != OP_IDENTITY;
-  L.nplanes = any ? 6 : 0;
+  long long fft_elems = 0;
+  lik_counts(li, n, L.nlik, L.ntiles, L.ntaps, fft_elems);
+  L.nplanes = L.nlik ? LP_COUNT : 0;
   for (int k = 0; k < L.nplanes; ++k) L.planes[k] = take(sizeof(float) * (size_t)plane);
-  L.extra = take(4096);
+  L.inst = take(sizeof(LikInst) * (size_t)std::max(L.nlik, 1));
+  L.tiles = take(sizeof(int4) * (size_t)std::max(L.ntiles, 1));
+  L.part0 = take(sizeof(double) * (size_t)std::max(L.ntiles, 1));
+  L.part1 = take(sizeof(double) * (size_t)std::max(L.ntiles, 1));
+  L.taps = take(sizeof(float) * (size_t)std::max(L.ntaps, 1));
+  // complex work buffers of the FFT path: two complex planes of the largest DFT instance
+  L.fft_bytes = (size_t)fft_elems * 2 * sizeof(float2);
+  L.fft = take(std::max<size_t>(L.fft_bytes, 256));
 }
 
 struct LikCtx {
-  bool any = false;
+  int nlik = 0, ntiles = 0;
+  std::vector<LikInst> hinst;
+  std::vector<int> inst_of;          // lik index -> instance index
+  LikInst* d_inst = nullptr;
+  int4* d_tiles = nullptr;
+  double* part0 = nullptr;
+  double* part1 = nullptr;
+  float* taps = nullptr;
+  float* planes[LP_COUNT]{};
+  float2* fft = nullptr;
+  InstState* d_st = nullptr;
+  const InstDev* d_idev = nullptr;
+  float* ypix = nullptr;
+  int pcur = 0;                      // which p plane holds the current search direction
+  int max_iters = kCgMaxIters;       // largest per-instance CG cap
+  std::vector<InstState> hst;        // staging for convergence polls
+  int n_all = 0;
+  // timing of H^T H applications
+  bool timing = false;
+  std::vector<hipEvent_t> ev;
+  size_t ev_used = 0;
+  std::vector<std::pair<int, int>> ev_apply;
 };
 
 hipError_t lik_create(LikCtx& lc, const LikInstInfo* li, int n, char* ws, const LikLayout& L,

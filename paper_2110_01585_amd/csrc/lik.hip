@@ -1,24 +1,691 @@
+// Likelihood-site update q_{x,0} for deconvolution (periodic blur).
+//
+// Eq. (tilted_P_1): the tilted distribution P_0 has mean
+//   E = (H^T H / xi + diag(tau_c))^{-1} (H^T y / xi + eta_c),
+// where (tau_c, eta_c) are the natural parameters of the cavity Q^{\0} (the sum
+// of the four colour-class sites).  E is found by Jacobi-preconditioned
+// conjugate gradients, warm-started from the previous sweep's E (the paper
+// notes that only products with the inverse covariance are needed).  The
+// diagonal of Cov_{P_0} is estimated spectrally: with the cavity precision
+// replaced by its mean d, the covariance is circulant with constant diagonal
+// c = mean_w 1 / (|H(w)|^2 / xi + d), giving the site precision
+// gamma = 1/c - d for every pixel.  Eq. (update_q0_x) then gives
+//   tau_0 = gamma,  eta_0 = (gamma + tau_c) E - eta_c,
+// clamped and damped like the colour-class sites.
+//
+// H^T H x for a periodic convolution is a periodic convolution with the
+// autocorrelation of the taps (radius kh-1, kw-1).  It is applied on 64 x 32
+// output tiles staged through LDS with the halo: two 1-D passes when the taps
+// are separable (rank one, e.g. Gaussian), otherwise H followed by H^T as two
+// 2-D passes.  Reductions (dot products, means) are per-tile FP64 partials
+// summed in a fixed order by one block per instance.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "fft.h"
 #include "lik.h"
 
 namespace eptv {
 
-hipError_t lik_create(LikCtx& lc, const LikInstInfo* li, int n, char*, const LikLayout&, long long,
-                      InstDev*, InstState*, int4*, int, float*, hipStream_t,
-                      std::string& err) {
-  for (int i = 0; i < n; ++i)
-    if (li[i].op != OP_IDENTITY) {
-      err = "operator not available in this build";
-      return hipErrorNotSupported;
+__device__ __forceinline__ int wrapi(int i, int n) {
+  int r = i % n;
+  return r < 0 ? r + n : r;
+}
+
+struct LikArgs {
+  const LikInst* inst;
+  const int4* tiles;         // {lik index, tile x, tile y, 0}
+  int ntiles;
+  InstState* st;
+  double* part0;
+  double* part1;
+  const float* taps;
+  float* hty; float* tauc; float* etac; float* b; float* x; float* r;
+  float* p_in; float* p_out; float* q; float* spec;
+};
+
+// Deterministic block sum of two doubles (256 threads).
+__device__ __forceinline__ void block_sum2(double a, double b, double* out_a, double* out_b) {
+  __shared__ double sa[256], sb[256];
+  sa[threadIdx.x] = a;
+  sb[threadIdx.x] = b;
+  __syncthreads();
+  for (int w = 128; w >= 1; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      sa[threadIdx.x] += sa[threadIdx.x + w];
+      sb[threadIdx.x] += sb[threadIdx.x + w];
     }
-  lc.any = false;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    *out_a = sa[0];
+    *out_b = sb[0];
+  }
+}
+
+struct TileXY {
+  int r0, c0, r1, c1;
+};
+
+__device__ __forceinline__ TileXY lik_tile(const int4 td, const LikInst& L) {
+  TileXY t;
+  t.c0 = td.y * kLikTW;
+  t.r0 = td.z * kLikTH;
+  t.c1 = min(t.c0 + kLikTW, L.W);
+  t.r1 = min(t.r0 + kLikTH, L.H);
+  return t;
+}
+
+// ---------------------------------------------------------------------------
+// 1. cavity of site 0, right-hand side, warm start (and d_bar, ||b||^2 partials)
+__global__ __launch_bounds__(256) void k_lik_prep(LikArgs A, const float2* __restrict__ S0,
+                                                  const float2* __restrict__ S1,
+                                                  const float2* __restrict__ S2,
+                                                  const float2* __restrict__ S3,
+                                                  const float2* __restrict__ S4) {
+  const int tile = blockIdx.x;
+  const int4 td = A.tiles[tile];
+  const LikInst L = A.inst[td.x];
+  const InstState& st = A.st[L.inst];
+  double at = 0.0, ab = 0.0;
+  if (st.active && st.sweeps > 0) {
+    const TileXY t = lik_tile(td, L);
+    const int cols = t.c1 - t.c0;
+    const int n = cols * (t.r1 - t.r0);
+    const bool init_x = !st.x_valid;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+      const int r = t.r0 + i / cols, c = t.c0 + i % cols;
+      const long long p = L.off + (long long)r * L.pitch + c;
+      const float2 s1 = S1[p], s2 = S2[p], s3 = S3[p], s4 = S4[p];
+      const double tc = (double)s1.x + (double)s2.x + (double)s3.x + (double)s4.x;
+      const double ec = (double)s1.y + (double)s2.y + (double)s3.y + (double)s4.y;
+      const float bv = (float)((double)A.hty[p] * (double)L.inv_xi + ec);
+      A.tauc[p] = (float)tc;
+      A.etac[p] = (float)ec;
+      A.b[p] = bv;
+      if (init_x) {
+        const float2 s0 = S0[p];
+        A.x[p] = (float)(((double)s0.y + ec) / ((double)s0.x + tc));
+      }
+      at += tc;
+      ab += (double)bv * (double)bv;
+    }
+  }
+  block_sum2(at, ab, &A.part0[tile], &A.part1[tile]);
+}
+
+// ---------------------------------------------------------------------------
+// 2. per-instance finalisation of the partial sums (one block per instance)
+enum { FIN_PREP = 0, FIN_SPEC, FIN_INIT, FIN_ALPHA, FIN_BETA };
+
+__global__ __launch_bounds__(256) void k_lik_fin(LikArgs A, int stage) {
+  const LikInst L = A.inst[blockIdx.x];
+  InstState& st = A.st[L.inst];
+  double s0 = 0.0, s1 = 0.0;
+  for (int t = threadIdx.x; t < L.ntiles; t += blockDim.x) {
+    s0 += A.part0[L.tile0 + t];
+    s1 += A.part1[L.tile0 + t];
+  }
+  __shared__ double r0, r1;
+  block_sum2(s0, s1, &r0, &r1);
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  const double N = (double)L.H * (double)L.W;
+  switch (stage) {
+    case FIN_PREP:
+      if (!st.active || st.sweeps == 0) {
+        st.cg_done = 1;          // nothing to do this sweep
+        break;
+      }
+      st.dbar = r0 / N;
+      st.cg_bb = r1;
+      st.cg_it = 0;
+      st.cg_done = 0;
+      st.x_valid = 1;
+      break;
+    case FIN_SPEC:
+      if (st.cg_done) break;
+      st.gamma = 1.0 / (r0 / N) - st.dbar;
+      break;
+    case FIN_INIT:
+      if (st.cg_done) break;
+      st.cg_rz = r0;
+      st.cg_rr = r1;
+      st.cg_beta = 0.0;
+      if (!(st.cg_rr > L.cg_tol2 * st.cg_bb)) st.cg_done = 1;
+      break;
+    case FIN_ALPHA:
+      if (st.cg_done) break;
+      st.cg_alpha = (r0 != 0.0) ? st.cg_rz / r0 : 0.0;
+      break;
+    case FIN_BETA:
+      if (st.cg_done) break;
+      st.cg_beta = (st.cg_rz != 0.0) ? r0 / st.cg_rz : 0.0;
+      st.cg_rz = r0;
+      st.cg_rr = r1;
+      st.cg_it += 1;
+      if (!(st.cg_rr > L.cg_tol2 * st.cg_bb) || st.cg_it >= L.cg_max_iters) st.cg_done = 1;
+      break;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// 3. spectral diagonal: partial sums of 1 / (|H(w)|^2 / xi + d_bar)
+__global__ __launch_bounds__(256) void k_lik_spec(LikArgs A) {
+  const int tile = blockIdx.x;
+  const int4 td = A.tiles[tile];
+  const LikInst L = A.inst[td.x];
+  const InstState& st = A.st[L.inst];
+  double acc = 0.0;
+  if (!st.cg_done) {
+    const TileXY t = lik_tile(td, L);
+    const int cols = t.c1 - t.c0;
+    const int n = cols * (t.r1 - t.r0);
+    const double d = st.dbar;
+    const double ix = (double)L.inv_xi;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+      const int r = t.r0 + i / cols, c = t.c0 + i % cols;
+      const long long p = L.off + (long long)r * L.pitch + c;
+      acc += 1.0 / ((double)A.spec[p] * ix + d);
+    }
+  }
+  block_sum2(acc, 0.0, &A.part0[tile], &A.part1[tile]);
+}
+
+// ---------------------------------------------------------------------------
+// 4. q = (H^T H / xi + diag(tau_c)) v on a tile, with v either the warm start x
+//    (MODE 0) or the new search direction p = z + beta p_old, z = r / diag(A)
+//    (MODE 1, p written to p_out).  Partial sums of v . q.
+template <int MODE>
+__device__ __forceinline__ float direction(const LikArgs& A, const LikInst& L, const InstState& st,
+                                           long long p) {
+  if (MODE == 0) return A.x[p];
+  const float z = A.r[p] / (L.diagA + A.tauc[p]);
+  return st.cg_it == 0 ? z : z + (float)st.cg_beta * A.p_in[p];
+}
+
+template <int MODE, bool SEP>
+__global__ __launch_bounds__(256) void k_apply(LikArgs A) {
+  constexpr int EWMAX = kLikTW + 2 * kMaxRadius;
+  constexpr int EHMAX = kLikTH + 2 * kMaxRadius;
+  __shared__ float P[EHMAX * EWMAX];          // v on the tile plus halo
+  __shared__ float T[EHMAX * EWMAX];          // first-pass result
+  const int tile = blockIdx.x;
+  const int4 td = A.tiles[tile];
+  const LikInst L = A.inst[td.x];
+  const InstState& st = A.st[L.inst];
+  if (st.cg_done) {
+    block_sum2(0.0, 0.0, &A.part0[tile], &A.part1[tile]);
+    return;
+  }
+  const TileXY t = lik_tile(td, L);
+  const int Rr = L.Rr, Rc = L.Rc;
+  const int EH = kLikTH + 2 * Rr, EW = kLikTW + 2 * Rc;
+  // stage v over the tile and its halo (periodic wrap); write p for the interior
+  for (int i = threadIdx.x; i < EH * EW; i += blockDim.x) {
+    const int er = i / EW, ec = i % EW;
+    const int gr = wrapi(t.r0 - Rr + er, L.H), gc = wrapi(t.c0 - Rc + ec, L.W);
+    const long long p = L.off + (long long)gr * L.pitch + gc;
+    const float v = direction<MODE>(A, L, st, p);
+    P[er * EW + ec] = v;
+    if (MODE == 1) {
+      const int lr = er - Rr, lc = ec - Rc;
+      if (lr >= 0 && lr < kLikTH && lc >= 0 && lc < kLikTW && t.r0 + lr < L.H && t.c0 + lc < L.W)
+        A.p_out[p] = v;
+    }
+  }
+  __syncthreads();
+  const float* tp = A.taps;
+  if (SEP) {
+    // rows of the combined kernel along columns, then along rows
+    const float* gc = tp + L.gc_off;   // 2 Rc + 1 taps
+    const float* gr = tp + L.gr_off;   // 2 Rr + 1 taps
+    for (int i = threadIdx.x; i < EH * kLikTW; i += blockDim.x) {
+      const int er = i / kLikTW, oc = i % kLikTW;
+      const float* row = P + er * EW + oc;
+      float acc = 0.f;
+      for (int d = 0; d <= 2 * Rc; ++d) acc += gc[d] * row[d];
+      T[er * kLikTW + oc] = acc;
+    }
+    __syncthreads();
+    double dot = 0.0;
+    for (int i = threadIdx.x; i < kLikTH * kLikTW; i += blockDim.x) {
+      const int orow = i / kLikTW, oc = i % kLikTW;
+      if (t.r0 + orow >= L.H || t.c0 + oc >= L.W) continue;
+      float acc = 0.f;
+      for (int d = 0; d <= 2 * Rr; ++d) acc += gr[d] * T[(orow + d) * kLikTW + oc];
+      const long long p = L.off + (long long)(t.r0 + orow) * L.pitch + (t.c0 + oc);
+      const float v = P[(orow + Rr) * EW + oc + Rc];
+      const float qv = acc * L.inv_xi + A.tauc[p] * v;
+      A.q[p] = qv;
+      dot += (double)v * (double)qv;
+    }
+    block_sum2(dot, 0.0, &A.part0[tile], &A.part1[tile]);
+  } else {
+    // H then H^T with the original taps (kh x kw, centred at (kh/2, kw/2))
+    const float* k = tp + L.k_off;
+    const int ch = L.kh / 2, cw = L.kw / 2;
+    const int TH = kLikTH + 2 * ch, TW = kLikTW + 2 * cw;
+    for (int i = threadIdx.x; i < TH * TW; i += blockDim.x) {
+      const int tr = i / TW, tc = i % TW;
+      float acc = 0.f;
+      for (int a = 0; a < L.kh; ++a)
+        for (int b2 = 0; b2 < L.kw; ++b2)
+          acc += k[a * L.kw + b2] * P[(tr - a + 2 * ch) * EW + (tc - b2 + 2 * cw)];
+      T[tr * TW + tc] = acc;
+    }
+    __syncthreads();
+    double dot = 0.0;
+    for (int i = threadIdx.x; i < kLikTH * kLikTW; i += blockDim.x) {
+      const int orow = i / kLikTW, oc = i % kLikTW;
+      if (t.r0 + orow >= L.H || t.c0 + oc >= L.W) continue;
+      float acc = 0.f;
+      for (int a = 0; a < L.kh; ++a)
+        for (int b2 = 0; b2 < L.kw; ++b2) acc += k[a * L.kw + b2] * T[(orow + a) * TW + (oc + b2)];
+      const long long p = L.off + (long long)(t.r0 + orow) * L.pitch + (t.c0 + oc);
+      const float v = P[(orow + Rr) * EW + oc + Rc];
+      const float qv = acc * L.inv_xi + A.tauc[p] * v;
+      A.q[p] = qv;
+      dot += (double)v * (double)qv;
+    }
+    block_sum2(dot, 0.0, &A.part0[tile], &A.part1[tile]);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// 5. CG start: r = b - A x (q holds A x); partials of r.z and r.r
+__global__ __launch_bounds__(256) void k_cg_init(LikArgs A) {
+  const int tile = blockIdx.x;
+  const int4 td = A.tiles[tile];
+  const LikInst L = A.inst[td.x];
+  const InstState& st = A.st[L.inst];
+  double rz = 0.0, rr = 0.0;
+  if (!st.cg_done) {
+    const TileXY t = lik_tile(td, L);
+    const int cols = t.c1 - t.c0;
+    const int n = cols * (t.r1 - t.r0);
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+      const int r = t.r0 + i / cols, c = t.c0 + i % cols;
+      const long long p = L.off + (long long)r * L.pitch + c;
+      const float rv = A.b[p] - A.q[p];
+      A.r[p] = rv;
+      rz += (double)rv * (double)rv / (double)(L.diagA + A.tauc[p]);
+      rr += (double)rv * (double)rv;
+    }
+  }
+  block_sum2(rz, rr, &A.part0[tile], &A.part1[tile]);
+}
+
+// 6. CG step: x += alpha p, r -= alpha q; partials of the new r.z and r.r
+__global__ __launch_bounds__(256) void k_cg_update(LikArgs A) {
+  const int tile = blockIdx.x;
+  const int4 td = A.tiles[tile];
+  const LikInst L = A.inst[td.x];
+  const InstState& st = A.st[L.inst];
+  double rz = 0.0, rr = 0.0;
+  if (!st.cg_done) {
+    const float alpha = (float)st.cg_alpha;
+    const TileXY t = lik_tile(td, L);
+    const int cols = t.c1 - t.c0;
+    const int n = cols * (t.r1 - t.r0);
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+      const int r = t.r0 + i / cols, c = t.c0 + i % cols;
+      const long long p = L.off + (long long)r * L.pitch + c;
+      const float pv = A.p_out[p];
+      A.x[p] += alpha * pv;
+      const float rv = A.r[p] - alpha * A.q[p];
+      A.r[p] = rv;
+      rz += (double)rv * (double)rv / (double)(L.diagA + A.tauc[p]);
+      rr += (double)rv * (double)rv;
+    }
+  }
+  block_sum2(rz, rr, &A.part0[tile], &A.part1[tile]);
+}
+
+// 7. site update q_{x,0} from E = x (Eq. (update_q0_x)), clamp, damping
+__global__ __launch_bounds__(256) void k_lik_site(LikArgs A, float2* __restrict__ S0) {
+  const int tile = blockIdx.x;
+  const int4 td = A.tiles[tile];
+  const LikInst L = A.inst[td.x];
+  InstState& st = A.st[L.inst];
+  if (!st.active || st.sweeps == 0) return;
+  if (tile == L.tile0 && threadIdx.x == 0) {
+    st.cg_last = st.cg_it;
+    st.cg_total += st.cg_it;
+  }
+  const TileXY t = lik_tile(td, L);
+  const int cols = t.c1 - t.c0;
+  const int n = cols * (t.r1 - t.r0);
+  float tau_new = (float)st.gamma;
+  if (!(tau_new >= kPrecFloor)) tau_new = kPrecFloor;
+  const float a = L.alpha;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    const int r = t.r0 + i / cols, c = t.c0 + i % cols;
+    const long long p = L.off + (long long)r * L.pitch + c;
+    const float eta_new = (float)(((double)tau_new + (double)A.tauc[p]) * (double)A.x[p] - (double)A.etac[p]);
+    const float2 old = S0[p];
+    S0[p] = make_float2(a * tau_new + (1.f - a) * old.x, a * eta_new + (1.f - a) * old.y);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// one-time kernels: H^T y (correlation with the taps) and |H(w)|^2
+__global__ __launch_bounds__(256) void k_hty_blur(LikArgs A, const float* __restrict__ ypix) {
+  const int tile = blockIdx.x;
+  const int4 td = A.tiles[tile];
+  const LikInst L = A.inst[td.x];
+  if (L.op != OP_BLUR) return;
+  const TileXY t = lik_tile(td, L);
+  const int cols = t.c1 - t.c0;
+  const int n = cols * (t.r1 - t.r0);
+  const float* k = A.taps + L.k_off;
+  const int ch = L.kh / 2, cw = L.kw / 2;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    const int r = t.r0 + i / cols, c = t.c0 + i % cols;
+    double acc = 0.0;
+    for (int a = 0; a < L.kh; ++a)
+      for (int b2 = 0; b2 < L.kw; ++b2) {
+        const int gr = wrapi(r + a - ch, L.H), gc = wrapi(c + b2 - cw, L.W);
+        acc += (double)k[a * L.kw + b2] * (double)ypix[L.off + (long long)gr * L.pitch + gc];
+      }
+    A.hty[L.off + (long long)r * L.pitch + c] = (float)acc;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_spectrum_blur(LikArgs A) {
+  const int tile = blockIdx.x;
+  const int4 td = A.tiles[tile];
+  const LikInst L = A.inst[td.x];
+  if (L.op != OP_BLUR) return;
+  const TileXY t = lik_tile(td, L);
+  const int cols = t.c1 - t.c0;
+  const int n = cols * (t.r1 - t.r0);
+  const float* k = A.taps + L.k_off;
+  const double two_pi = 6.283185307179586476925;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    const int r = t.r0 + i / cols, c = t.c0 + i % cols;
+    double re = 0.0, im = 0.0;
+    for (int a = 0; a < L.kh; ++a)
+      for (int b2 = 0; b2 < L.kw; ++b2) {
+        // phase of tap offset (a - kh/2, b - kw/2) at frequency (r, c), reduced exactly
+        const long long ph_r = ((long long)(a - L.kh / 2) * r) % L.H;
+        const long long ph_c = ((long long)(b2 - L.kw / 2) * c) % L.W;
+        const double ang = two_pi * ((double)ph_r / L.H + (double)ph_c / L.W);
+        double sn, cs;
+        sincos(ang, &sn, &cs);
+        re += (double)k[a * L.kw + b2] * cs;
+        im -= (double)k[a * L.kw + b2] * sn;
+      }
+    A.spec[L.off + (long long)r * L.pitch + c] = (float)(re * re + im * im);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// host side
+
+static LikArgs make_args(LikCtx& lc) {
+  LikArgs A;
+  A.inst = lc.d_inst;
+  A.tiles = lc.d_tiles;
+  A.ntiles = lc.ntiles;
+  A.st = lc.d_st;
+  A.part0 = lc.part0;
+  A.part1 = lc.part1;
+  A.taps = lc.taps;
+  A.hty = lc.planes[LP_HTY];
+  A.tauc = lc.planes[LP_TAUC];
+  A.etac = lc.planes[LP_ETAC];
+  A.b = lc.planes[LP_B];
+  A.x = lc.planes[LP_X];
+  A.r = lc.planes[LP_R];
+  A.p_in = lc.planes[lc.pcur ? LP_P1 : LP_P0];
+  A.p_out = lc.planes[lc.pcur ? LP_P0 : LP_P1];
+  A.q = lc.planes[LP_Q];
+  A.spec = lc.planes[LP_SPEC];
+  return A;
+}
+
+hipError_t lik_create(LikCtx& lc, const LikInstInfo* li, int n, char* ws, const LikLayout& L,
+                      long long plane, InstDev* d_inst, InstState* d_st, int4* d_tiles, int ntiles,
+                      float* ypix, hipStream_t s, std::string& err) {
+  (void)plane; (void)d_tiles; (void)ntiles;
+  lc = LikCtx();
+  lc.n_all = n;
+  lc.nlik = L.nlik;
+  lc.ntiles = L.ntiles;
+  lc.d_st = d_st;
+  lc.d_idev = d_inst;
+  lc.ypix = ypix;
+  if (lc.nlik == 0) return hipSuccess;
+  for (int k = 0; k < LP_COUNT; ++k) lc.planes[k] = reinterpret_cast<float*>(ws + L.planes[k]);
+  lc.d_inst = reinterpret_cast<LikInst*>(ws + L.inst);
+  lc.d_tiles = reinterpret_cast<int4*>(ws + L.tiles);
+  lc.part0 = reinterpret_cast<double*>(ws + L.part0);
+  lc.part1 = reinterpret_cast<double*>(ws + L.part1);
+  lc.taps = reinterpret_cast<float*>(ws + L.taps);
+  lc.fft = reinterpret_cast<float2*>(ws + L.fft);
+  std::vector<float> taps;
+  std::vector<int4> tiles;
+  for (int i = 0; i < n; ++i) {
+    const LikInstInfo& I = li[i];
+    if (I.op == OP_IDENTITY) continue;
+    LikInst d;
+    std::memset(&d, 0, sizeof(d));
+    d.H = I.H; d.W = I.W; d.pitch = I.pitch; d.op = I.op; d.off = I.off; d.inst = i;
+    d.tile0 = (int)tiles.size();
+    d.tiles_x = (I.W + kLikTW - 1) / kLikTW;
+    const int ty = (I.H + kLikTH - 1) / kLikTH;
+    d.ntiles = d.tiles_x * ty;
+    d.inv_xi = (float)(1.0 / I.xi);
+    d.alpha = (float)I.damping;
+    d.cg_tol2 = I.cg_tol * I.cg_tol;
+    d.cg_max_iters = I.cg_max_iters;
+    lc.max_iters = std::max(lc.max_iters, I.cg_max_iters);
+    const int li_idx = (int)lc.hinst.size();
+    for (int yy = 0; yy < ty; ++yy)
+      for (int xx = 0; xx < d.tiles_x; ++xx) tiles.push_back(make_int4(li_idx, xx, yy, 0));
+    if (I.op == OP_BLUR) {
+      const int kh = I.th, kw = I.tw;
+      d.kh = kh; d.kw = kw;
+      d.Rr = kh - 1; d.Rc = kw - 1;
+      d.k_off = (int)taps.size();
+      double ksq = 0.0, kmax = 0.0;
+      int a0 = 0, b0 = 0;
+      for (int a = 0; a < kh; ++a)
+        for (int b2 = 0; b2 < kw; ++b2) {
+          const double v = I.taps[a * kw + b2];
+          taps.push_back((float)v);
+          ksq += v * v;
+          if (std::fabs(v) > kmax) { kmax = std::fabs(v); a0 = a; b0 = b2; }
+        }
+      d.diagA = (float)(ksq / I.xi);
+      // rank-one test: taps == u v^T with u = column b0, v = row a0 / taps[a0][b0]
+      bool sep = kmax > 0.0;
+      std::vector<double> u(kh), v(kw);
+      if (sep) {
+        for (int a = 0; a < kh; ++a) u[a] = I.taps[a * kw + b0];
+        for (int b2 = 0; b2 < kw; ++b2) v[b2] = I.taps[a0 * kw + b2] / I.taps[a0 * kw + b0];
+        for (int a = 0; a < kh && sep; ++a)
+          for (int b2 = 0; b2 < kw; ++b2)
+            if (std::fabs(u[a] * v[b2] - I.taps[a * kw + b2]) > 1e-6 * kmax) { sep = false; break; }
+      }
+      d.sep = sep ? 1 : 0;
+      // autocorrelations g(d) = sum_t u(t) u(t + d), d = -(kh-1) .. kh-1 (same for v)
+      d.gr_off = (int)taps.size();
+      for (int dd = -(kh - 1); dd <= kh - 1; ++dd) {
+        double acc = 0.0;
+        for (int a = 0; a < kh; ++a)
+          if (a + dd >= 0 && a + dd < kh) acc += u[a] * u[a + dd];
+        taps.push_back((float)(sep ? acc : 0.0));
+      }
+      d.gc_off = (int)taps.size();
+      for (int dd = -(kw - 1); dd <= kw - 1; ++dd) {
+        double acc = 0.0;
+        for (int b2 = 0; b2 < kw; ++b2)
+          if (b2 + dd >= 0 && b2 + dd < kw) acc += v[b2] * v[b2 + dd];
+        taps.push_back((float)(sep ? acc : 0.0));
+      }
+    } else if (I.op == OP_DFT) {
+      d.Rr = 0; d.Rc = 0; d.sep = 0;
+      // H^T H of the masked orthonormal DFT has unit diagonal times the kept fraction
+      int kept = 0;
+      for (long long q = 0; q < (long long)I.H * I.W; ++q) kept += I.mask[q] ? 1 : 0;
+      d.diagA = (float)((double)kept / ((double)I.H * I.W) / I.xi);
+    }
+    lc.hinst.push_back(d);
+    lc.inst_of.push_back(i);
+  }
+  hipError_t e = hipMemcpyAsync(lc.d_inst, lc.hinst.data(), sizeof(LikInst) * lc.hinst.size(),
+                                hipMemcpyHostToDevice, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(lc.d_tiles, tiles.data(), sizeof(int4) * tiles.size(), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess && !taps.empty())
+    e = hipMemcpyAsync(lc.taps, taps.data(), sizeof(float) * taps.size(), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);   // host vectors go out of scope
+  if (e != hipSuccess) {
+    err = hipGetErrorString(e);
+    return e;
+  }
+  LikArgs A = make_args(lc);
+  hipLaunchKernelGGL(k_spectrum_blur, dim3(lc.ntiles), dim3(256), 0, s, A);
+  e = hipGetLastError();
+  if (e == hipSuccess) e = dft_setup(lc, li, n, s, err);
+  if (e != hipSuccess && err.empty()) err = hipGetErrorString(e);
+  lc.hst.resize(n);
+  return e;
+}
+
+hipError_t lik_set_observation(LikCtx& lc, const float* const* d_y, hipStream_t s) {
+  if (lc.nlik == 0) return hipSuccess;
+  LikArgs A = make_args(lc);
+  hipLaunchKernelGGL(k_hty_blur, dim3(lc.ntiles), dim3(256), 0, s, A, lc.ypix);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return dft_set_observation(lc, d_y, s);
+}
+
+static hipError_t set_x_invalid(LikCtx& lc, hipStream_t s);
+
+hipError_t lik_reset(LikCtx& lc, hipStream_t s) { return set_x_invalid(lc, s); }
+hipError_t lik_resume(LikCtx& lc, hipStream_t s) { return set_x_invalid(lc, s); }
+
+__global__ void k_x_invalid(InstState* st, const LikInst* inst, int nlik) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < nlik) st[inst[i].inst].x_valid = 0;
+}
+
+static hipError_t set_x_invalid(LikCtx& lc, hipStream_t s) {
+  if (lc.nlik == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_x_invalid, dim3((lc.nlik + 255) / 256), dim3(256), 0, s, lc.d_st, lc.d_inst,
+                     lc.nlik);
+  return hipGetLastError();
+}
+
+static hipError_t launch_apply(LikCtx& lc, int mode, hipStream_t s) {
+  const LikArgs A = make_args(lc);
+  bool all_sep = true, any_dft = false;
+  for (const LikInst& d : lc.hinst) {
+    if (d.op == OP_BLUR && !d.sep) all_sep = false;
+    if (d.op == OP_DFT) any_dft = true;
+  }
+  int i0 = 0, i1 = 0;
+  const bool tm = lc.timing && lc.ev_used + 2 <= 16384;
+  if (tm) {
+    if (lc.ev_used + 2 > lc.ev.size()) {
+      for (int k = 0; k < 2; ++k) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return hipErrorOutOfMemory;
+        lc.ev.push_back(e);
+      }
+    }
+    i0 = (int)lc.ev_used++;
+    i1 = (int)lc.ev_used++;
+    hipEventRecord(lc.ev[i0], s);
+  }
+  if (any_dft) {
+    hipError_t e = dft_apply(lc, mode, s);
+    if (e != hipSuccess) return e;
+  }
+  bool any_blur = false;
+  for (const LikInst& d : lc.hinst) any_blur = any_blur || d.op == OP_BLUR;
+  if (any_blur) {
+    if (mode == 0) {
+      if (all_sep) hipLaunchKernelGGL((k_apply<0, true>), dim3(lc.ntiles), dim3(256), 0, s, A);
+      else hipLaunchKernelGGL((k_apply<0, false>), dim3(lc.ntiles), dim3(256), 0, s, A);
+    } else {
+      if (all_sep) hipLaunchKernelGGL((k_apply<1, true>), dim3(lc.ntiles), dim3(256), 0, s, A);
+      else hipLaunchKernelGGL((k_apply<1, false>), dim3(lc.ntiles), dim3(256), 0, s, A);
+    }
+  }
+  if (tm) {
+    hipEventRecord(lc.ev[i1], s);
+    lc.ev_apply.emplace_back(i0, i1);
+  }
+  return hipGetLastError();
+}
+
+static hipError_t fin(LikCtx& lc, int stage, hipStream_t s) {
+  hipLaunchKernelGGL(k_lik_fin, dim3(lc.nlik), dim3(256), 0, s, make_args(lc), stage);
+  return hipGetLastError();
+}
+
+hipError_t lik_update(LikCtx& lc, float2* const S[5], hipStream_t s) {
+  if (lc.nlik == 0) return hipSuccess;
+  hipError_t e;
+  const dim3 g(lc.ntiles), b(256);
+  hipLaunchKernelGGL(k_lik_prep, g, b, 0, s, make_args(lc), S[0], S[1], S[2], S[3], S[4]);
+  if ((e = fin(lc, FIN_PREP, s)) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_lik_spec, g, b, 0, s, make_args(lc));
+  if ((e = fin(lc, FIN_SPEC, s)) != hipSuccess) return e;
+  if ((e = launch_apply(lc, 0, s)) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_cg_init, g, b, 0, s, make_args(lc));
+  if ((e = fin(lc, FIN_INIT, s)) != hipSuccess) return e;
+  const int poll = 4;
+  for (int it = 0; it < lc.max_iters; ++it) {
+    if ((e = launch_apply(lc, 1, s)) != hipSuccess) return e;   // p_out = z + beta p_in, q = A p_out
+    if ((e = fin(lc, FIN_ALPHA, s)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_cg_update, g, b, 0, s, make_args(lc));
+    if ((e = fin(lc, FIN_BETA, s)) != hipSuccess) return e;
+    lc.pcur ^= 1;
+    if ((it + 1) % poll == 0) {
+      e = hipMemcpyAsync(lc.hst.data(), lc.d_st, sizeof(InstState) * lc.n_all, hipMemcpyDeviceToHost, s);
+      if (e == hipSuccess) e = hipStreamSynchronize(s);
+      if (e != hipSuccess) return e;
+      bool any = false;
+      for (int i : lc.inst_of) any = any || !lc.hst[i].cg_done;
+      if (!any) break;
+    }
+  }
+  hipLaunchKernelGGL(k_lik_site, g, b, 0, s, make_args(lc), S[0]);
+  return hipGetLastError();
+}
+
+void lik_destroy(LikCtx& lc) {
+  for (hipEvent_t e : lc.ev) (void)hipEventDestroy(e);
+  lc.ev.clear();
+  dft_destroy(lc);
+}
+
+void lik_timing(LikCtx& lc, bool enable, bool clear) {
+  lc.timing = enable;
+  if (clear) {
+    lc.ev_used = 0;
+    lc.ev_apply.clear();
+  }
+}
+
+hipError_t lik_timing_read(LikCtx& lc, double& ms, int& launches) {
+  ms = 0.0;
+  launches = 0;
+  for (auto& pr : lc.ev_apply) {
+    float t = 0.f;
+    hipError_t e = hipEventElapsedTime(&t, lc.ev[pr.first], lc.ev[pr.second]);
+    if (e != hipSuccess) return e;
+    ms += t;
+    launches += 1;
+  }
   return hipSuccess;
 }
-hipError_t lik_set_observation(LikCtx&, const float* const*, hipStream_t) { return hipSuccess; }
-hipError_t lik_reset(LikCtx&, hipStream_t) { return hipSuccess; }
-hipError_t lik_resume(LikCtx&, hipStream_t) { return hipSuccess; }
-hipError_t lik_update(LikCtx&, float2* const*, hipStream_t) { return hipSuccess; }
-void lik_destroy(LikCtx&) {}
-void lik_timing(LikCtx&, bool, bool) {}
-hipError_t lik_timing_read(LikCtx&, double& ms, int& n) { ms = 0; n = 0; return hipSuccess; }
 
 }  // namespace eptv
