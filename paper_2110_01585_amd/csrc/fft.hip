@@ -1,18 +1,364 @@
+// Masked orthonormal 2-D DFT operator for compressive sensing, on a
+// hand-written FFT.
+//
+// Observation model (Sec. II-A, Eq. (1), with H = a subset of the orthonormal
+// 2-D DFT coefficients): y_w = (F x)_w + n_w for w in the mask, complex noise of
+// variance xi per real component.  Treating (Re, Im) as two real observations,
+//   H^T H v = Re(F^H diag(mask) F v),   H^T y = Re(F^H diag(mask) y),
+// and H^T H is circulant with eigenvalues (mask(w) + mask(-w)) / 2.
+//
+// FFT: power-of-two lengths up to 4096.  A 2-D transform is a batch of row
+// FFTs (one row per workgroup, the whole row in LDS, radix-2 Stockham
+// auto-sort stages, twiddles from a table), a tiled transpose, and a second
+// batch of row FFTs; the spectrum-domain products are applied in that
+// transposed layout (element (c, r) holds frequency (r, c)), and the inverse
+// transform undoes the transpose.  Loads and stores of every pass are
+// contiguous per row.  Element-wise work before and after the transform
+// (building the search direction, scaling, the final q = H^T H p / xi +
+// tau_c p) is fused into the first and last passes.
+#include <cmath>
+#include <cstring>
+
 #include "fft.h"
 
 namespace eptv {
 
-hipError_t dft_setup(LikCtx& lc, const LikInstInfo* li, int n, hipStream_t, std::string& err) {
-  (void)lc;
-  for (int i = 0; i < n; ++i)
-    if (li[i].op == OP_DFT) {
-      err = "DFT operator not available in this build";
-      return hipErrorNotSupported;
+enum {
+  PRE_COMPLEX = 0,   // load the complex row from `src`
+  PRE_REAL,          // load a real plane (pitched), imaginary part 0
+  PRE_DIRECTION,     // p = z + beta p_in (or x in mode 0) from the CG planes; store p_out
+  PRE_OBS            // observed coefficients (user array, interleaved) times the mask
+};
+enum {
+  POST_COMPLEX = 0,  // store the complex row to `dst`
+  POST_SCALE,        // multiply by `mul` (transposed layout, real) then store
+  POST_Q,            // q = Re(v) * scale / xi + tau_c * p  (real plane), store q
+  POST_REAL          // real part * scale -> real plane
+};
+
+struct FftArgs {
+  const float2* src;
+  float2* dst;
+  const float2* tw;          // e^{-2 pi i t / L}, t < L/2
+  int nrows, L, logL;
+  int pre, post, inverse;
+  // real planes (pitched) for PRE_REAL / PRE_DIRECTION / POST_Q / POST_REAL
+  long long off;
+  int pitch;
+  const float* real_in;      // PRE_REAL
+  float* real_out;           // POST_REAL, POST_Q
+  const float* mul;          // POST_SCALE: per-element real factor (transposed layout, dense)
+  float scale;
+  // CG planes
+  const float* r; const float* tauc; const float* x; const float* p_in; float* p_out;
+  const float* pvec;         // POST_Q: the vector whose product is formed
+  const float* zpl;          // PRE_DIRECTION with a stored preconditioned residual (else null)
+  float diagA, inv_xi;
+  const InstState* st;       // PRE_DIRECTION: beta and the iteration count of this instance
+  int inst;
+  int mode0;                 // PRE_DIRECTION: use x (the product A x for the CG start)
+  const float* obs;          // PRE_OBS: interleaved complex observations (user), dense
+  const uint8_t* mask;       // PRE_OBS
+};
+
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+__global__ __launch_bounds__(256) void k_fft_rows(FftArgs a) {
+  extern __shared__ float2 sm[];
+  float2* X = sm;
+  float2* Y = sm + a.L;
+  const int row = blockIdx.x;
+  const int L = a.L;
+  // ---- load (pre-op) ----
+  for (int c = threadIdx.x; c < L; c += blockDim.x) {
+    float2 v;
+    if (a.pre == PRE_COMPLEX) {
+      v = a.src[(long long)row * L + c];
+    } else if (a.pre == PRE_REAL) {
+      v = make_float2(a.real_in[a.off + (long long)row * a.pitch + c], 0.f);
+    } else if (a.pre == PRE_DIRECTION) {
+      const long long p = a.off + (long long)row * a.pitch + c;
+      float pv;
+      if (a.mode0) {
+        pv = a.x[p];
+      } else {
+        const InstState& st = a.st[a.inst];
+        const float z = a.zpl ? a.zpl[p] : a.r[p] / (a.diagA + a.tauc[p]);
+        pv = st.cg_it == 0 ? z : z + (float)st.cg_beta * a.p_in[p];
+        a.p_out[p] = pv;
+      }
+      v = make_float2(pv, 0.f);
+    } else {   // PRE_OBS
+      const long long q = (long long)row * L + c;
+      v = a.mask[q] ? make_float2(a.obs[2 * q], a.obs[2 * q + 1]) : make_float2(0.f, 0.f);
     }
+    X[c] = v;
+  }
+  __syncthreads();
+  // ---- radix-2 Stockham stages ----
+  const int half = L >> 1;
+  for (int s = 0, Ns = 1; s < a.logL; ++s, Ns <<= 1) {
+    for (int j = threadIdx.x; j < half; j += blockDim.x) {
+      const int k = j & (Ns - 1);
+      float2 w = a.tw[k * (half / Ns)];
+      if (a.inverse) w.y = -w.y;
+      const float2 u = X[j];
+      const float2 t = cmul(X[j + half], w);
+      const int o = ((j - k) << 1) + k;
+      Y[o] = make_float2(u.x + t.x, u.y + t.y);
+      Y[o + Ns] = make_float2(u.x - t.x, u.y - t.y);
+    }
+    __syncthreads();
+    float2* T = X; X = Y; Y = T;
+  }
+  // ---- store (post-op) ----
+  for (int c = threadIdx.x; c < L; c += blockDim.x) {
+    const float2 v = X[c];
+    if (a.post == POST_COMPLEX) {
+      a.dst[(long long)row * L + c] = v;
+    } else if (a.post == POST_SCALE) {
+      const float m = a.mul[(long long)row * L + c] * a.scale;
+      a.dst[(long long)row * L + c] = make_float2(v.x * m, v.y * m);
+    } else if (a.post == POST_Q) {
+      const long long p = a.off + (long long)row * a.pitch + c;
+      a.real_out[p] = v.x * a.scale * a.inv_xi + a.tauc[p] * a.pvec[p];
+    } else {   // POST_REAL
+      a.real_out[a.off + (long long)row * a.pitch + c] = v.x * a.scale;
+    }
+  }
+}
+
+// out (W x H) = transpose of in (H x W), 64 x 64 tiles through LDS
+__global__ __launch_bounds__(256) void k_transpose(const float2* __restrict__ in,
+                                                   float2* __restrict__ out, int H, int W) {
+  __shared__ float2 tile[64][65];
+  const int bx = blockIdx.x * 64, by = blockIdx.y * 64;
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  for (int r = ty; r < 64; r += 4) {
+    const int gr = by + r, gc = bx + tx;
+    if (gr < H && gc < W) tile[r][tx] = in[(long long)gr * W + gc];
+  }
+  __syncthreads();
+  for (int r = ty; r < 64; r += 4) {
+    const int gc = bx + r, gr = by + tx;   // output row = input column
+    if (gc < W && gr < H) out[(long long)gc * H + gr] = tile[tx][r];
+  }
+}
+
+__global__ void k_twiddles(float2* tw, int L) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= L / 2) return;
+  double s, c;
+  sincos(-6.283185307179586476925 * (double)t / (double)L, &s, &c);
+  tw[t] = make_float2((float)c, (float)s);
+}
+
+// eigenvalues of H^T H: (mask(w) + mask(-w)) / 2, in the plane layout (for the
+// spectral estimator) and in the transposed dense layout (for the products)
+__global__ void k_dft_spectrum(const uint8_t* __restrict__ mask, float* __restrict__ spec_plane,
+                               long long off, int pitch, float* __restrict__ specT, int H, int W) {
+  const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (i >= (long long)H * W) return;
+  const int r = (int)(i / W), c = (int)(i % W);
+  const int rn = (H - r) % H, cn = (W - c) % W;
+  const float v = 0.5f * ((mask[i] ? 1.f : 0.f) + (mask[(long long)rn * W + cn] ? 1.f : 0.f));
+  spec_plane[off + (long long)r * pitch + c] = v;
+  specT[(long long)c * H + r] = v;
+}
+
+// per-tile partial sums of p.q for DFT instances (the FFT passes work on rows)
+__global__ __launch_bounds__(256) void k_dot_tiles(const LikInst* __restrict__ inst,
+                                                   const int4* __restrict__ tiles, int tile0,
+                                                   int ntiles, const float* __restrict__ pv,
+                                                   const float* __restrict__ q,
+                                                   double* __restrict__ part0,
+                                                   double* __restrict__ part1,
+                                                   const InstState* __restrict__ st) {
+  __shared__ double sa[256];
+  const int tile = tile0 + blockIdx.x;
+  const int4 td = tiles[tile];
+  const LikInst L = inst[td.x];
+  double acc = 0.0;
+  if (!st[L.inst].cg_done) {
+    const int c0 = td.y * kLikTW, r0 = td.z * kLikTH;
+    const int c1 = min(c0 + kLikTW, L.W), r1 = min(r0 + kLikTH, L.H);
+    const int cols = c1 - c0, n = cols * (r1 - r0);
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+      const long long p = L.off + (long long)(r0 + i / cols) * L.pitch + (c0 + i % cols);
+      acc += (double)pv[p] * (double)q[p];
+    }
+  }
+  sa[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 128; w >= 1; w >>= 1) {
+    if ((int)threadIdx.x < w) sa[threadIdx.x] += sa[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    part0[tile] = sa[0];
+    part1[tile] = 0.0;
+  }
+  (void)ntiles;
+}
+
+// ---------------------------------------------------------------------------
+// host side
+
+static int ilog2(int n) {
+  int l = 0;
+  while ((1 << l) < n) ++l;
+  return l;
+}
+
+static hipError_t rows(const FftArgs& a, hipStream_t s) {
+  const size_t sh = sizeof(float2) * 2 * (size_t)a.L;
+  hipLaunchKernelGGL(k_fft_rows, dim3(a.nrows), dim3(256), sh, s, a);
+  return hipGetLastError();
+}
+
+static FftArgs base_args(const LikCtx& lc, const LikInst& L) {
+  FftArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.st = lc.d_st;
+  a.inst = L.inst;
+  a.off = L.off;
+  a.pitch = L.pitch;
+  a.scale = 1.f;
+  a.inv_xi = L.inv_xi;
+  a.diagA = L.diagA;
+  a.tauc = lc.planes[LP_TAUC];
+  return a;
+}
+
+hipError_t dft_setup(LikCtx& lc, const LikInstInfo* li, int n, hipStream_t s, std::string& err) {
+  auto& list = lc.dft;
+  list.clear();
+  // workspace: per DFT instance A, B (complex N each), twiddles, transposed spectrum, mask
+  char* cur = reinterpret_cast<char*>(lc.fft);
+  size_t used = 0;
+  for (size_t k = 0; k < lc.hinst.size(); ++k) {
+    const LikInst& L = lc.hinst[k];
+    if (L.op != OP_DFT) continue;
+    const LikInstInfo& I = li[L.inst];
+    DftPlan d;
+    d.li = (int)k;
+    d.H = L.H; d.W = L.W; d.logH = ilog2(L.H); d.logW = ilog2(L.W);
+    const size_t N = (size_t)L.H * L.W;
+    auto take = [&](size_t bytes) {
+      char* p = cur + used;
+      used += (bytes + 255) / 256 * 256;
+      return p;
+    };
+    d.A = reinterpret_cast<float2*>(take(N * sizeof(float2)));
+    d.B = reinterpret_cast<float2*>(take(N * sizeof(float2)));
+    d.twW = reinterpret_cast<float2*>(take(sizeof(float2) * (L.W / 2)));
+    d.twH = reinterpret_cast<float2*>(take(sizeof(float2) * (L.H / 2)));
+    d.specT = reinterpret_cast<float*>(take(N * sizeof(float)));
+    d.mask = reinterpret_cast<uint8_t*>(take(N));
+    hipError_t e = hipMemcpyAsync(d.mask, I.mask, N, hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_twiddles, dim3((L.W / 2 + 255) / 256), dim3(256), 0, s, d.twW, L.W);
+    hipLaunchKernelGGL(k_twiddles, dim3((L.H / 2 + 255) / 256), dim3(256), 0, s, d.twH, L.H);
+    hipLaunchKernelGGL(k_dft_spectrum, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, d.mask,
+                       lc.planes[LP_SPEC], L.off, L.pitch, d.specT, L.H, L.W);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    list.push_back(d);
+  }
+  (void)n;
+  (void)err;
+  return hipStreamSynchronize(s);   // the host mask copies must finish before they go away
+}
+
+// Forward 2-D DFT (unnormalised) of the A rows prepared by `pre`, result in B
+// (transposed layout), multiplied by mul * scale.
+static hipError_t forward_into_B(DftPlan& d, FftArgs pre, const float* mul, float scale,
+                                 hipStream_t s) {
+  pre.dst = d.A; pre.tw = d.twW; pre.nrows = d.H; pre.L = d.W; pre.logL = d.logW;
+  pre.post = POST_COMPLEX; pre.inverse = 0;
+  hipError_t e = rows(pre, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_transpose, dim3((d.W + 63) / 64, (d.H + 63) / 64), dim3(256), 0, s, d.A,
+                     d.B, d.H, d.W);
+  FftArgs c = pre;
+  c.pre = PRE_COMPLEX; c.src = d.B; c.dst = d.B; c.tw = d.twH; c.nrows = d.W; c.L = d.H;
+  c.logL = d.logH; c.post = POST_SCALE; c.mul = mul; c.scale = scale;
+  return rows(c, s);
+}
+
+// Inverse 2-D DFT (unnormalised) of B (transposed layout); the last row pass
+// applies `post` (real result times scale).
+static hipError_t inverse_from_B(DftPlan& d, FftArgs post, hipStream_t s) {
+  FftArgs c = post;
+  c.pre = PRE_COMPLEX; c.src = d.B; c.dst = d.B; c.tw = d.twH; c.nrows = d.W; c.L = d.H;
+  c.logL = d.logH; c.post = POST_COMPLEX; c.inverse = 1;
+  hipError_t e = rows(c, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_transpose, dim3((d.H + 63) / 64, (d.W + 63) / 64), dim3(256), 0, s, d.B,
+                     d.A, d.W, d.H);
+  FftArgs r = post;
+  r.pre = PRE_COMPLEX; r.src = d.A; r.tw = d.twW; r.nrows = d.H; r.L = d.W; r.logL = d.logW;
+  r.inverse = 1;
+  return rows(r, s);
+}
+
+hipError_t dft_set_observation(LikCtx& lc, const float* const* d_y, hipStream_t s) {
+  for (DftPlan& d : lc.dft) {
+    const LikInst& L = lc.hinst[d.li];
+    const double N = (double)d.H * d.W;
+    // H^T y = Re(F^H diag(mask) y) = Re(IDFT(mask y)) / sqrt(N), then y_pix = H^T y.
+    // The masked observation is copied into A (a row pass without stages is a
+    // plain copy), transposed into B and inverse-transformed.
+    FftArgs a = base_args(lc, L);
+    a.pre = PRE_OBS; a.obs = d_y[L.inst]; a.mask = d.mask;
+    a.dst = d.A; a.tw = d.twW; a.nrows = d.H; a.L = d.W; a.logL = 0; a.post = POST_COMPLEX;
+    hipError_t e = rows(a, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_transpose, dim3((d.W + 63) / 64, (d.H + 63) / 64), dim3(256), 0, s, d.A,
+                       d.B, d.H, d.W);
+    FftArgs post = base_args(lc, L);
+    post.post = POST_REAL;
+    post.real_out = lc.planes[LP_HTY];
+    post.scale = (float)(1.0 / std::sqrt(N));
+    if ((e = inverse_from_B(d, post, s)) != hipSuccess) return e;
+    // the cold start and the observation range use H^T y as the pixel-space observation
+    e = hipMemcpy2DAsync(lc.ypix + L.off, sizeof(float) * L.pitch, lc.planes[LP_HTY] + L.off,
+                         sizeof(float) * L.pitch, sizeof(float) * L.W, L.H,
+                         hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess) return e;
+  }
   return hipSuccess;
 }
-hipError_t dft_set_observation(LikCtx&, const float* const*, hipStream_t) { return hipSuccess; }
-hipError_t dft_apply(LikCtx&, int, hipStream_t) { return hipSuccess; }
-void dft_destroy(LikCtx&) {}
+
+hipError_t dft_apply(LikCtx& lc, int mode, hipStream_t s) {
+  for (DftPlan& d : lc.dft) {
+    const LikInst& L = lc.hinst[d.li];
+    const double N = (double)d.H * d.W;
+    float* p_in = lc.planes[lc.pcur ? LP_P1 : LP_P0];
+    float* p_out = lc.planes[lc.pcur ? LP_P0 : LP_P1];
+    // the CG kernels skip converged instances on the device; the transform
+    // itself always runs (its cost is independent of the values)
+    FftArgs pre = base_args(lc, L);
+    pre.pre = PRE_DIRECTION;
+    pre.r = lc.planes[LP_R]; pre.x = lc.planes[LP_X]; pre.p_in = p_in; pre.p_out = p_out;
+    pre.mode0 = mode == 0;
+    pre.zpl = nullptr;
+    hipError_t e = forward_into_B(d, pre, d.specT, (float)(1.0 / N), s);
+    if (e != hipSuccess) return e;
+    FftArgs post = base_args(lc, L);
+    post.post = POST_Q;
+    post.real_out = lc.planes[LP_Q];
+    post.pvec = mode == 0 ? lc.planes[LP_X] : p_out;
+    post.scale = 1.f;
+    if ((e = inverse_from_B(d, post, s)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_dot_tiles, dim3(L.ntiles), dim3(256), 0, s, lc.d_inst, lc.d_tiles, L.tile0,
+                       L.ntiles, post.pvec, lc.planes[LP_Q], lc.part0, lc.part1, lc.d_st);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+void dft_destroy(LikCtx& lc) { lc.dft.clear(); }
 
 }  // namespace eptv

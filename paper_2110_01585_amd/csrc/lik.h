@@ -82,13 +82,35 @@ void lik_layout(const LikInstInfo* li, int n, long long plane, Take&& take, LikL
   L.part0 = take(sizeof(double) * (size_t)std::max(L.ntiles, 1));
   L.part1 = take(sizeof(double) * (size_t)std::max(L.ntiles, 1));
   L.taps = take(sizeof(float) * (size_t)std::max(L.ntaps, 1));
-  // complex work buffers of the FFT path: two complex planes of the largest DFT instance
-  L.fft_bytes = (size_t)fft_elems * 2 * sizeof(float2);
+  // FFT work buffers, per DFT instance: two complex planes, twiddles, the
+  // transposed spectrum and the mask (each rounded up to 256 bytes)
+  L.fft_bytes = 0;
+  for (int i = 0; i < n; ++i) {
+    if (li[i].op != OP_DFT) continue;
+    const size_t N = (size_t)li[i].H * li[i].W;
+    auto r256 = [](size_t b) { return (b + 255) / 256 * 256; };
+    L.fft_bytes += 2 * r256(N * 8) + r256((size_t)li[i].W * 4) + r256((size_t)li[i].H * 4) +
+                   r256(N * 4) + r256(N);
+  }
+  (void)fft_elems;
   L.fft = take(std::max<size_t>(L.fft_bytes, 256));
 }
 
+// One masked-DFT instance's FFT work buffers (all in the workspace).
+struct DftPlan {
+  int li = 0;                // index into LikCtx::hinst
+  int H = 0, W = 0, logH = 0, logW = 0;
+  float2* A = nullptr;       // H x W complex
+  float2* B = nullptr;       // W x H complex (transposed layout)
+  float2* twW = nullptr;     // W/2 twiddles e^{-2 pi i t / W}
+  float2* twH = nullptr;     // H/2 twiddles
+  float* specT = nullptr;    // W x H eigenvalues of H^T H (transposed layout)
+  uint8_t* mask = nullptr;   // H x W
+};
+
 struct LikCtx {
   int nlik = 0, ntiles = 0;
+  std::vector<DftPlan> dft;
   std::vector<LikInst> hinst;
   std::vector<int> inst_of;          // lik index -> instance index
   LikInst* d_inst = nullptr;

@@ -527,7 +527,7 @@ hipError_t lik_create(LikCtx& lc, const LikInstInfo* li, int n, char* ws, const 
         taps.push_back((float)(sep ? acc : 0.0));
       }
     } else if (I.op == OP_DFT) {
-      d.Rr = 0; d.Rc = 0; d.sep = 0;
+      d.Rr = 0; d.Rc = 0; d.sep = 0; d.kh = 1; d.kw = 1;
       // H^T H of the masked orthonormal DFT has unit diagonal times the kept fraction
       int kept = 0;
       for (long long q = 0; q < (long long)I.H * I.W; ++q) kept += I.mask[q] ? 1 : 0;
