@@ -184,6 +184,16 @@ int ep_tv_get_stats(ep_tv_ctx* ctx, ep_tv_stats* stats);
 int ep_tv_tilted_moments(int32_t n, const float* d_m, const float* d_s, float lambda,
                          float* d_rho, float* d_delta, float* d_eabs, void* hip_stream);
 
+/* Diagnostic copy of the likelihood-site working planes of one instance with
+ * a non-identity operator (Eqs. (tilted_P_1), (update_q0_x)): d_out (device,
+ * 10*height*width floats, planar) receives, in order, E (the CG iterate),
+ * tau_c and eta_c (cavity of site 0), b = H^T y / xi + eta_c, the CG residual r,
+ * the preconditioned residual z, |H(w)|^2 (frequency (r, c) at pixel (r, c)),
+ * the two search-direction buffers and the last product q = A p.  Returns
+ * EP_TV_E_ARG for an identity-operator instance.
+ * Asynchronous. */
+int ep_tv_get_lik_planes(ep_tv_ctx* ctx, int32_t instance, float* d_out);
+
 /* Kernel timing for measurement.  With timing enabled, HIP events are recorded
  * on the context's stream around every launch of the fused TV sweep kernel and
  * around every likelihood-site update (its CG solve and site kernels), and

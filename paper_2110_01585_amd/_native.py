@@ -77,6 +77,7 @@ SIGNATURES = {
     "ep_tv_get_sites": (ctypes.c_int, [_P, _FPP]),
     "ep_tv_set_sites": (ctypes.c_int, [_P, _FPP, ctypes.POINTER(ctypes.c_double)]),
     "ep_tv_get_stats": (ctypes.c_int, [_P, ctypes.POINTER(EpTvStats)]),
+    "ep_tv_get_lik_planes": (ctypes.c_int, [_P, ctypes.c_int32, _P]),
     "ep_tv_tilted_moments": (ctypes.c_int, [ctypes.c_int32, _P, _P, ctypes.c_float, _P, _P, _P, _P]),
     "ep_tv_set_timing": (ctypes.c_int, [_P, ctypes.c_int32]),
     "ep_tv_get_timing": (ctypes.c_int, [_P, ctypes.POINTER(EpTvTiming)]),

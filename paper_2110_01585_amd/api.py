@@ -187,6 +187,10 @@ class Context:
         self._check(N.lib().ep_tv_get_stats(self.handle, st), "get_stats")
         return [self._stats_dict(s) for s in st]
 
+    def ep_tv_get_lik_planes(self, instance: int, out):
+        return self._check(N.lib().ep_tv_get_lik_planes(self.handle, int(instance), out.data_ptr()),
+                           "get_lik_planes")
+
     def ep_tv_set_timing(self, enable: bool):
         return self._check(N.lib().ep_tv_set_timing(self.handle, int(bool(enable))), "set_timing")
 

@@ -125,6 +125,8 @@ void make_layout(std::vector<InstHost>& ih, Layout& L) {
     li[i].op = ih[i].p.op;
     li[i].H = ih[i].p.height;
     li[i].W = ih[i].p.width;
+    li[i].th = ih[i].p.op == EP_TV_OP_BLUR_PERIODIC ? ih[i].p.blur_h : 0;
+    li[i].tw = ih[i].p.op == EP_TV_OP_BLUR_PERIODIC ? ih[i].p.blur_w : 0;
   }
   lik_layout(li.data(), n, L.plane, take, L.lik);
   L.total = cur;
@@ -554,6 +556,20 @@ int ep_tv_get_stats(ep_tv_ctx* c, ep_tv_stats* stats) {
   int rc = pull_states(c);
   if (rc) return rc;
   fill_stats(c, stats);
+  return EP_TV_OK;
+}
+
+int ep_tv_get_lik_planes(ep_tv_ctx* c, int32_t instance, float* d_out) {
+  if (!c || !d_out || instance < 0 || instance >= c->n) return EP_TV_E_ARG;
+  const InstHost& h = c->ih[instance];
+  if (h.p.op == EP_TV_OP_IDENTITY) return fail(c, EP_TV_E_ARG, "identity operator has no likelihood planes");
+  const int which[10] = {LP_X, LP_TAUC, LP_ETAC, LP_B, LP_R, LP_Z, LP_SPEC, LP_P0, LP_P1, LP_Q};
+  const size_t plane = (size_t)h.p.height * h.p.width;
+  for (int k = 0; k < 10; ++k)
+    HIPCHK(c, hipMemcpy2DAsync(d_out + k * plane, sizeof(float) * h.p.width,
+                               c->lik.planes[which[k]] + h.off, sizeof(float) * h.pitch,
+                               sizeof(float) * h.p.width, h.p.height, hipMemcpyDeviceToDevice,
+                               c->stream));
   return EP_TV_OK;
 }
 

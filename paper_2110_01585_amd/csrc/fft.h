@@ -1,5 +1,6 @@
-// Masked orthonormal 2-D DFT operator (compressive sensing): H^T y, |H(w)|^2
-// and H^T H v = Re(F^H diag(mask) F v), built on a hand-written FFT.
+// Hand-written FFT and what is built on it: the masked orthonormal 2-D DFT
+// operator (compressive sensing: H^T y, |H(w)|^2, H^T H v) and the circulant
+// CG preconditioner (H^T H / xi + d_bar I)^{-1}.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -10,10 +11,14 @@
 
 namespace eptv {
 
-hipError_t dft_setup(LikCtx& lc, const LikInstInfo* li, int n, hipStream_t s, std::string& err);
+hipError_t dft_setup(LikCtx& lc, const LikInstInfo* li, int n, size_t fft_bytes, hipStream_t s,
+                     std::string& err);
 hipError_t dft_set_observation(LikCtx& lc, const float* const* d_y, hipStream_t s);
 // mode 0: q = A x; mode 1: p_out = z + beta p_in, q = A p_out (with v.q partials)
 hipError_t dft_apply(LikCtx& lc, int mode, hipStream_t s);
 void dft_destroy(LikCtx& lc);
+// z = M^{-1} r with the circulant M = H^T H / xi + d_bar I, for instances
+// whose preconditioner is PRECOND_CIRCULANT
+hipError_t fft_precondition(LikCtx& lc, hipStream_t s);
 
 }  // namespace eptv

@@ -8,9 +8,10 @@
 // and H^T H is circulant with eigenvalues (mask(w) + mask(-w)) / 2.
 //
 // FFT: power-of-two lengths up to 4096.  A 2-D transform is a batch of row
-// FFTs (one row per workgroup, the whole row in LDS, radix-2 Stockham
-// auto-sort stages, twiddles from a table), a tiled transpose, and a second
-// batch of row FFTs; the spectrum-domain products are applied in that
+// FFTs (whole rows in LDS, up to 4096 points per workgroup; Stockham auto-sort
+// passes of radix 16, then 8, 4 or 2, each work item doing its radix-R DFT in
+// registers; twiddles from a full-circle table), a tiled transpose, and a
+// second batch of row FFTs; the spectrum-domain products are applied in that
 // transposed layout (element (c, r) holds frequency (r, c)), and the inverse
 // transform undoes the transpose.  Loads and stores of every pass are
 // contiguous per row.  Element-wise work before and after the transform
@@ -33,7 +34,8 @@ enum {
   POST_COMPLEX = 0,  // store the complex row to `dst`
   POST_SCALE,        // multiply by `mul` (transposed layout, real) then store
   POST_Q,            // q = Re(v) * scale / xi + tau_c * p  (real plane), store q
-  POST_REAL          // real part * scale -> real plane
+  POST_REAL,         // real part * scale -> real plane
+  POST_PRECOND       // multiply by scale / (mul / xi + d_bar) (transposed layout), store
 };
 
 struct FftArgs {
@@ -65,14 +67,108 @@ __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
   return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 
+// ---- in-register DFTs of size 2..16 (radix-2 decimation in time) ----
+// cos and sin of 2 pi k / 16
+__constant__ float kC16[16] = {1.0f, 0.92387953251128674f, 0.70710678118654752f,
+                               0.38268343236508977f, 0.0f, -0.38268343236508977f,
+                               -0.70710678118654752f, -0.92387953251128674f, -1.0f,
+                               -0.92387953251128674f, -0.70710678118654752f,
+                               -0.38268343236508977f, 0.0f, 0.38268343236508977f,
+                               0.70710678118654752f, 0.92387953251128674f};
+
+__device__ constexpr int bitrev_c(int i, int bits) {
+  int r = 0;
+  for (int b = 0; b < bits; ++b) r |= ((i >> b) & 1) << (bits - 1 - b);
+  return r;
+}
+
+template <int R>
+__device__ __forceinline__ void dft_reg(float2 (&v)[R], float sgn) {
+  constexpr int bits = R == 2 ? 1 : R == 4 ? 2 : R == 8 ? 3 : 4;
+#pragma unroll
+  for (int i = 0; i < R; ++i) {
+    const int j = bitrev_c(i, bits);
+    if (j > i) {
+      const float2 t = v[i];
+      v[i] = v[j];
+      v[j] = t;
+    }
+  }
+#pragma unroll
+  for (int m = 2; m <= R; m <<= 1) {
+#pragma unroll
+    for (int k = 0; k < R; k += m) {
+#pragma unroll
+      for (int j = 0; j < m / 2; ++j) {
+        // w = e^{sgn 2 pi i j / m} = cos + i sgn sin, index j * 16 / m into the 16-point table
+        const int t = j * (16 / m);
+        const float c = kC16[t], sn = kC16[(t + 12) & 15];   // sin(x) = cos(x - pi/2)
+        const float2 b = v[k + j + m / 2];
+        const float2 tw = make_float2(c * b.x - sgn * sn * b.y, c * b.y + sgn * sn * b.x);
+        const float2 u = v[k + j];
+        v[k + j] = make_float2(u.x + tw.x, u.y + tw.y);
+        v[k + j + m / 2] = make_float2(u.x - tw.x, u.y - tw.y);
+      }
+    }
+  }
+}
+
+// One radix-R Stockham pass over `rows` rows of length L held in LDS, in place:
+// every work item reads its R inputs into registers before the barrier and
+// writes its R outputs after it.  Work item j of a row (j < L/R), k = j mod Ns:
+//   in:  X[j + r L/R],  twiddled by e^{sgn 2 pi i r k / (R Ns)}
+//   out: X[(j - k) R + k + r Ns]
+template <int R>
+__device__ __forceinline__ void stockham_pass(float2* X, int rows, int L, int Ns,
+                                              const float2* __restrict__ tw, float sgn) {
+  constexpr int kItems = 16 / R;               // work items per thread (rows * L <= 4096)
+  const int per_row = L / R;
+  const int total = rows * per_row;
+  float2 v[kItems][R];
+  int base[kItems];
+#pragma unroll
+  for (int it = 0; it < kItems; ++it) {
+    const int w = threadIdx.x + it * 256;
+    base[it] = -1;
+    if (w < total) {
+      const int row = w / per_row, j = w % per_row;
+      const int k = j & (Ns - 1);
+      float2* Xr = X + row * L;
+      const int step = L / (R * Ns);
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        float2 x = Xr[j + r * per_row];
+        if (r > 0) {
+          float2 t = tw[r * k * step];
+          t.y *= -sgn;        // table holds e^{-2 pi i t / L}; sgn = +1 for the inverse
+          x = cmul(x, t);
+        }
+        v[it][r] = x;
+      }
+      base[it] = row * L + (j - k) * R + k;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int it = 0; it < kItems; ++it) {
+    if (base[it] >= 0) {
+      dft_reg<R>(v[it], sgn);
+#pragma unroll
+      for (int r = 0; r < R; ++r) X[base[it] + r * Ns] = v[it][r];
+    }
+  }
+  __syncthreads();
+}
+
+template <int L>
 __global__ __launch_bounds__(256) void k_fft_rows(FftArgs a) {
-  extern __shared__ float2 sm[];
-  float2* X = sm;
-  float2* Y = sm + a.L;
-  const int row = blockIdx.x;
-  const int L = a.L;
+  constexpr int kRows = L >= 4096 ? 1 : (4096 / L > 16 ? 16 : 4096 / L);
+  __shared__ float2 X[kRows * L];
+  const int row0 = blockIdx.x * kRows;
+  const int rows = min(kRows, a.nrows - row0);
   // ---- load (pre-op) ----
-  for (int c = threadIdx.x; c < L; c += blockDim.x) {
+  for (int i = threadIdx.x; i < rows * L; i += blockDim.x) {
+    const int row = row0 + i / L, c = i % L;
     float2 v;
     if (a.pre == PRE_COMPLEX) {
       v = a.src[(long long)row * L + c];
@@ -94,28 +190,23 @@ __global__ __launch_bounds__(256) void k_fft_rows(FftArgs a) {
       const long long q = (long long)row * L + c;
       v = a.mask[q] ? make_float2(a.obs[2 * q], a.obs[2 * q + 1]) : make_float2(0.f, 0.f);
     }
-    X[c] = v;
+    X[i] = v;
   }
   __syncthreads();
-  // ---- radix-2 Stockham stages ----
-  const int half = L >> 1;
-  for (int s = 0, Ns = 1; s < a.logL; ++s, Ns <<= 1) {
-    for (int j = threadIdx.x; j < half; j += blockDim.x) {
-      const int k = j & (Ns - 1);
-      float2 w = a.tw[k * (half / Ns)];
-      if (a.inverse) w.y = -w.y;
-      const float2 u = X[j];
-      const float2 t = cmul(X[j + half], w);
-      const int o = ((j - k) << 1) + k;
-      Y[o] = make_float2(u.x + t.x, u.y + t.y);
-      Y[o + Ns] = make_float2(u.x - t.x, u.y - t.y);
-    }
-    __syncthreads();
-    float2* T = X; X = Y; Y = T;
+  // ---- Stockham passes: radix 16 while possible, then 8, 4, 2 ----
+  if (a.logL > 0) {
+    const float sgn = a.inverse ? 1.f : -1.f;
+    int Ns = 1;
+    int rem = a.logL;
+    while (rem >= 4) { stockham_pass<16>(X, rows, L, Ns, a.tw, sgn); Ns *= 16; rem -= 4; }
+    if (rem == 3) stockham_pass<8>(X, rows, L, Ns, a.tw, sgn);
+    else if (rem == 2) stockham_pass<4>(X, rows, L, Ns, a.tw, sgn);
+    else if (rem == 1) stockham_pass<2>(X, rows, L, Ns, a.tw, sgn);
   }
   // ---- store (post-op) ----
-  for (int c = threadIdx.x; c < L; c += blockDim.x) {
-    const float2 v = X[c];
+  for (int i = threadIdx.x; i < rows * L; i += blockDim.x) {
+    const int row = row0 + i / L, c = i % L;
+    const float2 v = X[i];
     if (a.post == POST_COMPLEX) {
       a.dst[(long long)row * L + c] = v;
     } else if (a.post == POST_SCALE) {
@@ -124,8 +215,12 @@ __global__ __launch_bounds__(256) void k_fft_rows(FftArgs a) {
     } else if (a.post == POST_Q) {
       const long long p = a.off + (long long)row * a.pitch + c;
       a.real_out[p] = v.x * a.scale * a.inv_xi + a.tauc[p] * a.pvec[p];
-    } else {   // POST_REAL
+    } else if (a.post == POST_REAL) {
       a.real_out[a.off + (long long)row * a.pitch + c] = v.x * a.scale;
+    } else {   // POST_PRECOND
+      const float dbar = (float)a.st[a.inst].dbar;
+      const float m = a.scale / (a.mul[(long long)row * L + c] * a.inv_xi + dbar);
+      a.dst[(long long)row * L + c] = make_float2(v.x * m, v.y * m);
     }
   }
 }
@@ -149,7 +244,7 @@ __global__ __launch_bounds__(256) void k_transpose(const float2* __restrict__ in
 
 __global__ void k_twiddles(float2* tw, int L) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= L / 2) return;
+  if (t >= L) return;
   double s, c;
   sincos(-6.283185307179586476925 * (double)t / (double)L, &s, &c);
   tw[t] = make_float2((float)c, (float)s);
@@ -166,6 +261,15 @@ __global__ void k_dft_spectrum(const uint8_t* __restrict__ mask, float* __restri
   const float v = 0.5f * ((mask[i] ? 1.f : 0.f) + (mask[(long long)rn * W + cn] ? 1.f : 0.f));
   spec_plane[off + (long long)r * pitch + c] = v;
   specT[(long long)c * H + r] = v;
+}
+
+// transposed dense copy of a spectrum plane
+__global__ void k_spec_to_T(const float* __restrict__ spec_plane, long long off, int pitch,
+                            float* __restrict__ specT, int H, int W) {
+  const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (i >= (long long)H * W) return;
+  const int r = (int)(i / W), c = (int)(i % W);
+  specT[(long long)c * H + r] = spec_plane[off + (long long)r * pitch + c];
 }
 
 // per-tile partial sums of p.q for DFT instances (the FFT passes work on rows)
@@ -212,9 +316,27 @@ static int ilog2(int n) {
   return l;
 }
 
+template <int L>
+static void launch_rows(const FftArgs& a, hipStream_t s) {
+  constexpr int kRows = L >= 4096 ? 1 : (4096 / L > 16 ? 16 : 4096 / L);
+  hipLaunchKernelGGL(k_fft_rows<L>, dim3((a.nrows + kRows - 1) / kRows), dim3(256), 0, s, a);
+}
+
 static hipError_t rows(const FftArgs& a, hipStream_t s) {
-  const size_t sh = sizeof(float2) * 2 * (size_t)a.L;
-  hipLaunchKernelGGL(k_fft_rows, dim3(a.nrows), dim3(256), sh, s, a);
+  switch (a.L) {
+    case 4: launch_rows<4>(a, s); break;
+    case 8: launch_rows<8>(a, s); break;
+    case 16: launch_rows<16>(a, s); break;
+    case 32: launch_rows<32>(a, s); break;
+    case 64: launch_rows<64>(a, s); break;
+    case 128: launch_rows<128>(a, s); break;
+    case 256: launch_rows<256>(a, s); break;
+    case 512: launch_rows<512>(a, s); break;
+    case 1024: launch_rows<1024>(a, s); break;
+    case 2048: launch_rows<2048>(a, s); break;
+    case 4096: launch_rows<4096>(a, s); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 
@@ -232,7 +354,8 @@ static FftArgs base_args(const LikCtx& lc, const LikInst& L) {
   return a;
 }
 
-hipError_t dft_setup(LikCtx& lc, const LikInstInfo* li, int n, hipStream_t s, std::string& err) {
+hipError_t dft_setup(LikCtx& lc, const LikInstInfo* li, int n, size_t fft_bytes, hipStream_t s,
+                     std::string& err) {
   auto& list = lc.dft;
   list.clear();
   // workspace: per DFT instance A, B (complex N each), twiddles, transposed spectrum, mask
@@ -240,7 +363,7 @@ hipError_t dft_setup(LikCtx& lc, const LikInstInfo* li, int n, hipStream_t s, st
   size_t used = 0;
   for (size_t k = 0; k < lc.hinst.size(); ++k) {
     const LikInst& L = lc.hinst[k];
-    if (L.op != OP_DFT) continue;
+    if (!lik_uses_fft(L.op, L.H, L.W)) continue;
     const LikInstInfo& I = li[L.inst];
     DftPlan d;
     d.li = (int)k;
@@ -253,16 +376,26 @@ hipError_t dft_setup(LikCtx& lc, const LikInstInfo* li, int n, hipStream_t s, st
     };
     d.A = reinterpret_cast<float2*>(take(N * sizeof(float2)));
     d.B = reinterpret_cast<float2*>(take(N * sizeof(float2)));
-    d.twW = reinterpret_cast<float2*>(take(sizeof(float2) * (L.W / 2)));
-    d.twH = reinterpret_cast<float2*>(take(sizeof(float2) * (L.H / 2)));
+    d.twW = reinterpret_cast<float2*>(take(sizeof(float2) * L.W));
+    d.twH = reinterpret_cast<float2*>(take(sizeof(float2) * L.H));
     d.specT = reinterpret_cast<float*>(take(N * sizeof(float)));
     d.mask = reinterpret_cast<uint8_t*>(take(N));
-    hipError_t e = hipMemcpyAsync(d.mask, I.mask, N, hipMemcpyHostToDevice, s);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_twiddles, dim3((L.W / 2 + 255) / 256), dim3(256), 0, s, d.twW, L.W);
-    hipLaunchKernelGGL(k_twiddles, dim3((L.H / 2 + 255) / 256), dim3(256), 0, s, d.twH, L.H);
-    hipLaunchKernelGGL(k_dft_spectrum, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, d.mask,
-                       lc.planes[LP_SPEC], L.off, L.pitch, d.specT, L.H, L.W);
+    if (used > fft_bytes) {
+      err = "FFT workspace layout mismatch";
+      return hipErrorInvalidValue;
+    }
+    hipError_t e = hipSuccess;
+    hipLaunchKernelGGL(k_twiddles, dim3((L.W + 255) / 256), dim3(256), 0, s, d.twW, L.W);
+    hipLaunchKernelGGL(k_twiddles, dim3((L.H + 255) / 256), dim3(256), 0, s, d.twH, L.H);
+    if (L.op == OP_DFT) {
+      if ((e = hipMemcpyAsync(d.mask, I.mask, N, hipMemcpyHostToDevice, s)) != hipSuccess) return e;
+      hipLaunchKernelGGL(k_dft_spectrum, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, d.mask,
+                         lc.planes[LP_SPEC], L.off, L.pitch, d.specT, L.H, L.W);
+    } else {
+      // the blur spectrum plane was written by the setup kernel already
+      hipLaunchKernelGGL(k_spec_to_T, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s,
+                         lc.planes[LP_SPEC], L.off, L.pitch, d.specT, L.H, L.W);
+    }
     if ((e = hipGetLastError()) != hipSuccess) return e;
     list.push_back(d);
   }
@@ -274,7 +407,7 @@ hipError_t dft_setup(LikCtx& lc, const LikInstInfo* li, int n, hipStream_t s, st
 // Forward 2-D DFT (unnormalised) of the A rows prepared by `pre`, result in B
 // (transposed layout), multiplied by mul * scale.
 static hipError_t forward_into_B(DftPlan& d, FftArgs pre, const float* mul, float scale,
-                                 hipStream_t s) {
+                                 hipStream_t s, int post_mode = POST_SCALE) {
   pre.dst = d.A; pre.tw = d.twW; pre.nrows = d.H; pre.L = d.W; pre.logL = d.logW;
   pre.post = POST_COMPLEX; pre.inverse = 0;
   hipError_t e = rows(pre, s);
@@ -283,7 +416,7 @@ static hipError_t forward_into_B(DftPlan& d, FftArgs pre, const float* mul, floa
                      d.B, d.H, d.W);
   FftArgs c = pre;
   c.pre = PRE_COMPLEX; c.src = d.B; c.dst = d.B; c.tw = d.twH; c.nrows = d.W; c.L = d.H;
-  c.logL = d.logH; c.post = POST_SCALE; c.mul = mul; c.scale = scale;
+  c.logL = d.logH; c.post = post_mode; c.mul = mul; c.scale = scale;
   return rows(c, s);
 }
 
@@ -306,6 +439,7 @@ static hipError_t inverse_from_B(DftPlan& d, FftArgs post, hipStream_t s) {
 hipError_t dft_set_observation(LikCtx& lc, const float* const* d_y, hipStream_t s) {
   for (DftPlan& d : lc.dft) {
     const LikInst& L = lc.hinst[d.li];
+    if (L.op != OP_DFT) continue;
     const double N = (double)d.H * d.W;
     // H^T y = Re(F^H diag(mask) y) = Re(IDFT(mask y)) / sqrt(N), then y_pix = H^T y.
     // The masked observation is copied into A (a row pass without stages is a
@@ -334,6 +468,7 @@ hipError_t dft_set_observation(LikCtx& lc, const float* const* d_y, hipStream_t 
 hipError_t dft_apply(LikCtx& lc, int mode, hipStream_t s) {
   for (DftPlan& d : lc.dft) {
     const LikInst& L = lc.hinst[d.li];
+    if (L.op != OP_DFT) continue;
     const double N = (double)d.H * d.W;
     float* p_in = lc.planes[lc.pcur ? LP_P1 : LP_P0];
     float* p_out = lc.planes[lc.pcur ? LP_P0 : LP_P1];
@@ -343,7 +478,7 @@ hipError_t dft_apply(LikCtx& lc, int mode, hipStream_t s) {
     pre.pre = PRE_DIRECTION;
     pre.r = lc.planes[LP_R]; pre.x = lc.planes[LP_X]; pre.p_in = p_in; pre.p_out = p_out;
     pre.mode0 = mode == 0;
-    pre.zpl = nullptr;
+    pre.zpl = lc.planes[LP_Z];
     hipError_t e = forward_into_B(d, pre, d.specT, (float)(1.0 / N), s);
     if (e != hipSuccess) return e;
     FftArgs post = base_args(lc, L);
@@ -355,6 +490,25 @@ hipError_t dft_apply(LikCtx& lc, int mode, hipStream_t s) {
     hipLaunchKernelGGL(k_dot_tiles, dim3(L.ntiles), dim3(256), 0, s, lc.d_inst, lc.d_tiles, L.tile0,
                        L.ntiles, post.pvec, lc.planes[LP_Q], lc.part0, lc.part1, lc.d_st);
     if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t fft_precondition(LikCtx& lc, hipStream_t s) {
+  for (DftPlan& d : lc.dft) {
+    const LikInst& L = lc.hinst[d.li];
+    if (L.precond != PRECOND_CIRCULANT) continue;
+    const double N = (double)d.H * d.W;
+    FftArgs pre = base_args(lc, L);
+    pre.pre = PRE_REAL;
+    pre.real_in = lc.planes[LP_R];
+    hipError_t e = forward_into_B(d, pre, d.specT, (float)(1.0 / N), s, POST_PRECOND);
+    if (e != hipSuccess) return e;
+    FftArgs post = base_args(lc, L);
+    post.post = POST_REAL;
+    post.real_out = lc.planes[LP_Z];
+    post.scale = 1.f;
+    if ((e = inverse_from_B(d, post, s)) != hipSuccess) return e;
   }
   return hipSuccess;
 }

@@ -43,12 +43,20 @@ struct LikInst {
   int k_off, gr_off, gc_off; // offsets into the taps buffer
   float inv_xi, alpha, diagA, pad;   // diagA = sum of squared taps / xi (diagonal of H^T H / xi)
   double cg_tol2;            // squared relative residual tolerance
-  int cg_max_iters, pad2;
+  int cg_max_iters;
+  int precond;               // PRECOND_JACOBI or PRECOND_CIRCULANT
 };
 
 enum {
-  LP_HTY = 0, LP_TAUC, LP_ETAC, LP_B, LP_X, LP_R, LP_P0, LP_P1, LP_Q, LP_SPEC, LP_COUNT
+  LP_HTY = 0, LP_TAUC, LP_ETAC, LP_B, LP_X, LP_R, LP_Z, LP_P0, LP_P1, LP_Q, LP_SPEC, LP_COUNT
 };
+
+enum { PRECOND_JACOBI = 0, PRECOND_CIRCULANT = 1 };
+
+// The circulant preconditioner (and the masked-DFT operator) need FFT sizes.
+inline bool lik_uses_fft(int op, int H, int W) {
+  return op == OP_DFT || (fft_size_ok(H) && fft_size_ok(W));
+}
 
 struct LikLayout {
   size_t planes[LP_COUNT]{};
@@ -86,24 +94,25 @@ void lik_layout(const LikInstInfo* li, int n, long long plane, Take&& take, LikL
   // transposed spectrum and the mask (each rounded up to 256 bytes)
   L.fft_bytes = 0;
   for (int i = 0; i < n; ++i) {
-    if (li[i].op != OP_DFT) continue;
+    if (li[i].op == OP_IDENTITY || !lik_uses_fft(li[i].op, li[i].H, li[i].W)) continue;
     const size_t N = (size_t)li[i].H * li[i].W;
     auto r256 = [](size_t b) { return (b + 255) / 256 * 256; };
-    L.fft_bytes += 2 * r256(N * 8) + r256((size_t)li[i].W * 4) + r256((size_t)li[i].H * 4) +
+    L.fft_bytes += 2 * r256(N * 8) + r256((size_t)li[i].W * 8) + r256((size_t)li[i].H * 8) +
                    r256(N * 4) + r256(N);
   }
   (void)fft_elems;
   L.fft = take(std::max<size_t>(L.fft_bytes, 256));
 }
 
-// One masked-DFT instance's FFT work buffers (all in the workspace).
+// FFT work buffers of one instance that uses the FFT (masked DFT operator,
+// and the circulant preconditioner), all in the workspace.
 struct DftPlan {
   int li = 0;                // index into LikCtx::hinst
   int H = 0, W = 0, logH = 0, logW = 0;
   float2* A = nullptr;       // H x W complex
   float2* B = nullptr;       // W x H complex (transposed layout)
-  float2* twW = nullptr;     // W/2 twiddles e^{-2 pi i t / W}
-  float2* twH = nullptr;     // H/2 twiddles
+  float2* twW = nullptr;     // W twiddles e^{-2 pi i t / W}
+  float2* twH = nullptr;     // H twiddles
   float* specT = nullptr;    // W x H eigenvalues of H^T H (transposed layout)
   uint8_t* mask = nullptr;   // H x W
 };

@@ -41,7 +41,7 @@ struct LikArgs {
   double* part0;
   double* part1;
   const float* taps;
-  float* hty; float* tauc; float* etac; float* b; float* x; float* r;
+  float* hty; float* tauc; float* etac; float* b; float* x; float* r; float* z;
   float* p_in; float* p_out; float* q; float* spec;
 };
 
@@ -201,7 +201,7 @@ template <int MODE>
 __device__ __forceinline__ float direction(const LikArgs& A, const LikInst& L, const InstState& st,
                                            long long p) {
   if (MODE == 0) return A.x[p];
-  const float z = A.r[p] / (L.diagA + A.tauc[p]);
+  const float z = A.z[p];
   return st.cg_it == 0 ? z : z + (float)st.cg_beta * A.p_in[p];
 }
 
@@ -294,8 +294,26 @@ __global__ __launch_bounds__(256) void k_apply(LikArgs A) {
 }
 
 // ---------------------------------------------------------------------------
-// 5. CG start: r = b - A x (q holds A x); partials of r.z and r.r
+// 5. CG start: r = b - A x (q holds A x)
 __global__ __launch_bounds__(256) void k_cg_init(LikArgs A) {
+  const int tile = blockIdx.x;
+  const int4 td = A.tiles[tile];
+  const LikInst L = A.inst[td.x];
+  const InstState& st = A.st[L.inst];
+  if (st.cg_done) return;
+  const TileXY t = lik_tile(td, L);
+  const int cols = t.c1 - t.c0;
+  const int n = cols * (t.r1 - t.r0);
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    const int r = t.r0 + i / cols, c = t.c0 + i % cols;
+    const long long p = L.off + (long long)r * L.pitch + c;
+    A.r[p] = A.b[p] - A.q[p];
+  }
+}
+
+// 5b. z = M^{-1} r (Jacobi instances: here; circulant instances: z was written
+//     by the FFT pipeline) and partial sums of r.z and r.r
+__global__ __launch_bounds__(256) void k_precond_dot(LikArgs A) {
   const int tile = blockIdx.x;
   const int4 td = A.tiles[tile];
   const LikInst L = A.inst[td.x];
@@ -305,42 +323,42 @@ __global__ __launch_bounds__(256) void k_cg_init(LikArgs A) {
     const TileXY t = lik_tile(td, L);
     const int cols = t.c1 - t.c0;
     const int n = cols * (t.r1 - t.r0);
+    const bool jac = L.precond == PRECOND_JACOBI;
     for (int i = threadIdx.x; i < n; i += blockDim.x) {
       const int r = t.r0 + i / cols, c = t.c0 + i % cols;
       const long long p = L.off + (long long)r * L.pitch + c;
-      const float rv = A.b[p] - A.q[p];
-      A.r[p] = rv;
-      rz += (double)rv * (double)rv / (double)(L.diagA + A.tauc[p]);
+      const float rv = A.r[p];
+      float zv;
+      if (jac) {
+        zv = rv / (L.diagA + A.tauc[p]);
+        A.z[p] = zv;
+      } else {
+        zv = A.z[p];
+      }
+      rz += (double)rv * (double)zv;
       rr += (double)rv * (double)rv;
     }
   }
   block_sum2(rz, rr, &A.part0[tile], &A.part1[tile]);
 }
 
-// 6. CG step: x += alpha p, r -= alpha q; partials of the new r.z and r.r
+// 6. CG step: x += alpha p, r -= alpha q
 __global__ __launch_bounds__(256) void k_cg_update(LikArgs A) {
   const int tile = blockIdx.x;
   const int4 td = A.tiles[tile];
   const LikInst L = A.inst[td.x];
   const InstState& st = A.st[L.inst];
-  double rz = 0.0, rr = 0.0;
-  if (!st.cg_done) {
-    const float alpha = (float)st.cg_alpha;
-    const TileXY t = lik_tile(td, L);
-    const int cols = t.c1 - t.c0;
-    const int n = cols * (t.r1 - t.r0);
-    for (int i = threadIdx.x; i < n; i += blockDim.x) {
-      const int r = t.r0 + i / cols, c = t.c0 + i % cols;
-      const long long p = L.off + (long long)r * L.pitch + c;
-      const float pv = A.p_out[p];
-      A.x[p] += alpha * pv;
-      const float rv = A.r[p] - alpha * A.q[p];
-      A.r[p] = rv;
-      rz += (double)rv * (double)rv / (double)(L.diagA + A.tauc[p]);
-      rr += (double)rv * (double)rv;
-    }
+  if (st.cg_done) return;
+  const float alpha = (float)st.cg_alpha;
+  const TileXY t = lik_tile(td, L);
+  const int cols = t.c1 - t.c0;
+  const int n = cols * (t.r1 - t.r0);
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    const int r = t.r0 + i / cols, c = t.c0 + i % cols;
+    const long long p = L.off + (long long)r * L.pitch + c;
+    A.x[p] += alpha * A.p_out[p];
+    A.r[p] -= alpha * A.q[p];
   }
-  block_sum2(rz, rr, &A.part0[tile], &A.part1[tile]);
 }
 
 // 7. site update q_{x,0} from E = x (Eq. (update_q0_x)), clamp, damping
@@ -439,6 +457,7 @@ static LikArgs make_args(LikCtx& lc) {
   A.b = lc.planes[LP_B];
   A.x = lc.planes[LP_X];
   A.r = lc.planes[LP_R];
+  A.z = lc.planes[LP_Z];
   A.p_in = lc.planes[lc.pcur ? LP_P1 : LP_P0];
   A.p_out = lc.planes[lc.pcur ? LP_P0 : LP_P1];
   A.q = lc.planes[LP_Q];
@@ -481,6 +500,7 @@ hipError_t lik_create(LikCtx& lc, const LikInstInfo* li, int n, char* ws, const 
     d.alpha = (float)I.damping;
     d.cg_tol2 = I.cg_tol * I.cg_tol;
     d.cg_max_iters = I.cg_max_iters;
+    d.precond = lik_uses_fft(I.op, I.H, I.W) ? PRECOND_CIRCULANT : PRECOND_JACOBI;
     lc.max_iters = std::max(lc.max_iters, I.cg_max_iters);
     const int li_idx = (int)lc.hinst.size();
     for (int yy = 0; yy < ty; ++yy)
@@ -536,6 +556,10 @@ hipError_t lik_create(LikCtx& lc, const LikInstInfo* li, int n, char* ws, const 
     lc.hinst.push_back(d);
     lc.inst_of.push_back(i);
   }
+  if ((int)taps.size() > L.ntaps || (int)tiles.size() != L.ntiles) {
+    err = "likelihood layout mismatch (taps or tiles)";
+    return hipErrorInvalidValue;
+  }
   hipError_t e = hipMemcpyAsync(lc.d_inst, lc.hinst.data(), sizeof(LikInst) * lc.hinst.size(),
                                 hipMemcpyHostToDevice, s);
   if (e == hipSuccess)
@@ -550,7 +574,7 @@ hipError_t lik_create(LikCtx& lc, const LikInstInfo* li, int n, char* ws, const 
   LikArgs A = make_args(lc);
   hipLaunchKernelGGL(k_spectrum_blur, dim3(lc.ntiles), dim3(256), 0, s, A);
   e = hipGetLastError();
-  if (e == hipSuccess) e = dft_setup(lc, li, n, s, err);
+  if (e == hipSuccess) e = dft_setup(lc, li, n, L.fft_bytes, s, err);
   if (e != hipSuccess && err.empty()) err = hipGetErrorString(e);
   lc.hst.resize(n);
   return e;
@@ -640,12 +664,16 @@ hipError_t lik_update(LikCtx& lc, float2* const S[5], hipStream_t s) {
   if ((e = fin(lc, FIN_SPEC, s)) != hipSuccess) return e;
   if ((e = launch_apply(lc, 0, s)) != hipSuccess) return e;
   hipLaunchKernelGGL(k_cg_init, g, b, 0, s, make_args(lc));
+  if ((e = fft_precondition(lc, s)) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_precond_dot, g, b, 0, s, make_args(lc));
   if ((e = fin(lc, FIN_INIT, s)) != hipSuccess) return e;
   const int poll = 4;
   for (int it = 0; it < lc.max_iters; ++it) {
     if ((e = launch_apply(lc, 1, s)) != hipSuccess) return e;   // p_out = z + beta p_in, q = A p_out
     if ((e = fin(lc, FIN_ALPHA, s)) != hipSuccess) return e;
     hipLaunchKernelGGL(k_cg_update, g, b, 0, s, make_args(lc));
+    if ((e = fft_precondition(lc, s)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_precond_dot, g, b, 0, s, make_args(lc));
     if ((e = fin(lc, FIN_BETA, s)) != hipSuccess) return e;
     lc.pcur ^= 1;
     if ((it + 1) % poll == 0) {
