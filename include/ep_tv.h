@@ -81,8 +81,15 @@ typedef struct {
   double damping;              /* in (0, 1]: weight of the new site value in the damped update */
   double cg_tol;               /* CG relative residual ||r||/||b|| for the likelihood site; 0 = 1e-8 */
   int32_t cg_max_iters;        /* CG iteration cap per likelihood-site update; 0 = 200 */
-  int32_t reserved;            /* must be 0 */
+  int32_t cg_precond;          /* EP_TV_PRECOND_*: CG preconditioner of the likelihood site */
 } ep_tv_problem;
+
+/* Preconditioner of the likelihood-site CG.  CIRCULANT is (H^T H / xi + d I)^{-1}
+ * with d the mean cavity precision, applied by FFT; it needs power-of-two sizes
+ * in [4, 4096] and one FFT pipeline per instance, so JACOBI (the inverse
+ * diagonal) suits batches of many small instances.  AUTO = CIRCULANT where the
+ * sizes allow, else JACOBI. */
+enum { EP_TV_PRECOND_AUTO = 0, EP_TV_PRECOND_JACOBI = 1, EP_TV_PRECOND_CIRCULANT = 2 };
 
 /* Per-instance statistics (host struct filled by ep_tv_solve / ep_tv_get_stats). */
 typedef struct {
@@ -210,6 +217,39 @@ typedef struct {
 
 int ep_tv_set_timing(ep_tv_ctx* ctx, int32_t enable);
 int ep_tv_get_timing(ep_tv_ctx* ctx, ep_tv_timing* out);
+
+/* Launch options of a context.
+ *  EP_TV_OPT_GRAPH (0/1, default 0): run sweeps by replaying captured HIP
+ *    graphs instead of launching kernel by kernel.  The sequences (likelihood
+ *    head + CG iterations, further CG iterations, site update + TV sweep +
+ *    finalisation; for identity operators, 8 whole sweeps) are captured on a
+ *    private stream at first use and replayed on the context's stream; the
+ *    results are identical to direct launches.  ep_tv_run / ep_tv_solve use it;
+ *    ep_tv_em_step and timing always launch directly.
+ *  EP_TV_OPT_TILE_ROWS (even, >= 2): rows per tile of the TV sweep (every
+ *    tile is 124 interior columns wide).  Smaller heights than the workspace was
+ *    sized for (the smaller of 8 and the initial height) return EP_TV_E_ARG.
+ * Both synchronise the stream. */
+enum { EP_TV_OPT_GRAPH = 1, EP_TV_OPT_TILE_ROWS = 2 };
+int ep_tv_set_option(ep_tv_ctx* ctx, int32_t option, int64_t value);
+int ep_tv_get_option(ep_tv_ctx* ctx, int32_t option, int64_t* value);
+
+/* Autotuner of the TV-sweep tile height: times the sweep kernel (repeats
+ * launches per candidate, HIP events, on the context's stream and current
+ * state, which it leaves unchanged) for tile heights 8, 16, 32, 64 and 128 rows
+ * (heights that give the same tiling as a smaller one are skipped), keeps the
+ * fastest for this context and records it for later contexts with the same set
+ * of image sizes in this process (ep_tv_workspace_bytes and ep_tv_create then
+ * start from it).  Needs an observation.  Synchronises.  out (host) may be NULL. */
+typedef struct {
+  int32_t tile_rows;           /* chosen height */
+  int32_t candidates;          /* entries used in rows / ms */
+  int32_t rows[8];
+  double ms[8];                /* mean sweep-kernel time per candidate */
+  double best_ms;              /* time of the chosen height */
+  double default_ms;           /* time of the height in use before tuning */
+} ep_tv_tune_result;
+int ep_tv_autotune(ep_tv_ctx* ctx, int32_t repeats, ep_tv_tune_result* out);
 
 /* Message for the last error on this context ("" if none).  Static to the ctx. */
 const char* ep_tv_last_error(const ep_tv_ctx* ctx);

@@ -25,6 +25,11 @@ OP_BLUR_PERIODIC = 1
 OP_DFT_MASK = 2
 BND_FREE = 0
 BND_PERIODIC = 1
+PRECOND_AUTO = 0
+PRECOND_JACOBI = 1
+PRECOND_CIRCULANT = 2
+OPT_GRAPH = 1
+OPT_TILE_ROWS = 2
 
 STATUS_NAMES = {0: "OK", 1: "W_NOT_CONVERGED", 2: "W_WARM_FALLBACK", -1: "E_ARG", -2: "E_OOM",
                 -3: "E_HIP", -4: "E_NONFINITE", -5: "E_STATE"}
@@ -38,7 +43,7 @@ class EpTvProblem(ctypes.Structure):
                 ("dft_mask", ctypes.POINTER(ctypes.c_uint8)),
                 ("noise_var", ctypes.c_double), ("lambda0", ctypes.c_double),
                 ("damping", ctypes.c_double), ("cg_tol", ctypes.c_double),
-                ("cg_max_iters", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("cg_max_iters", ctypes.c_int32), ("cg_precond", ctypes.c_int32)]
 
 
 class EpTvStats(ctypes.Structure):
@@ -55,6 +60,12 @@ class EpTvTiming(ctypes.Structure):
     _fields_ = [("sweep_ms", ctypes.c_double), ("sweep_launches", ctypes.c_int32),
                 ("lik_ms", ctypes.c_double), ("lik_updates", ctypes.c_int32),
                 ("apply_ms", ctypes.c_double), ("apply_launches", ctypes.c_int32)]
+
+
+class EpTvTuneResult(ctypes.Structure):
+    _fields_ = [("tile_rows", ctypes.c_int32), ("candidates", ctypes.c_int32),
+                ("rows", ctypes.c_int32 * 8), ("ms", ctypes.c_double * 8),
+                ("best_ms", ctypes.c_double), ("default_ms", ctypes.c_double)]
 
 
 _P = ctypes.c_void_p
@@ -81,6 +92,9 @@ SIGNATURES = {
     "ep_tv_tilted_moments": (ctypes.c_int, [ctypes.c_int32, _P, _P, ctypes.c_float, _P, _P, _P, _P]),
     "ep_tv_set_timing": (ctypes.c_int, [_P, ctypes.c_int32]),
     "ep_tv_get_timing": (ctypes.c_int, [_P, ctypes.POINTER(EpTvTiming)]),
+    "ep_tv_set_option": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int64]),
+    "ep_tv_get_option": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64)]),
+    "ep_tv_autotune": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.POINTER(EpTvTuneResult)]),
     "ep_tv_last_error": (ctypes.c_char_p, [_P]),
     "ep_tv_destroy": (None, [_P]),
 }

@@ -35,13 +35,15 @@ class ProblemSpec:
     mask: Optional[np.ndarray] = None
     cg_tol: float = 0.0          # 0 = library default
     cg_max_iters: int = 0        # 0 = library default
+    cg_precond: int = N.PRECOND_AUTO
 
 
 _OPS = {"identity": N.OP_IDENTITY, "blur": N.OP_BLUR_PERIODIC, "dft": N.OP_DFT_MASK}
 _BNDS = {"free": N.BND_FREE, "periodic": N.BND_PERIODIC}
 
 
-def spec_from_synthetic(p, lam0=None, damping=None, cg_tol=0.0, cg_max_iters=0) -> ProblemSpec:
+def spec_from_synthetic(p, lam0=None, damping=None, cg_tol=0.0, cg_max_iters=0,
+                        cg_precond=N.PRECOND_AUTO) -> ProblemSpec:
     """ProblemSpec of a synthetic.Problem (same fields, C enums)."""
     h, w = p.shape
     return ProblemSpec(h, w, _OPS[p.op], _BNDS[p.boundary], float(p.xi),
@@ -49,7 +51,7 @@ def spec_from_synthetic(p, lam0=None, damping=None, cg_tol=0.0, cg_max_iters=0) 
                        float(p.damping if damping is None else damping),
                        taps=None if p.taps is None else np.asarray(p.taps, np.float32),
                        mask=None if p.mask is None else np.asarray(p.mask, np.uint8),
-                       cg_tol=cg_tol, cg_max_iters=cg_max_iters)
+                       cg_tol=cg_tol, cg_max_iters=cg_max_iters, cg_precond=cg_precond)
 
 
 def _problems(specs: Sequence[ProblemSpec]):
@@ -59,7 +61,7 @@ def _problems(specs: Sequence[ProblemSpec]):
         a = arr[i]
         a.height, a.width, a.op, a.boundary = s.height, s.width, s.op, s.boundary
         a.noise_var, a.lambda0, a.damping = s.noise_var, s.lambda0, s.damping
-        a.cg_tol, a.cg_max_iters, a.reserved = s.cg_tol, s.cg_max_iters, 0
+        a.cg_tol, a.cg_max_iters, a.cg_precond = s.cg_tol, s.cg_max_iters, s.cg_precond
         if s.taps is not None:
             t = np.ascontiguousarray(s.taps, dtype=np.float32)
             keep.append(t)
@@ -200,6 +202,20 @@ class Context:
         return {"sweep_ms": t.sweep_ms, "sweep_launches": t.sweep_launches, "lik_ms": t.lik_ms,
                 "lik_updates": t.lik_updates, "apply_ms": t.apply_ms,
                 "apply_launches": t.apply_launches}
+
+    def ep_tv_set_option(self, option: int, value: int):
+        return self._check(N.lib().ep_tv_set_option(self.handle, int(option), int(value)), "set_option")
+
+    def ep_tv_get_option(self, option: int) -> int:
+        v = ctypes.c_int64(0)
+        self._check(N.lib().ep_tv_get_option(self.handle, int(option), ctypes.byref(v)), "get_option")
+        return int(v.value)
+
+    def ep_tv_autotune(self, repeats: int = 5):
+        r = N.EpTvTuneResult()
+        self._check(N.lib().ep_tv_autotune(self.handle, int(repeats), ctypes.byref(r)), "autotune")
+        return {"tile_rows": r.tile_rows, "best_ms": r.best_ms, "default_ms": r.default_ms,
+                "candidates": {int(r.rows[i]): float(r.ms[i]) for i in range(r.candidates)}}
 
     @staticmethod
     def _stats_dict(s):

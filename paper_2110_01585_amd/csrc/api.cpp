@@ -10,6 +10,9 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <functional>
+#include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -35,22 +38,61 @@ struct InstHost {
 
 struct Layout {
   long long plane = 0;       // elements per plane (all instances)
-  int ntiles = 0;
+  int ntiles = 0;            // tiles at the initial tile height
+  int tile_cap = 0;          // tiles at the smallest tile height (sizes the tile arrays)
   size_t S0 = 0, SB[2][4]{}, ypix = 0, inst = 0, st = 0, tiles = 0;
   size_t part_e = 0, part_m = 0, part_v = 0, part_c = 0, part_f = 0, tab0 = 0, tab1 = 0;
   LikLayout lik;
   size_t total = 0;
 };
 
-int pick_chunk_rows(int H, int W) {
+// Tile heights (rows per sweep tile) the autotuner tries; all even, since the
+// sweep marches row pairs.
+constexpr int kTuneRows[] = {8, 16, 32, 64, 128};
+constexpr int kNumTuneRows = 5;
+constexpr int kMinChunkRows = 8;
+
+int env_chunk_rows() {
   if (const char* e = std::getenv("EPTV_CHUNK_ROWS")) {
     int v = std::atoi(e);
-    if (v >= 2 && v % 2 == 0) return v;
+    if (v >= 2 && v <= 4096 && v % 2 == 0) return v;
   }
-  const long long strips = (W + kStripInt - 1) / kStripInt;
+  return 0;
+}
+
+// Default tile height for a batch: the tallest of 32/16/8 rows that still gives
+// >= 8192 tiles (32 waves per CU) over the whole batch.
+int default_chunk_rows(const std::vector<ep_tv_problem>& ps) {
+  if (int v = env_chunk_rows()) return v;
   int ch = 32;
-  while (ch > 8 && strips * ((H + ch - 1) / ch) < 8192) ch /= 2;
+  while (ch > kMinChunkRows) {
+    long long tiles = 0;
+    for (const auto& p : ps)
+      tiles += (long long)((p.width + kStripInt - 1) / kStripInt) * ((p.height + ch - 1) / ch);
+    if (tiles >= 8192) break;
+    ch /= 2;
+  }
   return ch;
+}
+
+int count_tiles(const std::vector<InstHost>& ih, int rows) {
+  long long t = 0;
+  for (const auto& h : ih)
+    t += (long long)((h.p.width + kStripInt - 1) / kStripInt) * ((h.p.height + rows - 1) / rows);
+  return (int)std::min<long long>(t, 1LL << 30);
+}
+
+// Assign tile ranges for tile height `rows` (same height for every instance).
+void assign_tiles(std::vector<InstHost>& ih, int rows) {
+  int tiles = 0;
+  for (auto& h : ih) {
+    h.chunk_rows = rows;
+    h.strips = (h.p.width + kStripInt - 1) / kStripInt;
+    h.chunks = (h.p.height + rows - 1) / rows;
+    h.tile0 = tiles;
+    h.ntiles = h.strips * h.chunks;
+    tiles += h.ntiles;
+  }
 }
 
 const char* validate(const ep_tv_problem& p) {
@@ -65,7 +107,11 @@ const char* validate(const ep_tv_problem& p) {
   if (!(p.damping > 0.0 && p.damping <= 1.0)) return "damping must be in (0, 1]";
   if (!(p.cg_tol >= 0.0 && p.cg_tol < 1.0)) return "cg_tol must be in [0, 1)";
   if (p.cg_max_iters < 0 || p.cg_max_iters > 100000) return "cg_max_iters must be in [0, 100000]";
-  if (p.reserved != 0) return "reserved field must be 0";
+  if (p.cg_precond < EP_TV_PRECOND_AUTO || p.cg_precond > EP_TV_PRECOND_CIRCULANT)
+    return "cg_precond must be one of EP_TV_PRECOND_*";
+  if (p.cg_precond == EP_TV_PRECOND_CIRCULANT && p.op != EP_TV_OP_IDENTITY &&
+      !(fft_size_ok(p.height) && fft_size_ok(p.width)))
+    return "the circulant preconditioner needs power-of-two sizes in [4, 4096]";
   if (p.op == EP_TV_OP_BLUR_PERIODIC) {
     if (!p.blur_taps) return "blur operator needs blur_taps";
     if (p.blur_h < 1 || p.blur_w < 1 || p.blur_h % 2 == 0 || p.blur_w % 2 == 0 ||
@@ -81,24 +127,20 @@ const char* validate(const ep_tv_problem& p) {
   return nullptr;
 }
 
-void make_layout(std::vector<InstHost>& ih, Layout& L) {
+void make_layout(std::vector<InstHost>& ih, int rows, Layout& L) {
   long long off = 0;
-  int tiles = 0;
   for (auto& h : ih) {
     const int H = h.p.height, W = h.p.width;
     h.pitch = (int)align_up((size_t)W + 1, 64);   // +1: a lane's pixel pair never leaves the row
     h.off = off;
     off += (long long)h.pitch * H;
     off = (long long)align_up((size_t)off, 64);
-    h.chunk_rows = pick_chunk_rows(H, W);
-    h.strips = (W + kStripInt - 1) / kStripInt;
-    h.chunks = (H + h.chunk_rows - 1) / h.chunk_rows;
-    h.tile0 = tiles;
-    h.ntiles = h.strips * h.chunks;
-    tiles += h.ntiles;
   }
+  assign_tiles(ih, rows);
   L.plane = std::max<long long>(off, 64);
-  L.ntiles = tiles;
+  L.ntiles = count_tiles(ih, rows);
+  L.tile_cap = std::max(L.ntiles, count_tiles(ih, std::min(rows, kMinChunkRows)));
+  const int tiles = L.tile_cap;
   const int n = (int)ih.size();
   size_t cur = 0;
   auto take = [&](size_t bytes) {
@@ -127,6 +169,7 @@ void make_layout(std::vector<InstHost>& ih, Layout& L) {
     li[i].W = ih[i].p.width;
     li[i].th = ih[i].p.op == EP_TV_OP_BLUR_PERIODIC ? ih[i].p.blur_h : 0;
     li[i].tw = ih[i].p.op == EP_TV_OP_BLUR_PERIODIC ? ih[i].p.blur_w : 0;
+    li[i].precond_req = ih[i].p.cg_precond;
   }
   lik_layout(li.data(), n, L.plane, take, L.lik);
   L.total = cur;
@@ -134,10 +177,33 @@ void make_layout(std::vector<InstHost>& ih, Layout& L) {
 
 }  // namespace
 
+// Captured launch sequences (hipGraph) of one sweep, replayed on the caller's
+// stream.  The TV-site buffers alternate between sweeps, so the pieces that
+// read or write them exist once per buffer parity.
+struct Graphs {
+  bool valid = false;
+  int em = -1;
+  bool delta = false;
+  double tol = 0.0;
+  hipGraphExec_t head[2]{};    // likelihood head + kCgPoll CG iterations
+  hipGraphExec_t cg = nullptr; // kCgPoll CG iterations
+  hipGraphExec_t tail[2]{};    // likelihood site + TV sweep + finalize (one sweep)
+  hipGraphExec_t multi[2]{};   // kGraphSweeps whole sweeps (identity operators only)
+};
+
+constexpr int kGraphSweeps = 8;   // even: a multi-sweep graph ends on the parity it starts on
+
 struct ep_tv_ctx {
   int n = 0;
+  std::vector<InstDev> idev_host;
+  std::vector<int4> tiles_host;
   std::vector<InstHost> ih;
   Layout L;
+  int ntiles = 0;            // current sweep tile count
+  int chunk_rows = 0;        // current sweep tile height
+  bool use_graph = false;
+  Graphs g;
+  hipStream_t cap = nullptr; // private stream used only to capture graphs
   hipStream_t stream = nullptr;
   char* ws = nullptr;
   float2* S0 = nullptr;
@@ -207,6 +273,78 @@ static int hip_check(ep_tv_ctx* c, hipError_t e, const char* what) {
     if (_rc != EP_TV_OK) return _rc;                 \
   } while (0)
 
+// ---- tile-height choice shared by every context with the same instance sizes
+// (filled by ep_tv_autotune, read by ep_tv_workspace_bytes / ep_tv_create)
+static std::mutex g_tune_mu;
+static std::map<std::string, int> g_tune_rows;
+
+static std::string shape_key(const ep_tv_problem* p, int n) {
+  std::vector<std::pair<int, int>> v(n);
+  for (int i = 0; i < n; ++i) v[i] = {p[i].height, p[i].width};
+  std::sort(v.begin(), v.end());
+  std::string k;
+  for (auto& hw : v) k += std::to_string(hw.first) + "x" + std::to_string(hw.second) + ";";
+  return k;
+}
+
+static int initial_rows(const ep_tv_problem* p, int n) {
+  if (int v = env_chunk_rows()) return v;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune_rows.find(shape_key(p, n));
+    if (it != g_tune_rows.end()) return it->second;
+  }
+  return default_chunk_rows(std::vector<ep_tv_problem>(p, p + n));
+}
+
+// Per-instance device descriptors and the sweep tile list for the current
+// tile height.  Asynchronous uploads from host vectors that live in the ctx.
+static int upload_tiles(ep_tv_ctx* c) {
+  const int n = c->n;
+  c->idev_host.assign(n, InstDev{});
+  c->tiles_host.clear();
+  for (int i = 0; i < n; ++i) {
+    const InstHost& h = c->ih[i];
+    InstDev& d = c->idev_host[i];
+    std::memset(&d, 0, sizeof(d));
+    d.H = h.p.height; d.W = h.p.width; d.pitch = h.pitch; d.bnd = h.p.boundary;
+    d.off = h.off; d.op = h.p.op; d.strips = h.strips; d.chunks = h.chunks; d.tile0 = h.tile0;
+    d.ntiles = h.ntiles; d.chunk_rows = h.chunk_rows; d.npix = h.p.height * h.p.width;
+    d.xi = (float)h.p.noise_var; d.inv_xi = (float)(1.0 / h.p.noise_var);
+    d.alpha = (float)h.p.damping;
+    for (int st = 0; st < h.strips; ++st)
+      for (int ch = 0; ch < h.chunks; ++ch) c->tiles_host.push_back(make_int4(i, st, ch, 0));
+  }
+  if ((int)c->tiles_host.size() > c->L.tile_cap)
+    return fail(c, EP_TV_E_ARG, "tile count exceeds the workspace's tile capacity");
+  c->ntiles = (int)c->tiles_host.size();
+  c->sa.ntiles = c->ntiles;
+  HIPCHK(c, hipMemcpyAsync(c->d_inst, c->idev_host.data(), sizeof(InstDev) * n,
+                           hipMemcpyHostToDevice, c->stream));
+  if (!c->tiles_host.empty())
+    HIPCHK(c, hipMemcpyAsync(c->d_tiles, c->tiles_host.data(), sizeof(int4) * c->tiles_host.size(),
+                             hipMemcpyHostToDevice, c->stream));
+  return EP_TV_OK;
+}
+
+static void drop_graphs(ep_tv_ctx* c) {
+  Graphs& g = c->g;
+  hipGraphExec_t* all[] = {&g.head[0], &g.head[1], &g.cg, &g.tail[0], &g.tail[1], &g.multi[0], &g.multi[1]};
+  for (hipGraphExec_t* e : all)
+    if (*e) {
+      (void)hipGraphExecDestroy(*e);
+      *e = nullptr;
+    }
+  g.valid = false;
+}
+
+static int set_rows(ep_tv_ctx* c, int rows) {
+  assign_tiles(c->ih, rows);
+  c->chunk_rows = rows;
+  drop_graphs(c);
+  return upload_tiles(c);
+}
+
 extern "C" {
 
 const char* ep_tv_version(void) { return "eptv-gfx950 0.1"; }
@@ -219,7 +357,7 @@ int ep_tv_workspace_bytes(const ep_tv_problem* p, int32_t n, size_t* bytes) {
     ih[i].p = p[i];
   }
   Layout L;
-  make_layout(ih, L);
+  make_layout(ih, initial_rows(p, n), L);
   *bytes = L.total;
   return EP_TV_OK;
 }
@@ -250,7 +388,8 @@ int ep_tv_create(const ep_tv_problem* p, int32_t n, void* d_ws, size_t ws_bytes,
     }
     if (p[i].op != EP_TV_OP_IDENTITY) c->any_lik = true;
   }
-  make_layout(c->ih, c->L);
+  make_layout(c->ih, initial_rows(p, n), c->L);
+  c->chunk_rows = c->ih[0].chunk_rows;
   if (ws_bytes < c->L.total) {
     delete c;
     return EP_TV_E_OOM;
@@ -271,34 +410,12 @@ int ep_tv_create(const ep_tv_problem* p, int32_t n, void* d_ws, size_t ws_bytes,
   a.inst = c->d_inst;
   a.st = c->d_st;
   a.tiles = c->d_tiles;
-  a.ntiles = c->L.ntiles;
   a.part_eabs = reinterpret_cast<double*>(c->ws + c->L.part_e);
   a.part_dmu = reinterpret_cast<float*>(c->ws + c->L.part_m);
   a.part_dv = reinterpret_cast<float*>(c->ws + c->L.part_v);
   a.part_clamp = reinterpret_cast<unsigned*>(c->ws + c->L.part_c);
   a.part_flags = reinterpret_cast<unsigned*>(c->ws + c->L.part_f);
-
-
-  std::vector<InstDev> idev(n);
-  std::vector<int4> tiles;
-  tiles.reserve(c->L.ntiles);
-  for (int i = 0; i < n; ++i) {
-    const InstHost& h = c->ih[i];
-    InstDev& d = idev[i];
-    std::memset(&d, 0, sizeof(d));
-    d.H = h.p.height; d.W = h.p.width; d.pitch = h.pitch; d.bnd = h.p.boundary;
-    d.off = h.off; d.op = h.p.op; d.strips = h.strips; d.chunks = h.chunks; d.tile0 = h.tile0;
-    d.ntiles = h.ntiles; d.chunk_rows = h.chunk_rows; d.npix = h.p.height * h.p.width;
-    d.xi = (float)h.p.noise_var; d.inv_xi = (float)(1.0 / h.p.noise_var);
-    d.alpha = (float)h.p.damping;
-    for (int s = 0; s < h.strips; ++s)
-      for (int ch = 0; ch < h.chunks; ++ch) tiles.push_back(make_int4(i, s, ch, 0));
-  }
-  int rc = hip_check(c, hipMemcpyAsync(c->d_inst, idev.data(), sizeof(InstDev) * n,
-                                       hipMemcpyHostToDevice, c->stream), "copy instances");
-  if (rc == EP_TV_OK && !tiles.empty())
-    rc = hip_check(c, hipMemcpyAsync(c->d_tiles, tiles.data(), sizeof(int4) * tiles.size(),
-                                     hipMemcpyHostToDevice, c->stream), "copy tiles");
+  int rc = upload_tiles(c);
   if (rc == EP_TV_OK) {
     std::vector<LikInstInfo> li(n);
     for (int i = 0; i < n; ++i) {
@@ -311,6 +428,7 @@ int ep_tv_create(const ep_tv_problem* p, int32_t n, void* d_ws, size_t ws_bytes,
       li[i].damping = c->ih[i].p.damping;
       li[i].cg_tol = c->ih[i].p.cg_tol > 0.0 ? c->ih[i].p.cg_tol : kCgTol;
       li[i].cg_max_iters = c->ih[i].p.cg_max_iters > 0 ? c->ih[i].p.cg_max_iters : kCgMaxIters;
+      li[i].precond_req = c->ih[i].p.cg_precond;
       li[i].taps = c->ih[i].taps.empty() ? nullptr : c->ih[i].taps.data();
       li[i].th = c->ih[i].p.blur_h;
       li[i].tw = c->ih[i].p.blur_w;
@@ -320,7 +438,7 @@ int ep_tv_create(const ep_tv_problem* p, int32_t n, void* d_ws, size_t ws_bytes,
     }
     std::string e;
     if (lik_create(c->lik, li.data(), n, c->ws, c->L.lik, c->L.plane, c->d_inst, c->d_st,
-                   c->d_tiles, c->L.ntiles, c->ypix, c->stream, e) != hipSuccess)
+                   c->d_tiles, c->ntiles, c->ypix, c->stream, e) != hipSuccess)
       rc = fail(c, EP_TV_E_HIP, "likelihood-site setup: " + e);
   }
   if (rc == EP_TV_OK) rc = hip_check(c, hipStreamSynchronize(c->stream), "create sync");
@@ -352,7 +470,7 @@ int ep_tv_init_cold(ep_tv_ctx* c) {
   if (rc) return rc;
   HIPCHK(c, launch_yrange(c->ypix, c->d_inst, c->d_st, c->n, c->stream));
   c->cur = 0;
-  HIPCHK(c, launch_init_cold(cur_sites(c).S, c->ypix, c->d_inst, c->d_st, c->d_tiles, c->L.ntiles,
+  HIPCHK(c, launch_init_cold(cur_sites(c).S, c->ypix, c->d_inst, c->d_st, c->d_tiles, c->ntiles,
                              c->stream));
   HIPCHK(c, lik_reset(c->lik, c->stream));
   return EP_TV_OK;
@@ -371,6 +489,26 @@ int ep_tv_set_observation(ep_tv_ctx* c, const float* const* d_y) {
   HIPCHK(c, lik_set_observation(c->lik, d_y, c->stream));
   c->has_obs = true;
   return ep_tv_init_cold(c);
+}
+
+static CurSites sites_at(const ep_tv_ctx* c, int par) {
+  CurSites r;
+  r.S[0] = c->S0;
+  for (int k = 0; k < 4; ++k) r.S[k + 1] = c->SB[par][k];
+  return r;
+}
+
+// TV sweep reading the sites of buffer `par`, writing buffer par ^ 1, then the
+// per-instance finalisation (EM, convergence).
+static int enqueue_tv(ep_tv_ctx* c, int par, int em, bool delta, double tol, hipStream_t s) {
+  SweepArgs a = c->sa;
+  float2* const* in = c->SB[par];
+  float2* const* out = c->SB[par ^ 1];
+  a.I1 = in[0]; a.I2 = in[1]; a.I3 = in[2]; a.I4 = in[3];
+  a.O1 = out[0]; a.O2 = out[1]; a.O3 = out[2]; a.O4 = out[3];
+  HIPCHK(c, launch_tv_sweep(a, delta, s));
+  HIPCHK(c, launch_finalize(c->d_inst, c->d_st, c->n, a, em, tol, s));
+  return EP_TV_OK;
 }
 
 static int one_sweep(ep_tv_ctx* c, int em, bool delta, double tol) {
@@ -400,14 +538,115 @@ static int one_sweep(ep_tv_ctx* c, int em, bool delta, double tol) {
   return EP_TV_OK;
 }
 
-int ep_tv_run(ep_tv_ctx* c, int32_t n_sweeps, int32_t em) {
-  if (!c || n_sweeps < 0) return EP_TV_E_ARG;
-  if (!c->has_obs) return fail(c, EP_TV_E_STATE, "no observation set");
-  for (int t = 0; t < n_sweeps; ++t) {
-    int rc = one_sweep(c, em ? 1 : 0, false, 0.0);
+// ---- graph capture: the sequences are recorded on a private stream (nothing
+// runs while capturing) and replayed on the caller's stream.
+static int capture(ep_tv_ctx* c, hipGraphExec_t* out, const std::function<int(hipStream_t)>& body) {
+  if (!c->cap) HIPCHK(c, hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking));
+  HIPCHK(c, hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal));
+  const bool lt = c->lik.timing;
+  c->lik.timing = false;
+  int rc = body(c->cap);
+  c->lik.timing = lt;
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamEndCapture(c->cap, &g);
+  if (rc == EP_TV_OK) rc = hip_check(c, e, "hipStreamEndCapture");
+  if (rc == EP_TV_OK) rc = hip_check(c, hipGraphInstantiate(out, g, nullptr, nullptr, 0),
+                                     "hipGraphInstantiate");
+  if (g) (void)hipGraphDestroy(g);
+  return rc;
+}
+
+static int build_graphs(ep_tv_ctx* c, int em, bool delta, double tol) {
+  Graphs& g = c->g;
+  if (g.valid && g.em == em && g.delta == delta && g.tol == tol) return EP_TV_OK;
+  drop_graphs(c);
+  int rc = EP_TV_OK;
+  for (int par = 0; par < 2 && rc == EP_TV_OK; ++par) {
+    if (c->any_lik) {
+      rc = capture(c, &g.head[par], [&](hipStream_t s) -> int {
+        HIPCHK(c, lik_head(c->lik, sites_at(c, par).S, s));
+        HIPCHK(c, lik_iterations(c->lik, kCgPoll, s));
+        return EP_TV_OK;
+      });
+      if (rc == EP_TV_OK)
+        rc = capture(c, &g.tail[par], [&](hipStream_t s) -> int {
+          HIPCHK(c, lik_tail(c->lik, c->S0, s));
+          return enqueue_tv(c, par, em, delta, tol, s);
+        });
+    } else {
+      rc = capture(c, &g.tail[par], [&](hipStream_t s) -> int { return enqueue_tv(c, par, em, delta, tol, s); });
+      if (rc == EP_TV_OK)
+        rc = capture(c, &g.multi[par], [&](hipStream_t s) -> int {
+          for (int t = 0; t < kGraphSweeps; ++t) {
+            int r = enqueue_tv(c, par ^ (t & 1), em, delta, tol, s);
+            if (r) return r;
+          }
+          return EP_TV_OK;
+        });
+    }
+  }
+  if (rc == EP_TV_OK && c->any_lik)
+    rc = capture(c, &g.cg, [&](hipStream_t s) -> int {
+      HIPCHK(c, lik_iterations(c->lik, kCgPoll, s));
+      return EP_TV_OK;
+    });
+  if (rc != EP_TV_OK) {
+    drop_graphs(c);
+    return rc;
+  }
+  g.valid = true;
+  g.em = em;
+  g.delta = delta;
+  g.tol = tol;
+  return EP_TV_OK;
+}
+
+// One sweep from the graphs: the CG runs kCgPoll iterations per replay until
+// every instance's solve has converged (checked on the host between replays).
+static int graph_sweep(ep_tv_ctx* c) {
+  Graphs& g = c->g;
+  if (c->any_lik) {
+    HIPCHK(c, hipGraphLaunch(g.head[c->cur], c->stream));
+    int iters = kCgPoll;
+    bool done = false;
+    HIPCHK(c, lik_poll(c->lik, c->stream, done));
+    while (!done && iters < c->lik.max_iters) {
+      HIPCHK(c, hipGraphLaunch(g.cg, c->stream));
+      iters += kCgPoll;
+      HIPCHK(c, lik_poll(c->lik, c->stream, done));
+    }
+  }
+  HIPCHK(c, hipGraphLaunch(g.tail[c->cur], c->stream));
+  c->cur ^= 1;
+  return EP_TV_OK;
+}
+
+// Run n sweeps with the given finalisation settings (direct launches or graphs).
+static int advance(ep_tv_ctx* c, int n, int em, bool delta, double tol) {
+  if (!c->use_graph) {
+    for (int t = 0; t < n; ++t) {
+      int rc = one_sweep(c, em, delta, tol);
+      if (rc) return rc;
+    }
+    return EP_TV_OK;
+  }
+  int rc = build_graphs(c, em, delta, tol);
+  if (rc) return rc;
+  int t = 0;
+  if (!c->any_lik)
+    for (; t + kGraphSweeps <= n; t += kGraphSweeps)
+      HIPCHK(c, hipGraphLaunch(c->g.multi[c->cur], c->stream));
+  for (; t < n; ++t) {
+    rc = graph_sweep(c);
     if (rc) return rc;
   }
   return EP_TV_OK;
+}
+
+int ep_tv_run(ep_tv_ctx* c, int32_t n_sweeps, int32_t em) {
+  if (!c || n_sweeps < 0) return EP_TV_E_ARG;
+  if (!c->has_obs) return fail(c, EP_TV_E_STATE, "no observation set");
+  return advance(c, n_sweeps, em ? 1 : 0, false, 0.0);
 }
 
 static int pull_states(ep_tv_ctx* c) {
@@ -451,7 +690,7 @@ int ep_tv_marginals(ep_tv_ctx* c, float* const* d_mean, float* const* d_var) {
     int rc = set_tab(c, d_var, c->d_tab1, c->tab_host1);
     if (rc) return rc;
   }
-  HIPCHK(c, launch_marginals(cur_sites(c).S, c->d_inst, c->d_tiles, c->L.ntiles, d_mean ? c->d_tab0 : nullptr,
+  HIPCHK(c, launch_marginals(cur_sites(c).S, c->d_inst, c->d_tiles, c->ntiles, d_mean ? c->d_tab0 : nullptr,
                              d_var ? c->d_tab1 : nullptr, c->stream));
   return EP_TV_OK;
 }
@@ -484,12 +723,12 @@ int ep_tv_solve(ep_tv_ctx* c, int32_t max_sweeps, double tol, int32_t em, float*
   if (!c->has_obs) return fail(c, EP_TV_E_STATE, "no observation set");
   const auto t0 = std::chrono::steady_clock::now();
   const bool use_tol = tol > 0.0;
-  const int check_every = 8;
+  const int check_every = kGraphSweeps;
   int rc = EP_TV_OK;
-  for (int t = 0; t < max_sweeps; ++t) {
-    rc = one_sweep(c, em ? 1 : 0, true, use_tol ? tol : 0.0);
+  for (int t = 0; t < max_sweeps; t += check_every) {
+    rc = advance(c, std::min(check_every, max_sweeps - t), em ? 1 : 0, true, use_tol ? tol : 0.0);
     if (rc) return rc;
-    if (use_tol && ((t + 1) % check_every == 0)) {
+    if (use_tol) {
       rc = pull_states(c);
       if (rc) return rc;
       bool any = false;
@@ -518,7 +757,7 @@ int ep_tv_get_sites(ep_tv_ctx* c, float* const* d_out) {
   if (!c || !d_out) return EP_TV_E_ARG;
   int rc = set_tab(c, d_out, c->d_tab0, c->tab_host0);
   if (rc) return rc;
-  HIPCHK(c, launch_sites_io(cur_sites(c).S, c->d_inst, c->d_tiles, c->L.ntiles, c->d_tab0, 1,
+  HIPCHK(c, launch_sites_io(cur_sites(c).S, c->d_inst, c->d_tiles, c->ntiles, c->d_tab0, 1,
                             c->stream));
   return EP_TV_OK;
 }
@@ -545,7 +784,7 @@ int ep_tv_set_sites(ep_tv_ctx* c, const float* const* d_in, const double* lambda
                            hipMemcpyHostToDevice, c->stream));
   rc = set_tab(c, const_cast<float* const*>(d_in), c->d_tab0, c->tab_host0);
   if (rc) return rc;
-  HIPCHK(c, launch_sites_io(cur_sites(c).S, c->d_inst, c->d_tiles, c->L.ntiles, c->d_tab0, 0,
+  HIPCHK(c, launch_sites_io(cur_sites(c).S, c->d_inst, c->d_tiles, c->ntiles, c->d_tab0, 0,
                             c->stream));
   HIPCHK(c, lik_resume(c->lik, c->stream));
   return EP_TV_OK;
@@ -616,11 +855,112 @@ int ep_tv_get_timing(ep_tv_ctx* c, ep_tv_timing* out) {
   return EP_TV_OK;
 }
 
+int ep_tv_set_option(ep_tv_ctx* c, int32_t option, int64_t value) {
+  if (!c) return EP_TV_E_ARG;
+  switch (option) {
+    case EP_TV_OPT_GRAPH:
+      if (value != 0 && value != 1) return fail(c, EP_TV_E_ARG, "graph option must be 0 or 1");
+      HIPCHK(c, hipStreamSynchronize(c->stream));
+      c->use_graph = value != 0;
+      if (!c->use_graph) drop_graphs(c);
+      return EP_TV_OK;
+    case EP_TV_OPT_TILE_ROWS: {
+      if (value < 2 || value > 4096 || value % 2)
+        return fail(c, EP_TV_E_ARG, "tile rows must be even and in [2, 4096]");
+      std::vector<InstHost> probe = c->ih;
+      if (count_tiles(probe, (int)value) > c->L.tile_cap)
+        return fail(c, EP_TV_E_ARG, "tile rows below the workspace's tile capacity");
+      HIPCHK(c, hipStreamSynchronize(c->stream));
+      return set_rows(c, (int)value);
+    }
+    default:
+      return fail(c, EP_TV_E_ARG, "unknown option");
+  }
+}
+
+int ep_tv_get_option(ep_tv_ctx* c, int32_t option, int64_t* value) {
+  if (!c || !value) return EP_TV_E_ARG;
+  switch (option) {
+    case EP_TV_OPT_GRAPH: *value = c->use_graph ? 1 : 0; return EP_TV_OK;
+    case EP_TV_OPT_TILE_ROWS: *value = c->chunk_rows; return EP_TV_OK;
+    default: return fail(c, EP_TV_E_ARG, "unknown option");
+  }
+}
+
+int ep_tv_autotune(ep_tv_ctx* c, int32_t repeats, ep_tv_tune_result* out) {
+  if (!c || repeats < 1 || repeats > 1000) return EP_TV_E_ARG;
+  if (!c->has_obs) return fail(c, EP_TV_E_STATE, "no observation set");
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  ep_tv_tune_result r;
+  std::memset(&r, 0, sizeof(r));
+  const int rows0 = c->chunk_rows;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIPCHK(c, hipEventCreate(&e0));
+  int rc = hip_check(c, hipEventCreate(&e1), "hipEventCreate");
+  // the sweep kernel alone reads the current sites and writes the other buffer
+  // and the per-tile partials, so timing it leaves the EP state unchanged
+  SweepArgs a = c->sa;
+  float2* const* in = c->SB[c->cur];
+  float2* const* o = c->SB[c->cur ^ 1];
+  a.I1 = in[0]; a.I2 = in[1]; a.I3 = in[2]; a.I4 = in[3];
+  a.O1 = o[0]; a.O2 = o[1]; a.O3 = o[2]; a.O4 = o[3];
+  int last_tiles = -1;
+  double best = 1e300;
+  int best_rows = rows0;
+  for (int k = 0; k < kNumTuneRows && rc == EP_TV_OK; ++k) {
+    const int rows = kTuneRows[k];
+    const int nt = count_tiles(c->ih, rows);
+    if (nt > c->L.tile_cap || nt == last_tiles) continue;   // same tiling as a smaller height
+    last_tiles = nt;
+    rc = set_rows(c, rows);
+    if (rc) break;
+    a.ntiles = c->ntiles;
+    rc = hip_check(c, launch_tv_sweep(a, true, c->stream), "tune warm-up");
+    if (rc == EP_TV_OK) rc = hip_check(c, hipEventRecord(e0, c->stream), "hipEventRecord");
+    for (int t = 0; t < repeats && rc == EP_TV_OK; ++t)
+      rc = hip_check(c, launch_tv_sweep(a, true, c->stream), "tune launch");
+    if (rc == EP_TV_OK) rc = hip_check(c, hipEventRecord(e1, c->stream), "hipEventRecord");
+    if (rc == EP_TV_OK) rc = hip_check(c, hipEventSynchronize(e1), "hipEventSynchronize");
+    float ms = 0.f;
+    if (rc == EP_TV_OK) rc = hip_check(c, hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
+    if (rc != EP_TV_OK) break;
+    const double per = ms / repeats;
+    if (r.candidates < 8) {
+      r.rows[r.candidates] = rows;
+      r.ms[r.candidates] = per;
+      r.candidates += 1;
+    }
+    if (rows == rows0) r.default_ms = per;
+    if (per < best) {
+      best = per;
+      best_rows = rows;
+    }
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  int rc2 = set_rows(c, rc == EP_TV_OK ? best_rows : rows0);
+  if (rc != EP_TV_OK) return rc;
+  if (rc2 != EP_TV_OK) return rc2;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  r.tile_rows = best_rows;
+  r.best_ms = best;
+  {
+    std::vector<ep_tv_problem> ps(c->n);
+    for (int i = 0; i < c->n; ++i) ps[i] = c->ih[i].p;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune_rows[shape_key(ps.data(), c->n)] = best_rows;
+  }
+  if (out) *out = r;
+  return EP_TV_OK;
+}
+
 const char* ep_tv_last_error(const ep_tv_ctx* c) { return c ? c->err.c_str() : "null context"; }
 
 void ep_tv_destroy(ep_tv_ctx* c) {
   if (!c) return;
-  if (c->stream || true) (void)hipStreamSynchronize(c->stream);
+  (void)hipStreamSynchronize(c->stream);
+  drop_graphs(c);
+  if (c->cap) (void)hipStreamDestroy(c->cap);
   lik_destroy(c->lik);
   for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
   delete c;

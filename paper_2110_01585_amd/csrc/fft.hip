@@ -363,7 +363,7 @@ hipError_t dft_setup(LikCtx& lc, const LikInstInfo* li, int n, size_t fft_bytes,
   size_t used = 0;
   for (size_t k = 0; k < lc.hinst.size(); ++k) {
     const LikInst& L = lc.hinst[k];
-    if (!lik_uses_fft(L.op, L.H, L.W)) continue;
+    if (L.op != OP_DFT && L.precond != PRECOND_CIRCULANT) continue;
     const LikInstInfo& I = li[L.inst];
     DftPlan d;
     d.li = (int)k;

@@ -18,8 +18,12 @@ constexpr int kLikTH = 32;
 constexpr int kMaxRadius = kMaxTaps - 1;   // radius of the combined H^T H kernel
 constexpr int kCgMaxIters = 200;
 constexpr double kCgTol = 1e-8;            // relative residual ||r|| / ||b||
+constexpr int kCgPoll = 4;                 // CG iterations between convergence checks (even)
 
 inline bool fft_size_ok(int n) { return n >= 4 && n <= 4096 && (n & (n - 1)) == 0; }
+
+// Preconditioner request per instance (the ABI's EP_TV_PRECOND_* values).
+enum { PRECOND_REQ_AUTO = 0, PRECOND_REQ_JACOBI = 1, PRECOND_REQ_CIRCULANT = 2 };
 
 struct LikInstInfo {
   int op = 0, H = 0, W = 0, pitch = 0;
@@ -27,6 +31,7 @@ struct LikInstInfo {
   double xi = 1.0, damping = 1.0;
   double cg_tol = kCgTol;
   int cg_max_iters = kCgMaxIters;
+  int precond_req = PRECOND_REQ_AUTO;
   const float* taps = nullptr;
   int th = 0, tw = 0;
   const uint8_t* mask = nullptr;
@@ -53,9 +58,16 @@ enum {
 
 enum { PRECOND_JACOBI = 0, PRECOND_CIRCULANT = 1 };
 
-// The circulant preconditioner (and the masked-DFT operator) need FFT sizes.
-inline bool lik_uses_fft(int op, int H, int W) {
-  return op == OP_DFT || (fft_size_ok(H) && fft_size_ok(W));
+// The circulant preconditioner needs power-of-two FFT sizes; AUTO takes it
+// whenever the sizes allow.
+inline int lik_precond(int op, int H, int W, int req) {
+  if (req == PRECOND_REQ_JACOBI) return PRECOND_JACOBI;
+  return (fft_size_ok(H) && fft_size_ok(W)) ? PRECOND_CIRCULANT : PRECOND_JACOBI;
+}
+
+// FFT plans: the masked-DFT operator, and the circulant preconditioner.
+inline bool lik_uses_fft(int op, int H, int W, int req) {
+  return op == OP_DFT || (op == OP_BLUR && lik_precond(op, H, W, req) == PRECOND_CIRCULANT);
 }
 
 struct LikLayout {
@@ -94,7 +106,7 @@ void lik_layout(const LikInstInfo* li, int n, long long plane, Take&& take, LikL
   // transposed spectrum and the mask (each rounded up to 256 bytes)
   L.fft_bytes = 0;
   for (int i = 0; i < n; ++i) {
-    if (li[i].op == OP_IDENTITY || !lik_uses_fft(li[i].op, li[i].H, li[i].W)) continue;
+    if (li[i].op == OP_IDENTITY || !lik_uses_fft(li[i].op, li[i].H, li[i].W, li[i].precond_req)) continue;
     const size_t N = (size_t)li[i].H * li[i].W;
     auto r256 = [](size_t b) { return (b + 255) / 256 * 256; };
     L.fft_bytes += 2 * r256(N * 8) + r256((size_t)li[i].W * 8) + r256((size_t)li[i].H * 8) +
@@ -150,6 +162,14 @@ hipError_t lik_set_observation(LikCtx& lc, const float* const* d_y, hipStream_t 
 hipError_t lik_reset(LikCtx& lc, hipStream_t s);
 hipError_t lik_resume(LikCtx& lc, hipStream_t s);
 hipError_t lik_update(LikCtx& lc, float2* const S[5], hipStream_t s);
+// The pieces of lik_update, for graph capture: head (cavity, rhs, spectral
+// precision, CG start), n CG iterations (no host synchronisation; converged
+// instances are skipped on the device), a host poll of the CG flags, and the
+// site update.  n must be even for a captured sequence to be replayable.
+hipError_t lik_head(LikCtx& lc, float2* const S[5], hipStream_t s);
+hipError_t lik_iterations(LikCtx& lc, int n, hipStream_t s);
+hipError_t lik_poll(LikCtx& lc, hipStream_t s, bool& all_done);
+hipError_t lik_tail(LikCtx& lc, float2* S0, hipStream_t s);
 void lik_destroy(LikCtx& lc);
 void lik_timing(LikCtx& lc, bool enable, bool clear);
 hipError_t lik_timing_read(LikCtx& lc, double& ms, int& launches);

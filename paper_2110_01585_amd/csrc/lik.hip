@@ -215,6 +215,7 @@ __global__ __launch_bounds__(256) void k_apply(LikArgs A) {
   const int4 td = A.tiles[tile];
   const LikInst L = A.inst[td.x];
   const InstState& st = A.st[L.inst];
+  if (L.op != OP_BLUR) return;   // masked-DFT tiles: q and partials come from the FFT path
   if (st.cg_done) {
     block_sum2(0.0, 0.0, &A.part0[tile], &A.part1[tile]);
     return;
@@ -500,7 +501,7 @@ hipError_t lik_create(LikCtx& lc, const LikInstInfo* li, int n, char* ws, const 
     d.alpha = (float)I.damping;
     d.cg_tol2 = I.cg_tol * I.cg_tol;
     d.cg_max_iters = I.cg_max_iters;
-    d.precond = lik_uses_fft(I.op, I.H, I.W) ? PRECOND_CIRCULANT : PRECOND_JACOBI;
+    d.precond = lik_precond(I.op, I.H, I.W, I.precond_req);
     lc.max_iters = std::max(lc.max_iters, I.cg_max_iters);
     const int li_idx = (int)lc.hinst.size();
     for (int yy = 0; yy < ty; ++yy)
@@ -654,9 +655,10 @@ static hipError_t fin(LikCtx& lc, int stage, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t lik_update(LikCtx& lc, float2* const S[5], hipStream_t s) {
+hipError_t lik_head(LikCtx& lc, float2* const S[5], hipStream_t s) {
   if (lc.nlik == 0) return hipSuccess;
   hipError_t e;
+  lc.pcur = 0;   // the first iteration sets p = z whatever the p planes hold
   const dim3 g(lc.ntiles), b(256);
   hipLaunchKernelGGL(k_lik_prep, g, b, 0, s, make_args(lc), S[0], S[1], S[2], S[3], S[4]);
   if ((e = fin(lc, FIN_PREP, s)) != hipSuccess) return e;
@@ -666,9 +668,14 @@ hipError_t lik_update(LikCtx& lc, float2* const S[5], hipStream_t s) {
   hipLaunchKernelGGL(k_cg_init, g, b, 0, s, make_args(lc));
   if ((e = fft_precondition(lc, s)) != hipSuccess) return e;
   hipLaunchKernelGGL(k_precond_dot, g, b, 0, s, make_args(lc));
-  if ((e = fin(lc, FIN_INIT, s)) != hipSuccess) return e;
-  const int poll = 4;
-  for (int it = 0; it < lc.max_iters; ++it) {
+  return fin(lc, FIN_INIT, s);
+}
+
+hipError_t lik_iterations(LikCtx& lc, int n, hipStream_t s) {
+  if (lc.nlik == 0) return hipSuccess;
+  hipError_t e;
+  const dim3 g(lc.ntiles), b(256);
+  for (int it = 0; it < n; ++it) {
     if ((e = launch_apply(lc, 1, s)) != hipSuccess) return e;   // p_out = z + beta p_in, q = A p_out
     if ((e = fin(lc, FIN_ALPHA, s)) != hipSuccess) return e;
     hipLaunchKernelGGL(k_cg_update, g, b, 0, s, make_args(lc));
@@ -676,17 +683,38 @@ hipError_t lik_update(LikCtx& lc, float2* const S[5], hipStream_t s) {
     hipLaunchKernelGGL(k_precond_dot, g, b, 0, s, make_args(lc));
     if ((e = fin(lc, FIN_BETA, s)) != hipSuccess) return e;
     lc.pcur ^= 1;
-    if ((it + 1) % poll == 0) {
-      e = hipMemcpyAsync(lc.hst.data(), lc.d_st, sizeof(InstState) * lc.n_all, hipMemcpyDeviceToHost, s);
-      if (e == hipSuccess) e = hipStreamSynchronize(s);
-      if (e != hipSuccess) return e;
-      bool any = false;
-      for (int i : lc.inst_of) any = any || !lc.hst[i].cg_done;
-      if (!any) break;
-    }
   }
-  hipLaunchKernelGGL(k_lik_site, g, b, 0, s, make_args(lc), S[0]);
+  return hipSuccess;
+}
+
+hipError_t lik_poll(LikCtx& lc, hipStream_t s, bool& all_done) {
+  all_done = true;
+  if (lc.nlik == 0) return hipSuccess;
+  hipError_t e = hipMemcpyAsync(lc.hst.data(), lc.d_st, sizeof(InstState) * lc.n_all,
+                                hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return e;
+  for (int i : lc.inst_of) all_done = all_done && lc.hst[i].cg_done;
+  return hipSuccess;
+}
+
+hipError_t lik_tail(LikCtx& lc, float2* S0, hipStream_t s) {
+  if (lc.nlik == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_lik_site, dim3(lc.ntiles), dim3(256), 0, s, make_args(lc), S0);
   return hipGetLastError();
+}
+
+hipError_t lik_update(LikCtx& lc, float2* const S[5], hipStream_t s) {
+  if (lc.nlik == 0) return hipSuccess;
+  hipError_t e = lik_head(lc, S, s);
+  if (e != hipSuccess) return e;
+  for (int it = 0; it < lc.max_iters; it += kCgPoll) {
+    if ((e = lik_iterations(lc, kCgPoll, s)) != hipSuccess) return e;
+    bool done = false;
+    if ((e = lik_poll(lc, s, done)) != hipSuccess) return e;
+    if (done) break;
+  }
+  return lik_tail(lc, S[0], s);
 }
 
 void lik_destroy(LikCtx& lc) {

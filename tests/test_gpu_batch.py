@@ -1,0 +1,195 @@
+"""Batched solves on the GPU: many instances of uneven sizes and mixed operators
+in one context (one launch per step over the concatenated tile lists), the
+captured-graph launch mode, and the tile-height autotuner.  Parity is against
+the FP64 oracle, instance by instance; graph and direct launches, and different
+tile heights, must give bit-identical results where the arithmetic is the same."""
+import numpy as np
+import pytest
+
+import synthetic as syn
+from oracle import ep as oep
+from tests.gpu_util import MEAN_TOL, VAR_TOL, f32_problem, mean_err, observation_tensor, var_err
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_2110_01585_amd import Context, spec_from_synthetic  # noqa: E402
+from paper_2110_01585_amd import _native as N  # noqa: E402
+
+
+def _ctx(problems, graph=False, precond=N.PRECOND_AUTO, rows=None):
+    ctx = Context([spec_from_synthetic(p, cg_precond=precond) for p in problems])
+    if rows is not None:
+        ctx.ep_tv_set_option(N.OPT_TILE_ROWS, rows)
+    ctx.ep_tv_set_option(N.OPT_GRAPH, 1 if graph else 0)
+    ctx.ep_tv_set_observation([observation_tensor(p, torch) for p in problems])
+    return ctx
+
+
+def _out(ctx):
+    mus, vs = ctx.marginals()
+    st = ctx.ep_tv_get_stats()
+    torch.cuda.synchronize()
+    return [(m.cpu().numpy().astype(np.float64), v.cpu().numpy().astype(np.float64))
+            for m, v in zip(mus, vs)], st
+
+
+def _mixed(n_blur=2, n_dft=1, n_id=2, seed=0):
+    ps = []
+    for i in range(n_blur):
+        ps.append(syn.make_deconv(40 + 24 * i, 56 + 8 * i, 5, 0.02, 1.0 + 0.6 * i,
+                                  syn.rng_for(90 + seed, i), lam0=1.0, sweeps=20, em=True))
+    for i in range(n_dft):
+        ps.append(syn.make_cs(32 * (i + 1), 64, 6, 0.01, 0.3, syn.rng_for(91 + seed, i), sweeps=20,
+                              em=True))
+    for i in range(n_id):
+        ps.append(syn.make_denoise(37 + 30 * i, 91 - 20 * i, 5, 0.05, syn.rng_for(92 + seed, i),
+                                   mode="paint", lam0=1.0, sweeps=20, em=True))
+    return ps
+
+
+def test_graph_equals_direct_identity_batch():
+    ps = [syn.make_denoise(s, s + 7, 6, 0.1, syn.rng_for(93, s), mode="paint", lam0=1.0, sweeps=19,
+                           em=True) for s in (20, 64, 130)]
+    a = _ctx(ps, graph=False)
+    a.ep_tv_run(19, True)          # 2 graph replays of 8 sweeps + 3 single sweeps in graph mode
+    ra, sa = _out(a)
+    a.close()
+    b = _ctx(ps, graph=True)
+    b.ep_tv_run(19, True)
+    rb, sb = _out(b)
+    b.close()
+    for (ma, va), (mb, vb) in zip(ra, rb):
+        assert np.array_equal(ma, mb) and np.array_equal(va, vb)
+    assert [s["lambda"] for s in sa] == [s["lambda"] for s in sb]
+
+
+def test_graph_equals_direct_mixed_solve():
+    ps = _mixed()
+    res = []
+    for graph in (False, True):
+        c = _ctx(ps, graph=graph)
+        mus = [torch.empty(*p.shape, device="cuda") for p in ps]
+        vs = [torch.empty(*p.shape, device="cuda") for p in ps]
+        rc, st = c.ep_tv_solve(40, 1e-4, True, mus, vs)
+        torch.cuda.synchronize()
+        res.append(([m.cpu().numpy() for m in mus], [v.cpu().numpy() for v in vs], st))
+        c.close()
+    (ma, va, sa), (mb, vb, sb) = res
+    for i in range(len(ps)):
+        assert np.array_equal(ma[i], mb[i]) and np.array_equal(va[i], vb[i]), ps[i].name
+        assert sa[i]["sweeps"] == sb[i]["sweeps"] and sa[i]["cg_total"] == sb[i]["cg_total"]
+
+
+def test_mixed_operators_batch_vs_oracle():
+    """Blur, masked-DFT and identity instances in one context (each H^T H path
+    must leave the other instances' products alone)."""
+    ps = _mixed(seed=1)
+    c = _ctx(ps, graph=True)
+    c.ep_tv_run(20, True)
+    outs, st = _out(c)
+    c.close()
+    for p, (mu, v), s in zip(ps, outs, st):
+        mu_o, v_o, _, info = oep.solve(oep.problem_from_synthetic(f32_problem(p)), 20, True)
+        e_mu, e_v = mean_err(mu, mu_o), var_err(v, v_o)
+        print(f"{p.name} {p.shape}: mean {e_mu:.2e} var {e_v:.2e} lambda {s['lambda']:.6g} "
+              f"oracle {info['lam']:.6g}")
+        assert e_mu <= MEAN_TOL and e_v <= VAR_TOL, p.name
+        assert abs(s["lambda"] / info["lam"] - 1) <= 2e-4
+
+
+def test_batched_generator_reduced_vs_oracle():
+    """The batched workload's generator (uneven sizes, 50/50 denoise/deconv,
+    per-instance noise, blur width and EM) at sizes the oracle finishes fast,
+    graph mode, autotuned tiles, Jacobi CG."""
+    ps = syn.config3_instances(n_instances=10, max_sweeps=30, size_lo=16, size_hi=90)
+    c = _ctx(ps, graph=True, precond=N.PRECOND_JACOBI)
+    tune = c.ep_tv_autotune(3)
+    assert tune["tile_rows"] in tune["candidates"]
+    c.ep_tv_run(30, True)
+    outs, st = _out(c)
+    c.close()
+    for p, (mu, v), s in zip(ps, outs, st):
+        mu_o, v_o, _, info = oep.solve(oep.problem_from_synthetic(f32_problem(p)), 30, True)
+        e_mu, e_v = mean_err(mu, mu_o), var_err(v, v_o)
+        print(f"{p.name} {p.shape}: mean {e_mu:.2e} var {e_v:.2e}")
+        assert e_mu <= MEAN_TOL and e_v <= VAR_TOL, p.name
+        assert abs(s["lambda"] / info["lam"] - 1) <= 2e-4
+
+
+@pytest.mark.parametrize("rows", [8, 64])
+def test_tile_height_does_not_change_results(rows):
+    """Fixed lambda: every pixel's update is the same arithmetic whatever the
+    tiling, so results are bit-identical across tile heights."""
+    ps = [syn.make_deconv(96, 80, 5, 0.02, 1.5, syn.rng_for(94, 0), lam0=3.0, sweeps=10, em=False),
+          syn.make_denoise(150, 70, 5, 0.05, syn.rng_for(94, 1), mode="paint", lam0=5.0, sweeps=10,
+                           em=False)]
+    a = _ctx(ps)
+    a.ep_tv_run(10, False)
+    ra, _ = _out(a)
+    a.close()
+    b = _ctx(ps, rows=rows)
+    assert b.ep_tv_get_option(N.OPT_TILE_ROWS) == rows
+    b.ep_tv_run(10, False)
+    rb, _ = _out(b)
+    b.close()
+    for (ma, va), (mb, vb) in zip(ra, rb):
+        assert np.array_equal(ma, mb) and np.array_equal(va, vb)
+
+
+def test_autotune_leaves_state_and_is_reused():
+    ps = [syn.make_denoise(200, 260, 8, 0.1, syn.rng_for(95, 0), mode="paint", lam0=4.0, sweeps=6,
+                           em=False)]
+    a = _ctx(ps)
+    a.ep_tv_run(3, False)
+    tune = a.ep_tv_autotune(2)
+    a.ep_tv_run(3, False)
+    ra, _ = _out(a)
+    a.close()
+    b = _ctx(ps)   # same sizes: starts from the tuned height
+    assert b.ep_tv_get_option(N.OPT_TILE_ROWS) == tune["tile_rows"]
+    b.ep_tv_run(6, False)
+    rb, _ = _out(b)
+    b.close()
+    assert np.array_equal(ra[0][0], rb[0][0]) and np.array_equal(ra[0][1], rb[0][1])
+
+
+def test_option_errors():
+    ps = [syn.make_denoise(40, 40, 3, 0.1, syn.rng_for(96, 0), mode="paint", lam0=4.0, sweeps=2,
+                           em=False)]
+    c = _ctx(ps)
+    from paper_2110_01585_amd import EPTVError
+    for opt, val in [(N.OPT_GRAPH, 2), (N.OPT_TILE_ROWS, 3), (N.OPT_TILE_ROWS, 2), (99, 0)]:
+        with pytest.raises(EPTVError):
+            c.ep_tv_set_option(opt, val)
+    c.close()
+
+
+def test_batched_workload_full_size_sampled():
+    """The full batched workload (256 instances, sizes 64..1024, about 48M
+    pixels) in the launch mode the benchmark uses (graph, autotuned tiles,
+    Jacobi CG), 8 sweeps from cold with EM.  The oracle checks the smallest
+    denoising and the smallest deconvolution instance of the batch; every
+    instance must stay finite with non-negative site precisions and lambda > 0."""
+    ps = syn.config3_instances()
+    npx = sum(p.shape[0] * p.shape[1] for p in ps)
+    print(f"batch: {len(ps)} instances, {npx / 1e6:.1f} M pixels")
+    c = _ctx(ps, graph=True, precond=N.PRECOND_JACOBI)
+    c.ep_tv_autotune(2)
+    c.ep_tv_run(8, True)
+    outs, st = _out(c)
+    c.close()
+    for (mu, v), s in zip(outs, st):
+        assert np.isfinite(mu).all() and np.isfinite(v).all() and (v > 0).all()
+        assert s["lambda"] > 0 and s["status"] != N.EP_TV_E_NONFINITE and s["sweeps"] == 8
+    picks = {}
+    for i, p in enumerate(ps):
+        if p.op not in picks or p.shape[0] < ps[picks[p.op]].shape[0]:
+            picks[p.op] = i
+    for op, i in picks.items():
+        p = ps[i]
+        mu_o, v_o, _, info = oep.solve(oep.problem_from_synthetic(f32_problem(p)), 8, True)
+        e_mu, e_v = mean_err(outs[i][0], mu_o), var_err(outs[i][1], v_o)
+        print(f"sample {p.name} {p.shape}: mean {e_mu:.2e} var {e_v:.2e}")
+        assert e_mu <= MEAN_TOL and e_v <= VAR_TOL, p.name
+        assert abs(st[i]["lambda"] / info["lam"] - 1) <= 2e-4
