@@ -85,6 +85,7 @@ class EPState:
     clamp_count: int = 0
     cg_iters: int = 0
     history: list = field(default_factory=list)
+    warm: bool = False              # sites carry information already: no skipped q0 update
 
 
 class EPProblem:
@@ -210,7 +211,7 @@ def tv_block_update(pb: EPProblem, st: EPState, k: int) -> float:
 
 def sweep(pb: EPProblem, st: EPState, t: int, em: bool) -> float:
     """Sweep t (1-based).  Returns a_bar_u of the sweep."""
-    if pb.op.kind != ops.IDENTITY and t > 1:
+    if pb.op.kind != ops.IDENTITY and (t > 1 or st.warm):
         likelihood_site_update(pb, st)
     a_bar = 0.0
     for k in pb.order:
