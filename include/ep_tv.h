@@ -140,6 +140,25 @@ int ep_tv_set_observation(ep_tv_ctx* ctx, const float* const* d_y);
 /* Re-run the cold initialisation with the stored observations.  Asynchronous. */
 int ep_tv_init_cold(ep_tv_ctx* ctx);
 
+/* Warm start from a predicted posterior N(mu_hat, diag var_hat) per instance
+ * (e.g. the network of ep_tv_net.h).  The sites are set so that the global
+ * approximation of Eq. (Q_x_final) equals the prediction: for H = I the
+ * likelihood site keeps its exact value (1/xi, y/xi) and the remaining
+ * precision (at least 1e-8 per class) and eta are split equally over the colour
+ * classes covering the pixel; for the other operators precision and eta are
+ * split equally over the likelihood site and the covering classes.  Uncovered
+ * classes stay (0, 0).  The first sweep then updates the likelihood site too.
+ * lambda_scale > 0 sets lambda_0 = lambda_scale * N / a_x, where a_x is the sum
+ * over all pairs of E|x_i - x_j| under the prediction (option 1 of the
+ * approximations of a_0, Sec. IV-B; lambda_scale = 1 is that option as is);
+ * lambda_scale <= 0 keeps lambda0 of the problem descriptor.
+ * d_mu_hat, d_var_hat: host arrays of n_problems device pointers, height*width
+ * floats each.  An instance whose prediction holds a non-finite value or a
+ * variance <= 0 starts cold instead, and the call returns
+ * EP_TV_W_WARM_FALLBACK.  Synchronises the stream. */
+int ep_tv_init_warm(ep_tv_ctx* ctx, const float* const* d_mu_hat, const float* const* d_var_hat,
+                    double lambda_scale);
+
 /* Run n_sweeps sweeps of Algorithm 1 on every active instance; with em_enabled,
  * lambda <- N / a_bar_u after every sweep (the fast EP-EM of Algorithm 2, one EP
  * iteration per EM iteration).  Asynchronous; no host synchronisation. */

@@ -130,10 +130,12 @@ def normalise(y):
     return m, s
 
 
-def forward(theta, y, bf16=False, ch=CHANNELS):
-    """y: (N, H, W).  Returns (o, cache) with o: (N, H, W, 2)."""
+def forward(theta, y, bf16=False, ch=CHANNELS, ms=None):
+    """y: (N, H, W).  Returns (o, cache) with o: (N, H, W, 2).  ms = (m, s)
+    arrays replace the image statistics (to evaluate a crop of a larger image:
+    an output pixel depends on the input within 6 pixels)."""
     y = np.asarray(y, dtype=np.float64)
-    m, s = normalise(y)
+    m, s = normalise(y) if ms is None else (np.asarray(ms[0], np.float64), np.asarray(ms[1], np.float64))
     x0 = ((y - m[:, None, None]) / s[:, None, None])
     if bf16:
         x0 = np.asarray(x0, np.float32).astype(np.float64)   # the GPU forms x0 in float32

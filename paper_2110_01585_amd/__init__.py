@@ -8,6 +8,7 @@ does, and fails loudly if it has not been built.
 from .api import (Context, EPTVError, ProblemSpec, ep_tv_tilted_moments, ep_tv_version,
                   ep_tv_workspace_bytes, spec_from_synthetic)
 from . import _native as native
+from .net import Net, load_weights, save_weights
 
 __all__ = ["Context", "EPTVError", "ProblemSpec", "ep_tv_tilted_moments", "ep_tv_version", "ep_tv_workspace_bytes",
-           "spec_from_synthetic", "native"]
+           "spec_from_synthetic", "native", "Net", "load_weights", "save_weights"]

@@ -92,11 +92,31 @@ SIGNATURES = {
     "ep_tv_tilted_moments": (ctypes.c_int, [ctypes.c_int32, _P, _P, ctypes.c_float, _P, _P, _P, _P]),
     "ep_tv_set_timing": (ctypes.c_int, [_P, ctypes.c_int32]),
     "ep_tv_get_timing": (ctypes.c_int, [_P, ctypes.POINTER(EpTvTiming)]),
+    "ep_tv_init_warm": (ctypes.c_int, [_P, _FPP, _FPP, ctypes.c_double]),
     "ep_tv_set_option": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int64]),
     "ep_tv_get_option": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64)]),
     "ep_tv_autotune": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.POINTER(EpTvTuneResult)]),
     "ep_tv_last_error": (ctypes.c_char_p, [_P]),
     "ep_tv_destroy": (None, [_P]),
+    # learned warm start (include/ep_tv_net.h)
+    "ep_tv_net_param_count": (ctypes.c_int, []),
+    "ep_tv_net_workspace_bytes": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                                 ctypes.POINTER(ctypes.c_size_t)]),
+    "ep_tv_net_create": (ctypes.c_int, [_P, _P, ctypes.c_size_t, ctypes.c_int32, ctypes.c_int32,
+                                        ctypes.c_int32, _P, ctypes.POINTER(_P)]),
+    "ep_tv_net_sync": (ctypes.c_int, [_P]),
+    "ep_tv_net_infer": (ctypes.c_int, [_P, _P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                       ctypes.c_double, _P, _P]),
+    "ep_tv_net_loss_grad": (ctypes.c_int, [_P, _P, _P, _P, ctypes.c_int32, ctypes.c_int32,
+                                           ctypes.c_int32, ctypes.c_double, _P,
+                                           ctypes.POINTER(ctypes.c_double)]),
+    "ep_tv_net_adam_step": (ctypes.c_int, [_P, ctypes.c_float]),
+    "ep_tv_net_train_step": (ctypes.c_int, [_P, _P, _P, _P, ctypes.c_int32, ctypes.c_int32,
+                                            ctypes.c_int32, ctypes.c_double, ctypes.c_float,
+                                            ctypes.POINTER(ctypes.c_double)]),
+    "ep_tv_net_adam_count": (ctypes.c_int, [_P]),
+    "ep_tv_net_last_error": (ctypes.c_char_p, [_P]),
+    "ep_tv_net_destroy": (None, [_P]),
 }
 
 _lib = None

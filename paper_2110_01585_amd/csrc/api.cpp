@@ -345,9 +345,12 @@ static int set_rows(ep_tv_ctx* c, int rows) {
   return upload_tiles(c);
 }
 
+static int set_tab(ep_tv_ctx* c, float* const* host, float** dev, std::vector<float*>& keep);
+static int pull_states(ep_tv_ctx* c);
+
 extern "C" {
 
-const char* ep_tv_version(void) { return "eptv-gfx950 0.1"; }
+const char* ep_tv_version(void) { return "eptv-gfx950 0.2"; }
 
 int ep_tv_workspace_bytes(const ep_tv_problem* p, int32_t n, size_t* bytes) {
   if (!p || !bytes || n < 1 || n > 4096) return EP_TV_E_ARG;
@@ -473,6 +476,32 @@ int ep_tv_init_cold(ep_tv_ctx* c) {
   HIPCHK(c, launch_init_cold(cur_sites(c).S, c->ypix, c->d_inst, c->d_st, c->d_tiles, c->ntiles,
                              c->stream));
   HIPCHK(c, lik_reset(c->lik, c->stream));
+  return EP_TV_OK;
+}
+
+int ep_tv_init_warm(ep_tv_ctx* c, const float* const* d_mu_hat, const float* const* d_var_hat,
+                    double lambda_scale) {
+  if (!c || !d_mu_hat || !d_var_hat || !std::isfinite(lambda_scale)) return EP_TV_E_ARG;
+  for (int i = 0; i < c->n; ++i)
+    if (!d_mu_hat[i] || !d_var_hat[i]) return fail(c, EP_TV_E_ARG, "null prediction pointer");
+  int rc = ep_tv_init_cold(c);
+  if (rc) return rc;
+  rc = set_tab(c, const_cast<float* const*>(d_mu_hat), c->d_tab0, c->tab_host0);
+  if (rc) return rc;
+  rc = set_tab(c, const_cast<float* const*>(d_var_hat), c->d_tab1, c->tab_host1);
+  if (rc) return rc;
+  HIPCHK(c, launch_init_warm(cur_sites(c).S, c->ypix, c->d_inst, c->d_st, c->n, c->d_tiles, c->ntiles,
+                             c->d_tab0, c->d_tab1, lambda_scale, c->sa.part_eabs, c->sa.part_flags,
+                             c->stream));
+  rc = pull_states(c);
+  if (rc) return rc;
+  int rejected = 0;
+  for (int i = 0; i < c->n; ++i) rejected += c->host_st[i].warm_ok ? 0 : 1;
+  if (rejected) {
+    c->err = std::to_string(rejected) + " instance(s) had a non-finite or non-positive prediction and "
+             "start cold";
+    return EP_TV_W_WARM_FALLBACK;
+  }
   return EP_TV_OK;
 }
 
@@ -779,6 +808,8 @@ int ep_tv_set_sites(ep_tv_ctx* c, const float* const* d_in, const double* lambda
     s.clamps = 0u;
     s.flags = 0u;
     s.cg_total = 0;
+    s.warm = 1;               // restored sites are informative: no skipped q0 update
+    s.warm_ok = 1;
   }
   HIPCHK(c, hipMemcpyAsync(c->d_st, c->host_st.data(), sizeof(InstState) * c->n,
                            hipMemcpyHostToDevice, c->stream));

@@ -68,6 +68,181 @@ hipError_t launch_init_cold(float2* const S[5], const float* y_pix, const InstDe
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Warm start from a predicted posterior N(mu_hat, diag var_hat).  The sites are
+// chosen so that the global approximation (Eq. (Q_x_final)) equals the
+// prediction: for H = I the likelihood site is exact and keeps (1/xi, y/xi) and
+// the rest of the precision (at least 1e-8 per class) is split equally over the
+// covering colour classes; otherwise precision and eta are split equally over
+// the likelihood site and the covering classes.  lambda_0 follows option 1 of
+// the EM approximations of a_0 (Sec. IV-B): a_x = sum over pairs of E|x_i - x_j|
+// under the prediction (a folded-normal mean), lambda_0 = scale * N / a_x.
+__device__ __forceinline__ double folded_mean(double d, double var) {
+  const double sd = sqrt(var);
+  return d * erf(d / (sd * 1.4142135623730951)) + sd * 0.7978845608028654 * exp(-d * d / (2.0 * var));
+}
+
+__device__ __forceinline__ bool pred_ok(float m, float v) {
+  return isfinite(m) && isfinite(v) && v > 0.f;
+}
+
+__global__ __launch_bounds__(256) void k_warm_scan(const InstDev* __restrict__ inst,
+                                                   const int4* __restrict__ tiles,
+                                                   const float* const* __restrict__ mu_tab,
+                                                   const float* const* __restrict__ var_tab,
+                                                   double* __restrict__ part_a,
+                                                   unsigned* __restrict__ part_f) {
+  const int4 td = tiles[blockIdx.x];
+  const InstDev I = inst[td.x];
+  const TileBox b = tile_box(td, I);
+  const float* mu = mu_tab[td.x];
+  const float* va = var_tab[td.x];
+  const int cols = b.c1 - b.c0;
+  const int n = cols * (b.r1 - b.r0);
+  double acc = 0.0;
+  unsigned bad = 0u;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    const int r = b.r0 + i / cols, c = b.c0 + i % cols;
+    const long long p = (long long)r * I.W + c;
+    const float m0 = mu[p], v0 = va[p];
+    if (!pred_ok(m0, v0)) {
+      bad = 1u;
+      continue;
+    }
+    // pairs owned by this pixel: to the right and downwards (wrapping when periodic)
+    int cr = c + 1, rd = r + 1;
+    if (I.bnd == BND_PERIODIC) {
+      cr = cr == I.W ? 0 : cr;
+      rd = rd == I.H ? 0 : rd;
+    }
+    if (cr < I.W) {
+      const long long q = (long long)r * I.W + cr;
+      const float m1 = mu[q], v1 = va[q];
+      if (pred_ok(m1, v1)) acc += folded_mean((double)m0 - m1, (double)v0 + v1);
+    }
+    if (rd < I.H) {
+      const long long q = (long long)rd * I.W + c;
+      const float m1 = mu[q], v1 = va[q];
+      if (pred_ok(m1, v1)) acc += folded_mean((double)m0 - m1, (double)v0 + v1);
+    }
+  }
+  __shared__ double sa[256];
+  __shared__ unsigned sf[256];
+  sa[threadIdx.x] = acc;
+  sf[threadIdx.x] = bad;
+  __syncthreads();
+  for (int w = 128; w >= 1; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      sa[threadIdx.x] += sa[threadIdx.x + w];
+      sf[threadIdx.x] |= sf[threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    part_a[blockIdx.x] = sa[0];
+    part_f[blockIdx.x] = sf[0];
+  }
+}
+
+__global__ __launch_bounds__(256) void k_warm_fin(const InstDev* __restrict__ inst,
+                                                  InstState* __restrict__ st,
+                                                  const double* __restrict__ part_a,
+                                                  const unsigned* __restrict__ part_f, double scale) {
+  const InstDev I = inst[blockIdx.x];
+  InstState& S = st[blockIdx.x];
+  __shared__ double sa[256];
+  __shared__ unsigned sf[256];
+  double a = 0.0;
+  unsigned f = 0u;
+  for (int t = threadIdx.x; t < I.ntiles; t += blockDim.x) {
+    a += part_a[I.tile0 + t];
+    f |= part_f[I.tile0 + t];
+  }
+  sa[threadIdx.x] = a;
+  sf[threadIdx.x] = f;
+  __syncthreads();
+  for (int w = 128; w >= 1; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      sa[threadIdx.x] += sa[threadIdx.x + w];
+      sf[threadIdx.x] |= sf[threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x != 0) return;
+  if (sf[0]) {
+    S.warm = 0;
+    S.warm_ok = 0;
+    return;
+  }
+  S.warm = 1;
+  S.warm_ok = 1;
+  if (scale > 0.0 && sa[0] > 0.0) {
+    S.lam = scale * (double)I.npix / sa[0];
+    S.lam_prev = S.lam;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_warm_write(SitePtrs sp, const float* __restrict__ y_pix,
+                                                    const InstDev* __restrict__ inst,
+                                                    const InstState* __restrict__ st,
+                                                    const int4* __restrict__ tiles,
+                                                    const float* const* __restrict__ mu_tab,
+                                                    const float* const* __restrict__ var_tab) {
+  const int4 td = tiles[blockIdx.x];
+  if (!st[td.x].warm_ok) return;                 // rejected: the cold sites stay
+  const InstDev I = inst[td.x];
+  const TileBox b = tile_box(td, I);
+  const float* mu = mu_tab[td.x];
+  const float* va = var_tab[td.x];
+  const int cols = b.c1 - b.c0;
+  const int n = cols * (b.r1 - b.r0);
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    const int r = b.r0 + i / cols, c = b.c0 + i % cols;
+    const long long p = I.off + (long long)r * I.pitch + c;
+    const float m = mu[(long long)r * I.W + c];
+    const float prec = 1.f / va[(long long)r * I.W + c];
+    bool cov[4];
+    int cnt = 0;
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) {
+      cov[kk] = covered(kk, r, c, I);
+      cnt += cov[kk] ? 1 : 0;
+    }
+    float tk, ek;
+    if (I.op == OP_IDENTITY) {
+      const float yv = y_pix[p];
+      sp.S[0][p] = make_float2(I.inv_xi, yv * I.inv_xi);
+      const float rest = fmaxf(prec - I.inv_xi, (float)cnt * kSiteInitPrec);
+      const float rest_eta = m * (I.inv_xi + rest) - yv * I.inv_xi;
+      const float share = cnt ? 1.f / (float)cnt : 0.f;
+      tk = rest * share;
+      ek = rest_eta * share;
+    } else {
+      const float share = 1.f / (float)(1 + cnt);
+      tk = prec * share;
+      ek = m * prec * share;
+      sp.S[0][p] = make_float2(tk, ek);
+    }
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) sp.S[kk + 1][p] = cov[kk] ? make_float2(tk, ek) : make_float2(0.f, 0.f);
+  }
+}
+
+hipError_t launch_init_warm(float2* const S[5], const float* y_pix, const InstDev* inst,
+                            InstState* st, int n, const int4* tiles, int ntiles,
+                            const float* const* mu_tab, const float* const* var_tab,
+                            double lambda_scale, double* part_a, unsigned* part_f, hipStream_t s) {
+  if (ntiles == 0) return hipSuccess;
+  SitePtrs sp;
+  for (int k = 0; k < 5; ++k) sp.S[k] = S[k];
+  hipLaunchKernelGGL(k_warm_scan, dim3(ntiles), dim3(256), 0, s, inst, tiles, mu_tab, var_tab, part_a,
+                     part_f);
+  hipLaunchKernelGGL(k_warm_fin, dim3(n), dim3(256), 0, s, inst, st, part_a, part_f, lambda_scale);
+  hipLaunchKernelGGL(k_warm_write, dim3(ntiles), dim3(256), 0, s, sp, y_pix, inst, st, tiles, mu_tab,
+                     var_tab);
+  return hipGetLastError();
+}
+
 // One block per instance: deterministic fixed-shape reduction of the sweep's
 // per-tile partials, then lambda / convergence / counters.
 __global__ __launch_bounds__(256) void k_finalize(const InstDev* __restrict__ inst,

@@ -46,7 +46,7 @@ struct InstState {
   double cg_rz, cg_alpha, cg_beta;
   unsigned clamps, flags, active, sweeps;
   int cg_last, cg_total, converged, cg_done;
-  int cg_it, x_valid, pad0, pad1;
+  int cg_it, x_valid, warm, warm_ok;   // warm: sites were set from a prediction (no skipped q0)
 };
 
 enum { FLAG_NONFINITE = 1u };
@@ -94,5 +94,13 @@ hipError_t launch_sites_io(float2* const S[5], const InstDev* inst, const int4* 
                            float* const* d_tab, int to_user, hipStream_t s);
 hipError_t launch_yrange(const float* y_pix, const InstDev* inst, InstState* st, int n,
                          hipStream_t s);
+// Warm start from predicted marginals (device pointer tables, one per instance):
+// validates the prediction, computes lambda_0 = scale * N / a_x (a_x: sum over
+// pairs of the folded-normal mean of x_i - x_j under the prediction) when
+// scale > 0, and overwrites the sites of every accepted instance.
+hipError_t launch_init_warm(float2* const S[5], const float* y_pix, const InstDev* inst,
+                            InstState* st, int n, const int4* tiles, int ntiles,
+                            const float* const* mu_tab, const float* const* var_tab,
+                            double lambda_scale, double* part_a, unsigned* part_f, hipStream_t s);
 
 }  // namespace eptv

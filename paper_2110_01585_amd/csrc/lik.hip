@@ -89,7 +89,7 @@ __global__ __launch_bounds__(256) void k_lik_prep(LikArgs A, const float2* __res
   const LikInst L = A.inst[td.x];
   const InstState& st = A.st[L.inst];
   double at = 0.0, ab = 0.0;
-  if (st.active && st.sweeps > 0) {
+  if (st.active && (st.sweeps > 0 || st.warm)) {
     const TileXY t = lik_tile(td, L);
     const int cols = t.c1 - t.c0;
     const int n = cols * (t.r1 - t.r0);
@@ -134,7 +134,7 @@ __global__ __launch_bounds__(256) void k_lik_fin(LikArgs A, int stage) {
   const double N = (double)L.H * (double)L.W;
   switch (stage) {
     case FIN_PREP:
-      if (!st.active || st.sweeps == 0) {
+      if (!st.active || (st.sweeps == 0 && !st.warm)) {
         st.cg_done = 1;          // nothing to do this sweep
         break;
       }
@@ -368,7 +368,7 @@ __global__ __launch_bounds__(256) void k_lik_site(LikArgs A, float2* __restrict_
   const int4 td = A.tiles[tile];
   const LikInst L = A.inst[td.x];
   InstState& st = A.st[L.inst];
-  if (!st.active || st.sweeps == 0) return;
+  if (!st.active || (st.sweeps == 0 && !st.warm)) return;
   if (tile == L.tile0 && threadIdx.x == 0) {
     st.cg_last = st.cg_it;
     st.cg_total += st.cg_it;

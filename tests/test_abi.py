@@ -1,5 +1,5 @@
-"""CPU checks of the C-ABI library: it loads, exports every symbol that
-include/ep_tv.h declares, and validates descriptors on the host."""
+"""CPU checks of the C-ABI library: it loads, exports every symbol that the
+headers under include/ declare, and validates descriptors on the host."""
 import ctypes
 import os
 import re
@@ -12,20 +12,22 @@ from paper_2110_01585_amd import _native as N
 from paper_2110_01585_amd import ProblemSpec, ep_tv_workspace_bytes, EPTVError
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "ep_tv.h")
+HEADERS = [os.path.join(ROOT, "include", h) for h in sorted(os.listdir(os.path.join(ROOT, "include")))
+           if h.endswith(".h")]
 
 
 def _declared():
-    src = open(HEADER).read()
-    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    names = re.findall(r"\b(ep_tv_[a-z_]+)\s*\(", src)
-    return sorted(set(names))
+    names = set()
+    for h in HEADERS:
+        src = re.sub(r"/\*.*?\*/", "", open(h).read(), flags=re.S)
+        names |= set(re.findall(r"\b(ep_tv_[a-z_0-9]+)\s*\(", src))
+    return sorted(names)
 
 
 def test_library_exports_every_declared_symbol():
     lib = N.lib()
     declared = _declared()
-    assert len(declared) >= 14
+    assert len(declared) >= 30
     for name in declared:
         assert hasattr(lib, name), name
         assert name in N.SIGNATURES, f"binding lacks {name}"
@@ -66,3 +68,17 @@ def test_null_arguments_are_rejected():
     assert lib.ep_tv_solve(None, 1, 0.0, 0, None, None, None) == N.EP_TV_E_ARG
     assert lib.ep_tv_last_error(None) == b"null context"
     lib.ep_tv_destroy(None)
+
+
+def test_net_host_validation():
+    lib = N.lib()
+    assert lib.ep_tv_net_param_count() == 37890
+    nb = ctypes.c_size_t(0)
+    assert lib.ep_tv_net_workspace_bytes(16, 256, 256, ctypes.byref(nb)) == 0
+    assert nb.value > 16 * 256 * 256 * 64 * 7
+    for bad in [(0, 8, 8), (1, 0, 8), (1, 8, 0), (1, 20000, 8)]:
+        assert lib.ep_tv_net_workspace_bytes(*bad, ctypes.byref(nb)) == N.EP_TV_E_ARG
+    h = ctypes.c_void_p(None)
+    assert lib.ep_tv_net_create(None, None, 0, 1, 8, 8, None, ctypes.byref(h)) == N.EP_TV_E_ARG
+    assert lib.ep_tv_net_adam_count(None) == -1
+    assert lib.ep_tv_init_warm(None, None, None, 1.0) == N.EP_TV_E_ARG

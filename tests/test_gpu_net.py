@@ -1,0 +1,219 @@
+"""GPU parity of the learned warm start: network inference, loss and gradient
+(hand-written bfloat16 MFMA kernels) against the FP64 oracle network with the
+same bfloat16 storage rounding, the Adam update, and the warm site
+initialisation followed by EP sweeps against the oracle."""
+import math
+
+import numpy as np
+import pytest
+
+import synthetic as syn
+from oracle import ep as oep
+from oracle import net as onet
+from oracle import warm as owarm
+from tests.gpu_util import MEAN_TOL, VAR_TOL, f32_problem, mean_err, observation_tensor, var_err
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_2110_01585_amd import Context, Net, spec_from_synthetic  # noqa: E402
+from paper_2110_01585_amd import _native as N  # noqa: E402
+from paper_2110_01585_amd.net import init_params  # noqa: E402
+
+# Tolerances (derived in the design notes): both sides round activations and
+# gradients to bfloat16 at the same points, so differences come from float32
+# versus float64 accumulation flipping an occasional bfloat16 rounding (one
+# ulp = 2^-8 relative) and propagating through the later layers.
+OUT_TOL = 1e-2        # max |o_gpu - o_oracle| / max |o_oracle|
+GRAD_TOL = 2e-2       # per-tensor relative Frobenius error of the parameter gradient
+LOSS_TOL = 1e-3
+
+
+def _params(seed=0, bias=0.05):
+    p = init_params(seed).astype(np.float64)
+    rng = np.random.default_rng(seed + 100)
+    for w, b in onet.unpack(p):
+        b[:] = bias * rng.standard_normal(b.shape)
+    return p.astype(np.float32)
+
+
+def _images(b, h, w, seed=0):
+    ys, mus, vs = [], [], []
+    for i in range(b):
+        p = syn.make_deconv(h, w, 6, 0.02, 1.5, syn.rng_for(61, 1000 * seed + i), ksize=5)
+        ys.append(p.y)
+        mus.append(p.x_true + 0.01 * np.sin(np.arange(h * w).reshape(h, w)))
+        vs.append(np.full((h, w), 2e-4) * np.exp(0.3 * np.cos(np.arange(h * w).reshape(h, w) / 7.0)))
+    return np.array(ys), np.array(mus), np.array(vs)
+
+
+def _t(a):
+    return torch.tensor(np.ascontiguousarray(a, dtype=np.float32), device="cuda")
+
+
+def _o_from(mu, var, y, xi):
+    m, s = onet.normalise(y)
+    return np.stack([(mu - m[:, None, None]) / s[:, None, None], np.log(var / xi)], axis=-1)
+
+
+@pytest.mark.parametrize("b,h,w", [(2, 40, 70), (1, 33, 129), (3, 16, 16)])
+def test_infer_matches_oracle(b, h, w):
+    xi = 4e-4
+    theta = _params(b + h)
+    y, _, _ = _images(b, h, w, seed=h)
+    net = Net(theta, max_batch=b, max_h=h, max_w=w)
+    mu, var = net.infer(_t(y), xi)
+    torch.cuda.synchronize()
+    o_gpu = _o_from(mu.cpu().numpy().astype(np.float64), var.cpu().numpy().astype(np.float64), y, xi)
+    o_ref, _ = onet.forward(theta.astype(np.float64), y, bf16=True)
+    err = np.max(np.abs(o_gpu - o_ref)) / np.max(np.abs(o_ref))
+    print(f"infer {b}x{h}x{w}: max rel err {err:.2e}, mean abs {np.mean(np.abs(o_gpu - o_ref)):.2e}")
+    assert err <= OUT_TOL
+    net.close()
+
+
+@pytest.mark.parametrize("b,h,w", [(2, 48, 80), (1, 37, 45)])
+def test_loss_grad_matches_oracle(b, h, w):
+    xi = 2e-4
+    theta = _params(7 + h)
+    y, mu_t, v_t = _images(b, h, w, seed=h + 1)
+    net = Net(theta, max_batch=b, max_h=h, max_w=w)
+    loss, g = net.loss_grad(_t(y), _t(mu_t), _t(v_t), xi)
+    g = g.cpu().numpy().astype(np.float64)
+    l_ref, g_ref, _ = onet.loss_and_grad(theta.astype(np.float64), y, mu_t, v_t, xi, bf16=True)
+    print(f"loss gpu {loss:.8g} oracle {l_ref:.8g}")
+    assert abs(loss / l_ref - 1) <= LOSS_TOL
+    for li, ((gw, gb), (rw, rb)) in enumerate(zip(onet.unpack(g), onet.unpack(g_ref))):
+        for name, a, r in (("W", gw, rw), ("b", gb, rb)):
+            e = np.linalg.norm(a - r) / np.linalg.norm(r)
+            print(f"layer {li + 1} {name}: rel err {e:.2e}")
+            assert e <= GRAD_TOL, (li, name, e)
+    net.close()
+
+
+def test_adam_steps_follow_algorithm():
+    """Two Adam steps on the GPU equal Adam (float64, same gradients) to float32 round-off."""
+    xi = 2e-4
+    theta = _params(3)
+    y, mu_t, v_t = _images(2, 24, 24, seed=5)
+    net = Net(theta, max_batch=2, max_h=24, max_w=24)
+    opt = onet.Adam(theta.size)
+    ref = theta.astype(np.float64)
+    lr = 1e-3
+    for step in range(2):
+        _, g = net.loss_grad(_t(y), _t(mu_t), _t(v_t), xi)
+        net.adam_step(lr)
+        ref = opt.step(ref, g.cpu().numpy().astype(np.float64), lr)
+        got = net.params.cpu().numpy().astype(np.float64)
+        assert np.max(np.abs(got - ref)) <= 1e-6 + 1e-3 * lr, step
+    assert net.adam_count() == 2
+    net.close()
+
+
+def test_training_reduces_loss():
+    """A short run of the GPU training kernels on a fixed batch lowers the loss."""
+    xi = 2e-4
+    y, mu_t, v_t = _images(4, 32, 32, seed=9)
+    net = Net(_params(11), max_batch=4, max_h=32, max_w=32)
+    yt, mt, vt = _t(y), _t(mu_t), _t(v_t)
+    l0, _ = net.loss_grad(yt, mt, vt, xi, want_grad=False)
+    for _ in range(60):
+        net.train_step(yt, mt, vt, xi, 2e-3)
+    l1, _ = net.loss_grad(yt, mt, vt, xi, want_grad=False)
+    print(f"loss {l0:.4g} -> {l1:.4g}")
+    assert l1 < 0.5 * l0
+    net.close()
+
+
+def test_infer_full_size_sampled():
+    """2048^2 inference (the warm-start test image), checked at sampled pixels
+    (corners, edges, interior) against the oracle evaluated on the 13 x 13
+    receptive field of each pixel with the full image's statistics."""
+    p = syn.config4_test(seed=0)
+    xi = p.xi
+    theta = _params(21)
+    net = Net(theta, max_batch=1, max_h=2048, max_w=2048)
+    mu, var = net.infer(_t(p.y), xi)
+    torch.cuda.synchronize()
+    mu, var = mu.cpu().numpy().astype(np.float64), var.cpu().numpy().astype(np.float64)
+    net.close()
+    m, s = onet.normalise(p.y[None])
+    rng = np.random.default_rng(0)
+    pts = [(0, 0), (0, 2047), (2047, 0), (2047, 2047), (5, 1000), (1000, 2046), (1024, 1024)]
+    pts += [tuple(rng.integers(0, 2048, 2)) for _ in range(25)]
+    errs = []
+    for r, c in pts:
+        r0, c0 = max(0, r - 6), max(0, c - 6)
+        crop = p.y[r0:r + 7, c0:c + 7][None]
+        o_ref, _ = onet.forward(theta.astype(np.float64), crop, bf16=True, ms=(m, s))
+        o_ref = o_ref[0, r - r0, c - c0]
+        o_gpu = np.array([(mu[r, c] - m[0]) / s[0], math.log(var[r, c] / xi)])
+        errs.append(np.max(np.abs(o_gpu - o_ref)) / max(1.0, np.max(np.abs(o_ref))))
+    print(f"sampled max rel err {max(errs):.2e}")
+    assert max(errs) <= OUT_TOL
+
+
+def _warm_inputs(p, seed):
+    rng = np.random.default_rng(seed)
+    mu = p.x_true + 0.02 * rng.standard_normal(p.shape)
+    v = p.xi * 0.3 * np.exp(0.2 * rng.standard_normal(p.shape))
+    return mu, v
+
+
+def test_init_warm_sites_and_lambda_match_oracle():
+    ps = [syn.make_deconv(40, 52, 5, 0.02, 1.5, syn.rng_for(62, 0), lam0=1.0, sweeps=10, em=True),
+          syn.make_denoise(31, 45, 4, 0.05, syn.rng_for(62, 1), mode="paint", lam0=1.0, sweeps=10, em=True),
+          syn.make_cs(32, 32, 4, 0.01, 0.3, syn.rng_for(62, 2), sweeps=10, em=True)]
+    ps[1].boundary = "free"
+    preds = [_warm_inputs(p, i) for i, p in enumerate(ps)]
+    ctx = Context([spec_from_synthetic(p) for p in ps])
+    ctx.ep_tv_set_observation([observation_tensor(p, torch) for p in ps])
+    rc = ctx.ep_tv_init_warm([_t(m) for m, _ in preds], [_t(v) for _, v in preds], 1.0)
+    assert rc == N.EP_TV_OK
+    outs = [torch.empty(10 * p.shape[0] * p.shape[1], device="cuda") for p in ps]
+    ctx.ep_tv_get_sites(outs)
+    st = ctx.ep_tv_get_stats()
+    for p, (m, v), o, s in zip(ps, preds, outs, st):
+        pb = oep.problem_from_synthetic(f32_problem(p))
+        ref = owarm.init_warm(pb, m.astype(np.float32), v.astype(np.float32))
+        sites = o.cpu().numpy().astype(np.float64).reshape(10, -1)
+        tau, eta = sites[0::2], sites[1::2]
+        assert np.allclose(tau, ref.tau, rtol=2e-6, atol=1e-12)
+        assert np.allclose(eta, ref.eta, rtol=2e-5, atol=1e-6 * np.abs(ref.eta).max())
+        assert abs(s["lambda"] / ref.lam - 1) <= 1e-6
+    # EP from the warm start, against the oracle from the same warm start
+    ctx.ep_tv_run(10, True)
+    mus, vs = ctx.marginals()
+    st = ctx.ep_tv_get_stats()
+    torch.cuda.synchronize()
+    for p, (m, v), mg, vg, s in zip(ps, preds, mus, vs, st):
+        pb = oep.problem_from_synthetic(f32_problem(p))
+        ref = owarm.init_warm(pb, m.astype(np.float32), v.astype(np.float32))
+        mu_o, v_o, _, info = oep.solve(pb, 10, True, state=ref)
+        e_mu = mean_err(mg.cpu().numpy().astype(np.float64), mu_o)
+        e_v = var_err(vg.cpu().numpy().astype(np.float64), v_o)
+        print(f"{p.name}: warm 10 sweeps mean {e_mu:.2e} var {e_v:.2e}")
+        assert e_mu <= MEAN_TOL and e_v <= VAR_TOL
+        assert abs(s["lambda"] / info["lam"] - 1) <= 2e-4
+    ctx.close()
+
+
+def test_init_warm_rejects_bad_prediction_per_instance():
+    ps = [syn.make_deconv(32, 32, 4, 0.02, 1.5, syn.rng_for(63, i), lam0=2.0, sweeps=5, em=True)
+          for i in range(2)]
+    preds = [_warm_inputs(p, i) for i, p in enumerate(ps)]
+    bad_mu = preds[1][0].copy()
+    bad_mu[3, 4] = np.nan
+    ctx = Context([spec_from_synthetic(p) for p in ps])
+    ctx.ep_tv_set_observation([observation_tensor(p, torch) for p in ps])
+    rc = ctx.ep_tv_init_warm([_t(preds[0][0]), _t(bad_mu)], [_t(preds[0][1]), _t(preds[1][1])], 1.0)
+    assert rc == N.EP_TV_W_WARM_FALLBACK
+    outs = [torch.empty(10 * 32 * 32, device="cuda") for _ in ps]
+    ctx.ep_tv_get_sites(outs)
+    st = ctx.ep_tv_get_stats()
+    pb = oep.problem_from_synthetic(f32_problem(ps[1]))
+    cold = oep.init_cold(pb)
+    sites = outs[1].cpu().numpy().astype(np.float64).reshape(10, -1)
+    assert np.allclose(sites[0::2], cold.tau, rtol=1e-6) and np.allclose(sites[1::2], cold.eta, rtol=1e-5)
+    assert st[1]["lambda"] == 2.0 and st[0]["lambda"] != 2.0
+    ctx.close()
