@@ -20,5 +20,14 @@ void dft_destroy(LikCtx& lc);
 // z = M^{-1} r with the circulant M = H^T H / xi + d_bar I, for instances
 // whose preconditioner is PRECOND_CIRCULANT
 hipError_t fft_precondition(LikCtx& lc, hipStream_t s);
+// z = M^{-1} r through a real-input transform (half spectra, three row passes
+// and two transposes), writing r.z and r.r partials at [tile0, tile0 + npart)
+// (update = 1: first the CG step x += alpha p, r -= alpha q, fused into the
+// first pass)
+hipError_t rfft_precondition(LikCtx& lc, int update, hipStream_t s);
+// masked-DFT instances: p_out = z + beta p_in and q = (H^T H / xi + diag tau_c)
+// p_out by the real transform, with p.q partials at [tile0, tile0 + npart)
+hipError_t rfft_product(LikCtx& lc, hipStream_t s);
+int rfft_partials(int H, int W);
 
 }  // namespace eptv

@@ -67,6 +67,15 @@ __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
   return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 
+// LDS index with one pad element per 16: the radix-16 pass writes 16
+// consecutive outputs per work item, which without padding puts the lanes of a
+// wave 128 bytes apart and onto the same few LDS banks.
+__device__ __forceinline__ int pidx(int i) { return i + (i >> 4); }
+template <int N>
+struct Padded {
+  static constexpr int value = N + N / 16;
+};
+
 // ---- in-register DFTs of size 2..16 (radix-2 decimation in time) ----
 // cos and sin of 2 pi k / 16
 __constant__ float kC16[16] = {1.0f, 0.92387953251128674f, 0.70710678118654752f,
@@ -118,11 +127,13 @@ __device__ __forceinline__ void dft_reg(float2 (&v)[R], float sgn) {
 // writes its R outputs after it.  Work item j of a row (j < L/R), k = j mod Ns:
 //   in:  X[j + r L/R],  twiddled by e^{sgn 2 pi i r k / (R Ns)}
 //   out: X[(j - k) R + k + r Ns]
-template <int R>
-__device__ __forceinline__ void stockham_pass(float2* X, int rows, int L, int Ns,
-                                              const float2* __restrict__ tw, float sgn) {
+// R, Ns and L are compile-time, so the index arithmetic is shifts and masks.
+template <int R, int Ns, int L>
+__device__ __forceinline__ void stockham_pass(float2* X, int rows, const float2* __restrict__ tw,
+                                              float sgn) {
   constexpr int kItems = 16 / R;               // work items per thread (rows * L <= 4096)
-  const int per_row = L / R;
+  constexpr int per_row = L / R;
+  constexpr int step = L / (R * Ns);
   const int total = rows * per_row;
   float2 v[kItems][R];
   int base[kItems];
@@ -133,12 +144,11 @@ __device__ __forceinline__ void stockham_pass(float2* X, int rows, int L, int Ns
     if (w < total) {
       const int row = w / per_row, j = w % per_row;
       const int k = j & (Ns - 1);
-      float2* Xr = X + row * L;
-      const int step = L / (R * Ns);
+      const int rbase = row * L + j;
 #pragma unroll
       for (int r = 0; r < R; ++r) {
-        float2 x = Xr[j + r * per_row];
-        if (r > 0) {
+        float2 x = X[pidx(rbase + r * per_row)];
+        if (Ns > 1 && r > 0) {
           float2 t = tw[r * k * step];
           t.y *= -sgn;        // table holds e^{-2 pi i t / L}; sgn = +1 for the inverse
           x = cmul(x, t);
@@ -154,20 +164,35 @@ __device__ __forceinline__ void stockham_pass(float2* X, int rows, int L, int Ns
     if (base[it] >= 0) {
       dft_reg<R>(v[it], sgn);
 #pragma unroll
-      for (int r = 0; r < R; ++r) X[base[it] + r * Ns] = v[it][r];
+      for (int r = 0; r < R; ++r) X[pidx(base[it] + r * Ns)] = v[it][r];
     }
   }
   __syncthreads();
 }
 
+// All passes of a length-L transform: radix 16 while at least 16 points per
+// butterfly remain, then one pass of the remaining radix (8, 4 or 2).
+template <int L, int Ns>
+__device__ __forceinline__ void fft_passes(float2* X, int rows, const float2* __restrict__ tw,
+                                           float sgn) {
+  if constexpr (Ns < L) {
+    constexpr int R = (L / Ns) >= 16 ? 16 : (L / Ns);
+    stockham_pass<R, Ns, L>(X, rows, tw, sgn);
+    fft_passes<L, Ns * R>(X, rows, tw, sgn);
+  }
+}
+
 template <int L>
 __global__ __launch_bounds__(256) void k_fft_rows(FftArgs a) {
   constexpr int kRows = L >= 4096 ? 1 : (4096 / L > 16 ? 16 : 4096 / L);
-  __shared__ float2 X[kRows * L];
+  __shared__ float2 X[Padded<kRows * L>::value];
   const int row0 = blockIdx.x * kRows;
   const int rows = min(kRows, a.nrows - row0);
   // ---- load (pre-op) ----
-  for (int i = threadIdx.x; i < rows * L; i += blockDim.x) {
+  #pragma unroll
+  for (int u_ = 0; u_ < (kRows * L + 255) / 256; ++u_) {
+    const int i = threadIdx.x + u_ * 256;
+    if (i >= rows * L) continue;
     const int row = row0 + i / L, c = i % L;
     float2 v;
     if (a.pre == PRE_COMPLEX) {
@@ -190,23 +215,18 @@ __global__ __launch_bounds__(256) void k_fft_rows(FftArgs a) {
       const long long q = (long long)row * L + c;
       v = a.mask[q] ? make_float2(a.obs[2 * q], a.obs[2 * q + 1]) : make_float2(0.f, 0.f);
     }
-    X[i] = v;
+    X[pidx(i)] = v;
   }
   __syncthreads();
   // ---- Stockham passes: radix 16 while possible, then 8, 4, 2 ----
-  if (a.logL > 0) {
-    const float sgn = a.inverse ? 1.f : -1.f;
-    int Ns = 1;
-    int rem = a.logL;
-    while (rem >= 4) { stockham_pass<16>(X, rows, L, Ns, a.tw, sgn); Ns *= 16; rem -= 4; }
-    if (rem == 3) stockham_pass<8>(X, rows, L, Ns, a.tw, sgn);
-    else if (rem == 2) stockham_pass<4>(X, rows, L, Ns, a.tw, sgn);
-    else if (rem == 1) stockham_pass<2>(X, rows, L, Ns, a.tw, sgn);
-  }
+  if (a.logL > 0) fft_passes<L, 1>(X, rows, a.tw, a.inverse ? 1.f : -1.f);
   // ---- store (post-op) ----
-  for (int i = threadIdx.x; i < rows * L; i += blockDim.x) {
+  #pragma unroll
+  for (int u_ = 0; u_ < (kRows * L + 255) / 256; ++u_) {
+    const int i = threadIdx.x + u_ * 256;
+    if (i >= rows * L) continue;
     const int row = row0 + i / L, c = i % L;
-    const float2 v = X[i];
+    const float2 v = X[pidx(i)];
     if (a.post == POST_COMPLEX) {
       a.dst[(long long)row * L + c] = v;
     } else if (a.post == POST_SCALE) {
@@ -225,17 +245,220 @@ __global__ __launch_bounds__(256) void k_fft_rows(FftArgs a) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// Real-input 2-D transforms for the fast CG of circulant-preconditioned
+// instances: z = M^{-1} r with M = H^T H / xi + d_bar I, and the exact product
+// q = (H^T H / xi + diag tau_c) p, both through three row kernels and two
+// transposes on half spectra (the input is real, the spectra are even).
+//   RF_FWD:  complex row j = v[2j] + i v[2j+1] (two real rows), forward FFT, split
+//            into the half spectra of both rows, k = 0..W/2:
+//              V_a(k) = (Z(k) + conj Z(W-k)) / 2,  V_b(k) = (Z(k) - conj Z(W-k)) / 2i;
+//            stored as rows 2j, 2j+1 of an H x (W/2+1) array.  v = r, or the new
+//            search direction p = z + beta p (written back) for the product;
+//   RF_FILT: (after a transpose) rows of length H, one per k: forward FFT,
+//            multiply by scale / (spec / xi + d_bar) or by scale * spec / xi,
+//            inverse FFT;
+//   RF_INV:  (after the transpose back) rebuild Z(k) = V_a(k) + i V_b(k) for all k
+//            (V(W-k) = conj V(k)), inverse FFT, Re -> row 2j, Im -> row 2j+1:
+//            z with partials of r.z and r.r, or q = result + tau_c p with
+//            partials of p.q.
+enum { RF_FWD = 0, RF_FILT, RF_INV };
+enum { RFM_PRECOND = 0, RFM_PRODUCT = 1 };
+
+struct RfftArgs {
+  const float2* src;         // RF_FILT / RF_INV input (dense complex rows)
+  float2* dst;               // RF_FWD / RF_FILT output (dense complex rows)
+  const float2* tw;
+  int nrows;                 // complex rows processed (RF_FWD / RF_INV: H / 2; RF_FILT: W/2 + 1)
+  int logL;
+  int ld;                    // row stride of the half-spectrum array (W/2 + 1)
+  int mode;                  // RFM_PRECOND or RFM_PRODUCT
+  int update;                // RF_FWD precondition: first x += alpha p, r -= alpha q
+  long long off;             // real planes (pitched)
+  int pitch;
+  float* r;                  // residual
+  float* x;                  // CG iterate (RF_FWD precondition with update)
+  const float* q;            // A p (RF_FWD precondition with update)
+  const float* z;            // preconditioned residual (RF_FWD, product: direction update)
+  const float* p_in;         // previous search direction (RF_FWD product)
+  float* p;                  // current direction (RF_FWD product: written; RF_INV product and
+                             // RF_FWD precondition update: read)
+  const float* tauc;
+  float* out;                // RF_INV: z (precondition) or q (product)
+  const float* specT;        // eigenvalues of H^T H, transposed dense (W x H)
+  float inv_xi, scale;
+  const InstState* st;
+  int inst;
+  double* part0;             // RF_INV partials at [part_base + blockIdx.x]
+  double* part1;
+  int part_base;
+};
+
+template <int L, int STAGE>
+__global__ __launch_bounds__(256) void k_rfft(RfftArgs a) {
+  constexpr int kRows = L >= 4096 ? 1 : (4096 / L > 16 ? 16 : 4096 / L);
+  __shared__ float2 X[Padded<kRows * L>::value];
+  __shared__ float2 TW[L];            // twiddle table, read by every pass
+  const int row0 = blockIdx.x * kRows;
+  const int rows = min(kRows, a.nrows - row0);
+  const int half = L / 2;
+  const InstState& st = a.st[a.inst];
+  const bool skip = st.cg_done != 0;   // uniform per launch (one instance)
+  // ---- load ----
+  if (!skip) {
+#pragma unroll
+    for (int u_ = 0; u_ < (L + 255) / 256; ++u_) {
+      const int i = threadIdx.x + u_ * 256;
+      if (i < L) TW[i] = a.tw[i];
+    }
+    const float alpha = (float)st.cg_alpha;
+    #pragma unroll
+    for (int u_ = 0; u_ < (kRows * L + 255) / 256; ++u_) {
+      const int i = threadIdx.x + u_ * 256;
+      if (i >= rows * L) continue;
+      const int j = row0 + i / L, c = i % L;
+      float2 v;
+      if (STAGE == RF_FWD) {
+        const long long p = a.off + (long long)(2 * j) * a.pitch + c;
+        if (a.mode == RFM_PRECOND) {
+          if (a.update) {
+            const long long p1 = p + a.pitch;
+            const float r0 = a.r[p] - alpha * a.q[p], r1 = a.r[p1] - alpha * a.q[p1];
+            a.x[p] += alpha * a.p[p];
+            a.x[p1] += alpha * a.p[p1];
+            a.r[p] = r0;
+            a.r[p1] = r1;
+            v = make_float2(r0, r1);
+          } else {
+            v = make_float2(a.r[p], a.r[p + a.pitch]);
+          }
+        } else {
+          const bool first = st.cg_it == 0;
+          const float beta = (float)st.cg_beta;
+          const float p0 = first ? a.z[p] : a.z[p] + beta * a.p_in[p];
+          const float p1 = first ? a.z[p + a.pitch] : a.z[p + a.pitch] + beta * a.p_in[p + a.pitch];
+          a.p[p] = p0;
+          a.p[p + a.pitch] = p1;
+          v = make_float2(p0, p1);
+        }
+      } else if (STAGE == RF_FILT) {
+        v = a.src[(long long)j * L + c];
+      } else {
+        const bool lo = c <= half;
+        const int k = lo ? c : L - c;
+        float2 A = a.src[(long long)(2 * j) * a.ld + k];
+        float2 B = a.src[(long long)(2 * j + 1) * a.ld + k];
+        if (!lo) { A.y = -A.y; B.y = -B.y; }
+        v = make_float2(A.x - B.y, A.y + B.x);
+      }
+      X[pidx(i)] = v;
+    }
+  }
+  __syncthreads();
+  if (!skip) {
+    if (STAGE == RF_FWD) {
+      fft_passes<L, 1>(X, rows, TW, -1.f);
+    } else if (STAGE == RF_FILT) {
+      fft_passes<L, 1>(X, rows, TW, -1.f);
+      const float dbar = (float)st.dbar;
+      #pragma unroll
+      for (int u_ = 0; u_ < (kRows * L + 255) / 256; ++u_) {
+        const int i = threadIdx.x + u_ * 256;
+        if (i >= rows * L) continue;
+        const int j = row0 + i / L, c = i % L;
+        const float sp = a.specT[(long long)j * L + c] * a.inv_xi;
+        const float m = a.mode == RFM_PRECOND ? a.scale / (sp + dbar) : a.scale * sp;
+        X[pidx(i)] = make_float2(X[pidx(i)].x * m, X[pidx(i)].y * m);
+      }
+      __syncthreads();
+      fft_passes<L, 1>(X, rows, TW, 1.f);
+    } else {
+      fft_passes<L, 1>(X, rows, TW, 1.f);
+    }
+  }
+  // ---- store ----
+  if (STAGE == RF_FWD) {
+    if (skip) return;
+    #pragma unroll
+    for (int u_ = 0; u_ < (kRows * (L / 2 + 1) + 255) / 256; ++u_) {
+      const int i = threadIdx.x + u_ * 256;
+      if (i >= rows * (half + 1)) continue;
+      const int jr = i / (half + 1), k = i % (half + 1);
+      const float2 zk = X[pidx(jr * L + k)];
+      float2 zm = X[pidx(jr * L + ((L - k) & (L - 1)))];
+      zm.y = -zm.y;                                   // conj Z(W - k)
+      const float2 sa = make_float2(0.5f * (zk.x + zm.x), 0.5f * (zk.y + zm.y));
+      const float2 sb = make_float2(0.5f * (zk.y - zm.y), -0.5f * (zk.x - zm.x));   // (Z - conj) / 2i
+      const int j = row0 + jr;
+      a.dst[(long long)(2 * j) * a.ld + k] = sa;
+      a.dst[(long long)(2 * j + 1) * a.ld + k] = sb;
+    }
+  } else if (STAGE == RF_FILT) {
+    if (skip) return;
+    #pragma unroll
+    for (int u_ = 0; u_ < (kRows * L + 255) / 256; ++u_) {
+      const int i = threadIdx.x + u_ * 256;
+      if (i >= rows * L) continue;
+      const int j = row0 + i / L, c = i % L;
+      a.dst[(long long)j * L + c] = X[pidx(i)];
+    }
+  } else {
+    double s0 = 0.0, s1 = 0.0;
+    if (!skip) {
+      #pragma unroll
+      for (int u_ = 0; u_ < (kRows * L + 255) / 256; ++u_) {
+        const int i = threadIdx.x + u_ * 256;
+        if (i >= rows * L) continue;
+        const int j = row0 + i / L, c = i % L;
+        const long long p = a.off + (long long)(2 * j) * a.pitch + c;
+        const long long p1 = p + a.pitch;
+        if (a.mode == RFM_PRECOND) {
+          const float z0 = X[pidx(i)].x, z1 = X[pidx(i)].y;
+          a.out[p] = z0;
+          a.out[p1] = z1;
+          const float r0 = a.r[p], r1 = a.r[p1];
+          s0 += (double)r0 * z0 + (double)r1 * z1;
+          s1 += (double)r0 * r0 + (double)r1 * r1;
+        } else {
+          const float v0 = a.p[p], v1 = a.p[p1];
+          const float q0 = X[pidx(i)].x + a.tauc[p] * v0, q1 = X[pidx(i)].y + a.tauc[p1] * v1;
+          a.out[p] = q0;
+          a.out[p1] = q1;
+          s0 += (double)v0 * q0 + (double)v1 * q1;
+        }
+      }
+    }
+    __shared__ double sa[256], sb[256];
+    sa[threadIdx.x] = s0;
+    sb[threadIdx.x] = s1;
+    __syncthreads();
+    for (int w = 128; w >= 1; w >>= 1) {
+      if ((int)threadIdx.x < w) {
+        sa[threadIdx.x] += sa[threadIdx.x + w];
+        sb[threadIdx.x] += sb[threadIdx.x + w];
+      }
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+      a.part0[a.part_base + blockIdx.x] = sa[0];
+      a.part1[a.part_base + blockIdx.x] = sb[0];
+    }
+  }
+}
+
 // out (W x H) = transpose of in (H x W), 64 x 64 tiles through LDS
 __global__ __launch_bounds__(256) void k_transpose(const float2* __restrict__ in,
                                                    float2* __restrict__ out, int H, int W) {
   __shared__ float2 tile[64][65];
   const int bx = blockIdx.x * 64, by = blockIdx.y * 64;
   const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  #pragma unroll
   for (int r = ty; r < 64; r += 4) {
     const int gr = by + r, gc = bx + tx;
     if (gr < H && gc < W) tile[r][tx] = in[(long long)gr * W + gc];
   }
   __syncthreads();
+  #pragma unroll
   for (int r = ty; r < 64; r += 4) {
     const int gc = bx + r, gr = by + tx;   // output row = input column
     if (gc < W && gr < H) out[(long long)gc * H + gr] = tile[tx][r];
@@ -338,6 +561,37 @@ static hipError_t rows(const FftArgs& a, hipStream_t s) {
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
+}
+
+template <int L, int STAGE>
+static void launch_rfft_t(const RfftArgs& a, hipStream_t s) {
+  constexpr int kRows = L >= 4096 ? 1 : (4096 / L > 16 ? 16 : 4096 / L);
+  hipLaunchKernelGGL((k_rfft<L, STAGE>), dim3((a.nrows + kRows - 1) / kRows), dim3(256), 0, s, a);
+}
+
+template <int STAGE>
+static hipError_t launch_rfft(int L, const RfftArgs& a, hipStream_t s) {
+  switch (L) {
+    case 4: launch_rfft_t<4, STAGE>(a, s); break;
+    case 8: launch_rfft_t<8, STAGE>(a, s); break;
+    case 16: launch_rfft_t<16, STAGE>(a, s); break;
+    case 32: launch_rfft_t<32, STAGE>(a, s); break;
+    case 64: launch_rfft_t<64, STAGE>(a, s); break;
+    case 128: launch_rfft_t<128, STAGE>(a, s); break;
+    case 256: launch_rfft_t<256, STAGE>(a, s); break;
+    case 512: launch_rfft_t<512, STAGE>(a, s); break;
+    case 1024: launch_rfft_t<1024, STAGE>(a, s); break;
+    case 2048: launch_rfft_t<2048, STAGE>(a, s); break;
+    case 4096: launch_rfft_t<4096, STAGE>(a, s); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+// Number of partial-sum slots the RF_INV stage of an H x W instance writes.
+int rfft_partials(int H, int W) {
+  const int kRows = W >= 4096 ? 1 : (4096 / W > 16 ? 16 : 4096 / W);
+  return (H / 2 + kRows - 1) / kRows;
 }
 
 static FftArgs base_args(const LikCtx& lc, const LikInst& L) {
@@ -512,6 +766,51 @@ hipError_t fft_precondition(LikCtx& lc, hipStream_t s) {
   }
   return hipSuccess;
 }
+
+// Fast-CG transforms (RF_FWD, transpose, RF_FILT, transpose, RF_INV).
+// RFM_PRECOND, every circulant-preconditioned instance: z = M^{-1} r with r.z,
+// r.r partials (update = 1: first x += alpha p, r -= alpha q).  RFM_PRODUCT,
+// masked-DFT instances: p = z + beta p_in, q = (H^T H / xi + diag tau_c) p with
+// p.q partials.  Partials go to [tile0, tile0 + npart).
+hipError_t rfft_cg(LikCtx& lc, int mode, int update, hipStream_t s) {
+  for (DftPlan& d : lc.dft) {
+    const LikInst& L = lc.hinst[d.li];
+    if (L.precond != PRECOND_CIRCULANT) continue;
+    if (mode == RFM_PRODUCT && L.op != OP_DFT) continue;   // blur products: direct kernel
+    const int Wh = d.W / 2 + 1;
+    RfftArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.off = L.off; a.pitch = L.pitch; a.inv_xi = L.inv_xi; a.st = lc.d_st; a.inst = L.inst;
+    a.ld = Wh; a.mode = mode; a.update = update;
+    a.r = lc.planes[LP_R]; a.z = lc.planes[LP_Z]; a.tauc = lc.planes[LP_TAUC];
+    a.p_in = lc.planes[lc.pcur ? LP_P1 : LP_P0];     // same ping-pong as the CG kernels
+    a.p = lc.planes[lc.pcur ? LP_P0 : LP_P1];
+    a.x = lc.planes[LP_X]; a.q = lc.planes[LP_Q];
+    RfftArgs f = a;
+    f.dst = d.A; f.tw = d.twW; f.nrows = d.H / 2; f.logL = d.logW;
+    hipError_t e = launch_rfft<RF_FWD>(d.W, f, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_transpose, dim3((Wh + 63) / 64, (d.H + 63) / 64), dim3(256), 0, s, d.A, d.B,
+                       d.H, Wh);
+    RfftArgs g = a;
+    g.src = d.B; g.dst = d.B; g.tw = d.twH; g.nrows = Wh; g.logL = d.logH; g.specT = d.specT;
+    g.scale = (float)(1.0 / ((double)d.H * d.W));
+    if ((e = launch_rfft<RF_FILT>(d.H, g, s)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_transpose, dim3((d.H + 63) / 64, (Wh + 63) / 64), dim3(256), 0, s, d.B, d.A,
+                       Wh, d.H);
+    RfftArgs v = a;
+    v.src = d.A; v.tw = d.twW; v.nrows = d.H / 2; v.logL = d.logW;
+    v.out = lc.planes[mode == RFM_PRECOND ? LP_Z : LP_Q];
+    v.part0 = lc.part0; v.part1 = lc.part1; v.part_base = L.tile0;
+    if ((e = launch_rfft<RF_INV>(d.W, v, s)) != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t rfft_precondition(LikCtx& lc, int update, hipStream_t s) {
+  return rfft_cg(lc, RFM_PRECOND, update, s);
+}
+hipError_t rfft_product(LikCtx& lc, hipStream_t s) { return rfft_cg(lc, RFM_PRODUCT, 0, s); }
 
 void dft_destroy(LikCtx& lc) { lc.dft.clear(); }
 

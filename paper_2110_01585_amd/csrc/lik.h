@@ -50,6 +50,8 @@ struct LikInst {
   double cg_tol2;            // squared relative residual tolerance
   int cg_max_iters;
   int precond;               // PRECOND_JACOBI or PRECOND_CIRCULANT
+  int npart;                 // partial-sum slots of the real-transform passes (fast CG)
+  int fin_count[5];          // partial sums each finalisation stage reduces (set on the host)
 };
 
 enum {
@@ -145,6 +147,7 @@ struct LikCtx {
   const InstDev* d_idev = nullptr;
   float* ypix = nullptr;
   int pcur = 0;                      // which p plane holds the current search direction
+  bool fast = false;                 // every instance circulant: CG products and preconditioner by real FFTs
   int max_iters = kCgMaxIters;       // largest per-instance CG cap
   std::vector<InstState> hst;        // staging for convergence polls
   int n_all = 0;

@@ -123,7 +123,10 @@ __global__ __launch_bounds__(256) void k_lik_fin(LikArgs A, int stage) {
   const LikInst L = A.inst[blockIdx.x];
   InstState& st = A.st[L.inst];
   double s0 = 0.0, s1 = 0.0;
-  for (int t = threadIdx.x; t < L.ntiles; t += blockDim.x) {
+  // number of partials this stage sums (one per tile, or one per row block of the
+  // real-transform passes), chosen on the host
+  const int cnt = A.inst[blockIdx.x].fin_count[stage];
+  for (int t = threadIdx.x; t < cnt; t += blockDim.x) {
     s0 += A.part0[L.tile0 + t];
     s1 += A.part1[L.tile0 + t];
   }
@@ -205,7 +208,9 @@ __device__ __forceinline__ float direction(const LikArgs& A, const LikInst& L, c
   return st.cg_it == 0 ? z : z + (float)st.cg_beta * A.p_in[p];
 }
 
-template <int MODE, bool SEP>
+// General (non-separable) taps: H then H^T with the original taps (kh x kw,
+// centred at (kh/2, kw/2)) as two 2-D passes through LDS.
+template <int MODE>
 __global__ __launch_bounds__(256) void k_apply(LikArgs A) {
   constexpr int EWMAX = kLikTW + 2 * kMaxRadius;
   constexpr int EHMAX = kLikTH + 2 * kMaxRadius;
@@ -223,7 +228,6 @@ __global__ __launch_bounds__(256) void k_apply(LikArgs A) {
   const TileXY t = lik_tile(td, L);
   const int Rr = L.Rr, Rc = L.Rc;
   const int EH = kLikTH + 2 * Rr, EW = kLikTW + 2 * Rc;
-  // stage v over the tile and its halo (periodic wrap); write p for the interior
   for (int i = threadIdx.x; i < EH * EW; i += blockDim.x) {
     const int er = i / EW, ec = i % EW;
     const int gr = wrapi(t.r0 - Rr + er, L.H), gc = wrapi(t.c0 - Rc + ec, L.W);
@@ -237,61 +241,111 @@ __global__ __launch_bounds__(256) void k_apply(LikArgs A) {
     }
   }
   __syncthreads();
-  const float* tp = A.taps;
-  if (SEP) {
-    // rows of the combined kernel along columns, then along rows
-    const float* gc = tp + L.gc_off;   // 2 Rc + 1 taps
-    const float* gr = tp + L.gr_off;   // 2 Rr + 1 taps
-    for (int i = threadIdx.x; i < EH * kLikTW; i += blockDim.x) {
-      const int er = i / kLikTW, oc = i % kLikTW;
-      const float* row = P + er * EW + oc;
-      float acc = 0.f;
-      for (int d = 0; d <= 2 * Rc; ++d) acc += gc[d] * row[d];
-      T[er * kLikTW + oc] = acc;
-    }
-    __syncthreads();
-    double dot = 0.0;
-    for (int i = threadIdx.x; i < kLikTH * kLikTW; i += blockDim.x) {
-      const int orow = i / kLikTW, oc = i % kLikTW;
-      if (t.r0 + orow >= L.H || t.c0 + oc >= L.W) continue;
-      float acc = 0.f;
-      for (int d = 0; d <= 2 * Rr; ++d) acc += gr[d] * T[(orow + d) * kLikTW + oc];
-      const long long p = L.off + (long long)(t.r0 + orow) * L.pitch + (t.c0 + oc);
-      const float v = P[(orow + Rr) * EW + oc + Rc];
-      const float qv = acc * L.inv_xi + A.tauc[p] * v;
-      A.q[p] = qv;
-      dot += (double)v * (double)qv;
-    }
-    block_sum2(dot, 0.0, &A.part0[tile], &A.part1[tile]);
-  } else {
-    // H then H^T with the original taps (kh x kw, centred at (kh/2, kw/2))
-    const float* k = tp + L.k_off;
-    const int ch = L.kh / 2, cw = L.kw / 2;
-    const int TH = kLikTH + 2 * ch, TW = kLikTW + 2 * cw;
-    for (int i = threadIdx.x; i < TH * TW; i += blockDim.x) {
-      const int tr = i / TW, tc = i % TW;
-      float acc = 0.f;
-      for (int a = 0; a < L.kh; ++a)
-        for (int b2 = 0; b2 < L.kw; ++b2)
-          acc += k[a * L.kw + b2] * P[(tr - a + 2 * ch) * EW + (tc - b2 + 2 * cw)];
-      T[tr * TW + tc] = acc;
-    }
-    __syncthreads();
-    double dot = 0.0;
-    for (int i = threadIdx.x; i < kLikTH * kLikTW; i += blockDim.x) {
-      const int orow = i / kLikTW, oc = i % kLikTW;
-      if (t.r0 + orow >= L.H || t.c0 + oc >= L.W) continue;
-      float acc = 0.f;
-      for (int a = 0; a < L.kh; ++a)
-        for (int b2 = 0; b2 < L.kw; ++b2) acc += k[a * L.kw + b2] * T[(orow + a) * TW + (oc + b2)];
-      const long long p = L.off + (long long)(t.r0 + orow) * L.pitch + (t.c0 + oc);
-      const float v = P[(orow + Rr) * EW + oc + Rc];
-      const float qv = acc * L.inv_xi + A.tauc[p] * v;
-      A.q[p] = qv;
-      dot += (double)v * (double)qv;
-    }
-    block_sum2(dot, 0.0, &A.part0[tile], &A.part1[tile]);
+  const float* k = A.taps + L.k_off;
+  const int ch = L.kh / 2, cw = L.kw / 2;
+  const int TH = kLikTH + 2 * ch, TW = kLikTW + 2 * cw;
+  for (int i = threadIdx.x; i < TH * TW; i += blockDim.x) {
+    const int tr = i / TW, tc = i % TW;
+    float acc = 0.f;
+    for (int a = 0; a < L.kh; ++a)
+      for (int b2 = 0; b2 < L.kw; ++b2)
+        acc += k[a * L.kw + b2] * P[(tr - a + 2 * ch) * EW + (tc - b2 + 2 * cw)];
+    T[tr * TW + tc] = acc;
   }
+  __syncthreads();
+  double dot = 0.0;
+  for (int i = threadIdx.x; i < kLikTH * kLikTW; i += blockDim.x) {
+    const int orow = i / kLikTW, oc = i % kLikTW;
+    if (t.r0 + orow >= L.H || t.c0 + oc >= L.W) continue;
+    float acc = 0.f;
+    for (int a = 0; a < L.kh; ++a)
+      for (int b2 = 0; b2 < L.kw; ++b2) acc += k[a * L.kw + b2] * T[(orow + a) * TW + (oc + b2)];
+    const long long p = L.off + (long long)(t.r0 + orow) * L.pitch + (t.c0 + oc);
+    const float v = P[(orow + Rr) * EW + oc + Rc];
+    const float qv = acc * L.inv_xi + A.tauc[p] * v;
+    A.q[p] = qv;
+    dot += (double)v * (double)qv;
+  }
+  block_sum2(dot, 0.0, &A.part0[tile], &A.part1[tile]);
+}
+
+// Separable taps (rank one, e.g. Gaussian): H^T H is the separable periodic
+// convolution with the autocorrelations g_r (rows) and g_c (columns) of the two
+// factors, radius RI <= RT each.  RT is a compile-time bound (taps beyond an
+// instance's own radius are zero), so the tile geometry and index arithmetic are
+// constants: the 64 x 32 output tile plus an RT halo is staged in LDS (periodic
+// wrap only on border tiles), filtered along rows into a second LDS array, then
+// along columns.
+template <int RT, int MODE>
+__global__ __launch_bounds__(256) void k_hth_sep(LikArgs A) {
+  constexpr int EW = kLikTW + 2 * RT, EH = kLikTH + 2 * RT, NT = 2 * RT + 1;
+  __shared__ float P[EH * EW];
+  __shared__ float T[EH * kLikTW];
+  __shared__ float gr[NT], gc[NT];
+  const int tile = blockIdx.x;
+  const int4 td = A.tiles[tile];
+  const LikInst L = A.inst[td.x];
+  const InstState& st = A.st[L.inst];
+  if (L.op != OP_BLUR) return;   // masked-DFT tiles: the FFT path writes q and partials
+  if (st.cg_done) {
+    block_sum2(0.0, 0.0, &A.part0[tile], &A.part1[tile]);
+    return;
+  }
+  if (threadIdx.x < NT) {
+    const int d = (int)threadIdx.x - RT;       // offset -RT..RT
+    gr[threadIdx.x] = (d >= -L.Rr && d <= L.Rr) ? A.taps[L.gr_off + d + L.Rr] : 0.f;
+    gc[threadIdx.x] = (d >= -L.Rc && d <= L.Rc) ? A.taps[L.gc_off + d + L.Rc] : 0.f;
+  }
+  const TileXY t = lik_tile(td, L);
+  const bool inner = t.r0 >= RT && t.c0 >= RT && t.r0 + kLikTH + RT <= L.H && t.c0 + kLikTW + RT <= L.W;
+  const bool first = st.cg_it == 0;
+  const float beta = (float)st.cg_beta;
+  for (int i = threadIdx.x; i < EH * EW; i += 256) {
+    const int er = i / EW, ec = i - (i / EW) * EW;
+    int gy = t.r0 - RT + er, gx = t.c0 - RT + ec;
+    if (!inner) {   // periodic wrap; images smaller than the halo wrap more than once
+      gy = wrapi(gy, L.H);
+      gx = wrapi(gx, L.W);
+    }
+    const long long p = L.off + (long long)gy * L.pitch + gx;
+    float v;
+    if (MODE == 0) {
+      v = A.x[p];
+    } else {
+      const float z = A.z[p];
+      v = first ? z : z + beta * A.p_in[p];
+      const int lr = er - RT, lc = ec - RT;
+      if (lr >= 0 && lr < kLikTH && lc >= 0 && lc < kLikTW && t.r0 + lr < L.H && t.c0 + lc < L.W)
+        A.p_out[p] = v;
+    }
+    P[i] = v;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < EH * kLikTW; i += 256) {
+    const int er = i / kLikTW, oc = i % kLikTW;
+    const float* row = P + er * EW + oc;
+    float acc = 0.f;
+#pragma unroll
+    for (int d = 0; d < NT; ++d) acc += gc[d] * row[d];
+    T[i] = acc;
+  }
+  __syncthreads();
+  double dot = 0.0;
+#pragma unroll
+  for (int u = 0; u < kLikTH * kLikTW / 256; ++u) {
+    const int i = threadIdx.x + 256 * u;
+    const int orow = i / kLikTW, oc = i % kLikTW;
+    if (t.r0 + orow >= L.H || t.c0 + oc >= L.W) continue;
+    float acc = 0.f;
+#pragma unroll
+    for (int d = 0; d < NT; ++d) acc += gr[d] * T[(orow + d) * kLikTW + oc];
+    const long long p = L.off + (long long)(t.r0 + orow) * L.pitch + (t.c0 + oc);
+    const float v = P[(orow + RT) * EW + oc + RT];
+    const float qv = acc * L.inv_xi + A.tauc[p] * v;
+    A.q[p] = qv;
+    dot += (double)v * (double)qv;
+  }
+  block_sum2(dot, 0.0, &A.part0[tile], &A.part1[tile]);
 }
 
 // ---------------------------------------------------------------------------
@@ -502,6 +556,7 @@ hipError_t lik_create(LikCtx& lc, const LikInstInfo* li, int n, char* ws, const 
     d.cg_tol2 = I.cg_tol * I.cg_tol;
     d.cg_max_iters = I.cg_max_iters;
     d.precond = lik_precond(I.op, I.H, I.W, I.precond_req);
+    d.npart = d.precond == PRECOND_CIRCULANT ? rfft_partials(I.H, I.W) : d.ntiles;
     lc.max_iters = std::max(lc.max_iters, I.cg_max_iters);
     const int li_idx = (int)lc.hinst.size();
     for (int yy = 0; yy < ty; ++yy)
@@ -557,6 +612,21 @@ hipError_t lik_create(LikCtx& lc, const LikInstInfo* li, int n, char* ws, const 
     lc.hinst.push_back(d);
     lc.inst_of.push_back(i);
   }
+  lc.fast = !lc.hinst.empty();
+  for (const LikInst& d : lc.hinst) {
+    lc.fast = lc.fast && d.precond == PRECOND_CIRCULANT && d.npart <= d.ntiles;
+  }
+  // partial counts per finalisation stage: r.z / r.r (and p.q of masked-DFT
+  // instances) come from the real-transform passes in the fast CG, everything
+  // else from one partial per tile
+  for (LikInst& d : lc.hinst) {
+    const int tr = lc.fast ? d.npart : d.ntiles;
+    d.fin_count[FIN_PREP] = d.ntiles;
+    d.fin_count[FIN_SPEC] = d.ntiles;
+    d.fin_count[FIN_INIT] = tr;
+    d.fin_count[FIN_ALPHA] = (lc.fast && d.op == OP_DFT) ? d.npart : d.ntiles;
+    d.fin_count[FIN_BETA] = tr;
+  }
   if ((int)taps.size() > L.ntaps || (int)tiles.size() != L.ntiles) {
     err = "likelihood layout mismatch (taps or tiles)";
     return hipErrorInvalidValue;
@@ -607,13 +677,35 @@ static hipError_t set_x_invalid(LikCtx& lc, hipStream_t s) {
   return hipGetLastError();
 }
 
-static hipError_t launch_apply(LikCtx& lc, int mode, hipStream_t s) {
+// q = A v on every blur tile (v = x for mode 0, the new direction for mode 1)
+static hipError_t launch_apply_blur(LikCtx& lc, int mode, hipStream_t s) {
   const LikArgs A = make_args(lc);
-  bool all_sep = true, any_dft = false;
+  bool any_blur = false, all_sep = true;
+  int rmax = 0;
   for (const LikInst& d : lc.hinst) {
-    if (d.op == OP_BLUR && !d.sep) all_sep = false;
-    if (d.op == OP_DFT) any_dft = true;
+    if (d.op != OP_BLUR) continue;
+    any_blur = true;
+    all_sep = all_sep && d.sep;
+    rmax = std::max(rmax, std::max(d.Rr, d.Rc));
   }
+  if (!any_blur) return hipSuccess;
+  const dim3 g(lc.ntiles), b(256);
+  if (!all_sep) {
+    if (mode == 0) hipLaunchKernelGGL((k_apply<0>), g, b, 0, s, A);
+    else hipLaunchKernelGGL((k_apply<1>), g, b, 0, s, A);
+  } else if (rmax <= 8) {
+    if (mode == 0) hipLaunchKernelGGL((k_hth_sep<8, 0>), g, b, 0, s, A);
+    else hipLaunchKernelGGL((k_hth_sep<8, 1>), g, b, 0, s, A);
+  } else {
+    if (mode == 0) hipLaunchKernelGGL((k_hth_sep<kMaxRadius, 0>), g, b, 0, s, A);
+    else hipLaunchKernelGGL((k_hth_sep<kMaxRadius, 1>), g, b, 0, s, A);
+  }
+  return hipGetLastError();
+}
+
+static hipError_t launch_apply(LikCtx& lc, int mode, hipStream_t s) {
+  bool any_dft = false;
+  for (const LikInst& d : lc.hinst) any_dft = any_dft || d.op == OP_DFT;
   int i0 = 0, i1 = 0;
   const bool tm = lc.timing && lc.ev_used + 2 <= 16384;
   if (tm) {
@@ -632,17 +724,8 @@ static hipError_t launch_apply(LikCtx& lc, int mode, hipStream_t s) {
     hipError_t e = dft_apply(lc, mode, s);
     if (e != hipSuccess) return e;
   }
-  bool any_blur = false;
-  for (const LikInst& d : lc.hinst) any_blur = any_blur || d.op == OP_BLUR;
-  if (any_blur) {
-    if (mode == 0) {
-      if (all_sep) hipLaunchKernelGGL((k_apply<0, true>), dim3(lc.ntiles), dim3(256), 0, s, A);
-      else hipLaunchKernelGGL((k_apply<0, false>), dim3(lc.ntiles), dim3(256), 0, s, A);
-    } else {
-      if (all_sep) hipLaunchKernelGGL((k_apply<1, true>), dim3(lc.ntiles), dim3(256), 0, s, A);
-      else hipLaunchKernelGGL((k_apply<1, false>), dim3(lc.ntiles), dim3(256), 0, s, A);
-    }
-  }
+  hipError_t e = launch_apply_blur(lc, mode, s);
+  if (e != hipSuccess) return e;
   if (tm) {
     hipEventRecord(lc.ev[i1], s);
     lc.ev_apply.emplace_back(i0, i1);
@@ -666,8 +749,12 @@ hipError_t lik_head(LikCtx& lc, float2* const S[5], hipStream_t s) {
   if ((e = fin(lc, FIN_SPEC, s)) != hipSuccess) return e;
   if ((e = launch_apply(lc, 0, s)) != hipSuccess) return e;
   hipLaunchKernelGGL(k_cg_init, g, b, 0, s, make_args(lc));
-  if ((e = fft_precondition(lc, s)) != hipSuccess) return e;
-  hipLaunchKernelGGL(k_precond_dot, g, b, 0, s, make_args(lc));
+  if (lc.fast) {
+    if ((e = rfft_precondition(lc, 0, s)) != hipSuccess) return e;
+  } else {
+    if ((e = fft_precondition(lc, s)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_precond_dot, g, b, 0, s, make_args(lc));
+  }
   return fin(lc, FIN_INIT, s);
 }
 
@@ -675,6 +762,19 @@ hipError_t lik_iterations(LikCtx& lc, int n, hipStream_t s) {
   if (lc.nlik == 0) return hipSuccess;
   hipError_t e;
   const dim3 g(lc.ntiles), b(256);
+  if (lc.fast) {
+    for (int it = 0; it < n; ++it) {
+      // p_out = z + beta p_in and q = A p_out: blur tiles by the direct
+      // H^T H kernel, masked-DFT instances by the real transform
+      if ((e = launch_apply_blur(lc, 1, s)) != hipSuccess) return e;
+      if ((e = rfft_product(lc, s)) != hipSuccess) return e;
+      if ((e = fin(lc, FIN_ALPHA, s)) != hipSuccess) return e;
+      if ((e = rfft_precondition(lc, 1, s)) != hipSuccess) return e;   // with x, r update
+      if ((e = fin(lc, FIN_BETA, s)) != hipSuccess) return e;
+      lc.pcur ^= 1;
+    }
+    return hipGetLastError();
+  }
   for (int it = 0; it < n; ++it) {
     if ((e = launch_apply(lc, 1, s)) != hipSuccess) return e;   // p_out = z + beta p_in, q = A p_out
     if ((e = fin(lc, FIN_ALPHA, s)) != hipSuccess) return e;
