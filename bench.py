@@ -263,11 +263,11 @@ def converge(ctx, args, em, p, y, dev, torch):
     e0.record()
     net.infer(y, p.xi, mu_hat, var_hat)
     e1.record()
-    wrc = ctx.ep_tv_init_warm([mu_hat], [var_hat], meta["lambda_scale"])
+    wrc = ctx.ep_tv_init_warm([mu_hat], [var_hat], meta["lambda_scale"], meta.get("lambda_power", 1.0))
     rc, st_w = ctx.ep_tv_solve(args.max_sweeps, args.tol, em, [mu_w], [var_w])
     torch.cuda.synchronize()
     t5 = time.perf_counter()
-    ctx.ep_tv_init_warm([mu_hat], [var_hat], meta["lambda_scale"])   # untimed: report lambda_0
+    ctx.ep_tv_init_warm([mu_hat], [var_hat], meta["lambda_scale"], meta.get("lambda_power", 1.0))  # untimed
     conv["lambda0_warm"] = ctx.ep_tv_get_stats()[0]["lambda"]
     conv.update({"s_to_converged_warm": round(t5 - t4, 4), "sweeps_warm": st_w[0]["sweeps"],
                  "converged_warm": st_w[0]["converged"], "lambda_warm": st_w[0]["lambda"],

@@ -148,16 +148,18 @@ int ep_tv_init_cold(ep_tv_ctx* ctx);
  * classes covering the pixel; for the other operators precision and eta are
  * split equally over the likelihood site and the covering classes.  Uncovered
  * classes stay (0, 0).  The first sweep then updates the likelihood site too.
- * lambda_scale > 0 sets lambda_0 = lambda_scale * N / a_x, where a_x is the sum
- * over all pairs of E|x_i - x_j| under the prediction (option 1 of the
- * approximations of a_0, Sec. IV-B; lambda_scale = 1 is that option as is);
- * lambda_scale <= 0 keeps lambda0 of the problem descriptor.
+ * lambda_scale > 0 sets lambda_0 = lambda_scale * (N / a_x)^lambda_power, where
+ * a_x is the sum over all pairs of E|x_i - x_j| under the prediction (option 1
+ * of the approximations of a_0, Sec. IV-B; lambda_scale = lambda_power = 1 is
+ * that option as is; other values correct its bias, e.g. as calibrated on
+ * training data); lambda_scale <= 0 keeps lambda0 of the problem descriptor.
+ * lambda_power must be > 0.
  * d_mu_hat, d_var_hat: host arrays of n_problems device pointers, height*width
  * floats each.  An instance whose prediction holds a non-finite value or a
  * variance <= 0 starts cold instead, and the call returns
  * EP_TV_W_WARM_FALLBACK.  Synchronises the stream. */
 int ep_tv_init_warm(ep_tv_ctx* ctx, const float* const* d_mu_hat, const float* const* d_var_hat,
-                    double lambda_scale);
+                    double lambda_scale, double lambda_power);
 
 /* Run n_sweeps sweeps of Algorithm 1 on every active instance; with em_enabled,
  * lambda <- N / a_bar_u after every sweep (the fast EP-EM of Algorithm 2, one EP

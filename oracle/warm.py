@@ -47,12 +47,13 @@ def a_x(pb: ep.EPProblem, mu, v):
     return tot
 
 
-def lambda_option1(pb: ep.EPProblem, mu, v):
+def lambda_option1(pb: ep.EPProblem, mu, v, scale=1.0, power=1.0):
+    """scale * (N / a_x)^power; scale = power = 1 is option 1 as is."""
     a = a_x(pb, mu, v)
-    return pb.N / a if a > 0.0 else pb.lam0
+    return scale * (pb.N / a) ** power if a > 0.0 else pb.lam0
 
 
-def init_warm(pb: ep.EPProblem, mu_hat, v_hat, set_lambda=True):
+def init_warm(pb: ep.EPProblem, mu_hat, v_hat, set_lambda=True, scale=1.0, power=1.0):
     """EPState with the warm sites, or None when the prediction is unusable."""
     mu = np.asarray(mu_hat, np.float64).ravel()
     v = np.asarray(v_hat, np.float64).ravel()
@@ -81,5 +82,5 @@ def init_warm(pb: ep.EPProblem, mu_hat, v_hat, set_lambda=True):
         for k in range(4):
             tau[k + 1] = np.where(cov[k], prec / n, 0.0)
             eta[k + 1] = np.where(cov[k], mu * prec / n, 0.0)
-    lam = lambda_option1(pb, mu, v) if set_lambda else pb.lam0
+    lam = lambda_option1(pb, mu, v, scale, power) if set_lambda else pb.lam0
     return ep.EPState(tau=tau, eta=eta, lam=lam, warm=True)

@@ -92,7 +92,7 @@ SIGNATURES = {
     "ep_tv_tilted_moments": (ctypes.c_int, [ctypes.c_int32, _P, _P, ctypes.c_float, _P, _P, _P, _P]),
     "ep_tv_set_timing": (ctypes.c_int, [_P, ctypes.c_int32]),
     "ep_tv_get_timing": (ctypes.c_int, [_P, ctypes.POINTER(EpTvTiming)]),
-    "ep_tv_init_warm": (ctypes.c_int, [_P, _FPP, _FPP, ctypes.c_double]),
+    "ep_tv_init_warm": (ctypes.c_int, [_P, _FPP, _FPP, ctypes.c_double, ctypes.c_double]),
     "ep_tv_set_option": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int64]),
     "ep_tv_get_option": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64)]),
     "ep_tv_autotune": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.POINTER(EpTvTuneResult)]),

@@ -203,9 +203,11 @@ class Context:
                 "lik_updates": t.lik_updates, "apply_ms": t.apply_ms,
                 "apply_launches": t.apply_launches}
 
-    def ep_tv_init_warm(self, mu_hats, var_hats, lambda_scale: float = 1.0) -> int:
+    def ep_tv_init_warm(self, mu_hats, var_hats, lambda_scale: float = 1.0,
+                        lambda_power: float = 1.0) -> int:
         """Returns the status (EP_TV_OK or EP_TV_W_WARM_FALLBACK)."""
-        rc = N.lib().ep_tv_init_warm(self.handle, _ptrs(mu_hats), _ptrs(var_hats), float(lambda_scale))
+        rc = N.lib().ep_tv_init_warm(self.handle, _ptrs(mu_hats), _ptrs(var_hats), float(lambda_scale),
+                                     float(lambda_power))
         return self._check(rc, "init_warm", ok=(0, N.EP_TV_W_WARM_FALLBACK))
 
     def ep_tv_set_option(self, option: int, value: int):

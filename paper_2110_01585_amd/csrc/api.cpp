@@ -480,8 +480,10 @@ int ep_tv_init_cold(ep_tv_ctx* c) {
 }
 
 int ep_tv_init_warm(ep_tv_ctx* c, const float* const* d_mu_hat, const float* const* d_var_hat,
-                    double lambda_scale) {
-  if (!c || !d_mu_hat || !d_var_hat || !std::isfinite(lambda_scale)) return EP_TV_E_ARG;
+                    double lambda_scale, double lambda_power) {
+  if (!c || !d_mu_hat || !d_var_hat || !std::isfinite(lambda_scale) || !std::isfinite(lambda_power) ||
+      !(lambda_power > 0.0))
+    return EP_TV_E_ARG;
   for (int i = 0; i < c->n; ++i)
     if (!d_mu_hat[i] || !d_var_hat[i]) return fail(c, EP_TV_E_ARG, "null prediction pointer");
   int rc = ep_tv_init_cold(c);
@@ -491,8 +493,8 @@ int ep_tv_init_warm(ep_tv_ctx* c, const float* const* d_mu_hat, const float* con
   rc = set_tab(c, const_cast<float* const*>(d_var_hat), c->d_tab1, c->tab_host1);
   if (rc) return rc;
   HIPCHK(c, launch_init_warm(cur_sites(c).S, c->ypix, c->d_inst, c->d_st, c->n, c->d_tiles, c->ntiles,
-                             c->d_tab0, c->d_tab1, lambda_scale, c->sa.part_eabs, c->sa.part_flags,
-                             c->stream));
+                             c->d_tab0, c->d_tab1, lambda_scale, lambda_power, c->sa.part_eabs,
+                             c->sa.part_flags, c->stream));
   rc = pull_states(c);
   if (rc) return rc;
   int rejected = 0;

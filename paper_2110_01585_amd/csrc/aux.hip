@@ -76,7 +76,7 @@ hipError_t launch_init_cold(float2* const S[5], const float* y_pix, const InstDe
 // covering colour classes; otherwise precision and eta are split equally over
 // the likelihood site and the covering classes.  lambda_0 follows option 1 of
 // the EM approximations of a_0 (Sec. IV-B): a_x = sum over pairs of E|x_i - x_j|
-// under the prediction (a folded-normal mean), lambda_0 = scale * N / a_x.
+// under the prediction (a folded-normal mean), lambda_0 = scale * (N / a_x)^power.
 __device__ __forceinline__ double folded_mean(double d, double var) {
   const double sd = sqrt(var);
   return d * erf(d / (sd * 1.4142135623730951)) + sd * 0.7978845608028654 * exp(-d * d / (2.0 * var));
@@ -147,7 +147,8 @@ __global__ __launch_bounds__(256) void k_warm_scan(const InstDev* __restrict__ i
 __global__ __launch_bounds__(256) void k_warm_fin(const InstDev* __restrict__ inst,
                                                   InstState* __restrict__ st,
                                                   const double* __restrict__ part_a,
-                                                  const unsigned* __restrict__ part_f, double scale) {
+                                                  const unsigned* __restrict__ part_f, double scale,
+                                                  double power) {
   const InstDev I = inst[blockIdx.x];
   InstState& S = st[blockIdx.x];
   __shared__ double sa[256];
@@ -177,7 +178,7 @@ __global__ __launch_bounds__(256) void k_warm_fin(const InstDev* __restrict__ in
   S.warm = 1;
   S.warm_ok = 1;
   if (scale > 0.0 && sa[0] > 0.0) {
-    S.lam = scale * (double)I.npix / sa[0];
+    S.lam = scale * pow((double)I.npix / sa[0], power);
     S.lam_prev = S.lam;
   }
 }
@@ -231,13 +232,15 @@ __global__ __launch_bounds__(256) void k_warm_write(SitePtrs sp, const float* __
 hipError_t launch_init_warm(float2* const S[5], const float* y_pix, const InstDev* inst,
                             InstState* st, int n, const int4* tiles, int ntiles,
                             const float* const* mu_tab, const float* const* var_tab,
-                            double lambda_scale, double* part_a, unsigned* part_f, hipStream_t s) {
+                            double lambda_scale, double lambda_power, double* part_a,
+                            unsigned* part_f, hipStream_t s) {
   if (ntiles == 0) return hipSuccess;
   SitePtrs sp;
   for (int k = 0; k < 5; ++k) sp.S[k] = S[k];
   hipLaunchKernelGGL(k_warm_scan, dim3(ntiles), dim3(256), 0, s, inst, tiles, mu_tab, var_tab, part_a,
                      part_f);
-  hipLaunchKernelGGL(k_warm_fin, dim3(n), dim3(256), 0, s, inst, st, part_a, part_f, lambda_scale);
+  hipLaunchKernelGGL(k_warm_fin, dim3(n), dim3(256), 0, s, inst, st, part_a, part_f, lambda_scale,
+                     lambda_power);
   hipLaunchKernelGGL(k_warm_write, dim3(ntiles), dim3(256), 0, s, sp, y_pix, inst, st, tiles, mu_tab,
                      var_tab);
   return hipGetLastError();

@@ -95,12 +95,13 @@ hipError_t launch_sites_io(float2* const S[5], const InstDev* inst, const int4* 
 hipError_t launch_yrange(const float* y_pix, const InstDev* inst, InstState* st, int n,
                          hipStream_t s);
 // Warm start from predicted marginals (device pointer tables, one per instance):
-// validates the prediction, computes lambda_0 = scale * N / a_x (a_x: sum over
-// pairs of the folded-normal mean of x_i - x_j under the prediction) when
+// validates the prediction, computes lambda_0 = scale * (N / a_x)^power (a_x: sum
+// over pairs of the folded-normal mean of x_i - x_j under the prediction) when
 // scale > 0, and overwrites the sites of every accepted instance.
 hipError_t launch_init_warm(float2* const S[5], const float* y_pix, const InstDev* inst,
                             InstState* st, int n, const int4* tiles, int ntiles,
                             const float* const* mu_tab, const float* const* var_tab,
-                            double lambda_scale, double* part_a, unsigned* part_f, hipStream_t s);
+                            double lambda_scale, double lambda_power, double* part_a,
+                            unsigned* part_f, hipStream_t s);
 
 }  // namespace eptv

@@ -4,14 +4,17 @@
         [--out paper_2110_01585_amd/weights/warmstart_deconv_sb2_s001]
 
 1. Training set: seeded 256 x 256 deconvolution instances (9 x 9 Gaussian blur,
-   sigma_b = 2, periodic; noise sigma = 0.01; piecewise-constant images), each
+   sigma_b = 2, periodic; noise sigma = 0.01; piecewise-constant images drawn
+   as windows of 256^2 .. 2048^2-scale images, synthetic.config4_train_mixed), each
    solved to convergence by the batched GPU EP-EM solver (graph launches, Jacobi
    CG) from a cold start.  Targets: the converged marginal means and variances.
 2. Training: the network's own GPU kernels (bfloat16 MFMA forward / backward,
    Adam), batches of 16 images, cosine learning-rate decay.
-3. Calibration of lambda_0: option 1 (N / a_x under the prediction) is biased
-   low because it treats the pixels as independent; the median over training
-   instances of lambda* / lambda_option1(prediction) becomes `lambda_scale`.
+3. Calibration of lambda_0: option 1 (lambda_1 = N / a_x under the prediction)
+   is biased low because it treats the pixels as independent, by a factor that
+   drifts with the image scale; lambda_0 = kappa * lambda_1^rho is fitted to the
+   converged lambda* of training instances (least squares in log space) and
+   stored as `lambda_scale` = kappa, `lambda_power` = rho.
 4. Held-out check: sweeps to convergence, warm versus cold.
 
 Everything runs on the GPU except the image generation (NumPy, a process pool).
@@ -41,8 +44,8 @@ def log(msg):
 
 
 def _gen(i, size):
-    p = syn.config4_train(i, size=size)
-    return p.y.astype(np.float32), p.taps, p.xi
+    p = syn.config4_train_mixed(i, size=size)
+    return p.y.astype(np.float32), p.taps, p.xi, p.boundary, p.meta.get("scale", size)
 
 
 def generate(ids, size, workers):
@@ -50,7 +53,8 @@ def generate(ids, size, workers):
         return list(ex.map(_gen, ids, [size] * len(ids), chunksize=16))
 
 
-def solve_batch(torch, probs, y_dev, mu_out, v_out, max_sweeps, tol, warm=None, lam_scale=1.0):
+def solve_batch(torch, probs, y_dev, mu_out, v_out, max_sweeps, tol, warm=None, lam_scale=1.0,
+                lam_power=1.0):
     """Solve a batch of instances (list of synthetic.Problem-like specs) on the GPU."""
     from paper_2110_01585_amd import Context, spec_from_synthetic
     from paper_2110_01585_amd import _native as N
@@ -58,7 +62,7 @@ def solve_batch(torch, probs, y_dev, mu_out, v_out, max_sweeps, tol, warm=None, 
     ctx.ep_tv_set_option(N.OPT_GRAPH, 1)
     ctx.ep_tv_set_observation(list(y_dev))
     if warm is not None:
-        ctx.ep_tv_init_warm(warm[0], warm[1], lam_scale)
+        ctx.ep_tv_init_warm(warm[0], warm[1], lam_scale, lam_power)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     rc, st = ctx.ep_tv_solve(max_sweeps, tol, True, list(mu_out), list(v_out))
@@ -71,10 +75,11 @@ def solve_batch(torch, probs, y_dev, mu_out, v_out, max_sweeps, tol, warm=None, 
 class _Spec:
     """The fields spec_from_synthetic reads, for a generated instance."""
 
-    def __init__(self, y, taps, xi, size):
+    def __init__(self, y, taps, xi, size, boundary, scale):
         self.shape = (size, size)
         self.op = "blur"
-        self.boundary = "periodic"
+        self.boundary = boundary
+        self.scale = scale
         self.xi = xi
         self.lam0 = 1.0
         self.damping = 0.5
@@ -107,7 +112,7 @@ def main(argv=None):
     # forked before this process touches the GPU), then solve with the batched
     # EP solver
     gen = generate(list(range(n_all)), S, args.workers)
-    specs = [_Spec(y, taps, xi, S) for (y, taps, xi) in gen]
+    specs = [_Spec(y, taps, xi, S, bnd, sc) for (y, taps, xi, bnd, sc) in gen]
     log(f"generated {n_all} images of {S}x{S} in {time.perf_counter() - t_start:.1f} s")
 
     import torch
@@ -176,7 +181,7 @@ def main(argv=None):
     log(f"training done in {train_s:.1f} s ({total} steps); validation loss {val_loss:.5f}")
 
     # ---- 3. lambda_0 calibration on training instances
-    cal = list(range(min(256, ntr)))
+    cal = list(range(min(512, ntr)))
     mu_h = torch.empty(len(cal), S, S, device=dev)
     v_h = torch.empty(len(cal), S, S, device=dev)
     for b0 in range(0, len(cal), args.batch):
@@ -184,13 +189,25 @@ def main(argv=None):
         net.infer(Y[cal[sl.start]:cal[sl.stop - 1] + 1].contiguous(), xi, mu_h[sl], v_h[sl])
     ctx = Context([spec_from_synthetic(specs[k], cg_precond=N.PRECOND_JACOBI) for k in cal])
     ctx.ep_tv_set_observation([Y[k] for k in cal])
-    ctx.ep_tv_init_warm([mu_h[i] for i in range(len(cal))], [v_h[i] for i in range(len(cal))], 1.0)
+    ctx.ep_tv_init_warm([mu_h[i] for i in range(len(cal))], [v_h[i] for i in range(len(cal))], 1.0, 1.0)
     lam1 = np.array([s["lambda"] for s in ctx.ep_tv_get_stats()])
     ctx.close()
     ratio = lam_star[cal] / lam1
-    lam_scale = float(np.median(ratio))
-    log(f"lambda calibration: option-1 ratio lambda*/lambda1 median {lam_scale:.4f} "
-        f"(IQR {np.percentile(ratio, 25):.4f}..{np.percentile(ratio, 75):.4f})")
+    # lambda_0 = kappa * lambda_1^rho, least squares in log space
+    A = np.stack([np.ones(len(cal)), np.log(lam1)], axis=1)
+    coef, *_ = np.linalg.lstsq(A, np.log(lam_star[cal]), rcond=None)
+    lam_scale, lam_power = float(np.exp(coef[0])), float(coef[1])
+    resid = np.log(lam_star[cal]) - A @ coef
+    log(f"lambda calibration: ratio lambda*/lambda1 median {np.median(ratio):.4f} "
+        f"(IQR {np.percentile(ratio, 25):.4f}..{np.percentile(ratio, 75):.4f}); fit "
+        f"lambda0 = {lam_scale:.4f} lambda1^{lam_power:.4f}, log residual std {resid.std():.4f}")
+    scales = np.array([specs[k].scale for k in cal])
+    by_scale = {}
+    for sc in sorted(set(scales.tolist())):
+        m = scales == sc
+        by_scale[int(sc)] = {"ratio_median": float(np.median(ratio[m])),
+                             "lambda_star_median": float(np.median(lam_star[cal][m]))}
+    log(f"  by image scale: {by_scale}")
 
     # ---- 4. held-out: warm versus cold sweeps
     vk = val
@@ -206,7 +223,7 @@ def main(argv=None):
     st_w, dt_w = solve_batch(torch, [specs[k] for k in vk], [Y[k] for k in vk], list(out_mu), list(out_v),
                              args.max_sweeps, args.tol,
                              warm=([mu_v[i] for i in range(len(vk))], [v_v[i] for i in range(len(vk))]),
-                             lam_scale=lam_scale)
+                             lam_scale=lam_scale, lam_power=lam_power)
     sc = np.array([s["sweeps"] for s in st_c])
     sw = np.array([s["sweeps"] for s in st_w])
     log(f"held-out {len(vk)}: cold mean sweeps {sc.mean():.1f} ({dt_c:.2f} s), "
@@ -214,12 +231,14 @@ def main(argv=None):
 
     params = net.params.cpu().numpy()
     meta = {"architecture": "3x3 conv x6, channels 1-32-32-32-32-32-2, ReLU, zero padding",
-            "train_instances": ntr, "size": S, "generator": "synthetic.config4_train",
-            "operator": "blur sigma_b=2 9x9 periodic", "noise_sigma": 0.01,
+            "train_instances": ntr, "size": S, "generator": "synthetic.config4_train_mixed",
+            "operator": "blur sigma_b=2 9x9 periodic, free TV boundary", "noise_sigma": 0.01,
             "epochs": args.epochs, "batch": args.batch, "lr": args.lr, "steps": total,
             "train_seconds": round(train_s, 1), "epoch_loss": [round(h, 6) for h in hist],
-            "val_loss": val_loss, "lambda_scale": lam_scale,
+            "val_loss": val_loss, "lambda_scale": lam_scale, "lambda_power": lam_power,
+            "lambda_fit_log_residual_std": float(resid.std()),
             "lambda_ratio_iqr": [float(np.percentile(ratio, 25)), float(np.percentile(ratio, 75))],
+            "lambda_by_scale": by_scale,
             "ep_targets": {"tol": args.tol, "max_sweeps": args.max_sweeps,
                            "converged_fraction": float(conv.mean()), "mean_sweeps": float(sweeps.mean())},
             "heldout": {"n": len(vk), "cold_mean_sweeps": float(sc.mean()),

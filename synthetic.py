@@ -81,6 +81,45 @@ def piecewise_image(h: int, w: int, n_shapes: int, rng: np.random.Generator,
     return img
 
 
+def window_image(h: int, w: int, scale: int, rng: np.random.Generator,
+                 density: float = 60.0 / (512 * 512), disk_fraction: float = 0.5) -> np.ndarray:
+    """An h x w window of a large painted canvas whose shapes are sized for an
+    S x S image, S = ``scale`` (rectangle sides U{ceil(S/16) .. ceil(S/4)}, disk
+    radii U[S/32, S/8]), with ``density`` shapes per canvas pixel.  Shape anchors
+    are uniform over the window grown by the largest shape extent on every side,
+    so every shape that can overlap the window is drawn; only the overlap is
+    painted (in drawing order, background 0)."""
+    s = scale
+    lo, hi = max(1, math.ceil(s / 16)), max(1, math.ceil(s / 4))
+    ext = hi
+    n = int(round(density * (h + 2 * ext) * (w + 2 * ext)))
+    img = np.zeros((h, w), dtype=np.float64)
+    for _ in range(n):
+        is_disk = rng.random() < disk_fraction
+        val = rng.random()
+        if is_disk:
+            r0 = rng.uniform(-ext, h + ext)
+            c0 = rng.uniform(-ext, w + ext)
+            rad = rng.uniform(s / 32.0, s / 8.0)
+            ra, rb = max(0, int(math.floor(r0 - rad)) - 1), min(h, int(math.ceil(r0 + rad)) + 1)
+            ca, cb = max(0, int(math.floor(c0 - rad)) - 1), min(w, int(math.ceil(c0 + rad)) + 1)
+            if ra >= rb or ca >= cb:
+                continue
+            rr, cc = np.mgrid[ra:rb, ca:cb]
+            m = (rr + 0.5 - r0) ** 2 + (cc + 0.5 - c0) ** 2 <= rad * rad
+            img[ra:rb, ca:cb][m] = val
+        else:
+            hh = int(rng.integers(lo, hi + 1))
+            ww = int(rng.integers(lo, hi + 1))
+            r0 = int(rng.integers(-ext, h + ext))
+            c0 = int(rng.integers(-ext, w + ext))
+            ra, rb = max(0, r0), min(h, r0 + hh)
+            ca, cb = max(0, c0), min(w, c0 + ww)
+            if ra < rb and ca < cb:
+                img[ra:rb, ca:cb] = val
+    return img
+
+
 def gaussian_taps(sigma_b: float, size: int = 9) -> np.ndarray:
     """Centred size x size Gaussian kernel exp(-(a^2+b^2)/(2 sigma_b^2)), sum 1."""
     a = np.arange(size) - size // 2
@@ -215,6 +254,25 @@ def config4_train(index: int, size: int = 256) -> Problem:
     shapes = max(3, round(60 * size * size / (512 * 512)))
     return make_deconv(size, size, shapes, 0.01, 2.0, rng, lam0=1.0, sweeps=200,
                        em=True, name=f"train{index}")
+
+
+def config4_train_mixed(index: int, size: int = 256) -> Problem:
+    """Warm-start training instance across image scales: instance i is a
+    size x size window of a canvas whose shapes are sized for an S x S image,
+    S = size * 2^(i mod 4) (256^2 windows of 256^2 ... 2048^2 scale images), so
+    that the training pixels cover the statistics of the large test image.
+    i mod 4 == 0 is exactly config4_train(i).  Operator and noise as the
+    deconvolution workload: 9 x 9 Gaussian blur sigma_b = 2, sigma = 0.01."""
+    k = index % 4
+    if k == 0:
+        return config4_train(index, size)
+    rng = rng_for(4, 200000 + index)
+    x = window_image(size, size, size << k, rng)
+    taps = gaussian_taps(2.0, 9)
+    y = _circular_blur_fft(x, taps) + 0.01 * rng.standard_normal((size, size))
+    return Problem(name=f"trainmix{index}", x_true=x, y=y, op=OP_BLUR, xi=0.01 ** 2, lam0=1.0,
+                   damping=0.5, sweeps=200, em=True, taps=taps, boundary="free",
+                   meta={"sigma": 0.01, "sigma_b": 2.0, "scale": size << k})
 
 
 def config4_test(seed: int = 0, size: int = 2048) -> Problem:

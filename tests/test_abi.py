@@ -81,4 +81,4 @@ def test_net_host_validation():
     h = ctypes.c_void_p(None)
     assert lib.ep_tv_net_create(None, None, 0, 1, 8, 8, None, ctypes.byref(h)) == N.EP_TV_E_ARG
     assert lib.ep_tv_net_adam_count(None) == -1
-    assert lib.ep_tv_init_warm(None, None, None, 1.0) == N.EP_TV_E_ARG
+    assert lib.ep_tv_init_warm(None, None, None, 1.0, 1.0) == N.EP_TV_E_ARG

@@ -168,14 +168,15 @@ def test_init_warm_sites_and_lambda_match_oracle():
     preds = [_warm_inputs(p, i) for i, p in enumerate(ps)]
     ctx = Context([spec_from_synthetic(p) for p in ps])
     ctx.ep_tv_set_observation([observation_tensor(p, torch) for p in ps])
-    rc = ctx.ep_tv_init_warm([_t(m) for m, _ in preds], [_t(v) for _, v in preds], 1.0)
+    kappa, rho = 1.3, 0.9          # a calibrated lambda_0 = kappa * (N / a_x)^rho
+    rc = ctx.ep_tv_init_warm([_t(m) for m, _ in preds], [_t(v) for _, v in preds], kappa, rho)
     assert rc == N.EP_TV_OK
     outs = [torch.empty(10 * p.shape[0] * p.shape[1], device="cuda") for p in ps]
     ctx.ep_tv_get_sites(outs)
     st = ctx.ep_tv_get_stats()
     for p, (m, v), o, s in zip(ps, preds, outs, st):
         pb = oep.problem_from_synthetic(f32_problem(p))
-        ref = owarm.init_warm(pb, m.astype(np.float32), v.astype(np.float32))
+        ref = owarm.init_warm(pb, m.astype(np.float32), v.astype(np.float32), scale=kappa, power=rho)
         sites = o.cpu().numpy().astype(np.float64).reshape(10, -1)
         tau, eta = sites[0::2], sites[1::2]
         assert np.allclose(tau, ref.tau, rtol=2e-6, atol=1e-12)
@@ -188,7 +189,7 @@ def test_init_warm_sites_and_lambda_match_oracle():
     torch.cuda.synchronize()
     for p, (m, v), mg, vg, s in zip(ps, preds, mus, vs, st):
         pb = oep.problem_from_synthetic(f32_problem(p))
-        ref = owarm.init_warm(pb, m.astype(np.float32), v.astype(np.float32))
+        ref = owarm.init_warm(pb, m.astype(np.float32), v.astype(np.float32), scale=kappa, power=rho)
         mu_o, v_o, _, info = oep.solve(pb, 10, True, state=ref)
         e_mu = mean_err(mg.cpu().numpy().astype(np.float64), mu_o)
         e_v = var_err(vg.cpu().numpy().astype(np.float64), v_o)
@@ -206,7 +207,7 @@ def test_init_warm_rejects_bad_prediction_per_instance():
     bad_mu[3, 4] = np.nan
     ctx = Context([spec_from_synthetic(p) for p in ps])
     ctx.ep_tv_set_observation([observation_tensor(p, torch) for p in ps])
-    rc = ctx.ep_tv_init_warm([_t(preds[0][0]), _t(bad_mu)], [_t(preds[0][1]), _t(preds[1][1])], 1.0)
+    rc = ctx.ep_tv_init_warm([_t(preds[0][0]), _t(bad_mu)], [_t(preds[0][1]), _t(preds[1][1])], 1.0, 1.0)
     assert rc == N.EP_TV_W_WARM_FALLBACK
     outs = [torch.empty(10 * 32 * 32, device="cuda") for _ in ps]
     ctx.ep_tv_get_sites(outs)

@@ -49,7 +49,7 @@ def test_warm_start_gain(size, seed):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     mh, vh = net.infer(y, p.xi)
-    rc = ctx.ep_tv_init_warm([mh], [vh], meta["lambda_scale"])
+    rc = ctx.ep_tv_init_warm([mh], [vh], meta["lambda_scale"], meta.get("lambda_power", 1.0))
     mu_w, v_w, st_w = _solve(ctx, p.shape, TOL, 2000)
     torch.cuda.synchronize()
     t_warm = time.perf_counter() - t0
