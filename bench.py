@@ -32,6 +32,46 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 SWEEP_BYTES_PER_PX = 72        # 5 sites (tau, eta) read + 4 written, float32
+HTH_BYTES_PER_PX = 20          # z, p_in, tau_c read; p_out, q written (float32)
+PMC_FILE = os.path.join(ROOT, "profiles", "pmc_traffic.json")
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary, or None when there is none or the kernel's source changed since."""
+    import hashlib
+    try:
+        with open(PMC_FILE) as f:
+            rec = json.load(f).get(kernel)
+    except (OSError, ValueError):
+        return None
+    if not rec:
+        return None
+    with open(os.path.join(ROOT, rec["source"]), "rb") as f:
+        if hashlib.sha256(f.read()).hexdigest() != rec["source_sha256"]:
+            return None
+    return rec["traffic_bytes_per_launch"]
+
+
+def roofline_entry(kernel, bytes_per_launch, avg_s):
+    achieved = bytes_per_launch / avg_s / 1e9
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(kernel),
+            "kernel": kernel, "bytes_per_launch": bytes_per_launch,
+            "avg_launch_us": round(avg_s * 1e6, 2)}
+
+
+def copy_probe(nbytes=1 << 30, reps=5):
+    """A plain device-to-device copy of known size (for scaling the HBM byte
+    counters of rocprofv3)."""
+    import torch
+    src = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    dst = torch.empty_like(src)
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes_read": nbytes, "copy_probe_bytes_written": nbytes,
+                      "repetitions": reps}), flush=True)
 
 
 def make_workload(name):
@@ -96,7 +136,11 @@ def main():
     ap.add_argument("--no-warm", action="store_true")
     ap.add_argument("--cpu-sweeps", type=int, default=4)
     ap.add_argument("--cpu-size", type=int, default=256)
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run a plain 1 GiB device copy (counter scaling for rocprofv3)")
     args = ap.parse_args()
+    if args.copy_probe:
+        return copy_probe()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(see DESIGN.md for how the sweep would shard)", file=sys.stderr)
@@ -137,14 +181,18 @@ def main():
           f"{tm['sweep_launches']}, likelihood {tm['lik_ms']:.2f} ms / {tm['lik_updates']}",
           file=sys.stderr, flush=True)
 
-    # roofline of the sweep kernel (algorithmic bytes: every site read once, TV sites written once)
+    # rooflines (algorithmic bytes per launch / average launch time from HIP
+    # events on the context's stream): the TV sweep (every site read once, the
+    # TV sites written once) and, for deconvolution, the H^T H kernel of the CG;
+    # `roofline` is the one with the larger total time
     sweep_avg_s = tm["sweep_ms"] / max(tm["sweep_launches"], 1) / 1e3
-    sweep_bytes = SWEEP_BYTES_PER_PX * h * w
-    achieved = sweep_bytes / sweep_avg_s / 1e9
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "kernel": "k_tv_sweep", "bytes_per_launch": sweep_bytes,
-                "avg_launch_us": round(sweep_avg_s * 1e6, 2)}
+    roof_sweep = roofline_entry("k_tv_sweep", SWEEP_BYTES_PER_PX * h * w, sweep_avg_s)
+    roofline = roof_sweep
+    if p.op == "blur" and tm["apply_launches"] > 0:
+        apply_avg_s = tm["apply_ms"] / tm["apply_launches"] / 1e3
+        roof_apply = roofline_entry("k_hth_sep", HTH_BYTES_PER_PX * h * w, apply_avg_s)
+        if tm["apply_ms"] > tm["sweep_ms"]:
+            roofline = roof_apply
 
     # seconds to converged from a cold start (y resident on the GPU)
     conv = None
@@ -156,7 +204,7 @@ def main():
     if not args.no_cpu_baseline:
         print("[bench] timing the oracle on the host", file=sys.stderr, flush=True)
         cpu = cpu_baseline(args.workload, args.cpu_size, args.cpu_sweeps)
-    return emit(args, p, em, h, w, value, dt, roofline, cpu, conv, tm)
+    return emit(args, p, em, h, w, value, dt, roofline, cpu, conv, tm, roof_sweep)
 
 
 def bench_batch(args, ps, em):
@@ -189,12 +237,7 @@ def bench_batch(args, ps, em):
     value = E * args.steps / dt
     print(f"[bench] {args.steps} sweeps in {dt * 1e3:.1f} ms", file=sys.stderr, flush=True)
     sweep_avg_s = tm["sweep_ms"] / max(tm["sweep_launches"], 1) / 1e3
-    sweep_bytes = SWEEP_BYTES_PER_PX * npx
-    achieved = sweep_bytes / sweep_avg_s / 1e9
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "kernel": "k_tv_sweep", "bytes_per_launch": sweep_bytes,
-                "avg_launch_us": round(sweep_avg_s * 1e6, 2)}
+    roofline = roofline_entry("k_tv_sweep", SWEEP_BYTES_PER_PX * npx, sweep_avg_s)
     conv = None
     if args.max_sweeps > 0:
         ctx.ep_tv_init_cold()
@@ -291,7 +334,7 @@ def converge(ctx, args, em, p, y, dev, torch):
     return conv
 
 
-def emit(args, p, em, h, w, value, dt, roofline, cpu, conv, tm):
+def emit(args, p, em, h, w, value, dt, roofline, cpu, conv, tm, roof_sweep):
     E = edges(h, w)
     line = {
         "metric": "EP factor-updates/s + s to converged 2048^2 deconv, warm-start vs plain, 1 GPU",
@@ -300,9 +343,11 @@ def emit(args, p, em, h, w, value, dt, roofline, cpu, conv, tm):
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": args.workload, "height": h, "width": w, "op": p.op, "em": em,
                    "edges_per_sweep": E, "damping": p.damping, "xi": p.xi},
-        "roofline": roofline, "cpu_baseline": cpu, "convergence": conv,
+        "roofline": roofline, "roofline_sweep": roof_sweep, "cpu_baseline": cpu, "convergence": conv,
         "timing_ms": {"sweep": tm["sweep_ms"], "likelihood": tm["lik_ms"],
-                      "hth_apply": tm["apply_ms"]},
+                      "cg_products": tm["apply_ms"], "cg_products_launches": tm["apply_launches"],
+                      "cg_preconditioner": tm["precond_ms"],
+                      "cg_preconditioner_launches": tm["precond_launches"]},
     }
     print(json.dumps(line), flush=True)
 

@@ -232,8 +232,12 @@ typedef struct {
   int32_t sweep_launches;
   double lik_ms;               /* total GPU time of likelihood-site updates */
   int32_t lik_updates;
-  double apply_ms;             /* total GPU time of H^T H applications inside CG */
+  double apply_ms;             /* total GPU time of the products with A inside CG (for blur
+                                  instances with separable taps: the H^T H kernel alone) */
   int32_t apply_launches;
+  double precond_ms;           /* total GPU time of the real-transform preconditioner of the
+                                  circulant-preconditioned CG (with the fused x, r update) */
+  int32_t precond_launches;
 } ep_tv_timing;
 
 int ep_tv_set_timing(ep_tv_ctx* ctx, int32_t enable);

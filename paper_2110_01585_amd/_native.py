@@ -59,7 +59,8 @@ class EpTvStats(ctypes.Structure):
 class EpTvTiming(ctypes.Structure):
     _fields_ = [("sweep_ms", ctypes.c_double), ("sweep_launches", ctypes.c_int32),
                 ("lik_ms", ctypes.c_double), ("lik_updates", ctypes.c_int32),
-                ("apply_ms", ctypes.c_double), ("apply_launches", ctypes.c_int32)]
+                ("apply_ms", ctypes.c_double), ("apply_launches", ctypes.c_int32),
+                ("precond_ms", ctypes.c_double), ("precond_launches", ctypes.c_int32)]
 
 
 class EpTvTuneResult(ctypes.Structure):

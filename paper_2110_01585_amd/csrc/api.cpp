@@ -880,11 +880,13 @@ int ep_tv_get_timing(ep_tv_ctx* c, ep_tv_timing* out) {
     out->lik_ms += ms;
     out->lik_updates += 1;
   }
-  double ams = 0.0;
-  int an = 0;
-  HIPCHK(c, lik_timing_read(c->lik, ams, an));
+  double ams = 0.0, pms = 0.0;
+  int an = 0, pn = 0;
+  HIPCHK(c, lik_timing_read(c->lik, ams, an, pms, pn));
   out->apply_ms = ams;
   out->apply_launches = an;
+  out->precond_ms = pms;
+  out->precond_launches = pn;
   return EP_TV_OK;
 }
 

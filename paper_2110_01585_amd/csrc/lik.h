@@ -155,7 +155,8 @@ struct LikCtx {
   bool timing = false;
   std::vector<hipEvent_t> ev;
   size_t ev_used = 0;
-  std::vector<std::pair<int, int>> ev_apply;
+  std::vector<std::pair<int, int>> ev_apply;     // products with A inside CG
+  std::vector<std::pair<int, int>> ev_precond;   // fast-CG preconditioner (with the x, r update)
 };
 
 hipError_t lik_create(LikCtx& lc, const LikInstInfo* li, int n, char* ws, const LikLayout& L,
@@ -175,6 +176,6 @@ hipError_t lik_poll(LikCtx& lc, hipStream_t s, bool& all_done);
 hipError_t lik_tail(LikCtx& lc, float2* S0, hipStream_t s);
 void lik_destroy(LikCtx& lc);
 void lik_timing(LikCtx& lc, bool enable, bool clear);
-hipError_t lik_timing_read(LikCtx& lc, double& ms, int& launches);
+hipError_t lik_timing_read(LikCtx& lc, double& ms, int& launches, double& pms, int& plaunches);
 
 }  // namespace eptv

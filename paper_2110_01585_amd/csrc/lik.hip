@@ -703,34 +703,41 @@ static hipError_t launch_apply_blur(LikCtx& lc, int mode, hipStream_t s) {
   return hipGetLastError();
 }
 
-static hipError_t launch_apply(LikCtx& lc, int mode, hipStream_t s) {
-  bool any_dft = false;
-  for (const LikInst& d : lc.hinst) any_dft = any_dft || d.op == OP_DFT;
-  int i0 = 0, i1 = 0;
+// Run `body` between two timing events (when timing is on), recording the pair
+// in `bucket`.
+template <class F>
+static hipError_t timed(LikCtx& lc, std::vector<std::pair<int, int>>& bucket, hipStream_t s, F&& body) {
   const bool tm = lc.timing && lc.ev_used + 2 <= 16384;
+  int i0 = 0, i1 = 0;
   if (tm) {
-    if (lc.ev_used + 2 > lc.ev.size()) {
-      for (int k = 0; k < 2; ++k) {
-        hipEvent_t e;
-        if (hipEventCreate(&e) != hipSuccess) return hipErrorOutOfMemory;
-        lc.ev.push_back(e);
-      }
+    while (lc.ev_used + 2 > lc.ev.size()) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) return hipErrorOutOfMemory;
+      lc.ev.push_back(e);
     }
     i0 = (int)lc.ev_used++;
     i1 = (int)lc.ev_used++;
     hipEventRecord(lc.ev[i0], s);
   }
-  if (any_dft) {
-    hipError_t e = dft_apply(lc, mode, s);
-    if (e != hipSuccess) return e;
-  }
-  hipError_t e = launch_apply_blur(lc, mode, s);
+  hipError_t e = body();
   if (e != hipSuccess) return e;
   if (tm) {
     hipEventRecord(lc.ev[i1], s);
-    lc.ev_apply.emplace_back(i0, i1);
+    bucket.emplace_back(i0, i1);
   }
   return hipGetLastError();
+}
+
+static hipError_t launch_apply(LikCtx& lc, int mode, hipStream_t s) {
+  bool any_dft = false;
+  for (const LikInst& d : lc.hinst) any_dft = any_dft || d.op == OP_DFT;
+  return timed(lc, lc.ev_apply, s, [&]() -> hipError_t {
+    if (any_dft) {
+      hipError_t e = dft_apply(lc, mode, s);
+      if (e != hipSuccess) return e;
+    }
+    return launch_apply_blur(lc, mode, s);
+  });
 }
 
 static hipError_t fin(LikCtx& lc, int stage, hipStream_t s) {
@@ -766,10 +773,14 @@ hipError_t lik_iterations(LikCtx& lc, int n, hipStream_t s) {
     for (int it = 0; it < n; ++it) {
       // p_out = z + beta p_in and q = A p_out: blur tiles by the direct
       // H^T H kernel, masked-DFT instances by the real transform
-      if ((e = launch_apply_blur(lc, 1, s)) != hipSuccess) return e;
-      if ((e = rfft_product(lc, s)) != hipSuccess) return e;
+      e = timed(lc, lc.ev_apply, s, [&]() -> hipError_t {
+        hipError_t e2 = launch_apply_blur(lc, 1, s);
+        return e2 != hipSuccess ? e2 : rfft_product(lc, s);
+      });
+      if (e != hipSuccess) return e;
       if ((e = fin(lc, FIN_ALPHA, s)) != hipSuccess) return e;
-      if ((e = rfft_precondition(lc, 1, s)) != hipSuccess) return e;   // with x, r update
+      e = timed(lc, lc.ev_precond, s, [&]() { return rfft_precondition(lc, 1, s); });   // with x, r update
+      if (e != hipSuccess) return e;
       if ((e = fin(lc, FIN_BETA, s)) != hipSuccess) return e;
       lc.pcur ^= 1;
     }
@@ -828,20 +839,27 @@ void lik_timing(LikCtx& lc, bool enable, bool clear) {
   if (clear) {
     lc.ev_used = 0;
     lc.ev_apply.clear();
+    lc.ev_precond.clear();
   }
 }
 
-hipError_t lik_timing_read(LikCtx& lc, double& ms, int& launches) {
+static hipError_t sum_events(LikCtx& lc, const std::vector<std::pair<int, int>>& b, double& ms, int& n) {
   ms = 0.0;
-  launches = 0;
-  for (auto& pr : lc.ev_apply) {
+  n = 0;
+  for (auto& pr : b) {
     float t = 0.f;
     hipError_t e = hipEventElapsedTime(&t, lc.ev[pr.first], lc.ev[pr.second]);
     if (e != hipSuccess) return e;
     ms += t;
-    launches += 1;
+    n += 1;
   }
   return hipSuccess;
+}
+
+hipError_t lik_timing_read(LikCtx& lc, double& ms, int& launches, double& pms, int& plaunches) {
+  hipError_t e = sum_events(lc, lc.ev_apply, ms, launches);
+  if (e != hipSuccess) return e;
+  return sum_events(lc, lc.ev_precond, pms, plaunches);
 }
 
 }  // namespace eptv

@@ -242,6 +242,11 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, int tile, int lan
     const int g = per ? wrap(r, H) : r;
     return I.off + (long long)g * I.pitch + gcl;
   };
+  // software pipelining: the next row pair is requested before the current one
+  // is processed, so its loads are in flight during the tilted-moment work
+  Raw nb, nc;
+  fetch(a, row_idx(R0 - 2), row_ok(R0 - 2) && vL, nb);
+  fetch(a, row_idx(R0 - 1), row_ok(R0 - 1) && vL, nc);
   for (int r = R0 - 2; r <= R1; r += 2) {
     const bool bv = row_ok(r);
     const bool cv = row_ok(r + 1);
@@ -249,12 +254,11 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, int tile, int lan
     const bool cint = r + 1 >= R0 && r + 1 < R1;
     const long long ib = row_idx(r);
     Px bL, bR, cL, cR;
-    {
-      Raw nb, nc;
-      fetch(a, ib, bv && vL, nb);
-      fetch(a, row_idx(r + 1), cv && vL, nc);
-      unpack(nb, vR, bL, bR);
-      unpack(nc, vR, cL, cR);
+    unpack(nb, vR, bL, bR);
+    unpack(nc, vR, cL, cR);
+    if (r + 2 <= R1) {
+      fetch(a, row_idx(r + 2), row_ok(r + 2) && vL, nb);
+      fetch(a, row_idx(r + 3), row_ok(r + 3) && vL, nc);
     }
     float bomL = 0.f, bovL = 1.f, bomR = 0.f, bovR = 1.f, comL = 0.f, covL = 1.f, comR = 0.f,
           covR = 1.f;

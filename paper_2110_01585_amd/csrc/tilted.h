@@ -36,15 +36,25 @@ struct Tilt {
 };
 
 // (K, r) of a component whose cut lies x >= kTailX standard deviations beyond
-// its mean, by the bottom-up continued fraction K = 1/(x + L),
-// L = 2/(x + 3/(x + ...)).  Every step adds positive numbers, so the
-// recurrence is stable in FP32 (relative error ~ depth * eps) and, unlike the
-// direct formula, never subtracts nearly equal quantities.
+// its mean, from Laplace's continued fraction K = 1/(x + L),
+// L = 2/(x + 3/(x + 4/(x + ...))), truncated at depth kTailDepth.  L is
+// evaluated forwards as a ratio A/B of the fraction's convergents, scaled by
+// x^-j so that they stay O(1): with u = 1/x,
+//   A_j = A_{j-1} + (j+1) u^2 A_{j-2},  B_j = B_{j-1} + (j+1) u^2 B_{j-2},
+//   A_0 = 0, B_0 = 1, A_1 = 2u, B_1 = 1.
+// Every term is positive (no cancellation, as in the bottom-up evaluation) and
+// the whole tail costs two reciprocals.
 __device__ __forceinline__ void tail_cf(float x, float& K, float& r) {
-  float t = 0.0f;
+  const float u = frcp(x);
+  const float u2 = u * u;
+  float A2 = 0.0f, B2 = 1.0f, A1 = 2.0f * u, B1 = 1.0f;
 #pragma unroll
-  for (int n = kTailDepth; n >= 2; --n) t = (float)n * frcp(x + t);
-  K = frcp(x + t);
+  for (int j = 2; j < kTailDepth; ++j) {
+    const float a = (float)(j + 1) * u2;
+    const float A0 = A1 + a * A2, B0 = B1 + a * B2;
+    A2 = A1; B2 = B1; A1 = A0; B1 = B0;
+  }
+  K = frcp(x + A1 * frcp(B1));
   r = x + K;
 }
 
@@ -57,8 +67,25 @@ __device__ __forceinline__ Tilt laplace_tilt(float m, float s, float lam) {
   const float k = kInvSqrt2 * frcp(sig);
   const float zp = (ls - m) * k;
   const float zm = (ls + m) * k;
-  const float exp_ = erfcxf(fabsf(zp));
-  const float exm = erfcxf(fabsf(zm));
+  const float xp = kSqrt2 * zp;
+  const float xm = kSqrt2 * zm;
+  // A component in the far tail takes K, r and its weight erfcx(z) = sqrt(2/pi)/r
+  // from the continued fraction; the others call erfcx.
+  const bool tp = xp >= kTailX, tm = xm >= kTailX;
+  float Kpt = 0.0f, rpt = 1.0f, Kmt = 0.0f, rmt = 1.0f;
+  float exp_, exm;
+  if (tp) {
+    tail_cf(xp, Kpt, rpt);
+    exp_ = kSqrt2OverPi * frcp(rpt);
+  } else {
+    exp_ = erfcxf(fabsf(zp));
+  }
+  if (tm) {
+    tail_cf(xm, Kmt, rmt);
+    exm = kSqrt2OverPi * frcp(rmt);
+  } else {
+    exm = erfcxf(fabsf(zm));
+  }
   // At most one of z+, z- is negative (their sum is sqrt2 lambda sigma >= 0).
   // For z < 0, erfcx(z) = e^{z^2} erfc(z) with erfc(z) = 2 - e^{-z^2} erfcx(|z|);
   // both weights are rescaled by e^{-z^2} so nothing overflows.
@@ -84,14 +111,10 @@ __device__ __forceinline__ Tilt laplace_tilt(float m, float s, float lam) {
   const float inv = frcp(wp + wm);
   const float pp = wp * inv;
   const float pm = wm * inv;
-  const float xp = kSqrt2 * zp;
-  const float xm = kSqrt2 * zm;
   float Kp = rp - xp;
   float Km = rm - xm;
-  if (xp >= kTailX || xm >= kTailX) {
-    if (xp >= kTailX) tail_cf(xp, Kp, rp);
-    if (xm >= kTailX) tail_cf(xm, Km, rm);
-  }
+  if (tp) { Kp = Kpt; rp = rpt; }
+  if (tm) { Km = Kmt; rm = rmt; }
   Tilt T;
   const float Ks = Kp + Km;
   T.rho = pp * rp * Kp + pm * rm * Km - pp * pm * Ks * Ks;
