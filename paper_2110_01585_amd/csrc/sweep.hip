@@ -64,6 +64,9 @@ struct PairOut {
 // form tau_i = rho / (s - rho c_i), eta_i = tau_i E_i + delta / s (and i<->j,
 // delta -> -delta); variance clamp of Sec. III-C at 1e8.
 __device__ __forceinline__ PairOut pair_core(float ci, float mi, float cj, float mj, float lam) {
+  // no fused multiply-adds: the update of (i, j) must be the exact mirror of
+  // the update of (j, i)
+#pragma clang fp contract(off)
   const float s = ci + cj;
   const Tilt T = laplace_tilt(mi - mj, s, lam);
   const float dels = T.delta * frcp(s);

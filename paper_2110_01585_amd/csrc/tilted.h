@@ -58,7 +58,11 @@ __device__ __forceinline__ void tail_cf(float x, float& K, float& r) {
   r = x + K;
 }
 
+// Contraction into fused multiply-adds is switched off here: fma(a, b, c d)
+// is not symmetric under exchanging the two components, and with it the moments
+// of -m would not be exactly the mirror image of those of m.
 __device__ __forceinline__ Tilt laplace_tilt(float m, float s, float lam) {
+#pragma clang fp contract(off)
   const float kSqrt2 = 1.41421356237309515f;
   const float kInvSqrt2 = 0.707106781186547573f;
   const float kSqrt2OverPi = 0.797884560802865406f;
