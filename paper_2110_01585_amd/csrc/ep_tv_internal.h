@@ -22,8 +22,6 @@ constexpr int kStripInt = kStripPx - 4;   // interior columns per strip (2-px ha
 constexpr int kWavesPerBlock = 4;
 constexpr float kPrecFloor = 1e-8f;       // clamp: site variance < 0 or > 1e8 -> 1e8
 constexpr float kSiteInitPrec = 1e-8f;    // initial TV-site variance 1e8
-constexpr int kTailDepth = 20;            // Laplace continued-fraction depth (x >= 3)
-constexpr float kTailX = 3.0f;
 
 enum { OP_IDENTITY = 0, OP_BLUR = 1, OP_DFT = 2 };
 enum { BND_FREE = 0, BND_PERIODIC = 1 };

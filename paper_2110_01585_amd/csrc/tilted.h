@@ -3,19 +3,16 @@
 // (Eq. (L1_TV)), and the site update that follows from the Gehre-Jin pair
 // projection and Eq. (update_qk_x).
 //
-// Precision: FP32.  In the far tails of the truncated Gaussian components the
-// direct formula for the variance cancels catastrophically; there K and r come
-// from Laplace's continued fraction of the Mills ratio, whose evaluation only
-// adds positive terms.  The expressions are arranged so that the quantities the site update
-// needs -- rho = 1 - S_bar/s and delta = m_bar - m -- never come out of a
-// difference of nearly equal numbers:
+// Precision: FP32, with no branch on the argument.  For a truncated Gaussian
+// component whose cut lies x >= 0 standard deviations beyond its mean, every
+// moment follows from K(x) = r(x) - x, r = sqrt(2/pi) / erfcx(x / sqrt2) the
+// inverse Mills ratio: the mean lies sigma K beyond the cut and the variance is
+// s (1 - r K).  K comes from one polynomial (below) valid on the whole half line,
+// and r = x + K only adds positive numbers, so nothing cancels in the far tail:
 //
 //   the tilted density is a mixture of  N(m - lambda s, s) on u > 0  and
 //   N(m + lambda s, s) on u < 0, with weights proportional to erfcx(z+) and
-//   erfcx(z-), z+- = (lambda s -+ m) / (sigma sqrt 2).  For a component with its
-//   cut x = sqrt2 z standard deviations beyond its mean, r = sqrt(2/pi)/erfcx(z)
-//   (inverse Mills ratio) and K = r - x give the mean sigma K beyond the cut and
-//   the variance s (1 - r K).  Hence
+//   erfcx(z-), z+- = (lambda s -+ m) / (sigma sqrt 2).  Hence
 //     rho   = p+ r+ K+ + p- r- K- - p+ p- (K+ + K-)^2,
 //     delta = sigma (p+ r+ - p- r-) - lambda s (p+ - p-),
 //     E|u|  = sigma (p+ K+ + p- K-).
@@ -35,26 +32,34 @@ struct Tilt {
   float eabs;   // E|u| under the tilted distribution
 };
 
-// (K, r) of a component whose cut lies x >= kTailX standard deviations beyond
-// its mean, from Laplace's continued fraction K = 1/(x + L),
-// L = 2/(x + 3/(x + 4/(x + ...))), truncated at depth kTailDepth.  L is
-// evaluated forwards as a ratio A/B of the fraction's convergents, scaled by
-// x^-j so that they stay O(1): with u = 1/x,
-//   A_j = A_{j-1} + (j+1) u^2 A_{j-2},  B_j = B_{j-1} + (j+1) u^2 B_{j-2},
-//   A_0 = 0, B_0 = 1, A_1 = 2u, B_1 = 1.
-// Every term is positive (no cancellation, as in the bottom-up evaluation) and
-// the whole tail costs two reciprocals.
-__device__ __forceinline__ void tail_cf(float x, float& K, float& r) {
-  const float u = frcp(x);
-  const float u2 = u * u;
-  float A2 = 0.0f, B2 = 1.0f, A1 = 2.0f * u, B1 = 1.0f;
+// K(x) = t G(s) with z = x / sqrt2, t = 2 / (2 + z), s = 2 t - 1: G is a
+// degree-12 polynomial in s fitted for minimum maximum relative error against K
+// at 50 digits (fit_mills.py in this directory writes the table); the fit error
+// is 3e-8 and the FP32 Horner evaluation stays within 1.2e-7 of K for every
+// x >= 0, the x -> inf limit K ~ 1/x included.
+constexpr float kMillsPoly[13] = {
+    5.913686752e-01f,
+    2.712919712e-01f,
+    -1.626213081e-02f,
+    -6.369908899e-02f,
+    1.618392300e-03f,
+    1.930276118e-02f,
+    -1.965504140e-03f,
+    -6.114535499e-03f,
+    1.438202569e-03f,
+    1.636359608e-03f,
+    -5.852500326e-04f,
+    -2.518910915e-04f,
+    1.065924080e-04f};
+
+// (K, r) at a cut x = sqrt2 z >= 0 standard deviations beyond the mean.
+__device__ __forceinline__ void mills(float z, float x, float& K, float& r) {
+  const float t = 2.0f * frcp(2.0f + z);
+  const float s = 2.0f * t - 1.0f;
+  float G = kMillsPoly[12];
 #pragma unroll
-  for (int j = 2; j < kTailDepth; ++j) {
-    const float a = (float)(j + 1) * u2;
-    const float A0 = A1 + a * A2, B0 = B1 + a * B2;
-    A2 = A1; B2 = B1; A1 = A0; B1 = B0;
-  }
-  K = frcp(x + A1 * frcp(B1));
+  for (int k = 11; k >= 0; --k) G = __builtin_fmaf(G, s, kMillsPoly[k]);
+  K = t * G;
   r = x + K;
 }
 
@@ -73,52 +78,32 @@ __device__ __forceinline__ Tilt laplace_tilt(float m, float s, float lam) {
   const float zm = (ls + m) * k;
   const float xp = kSqrt2 * zp;
   const float xm = kSqrt2 * zm;
-  // A component in the far tail takes K, r and its weight erfcx(z) = sqrt(2/pi)/r
-  // from the continued fraction; the others call erfcx.
-  const bool tp = xp >= kTailX, tm = xm >= kTailX;
-  float Kpt = 0.0f, rpt = 1.0f, Kmt = 0.0f, rmt = 1.0f;
-  float exp_, exm;
-  if (tp) {
-    tail_cf(xp, Kpt, rpt);
-    exp_ = kSqrt2OverPi * frcp(rpt);
-  } else {
-    exp_ = erfcxf(fabsf(zp));
-  }
-  if (tm) {
-    tail_cf(xm, Kmt, rmt);
-    exm = kSqrt2OverPi * frcp(rmt);
-  } else {
-    exm = erfcxf(fabsf(zm));
-  }
+  // Both components evaluated at |z|: exact for a component with z >= 0.
+  float Kp1, rp1, Km1, rm1;
+  mills(fabsf(zp), fabsf(xp), Kp1, rp1);
+  mills(fabsf(zm), fabsf(xm), Km1, rm1);
   // At most one of z+, z- is negative (their sum is sqrt2 lambda sigma >= 0).
   // For z < 0, erfcx(z) = e^{z^2} erfc(z) with erfc(z) = 2 - e^{-z^2} erfcx(|z|);
-  // both weights are rescaled by e^{-z^2} so nothing overflows.
+  // both weights are rescaled by g = e^{-z^2} so nothing overflows: the negative
+  // component weighs wn = 2 - g erfcx(|z|) and has r = sqrt(2/pi) g / wn, the
+  // other one weighs g sqrt(2/pi) / r.  Only the ratio of the weights matters,
+  // so they are scaled by the positive components' r (no reciprocal when both
+  // z are non-negative: weights r-, r+).
+  const bool sp = zp < 0.0f, sm = zm < 0.0f;
   const float zneg = fminf(fminf(zp, zm), 0.0f);
   const float g = __expf(-zneg * zneg);
-  float wp, wm, rp, rm;
-  if (zp < 0.0f) {
-    wp = 2.0f - g * exp_;
-    wm = exm * g;
-    rp = kSqrt2OverPi * g * frcp(wp);
-    rm = kSqrt2OverPi * frcp(exm);
-  } else if (zm < 0.0f) {
-    wm = 2.0f - g * exm;
-    wp = exp_ * g;
-    rm = kSqrt2OverPi * g * frcp(wm);
-    rp = kSqrt2OverPi * frcp(exp_);
-  } else {
-    wp = exp_;
-    wm = exm;
-    rp = kSqrt2OverPi * frcp(exp_);
-    rm = kSqrt2OverPi * frcp(exm);
-  }
-  const float inv = frcp(wp + wm);
-  const float pp = wp * inv;
-  const float pm = wm * inv;
-  float Kp = rp - xp;
-  float Km = rm - xm;
-  if (tp) { Kp = Kpt; rp = rpt; }
-  if (tm) { Km = Kmt; rm = rmt; }
+  const float gc = g * kSqrt2OverPi;
+  const float wn = 2.0f - g * (kSqrt2OverPi * frcp(sp ? rp1 : rm1));
+  const float rn = gc * frcp(wn);
+  const float Wp = sp ? wn * rm1 : (sm ? gc : rm1);
+  const float Wm = sm ? wn * rp1 : (sp ? gc : rp1);
+  const float inv = frcp(Wp + Wm);
+  const float pp = Wp * inv;
+  const float pm = Wm * inv;
+  const float rp = sp ? rn : rp1;
+  const float rm = sm ? rn : rm1;
+  const float Kp = sp ? rn - xp : Kp1;
+  const float Km = sm ? rn - xm : Km1;
   Tilt T;
   const float Ks = Kp + Km;
   T.rho = pp * rp * Kp + pm * rm * Km - pp * pm * Ks * Ks;
