@@ -7,8 +7,9 @@
 // column.  The state of a pixel after the four classes therefore depends on
 // pixels at most 2 columns and 2 rows away.  One wave owns a vertical strip of
 // 128 columns (2 per lane; lane l holds columns c0-2+2l and c0-1+2l, so every V1
-// pair is inside a lane) of which the middle 124 are written, and marches down a
-// chunk of rows two at a time:
+// pair is inside a lane) of which the middle 124 are written, and marches through
+// a chunk of rows two at a time (downwards shown; odd chunks march down, even
+// chunks up, the mirror image of this order):
 //
 //   load rows (r, r+1)  ->  V1 on both rows (lane-local)
 //                       ->  V2 on both rows (pair = lane's right pixel and the
@@ -201,9 +202,45 @@ __device__ __forceinline__ int wrap(int i, int n) {
   return r < 0 ? r + n : r;
 }
 
+// Store a final row of the strip and fold its change into the convergence
+// measures (DELTA): largest |mu - mu_old| and |v / v_old - 1| over stored pixels.
+template <bool DELTA>
+__device__ __forceinline__ void finish_row(const SweepArgs& a, long long idx, bool wL, bool wR,
+                                           const Px& L, const Px& R, float omL, float ovL,
+                                           float omR, float ovR, float& dmu, float& dv,
+                                           unsigned& flags) {
+  store_row(a, idx, wL, wR, L, R);
+  if (DELTA) {
+    float m1, v1;
+    if (wL) {
+      totals(L, m1, v1);
+      dmu = fmaxf(dmu, fabsf(m1 - omL));
+      dv = fmaxf(dv, fabsf(v1 / ovL - 1.f));
+      if (!(fabsf(m1) < 3.0e38f) || !(v1 > 0.f && v1 < 3.0e38f)) flags |= FLAG_NONFINITE;
+    }
+    if (wR) {
+      totals(R, m1, v1);
+      dmu = fmaxf(dmu, fabsf(m1 - omR));
+      dv = fmaxf(dv, fabsf(v1 / ovR - 1.f));
+      if (!(fabsf(m1) < 3.0e38f) || !(v1 > 0.f && v1 < 3.0e38f)) flags |= FLAG_NONFINITE;
+    }
+  }
+}
+
 // One tile (strip x chunk) of one instance; `tile` and every value derived from
 // the tile descriptor are wave-uniform (scalar registers).
-template <bool DELTA>
+//
+// The tile's row pairs (r, r+1), r = R0-2, R0, ..., are visited downwards
+// (UP = false) or upwards (UP = true); the result is the same either way, since
+// every update of a class reads only the previous classes' results.  Even
+// chunks march up and odd chunks down, so the halo rows two neighbouring chunks
+// share are read by both at about the same time (both start there, or both end
+// there) and the second read is served by L2.
+//   down: pair (r, r+1), then V4 on (r-1, r) with row r-1 carried; rows r-1, r
+//         are final; row r+1 is carried;
+//   up:   pair (r, r+1), then V4 on (r+1, r+2) with row r+2 carried; rows
+//         r+1, r+2 are final; row r is carried.
+template <bool DELTA, bool UP>
 __device__ __forceinline__ void sweep_tile(const SweepArgs& a, int tile, int lane) {
   const int4 td = a.tiles[tile];
   const InstDev I = a.inst[td.x];
@@ -233,14 +270,18 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, int tile, int lan
 
   const int R0 = td.z * I.chunk_rows;
   const int R1 = min(R0 + I.chunk_rows, H);
+  const int npairs = (R1 - R0 + 2) / 2 + 1;       // r = R0-2 .. R0-2 + 2 (npairs-1)
+  const int rfirst = UP ? R0 - 2 + 2 * (npairs - 1) : R0 - 2;
+  constexpr int kStep = UP ? -2 : 2;
 
   Acc acc{0.0, 0u};
   float dmu = 0.f, dv = 0.f;
   unsigned flags = 0u;
-  Px aL, aR;                    // row r-1 after V3 (carried)
+  Px aL, aR;                    // carried row after V3
   float aomL = 0.f, aovL = 1.f, aomR = 0.f, aovR = 1.f;
 
   auto row_ok = [&](int r) { return per || (r >= 0 && r < H); };
+  auto row_in = [&](int r) { return r >= R0 && r < R1; };
   auto row_idx = [&](int r) {
     const int g = per ? wrap(r, H) : r;
     return I.off + (long long)g * I.pitch + gcl;
@@ -248,20 +289,20 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, int tile, int lan
   // software pipelining: the next row pair is requested before the current one
   // is processed, so its loads are in flight during the tilted-moment work
   Raw nb, nc;
-  fetch(a, row_idx(R0 - 2), row_ok(R0 - 2) && vL, nb);
-  fetch(a, row_idx(R0 - 1), row_ok(R0 - 1) && vL, nc);
-  for (int r = R0 - 2; r <= R1; r += 2) {
+  fetch(a, row_idx(rfirst), row_ok(rfirst) && vL, nb);
+  fetch(a, row_idx(rfirst + 1), row_ok(rfirst + 1) && vL, nc);
+  for (int it = 0; it < npairs; ++it) {
+    const int r = rfirst + it * kStep;
     const bool bv = row_ok(r);
     const bool cv = row_ok(r + 1);
-    const bool bint = r >= R0 && r < R1;
-    const bool cint = r + 1 >= R0 && r + 1 < R1;
-    const long long ib = row_idx(r);
+    const bool bint = row_in(r);
+    const bool cint = row_in(r + 1);
     Px bL, bR, cL, cR;
     unpack(nb, vR, bL, bR);
     unpack(nc, vR, cL, cR);
-    if (r + 2 <= R1) {
-      fetch(a, row_idx(r + 2), row_ok(r + 2) && vL, nb);
-      fetch(a, row_idx(r + 3), row_ok(r + 3) && vL, nc);
+    if (it + 1 < npairs) {
+      fetch(a, row_idx(r + kStep), row_ok(r + kStep) && vL, nb);
+      fetch(a, row_idx(r + kStep + 1), row_ok(r + kStep + 1) && vL, nc);
     }
     float bomL = 0.f, bovL = 1.f, bomR = 0.f, bovR = 1.f, comL = 0.f, covL = 1.f, comR = 0.f,
           covR = 1.f;
@@ -283,53 +324,40 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, int tile, int lan
       pair_local<3>(bL, cL, ex && vL, bint && wL, bint && wL, cint && wL, lam, alpha, acc);
       pair_local<3>(bR, cR, ex && vR, bint && wR, bint && wR, cint && wR, lam, alpha, acc);
     }
-    // V4 on (r-1, r), then rows r-1 and r are final
-    if (r > R0 - 2) {
-      const bool av = per || (r - 1 >= 0 && r - 1 < H);
-      const bool aint = r - 1 >= R0 && r - 1 < R1;
-      const bool ex = av && bv;
-      pair_local<4>(aL, bL, ex && vL, aint && wL, aint && wL, bint && wL, lam, alpha, acc);
-      pair_local<4>(aR, bR, ex && vR, aint && wR, aint && wR, bint && wR, lam, alpha, acc);
-      if (aint) {
-        store_row(a, row_idx(r - 1), wL, wR, aL, aR);
-        if (DELTA) {
-          float m1, v1;
-          if (wL) {
-            totals(aL, m1, v1);
-            dmu = fmaxf(dmu, fabsf(m1 - aomL));
-            dv = fmaxf(dv, fabsf(v1 / aovL - 1.f));
-            if (!(fabsf(m1) < 3.0e38f) || !(v1 > 0.f && v1 < 3.0e38f)) flags |= FLAG_NONFINITE;
-          }
-          if (wR) {
-            totals(aR, m1, v1);
-            dmu = fmaxf(dmu, fabsf(m1 - aomR));
-            dv = fmaxf(dv, fabsf(v1 / aovR - 1.f));
-            if (!(fabsf(m1) < 3.0e38f) || !(v1 > 0.f && v1 < 3.0e38f)) flags |= FLAG_NONFINITE;
-          }
-        }
+    if (!UP) {
+      // V4 on (r-1, r), then rows r-1 and r are final
+      if (it > 0) {
+        const bool aint = row_in(r - 1);
+        const bool ex = row_ok(r - 1) && bv;
+        pair_local<4>(aL, bL, ex && vL, aint && wL, aint && wL, bint && wL, lam, alpha, acc);
+        pair_local<4>(aR, bR, ex && vR, aint && wR, aint && wR, bint && wR, lam, alpha, acc);
+        if (aint)
+          finish_row<DELTA>(a, row_idx(r - 1), wL, wR, aL, aR, aomL, aovL, aomR, aovR, dmu, dv,
+                            flags);
       }
-    }
-    if (bint) {
-      store_row(a, ib, wL, wR, bL, bR);
-      if (DELTA) {
-        float m1, v1;
-        if (wL) {
-          totals(bL, m1, v1);
-          dmu = fmaxf(dmu, fabsf(m1 - bomL));
-          dv = fmaxf(dv, fabsf(v1 / bovL - 1.f));
-          if (!(fabsf(m1) < 3.0e38f) || !(v1 > 0.f && v1 < 3.0e38f)) flags |= FLAG_NONFINITE;
-        }
-        if (wR) {
-          totals(bR, m1, v1);
-          dmu = fmaxf(dmu, fabsf(m1 - bomR));
-          dv = fmaxf(dv, fabsf(v1 / bovR - 1.f));
-          if (!(fabsf(m1) < 3.0e38f) || !(v1 > 0.f && v1 < 3.0e38f)) flags |= FLAG_NONFINITE;
-        }
+      if (bint)
+        finish_row<DELTA>(a, row_idx(r), wL, wR, bL, bR, bomL, bovL, bomR, bovR, dmu, dv, flags);
+      aL = cL;
+      aR = cR;
+      aomL = comL; aovL = covL; aomR = comR; aovR = covR;
+    } else {
+      // V4 on (r+1, r+2), then rows r+1 and r+2 are final
+      if (it > 0) {
+        const bool aint = row_in(r + 2);
+        const bool ex = cv && row_ok(r + 2);
+        pair_local<4>(cL, aL, ex && vL, cint && wL, cint && wL, aint && wL, lam, alpha, acc);
+        pair_local<4>(cR, aR, ex && vR, cint && wR, cint && wR, aint && wR, lam, alpha, acc);
+        if (aint)
+          finish_row<DELTA>(a, row_idx(r + 2), wL, wR, aL, aR, aomL, aovL, aomR, aovR, dmu, dv,
+                            flags);
       }
+      if (cint)
+        finish_row<DELTA>(a, row_idx(r + 1), wL, wR, cL, cR, comL, covL, comR, covR, dmu, dv,
+                          flags);
+      aL = bL;
+      aR = bR;
+      aomL = bomL; aovL = bovL; aomR = bomR; aovR = bovR;
     }
-    aL = cL;
-    aR = cR;
-    aomL = comL; aovL = covL; aomR = comR; aovR = covR;
   }
 
   // wave reductions (fixed order -> deterministic)
@@ -371,7 +399,10 @@ __global__ __launch_bounds__(256) void k_tv_sweep(SweepArgs a) {
     }
     return;
   }
-  sweep_tile<DELTA>(a, tile, lane);
+  if (td.z & 1)
+    sweep_tile<DELTA, false>(a, tile, lane);
+  else
+    sweep_tile<DELTA, true>(a, tile, lane);
 }
 
 __global__ __launch_bounds__(256) void k_tilted(int n, const float* __restrict__ m,
