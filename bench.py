@@ -161,6 +161,10 @@ def main():
     y = torch.tensor(p.y, dtype=torch.float32, device=dev).contiguous()
     ctx.ep_tv_set_observation([y])
     ctx.ep_tv_run(args.warmup, em)
+    # tile height of the sweep chosen by the autotuner (times the sweep kernel
+    # only and leaves the EP state unchanged)
+    tune = ctx.ep_tv_autotune(5)
+    print(f"[bench] autotune: {tune}", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
 
     # timed region: K sweeps from a cold start
@@ -204,7 +208,7 @@ def main():
     if not args.no_cpu_baseline:
         print("[bench] timing the oracle on the host", file=sys.stderr, flush=True)
         cpu = cpu_baseline(args.workload, args.cpu_size, args.cpu_sweeps)
-    return emit(args, p, em, h, w, value, dt, roofline, cpu, conv, tm, roof_sweep)
+    return emit(args, p, em, h, w, value, dt, roofline, cpu, conv, tm, roof_sweep, tune)
 
 
 def bench_batch(args, ps, em):
@@ -334,7 +338,7 @@ def converge(ctx, args, em, p, y, dev, torch):
     return conv
 
 
-def emit(args, p, em, h, w, value, dt, roofline, cpu, conv, tm, roof_sweep):
+def emit(args, p, em, h, w, value, dt, roofline, cpu, conv, tm, roof_sweep, tune):
     E = edges(h, w)
     line = {
         "metric": "EP factor-updates/s + s to converged 2048^2 deconv, warm-start vs plain, 1 GPU",
@@ -342,7 +346,8 @@ def emit(args, p, em, h, w, value, dt, roofline, cpu, conv, tm, roof_sweep):
         "warmup": args.warmup, "ms_per_step": dt * 1e3 / args.steps, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": args.workload, "height": h, "width": w, "op": p.op, "em": em,
-                   "edges_per_sweep": E, "damping": p.damping, "xi": p.xi},
+                   "edges_per_sweep": E, "damping": p.damping, "xi": p.xi,
+                   "tile_rows": tune["tile_rows"]},
         "roofline": roofline, "roofline_sweep": roof_sweep, "cpu_baseline": cpu, "convergence": conv,
         "timing_ms": {"sweep": tm["sweep_ms"], "likelihood": tm["lik_ms"],
                       "cg_products": tm["apply_ms"], "cg_products_launches": tm["apply_launches"],

@@ -261,16 +261,18 @@ int ep_tv_get_option(ep_tv_ctx* ctx, int32_t option, int64_t* value);
 
 /* Autotuner of the TV-sweep tile height: times the sweep kernel (repeats
  * launches per candidate, HIP events, on the context's stream and current
- * state, which it leaves unchanged) for tile heights 8, 16, 32, 64 and 128 rows
- * (heights that give the same tiling as a smaller one are skipped), keeps the
+ * state, which it leaves unchanged) for the even tile heights 8, 10, 12, 14, 16,
+ * 18, 20, 24, 28, 32, 40, 48, 64, 96 and 128 rows (heights that give the same
+ * tiling as a smaller one are skipped; heights that are not a power of two let
+ * the tile count fit a whole number of rounds of resident waves), keeps the
  * fastest for this context and records it for later contexts with the same set
  * of image sizes in this process (ep_tv_workspace_bytes and ep_tv_create then
  * start from it).  Needs an observation.  Synchronises.  out (host) may be NULL. */
 typedef struct {
   int32_t tile_rows;           /* chosen height */
   int32_t candidates;          /* entries used in rows / ms */
-  int32_t rows[8];
-  double ms[8];                /* mean sweep-kernel time per candidate */
+  int32_t rows[16];
+  double ms[16];               /* mean sweep-kernel time per candidate */
   double best_ms;              /* time of the chosen height */
   double default_ms;           /* time of the height in use before tuning */
 } ep_tv_tune_result;

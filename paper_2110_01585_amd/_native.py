@@ -65,7 +65,7 @@ class EpTvTiming(ctypes.Structure):
 
 class EpTvTuneResult(ctypes.Structure):
     _fields_ = [("tile_rows", ctypes.c_int32), ("candidates", ctypes.c_int32),
-                ("rows", ctypes.c_int32 * 8), ("ms", ctypes.c_double * 8),
+                ("rows", ctypes.c_int32 * 16), ("ms", ctypes.c_double * 16),
                 ("best_ms", ctypes.c_double), ("default_ms", ctypes.c_double)]
 
 

@@ -48,8 +48,8 @@ struct Layout {
 
 // Tile heights (rows per sweep tile) the autotuner tries; all even, since the
 // sweep marches row pairs.
-constexpr int kTuneRows[] = {8, 16, 32, 64, 128};
-constexpr int kNumTuneRows = 5;
+constexpr int kTuneRows[] = {8, 10, 12, 14, 16, 18, 20, 24, 28, 32, 40, 48, 64, 96, 128};
+constexpr int kNumTuneRows = 15;
 constexpr int kMinChunkRows = 8;
 
 int env_chunk_rows() {
@@ -960,7 +960,7 @@ int ep_tv_autotune(ep_tv_ctx* c, int32_t repeats, ep_tv_tune_result* out) {
     if (rc == EP_TV_OK) rc = hip_check(c, hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
     if (rc != EP_TV_OK) break;
     const double per = ms / repeats;
-    if (r.candidates < 8) {
+    if (r.candidates < 16) {
       r.rows[r.candidates] = rows;
       r.ms[r.candidates] = per;
       r.candidates += 1;
