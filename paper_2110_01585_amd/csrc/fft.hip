@@ -182,9 +182,15 @@ __device__ __forceinline__ void fft_passes(float2* X, int rows, const float2* __
   }
 }
 
+
+// Complex rows per workgroup of the row-transform kernels for length L; the
+// kernels' LDS arrays, their launch grids and the RF_INV partial counts all
+// follow from this one definition.
+constexpr int rows_per_block(int L) { return L >= 4096 ? 1 : (4096 / L > 16 ? 16 : 4096 / L); }
+
 template <int L>
 __global__ __launch_bounds__(256) void k_fft_rows(FftArgs a) {
-  constexpr int kRows = L >= 4096 ? 1 : (4096 / L > 16 ? 16 : 4096 / L);
+  constexpr int kRows = rows_per_block(L);
   __shared__ float2 X[Padded<kRows * L>::value];
   const int row0 = blockIdx.x * kRows;
   const int rows = min(kRows, a.nrows - row0);
@@ -296,7 +302,7 @@ struct RfftArgs {
 
 template <int L, int STAGE>
 __global__ __launch_bounds__(256) void k_rfft(RfftArgs a) {
-  constexpr int kRows = L >= 4096 ? 1 : (4096 / L > 16 ? 16 : 4096 / L);
+  constexpr int kRows = rows_per_block(L);
   __shared__ float2 X[Padded<kRows * L>::value];
   __shared__ float2 TW[L];            // twiddle table, read by every pass
   const int row0 = blockIdx.x * kRows;
@@ -541,7 +547,7 @@ static int ilog2(int n) {
 
 template <int L>
 static void launch_rows(const FftArgs& a, hipStream_t s) {
-  constexpr int kRows = L >= 4096 ? 1 : (4096 / L > 16 ? 16 : 4096 / L);
+  constexpr int kRows = rows_per_block(L);
   hipLaunchKernelGGL(k_fft_rows<L>, dim3((a.nrows + kRows - 1) / kRows), dim3(256), 0, s, a);
 }
 
@@ -565,7 +571,7 @@ static hipError_t rows(const FftArgs& a, hipStream_t s) {
 
 template <int L, int STAGE>
 static void launch_rfft_t(const RfftArgs& a, hipStream_t s) {
-  constexpr int kRows = L >= 4096 ? 1 : (4096 / L > 16 ? 16 : 4096 / L);
+  constexpr int kRows = rows_per_block(L);
   hipLaunchKernelGGL((k_rfft<L, STAGE>), dim3((a.nrows + kRows - 1) / kRows), dim3(256), 0, s, a);
 }
 
@@ -590,7 +596,7 @@ static hipError_t launch_rfft(int L, const RfftArgs& a, hipStream_t s) {
 
 // Number of partial-sum slots the RF_INV stage of an H x W instance writes.
 int rfft_partials(int H, int W) {
-  const int kRows = W >= 4096 ? 1 : (4096 / W > 16 ? 16 : 4096 / W);
+  const int kRows = rows_per_block(W);
   return (H / 2 + kRows - 1) / kRows;
 }
 

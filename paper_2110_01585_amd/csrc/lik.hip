@@ -216,7 +216,7 @@ __global__ __launch_bounds__(256) void k_apply(LikArgs A) {
   constexpr int EHMAX = kLikTH + 2 * kMaxRadius;
   __shared__ float P[EHMAX * EWMAX];          // v on the tile plus halo
   __shared__ float T[EHMAX * EWMAX];          // first-pass result
-  const int tile = blockIdx.x;
+  const int tile = xcd_remap(blockIdx.x, gridDim.x);   // neighbours share an L2
   const int4 td = A.tiles[tile];
   const LikInst L = A.inst[td.x];
   const InstState& st = A.st[L.inst];
@@ -282,7 +282,7 @@ __global__ __launch_bounds__(256) void k_hth_sep(LikArgs A) {
   __shared__ float P[EH * EW];
   __shared__ float T[EH * kLikTW];
   __shared__ float gr[NT], gc[NT];
-  const int tile = blockIdx.x;
+  const int tile = xcd_remap(blockIdx.x, gridDim.x);   // neighbours share an L2
   const int4 td = A.tiles[tile];
   const LikInst L = A.inst[td.x];
   const InstState& st = A.st[L.inst];
@@ -557,6 +557,7 @@ hipError_t lik_create(LikCtx& lc, const LikInstInfo* li, int n, char* ws, const 
     d.cg_max_iters = I.cg_max_iters;
     d.precond = lik_precond(I.op, I.H, I.W, I.precond_req);
     d.npart = d.precond == PRECOND_CIRCULANT ? rfft_partials(I.H, I.W) : d.ntiles;
+    if (d.npart > d.ntiles) return hipErrorInvalidValue;   // partial slots are per tile
     lc.max_iters = std::max(lc.max_iters, I.cg_max_iters);
     const int li_idx = (int)lc.hinst.size();
     for (int yy = 0; yy < ty; ++yy)

@@ -202,6 +202,43 @@ __device__ __forceinline__ int wrap(int i, int n) {
   return r < 0 ? r + n : r;
 }
 
+// V4 pair across a boundary shared with a neighbouring wave of the block: both
+// waves publish the class-4 cavity (c, m) of their boundary pixels in LDS, then
+// each evaluates the pair (top, bottom) from the same inputs and keeps the
+// update of its own pixel.  Every wave of the block calls this at the same two
+// points (after its first and after its last row pair), shared boundary or not,
+// so the barriers match.  X: LDS, [2 phases][kWavesPerBlock][kWave].
+__device__ __forceinline__ void pair_x4_one(Px& own, bool own_top, float co, float mo, float cp,
+                                            float mp, bool exists, bool own_int, float lam,
+                                            float alpha, Acc& acc) {
+  const float ci = own_top ? co : cp, mi = own_top ? mo : mp;
+  const float cj = own_top ? cp : co, mj = own_top ? mp : mo;
+  const PairOut o = pair_core(ci, mi, cj, mj, lam);
+  if (exists) {
+    damp<4>(own, own_top ? o.ti : o.tj, own_top ? o.ei : o.ej, alpha);
+    if (own_top && own_int) acc.eabs += (double)o.eabs;   // the top pixel's wave counts the edge
+    acc.clamps += (own_int && (own_top ? o.ki : o.kj)) ? 1u : 0u;
+  }
+}
+
+__device__ __forceinline__ void exchange_v4(float4* X, int phase, int wave, int partner, int lane,
+                                            bool shared, Px& oL, Px& oR, bool own_top, bool vL,
+                                            bool vR, bool wL, bool wR, float lam, float alpha,
+                                            Acc& acc) {
+  float cL = 0.f, mL = 0.f, cR = 0.f, mR = 0.f;
+  if (shared) {
+    cavity<4>(oL, cL, mL);
+    cavity<4>(oR, cR, mR);
+    X[(phase * kWavesPerBlock + wave) * kWave + lane] = make_float4(cL, mL, cR, mR);
+  }
+  __syncthreads();
+  if (shared) {
+    const float4 q = X[(phase * kWavesPerBlock + partner) * kWave + lane];
+    pair_x4_one(oL, own_top, cL, mL, q.x, q.y, vL, wL, lam, alpha, acc);
+    pair_x4_one(oR, own_top, cR, mR, q.z, q.w, vR, wR, lam, alpha, acc);
+  }
+}
+
 // Store a final row of the strip and fold its change into the convergence
 // measures (DELTA): largest |mu - mu_old| and |v / v_old - 1| over stored pixels.
 template <bool DELTA>
@@ -241,7 +278,8 @@ __device__ __forceinline__ void finish_row(const SweepArgs& a, long long idx, bo
 //   up:   pair (r, r+1), then V4 on (r+1, r+2) with row r+2 carried; rows
 //         r+1, r+2 are final; row r is carried.
 template <bool DELTA, bool UP>
-__device__ __forceinline__ void sweep_tile(const SweepArgs& a, int tile, int lane) {
+__device__ __forceinline__ void sweep_tile(const SweepArgs& a, int tile, int wave, int lane,
+                                           bool x_start, bool x_end, float4* X) {
   const int4 td = a.tiles[tile];
   const InstDev I = a.inst[td.x];
   const InstState& ST = a.st[td.x];
@@ -270,8 +308,15 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, int tile, int lan
 
   const int R0 = td.z * I.chunk_rows;
   const int R1 = min(R0 + I.chunk_rows, H);
-  const int npairs = (R1 - R0 + 2) / 2 + 1;       // r = R0-2 .. R0-2 + 2 (npairs-1)
-  const int rfirst = UP ? R0 - 2 + 2 * (npairs - 1) : R0 - 2;
+  // row pairs (r, r+1), r = lo, lo+2, ..., hi: two halo rows beyond each boundary
+  // that is not shared with a neighbouring wave of the block (x_start: the
+  // boundary where the march starts, x_end: where it ends)
+  const bool sh_top = UP ? x_end : x_start;
+  const bool sh_bot = UP ? x_start : x_end;
+  const int lo = sh_top ? R0 : R0 - 2;
+  const int hi = sh_bot ? R1 - 2 : R0 - 2 + 2 * ((R1 - R0 + 2) / 2);
+  const int npairs = (hi - lo) / 2 + 1;
+  const int rfirst = UP ? hi : lo;
   constexpr int kStep = UP ? -2 : 2;
 
   Acc acc{0.0, 0u};
@@ -334,6 +379,10 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, int tile, int lan
         if (aint)
           finish_row<DELTA>(a, row_idx(r - 1), wL, wR, aL, aR, aomL, aovL, aomR, aovR, dmu, dv,
                             flags);
+      } else {
+        // shared top boundary: row R0 pairs with the wave above's row R0-1
+        exchange_v4(X, 0, wave, wave - 1, lane, x_start, bL, bR, false, vL, vR, wL, wR, lam, alpha,
+                    acc);
       }
       if (bint)
         finish_row<DELTA>(a, row_idx(r), wL, wR, bL, bR, bomL, bovL, bomR, bovR, dmu, dv, flags);
@@ -350,6 +399,10 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, int tile, int lan
         if (aint)
           finish_row<DELTA>(a, row_idx(r + 2), wL, wR, aL, aR, aomL, aovL, aomR, aovR, dmu, dv,
                             flags);
+      } else {
+        // shared bottom boundary: row R1-1 pairs with the wave below's row R1
+        exchange_v4(X, 0, wave, wave + 1, lane, x_start, cL, cR, true, vL, vR, wL, wR, lam, alpha,
+                    acc);
       }
       if (cint)
         finish_row<DELTA>(a, row_idx(r + 1), wL, wR, cL, cR, comL, covL, comR, covR, dmu, dv,
@@ -358,6 +411,17 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, int tile, int lan
       aR = bR;
       aomL = bomL; aovL = bovL; aomR = bomR; aovR = bovR;
     }
+  }
+  // the boundary where the march ends: the carried row pairs with the
+  // neighbouring wave's row and is final after that
+  if (!UP) {
+    exchange_v4(X, 1, wave, wave + 1, lane, x_end, aL, aR, true, vL, vR, wL, wR, lam, alpha, acc);
+    if (x_end)
+      finish_row<DELTA>(a, row_idx(R1 - 1), wL, wR, aL, aR, aomL, aovL, aomR, aovR, dmu, dv, flags);
+  } else {
+    exchange_v4(X, 1, wave, wave - 1, lane, x_end, aL, aR, false, vL, vR, wL, wR, lam, alpha, acc);
+    if (x_end)
+      finish_row<DELTA>(a, row_idx(R0), wL, wR, aL, aR, aomL, aovL, aomR, aovR, dmu, dv, flags);
   }
 
   // wave reductions (fixed order -> deterministic)
@@ -380,29 +444,42 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, int tile, int lan
   }
 }
 
-// One wave per tile; consecutive tiles (vertically adjacent chunks of a strip,
-// which share halo rows) are mapped to the same XCD.
+// One wave per tile; consecutive tiles (vertically adjacent chunks of a strip)
+// form a block, whose shared boundaries exchange cavities in LDS instead of
+// recomputing halo rows; neighbouring blocks are mapped to the same XCD.
 template <bool DELTA>
-__global__ __launch_bounds__(256) void k_tv_sweep(SweepArgs a) {
+__global__ __launch_bounds__(kWavesPerBlock * kWave) void k_tv_sweep(SweepArgs a) {
+  __shared__ float4 X[2 * kWavesPerBlock * kWave];
   const int wave = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
   const int tile = xcd_remap(blockIdx.x, gridDim.x) * kWavesPerBlock + wave;
-  if (tile >= a.ntiles) return;
-  const int4 td = a.tiles[tile];
-  if (!a.st[td.x].active) {
-    if (lane == 0) {
+  const bool has = tile < a.ntiles;
+  const int4 td = has ? a.tiles[tile] : make_int4(0, 0, 0, 0);
+  if (!has || !a.st[td.x].active) {
+    if (has && lane == 0) {
       a.part_eabs[tile] = 0.0;
       a.part_dmu[tile] = 0.f;
       a.part_dv[tile] = 0.f;
       a.part_clamp[tile] = 0u;
       a.part_flags[tile] = 0u;
     }
+    __syncthreads();   // the two exchange points of the other waves
+    __syncthreads();
     return;
   }
+  bool sh_up = false, sh_dn = false;
+  if (wave > 0) {
+    const int4 t = a.tiles[tile - 1];
+    sh_up = t.x == td.x && t.y == td.y && t.z == td.z - 1;
+  }
+  if (wave < kWavesPerBlock - 1 && tile + 1 < a.ntiles) {
+    const int4 t = a.tiles[tile + 1];
+    sh_dn = t.x == td.x && t.y == td.y && t.z == td.z + 1;
+  }
   if (td.z & 1)
-    sweep_tile<DELTA, false>(a, tile, lane);
+    sweep_tile<DELTA, false>(a, tile, wave, lane, sh_up, sh_dn, X);
   else
-    sweep_tile<DELTA, true>(a, tile, lane);
+    sweep_tile<DELTA, true>(a, tile, wave, lane, sh_dn, sh_up, X);
 }
 
 __global__ __launch_bounds__(256) void k_tilted(int n, const float* __restrict__ m,
@@ -429,9 +506,9 @@ hipError_t launch_tv_sweep(const SweepArgs& a, bool want_delta, hipStream_t s) {
   const int blocks = (a.ntiles + kWavesPerBlock - 1) / kWavesPerBlock;
   if (blocks == 0) return hipSuccess;
   if (want_delta)
-    hipLaunchKernelGGL(k_tv_sweep<true>, dim3(blocks), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_tv_sweep<true>, dim3(blocks), dim3(kWavesPerBlock * kWave), 0, s, a);
   else
-    hipLaunchKernelGGL(k_tv_sweep<false>, dim3(blocks), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_tv_sweep<false>, dim3(blocks), dim3(kWavesPerBlock * kWave), 0, s, a);
   return hipGetLastError();
 }
 
