@@ -186,7 +186,7 @@ __device__ __forceinline__ void fft_passes(float2* X, int rows, const float2* __
 // Complex rows per workgroup of the row-transform kernels for length L; the
 // kernels' LDS arrays, their launch grids and the RF_INV partial counts all
 // follow from this one definition.
-constexpr int rows_per_block(int L) { return L >= 4096 ? 1 : (4096 / L > 16 ? 16 : 4096 / L); }
+constexpr int rows_per_block(int L) { return L >= 2048 ? 1 : (2048 / L > 16 ? 16 : 2048 / L); }
 
 template <int L>
 __global__ __launch_bounds__(256) void k_fft_rows(FftArgs a) {
@@ -318,46 +318,81 @@ __global__ __launch_bounds__(256) void k_rfft(RfftArgs a) {
       if (i < L) TW[i] = a.tw[i];
     }
     const float alpha = (float)st.cg_alpha;
-    #pragma unroll
-    for (int u_ = 0; u_ < (kRows * L + 255) / 256; ++u_) {
-      const int i = threadIdx.x + u_ * 256;
-      if (i >= rows * L) continue;
-      const int j = row0 + i / L, c = i % L;
-      float2 v;
-      if (STAGE == RF_FWD) {
-        const long long p = a.off + (long long)(2 * j) * a.pitch + c;
-        if (a.mode == RFM_PRECOND) {
-          if (a.update) {
-            const long long p1 = p + a.pitch;
-            const float r0 = a.r[p] - alpha * a.q[p], r1 = a.r[p1] - alpha * a.q[p1];
-            a.x[p] += alpha * a.p[p];
-            a.x[p1] += alpha * a.p[p1];
-            a.r[p] = r0;
-            a.r[p1] = r1;
-            v = make_float2(r0, r1);
+    const bool first = st.cg_it == 0;
+    const float beta = (float)st.cg_beta;
+    // In chunks of up to 8 elements per thread: every global load of a chunk
+    // is issued before its first global store (a store may alias the loaded
+    // planes as far as the compiler knows, which would serialise the loads).
+    constexpr int NU = (kRows * L + 255) / 256;
+    constexpr int CH = NU < 8 ? NU : 8;
+#pragma unroll
+    for (int b0 = 0; b0 < NU; b0 += CH) {
+      float2 la[CH], lb[CH], lc[CH], ld[CH];
+#pragma unroll
+      for (int k = 0; k < CH; ++k) {
+        const int i = threadIdx.x + (b0 + k) * 256;
+        la[k] = lb[k] = lc[k] = ld[k] = make_float2(0.f, 0.f);
+        if (b0 + k >= NU || i >= rows * L) continue;
+        const int j = row0 + i / L, c = i % L;
+        if (STAGE == RF_FWD) {
+          const long long p = a.off + (long long)(2 * j) * a.pitch + c;
+          const long long p1 = p + a.pitch;
+          if (a.mode == RFM_PRECOND) {
+            la[k] = make_float2(a.r[p], a.r[p1]);
+            if (a.update) {
+              lb[k] = make_float2(a.q[p], a.q[p1]);
+              lc[k] = make_float2(a.x[p], a.x[p1]);
+              ld[k] = make_float2(a.p[p], a.p[p1]);
+            }
           } else {
-            v = make_float2(a.r[p], a.r[p + a.pitch]);
+            la[k] = make_float2(a.z[p], a.z[p1]);
+            if (!first) lb[k] = make_float2(a.p_in[p], a.p_in[p1]);
           }
+        } else if (STAGE == RF_FILT) {
+          la[k] = a.src[(long long)j * L + c];
         } else {
-          const bool first = st.cg_it == 0;
-          const float beta = (float)st.cg_beta;
-          const float p0 = first ? a.z[p] : a.z[p] + beta * a.p_in[p];
-          const float p1 = first ? a.z[p + a.pitch] : a.z[p + a.pitch] + beta * a.p_in[p + a.pitch];
-          a.p[p] = p0;
-          a.p[p + a.pitch] = p1;
-          v = make_float2(p0, p1);
+          const bool lo = c <= half;
+          const int kk = lo ? c : L - c;
+          la[k] = a.src[(long long)(2 * j) * a.ld + kk];
+          lb[k] = a.src[(long long)(2 * j + 1) * a.ld + kk];
         }
-      } else if (STAGE == RF_FILT) {
-        v = a.src[(long long)j * L + c];
-      } else {
-        const bool lo = c <= half;
-        const int k = lo ? c : L - c;
-        float2 A = a.src[(long long)(2 * j) * a.ld + k];
-        float2 B = a.src[(long long)(2 * j + 1) * a.ld + k];
-        if (!lo) { A.y = -A.y; B.y = -B.y; }
-        v = make_float2(A.x - B.y, A.y + B.x);
       }
-      X[pidx(i)] = v;
+#pragma unroll
+      for (int k = 0; k < CH; ++k) {
+        const int i = threadIdx.x + (b0 + k) * 256;
+        if (b0 + k >= NU || i >= rows * L) continue;
+        const int j = row0 + i / L, c = i % L;
+        float2 v;
+        if (STAGE == RF_FWD) {
+          const long long p = a.off + (long long)(2 * j) * a.pitch + c;
+          const long long p1 = p + a.pitch;
+          if (a.mode == RFM_PRECOND) {
+            if (a.update) {
+              const float r0 = la[k].x - alpha * lb[k].x, r1 = la[k].y - alpha * lb[k].y;
+              a.x[p] = lc[k].x + alpha * ld[k].x;
+              a.x[p1] = lc[k].y + alpha * ld[k].y;
+              a.r[p] = r0;
+              a.r[p1] = r1;
+              v = make_float2(r0, r1);
+            } else {
+              v = la[k];
+            }
+          } else {
+            const float p0 = first ? la[k].x : la[k].x + beta * lb[k].x;
+            const float p1v = first ? la[k].y : la[k].y + beta * lb[k].y;
+            a.p[p] = p0;
+            a.p[p1] = p1v;
+            v = make_float2(p0, p1v);
+          }
+        } else if (STAGE == RF_FILT) {
+          v = la[k];
+        } else {
+          float2 A = la[k], B = lb[k];
+          if (!(c <= half)) { A.y = -A.y; B.y = -B.y; }
+          v = make_float2(A.x - B.y, A.y + B.x);
+        }
+        X[pidx(i)] = v;
+      }
     }
   }
   __syncthreads();
@@ -411,26 +446,47 @@ __global__ __launch_bounds__(256) void k_rfft(RfftArgs a) {
   } else {
     double s0 = 0.0, s1 = 0.0;
     if (!skip) {
-      #pragma unroll
-      for (int u_ = 0; u_ < (kRows * L + 255) / 256; ++u_) {
-        const int i = threadIdx.x + u_ * 256;
-        if (i >= rows * L) continue;
-        const int j = row0 + i / L, c = i % L;
-        const long long p = a.off + (long long)(2 * j) * a.pitch + c;
-        const long long p1 = p + a.pitch;
-        if (a.mode == RFM_PRECOND) {
-          const float z0 = X[pidx(i)].x, z1 = X[pidx(i)].y;
-          a.out[p] = z0;
-          a.out[p1] = z1;
-          const float r0 = a.r[p], r1 = a.r[p1];
-          s0 += (double)r0 * z0 + (double)r1 * z1;
-          s1 += (double)r0 * r0 + (double)r1 * r1;
-        } else {
-          const float v0 = a.p[p], v1 = a.p[p1];
-          const float q0 = X[pidx(i)].x + a.tauc[p] * v0, q1 = X[pidx(i)].y + a.tauc[p1] * v1;
-          a.out[p] = q0;
-          a.out[p1] = q1;
-          s0 += (double)v0 * q0 + (double)v1 * q1;
+      constexpr int NU = (kRows * L + 255) / 256;
+      constexpr int CH = NU < 8 ? NU : 8;
+#pragma unroll
+      for (int b0 = 0; b0 < NU; b0 += CH) {
+        float2 la[CH], lb[CH];   // r (precondition) or p and tau_c (product), loaded first
+#pragma unroll
+        for (int k = 0; k < CH; ++k) {
+          const int i = threadIdx.x + (b0 + k) * 256;
+          la[k] = lb[k] = make_float2(0.f, 0.f);
+          if (b0 + k >= NU || i >= rows * L) continue;
+          const int j = row0 + i / L, c = i % L;
+          const long long p = a.off + (long long)(2 * j) * a.pitch + c;
+          const long long p1 = p + a.pitch;
+          if (a.mode == RFM_PRECOND) {
+            la[k] = make_float2(a.r[p], a.r[p1]);
+          } else {
+            la[k] = make_float2(a.p[p], a.p[p1]);
+            lb[k] = make_float2(a.tauc[p], a.tauc[p1]);
+          }
+        }
+#pragma unroll
+        for (int k = 0; k < CH; ++k) {
+          const int i = threadIdx.x + (b0 + k) * 256;
+          if (b0 + k >= NU || i >= rows * L) continue;
+          const int j = row0 + i / L, c = i % L;
+          const long long p = a.off + (long long)(2 * j) * a.pitch + c;
+          const long long p1 = p + a.pitch;
+          if (a.mode == RFM_PRECOND) {
+            const float z0 = X[pidx(i)].x, z1 = X[pidx(i)].y;
+            a.out[p] = z0;
+            a.out[p1] = z1;
+            const float r0 = la[k].x, r1 = la[k].y;
+            s0 += (double)r0 * z0 + (double)r1 * z1;
+            s1 += (double)r0 * r0 + (double)r1 * r1;
+          } else {
+            const float v0 = la[k].x, v1 = la[k].y;
+            const float q0 = X[pidx(i)].x + lb[k].x * v0, q1 = X[pidx(i)].y + lb[k].y * v1;
+            a.out[p] = q0;
+            a.out[p1] = q1;
+            s0 += (double)v0 * q0 + (double)v1 * q1;
+          }
         }
       }
     }
@@ -458,14 +514,17 @@ __global__ __launch_bounds__(256) void k_transpose(const float2* __restrict__ in
   __shared__ float2 tile[64][65];
   const int bx = blockIdx.x * 64, by = blockIdx.y * 64;
   const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
-  #pragma unroll
-  for (int r = ty; r < 64; r += 4) {
+  // compile-time trip counts, so all 16 loads of a thread are in flight at once
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    const int r = ty + 4 * k;
     const int gr = by + r, gc = bx + tx;
     if (gr < H && gc < W) tile[r][tx] = in[(long long)gr * W + gc];
   }
   __syncthreads();
-  #pragma unroll
-  for (int r = ty; r < 64; r += 4) {
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    const int r = ty + 4 * k;
     const int gc = bx + r, gr = by + tx;   // output row = input column
     if (gc < W && gr < H) out[(long long)gc * H + gr] = tile[tx][r];
   }

@@ -300,23 +300,55 @@ __global__ __launch_bounds__(256) void k_hth_sep(LikArgs A) {
   const bool inner = t.r0 >= RT && t.c0 >= RT && t.r0 + kLikTH + RT <= L.H && t.c0 + kLikTW + RT <= L.W;
   const bool first = st.cg_it == 0;
   const float beta = (float)st.cg_beta;
-  for (int i = threadIdx.x; i < EH * EW; i += 256) {
+  // Every global load of the tile is issued before the first store (a store to
+  // p_out or q may alias the loaded planes as far as the compiler knows, so
+  // interleaving them would serialise the loads on memory latency).
+  constexpr int NL = (EH * EW + 255) / 256;     // halo elements per thread
+  constexpr int NO = kLikTH * kLikTW / 256;     // output pixels per thread
+  auto halo_index = [&](int i) {
     const int er = i / EW, ec = i - (i / EW) * EW;
     int gy = t.r0 - RT + er, gx = t.c0 - RT + ec;
     if (!inner) {   // periodic wrap; images smaller than the halo wrap more than once
       gy = wrapi(gy, L.H);
       gx = wrapi(gx, L.W);
     }
-    const long long p = L.off + (long long)gy * L.pitch + gx;
-    float v;
-    if (MODE == 0) {
-      v = A.x[p];
-    } else {
-      const float z = A.z[p];
-      v = first ? z : z + beta * A.p_in[p];
+    return L.off + (long long)gy * L.pitch + gx;
+  };
+  float zv[NL], pv[NL], tc[NO];
+#pragma unroll
+  for (int u = 0; u < NL; ++u) {
+    const int i = threadIdx.x + 256 * u;
+    zv[u] = 0.f;
+    pv[u] = 0.f;
+    if (i < EH * EW) {
+      const long long p = halo_index(i);
+      if (MODE == 0) {
+        zv[u] = A.x[p];
+      } else {
+        zv[u] = A.z[p];
+        if (!first) pv[u] = A.p_in[p];
+      }
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < NO; ++u) {
+    const int i = threadIdx.x + 256 * u;
+    const int orow = i / kLikTW, oc = i % kLikTW;
+    tc[u] = 0.f;
+    if (t.r0 + orow < L.H && t.c0 + oc < L.W)
+      tc[u] = A.tauc[L.off + (long long)(t.r0 + orow) * L.pitch + (t.c0 + oc)];
+  }
+#pragma unroll
+  for (int u = 0; u < NL; ++u) {
+    const int i = threadIdx.x + 256 * u;
+    if (i >= EH * EW) continue;
+    float v = zv[u];
+    if (MODE == 1) {
+      v = first ? zv[u] : zv[u] + beta * pv[u];
+      const int er = i / EW, ec = i - (i / EW) * EW;
       const int lr = er - RT, lc = ec - RT;
       if (lr >= 0 && lr < kLikTH && lc >= 0 && lc < kLikTW && t.r0 + lr < L.H && t.c0 + lc < L.W)
-        A.p_out[p] = v;
+        A.p_out[halo_index(i)] = v;
     }
     P[i] = v;
   }
@@ -332,7 +364,7 @@ __global__ __launch_bounds__(256) void k_hth_sep(LikArgs A) {
   __syncthreads();
   double dot = 0.0;
 #pragma unroll
-  for (int u = 0; u < kLikTH * kLikTW / 256; ++u) {
+  for (int u = 0; u < NO; ++u) {
     const int i = threadIdx.x + 256 * u;
     const int orow = i / kLikTW, oc = i % kLikTW;
     if (t.r0 + orow >= L.H || t.c0 + oc >= L.W) continue;
@@ -341,7 +373,7 @@ __global__ __launch_bounds__(256) void k_hth_sep(LikArgs A) {
     for (int d = 0; d < NT; ++d) acc += gr[d] * T[(orow + d) * kLikTW + oc];
     const long long p = L.off + (long long)(t.r0 + orow) * L.pitch + (t.c0 + oc);
     const float v = P[(orow + RT) * EW + oc + RT];
-    const float qv = acc * L.inv_xi + A.tauc[p] * v;
+    const float qv = acc * L.inv_xi + tc[u] * v;
     A.q[p] = qv;
     dot += (double)v * (double)qv;
   }
