@@ -36,27 +36,31 @@ HTH_BYTES_PER_PX = 20          # z, p_in, tau_c read; p_out, q written (float32)
 PMC_FILE = os.path.join(ROOT, "profiles", "pmc_traffic.json")
 
 
-def measured_traffic(kernel):
-    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
-    summary, or None when there is none or the kernel's source changed since."""
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch of `kernel` on `workload` from the committed rocprofv3
+    counter summary, or None when there is none for this workload or a source
+    file the kernel is built from changed since the counters were taken."""
     import hashlib
     try:
         with open(PMC_FILE) as f:
             rec = json.load(f).get(kernel)
     except (OSError, ValueError):
         return None
-    if not rec:
+    if not rec or rec.get("workload") != workload:
         return None
-    with open(os.path.join(ROOT, rec["source"]), "rb") as f:
-        if hashlib.sha256(f.read()).hexdigest() != rec["source_sha256"]:
-            return None
+    h = hashlib.sha256()
+    for src in rec["sources"]:
+        with open(os.path.join(ROOT, src), "rb") as f:
+            h.update(f.read())
+    if h.hexdigest() != rec["sources_sha256"]:
+        return None
     return rec["traffic_bytes_per_launch"]
 
 
-def roofline_entry(kernel, bytes_per_launch, avg_s):
+def roofline_entry(kernel, bytes_per_launch, avg_s, workload):
     achieved = bytes_per_launch / avg_s / 1e9
     return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(kernel),
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(kernel, workload),
             "kernel": kernel, "bytes_per_launch": bytes_per_launch,
             "avg_launch_us": round(avg_s * 1e6, 2)}
 
@@ -190,11 +194,11 @@ def main():
     # TV sites written once) and, for deconvolution, the H^T H kernel of the CG;
     # `roofline` is the one with the larger total time
     sweep_avg_s = tm["sweep_ms"] / max(tm["sweep_launches"], 1) / 1e3
-    roof_sweep = roofline_entry("k_tv_sweep", SWEEP_BYTES_PER_PX * h * w, sweep_avg_s)
+    roof_sweep = roofline_entry("k_tv_sweep", SWEEP_BYTES_PER_PX * h * w, sweep_avg_s, args.workload)
     roofline = roof_sweep
     if p.op == "blur" and tm["apply_launches"] > 0:
         apply_avg_s = tm["apply_ms"] / tm["apply_launches"] / 1e3
-        roof_apply = roofline_entry("k_hth_sep", HTH_BYTES_PER_PX * h * w, apply_avg_s)
+        roof_apply = roofline_entry("k_hth_sep", HTH_BYTES_PER_PX * h * w, apply_avg_s, args.workload)
         if tm["apply_ms"] > tm["sweep_ms"]:
             roofline = roof_apply
 
@@ -241,7 +245,7 @@ def bench_batch(args, ps, em):
     value = E * args.steps / dt
     print(f"[bench] {args.steps} sweeps in {dt * 1e3:.1f} ms", file=sys.stderr, flush=True)
     sweep_avg_s = tm["sweep_ms"] / max(tm["sweep_launches"], 1) / 1e3
-    roofline = roofline_entry("k_tv_sweep", SWEEP_BYTES_PER_PX * npx, sweep_avg_s)
+    roofline = roofline_entry("k_tv_sweep", SWEEP_BYTES_PER_PX * npx, sweep_avg_s, args.workload)
     conv = None
     if args.max_sweeps > 0:
         ctx.ep_tv_init_cold()
