@@ -170,15 +170,19 @@ __device__ __forceinline__ void stockham_pass(float2* X, int rows, const float2*
   __syncthreads();
 }
 
-// All passes of a length-L transform: radix 16 while at least 16 points per
-// butterfly remain, then one pass of the remaining radix (8, 4 or 2).
-template <int L, int Ns>
+// Largest radix of a pass in a workgroup that holds NP points.
+constexpr int max_radix(int NP) { return 16; }
+
+// All passes of a length-L transform: the largest radix while enough points per
+// butterfly remain, then one pass of the remaining radix.
+template <int L, int Ns, int NP>
 __device__ __forceinline__ void fft_passes(float2* X, int rows, const float2* __restrict__ tw,
                                            float sgn) {
   if constexpr (Ns < L) {
-    constexpr int R = (L / Ns) >= 16 ? 16 : (L / Ns);
+    constexpr int RM = max_radix(NP);
+    constexpr int R = (L / Ns) >= RM ? RM : (L / Ns);
     stockham_pass<R, Ns, L>(X, rows, tw, sgn);
-    fft_passes<L, Ns * R>(X, rows, tw, sgn);
+    fft_passes<L, Ns * R, NP>(X, rows, tw, sgn);
   }
 }
 
@@ -225,7 +229,7 @@ __global__ __launch_bounds__(256) void k_fft_rows(FftArgs a) {
   }
   __syncthreads();
   // ---- Stockham passes: radix 16 while possible, then 8, 4, 2 ----
-  if (a.logL > 0) fft_passes<L, 1>(X, rows, a.tw, a.inverse ? 1.f : -1.f);
+  if (a.logL > 0) fft_passes<L, 1, kRows * L>(X, rows, a.tw, a.inverse ? 1.f : -1.f);
   // ---- store (post-op) ----
   #pragma unroll
   for (int u_ = 0; u_ < (kRows * L + 255) / 256; ++u_) {
@@ -304,7 +308,6 @@ template <int L, int STAGE>
 __global__ __launch_bounds__(256) void k_rfft(RfftArgs a) {
   constexpr int kRows = rows_per_block(L);
   __shared__ float2 X[Padded<kRows * L>::value];
-  __shared__ float2 TW[L];            // twiddle table, read by every pass
   const int row0 = blockIdx.x * kRows;
   const int rows = min(kRows, a.nrows - row0);
   const int half = L / 2;
@@ -312,11 +315,6 @@ __global__ __launch_bounds__(256) void k_rfft(RfftArgs a) {
   const bool skip = st.cg_done != 0;   // uniform per launch (one instance)
   // ---- load ----
   if (!skip) {
-#pragma unroll
-    for (int u_ = 0; u_ < (L + 255) / 256; ++u_) {
-      const int i = threadIdx.x + u_ * 256;
-      if (i < L) TW[i] = a.tw[i];
-    }
     const float alpha = (float)st.cg_alpha;
     const bool first = st.cg_it == 0;
     const float beta = (float)st.cg_beta;
@@ -398,9 +396,9 @@ __global__ __launch_bounds__(256) void k_rfft(RfftArgs a) {
   __syncthreads();
   if (!skip) {
     if (STAGE == RF_FWD) {
-      fft_passes<L, 1>(X, rows, TW, -1.f);
+      fft_passes<L, 1, kRows * L>(X, rows, a.tw, -1.f);
     } else if (STAGE == RF_FILT) {
-      fft_passes<L, 1>(X, rows, TW, -1.f);
+      fft_passes<L, 1, kRows * L>(X, rows, a.tw, -1.f);
       const float dbar = (float)st.dbar;
       #pragma unroll
       for (int u_ = 0; u_ < (kRows * L + 255) / 256; ++u_) {
@@ -412,9 +410,9 @@ __global__ __launch_bounds__(256) void k_rfft(RfftArgs a) {
         X[pidx(i)] = make_float2(X[pidx(i)].x * m, X[pidx(i)].y * m);
       }
       __syncthreads();
-      fft_passes<L, 1>(X, rows, TW, 1.f);
+      fft_passes<L, 1, kRows * L>(X, rows, a.tw, 1.f);
     } else {
-      fft_passes<L, 1>(X, rows, TW, 1.f);
+      fft_passes<L, 1, kRows * L>(X, rows, a.tw, 1.f);
     }
   }
   // ---- store ----
@@ -508,23 +506,25 @@ __global__ __launch_bounds__(256) void k_rfft(RfftArgs a) {
   }
 }
 
-// out (W x H) = transpose of in (H x W), 64 x 64 tiles through LDS
+// out (W x H) = transpose of in (H x W), kTrT x kTrT tiles through padded LDS
+constexpr int kTrT = 32;
 __global__ __launch_bounds__(256) void k_transpose(const float2* __restrict__ in,
                                                    float2* __restrict__ out, int H, int W) {
-  __shared__ float2 tile[64][65];
-  const int bx = blockIdx.x * 64, by = blockIdx.y * 64;
-  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
-  // compile-time trip counts, so all 16 loads of a thread are in flight at once
+  constexpr int kRowsPer = 256 / kTrT;
+  __shared__ float2 tile[kTrT][kTrT + 1];
+  const int bx = blockIdx.x * kTrT, by = blockIdx.y * kTrT;
+  const int tx = threadIdx.x % kTrT, ty = threadIdx.x / kTrT;
+  // compile-time trip counts, so all loads of a thread are in flight at once
 #pragma unroll
-  for (int k = 0; k < 16; ++k) {
-    const int r = ty + 4 * k;
+  for (int k = 0; k < kTrT / kRowsPer; ++k) {
+    const int r = ty + kRowsPer * k;
     const int gr = by + r, gc = bx + tx;
     if (gr < H && gc < W) tile[r][tx] = in[(long long)gr * W + gc];
   }
   __syncthreads();
 #pragma unroll
-  for (int k = 0; k < 16; ++k) {
-    const int r = ty + 4 * k;
+  for (int k = 0; k < kTrT / kRowsPer; ++k) {
+    const int r = ty + kRowsPer * k;
     const int gc = bx + r, gr = by + tx;   // output row = input column
     if (gc < W && gr < H) out[(long long)gc * H + gr] = tile[tx][r];
   }
@@ -731,7 +731,7 @@ static hipError_t forward_into_B(DftPlan& d, FftArgs pre, const float* mul, floa
   pre.post = POST_COMPLEX; pre.inverse = 0;
   hipError_t e = rows(pre, s);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_transpose, dim3((d.W + 63) / 64, (d.H + 63) / 64), dim3(256), 0, s, d.A,
+  hipLaunchKernelGGL(k_transpose, dim3((d.W + kTrT - 1) / kTrT, (d.H + kTrT - 1) / kTrT), dim3(256), 0, s, d.A,
                      d.B, d.H, d.W);
   FftArgs c = pre;
   c.pre = PRE_COMPLEX; c.src = d.B; c.dst = d.B; c.tw = d.twH; c.nrows = d.W; c.L = d.H;
@@ -747,7 +747,7 @@ static hipError_t inverse_from_B(DftPlan& d, FftArgs post, hipStream_t s) {
   c.logL = d.logH; c.post = POST_COMPLEX; c.inverse = 1;
   hipError_t e = rows(c, s);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_transpose, dim3((d.H + 63) / 64, (d.W + 63) / 64), dim3(256), 0, s, d.B,
+  hipLaunchKernelGGL(k_transpose, dim3((d.H + kTrT - 1) / kTrT, (d.W + kTrT - 1) / kTrT), dim3(256), 0, s, d.B,
                      d.A, d.W, d.H);
   FftArgs r = post;
   r.pre = PRE_COMPLEX; r.src = d.A; r.tw = d.twW; r.nrows = d.H; r.L = d.W; r.logL = d.logW;
@@ -768,7 +768,7 @@ hipError_t dft_set_observation(LikCtx& lc, const float* const* d_y, hipStream_t 
     a.dst = d.A; a.tw = d.twW; a.nrows = d.H; a.L = d.W; a.logL = 0; a.post = POST_COMPLEX;
     hipError_t e = rows(a, s);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_transpose, dim3((d.W + 63) / 64, (d.H + 63) / 64), dim3(256), 0, s, d.A,
+    hipLaunchKernelGGL(k_transpose, dim3((d.W + kTrT - 1) / kTrT, (d.H + kTrT - 1) / kTrT), dim3(256), 0, s, d.A,
                        d.B, d.H, d.W);
     FftArgs post = base_args(lc, L);
     post.post = POST_REAL;
@@ -855,13 +855,13 @@ hipError_t rfft_cg(LikCtx& lc, int mode, int update, hipStream_t s) {
     f.dst = d.A; f.tw = d.twW; f.nrows = d.H / 2; f.logL = d.logW;
     hipError_t e = launch_rfft<RF_FWD>(d.W, f, s);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_transpose, dim3((Wh + 63) / 64, (d.H + 63) / 64), dim3(256), 0, s, d.A, d.B,
+    hipLaunchKernelGGL(k_transpose, dim3((Wh + kTrT - 1) / kTrT, (d.H + kTrT - 1) / kTrT), dim3(256), 0, s, d.A, d.B,
                        d.H, Wh);
     RfftArgs g = a;
     g.src = d.B; g.dst = d.B; g.tw = d.twH; g.nrows = Wh; g.logL = d.logH; g.specT = d.specT;
     g.scale = (float)(1.0 / ((double)d.H * d.W));
     if ((e = launch_rfft<RF_FILT>(d.H, g, s)) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_transpose, dim3((d.H + 63) / 64, (Wh + 63) / 64), dim3(256), 0, s, d.B, d.A,
+    hipLaunchKernelGGL(k_transpose, dim3((d.H + kTrT - 1) / kTrT, (Wh + kTrT - 1) / kTrT), dim3(256), 0, s, d.B, d.A,
                        Wh, d.H);
     RfftArgs v = a;
     v.src = d.A; v.tw = d.twW; v.nrows = d.H / 2; v.logL = d.logW;

@@ -77,6 +77,33 @@ __device__ __forceinline__ TileXY lik_tile(const int4 td, const LikInst& L) {
   return t;
 }
 
+// Element-wise work on one tile in two phases: load(u, p) for every pixel of
+// the tile (u < kTileItems, p its plane index), then op(u, p).  Every load of
+// the tile is in flight before the first store, which the compiler would not
+// arrange itself: a store through one plane may alias the others as far as it
+// knows.  Launched with 256 threads.
+constexpr int kTileItems = kLikTH * kLikTW / 256;
+template <class Load, class Op>
+__device__ __forceinline__ void tile_two_phase(const TileXY& t, const LikInst& L, Load&& load,
+                                               Op&& op) {
+  const int cols = t.c1 - t.c0;
+  const int n = cols * (t.r1 - t.r0);
+  long long pp[kTileItems];
+#pragma unroll
+  for (int u = 0; u < kTileItems; ++u) {
+    const int i = threadIdx.x + 256 * u;
+    pp[u] = -1;
+    if (i < n) {
+      const int r = t.r0 + i / cols, c = t.c0 + i % cols;
+      pp[u] = L.off + (long long)r * L.pitch + c;
+      load(u, pp[u]);
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < kTileItems; ++u)
+    if (pp[u] >= 0) op(u, pp[u]);
+}
+
 // ---------------------------------------------------------------------------
 // 1. cavity of site 0, right-hand side, warm start (and d_bar, ||b||^2 partials)
 __global__ __launch_bounds__(256) void k_lik_prep(LikArgs A, const float2* __restrict__ S0,
@@ -91,26 +118,27 @@ __global__ __launch_bounds__(256) void k_lik_prep(LikArgs A, const float2* __res
   double at = 0.0, ab = 0.0;
   if (st.active && (st.sweeps > 0 || st.warm)) {
     const TileXY t = lik_tile(td, L);
-    const int cols = t.c1 - t.c0;
-    const int n = cols * (t.r1 - t.r0);
     const bool init_x = !st.x_valid;
-    for (int i = threadIdx.x; i < n; i += blockDim.x) {
-      const int r = t.r0 + i / cols, c = t.c0 + i % cols;
-      const long long p = L.off + (long long)r * L.pitch + c;
-      const float2 s1 = S1[p], s2 = S2[p], s3 = S3[p], s4 = S4[p];
-      const double tc = (double)s1.x + (double)s2.x + (double)s3.x + (double)s4.x;
-      const double ec = (double)s1.y + (double)s2.y + (double)s3.y + (double)s4.y;
-      const float bv = (float)((double)A.hty[p] * (double)L.inv_xi + ec);
-      A.tauc[p] = (float)tc;
-      A.etac[p] = (float)ec;
-      A.b[p] = bv;
-      if (init_x) {
-        const float2 s0 = S0[p];
-        A.x[p] = (float)(((double)s0.y + ec) / ((double)s0.x + tc));
-      }
-      at += tc;
-      ab += (double)bv * (double)bv;
-    }
+    float2 s1[kTileItems], s2[kTileItems], s3[kTileItems], s4[kTileItems], s0[kTileItems];
+    float hy[kTileItems];
+    tile_two_phase(
+        t, L,
+        [&](int u, long long p) {
+          s1[u] = S1[p]; s2[u] = S2[p]; s3[u] = S3[p]; s4[u] = S4[p];
+          hy[u] = A.hty[p];
+          if (init_x) s0[u] = S0[p];
+        },
+        [&](int u, long long p) {
+          const double tc = (double)s1[u].x + (double)s2[u].x + (double)s3[u].x + (double)s4[u].x;
+          const double ec = (double)s1[u].y + (double)s2[u].y + (double)s3[u].y + (double)s4[u].y;
+          const float bv = (float)((double)hy[u] * (double)L.inv_xi + ec);
+          A.tauc[p] = (float)tc;
+          A.etac[p] = (float)ec;
+          A.b[p] = bv;
+          if (init_x) A.x[p] = (float)(((double)s0[u].y + ec) / ((double)s0[u].x + tc));
+          at += tc;
+          ab += (double)bv * (double)bv;
+        });
   }
   block_sum2(at, ab, &A.part0[tile], &A.part1[tile]);
 }
@@ -279,8 +307,8 @@ __global__ __launch_bounds__(256) void k_apply(LikArgs A) {
 template <int RT, int MODE>
 __global__ __launch_bounds__(256) void k_hth_sep(LikArgs A) {
   constexpr int EW = kLikTW + 2 * RT, EH = kLikTH + 2 * RT, NT = 2 * RT + 1;
-  __shared__ float P[EH * EW];
-  __shared__ float T[EH * kLikTW];
+  __shared__ __align__(16) float P[EH * EW];
+  __shared__ __align__(16) float T[EH * kLikTW];
   __shared__ float gr[NT], gc[NT];
   const int tile = xcd_remap(blockIdx.x, gridDim.x);   // neighbours share an L2
   const int4 td = A.tiles[tile];
@@ -303,8 +331,8 @@ __global__ __launch_bounds__(256) void k_hth_sep(LikArgs A) {
   // Every global load of the tile is issued before the first store (a store to
   // p_out or q may alias the loaded planes as far as the compiler knows, so
   // interleaving them would serialise the loads on memory latency).
-  constexpr int NL = (EH * EW + 255) / 256;     // halo elements per thread
-  constexpr int NO = kLikTH * kLikTW / 256;     // output pixels per thread
+  constexpr int NL = (EH * EW + 255) / 256;          // halo elements per thread
+  constexpr int NQ = kLikTH * kLikTW / 4 / 256;      // output quads (4 columns) per thread
   auto halo_index = [&](int i) {
     const int er = i / EW, ec = i - (i / EW) * EW;
     int gy = t.r0 - RT + er, gx = t.c0 - RT + ec;
@@ -314,7 +342,12 @@ __global__ __launch_bounds__(256) void k_hth_sep(LikArgs A) {
     }
     return L.off + (long long)gy * L.pitch + gx;
   };
-  float zv[NL], pv[NL], tc[NO];
+  // output quad u of this thread: row qrow(u), columns qcol(u) .. qcol(u) + 3
+  auto qrow = [&](int u) { return (int)(threadIdx.x + 256 * u) / (kLikTW / 4); };
+  auto qcol = [&](int u) { return 4 * ((int)(threadIdx.x + 256 * u) % (kLikTW / 4)); };
+  auto qfull = [&](int u) { return t.r0 + qrow(u) < L.H && t.c0 + qcol(u) + 3 < L.W; };
+  float zv[NL], pv[NL];
+  float4 tc[NQ];
 #pragma unroll
   for (int u = 0; u < NL; ++u) {
     const int i = threadIdx.x + 256 * u;
@@ -331,12 +364,17 @@ __global__ __launch_bounds__(256) void k_hth_sep(LikArgs A) {
     }
   }
 #pragma unroll
-  for (int u = 0; u < NO; ++u) {
-    const int i = threadIdx.x + 256 * u;
-    const int orow = i / kLikTW, oc = i % kLikTW;
-    tc[u] = 0.f;
-    if (t.r0 + orow < L.H && t.c0 + oc < L.W)
-      tc[u] = A.tauc[L.off + (long long)(t.r0 + orow) * L.pitch + (t.c0 + oc)];
+  for (int u = 0; u < NQ; ++u) {
+    const long long p = L.off + (long long)(t.r0 + qrow(u)) * L.pitch + (t.c0 + qcol(u));
+    float e[4] = {0.f, 0.f, 0.f, 0.f};
+    if (qfull(u)) {
+      tc[u] = *reinterpret_cast<const float4*>(A.tauc + p);
+    } else {
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+        if (t.r0 + qrow(u) < L.H && t.c0 + qcol(u) + k < L.W) e[k] = A.tauc[p + k];
+      tc[u] = make_float4(e[0], e[1], e[2], e[3]);
+    }
   }
 #pragma unroll
   for (int u = 0; u < NL; ++u) {
@@ -353,29 +391,58 @@ __global__ __launch_bounds__(256) void k_hth_sep(LikArgs A) {
     P[i] = v;
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < EH * kLikTW; i += 256) {
-    const int er = i / kLikTW, oc = i % kLikTW;
-    const float* row = P + er * EW + oc;
-    float acc = 0.f;
+  // row pass, four adjacent outputs per work item from 128-bit LDS reads
+  constexpr int NW = (NT + 3 + 3) / 4;               // float4 words of the input window
+  for (int w = threadIdx.x; w < EH * kLikTW / 4; w += 256) {
+    const int er = w / (kLikTW / 4), oc = 4 * (w % (kLikTW / 4));
+    float win[4 * NW];
 #pragma unroll
-    for (int d = 0; d < NT; ++d) acc += gc[d] * row[d];
-    T[i] = acc;
+    for (int q = 0; q < NW; ++q) {
+      const float4 x = *reinterpret_cast<const float4*>(P + er * EW + oc + 4 * q);
+      win[4 * q] = x.x; win[4 * q + 1] = x.y; win[4 * q + 2] = x.z; win[4 * q + 3] = x.w;
+    }
+    float acc[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int d = 0; d < NT; ++d) {
+      const float g = gc[d];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) acc[k] += g * win[k + d];
+    }
+    *reinterpret_cast<float4*>(T + er * kLikTW + oc) = make_float4(acc[0], acc[1], acc[2], acc[3]);
   }
   __syncthreads();
+  // column pass and q = H^T H p / xi + tau_c p, four adjacent columns per item
   double dot = 0.0;
 #pragma unroll
-  for (int u = 0; u < NO; ++u) {
-    const int i = threadIdx.x + 256 * u;
-    const int orow = i / kLikTW, oc = i % kLikTW;
+  for (int u = 0; u < NQ; ++u) {
+    const int orow = qrow(u), oc = qcol(u);
     if (t.r0 + orow >= L.H || t.c0 + oc >= L.W) continue;
-    float acc = 0.f;
+    float acc[4] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int d = 0; d < NT; ++d) acc += gr[d] * T[(orow + d) * kLikTW + oc];
+    for (int d = 0; d < NT; ++d) {
+      const float g = gr[d];
+      const float4 x = *reinterpret_cast<const float4*>(T + (orow + d) * kLikTW + oc);
+      acc[0] += g * x.x; acc[1] += g * x.y; acc[2] += g * x.z; acc[3] += g * x.w;
+    }
+    const float4 v4 = *reinterpret_cast<const float4*>(P + (orow + RT) * EW + oc + RT);
+    const float v[4] = {v4.x, v4.y, v4.z, v4.w};
+    const float tq[4] = {tc[u].x, tc[u].y, tc[u].z, tc[u].w};
+    float qv[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) qv[k] = acc[k] * L.inv_xi + tq[k] * v[k];
     const long long p = L.off + (long long)(t.r0 + orow) * L.pitch + (t.c0 + oc);
-    const float v = P[(orow + RT) * EW + oc + RT];
-    const float qv = acc * L.inv_xi + tc[u] * v;
-    A.q[p] = qv;
-    dot += (double)v * (double)qv;
+    if (qfull(u)) {
+      *reinterpret_cast<float4*>(A.q + p) = make_float4(qv[0], qv[1], qv[2], qv[3]);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) dot += (double)v[k] * (double)qv[k];
+    } else {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        if (t.c0 + oc + k >= L.W) continue;
+        A.q[p + k] = qv[k];
+        dot += (double)v[k] * (double)qv[k];
+      }
+    }
   }
   block_sum2(dot, 0.0, &A.part0[tile], &A.part1[tile]);
 }
@@ -389,13 +456,10 @@ __global__ __launch_bounds__(256) void k_cg_init(LikArgs A) {
   const InstState& st = A.st[L.inst];
   if (st.cg_done) return;
   const TileXY t = lik_tile(td, L);
-  const int cols = t.c1 - t.c0;
-  const int n = cols * (t.r1 - t.r0);
-  for (int i = threadIdx.x; i < n; i += blockDim.x) {
-    const int r = t.r0 + i / cols, c = t.c0 + i % cols;
-    const long long p = L.off + (long long)r * L.pitch + c;
-    A.r[p] = A.b[p] - A.q[p];
-  }
+  float bv[kTileItems], qv[kTileItems];
+  tile_two_phase(
+      t, L, [&](int u, long long p) { bv[u] = A.b[p]; qv[u] = A.q[p]; },
+      [&](int u, long long p) { A.r[p] = bv[u] - qv[u]; });
 }
 
 // 5b. z = M^{-1} r (Jacobi instances: here; circulant instances: z was written
@@ -408,23 +472,25 @@ __global__ __launch_bounds__(256) void k_precond_dot(LikArgs A) {
   double rz = 0.0, rr = 0.0;
   if (!st.cg_done) {
     const TileXY t = lik_tile(td, L);
-    const int cols = t.c1 - t.c0;
-    const int n = cols * (t.r1 - t.r0);
     const bool jac = L.precond == PRECOND_JACOBI;
-    for (int i = threadIdx.x; i < n; i += blockDim.x) {
-      const int r = t.r0 + i / cols, c = t.c0 + i % cols;
-      const long long p = L.off + (long long)r * L.pitch + c;
-      const float rv = A.r[p];
-      float zv;
-      if (jac) {
-        zv = rv / (L.diagA + A.tauc[p]);
-        A.z[p] = zv;
-      } else {
-        zv = A.z[p];
-      }
-      rz += (double)rv * (double)zv;
-      rr += (double)rv * (double)rv;
-    }
+    float rv[kTileItems], wv[kTileItems];   // r, and tau_c (Jacobi) or z
+    tile_two_phase(
+        t, L,
+        [&](int u, long long p) {
+          rv[u] = A.r[p];
+          wv[u] = jac ? A.tauc[p] : A.z[p];
+        },
+        [&](int u, long long p) {
+          float zv;
+          if (jac) {
+            zv = rv[u] / (L.diagA + wv[u]);
+            A.z[p] = zv;
+          } else {
+            zv = wv[u];
+          }
+          rz += (double)rv[u] * (double)zv;
+          rr += (double)rv[u] * (double)rv[u];
+        });
   }
   block_sum2(rz, rr, &A.part0[tile], &A.part1[tile]);
 }
@@ -438,14 +504,14 @@ __global__ __launch_bounds__(256) void k_cg_update(LikArgs A) {
   if (st.cg_done) return;
   const float alpha = (float)st.cg_alpha;
   const TileXY t = lik_tile(td, L);
-  const int cols = t.c1 - t.c0;
-  const int n = cols * (t.r1 - t.r0);
-  for (int i = threadIdx.x; i < n; i += blockDim.x) {
-    const int r = t.r0 + i / cols, c = t.c0 + i % cols;
-    const long long p = L.off + (long long)r * L.pitch + c;
-    A.x[p] += alpha * A.p_out[p];
-    A.r[p] -= alpha * A.q[p];
-  }
+  float xv[kTileItems], pv[kTileItems], rv[kTileItems], qv[kTileItems];
+  tile_two_phase(
+      t, L,
+      [&](int u, long long p) { xv[u] = A.x[p]; pv[u] = A.p_out[p]; rv[u] = A.r[p]; qv[u] = A.q[p]; },
+      [&](int u, long long p) {
+        A.x[p] = xv[u] + alpha * pv[u];
+        A.r[p] = rv[u] - alpha * qv[u];
+      });
 }
 
 // 7. site update q_{x,0} from E = x (Eq. (update_q0_x)), clamp, damping
@@ -460,18 +526,18 @@ __global__ __launch_bounds__(256) void k_lik_site(LikArgs A, float2* __restrict_
     st.cg_total += st.cg_it;
   }
   const TileXY t = lik_tile(td, L);
-  const int cols = t.c1 - t.c0;
-  const int n = cols * (t.r1 - t.r0);
   float tau_new = (float)st.gamma;
   if (!(tau_new >= kPrecFloor)) tau_new = kPrecFloor;
   const float a = L.alpha;
-  for (int i = threadIdx.x; i < n; i += blockDim.x) {
-    const int r = t.r0 + i / cols, c = t.c0 + i % cols;
-    const long long p = L.off + (long long)r * L.pitch + c;
-    const float eta_new = (float)(((double)tau_new + (double)A.tauc[p]) * (double)A.x[p] - (double)A.etac[p]);
-    const float2 old = S0[p];
-    S0[p] = make_float2(a * tau_new + (1.f - a) * old.x, a * eta_new + (1.f - a) * old.y);
-  }
+  float tcv[kTileItems], xv[kTileItems], ecv[kTileItems];
+  float2 ov[kTileItems];
+  tile_two_phase(
+      t, L,
+      [&](int u, long long p) { tcv[u] = A.tauc[p]; xv[u] = A.x[p]; ecv[u] = A.etac[p]; ov[u] = S0[p]; },
+      [&](int u, long long p) {
+        const float eta_new = (float)(((double)tau_new + (double)tcv[u]) * (double)xv[u] - (double)ecv[u]);
+        S0[p] = make_float2(a * tau_new + (1.f - a) * ov[u].x, a * eta_new + (1.f - a) * ov[u].y);
+      });
 }
 
 // ---------------------------------------------------------------------------
