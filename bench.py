@@ -7,9 +7,11 @@ colour classes (cavity, tilted moments, site update, damping, clamp), and the
 EM update of lambda.  value = factor updates (edges per sweep x sweeps) per
 second of wall time over the K timed sweeps, inputs already resident on the GPU.
 
-Workloads (synthetic, seeded; see the design doc for the recipe):
+Workloads (synthetic, seeded; generators in synthetic.py):
   deconv2048  2048^2 deconvolution, 9x9 Gaussian blur sigma_b = 2 (periodic),
               sigma = 0.01, EM from lambda = 1, damping 0.5     [default]
+              (--launch graph [default]: each sweep replayed as a hipGraph;
+              --launch stream: every kernel launched on the stream)
   denoise128  128^2 denoising, sigma = 0.1, lambda = 10 fixed, damping 0.5
   denoise4096 4096^2 denoising, sigma = 0.1, EM (an HBM-resident probe of the sweep)
   batch256    256 instances, square sizes log-uniform in [64, 1024], 50/50 denoising /
@@ -138,6 +140,9 @@ def main():
     ap.add_argument("--max-sweeps", type=int, default=2000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-warm", action="store_true")
+    ap.add_argument("--launch", choices=("graph", "stream"), default="graph",
+                    help="single-image workloads: replay each sweep's launches as a hipGraph, "
+                         "or launch them one by one on the stream")
     ap.add_argument("--cpu-sweeps", type=int, default=4)
     ap.add_argument("--cpu-size", type=int, default=256)
     ap.add_argument("--copy-probe", action="store_true",
@@ -146,8 +151,7 @@ def main():
     if args.copy_probe:
         return copy_probe()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(see DESIGN.md for how the sweep would shard)", file=sys.stderr)
+        print("bench.py measures one GPU only: there is no multi-GPU path", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
@@ -164,6 +168,7 @@ def main():
     ctx = Context([spec_from_synthetic(p)], device=dev)
     y = torch.tensor(p.y, dtype=torch.float32, device=dev).contiguous()
     ctx.ep_tv_set_observation([y])
+    ctx.ep_tv_set_option(_native.OPT_GRAPH, 1 if args.launch == "graph" else 0)
     ctx.ep_tv_run(args.warmup, em)
     # tile height of the sweep chosen by the autotuner (times the sweep kernel
     # only and leaves the EP state unchanged)
@@ -183,6 +188,17 @@ def main():
     ctx.ep_tv_set_timing(False)
     st = ctx.ep_tv_get_stats()[0]
     dt = t1 - t0
+    if args.launch == "graph":
+        # kernel events are not recorded inside replayed graphs: the per-kernel
+        # durations come from the same sweeps launched on the stream
+        ctx.ep_tv_set_option(_native.OPT_GRAPH, 0)
+        ctx.ep_tv_init_cold()
+        ctx.ep_tv_set_timing(True)
+        ctx.ep_tv_run(args.steps, em)
+        tm = ctx.ep_tv_get_timing()
+        ctx.ep_tv_set_timing(False)
+        ctx.ep_tv_set_option(_native.OPT_GRAPH, 1)
+        torch.cuda.synchronize()
     E = edges(h, w)
     value = E * args.steps / dt
     print(f"[bench] {args.steps} sweeps in {dt*1e3:.1f} ms; sweep kernel {tm['sweep_ms']:.2f} ms / "
@@ -351,7 +367,12 @@ def emit(args, p, em, h, w, value, dt, roofline, cpu, conv, tm, roof_sweep, tune
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": args.workload, "height": h, "width": w, "op": p.op, "em": em,
                    "edges_per_sweep": E, "damping": p.damping, "xi": p.xi,
-                   "tile_rows": tune["tile_rows"]},
+                   "tile_rows": tune["tile_rows"], "launch": args.launch},
+        "kernel_timing": ("HIP events on the context's stream over the timed sweeps"
+                          if args.launch == "stream" else
+                          "HIP events on the context's stream over the same sweeps launched on "
+                          "the stream right after the timed graph replays (events are not "
+                          "recorded inside a replayed graph)"),
         "roofline": roofline, "roofline_sweep": roof_sweep, "cpu_baseline": cpu, "convergence": conv,
         "timing_ms": {"sweep": tm["sweep_ms"], "likelihood": tm["lik_ms"],
                       "cg_products": tm["apply_ms"], "cg_products_launches": tm["apply_launches"],

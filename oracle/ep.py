@@ -16,7 +16,7 @@ FREE boundary keeps only edges inside the image; PERIODIC (even sizes) adds the
 wrap edges (r, W-1)-(r, 0) to V2 and (H-1, c)-(0, c) to V4.  A pixel that no
 edge of V_k touches keeps the flat site (tau_k, eta_k) = (0, 0).
 
-One sweep t (readings of the paper's silent points are listed in the design doc):
+One sweep t (where the paper is silent, the reading taken is stated at the step):
   1. likelihood site (Eqs. (tilted_P_1), (update_q0_x)), skipped for H = I,
      where it is exact and constant, and in sweep 1, where the initial
      q_{x,0} of the initialisation line stands in for it;
