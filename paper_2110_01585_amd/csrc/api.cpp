@@ -220,6 +220,7 @@ struct ep_tv_ctx {
   bool has_obs = false;
   bool any_lik = false;
   std::vector<InstState> host_st;
+  InstState* pull_st = nullptr;      // pinned host staging for state pulls (allocated on first pull)
   std::vector<float*> tab_host0, tab_host1;
   double last_elapsed_ms = 0.0;
   std::string err;
@@ -681,9 +682,17 @@ int ep_tv_run(ep_tv_ctx* c, int32_t n_sweeps, int32_t em) {
 }
 
 static int pull_states(ep_tv_ctx* c) {
-  HIPCHK(c, hipMemcpyAsync(c->host_st.data(), c->d_st, sizeof(InstState) * c->n,
-                           hipMemcpyDeviceToHost, c->stream));
+  if (!c->pull_st) {   // pinned, so the copy goes straight to host memory
+    if (hipHostMalloc(reinterpret_cast<void**>(&c->pull_st), sizeof(InstState) * (size_t)c->n) !=
+        hipSuccess) {
+      c->pull_st = nullptr;
+      return fail(c, EP_TV_E_HIP, "hipHostMalloc of the state staging buffer failed");
+    }
+  }
+  HIPCHK(c, hipMemcpyAsync(c->pull_st, c->d_st, sizeof(InstState) * c->n, hipMemcpyDeviceToHost,
+                           c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
+  std::memcpy(c->host_st.data(), c->pull_st, sizeof(InstState) * c->n);
   return EP_TV_OK;
 }
 
@@ -998,6 +1007,7 @@ void ep_tv_destroy(ep_tv_ctx* c) {
   if (c->cap) (void)hipStreamDestroy(c->cap);
   lik_destroy(c->lik);
   for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
+  if (c->pull_st) (void)hipHostFree(c->pull_st);
   delete c;
 }
 

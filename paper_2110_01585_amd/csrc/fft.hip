@@ -509,8 +509,10 @@ __global__ __launch_bounds__(256) void k_rfft(RfftArgs a) {
 // out (W x H) = transpose of in (H x W), kTrT x kTrT tiles through padded LDS
 constexpr int kTrT = 32;
 __global__ __launch_bounds__(256) void k_transpose(const float2* __restrict__ in,
-                                                   float2* __restrict__ out, int H, int W) {
+                                                   float2* __restrict__ out, int H, int W,
+                                                   const InstState* __restrict__ st, int inst) {
   constexpr int kRowsPer = 256 / kTrT;
+  if (st && st[inst].cg_done) return;   // a finished CG's passes are skipped, so is this
   __shared__ float2 tile[kTrT][kTrT + 1];
   const int bx = blockIdx.x * kTrT, by = blockIdx.y * kTrT;
   const int tx = threadIdx.x % kTrT, ty = threadIdx.x / kTrT;
@@ -732,7 +734,7 @@ static hipError_t forward_into_B(DftPlan& d, FftArgs pre, const float* mul, floa
   hipError_t e = rows(pre, s);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_transpose, dim3((d.W + kTrT - 1) / kTrT, (d.H + kTrT - 1) / kTrT), dim3(256), 0, s, d.A,
-                     d.B, d.H, d.W);
+                     d.B, d.H, d.W, nullptr, 0);
   FftArgs c = pre;
   c.pre = PRE_COMPLEX; c.src = d.B; c.dst = d.B; c.tw = d.twH; c.nrows = d.W; c.L = d.H;
   c.logL = d.logH; c.post = post_mode; c.mul = mul; c.scale = scale;
@@ -748,7 +750,7 @@ static hipError_t inverse_from_B(DftPlan& d, FftArgs post, hipStream_t s) {
   hipError_t e = rows(c, s);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_transpose, dim3((d.H + kTrT - 1) / kTrT, (d.W + kTrT - 1) / kTrT), dim3(256), 0, s, d.B,
-                     d.A, d.W, d.H);
+                     d.A, d.W, d.H, nullptr, 0);
   FftArgs r = post;
   r.pre = PRE_COMPLEX; r.src = d.A; r.tw = d.twW; r.nrows = d.H; r.L = d.W; r.logL = d.logW;
   r.inverse = 1;
@@ -769,7 +771,7 @@ hipError_t dft_set_observation(LikCtx& lc, const float* const* d_y, hipStream_t 
     hipError_t e = rows(a, s);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_transpose, dim3((d.W + kTrT - 1) / kTrT, (d.H + kTrT - 1) / kTrT), dim3(256), 0, s, d.A,
-                       d.B, d.H, d.W);
+                       d.B, d.H, d.W, nullptr, 0);
     FftArgs post = base_args(lc, L);
     post.post = POST_REAL;
     post.real_out = lc.planes[LP_HTY];
@@ -856,13 +858,13 @@ hipError_t rfft_cg(LikCtx& lc, int mode, int update, hipStream_t s) {
     hipError_t e = launch_rfft<RF_FWD>(d.W, f, s);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_transpose, dim3((Wh + kTrT - 1) / kTrT, (d.H + kTrT - 1) / kTrT), dim3(256), 0, s, d.A, d.B,
-                       d.H, Wh);
+                       d.H, Wh, lc.d_st, L.inst);
     RfftArgs g = a;
     g.src = d.B; g.dst = d.B; g.tw = d.twH; g.nrows = Wh; g.logL = d.logH; g.specT = d.specT;
     g.scale = (float)(1.0 / ((double)d.H * d.W));
     if ((e = launch_rfft<RF_FILT>(d.H, g, s)) != hipSuccess) return e;
     hipLaunchKernelGGL(k_transpose, dim3((d.H + kTrT - 1) / kTrT, (Wh + kTrT - 1) / kTrT), dim3(256), 0, s, d.B, d.A,
-                       Wh, d.H);
+                       Wh, d.H, lc.d_st, L.inst);
     RfftArgs v = a;
     v.src = d.A; v.tw = d.twW; v.nrows = d.H / 2; v.logL = d.logW;
     v.out = lc.planes[mode == RFM_PRECOND ? LP_Z : LP_Q];

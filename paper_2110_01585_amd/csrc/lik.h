@@ -149,7 +149,7 @@ struct LikCtx {
   int pcur = 0;                      // which p plane holds the current search direction
   bool fast = false;                 // every instance circulant: CG products and preconditioner by real FFTs
   int max_iters = kCgMaxIters;       // largest per-instance CG cap
-  std::vector<InstState> hst;        // staging for convergence polls
+  InstState* hst = nullptr;          // pinned host staging for CG polls (allocated on first poll)
   int n_all = 0;
   // timing of H^T H applications
   bool timing = false;

@@ -746,7 +746,6 @@ hipError_t lik_create(LikCtx& lc, const LikInstInfo* li, int n, char* ws, const 
   e = hipGetLastError();
   if (e == hipSuccess) e = dft_setup(lc, li, n, L.fft_bytes, s, err);
   if (e != hipSuccess && err.empty()) err = hipGetErrorString(e);
-  lc.hst.resize(n);
   return e;
 }
 
@@ -900,7 +899,15 @@ hipError_t lik_iterations(LikCtx& lc, int n, hipStream_t s) {
 hipError_t lik_poll(LikCtx& lc, hipStream_t s, bool& all_done) {
   all_done = true;
   if (lc.nlik == 0) return hipSuccess;
-  hipError_t e = hipMemcpyAsync(lc.hst.data(), lc.d_st, sizeof(InstState) * lc.n_all,
+  if (!lc.hst) {   // pinned, so the copy goes straight to host memory
+    const hipError_t ea = hipHostMalloc(reinterpret_cast<void**>(&lc.hst),
+                                        sizeof(InstState) * (size_t)std::max(lc.n_all, 1));
+    if (ea != hipSuccess) {
+      lc.hst = nullptr;
+      return ea;
+    }
+  }
+  hipError_t e = hipMemcpyAsync(lc.hst, lc.d_st, sizeof(InstState) * lc.n_all,
                                 hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) return e;
@@ -930,6 +937,8 @@ hipError_t lik_update(LikCtx& lc, float2* const S[5], hipStream_t s) {
 void lik_destroy(LikCtx& lc) {
   for (hipEvent_t e : lc.ev) (void)hipEventDestroy(e);
   lc.ev.clear();
+  if (lc.hst) (void)hipHostFree(lc.hst);
+  lc.hst = nullptr;
   dft_destroy(lc);
 }
 
