@@ -392,12 +392,13 @@ __global__ __launch_bounds__(1024) void k_yrange(const float* __restrict__ y_pix
   __shared__ float smin[1024], smax[1024];
   const InstDev I = inst[blockIdx.x];
   float lo = 3.0e38f, hi = -3.0e38f;
-  const long long n = (long long)I.H * I.W;
-  for (long long i = threadIdx.x; i < n; i += blockDim.x) {
-    const int r = (int)(i / I.W), c = (int)(i % I.W);
-    const float v = y_pix[I.off + (long long)r * I.pitch + c];
-    lo = fminf(lo, v);
-    hi = fmaxf(hi, v);
+  for (int r = 0; r < I.H; ++r) {
+    const float* row = y_pix + I.off + (long long)r * I.pitch;
+    for (int c = threadIdx.x; c < I.W; c += blockDim.x) {
+      const float v = row[c];
+      lo = fminf(lo, v);
+      hi = fmaxf(hi, v);
+    }
   }
   smin[threadIdx.x] = lo;
   smax[threadIdx.x] = hi;

@@ -282,6 +282,8 @@ struct RfftArgs {
   int nrows;                 // complex rows processed (RF_FWD / RF_INV: H / 2; RF_FILT: W/2 + 1)
   int logL;
   int ld;                    // row stride of the half-spectrum array (W/2 + 1)
+  int tld;                   // RF_FWD output / RF_INV input: the half spectrum transposed,
+                             // element (row, k) at [k tld + row] (tld = H)
   int mode;                  // RFM_PRECOND or RFM_PRODUCT
   int update;                // RF_FWD precondition: first x += alpha p, r -= alpha q
   long long off;             // real planes (pitched)
@@ -308,7 +310,9 @@ template <int L, int STAGE>
 __global__ __launch_bounds__(256) void k_rfft(RfftArgs a) {
   constexpr int kRows = rows_per_block(L);
   __shared__ float2 X[Padded<kRows * L>::value];
-  const int row0 = blockIdx.x * kRows;
+  // neighbouring row blocks (which share the cache lines of the transposed
+  // half spectrum) run on one XCD
+  const int row0 = xcd_remap(blockIdx.x, gridDim.x) * kRows;
   const int rows = min(kRows, a.nrows - row0);
   const int half = L / 2;
   const InstState& st = a.st[a.inst];
@@ -351,8 +355,9 @@ __global__ __launch_bounds__(256) void k_rfft(RfftArgs a) {
         } else {
           const bool lo = c <= half;
           const int kk = lo ? c : L - c;
-          la[k] = a.src[(long long)(2 * j) * a.ld + kk];
-          lb[k] = a.src[(long long)(2 * j + 1) * a.ld + kk];
+          const float4 ab = *reinterpret_cast<const float4*>(a.src + (long long)kk * a.tld + 2 * j);
+          la[k] = make_float2(ab.x, ab.y);
+          lb[k] = make_float2(ab.z, ab.w);
         }
       }
 #pragma unroll
@@ -429,8 +434,7 @@ __global__ __launch_bounds__(256) void k_rfft(RfftArgs a) {
       const float2 sa = make_float2(0.5f * (zk.x + zm.x), 0.5f * (zk.y + zm.y));
       const float2 sb = make_float2(0.5f * (zk.y - zm.y), -0.5f * (zk.x - zm.x));   // (Z - conj) / 2i
       const int j = row0 + jr;
-      a.dst[(long long)(2 * j) * a.ld + k] = sa;
-      a.dst[(long long)(2 * j + 1) * a.ld + k] = sb;
+      *reinterpret_cast<float4*>(a.dst + (long long)k * a.tld + 2 * j) = make_float4(sa.x, sa.y, sb.x, sb.y);
     }
   } else if (STAGE == RF_FILT) {
     if (skip) return;
@@ -853,20 +857,19 @@ hipError_t rfft_cg(LikCtx& lc, int mode, int update, hipStream_t s) {
     a.p_in = lc.planes[lc.pcur ? LP_P1 : LP_P0];     // same ping-pong as the CG kernels
     a.p = lc.planes[lc.pcur ? LP_P0 : LP_P1];
     a.x = lc.planes[LP_X]; a.q = lc.planes[LP_Q];
+    // the row passes write and read the half spectrum transposed (W/2+1 rows of
+    // length H), which is the layout the column pass works in: no transposes
+    a.tld = d.H;
     RfftArgs f = a;
-    f.dst = d.A; f.tw = d.twW; f.nrows = d.H / 2; f.logL = d.logW;
+    f.dst = d.B; f.tw = d.twW; f.nrows = d.H / 2; f.logL = d.logW;
     hipError_t e = launch_rfft<RF_FWD>(d.W, f, s);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_transpose, dim3((Wh + kTrT - 1) / kTrT, (d.H + kTrT - 1) / kTrT), dim3(256), 0, s, d.A, d.B,
-                       d.H, Wh, lc.d_st, L.inst);
     RfftArgs g = a;
     g.src = d.B; g.dst = d.B; g.tw = d.twH; g.nrows = Wh; g.logL = d.logH; g.specT = d.specT;
     g.scale = (float)(1.0 / ((double)d.H * d.W));
     if ((e = launch_rfft<RF_FILT>(d.H, g, s)) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_transpose, dim3((d.H + kTrT - 1) / kTrT, (Wh + kTrT - 1) / kTrT), dim3(256), 0, s, d.B, d.A,
-                       Wh, d.H, lc.d_st, L.inst);
     RfftArgs v = a;
-    v.src = d.A; v.tw = d.twW; v.nrows = d.H / 2; v.logL = d.logW;
+    v.src = d.B; v.tw = d.twW; v.nrows = d.H / 2; v.logL = d.logW;
     v.out = lc.planes[mode == RFM_PRECOND ? LP_Z : LP_Q];
     v.part0 = lc.part0; v.part1 = lc.part1; v.part_base = L.tile0;
     if ((e = launch_rfft<RF_INV>(d.W, v, s)) != hipSuccess) return e;
