@@ -81,6 +81,30 @@ def test_graph_equals_direct_mixed_solve():
         assert sa[i]["sweeps"] == sb[i]["sweeps"] and sa[i]["cg_total"] == sb[i]["cg_total"]
 
 
+def test_graph_equals_direct_fast_cg():
+    """Power-of-two blur and masked-DFT instances: every likelihood solve takes
+    the real-FFT preconditioned CG.  A replayed graph runs a fixed number of CG
+    iterations between polls, so the iterations after convergence must leave
+    everything untouched: marginals, sweep counts and CG iteration totals are
+    the same as with direct launches, bit for bit."""
+    ps = [syn.make_deconv(128, 128, 8, 0.01, 2.0, syn.rng_for(97, 0), lam0=1.0, sweeps=40, em=True),
+          syn.make_cs(64, 64, 6, 0.01, 0.3, syn.rng_for(97, 1), sweeps=40, em=True)]
+    res = []
+    for graph in (False, True):
+        c = _ctx(ps, graph=graph)
+        mus = [torch.empty(*p.shape, device="cuda") for p in ps]
+        vs = [torch.empty(*p.shape, device="cuda") for p in ps]
+        rc, st = c.ep_tv_solve(60, 1e-6, True, mus, vs)
+        torch.cuda.synchronize()
+        res.append(([m.cpu().numpy() for m in mus], [v.cpu().numpy() for v in vs], st))
+        c.close()
+    (ma, va, sa), (mb, vb, sb) = res
+    for i in range(len(ps)):
+        assert sa[i]["cg_total"] > 0
+        assert np.array_equal(ma[i], mb[i]) and np.array_equal(va[i], vb[i]), ps[i].name
+        assert sa[i]["sweeps"] == sb[i]["sweeps"] and sa[i]["cg_total"] == sb[i]["cg_total"]
+
+
 def test_mixed_operators_batch_vs_oracle():
     """Blur, masked-DFT and identity instances in one context (each H^T H path
     must leave the other instances' products alone)."""
