@@ -13,8 +13,8 @@
 namespace eptv {
 
 constexpr int kMaxTaps = 17;
-constexpr int kLikTW = 64;       // likelihood-kernel tile: 64 columns x 32 rows
-constexpr int kLikTH = 32;
+constexpr int kLikTW = 64;       // likelihood-kernel tile: 64 columns x 16 rows
+constexpr int kLikTH = 16;
 constexpr int kMaxRadius = kMaxTaps - 1;   // radius of the combined H^T H kernel
 constexpr int kCgMaxIters = 200;
 constexpr double kCgTol = 1e-8;            // relative residual ||r|| / ||b||

@@ -14,7 +14,7 @@
 // clamped and damped like the colour-class sites.
 //
 // H^T H x for a periodic convolution is a periodic convolution with the
-// autocorrelation of the taps (radius kh-1, kw-1).  It is applied on 64 x 32
+// autocorrelation of the taps (radius kh-1, kw-1).  It is applied on 64 x 16
 // output tiles staged through LDS with the halo: two 1-D passes when the taps
 // are separable (rank one, e.g. Gaussian), otherwise H followed by H^T as two
 // 2-D passes.  Reductions (dot products, means) are per-tile FP64 partials
@@ -301,7 +301,7 @@ __global__ __launch_bounds__(256) void k_apply(LikArgs A) {
 // convolution with the autocorrelations g_r (rows) and g_c (columns) of the two
 // factors, radius RI <= RT each.  RT is a compile-time bound (taps beyond an
 // instance's own radius are zero), so the tile geometry and index arithmetic are
-// constants: the 64 x 32 output tile plus an RT halo is staged in LDS (periodic
+// constants: the 64 x 16 output tile plus an RT halo is staged in LDS (periodic
 // wrap only on border tiles), filtered along rows into a second LDS array, then
 // along columns.
 template <int RT, int MODE>
