@@ -815,12 +815,14 @@ static hipError_t timed(LikCtx& lc, std::vector<std::pair<int, int>>& bucket, hi
     }
     i0 = (int)lc.ev_used++;
     i1 = (int)lc.ev_used++;
-    hipEventRecord(lc.ev[i0], s);
+    const hipError_t e0 = hipEventRecord(lc.ev[i0], s);
+    if (e0 != hipSuccess) return e0;
   }
   hipError_t e = body();
   if (e != hipSuccess) return e;
   if (tm) {
-    hipEventRecord(lc.ev[i1], s);
+    const hipError_t e1 = hipEventRecord(lc.ev[i1], s);
+    if (e1 != hipSuccess) return e1;
     bucket.emplace_back(i0, i1);
   }
   return hipGetLastError();
