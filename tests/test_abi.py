@@ -19,7 +19,8 @@ HEADERS = [os.path.join(ROOT, "include", h) for h in sorted(os.listdir(os.path.j
 def _declared():
     names = set()
     for h in HEADERS:
-        src = re.sub(r"/\*.*?\*/", "", open(h).read(), flags=re.S)
+        with open(h) as f:
+            src = re.sub(r"/\*.*?\*/", "", f.read(), flags=re.S)
         names |= set(re.findall(r"\b(ep_tv_[a-z_0-9]+)\s*\(", src))
     return sorted(names)
 
