@@ -65,23 +65,25 @@ struct PairOut {
 // form tau_i = rho / (s - rho c_i), eta_i = tau_i E_i + delta / s (and i<->j,
 // delta -> -delta); variance clamp of Sec. III-C at 1e8.
 __device__ __forceinline__ PairOut pair_core(float ci, float mi, float cj, float mj, float lam) {
-  // no fused multiply-adds: the update of (i, j) must be the exact mirror of
-  // the update of (j, i)
+  // no contraction into fused multiply-adds: the update of (i, j) must be the
+  // exact mirror of the update of (j, i).  The fused multiply-adds written out
+  // map onto each other under the exchange (delta changes sign, s and rho do
+  // not), so they keep the mirror exact.
 #pragma clang fp contract(off)
   const float s = ci + cj;
   const Tilt T = laplace_tilt(mi - mj, s, lam);
   const float dels = T.delta * frcp(s);
-  const float Ei = mi + dels * ci;
-  const float Ej = mj - dels * cj;
+  const float Ei = __builtin_fmaf(dels, ci, mi);
+  const float Ej = __builtin_fmaf(-dels, cj, mj);
   PairOut o;
-  o.ti = T.rho * frcp(s - T.rho * ci);
-  o.tj = T.rho * frcp(s - T.rho * cj);
+  o.ti = T.rho * frcp(__builtin_fmaf(-T.rho, ci, s));
+  o.tj = T.rho * frcp(__builtin_fmaf(-T.rho, cj, s));
   o.ki = o.ti < kPrecFloor;
   o.kj = o.tj < kPrecFloor;
   o.ti = o.ki ? kPrecFloor : o.ti;
   o.tj = o.kj ? kPrecFloor : o.tj;
-  o.ei = o.ti * Ei + dels;
-  o.ej = o.tj * Ej - dels;
+  o.ei = __builtin_fmaf(o.ti, Ei, dels);
+  o.ej = __builtin_fmaf(o.tj, Ej, -dels);
   o.eabs = T.eabs;
   return o;
 }

@@ -66,7 +66,10 @@ __device__ __forceinline__ void mills(float z, float x, float& K, float& r) {
 
 // Contraction into fused multiply-adds is switched off here: fma(a, b, c d)
 // is not symmetric under exchanging the two components, and with it the moments
-// of -m would not be exactly the mirror image of those of m.
+// of -m would not be exactly the mirror image of those of m.  The fused
+// multiply-adds written out below take operands that are each either unchanged
+// or negated by the exchange (fma(-a, b, -c) = -fma(a, b, c) in
+// round-to-nearest), so the mirror stays exact.
 __device__ __forceinline__ Tilt laplace_tilt(float m, float s, float lam) {
 #pragma clang fp contract(off)
   const float kSqrt2 = 1.41421356237309515f;
@@ -94,7 +97,7 @@ __device__ __forceinline__ Tilt laplace_tilt(float m, float s, float lam) {
   const float zneg = fminf(fminf(zp, zm), 0.0f);
   const float g = __expf(-zneg * zneg);
   const float gc = g * kSqrt2OverPi;
-  const float wn = 2.0f - g * (kSqrt2OverPi * frcp(sp ? rp1 : rm1));
+  const float wn = __builtin_fmaf(-g, kSqrt2OverPi * frcp(sp ? rp1 : rm1), 2.0f);
   const float rn = gc * frcp(wn);
   const float Wp = sp ? wn * rm1 : (sm ? gc : rm1);
   const float Wm = sm ? wn * rp1 : (sp ? gc : rp1);
@@ -107,8 +110,8 @@ __device__ __forceinline__ Tilt laplace_tilt(float m, float s, float lam) {
   const float Km = sm ? rn - xm : Km1;
   Tilt T;
   const float Ks = Kp + Km;
-  T.rho = pp * rp * Kp + pm * rm * Km - pp * pm * Ks * Ks;
-  T.delta = sig * (pp * rp - pm * rm) - ls * (pp - pm);
+  T.rho = __builtin_fmaf(-(pp * pm * Ks), Ks, pp * rp * Kp + pm * rm * Km);
+  T.delta = __builtin_fmaf(sig, pp * rp - pm * rm, -(ls * (pp - pm)));
   T.eabs = sig * (pp * Kp + pm * Km);
   return T;
 }
