@@ -492,20 +492,22 @@ __global__ __launch_bounds__(256) void k_rfft(RfftArgs a) {
         }
       }
     }
-    __shared__ double sa[256], sb[256];
-    sa[threadIdx.x] = s0;
-    sb[threadIdx.x] = s1;
-    __syncthreads();
-    for (int w = 128; w >= 1; w >>= 1) {
-      if ((int)threadIdx.x < w) {
-        sa[threadIdx.x] += sa[threadIdx.x + w];
-        sb[threadIdx.x] += sb[threadIdx.x + w];
-      }
-      __syncthreads();
+    // deterministic block sum: butterfly over each wave, then the four wave
+    // totals in a fixed order
+#pragma unroll
+    for (int off = kWave / 2; off >= 1; off >>= 1) {
+      s0 += __shfl_xor(s0, off, kWave);
+      s1 += __shfl_xor(s1, off, kWave);
     }
+    __shared__ double sa[4], sb[4];
+    if (threadIdx.x % kWave == 0) {
+      sa[threadIdx.x / kWave] = s0;
+      sb[threadIdx.x / kWave] = s1;
+    }
+    __syncthreads();
     if (threadIdx.x == 0) {
-      a.part0[a.part_base + blockIdx.x] = sa[0];
-      a.part1[a.part_base + blockIdx.x] = sb[0];
+      a.part0[a.part_base + blockIdx.x] = (sa[0] + sa[1]) + (sa[2] + sa[3]);
+      a.part1[a.part_base + blockIdx.x] = (sb[0] + sb[1]) + (sb[2] + sb[3]);
     }
   }
 }

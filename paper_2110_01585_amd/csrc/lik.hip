@@ -45,22 +45,26 @@ struct LikArgs {
   float* p_in; float* p_out; float* q; float* spec;
 };
 
-// Deterministic block sum of two doubles (256 threads).
+// Deterministic block sum of two doubles (256 threads): a butterfly over the
+// 64 lanes of each wave (every lane ends with the same bits, since each step
+// adds the same two numbers on both lanes), then the four wave totals in a
+// fixed order.  One barrier instead of one per tree level.
 __device__ __forceinline__ void block_sum2(double a, double b, double* out_a, double* out_b) {
-  __shared__ double sa[256], sb[256];
-  sa[threadIdx.x] = a;
-  sb[threadIdx.x] = b;
-  __syncthreads();
-  for (int w = 128; w >= 1; w >>= 1) {
-    if ((int)threadIdx.x < w) {
-      sa[threadIdx.x] += sa[threadIdx.x + w];
-      sb[threadIdx.x] += sb[threadIdx.x + w];
-    }
-    __syncthreads();
+  __shared__ double wa[4], wb[4];
+#pragma unroll
+  for (int off = kWave / 2; off >= 1; off >>= 1) {
+    a += __shfl_xor(a, off, kWave);
+    b += __shfl_xor(b, off, kWave);
   }
+  const int w = threadIdx.x / kWave;
+  if (threadIdx.x % kWave == 0) {
+    wa[w] = a;
+    wb[w] = b;
+  }
+  __syncthreads();
   if (threadIdx.x == 0) {
-    *out_a = sa[0];
-    *out_b = sb[0];
+    *out_a = (wa[0] + wa[1]) + (wa[2] + wa[3]);
+    *out_b = (wb[0] + wb[1]) + (wb[2] + wb[3]);
   }
 }
 
@@ -154,9 +158,22 @@ __global__ __launch_bounds__(256) void k_lik_fin(LikArgs A, int stage) {
   // number of partials this stage sums (one per tile, or one per row block of the
   // real-transform passes), chosen on the host
   const int cnt = A.inst[blockIdx.x].fin_count[stage];
-  for (int t = threadIdx.x; t < cnt; t += blockDim.x) {
-    s0 += A.part0[L.tile0 + t];
-    s1 += A.part1[L.tile0 + t];
+  // 16 partials per thread are requested before the first is added (the sum
+  // is still taken in ascending order), so their latencies overlap
+  constexpr int kU = 16;
+  for (int t0 = threadIdx.x; t0 < cnt; t0 += kU * 256) {
+    double v0[kU], v1[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int t = t0 + u * 256;
+      v0[u] = t < cnt ? A.part0[L.tile0 + t] : 0.0;
+      v1[u] = t < cnt ? A.part1[L.tile0 + t] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      s0 += v0[u];
+      s1 += v1[u];
+    }
   }
   __shared__ double r0, r1;
   block_sum2(s0, s1, &r0, &r1);
