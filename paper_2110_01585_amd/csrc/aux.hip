@@ -392,12 +392,22 @@ __global__ __launch_bounds__(1024) void k_yrange(const float* __restrict__ y_pix
   __shared__ float smin[1024], smax[1024];
   const InstDev I = inst[blockIdx.x];
   float lo = 3.0e38f, hi = -3.0e38f;
-  for (int r = 0; r < I.H; ++r) {
-    const float* row = y_pix + I.off + (long long)r * I.pitch;
+  // 16 rows per step, all requested before the first comparison; rows past the
+  // last one repeat the step's first row (min and max are unaffected)
+  constexpr int kR = 16;
+  for (int r0 = 0; r0 < I.H; r0 += kR) {
     for (int c = threadIdx.x; c < I.W; c += blockDim.x) {
-      const float v = row[c];
-      lo = fminf(lo, v);
-      hi = fmaxf(hi, v);
+      float v[kR];
+#pragma unroll
+      for (int k = 0; k < kR; ++k) {
+        const int r = r0 + k < I.H ? r0 + k : r0;
+        v[k] = y_pix[I.off + (long long)r * I.pitch + c];
+      }
+#pragma unroll
+      for (int k = 0; k < kR; ++k) {
+        lo = fminf(lo, v[k]);
+        hi = fmaxf(hi, v[k]);
+      }
     }
   }
   smin[threadIdx.x] = lo;

@@ -228,15 +228,12 @@ __global__ __launch_bounds__(256) void k_lik_spec(LikArgs A) {
   double acc = 0.0;
   if (!st.cg_done) {
     const TileXY t = lik_tile(td, L);
-    const int cols = t.c1 - t.c0;
-    const int n = cols * (t.r1 - t.r0);
     const double d = st.dbar;
     const double ix = (double)L.inv_xi;
-    for (int i = threadIdx.x; i < n; i += blockDim.x) {
-      const int r = t.r0 + i / cols, c = t.c0 + i % cols;
-      const long long p = L.off + (long long)r * L.pitch + c;
-      acc += 1.0 / ((double)A.spec[p] * ix + d);
-    }
+    float sp[kTileItems];
+    tile_two_phase(
+        t, L, [&](int u, long long p) { sp[u] = A.spec[p]; },
+        [&](int u, long long) { acc += 1.0 / ((double)sp[u] * ix + d); });
   }
   block_sum2(acc, 0.0, &A.part0[tile], &A.part1[tile]);
 }
