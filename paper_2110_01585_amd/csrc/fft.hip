@@ -286,6 +286,8 @@ struct RfftArgs {
                              // element (row, k) at [k tld + row] (tld = H)
   int mode;                  // RFM_PRECOND or RFM_PRODUCT
   int update;                // RF_FWD precondition: first x += alpha p, r -= alpha q
+  const double* apart;       // RF_FWD update: the p.q partials alpha is formed from
+  int acount;
   long long off;             // real planes (pitched)
   int pitch;
   float* r;                  // residual
@@ -300,11 +302,39 @@ struct RfftArgs {
   const float* specT;        // eigenvalues of H^T H, transposed dense (W x H)
   float inv_xi, scale;
   const InstState* st;
+  InstState* st_w;           // RF_FWD update: block 0 records alpha
   int inst;
   double* part0;             // RF_INV partials at [part_base + blockIdx.x]
   double* part1;
   int part_base;
 };
+
+// alpha = r.z / p.q of a CG step (Hestenes-Stiefel), from the p.q partials of
+// the product, summed exactly as the per-instance finishing kernel sums them:
+// each thread in ascending order, a butterfly over each wave, then the four
+// wave totals in a fixed order.  Every workgroup of the pass forms the same
+// value.  Called by all 256 threads.
+__device__ __forceinline__ double cg_alpha(const double* __restrict__ part, int cnt, double rz) {
+  double s = 0.0;
+  constexpr int kU = 16;
+  for (int t0 = threadIdx.x; t0 < cnt; t0 += kU * 256) {
+    double v[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int t = t0 + u * 256;
+      v[u] = t < cnt ? part[t] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < kU; ++u) s += v[u];
+  }
+#pragma unroll
+  for (int off = kWave / 2; off >= 1; off >>= 1) s += __shfl_xor(s, off, kWave);
+  __shared__ double w[4];
+  if (threadIdx.x % kWave == 0) w[threadIdx.x / kWave] = s;
+  __syncthreads();
+  const double pq = (w[0] + w[1]) + (w[2] + w[3]);
+  return pq != 0.0 ? rz / pq : 0.0;
+}
 
 template <int L, int STAGE>
 __global__ __launch_bounds__(256) void k_rfft(RfftArgs a) {
@@ -319,7 +349,12 @@ __global__ __launch_bounds__(256) void k_rfft(RfftArgs a) {
   const bool skip = st.cg_done != 0;   // uniform per launch (one instance)
   // ---- load ----
   if (!skip) {
-    const float alpha = (float)st.cg_alpha;
+    float alpha = 0.f;
+    if (STAGE == RF_FWD && a.mode == RFM_PRECOND && a.update) {
+      const double al = cg_alpha(a.apart, a.acount, st.cg_rz);
+      alpha = (float)al;
+      if (blockIdx.x == 0 && threadIdx.x == 0) a.st_w[a.inst].cg_alpha = al;
+    }
     const bool first = st.cg_it == 0;
     const float beta = (float)st.cg_beta;
     // In chunks of up to 8 elements per thread: every global load of a chunk
@@ -853,7 +888,8 @@ hipError_t rfft_cg(LikCtx& lc, int mode, int update, hipStream_t s) {
     const int Wh = d.W / 2 + 1;
     RfftArgs a;
     std::memset(&a, 0, sizeof(a));
-    a.off = L.off; a.pitch = L.pitch; a.inv_xi = L.inv_xi; a.st = lc.d_st; a.inst = L.inst;
+    a.off = L.off; a.pitch = L.pitch; a.inv_xi = L.inv_xi; a.st = lc.d_st; a.st_w = lc.d_st;
+    a.inst = L.inst;
     a.ld = Wh; a.mode = mode; a.update = update;
     a.r = lc.planes[LP_R]; a.z = lc.planes[LP_Z]; a.tauc = lc.planes[LP_TAUC];
     a.p_in = lc.planes[lc.pcur ? LP_P1 : LP_P0];     // same ping-pong as the CG kernels
@@ -864,6 +900,7 @@ hipError_t rfft_cg(LikCtx& lc, int mode, int update, hipStream_t s) {
     a.tld = d.H;
     RfftArgs f = a;
     f.dst = d.B; f.tw = d.twW; f.nrows = d.H / 2; f.logL = d.logW;
+    f.apart = lc.part0 + L.tile0; f.acount = L.fin_count[FIN_ALPHA];
     hipError_t e = launch_rfft<RF_FWD>(d.W, f, s);
     if (e != hipSuccess) return e;
     RfftArgs g = a;

@@ -39,6 +39,9 @@ struct LikInstInfo {
 };
 
 // Device description of one instance with a non-identity operator.
+// stages of the per-instance finishing kernel (index into LikInst::fin_count)
+enum { FIN_PREP = 0, FIN_SPEC, FIN_INIT, FIN_ALPHA, FIN_BETA };
+
 struct LikInst {
   int H, W, pitch, op;
   long long off;             // element offset in the pixel planes

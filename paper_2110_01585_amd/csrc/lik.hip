@@ -149,8 +149,6 @@ __global__ __launch_bounds__(256) void k_lik_prep(LikArgs A, const float2* __res
 
 // ---------------------------------------------------------------------------
 // 2. per-instance finalisation of the partial sums (one block per instance)
-enum { FIN_PREP = 0, FIN_SPEC, FIN_INIT, FIN_ALPHA, FIN_BETA };
-
 __global__ __launch_bounds__(256) void k_lik_fin(LikArgs A, int stage) {
   const LikInst L = A.inst[blockIdx.x];
   InstState& st = A.st[L.inst];
@@ -892,7 +890,8 @@ hipError_t lik_iterations(LikCtx& lc, int n, hipStream_t s) {
         return e2 != hipSuccess ? e2 : rfft_product(lc, s);
       });
       if (e != hipSuccess) return e;
-      if ((e = fin(lc, FIN_ALPHA, s)) != hipSuccess) return e;
+      // alpha = r.z / p.q is formed by every workgroup of the first transform
+      // pass from the p.q partials, so no finishing kernel runs in between
       e = timed(lc, lc.ev_precond, s, [&]() { return rfft_precondition(lc, 1, s); });   // with x, r update
       if (e != hipSuccess) return e;
       if ((e = fin(lc, FIN_BETA, s)) != hipSuccess) return e;
