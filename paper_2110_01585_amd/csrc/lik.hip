@@ -358,20 +358,45 @@ __global__ __launch_bounds__(256) void k_hth_sep(LikArgs A) {
   auto qrow = [&](int u) { return (int)(threadIdx.x + 256 * u) / (kLikTW / 4); };
   auto qcol = [&](int u) { return 4 * ((int)(threadIdx.x + 256 * u) % (kLikTW / 4)); };
   auto qfull = [&](int u) { return t.r0 + qrow(u) < L.H && t.c0 + qcol(u) + 3 < L.W; };
+  // Tiles whose halo lies inside the image (no wrap) load it as 16-byte words:
+  // the halo starts RT columns left of a 64-column tile boundary, and planes
+  // and their row pitch are 64-float aligned, so every word is aligned.
+  static_assert(RT % 4 == 0 && EW % 4 == 0 && kLikTW % 4 == 0, "16-byte halo words");
+  constexpr int EW4 = EW / 4;
+  constexpr int NL4 = (EH * EW4 + 255) / 256;        // halo words per thread
+  float4 zv4[NL4], pv4[NL4];
   float zv[NL], pv[NL];
   float4 tc[NQ];
+  if (inner) {
 #pragma unroll
-  for (int u = 0; u < NL; ++u) {
-    const int i = threadIdx.x + 256 * u;
-    zv[u] = 0.f;
-    pv[u] = 0.f;
-    if (i < EH * EW) {
-      const long long p = halo_index(i);
-      if (MODE == 0) {
-        zv[u] = A.x[p];
-      } else {
-        zv[u] = A.z[p];
-        if (!first) pv[u] = A.p_in[p];
+    for (int u = 0; u < NL4; ++u) {
+      const int i = threadIdx.x + 256 * u;
+      zv4[u] = pv4[u] = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (i < EH * EW4) {
+        const int er = i / EW4, ec = 4 * (i - (i / EW4) * EW4);
+        const long long p = L.off + (long long)(t.r0 - RT + er) * L.pitch + (t.c0 - RT + ec);
+        if (MODE == 0) {
+          zv4[u] = *reinterpret_cast<const float4*>(A.x + p);
+        } else {
+          zv4[u] = *reinterpret_cast<const float4*>(A.z + p);
+          if (!first) pv4[u] = *reinterpret_cast<const float4*>(A.p_in + p);
+        }
+      }
+    }
+  } else {
+#pragma unroll
+    for (int u = 0; u < NL; ++u) {
+      const int i = threadIdx.x + 256 * u;
+      zv[u] = 0.f;
+      pv[u] = 0.f;
+      if (i < EH * EW) {
+        const long long p = halo_index(i);
+        if (MODE == 0) {
+          zv[u] = A.x[p];
+        } else {
+          zv[u] = A.z[p];
+          if (!first) pv[u] = A.p_in[p];
+        }
       }
     }
   }
@@ -388,19 +413,43 @@ __global__ __launch_bounds__(256) void k_hth_sep(LikArgs A) {
       tc[u] = make_float4(e[0], e[1], e[2], e[3]);
     }
   }
+  if (inner) {
 #pragma unroll
-  for (int u = 0; u < NL; ++u) {
-    const int i = threadIdx.x + 256 * u;
-    if (i >= EH * EW) continue;
-    float v = zv[u];
-    if (MODE == 1) {
-      v = first ? zv[u] : zv[u] + beta * pv[u];
-      const int er = i / EW, ec = i - (i / EW) * EW;
-      const int lr = er - RT, lc = ec - RT;
-      if (lr >= 0 && lr < kLikTH && lc >= 0 && lc < kLikTW && t.r0 + lr < L.H && t.c0 + lc < L.W)
-        A.p_out[halo_index(i)] = v;
+    for (int u = 0; u < NL4; ++u) {
+      const int i = threadIdx.x + 256 * u;
+      if (i >= EH * EW4) continue;
+      float4 v = zv4[u];
+      const int er = i / EW4, ec = 4 * (i - (i / EW4) * EW4);
+      if (MODE == 1) {
+        if (!first) {
+          v.x = zv4[u].x + beta * pv4[u].x;
+          v.y = zv4[u].y + beta * pv4[u].y;
+          v.z = zv4[u].z + beta * pv4[u].z;
+          v.w = zv4[u].w + beta * pv4[u].w;
+        }
+        const int lr = er - RT, lc = ec - RT;   // a word is all inside or all outside the tile
+        if (lr >= 0 && lr < kLikTH && lc >= 0 && lc < kLikTW) {
+          const long long p = L.off + (long long)(t.r0 + lr) * L.pitch + (t.c0 + lc);
+          *reinterpret_cast<float4*>(A.p_out + p) = v;
+        }
+      }
+      *reinterpret_cast<float4*>(P + er * EW + ec) = v;
     }
-    P[i] = v;
+  } else {
+#pragma unroll
+    for (int u = 0; u < NL; ++u) {
+      const int i = threadIdx.x + 256 * u;
+      if (i >= EH * EW) continue;
+      float v = zv[u];
+      if (MODE == 1) {
+        v = first ? zv[u] : zv[u] + beta * pv[u];
+        const int er = i / EW, ec = i - (i / EW) * EW;
+        const int lr = er - RT, lc = ec - RT;
+        if (lr >= 0 && lr < kLikTH && lc >= 0 && lc < kLikTW && t.r0 + lr < L.H && t.c0 + lc < L.W)
+          A.p_out[halo_index(i)] = v;
+      }
+      P[i] = v;
+    }
   }
   __syncthreads();
   // row pass, four adjacent outputs per work item from 128-bit LDS reads
