@@ -348,44 +348,112 @@ __global__ __launch_bounds__(256) void k_rfft(RfftArgs a) {
   const InstState& st = a.st[a.inst];
   const bool skip = st.cg_done != 0;   // uniform per launch (one instance)
   // ---- load ----
-  if (!skip) {
+  if (STAGE == RF_FWD && !skip) {
+    // The two real rows 2j, 2j+1 of each complex row, as 16-byte words of four
+    // columns (planes and pitches are 64-float aligned, L is a multiple of 4).
+    // Every load is issued before alpha's partials are summed and before the
+    // first store.
+    const bool first = st.cg_it == 0;
+    const float beta = (float)st.cg_beta;
+    const bool upd = a.mode == RFM_PRECOND && a.update;
+    constexpr int NQ4 = (kRows * L / 4 + 255) / 256;   // words per thread and row
+    float4 va[NQ4], vb[NQ4], qa[NQ4], qb[NQ4], xa[NQ4], xb[NQ4], pa[NQ4], pb[NQ4];
+#pragma unroll
+    for (int u = 0; u < NQ4; ++u) {
+      const int i = 4 * ((int)threadIdx.x + 256 * u);
+      va[u] = vb[u] = qa[u] = qb[u] = xa[u] = xb[u] = pa[u] = pb[u] = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (i >= rows * L) continue;
+      const long long p = a.off + (long long)(2 * (row0 + i / L)) * a.pitch + i % L;
+      const long long p1 = p + a.pitch;
+      if (a.mode == RFM_PRECOND) {
+        va[u] = *reinterpret_cast<const float4*>(a.r + p);
+        vb[u] = *reinterpret_cast<const float4*>(a.r + p1);
+        if (upd) {
+          qa[u] = *reinterpret_cast<const float4*>(a.q + p);
+          qb[u] = *reinterpret_cast<const float4*>(a.q + p1);
+          xa[u] = *reinterpret_cast<const float4*>(a.x + p);
+          xb[u] = *reinterpret_cast<const float4*>(a.x + p1);
+          pa[u] = *reinterpret_cast<const float4*>(a.p + p);
+          pb[u] = *reinterpret_cast<const float4*>(a.p + p1);
+        }
+      } else {
+        va[u] = *reinterpret_cast<const float4*>(a.z + p);
+        vb[u] = *reinterpret_cast<const float4*>(a.z + p1);
+        if (!first) {
+          qa[u] = *reinterpret_cast<const float4*>(a.p_in + p);
+          qb[u] = *reinterpret_cast<const float4*>(a.p_in + p1);
+        }
+      }
+    }
     float alpha = 0.f;
-    if (STAGE == RF_FWD && a.mode == RFM_PRECOND && a.update) {
+    if (upd) {
       const double al = cg_alpha(a.apart, a.acount, st.cg_rz);
       alpha = (float)al;
       if (blockIdx.x == 0 && threadIdx.x == 0) a.st_w[a.inst].cg_alpha = al;
     }
-    const bool first = st.cg_it == 0;
-    const float beta = (float)st.cg_beta;
+#pragma unroll
+    for (int u = 0; u < NQ4; ++u) {
+      const int i = 4 * ((int)threadIdx.x + 256 * u);
+      if (i >= rows * L) continue;
+      const long long p = a.off + (long long)(2 * (row0 + i / L)) * a.pitch + i % L;
+      const long long p1 = p + a.pitch;
+      const float ra[4] = {va[u].x, va[u].y, va[u].z, va[u].w};
+      const float rb[4] = {vb[u].x, vb[u].y, vb[u].z, vb[u].w};
+      const float sa[4] = {qa[u].x, qa[u].y, qa[u].z, qa[u].w};
+      const float sb[4] = {qb[u].x, qb[u].y, qb[u].z, qb[u].w};
+      float oa[4], ob[4];
+      if (a.mode == RFM_PRECOND) {
+        if (upd) {
+          const float xa4[4] = {xa[u].x, xa[u].y, xa[u].z, xa[u].w};
+          const float xb4[4] = {xb[u].x, xb[u].y, xb[u].z, xb[u].w};
+          const float pa4[4] = {pa[u].x, pa[u].y, pa[u].z, pa[u].w};
+          const float pb4[4] = {pb[u].x, pb[u].y, pb[u].z, pb[u].w};
+          float na[4], nb[4];
+#pragma unroll
+          for (int k = 0; k < 4; ++k) {
+            oa[k] = ra[k] - alpha * sa[k];
+            ob[k] = rb[k] - alpha * sb[k];
+            na[k] = xa4[k] + alpha * pa4[k];
+            nb[k] = xb4[k] + alpha * pb4[k];
+          }
+          *reinterpret_cast<float4*>(a.x + p) = make_float4(na[0], na[1], na[2], na[3]);
+          *reinterpret_cast<float4*>(a.x + p1) = make_float4(nb[0], nb[1], nb[2], nb[3]);
+          *reinterpret_cast<float4*>(a.r + p) = make_float4(oa[0], oa[1], oa[2], oa[3]);
+          *reinterpret_cast<float4*>(a.r + p1) = make_float4(ob[0], ob[1], ob[2], ob[3]);
+        } else {
+#pragma unroll
+          for (int k = 0; k < 4; ++k) {
+            oa[k] = ra[k];
+            ob[k] = rb[k];
+          }
+        }
+      } else {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          oa[k] = first ? ra[k] : ra[k] + beta * sa[k];
+          ob[k] = first ? rb[k] : rb[k] + beta * sb[k];
+        }
+        *reinterpret_cast<float4*>(a.p + p) = make_float4(oa[0], oa[1], oa[2], oa[3]);
+        *reinterpret_cast<float4*>(a.p + p1) = make_float4(ob[0], ob[1], ob[2], ob[3]);
+      }
+#pragma unroll
+      for (int k = 0; k < 4; ++k) X[pidx(i + k)] = make_float2(oa[k], ob[k]);
+    }
+  } else if (STAGE != RF_FWD && !skip) {
     // In chunks of up to 8 elements per thread: every global load of a chunk
-    // is issued before its first global store (a store may alias the loaded
-    // planes as far as the compiler knows, which would serialise the loads).
+    // is issued before its first LDS store.
     constexpr int NU = (kRows * L + 255) / 256;
     constexpr int CH = NU < 8 ? NU : 8;
 #pragma unroll
     for (int b0 = 0; b0 < NU; b0 += CH) {
-      float2 la[CH], lb[CH], lc[CH], ld[CH];
+      float2 la[CH], lb[CH];
 #pragma unroll
       for (int k = 0; k < CH; ++k) {
         const int i = threadIdx.x + (b0 + k) * 256;
-        la[k] = lb[k] = lc[k] = ld[k] = make_float2(0.f, 0.f);
+        la[k] = lb[k] = make_float2(0.f, 0.f);
         if (b0 + k >= NU || i >= rows * L) continue;
         const int j = row0 + i / L, c = i % L;
-        if (STAGE == RF_FWD) {
-          const long long p = a.off + (long long)(2 * j) * a.pitch + c;
-          const long long p1 = p + a.pitch;
-          if (a.mode == RFM_PRECOND) {
-            la[k] = make_float2(a.r[p], a.r[p1]);
-            if (a.update) {
-              lb[k] = make_float2(a.q[p], a.q[p1]);
-              lc[k] = make_float2(a.x[p], a.x[p1]);
-              ld[k] = make_float2(a.p[p], a.p[p1]);
-            }
-          } else {
-            la[k] = make_float2(a.z[p], a.z[p1]);
-            if (!first) lb[k] = make_float2(a.p_in[p], a.p_in[p1]);
-          }
-        } else if (STAGE == RF_FILT) {
+        if (STAGE == RF_FILT) {
           la[k] = a.src[(long long)j * L + c];
         } else {
           const bool lo = c <= half;
@@ -399,30 +467,9 @@ __global__ __launch_bounds__(256) void k_rfft(RfftArgs a) {
       for (int k = 0; k < CH; ++k) {
         const int i = threadIdx.x + (b0 + k) * 256;
         if (b0 + k >= NU || i >= rows * L) continue;
-        const int j = row0 + i / L, c = i % L;
+        const int c = i % L;
         float2 v;
-        if (STAGE == RF_FWD) {
-          const long long p = a.off + (long long)(2 * j) * a.pitch + c;
-          const long long p1 = p + a.pitch;
-          if (a.mode == RFM_PRECOND) {
-            if (a.update) {
-              const float r0 = la[k].x - alpha * lb[k].x, r1 = la[k].y - alpha * lb[k].y;
-              a.x[p] = lc[k].x + alpha * ld[k].x;
-              a.x[p1] = lc[k].y + alpha * ld[k].y;
-              a.r[p] = r0;
-              a.r[p1] = r1;
-              v = make_float2(r0, r1);
-            } else {
-              v = la[k];
-            }
-          } else {
-            const float p0 = first ? la[k].x : la[k].x + beta * lb[k].x;
-            const float p1v = first ? la[k].y : la[k].y + beta * lb[k].y;
-            a.p[p] = p0;
-            a.p[p1] = p1v;
-            v = make_float2(p0, p1v);
-          }
-        } else if (STAGE == RF_FILT) {
+        if (STAGE == RF_FILT) {
           v = la[k];
         } else {
           float2 A = la[k], B = lb[k];
@@ -483,48 +530,54 @@ __global__ __launch_bounds__(256) void k_rfft(RfftArgs a) {
   } else {
     double s0 = 0.0, s1 = 0.0;
     if (!skip) {
-      constexpr int NU = (kRows * L + 255) / 256;
-      constexpr int CH = NU < 8 ? NU : 8;
+      // rows 2j, 2j+1 as 16-byte words of four columns; r (precondition) or p
+      // and tau_c (product) are loaded before the first store
+      constexpr int NQ4 = (kRows * L / 4 + 255) / 256;
+      float4 ea[NQ4], eb[NQ4], ta[NQ4], tb[NQ4];
 #pragma unroll
-      for (int b0 = 0; b0 < NU; b0 += CH) {
-        float2 la[CH], lb[CH];   // r (precondition) or p and tau_c (product), loaded first
+      for (int u = 0; u < NQ4; ++u) {
+        const int i = 4 * ((int)threadIdx.x + 256 * u);
+        ea[u] = eb[u] = ta[u] = tb[u] = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (i >= rows * L) continue;
+        const long long p = a.off + (long long)(2 * (row0 + i / L)) * a.pitch + i % L;
+        const long long p1 = p + a.pitch;
+        if (a.mode == RFM_PRECOND) {
+          ea[u] = *reinterpret_cast<const float4*>(a.r + p);
+          eb[u] = *reinterpret_cast<const float4*>(a.r + p1);
+        } else {
+          ea[u] = *reinterpret_cast<const float4*>(a.p + p);
+          eb[u] = *reinterpret_cast<const float4*>(a.p + p1);
+          ta[u] = *reinterpret_cast<const float4*>(a.tauc + p);
+          tb[u] = *reinterpret_cast<const float4*>(a.tauc + p1);
+        }
+      }
 #pragma unroll
-        for (int k = 0; k < CH; ++k) {
-          const int i = threadIdx.x + (b0 + k) * 256;
-          la[k] = lb[k] = make_float2(0.f, 0.f);
-          if (b0 + k >= NU || i >= rows * L) continue;
-          const int j = row0 + i / L, c = i % L;
-          const long long p = a.off + (long long)(2 * j) * a.pitch + c;
-          const long long p1 = p + a.pitch;
+      for (int u = 0; u < NQ4; ++u) {
+        const int i = 4 * ((int)threadIdx.x + 256 * u);
+        if (i >= rows * L) continue;
+        const long long p = a.off + (long long)(2 * (row0 + i / L)) * a.pitch + i % L;
+        const long long p1 = p + a.pitch;
+        const float va[4] = {ea[u].x, ea[u].y, ea[u].z, ea[u].w};
+        const float vb[4] = {eb[u].x, eb[u].y, eb[u].z, eb[u].w};
+        const float ua[4] = {ta[u].x, ta[u].y, ta[u].z, ta[u].w};
+        const float ub[4] = {tb[u].x, tb[u].y, tb[u].z, tb[u].w};
+        float oa[4], ob[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const float2 zz = X[pidx(i + k)];
           if (a.mode == RFM_PRECOND) {
-            la[k] = make_float2(a.r[p], a.r[p1]);
+            oa[k] = zz.x;
+            ob[k] = zz.y;
+            s0 += (double)va[k] * oa[k] + (double)vb[k] * ob[k];
+            s1 += (double)va[k] * va[k] + (double)vb[k] * vb[k];
           } else {
-            la[k] = make_float2(a.p[p], a.p[p1]);
-            lb[k] = make_float2(a.tauc[p], a.tauc[p1]);
+            oa[k] = zz.x + ua[k] * va[k];
+            ob[k] = zz.y + ub[k] * vb[k];
+            s0 += (double)va[k] * oa[k] + (double)vb[k] * ob[k];
           }
         }
-#pragma unroll
-        for (int k = 0; k < CH; ++k) {
-          const int i = threadIdx.x + (b0 + k) * 256;
-          if (b0 + k >= NU || i >= rows * L) continue;
-          const int j = row0 + i / L, c = i % L;
-          const long long p = a.off + (long long)(2 * j) * a.pitch + c;
-          const long long p1 = p + a.pitch;
-          if (a.mode == RFM_PRECOND) {
-            const float z0 = X[pidx(i)].x, z1 = X[pidx(i)].y;
-            a.out[p] = z0;
-            a.out[p1] = z1;
-            const float r0 = la[k].x, r1 = la[k].y;
-            s0 += (double)r0 * z0 + (double)r1 * z1;
-            s1 += (double)r0 * r0 + (double)r1 * r1;
-          } else {
-            const float v0 = la[k].x, v1 = la[k].y;
-            const float q0 = X[pidx(i)].x + lb[k].x * v0, q1 = X[pidx(i)].y + lb[k].y * v1;
-            a.out[p] = q0;
-            a.out[p1] = q1;
-            s0 += (double)v0 * q0 + (double)v1 * q1;
-          }
-        }
+        *reinterpret_cast<float4*>(a.out + p) = make_float4(oa[0], oa[1], oa[2], oa[3]);
+        *reinterpret_cast<float4*>(a.out + p1) = make_float4(ob[0], ob[1], ob[2], ob[3]);
       }
     }
     // deterministic block sum: butterfly over each wave, then the four wave
