@@ -439,7 +439,25 @@ __global__ __launch_bounds__(256) void k_rfft(RfftArgs a) {
 #pragma unroll
       for (int k = 0; k < 4; ++k) X[pidx(i + k)] = make_float2(oa[k], ob[k]);
     }
-  } else if (STAGE != RF_FWD && !skip) {
+  } else if (STAGE == RF_FILT && !skip) {
+    // two complex values (16 bytes) per load; rows are contiguous
+    constexpr int NP2 = (kRows * L / 2 + 255) / 256;
+    float4 lv[NP2];
+#pragma unroll
+    for (int u = 0; u < NP2; ++u) {
+      const int i = 2 * ((int)threadIdx.x + 256 * u);
+      lv[u] = i < rows * L
+                  ? *reinterpret_cast<const float4*>(a.src + (long long)(row0 + i / L) * L + i % L)
+                  : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+#pragma unroll
+    for (int u = 0; u < NP2; ++u) {
+      const int i = 2 * ((int)threadIdx.x + 256 * u);
+      if (i >= rows * L) continue;
+      X[pidx(i)] = make_float2(lv[u].x, lv[u].y);
+      X[pidx(i + 1)] = make_float2(lv[u].z, lv[u].w);
+    }
+  } else if (STAGE == RF_INV && !skip) {
     // In chunks of up to 8 elements per thread: every global load of a chunk
     // is issued before its first LDS store.
     constexpr int NU = (kRows * L + 255) / 256;
@@ -453,30 +471,19 @@ __global__ __launch_bounds__(256) void k_rfft(RfftArgs a) {
         la[k] = lb[k] = make_float2(0.f, 0.f);
         if (b0 + k >= NU || i >= rows * L) continue;
         const int j = row0 + i / L, c = i % L;
-        if (STAGE == RF_FILT) {
-          la[k] = a.src[(long long)j * L + c];
-        } else {
-          const bool lo = c <= half;
-          const int kk = lo ? c : L - c;
-          const float4 ab = *reinterpret_cast<const float4*>(a.src + (long long)kk * a.tld + 2 * j);
-          la[k] = make_float2(ab.x, ab.y);
-          lb[k] = make_float2(ab.z, ab.w);
-        }
+        const int kk = c <= half ? c : L - c;
+        const float4 ab = *reinterpret_cast<const float4*>(a.src + (long long)kk * a.tld + 2 * j);
+        la[k] = make_float2(ab.x, ab.y);
+        lb[k] = make_float2(ab.z, ab.w);
       }
 #pragma unroll
       for (int k = 0; k < CH; ++k) {
         const int i = threadIdx.x + (b0 + k) * 256;
         if (b0 + k >= NU || i >= rows * L) continue;
         const int c = i % L;
-        float2 v;
-        if (STAGE == RF_FILT) {
-          v = la[k];
-        } else {
-          float2 A = la[k], B = lb[k];
-          if (!(c <= half)) { A.y = -A.y; B.y = -B.y; }
-          v = make_float2(A.x - B.y, A.y + B.x);
-        }
-        X[pidx(i)] = v;
+        float2 A = la[k], B = lb[k];
+        if (!(c <= half)) { A.y = -A.y; B.y = -B.y; }
+        X[pidx(i)] = make_float2(A.x - B.y, A.y + B.x);
       }
     }
   }
@@ -488,13 +495,18 @@ __global__ __launch_bounds__(256) void k_rfft(RfftArgs a) {
       fft_passes<L, 1, kRows * L>(X, rows, a.tw, -1.f);
       const float dbar = (float)st.dbar;
       #pragma unroll
-      for (int u_ = 0; u_ < (kRows * L + 255) / 256; ++u_) {
-        const int i = threadIdx.x + u_ * 256;
+      for (int u_ = 0; u_ < (kRows * L / 2 + 255) / 256; ++u_) {
+        const int i = 2 * ((int)threadIdx.x + u_ * 256);
         if (i >= rows * L) continue;
-        const int j = row0 + i / L, c = i % L;
-        const float sp = a.specT[(long long)j * L + c] * a.inv_xi;
-        const float m = a.mode == RFM_PRECOND ? a.scale / (sp + dbar) : a.scale * sp;
-        X[pidx(i)] = make_float2(X[pidx(i)].x * m, X[pidx(i)].y * m);
+        const float2 sp2 =
+            *reinterpret_cast<const float2*>(a.specT + (long long)(row0 + i / L) * L + i % L);
+        const float spv[2] = {sp2.x, sp2.y};
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+          const float sp = spv[k] * a.inv_xi;
+          const float m = a.mode == RFM_PRECOND ? a.scale / (sp + dbar) : a.scale * sp;
+          X[pidx(i + k)] = make_float2(X[pidx(i + k)].x * m, X[pidx(i + k)].y * m);
+        }
       }
       __syncthreads();
       fft_passes<L, 1, kRows * L>(X, rows, a.tw, 1.f);
@@ -521,11 +533,12 @@ __global__ __launch_bounds__(256) void k_rfft(RfftArgs a) {
   } else if (STAGE == RF_FILT) {
     if (skip) return;
     #pragma unroll
-    for (int u_ = 0; u_ < (kRows * L + 255) / 256; ++u_) {
-      const int i = threadIdx.x + u_ * 256;
+    for (int u_ = 0; u_ < (kRows * L / 2 + 255) / 256; ++u_) {
+      const int i = 2 * ((int)threadIdx.x + u_ * 256);
       if (i >= rows * L) continue;
-      const int j = row0 + i / L, c = i % L;
-      a.dst[(long long)j * L + c] = X[pidx(i)];
+      const float2 v0 = X[pidx(i)], v1 = X[pidx(i + 1)];
+      *reinterpret_cast<float4*>(a.dst + (long long)(row0 + i / L) * L + i % L) =
+          make_float4(v0.x, v0.y, v1.x, v1.y);
     }
   } else {
     double s0 = 0.0, s1 = 0.0;
