@@ -87,11 +87,24 @@ __device__ __forceinline__ TileXY lik_tile(const int4 td, const LikInst& L) {
 // arrange itself: a store through one plane may alias the others as far as it
 // knows.  Launched with 256 threads.
 constexpr int kTileItems = kLikTH * kLikTW / 256;
-template <class Load, class Op>
+// QUAD: a full tile gives each thread four adjacent pixels of one row instead
+// (the compiler then merges a kernel's per-pixel loads into 16-byte words; it
+// pays where the stores merge too, or where there are none).
+template <bool QUAD = false, class Load, class Op>
 __device__ __forceinline__ void tile_two_phase(const TileXY& t, const LikInst& L, Load&& load,
                                                Op&& op) {
   const int cols = t.c1 - t.c0;
   const int n = cols * (t.r1 - t.r0);
+  static_assert(kTileItems == 4 && kLikTW % 4 == 0, "four adjacent pixels per thread");
+  if (QUAD && n == kLikTH * kLikTW) {
+    const int r = t.r0 + 4 * (int)threadIdx.x / kLikTW, c = t.c0 + 4 * (int)threadIdx.x % kLikTW;
+    const long long p0 = L.off + (long long)r * L.pitch + c;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) load(u, p0 + u);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) op(u, p0 + u);
+    return;
+  }
   long long pp[kTileItems];
 #pragma unroll
   for (int u = 0; u < kTileItems; ++u) {
@@ -229,7 +242,7 @@ __global__ __launch_bounds__(256) void k_lik_spec(LikArgs A) {
     const double d = st.dbar;
     const double ix = (double)L.inv_xi;
     float sp[kTileItems];
-    tile_two_phase(
+    tile_two_phase<true>(
         t, L, [&](int u, long long p) { sp[u] = A.spec[p]; },
         [&](int u, long long) { acc += 1.0 / ((double)sp[u] * ix + d); });
   }
@@ -592,7 +605,7 @@ __global__ __launch_bounds__(256) void k_lik_site(LikArgs A, float2* __restrict_
   const float a = L.alpha;
   float tcv[kTileItems], xv[kTileItems], ecv[kTileItems];
   float2 ov[kTileItems];
-  tile_two_phase(
+  tile_two_phase<true>(
       t, L,
       [&](int u, long long p) { tcv[u] = A.tauc[p]; xv[u] = A.x[p]; ecv[u] = A.etac[p]; ov[u] = S0[p]; },
       [&](int u, long long p) {
