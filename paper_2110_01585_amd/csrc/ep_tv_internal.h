@@ -45,6 +45,7 @@ struct InstState {
   unsigned clamps, flags, active, sweeps;
   int cg_last, cg_total, converged, cg_done;
   int cg_it, x_valid, warm, warm_ok;   // warm: sites were set from a prediction (no skipped q0)
+  int xprev_valid, pad_;               // the plane of the solve before the last holds its E
 };
 
 enum { FLAG_NONFINITE = 1u };

@@ -58,7 +58,7 @@ struct LikInst {
 };
 
 enum {
-  LP_HTY = 0, LP_TAUC, LP_ETAC, LP_B, LP_X, LP_R, LP_Z, LP_P0, LP_P1, LP_Q, LP_SPEC, LP_COUNT
+  LP_HTY = 0, LP_TAUC, LP_ETAC, LP_B, LP_X, LP_R, LP_Z, LP_P0, LP_P1, LP_Q, LP_SPEC, LP_XPREV, LP_COUNT
 };
 
 enum { PRECOND_JACOBI = 0, PRECOND_CIRCULANT = 1 };

@@ -42,7 +42,7 @@ struct LikArgs {
   double* part1;
   const float* taps;
   float* hty; float* tauc; float* etac; float* b; float* x; float* r; float* z;
-  float* p_in; float* p_out; float* q; float* spec;
+  float* p_in; float* p_out; float* q; float* spec; float* xprev;
 };
 
 // Deterministic block sum of two doubles (256 threads): a butterfly over the
@@ -122,7 +122,13 @@ __device__ __forceinline__ void tile_two_phase(const TileXY& t, const LikInst& L
 }
 
 // ---------------------------------------------------------------------------
-// 1. cavity of site 0, right-hand side, warm start (and d_bar, ||b||^2 partials)
+// 1. cavity of site 0, right-hand side, CG starting point (and d_bar, ||b||^2
+//    partials).  The start is the mean of the global approximation when no
+//    earlier solve exists, the last solve's E after one solve, and the linear
+//    extrapolation 2 E_1 - E_2 of the last two solves after that: the sites move
+//    smoothly from sweep to sweep (damped updates), so the extrapolated point
+//    is closer to the new solution and the CG needs fewer iterations; the
+//    solution itself is fixed by the residual tolerance, not by the start.
 __global__ __launch_bounds__(256) void k_lik_prep(LikArgs A, const float2* __restrict__ S0,
                                                   const float2* __restrict__ S1,
                                                   const float2* __restrict__ S2,
@@ -136,14 +142,17 @@ __global__ __launch_bounds__(256) void k_lik_prep(LikArgs A, const float2* __res
   if (st.active && (st.sweeps > 0 || st.warm)) {
     const TileXY t = lik_tile(td, L);
     const bool init_x = !st.x_valid;
+    const bool extrap = st.x_valid && st.xprev_valid;
     float2 s1[kTileItems], s2[kTileItems], s3[kTileItems], s4[kTileItems], s0[kTileItems];
-    float hy[kTileItems];
+    float hy[kTileItems], xv[kTileItems], xp[kTileItems];
     tile_two_phase(
         t, L,
         [&](int u, long long p) {
           s1[u] = S1[p]; s2[u] = S2[p]; s3[u] = S3[p]; s4[u] = S4[p];
           hy[u] = A.hty[p];
           if (init_x) s0[u] = S0[p];
+          if (!init_x) xv[u] = A.x[p];
+          if (extrap) xp[u] = A.xprev[p];
         },
         [&](int u, long long p) {
           const double tc = (double)s1[u].x + (double)s2[u].x + (double)s3[u].x + (double)s4[u].x;
@@ -152,7 +161,12 @@ __global__ __launch_bounds__(256) void k_lik_prep(LikArgs A, const float2* __res
           A.tauc[p] = (float)tc;
           A.etac[p] = (float)ec;
           A.b[p] = bv;
-          if (init_x) A.x[p] = (float)(((double)s0[u].y + ec) / ((double)s0[u].x + tc));
+          if (init_x) {
+            A.x[p] = (float)(((double)s0[u].y + ec) / ((double)s0[u].x + tc));
+          } else {
+            A.xprev[p] = xv[u];
+            if (extrap) A.x[p] = 2.0f * xv[u] - xp[u];
+          }
           at += tc;
           ab += (double)bv * (double)bv;
         });
@@ -201,6 +215,7 @@ __global__ __launch_bounds__(256) void k_lik_fin(LikArgs A, int stage) {
       st.cg_bb = r1;
       st.cg_it = 0;
       st.cg_done = 0;
+      st.xprev_valid = st.x_valid;   // prep has just kept the last solve's E
       st.x_valid = 1;
       break;
     case FIN_SPEC:
@@ -689,6 +704,7 @@ static LikArgs make_args(LikCtx& lc) {
   A.p_out = lc.planes[lc.pcur ? LP_P0 : LP_P1];
   A.q = lc.planes[LP_Q];
   A.spec = lc.planes[LP_SPEC];
+  A.xprev = lc.planes[LP_XPREV];
   return A;
 }
 
@@ -839,7 +855,10 @@ hipError_t lik_resume(LikCtx& lc, hipStream_t s) { return set_x_invalid(lc, s); 
 
 __global__ void k_x_invalid(InstState* st, const LikInst* inst, int nlik) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < nlik) st[inst[i].inst].x_valid = 0;
+  if (i < nlik) {
+    st[inst[i].inst].x_valid = 0;
+    st[inst[i].inst].xprev_valid = 0;
+  }
 }
 
 static hipError_t set_x_invalid(LikCtx& lc, hipStream_t s) {
