@@ -82,6 +82,12 @@ typedef struct {
   double cg_tol;               /* CG relative residual ||r||/||b|| for the likelihood site; 0 = 1e-8 */
   int32_t cg_max_iters;        /* CG iteration cap per likelihood-site update; 0 = 200 */
   int32_t cg_precond;          /* EP_TV_PRECOND_*: CG preconditioner of the likelihood site */
+  double cg_reduce;            /* in [0, 1): also stop a likelihood-site CG once its residual
+                                  has fallen by this factor from where the solve started
+                                  (inexact solves while EP is far from its fixed point; the
+                                  cg_tol floor still holds near it).  0 = solve to cg_tol, as
+                                  every earlier sweep's result then follows the exact-solve
+                                  trajectory */
 } ep_tv_problem;
 
 /* Preconditioner of the likelihood-site CG.  CIRCULANT is (H^T H / xi + d I)^{-1}

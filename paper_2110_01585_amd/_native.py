@@ -43,7 +43,8 @@ class EpTvProblem(ctypes.Structure):
                 ("dft_mask", ctypes.POINTER(ctypes.c_uint8)),
                 ("noise_var", ctypes.c_double), ("lambda0", ctypes.c_double),
                 ("damping", ctypes.c_double), ("cg_tol", ctypes.c_double),
-                ("cg_max_iters", ctypes.c_int32), ("cg_precond", ctypes.c_int32)]
+                ("cg_max_iters", ctypes.c_int32), ("cg_precond", ctypes.c_int32),
+                ("cg_reduce", ctypes.c_double)]
 
 
 class EpTvStats(ctypes.Structure):

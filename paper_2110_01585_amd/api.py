@@ -36,6 +36,7 @@ class ProblemSpec:
     cg_tol: float = 0.0          # 0 = library default
     cg_max_iters: int = 0        # 0 = library default
     cg_precond: int = N.PRECOND_AUTO
+    cg_reduce: float = 0.0       # 0 = every solve to cg_tol
 
 
 _OPS = {"identity": N.OP_IDENTITY, "blur": N.OP_BLUR_PERIODIC, "dft": N.OP_DFT_MASK}
@@ -43,7 +44,7 @@ _BNDS = {"free": N.BND_FREE, "periodic": N.BND_PERIODIC}
 
 
 def spec_from_synthetic(p, lam0=None, damping=None, cg_tol=0.0, cg_max_iters=0,
-                        cg_precond=N.PRECOND_AUTO) -> ProblemSpec:
+                        cg_precond=N.PRECOND_AUTO, cg_reduce=0.0) -> ProblemSpec:
     """ProblemSpec of a synthetic.Problem (same fields, C enums)."""
     h, w = p.shape
     return ProblemSpec(h, w, _OPS[p.op], _BNDS[p.boundary], float(p.xi),
@@ -51,7 +52,8 @@ def spec_from_synthetic(p, lam0=None, damping=None, cg_tol=0.0, cg_max_iters=0,
                        float(p.damping if damping is None else damping),
                        taps=None if p.taps is None else np.asarray(p.taps, np.float32),
                        mask=None if p.mask is None else np.asarray(p.mask, np.uint8),
-                       cg_tol=cg_tol, cg_max_iters=cg_max_iters, cg_precond=cg_precond)
+                       cg_tol=cg_tol, cg_max_iters=cg_max_iters, cg_precond=cg_precond,
+                       cg_reduce=cg_reduce)
 
 
 def _problems(specs: Sequence[ProblemSpec]):
@@ -62,6 +64,7 @@ def _problems(specs: Sequence[ProblemSpec]):
         a.height, a.width, a.op, a.boundary = s.height, s.width, s.op, s.boundary
         a.noise_var, a.lambda0, a.damping = s.noise_var, s.lambda0, s.damping
         a.cg_tol, a.cg_max_iters, a.cg_precond = s.cg_tol, s.cg_max_iters, s.cg_precond
+        a.cg_reduce = s.cg_reduce
         if s.taps is not None:
             t = np.ascontiguousarray(s.taps, dtype=np.float32)
             keep.append(t)

@@ -106,6 +106,7 @@ const char* validate(const ep_tv_problem& p) {
   if (!(p.lambda0 > 0.0) || !std::isfinite(p.lambda0)) return "lambda0 must be > 0";
   if (!(p.damping > 0.0 && p.damping <= 1.0)) return "damping must be in (0, 1]";
   if (!(p.cg_tol >= 0.0 && p.cg_tol < 1.0)) return "cg_tol must be in [0, 1)";
+  if (!(p.cg_reduce >= 0.0 && p.cg_reduce < 1.0)) return "cg_reduce must be in [0, 1)";
   if (p.cg_max_iters < 0 || p.cg_max_iters > 100000) return "cg_max_iters must be in [0, 100000]";
   if (p.cg_precond < EP_TV_PRECOND_AUTO || p.cg_precond > EP_TV_PRECOND_CIRCULANT)
     return "cg_precond must be one of EP_TV_PRECOND_*";
@@ -432,6 +433,7 @@ int ep_tv_create(const ep_tv_problem* p, int32_t n, void* d_ws, size_t ws_bytes,
       li[i].damping = c->ih[i].p.damping;
       li[i].cg_tol = c->ih[i].p.cg_tol > 0.0 ? c->ih[i].p.cg_tol : kCgTol;
       li[i].cg_max_iters = c->ih[i].p.cg_max_iters > 0 ? c->ih[i].p.cg_max_iters : kCgMaxIters;
+      li[i].cg_reduce = c->ih[i].p.cg_reduce;
       li[i].precond_req = c->ih[i].p.cg_precond;
       li[i].taps = c->ih[i].taps.empty() ? nullptr : c->ih[i].taps.data();
       li[i].th = c->ih[i].p.blur_h;

@@ -42,6 +42,7 @@ struct InstState {
   double gamma, dbar;        // likelihood site: spectral precision, mean cavity precision
   double cg_rr, cg_bb;       // CG residual / rhs squared norms
   double cg_rz, cg_alpha, cg_beta;
+  double cg_stop2;           // this solve's stopping threshold on ||r||^2 / ||b||^2
   unsigned clamps, flags, active, sweeps;
   int cg_last, cg_total, converged, cg_done;
   int cg_it, x_valid, warm, warm_ok;   // warm: sites were set from a prediction (no skipped q0)

@@ -30,6 +30,7 @@ struct LikInstInfo {
   long long off = 0;
   double xi = 1.0, damping = 1.0;
   double cg_tol = kCgTol;
+  double cg_reduce = 0.0;
   int cg_max_iters = kCgMaxIters;
   int precond_req = PRECOND_REQ_AUTO;
   const float* taps = nullptr;
@@ -51,6 +52,7 @@ struct LikInst {
   int k_off, gr_off, gc_off; // offsets into the taps buffer
   float inv_xi, alpha, diagA, pad;   // diagA = sum of squared taps / xi (diagonal of H^T H / xi)
   double cg_tol2;            // squared relative residual tolerance
+  double cg_reduce2;         // squared residual reduction at which a solve may stop (0: off)
   int cg_max_iters;
   int precond;               // PRECOND_JACOBI or PRECOND_CIRCULANT
   int npart;                 // partial-sum slots of the real-transform passes (fast CG)

@@ -227,6 +227,10 @@ __global__ __launch_bounds__(256) void k_lik_fin(LikArgs A, int stage) {
       st.cg_rz = r0;
       st.cg_rr = r1;
       st.cg_beta = 0.0;
+      // stop at the tolerance, or (cg_reduce > 0) once the residual has fallen
+      // by cg_reduce from where this solve started, whichever comes first
+      st.cg_stop2 = L.cg_tol2;
+      if (st.cg_bb > 0.0) st.cg_stop2 = fmax(L.cg_tol2, L.cg_reduce2 * st.cg_rr / st.cg_bb);
       if (!(st.cg_rr > L.cg_tol2 * st.cg_bb)) st.cg_done = 1;
       break;
     case FIN_ALPHA:
@@ -239,7 +243,7 @@ __global__ __launch_bounds__(256) void k_lik_fin(LikArgs A, int stage) {
       st.cg_rz = r0;
       st.cg_rr = r1;
       st.cg_it += 1;
-      if (!(st.cg_rr > L.cg_tol2 * st.cg_bb) || st.cg_it >= L.cg_max_iters) st.cg_done = 1;
+      if (!(st.cg_rr > st.cg_stop2 * st.cg_bb) || st.cg_it >= L.cg_max_iters) st.cg_done = 1;
       break;
   }
 }
@@ -742,6 +746,7 @@ hipError_t lik_create(LikCtx& lc, const LikInstInfo* li, int n, char* ws, const 
     d.inv_xi = (float)(1.0 / I.xi);
     d.alpha = (float)I.damping;
     d.cg_tol2 = I.cg_tol * I.cg_tol;
+    d.cg_reduce2 = I.cg_reduce * I.cg_reduce;
     d.cg_max_iters = I.cg_max_iters;
     d.precond = lik_precond(I.op, I.H, I.W, I.precond_req);
     d.npart = d.precond == PRECOND_CIRCULANT ? rfft_partials(I.H, I.W) : d.ntiles;

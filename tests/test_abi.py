@@ -52,7 +52,7 @@ def test_workspace_bytes_and_validation():
            ProblemSpec(8, 8, op=N.OP_BLUR_PERIODIC, taps=np.ones((4, 3), np.float32)),
            ProblemSpec(8, 8, op=N.OP_BLUR_PERIODIC),
            ProblemSpec(12, 8, op=N.OP_DFT_MASK, mask=np.ones((12, 8), np.uint8)),
-           ProblemSpec(8, 8, op=7)]
+           ProblemSpec(8, 8, op=7), ProblemSpec(5, 5, cg_reduce=1.0), ProblemSpec(5, 5, cg_reduce=-0.1)]
     for s in bad:
         with pytest.raises(EPTVError):
             ep_tv_workspace_bytes([s])
