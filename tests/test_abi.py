@@ -46,13 +46,17 @@ def test_workspace_bytes_and_validation():
     b1 = ep_tv_workspace_bytes([ok])
     b2 = ep_tv_workspace_bytes([ok, ProblemSpec(300, 17)])
     assert b1 >= 128 * 128 * (5 * 8 + 4) and b2 > b1
+    # the largest accepted sizes (16384 on a side) size without error
+    big = ep_tv_workspace_bytes([ProblemSpec(16384, 3), ProblemSpec(2, 16384)])
+    assert big >= (16384 * 3 + 2 * 16384) * (5 * 8)
     bad = [ProblemSpec(0, 5), ProblemSpec(5, 5, noise_var=0.0), ProblemSpec(5, 5, lambda0=-1),
            ProblemSpec(5, 5, damping=0.0), ProblemSpec(5, 5, damping=1.5),
            ProblemSpec(5, 6, boundary=N.BND_PERIODIC),
            ProblemSpec(8, 8, op=N.OP_BLUR_PERIODIC, taps=np.ones((4, 3), np.float32)),
            ProblemSpec(8, 8, op=N.OP_BLUR_PERIODIC),
            ProblemSpec(12, 8, op=N.OP_DFT_MASK, mask=np.ones((12, 8), np.uint8)),
-           ProblemSpec(8, 8, op=7), ProblemSpec(5, 5, cg_reduce=1.0), ProblemSpec(5, 5, cg_reduce=-0.1)]
+           ProblemSpec(8, 8, op=7), ProblemSpec(5, 5, cg_reduce=1.0), ProblemSpec(5, 5, cg_reduce=-0.1),
+           ProblemSpec(16385, 4), ProblemSpec(4, 16385)]
     for s in bad:
         with pytest.raises(EPTVError):
             ep_tv_workspace_bytes([s])
