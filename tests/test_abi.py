@@ -66,6 +66,9 @@ def test_null_arguments_are_rejected():
     lib = N.lib()
     out = ctypes.c_size_t(0)
     assert lib.ep_tv_workspace_bytes(None, 1, ctypes.byref(out)) == N.EP_TV_E_ARG
+    one = (N.EpTvProblem * 1)()
+    assert lib.ep_tv_workspace_bytes(one, 0, ctypes.byref(out)) == N.EP_TV_E_ARG   # empty batch
+    assert lib.ep_tv_workspace_bytes(one, -1, ctypes.byref(out)) == N.EP_TV_E_ARG
     h = ctypes.c_void_p(None)
     arr = (N.EpTvProblem * 1)()
     assert lib.ep_tv_create(arr, 1, None, 0, None, ctypes.byref(h)) == N.EP_TV_E_ARG
