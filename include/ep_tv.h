@@ -80,7 +80,7 @@ typedef struct {
   double lambda0;              /* > 0: lambda (fixed, or the EM starting value) */
   double damping;              /* in (0, 1]: weight of the new site value in the damped update */
   double cg_tol;               /* CG relative residual ||r||/||b|| for the likelihood site; 0 = 1e-8 */
-  int32_t cg_max_iters;        /* CG iteration cap per likelihood-site update; 0 = 200 */
+  int32_t cg_max_iters;        /* CG iteration cap per likelihood-site update; 0 = 50 */
   int32_t cg_precond;          /* EP_TV_PRECOND_*: CG preconditioner of the likelihood site */
   double cg_reduce;            /* in [0, 1): also stop a likelihood-site CG once its residual
                                   has fallen by this factor from where the solve started

@@ -16,7 +16,11 @@ constexpr int kMaxTaps = 17;
 constexpr int kLikTW = 64;       // likelihood-kernel tile: 64 columns x 16 rows
 constexpr int kLikTH = 16;
 constexpr int kMaxRadius = kMaxTaps - 1;   // radius of the combined H^T H kernel
-constexpr int kCgMaxIters = 200;
+// Iteration cap of one likelihood solve.  It binds only in the first sweeps
+// from a cold start, whose solves cannot reach the tolerance in any affordable
+// number of iterations (thousands, with tau_c spanning ten decades) and whose
+// error EP forgets; the solves near the fixed point need a few iterations.
+constexpr int kCgMaxIters = 50;
 constexpr double kCgTol = 1e-8;            // relative residual ||r|| / ||b||
 constexpr int kCgPoll = 4;                 // CG iterations between convergence checks (even)
 
