@@ -43,6 +43,7 @@ struct LikArgs {
   const float* taps;
   float* hty; float* tauc; float* etac; float* b; float* x; float* r; float* z;
   float* p_in; float* p_out; float* q; float* spec; float* xprev;
+  int r_from_apply;          // the separable H^T H kernel writes the CG start r = b - A x itself
 };
 
 // Deterministic block sum of two doubles (256 threads): a butterfly over the
@@ -398,7 +399,7 @@ __global__ __launch_bounds__(256) void k_hth_sep(LikArgs A) {
   constexpr int NL4 = (EH * EW4 + 255) / 256;        // halo words per thread
   float4 zv4[NL4], pv4[NL4];
   float zv[NL], pv[NL];
-  float4 tc[NQ];
+  float4 tc[NQ], bq[NQ];
   if (inner) {
 #pragma unroll
     for (int u = 0; u < NL4; ++u) {
@@ -435,14 +436,19 @@ __global__ __launch_bounds__(256) void k_hth_sep(LikArgs A) {
 #pragma unroll
   for (int u = 0; u < NQ; ++u) {
     const long long p = L.off + (long long)(t.r0 + qrow(u)) * L.pitch + (t.c0 + qcol(u));
-    float e[4] = {0.f, 0.f, 0.f, 0.f};
+    float e[4] = {0.f, 0.f, 0.f, 0.f}, f[4] = {0.f, 0.f, 0.f, 0.f};
     if (qfull(u)) {
       tc[u] = *reinterpret_cast<const float4*>(A.tauc + p);
+      if (MODE == 0 && A.r_from_apply) bq[u] = *reinterpret_cast<const float4*>(A.b + p);
     } else {
 #pragma unroll
       for (int k = 0; k < 4; ++k)
-        if (t.r0 + qrow(u) < L.H && t.c0 + qcol(u) + k < L.W) e[k] = A.tauc[p + k];
+        if (t.r0 + qrow(u) < L.H && t.c0 + qcol(u) + k < L.W) {
+          e[k] = A.tauc[p + k];
+          if (MODE == 0 && A.r_from_apply) f[k] = A.b[p + k];
+        }
       tc[u] = make_float4(e[0], e[1], e[2], e[3]);
+      if (MODE == 0 && A.r_from_apply) bq[u] = make_float4(f[0], f[1], f[2], f[3]);
     }
   }
   if (inner) {
@@ -520,19 +526,25 @@ __global__ __launch_bounds__(256) void k_hth_sep(LikArgs A) {
     const float4 v4 = *reinterpret_cast<const float4*>(P + (orow + RT) * EW + oc + RT);
     const float v[4] = {v4.x, v4.y, v4.z, v4.w};
     const float tq[4] = {tc[u].x, tc[u].y, tc[u].z, tc[u].w};
-    float qv[4];
+    float qv[4], ov[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) qv[k] = acc[k] * L.inv_xi + tq[k] * v[k];
+    // MODE 0 with r_from_apply: the CG start r = b - A x goes out instead of A x
+    const bool wr = MODE == 0 && A.r_from_apply;
+    const float bb[4] = {bq[u].x, bq[u].y, bq[u].z, bq[u].w};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) ov[k] = wr ? bb[k] - qv[k] : qv[k];
+    float* out = wr ? A.r : A.q;
     const long long p = L.off + (long long)(t.r0 + orow) * L.pitch + (t.c0 + oc);
     if (qfull(u)) {
-      *reinterpret_cast<float4*>(A.q + p) = make_float4(qv[0], qv[1], qv[2], qv[3]);
+      *reinterpret_cast<float4*>(out + p) = make_float4(ov[0], ov[1], ov[2], ov[3]);
 #pragma unroll
       for (int k = 0; k < 4; ++k) dot += (double)v[k] * (double)qv[k];
     } else {
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
         if (t.c0 + oc + k >= L.W) continue;
-        A.q[p + k] = qv[k];
+        out[p + k] = ov[k];
         dot += (double)v[k] * (double)qv[k];
       }
     }
@@ -541,13 +553,14 @@ __global__ __launch_bounds__(256) void k_hth_sep(LikArgs A) {
 }
 
 // ---------------------------------------------------------------------------
-// 5. CG start: r = b - A x (q holds A x)
+// 5. CG start: r = b - A x (q holds A x); blur tiles whose product kernel
+//    wrote r itself are skipped
 __global__ __launch_bounds__(256) void k_cg_init(LikArgs A) {
   const int tile = blockIdx.x;
   const int4 td = A.tiles[tile];
   const LikInst L = A.inst[td.x];
   const InstState& st = A.st[L.inst];
-  if (st.cg_done) return;
+  if (st.cg_done || (A.r_from_apply && L.op == OP_BLUR)) return;
   const TileXY t = lik_tile(td, L);
   float bv[kTileItems], qv[kTileItems];
   tile_two_phase(
@@ -688,8 +701,17 @@ __global__ __launch_bounds__(256) void k_spectrum_blur(LikArgs A) {
 // ---------------------------------------------------------------------------
 // host side
 
+// Blur instances go to the separable H^T H kernel when all of them have
+// separable taps (one kernel per launch), else to the general one.
+static bool blur_all_sep(const LikCtx& lc) {
+  for (const LikInst& d : lc.hinst)
+    if (d.op == OP_BLUR && !d.sep) return false;
+  return true;
+}
+
 static LikArgs make_args(LikCtx& lc) {
   LikArgs A;
+  A.r_from_apply = blur_all_sep(lc) ? 1 : 0;
   A.inst = lc.d_inst;
   A.tiles = lc.d_tiles;
   A.ntiles = lc.ntiles;
