@@ -975,7 +975,9 @@ hipError_t lik_head(LikCtx& lc, float2* const S[5], hipStream_t s) {
   hipLaunchKernelGGL(k_lik_spec, g, b, 0, s, make_args(lc));
   if ((e = fin(lc, FIN_SPEC, s)) != hipSuccess) return e;
   if ((e = launch_apply(lc, 0, s)) != hipSuccess) return e;
-  hipLaunchKernelGGL(k_cg_init, g, b, 0, s, make_args(lc));
+  bool cg_init_needed = !blur_all_sep(lc);
+  for (const LikInst& d : lc.hinst) cg_init_needed = cg_init_needed || d.op != OP_BLUR;
+  if (cg_init_needed) hipLaunchKernelGGL(k_cg_init, g, b, 0, s, make_args(lc));
   if (lc.fast) {
     if ((e = rfft_precondition(lc, 0, s)) != hipSuccess) return e;
   } else {
