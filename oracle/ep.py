@@ -99,7 +99,8 @@ class EPProblem:
         self.h, self.w = op.shape
         self.N = self.h * self.w
         self.xi = float(xi)
-        self.lam0 = float(lam)
+        # l1: lambda; l2: beta; mog2: (omega, s1^2, s2^2); bg: (omega, s^2)
+        self.lam0 = tuple(float(t) for t in lam) if prior in ("mog2", "bg") else float(lam)
         self.damping = float(damping)
         self.prior = prior
         self.boundary = boundary
@@ -245,7 +246,7 @@ def solve(pb: EPProblem, sweeps: int, em: bool, tol: Optional[float] = None,
         mu, v = marginals(st)
         dmu = float(np.max(np.abs(mu - mu_prev))) / yrange
         dv = float(np.max(np.abs(v / v_prev - 1.0)))
-        dl = abs(st.lam / lam_prev - 1.0)
+        dl = abs(st.lam / lam_prev - 1.0) if em else 0.0   # lambda moves under EM only
         if record:
             st.history.append({"t": t, "lam": st.lam, "a_bar": a_bar, "dmu": dmu, "dv": dv,
                                "cg": st.cg_iters})

@@ -34,6 +34,15 @@ l2 check prior, phi(u) = exp(-beta u^2 / 2) (the MoG2-TV prior of Eq.
 (MoG2_TV_prior) with s1 = s2 = 1/beta, up to a constant): the tilted density is
 Gaussian with precision 1/s + beta.
 
+Gaussian-mixture priors, phi(u) = sum_k a_k N(u; 0, v_k): MoG2-TV (Eq.
+(MoG2_TV_prior)), a = (omega, 1 - omega), v = (s1^2, s2^2); BG-TV (Eq. (BG_TV)),
+a = (omega, 1 - omega), v = (s^2, 0), the point mass delta(u) being the v -> 0
+limit of N(u; 0, v).  Each product N(u; m, s) N(u; 0, v_k) is the Gaussian
+N(m; 0, s + v_k) N(u; mu_k, sigma_k^2) with sigma_k^2 = s v_k / (s + v_k) and
+mu_k = m v_k / (s + v_k), so the tilted distribution is the mixture of those
+Gaussians with weights w_k proportional to a_k N(m; 0, s + v_k): its mean is
+sum_k w_k mu_k and its variance sum_k w_k sigma_k^2 + sum_k w_k (mu_k - mean)^2.
+
 Parity pins: tests/test_oracle_tilted.py checks every branch against adaptive
 quadrature and mpmath at 50 digits, plus the lambda -> 0, m = 0 and Laplace
 limits.
@@ -131,9 +140,52 @@ def gauss_tilted(m, s, beta):
     return mu, v, e_abs
 
 
+def mixture_tilted(m, s, a, v):
+    """Mean, variance and E|u| of P(u) ~ N(u; m, s) sum_k a[k] N(u; 0, v[k]),
+    a[k] >= 0, v[k] >= 0 (v[k] = 0: a point mass at 0)."""
+    m = np.asarray(m, dtype=np.float64)
+    s = np.asarray(s, dtype=np.float64)
+    comps = []
+    for ak, vk in zip(a, v):
+        t = s + vk
+        with np.errstate(divide="ignore"):
+            logw = np.log(ak) - 0.5 * np.log(2.0 * math.pi * t) - m * m / (2.0 * t)
+        comps.append((logw, s * vk / t, m * vk / t))
+    top = np.max([c[0] for c in comps], axis=0)
+    ws = [np.exp(c[0] - top) for c in comps]
+    tot = np.sum(ws, axis=0)
+    ws = [w / tot for w in ws]
+    mean = np.sum([w * c[2] for w, c in zip(ws, comps)], axis=0)
+    var = np.sum([w * (c[1] + (c[2] - mean) ** 2) for w, c in zip(ws, comps)], axis=0)
+    e_abs = 0.0
+    for w, (_, vk, mk) in zip(ws, comps):
+        sd = np.sqrt(vk)
+        with np.errstate(divide="ignore", invalid="ignore"):
+            fold = np.where(sd > 0.0, sd * SQRT_2_OVER_PI * np.exp(-mk * mk / (2.0 * np.where(vk > 0, vk, 1.0)))
+                            + mk * (1.0 - erfc(mk / (np.where(sd > 0, sd, 1.0) * SQRT2))), np.abs(mk))
+        e_abs = e_abs + w * fold
+    return mean, var, e_abs
+
+
+def mog2_tilted(m, s, theta):
+    """MoG2-TV (Eq. (MoG2_TV_prior)), theta = (omega, s1^2, s2^2)."""
+    omega, v1, v2 = theta
+    return mixture_tilted(m, s, (omega, 1.0 - omega), (v1, v2))
+
+
+def bg_tilted(m, s, theta):
+    """BG-TV (Eq. (BG_TV)), theta = (omega, s^2)."""
+    omega, v = theta
+    return mixture_tilted(m, s, (omega, 1.0 - omega), (v, 0.0))
+
+
 def tilted(prior, m, s, theta):
     if prior == "l1":
         return laplace_tilted(m, s, theta)
     if prior == "l2":
         return gauss_tilted(m, s, theta)
+    if prior == "mog2":
+        return mog2_tilted(m, s, theta)
+    if prior == "bg":
+        return bg_tilted(m, s, theta)
     raise ValueError(f"unknown prior {prior!r}")

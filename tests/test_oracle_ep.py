@@ -118,6 +118,47 @@ def test_single_edge_update_is_exact_posterior():
     assert abs(v[0, 0] / s1 - 1) < 1e-7 and abs(v[0, 1] / s2 - 1) < 1e-7
 
 
+def test_single_edge_update_is_exact_posterior_mog2():
+    """The same single-edge exactness for the MoG2-TV prior (Eq. (MoG2_TV_prior)):
+    the posterior is a mixture of two 2-D Gaussians, integrated numerically.
+    Exact as long as the tilted variance of u stays below the cavity variance
+    (rho > 0, here 0.63); beyond that the site precision would be negative and
+    the clamp of Sec. III-C applies instead."""
+    y = np.array([[0.2, -0.1]])
+    xi = 0.04
+    theta = (0.3, 0.5, 0.01)
+    pb = ep.EPProblem(y, ops.Operator(ops.IDENTITY, (1, 2)), xi, theta, damping=1.0, prior="mog2")
+    mu, v, st, _ = ep.solve(pb, 1, em=False)
+    om, v1, v2 = theta
+
+    def post(x1, x2):
+        u = x1 - x2
+        phi = om * math.exp(-u * u / (2 * v1)) / math.sqrt(v1) + (1 - om) * math.exp(-u * u / (2 * v2)) / math.sqrt(v2)
+        return math.exp(-((x1 - y[0, 0]) ** 2 + (x2 - y[0, 1]) ** 2) / (2 * xi)) * phi
+    lo, hi = -2.5, 2.5
+    opts = dict(epsabs=0, epsrel=1e-12)
+    Z = integrate.dblquad(lambda b, a: post(a, b), lo, hi, lo, hi, **opts)[0]
+    m1 = integrate.dblquad(lambda b, a: a * post(a, b), lo, hi, lo, hi, **opts)[0] / Z
+    m2 = integrate.dblquad(lambda b, a: b * post(a, b), lo, hi, lo, hi, **opts)[0] / Z
+    s1 = integrate.dblquad(lambda b, a: (a - m1) ** 2 * post(a, b), lo, hi, lo, hi, **opts)[0] / Z
+    s2 = integrate.dblquad(lambda b, a: (b - m2) ** 2 * post(a, b), lo, hi, lo, hi, **opts)[0] / Z
+    assert abs(mu[0, 0] - m1) < 1e-8 and abs(mu[0, 1] - m2) < 1e-8
+    assert abs(v[0, 0] / s1 - 1) < 1e-7 and abs(v[0, 1] / s2 - 1) < 1e-7
+
+
+def test_mixture_prior_with_equal_components_is_l2():
+    """MoG2-TV with s1 = s2 is the Gaussian (l2) pair factor: the whole EP run,
+    through the mixture code path, gives the l2 run's result."""
+    h = w = 8
+    rng = np.random.default_rng(3)
+    y = syn.piecewise_image(h, w, 4, rng) + 0.1 * rng.normal(size=(h, w))
+    op = ops.Operator(ops.IDENTITY, (h, w))
+    beta = 30.0
+    a = ep.solve(ep.EPProblem(y, op, 0.01, beta, damping=0.5, prior="l2"), 30, em=False)
+    b = ep.solve(ep.EPProblem(y, op, 0.01, (0.4, 1 / beta, 1 / beta), damping=0.5, prior="mog2"), 30, em=False)
+    assert np.allclose(a[0], b[0], rtol=0, atol=1e-12) and np.allclose(a[1], b[1], rtol=1e-12)
+
+
 def test_em_fixed_point_is_marginal_likelihood_stationary_point():
     """Single edge: EP is exact, so fast EP-EM converges to a local maximiser of
     log f(y | lambda) = N log(lambda) + log int N(u; y1 - y2, 2 xi) e^{-lambda |u|} du

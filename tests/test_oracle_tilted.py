@@ -185,3 +185,69 @@ def test_gauss_tilted_is_product_of_gaussians():
     f = lambda u: abs(u) * math.exp(-(u - mu[0]) ** 2 / (2 * v[0])) / math.sqrt(2 * math.pi * v[0])
     q = integrate.quad(f, -np.inf, 0)[0] + integrate.quad(f, 0, np.inf)[0]
     assert abs(ea[0] - q) < 1e-12
+
+
+# ---- Gaussian-mixture priors: MoG2-TV (Eq. (MoG2_TV_prior)) and BG-TV (Eq. (BG_TV)) ----
+
+def _mix_quad(m, s, a, v):
+    """Mean and variance of N(u; m, s) sum_k a_k N(u; 0, v_k) by adaptive
+    quadrature (all v_k > 0), with break points at 0 and the component means."""
+    def dens(u):
+        g = math.exp(-(u - m) ** 2 / (2 * s)) / math.sqrt(2 * math.pi * s)
+        return g * sum(ak * math.exp(-u * u / (2 * vk)) / math.sqrt(2 * math.pi * vk) for ak, vk in zip(a, v))
+    sd = math.sqrt(s)
+    lo, hi = min(m, 0.0) - 40 * sd, max(m, 0.0) + 40 * sd
+    pts = sorted({0.0, m} | {m * vk / (s + vk) for vk in v})
+    z = integrate.quad(dens, lo, hi, points=pts, epsabs=0, epsrel=1e-13, limit=400)[0]
+    m1 = integrate.quad(lambda u: u * dens(u), lo, hi, points=pts, epsabs=0, epsrel=1e-13, limit=400)[0] / z
+    m2 = integrate.quad(lambda u: (u - m1) ** 2 * dens(u), lo, hi, points=pts, epsabs=0, epsrel=1e-13,
+                        limit=400)[0] / z
+    return m1, m2
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_mog2_tilted_vs_quad(seed):
+    rng = np.random.default_rng(100 + seed)
+    s = float(10 ** rng.uniform(-3, 0))
+    omega = float(rng.uniform(0.05, 0.95))
+    v1 = float(10 ** rng.uniform(-1, 1))          # large gradients (object boundaries)
+    v2 = float(10 ** rng.uniform(-4, -2))         # small gradients (flat regions)
+    for m in (0.0, 0.3 * math.sqrt(s), -2.0 * math.sqrt(s), 5.0 * math.sqrt(s), 0.7):
+        mean, var, _ = T.mog2_tilted(np.array([m]), np.array([s]), (omega, v1, v2))
+        qm, qv = _mix_quad(m, s, (omega, 1 - omega), (v1, v2))
+        scale = math.sqrt(s)
+        assert abs(mean[0] - qm) <= 1e-9 * scale, (m, mean[0], qm)
+        assert abs(var[0] / qv - 1) <= 1e-8, (m, var[0], qv)
+
+
+def test_bg_tilted_is_the_limit_of_mog2():
+    """The point mass of BG-TV is the s2 -> 0 limit of the MoG2-TV component."""
+    rng = np.random.default_rng(7)
+    m = rng.normal(size=50) * 0.5
+    s = 10 ** rng.uniform(-3, -1, 50)
+    for omega, v in ((0.3, 0.5), (0.9, 2.0), (0.02, 0.1)):
+        b = T.bg_tilted(m, s, (omega, v))
+        g = T.mog2_tilted(m, s, (omega, v, 1e-13))
+        assert np.max(np.abs(b[0] - g[0]) / np.sqrt(s)) <= 1e-5
+        assert np.max(np.abs(b[1] - g[1]) / s) <= 1e-5
+
+
+def test_mixture_special_cases():
+    m = np.array([-1.3, -0.2, 0.0, 0.4, 2.5])
+    s = np.array([0.04, 0.5, 0.1, 0.01, 0.3])
+    # one component, or two equal ones: the Gaussian (l2) prior with beta = 1 / v
+    for theta in ((1.0, 0.7, 0.01), (0.35, 0.7, 0.7)):
+        mean, var, eabs = T.mog2_tilted(m, s, theta)
+        gm, gv, ge = T.gauss_tilted(m, s, 1.0 / 0.7)
+        assert np.allclose(mean, gm, rtol=1e-13, atol=1e-15) and np.allclose(var, gv, rtol=1e-13)
+        assert np.allclose(eabs, ge, rtol=1e-12)
+    # even priors: the moments of -m mirror those of m
+    for f, theta in ((T.mog2_tilted, (0.3, 1.0, 0.001)), (T.bg_tilted, (0.3, 1.0))):
+        a = f(m, s, theta)
+        b = f(-m, s, theta)
+        assert np.array_equal(a[0], -b[0]) and np.array_equal(a[1], b[1])
+    # BG with (almost) all prior mass on the point mass: u is pinned to 0 (the
+    # Gaussian part still gains weight where m is many sigma from 0, so omega
+    # must be far below the likelihood ratio exp(-m^2 / 2s) of these draws)
+    mean, var, _ = T.bg_tilted(m, s, (1e-30, 1.0))
+    assert np.max(np.abs(mean)) <= 1e-9 and np.max(var) <= 1e-9
