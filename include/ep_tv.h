@@ -65,6 +65,14 @@ enum {
  * PERIODIC: wrap-around pairs added (requires even height and width). */
 enum { EP_TV_BND_FREE = 0, EP_TV_BND_PERIODIC = 1 };
 
+/* Pixel-difference factor phi(x_i - x_j) of the TV prior (Sec. II-B):
+ *   L1:   exp(-lambda |u|)                                    (Eq. (L1_TV));
+ *   MOG2: omega N(u; 0, s1^2) + (1 - omega) N(u; 0, s2^2)     (Eq. (MoG2_TV_prior));
+ *   BG:   omega N(u; 0, s^2) + (1 - omega) delta(u)           (Eq. (BG_TV)).
+ * EM of the hyperparameters (Algorithm 2) is defined for L1 only; every
+ * instance of a context uses the same kind. */
+enum { EP_TV_PRIOR_L1 = 0, EP_TV_PRIOR_MOG2 = 1, EP_TV_PRIOR_BG = 2 };
+
 /* One restoration problem.  Host pointers inside are read (copied) by
  * ep_tv_create only. */
 typedef struct {
@@ -88,6 +96,12 @@ typedef struct {
                                   cg_tol floor still holds near it).  0 = solve to cg_tol, as
                                   every earlier sweep's result then follows the exact-solve
                                   trajectory */
+  int32_t prior;               /* EP_TV_PRIOR_*; lambda0 is the L1 lambda (still checked > 0
+                                  for the mixtures, which do not use it) */
+  int32_t reserved;            /* 0 */
+  double prior_omega;          /* MOG2 / BG: omega in (0, 1] */
+  double prior_s1sq;           /* MOG2: s1^2 > 0; BG: s^2 > 0 */
+  double prior_s2sq;           /* MOG2: s2^2 > 0; BG: unused */
 } ep_tv_problem;
 
 /* Preconditioner of the likelihood-site CG.  CIRCULANT is (H^T H / xi + d I)^{-1}
@@ -217,6 +231,15 @@ int ep_tv_get_stats(ep_tv_ctx* ctx, ep_tv_stats* stats);
  * Asynchronous. */
 int ep_tv_tilted_moments(int32_t n, const float* d_m, const float* d_s, float lambda,
                          float* d_rho, float* d_delta, float* d_eabs, void* hip_stream);
+
+/* The same for any factor kind (Sec. III-C with Eqs. (L1_TV), (MoG2_TV_prior),
+ * (BG_TV)): prior = EP_TV_PRIOR_*, theta a host array of its hyperparameters
+ * ({lambda}, {omega, s1^2, s2^2} or {omega, s^2}, validated as in ep_tv_problem).
+ * For the mixtures eabs is written as 0 (E|u| serves only the L1 EM).
+ * Asynchronous. */
+int ep_tv_tilted_moments_prior(int32_t prior, const double* theta, int32_t n, const float* d_m,
+                               const float* d_s, float* d_rho, float* d_delta, float* d_eabs,
+                               void* hip_stream);
 
 /* Diagnostic copy of the likelihood-site working planes of one instance with
  * a non-identity operator (Eqs. (tilted_P_1), (update_q0_x)): d_out (device,

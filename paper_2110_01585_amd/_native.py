@@ -28,6 +28,9 @@ BND_PERIODIC = 1
 PRECOND_AUTO = 0
 PRECOND_JACOBI = 1
 PRECOND_CIRCULANT = 2
+PRIOR_L1 = 0
+PRIOR_MOG2 = 1
+PRIOR_BG = 2
 OPT_GRAPH = 1
 OPT_TILE_ROWS = 2
 
@@ -44,7 +47,10 @@ class EpTvProblem(ctypes.Structure):
                 ("noise_var", ctypes.c_double), ("lambda0", ctypes.c_double),
                 ("damping", ctypes.c_double), ("cg_tol", ctypes.c_double),
                 ("cg_max_iters", ctypes.c_int32), ("cg_precond", ctypes.c_int32),
-                ("cg_reduce", ctypes.c_double)]
+                ("cg_reduce", ctypes.c_double),
+                ("prior", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("prior_omega", ctypes.c_double), ("prior_s1sq", ctypes.c_double),
+                ("prior_s2sq", ctypes.c_double)]
 
 
 class EpTvStats(ctypes.Structure):
@@ -92,6 +98,8 @@ SIGNATURES = {
     "ep_tv_get_stats": (ctypes.c_int, [_P, ctypes.POINTER(EpTvStats)]),
     "ep_tv_get_lik_planes": (ctypes.c_int, [_P, ctypes.c_int32, _P]),
     "ep_tv_tilted_moments": (ctypes.c_int, [ctypes.c_int32, _P, _P, ctypes.c_float, _P, _P, _P, _P]),
+    "ep_tv_tilted_moments_prior": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
+                                                  ctypes.c_int32, _P, _P, _P, _P, _P, _P]),
     "ep_tv_set_timing": (ctypes.c_int, [_P, ctypes.c_int32]),
     "ep_tv_get_timing": (ctypes.c_int, [_P, ctypes.POINTER(EpTvTiming)]),
     "ep_tv_init_warm": (ctypes.c_int, [_P, _FPP, _FPP, ctypes.c_double, ctypes.c_double]),

@@ -37,6 +37,10 @@ class ProblemSpec:
     cg_max_iters: int = 0        # 0 = library default
     cg_precond: int = N.PRECOND_AUTO
     cg_reduce: float = 0.0       # 0 = every solve to cg_tol
+    prior: int = N.PRIOR_L1      # N.PRIOR_*; the mixtures take the three fields below
+    prior_omega: float = 1.0
+    prior_s1sq: float = 1.0
+    prior_s2sq: float = 1.0
 
 
 _OPS = {"identity": N.OP_IDENTITY, "blur": N.OP_BLUR_PERIODIC, "dft": N.OP_DFT_MASK}
@@ -65,6 +69,7 @@ def _problems(specs: Sequence[ProblemSpec]):
         a.noise_var, a.lambda0, a.damping = s.noise_var, s.lambda0, s.damping
         a.cg_tol, a.cg_max_iters, a.cg_precond = s.cg_tol, s.cg_max_iters, s.cg_precond
         a.cg_reduce = s.cg_reduce
+        a.prior, a.prior_omega, a.prior_s1sq, a.prior_s2sq = s.prior, s.prior_omega, s.prior_s1sq, s.prior_s2sq
         if s.taps is not None:
             t = np.ascontiguousarray(s.taps, dtype=np.float32)
             keep.append(t)
@@ -95,6 +100,22 @@ def ep_tv_workspace_bytes(specs: Sequence[ProblemSpec]) -> int:
     if rc != 0:
         raise EPTVError(rc, "invalid problem description")
     return int(out.value)
+
+
+def ep_tv_tilted_moments_prior(prior, theta, m, s, stream=None):
+    """rho, delta and E|u| (0 for the mixtures) of N(u; m, s) phi(u) for the factor
+    kind `prior` (N.PRIOR_*) with hyperparameters theta ({lambda}, {omega, s1^2,
+    s2^2} or {omega, s^2}).  m, s: contiguous float32 CUDA tensors."""
+    import torch
+    n = m.numel()
+    rho = torch.empty_like(m); de = torch.empty_like(m); ea = torch.empty_like(m)
+    th = (ctypes.c_double * 3)(*([float(t) for t in theta] + [0.0] * (3 - len(theta))))
+    st = stream if stream is not None else torch.cuda.current_stream()
+    rc = N.lib().ep_tv_tilted_moments_prior(int(prior), th, n, m.data_ptr(), s.data_ptr(), rho.data_ptr(),
+                                            de.data_ptr(), ea.data_ptr(), st.cuda_stream)
+    if rc != 0:
+        raise EPTVError(rc, "ep_tv_tilted_moments_prior failed")
+    return rho, de, ea
 
 
 def ep_tv_tilted_moments(m, s, lam, stream=None):

@@ -107,6 +107,13 @@ const char* validate(const ep_tv_problem& p) {
   if (!(p.damping > 0.0 && p.damping <= 1.0)) return "damping must be in (0, 1]";
   if (!(p.cg_tol >= 0.0 && p.cg_tol < 1.0)) return "cg_tol must be in [0, 1)";
   if (!(p.cg_reduce >= 0.0 && p.cg_reduce < 1.0)) return "cg_reduce must be in [0, 1)";
+  if (p.prior < EP_TV_PRIOR_L1 || p.prior > EP_TV_PRIOR_BG) return "prior must be one of EP_TV_PRIOR_*";
+  if (p.prior != EP_TV_PRIOR_L1) {
+    if (!(p.prior_omega > 0.0 && p.prior_omega <= 1.0)) return "prior_omega must be in (0, 1]";
+    if (!(p.prior_s1sq > 0.0) || !std::isfinite(p.prior_s1sq)) return "prior_s1sq must be > 0";
+    if (p.prior == EP_TV_PRIOR_MOG2 && (!(p.prior_s2sq > 0.0) || !std::isfinite(p.prior_s2sq)))
+      return "prior_s2sq must be > 0";
+  }
   if (p.cg_max_iters < 0 || p.cg_max_iters > 100000) return "cg_max_iters must be in [0, 100000]";
   if (p.cg_precond < EP_TV_PRECOND_AUTO || p.cg_precond > EP_TV_PRECOND_CIRCULANT)
     return "cg_precond must be one of EP_TV_PRECOND_*";
@@ -314,6 +321,15 @@ static int upload_tiles(ep_tv_ctx* c) {
     d.ntiles = h.ntiles; d.chunk_rows = h.chunk_rows; d.npix = h.p.height * h.p.width;
     d.xi = (float)h.p.noise_var; d.inv_xi = (float)(1.0 / h.p.noise_var);
     d.alpha = (float)h.p.damping;
+    if (h.p.prior != EP_TV_PRIOR_L1) {
+      // phi = a1 N(0, v1) + a2 N(0, v2): MoG2 (omega, 1 - omega; s1^2, s2^2), BG (v2 = 0)
+      const double a1 = h.p.prior_omega, a2 = 1.0 - h.p.prior_omega;
+      const double v1 = h.p.prior_s1sq, v2 = h.p.prior == EP_TV_PRIOR_MOG2 ? h.p.prior_s2sq : 0.0;
+      d.mix_dla = (float)(a2 > 0.0 ? std::log(a2 / a1) : -HUGE_VAL);
+      d.mix_dv = (float)(v1 - v2);
+      d.mix_v1 = (float)v1;
+      d.mix_v2 = (float)v2;
+    }
     for (int st = 0; st < h.strips; ++st)
       for (int ch = 0; ch < h.chunks; ++ch) c->tiles_host.push_back(make_int4(i, st, ch, 0));
   }
@@ -392,7 +408,12 @@ int ep_tv_create(const ep_tv_problem* p, int32_t n, void* d_ws, size_t ws_bytes,
       c->ih[i].p.dft_mask = nullptr;
     }
     if (p[i].op != EP_TV_OP_IDENTITY) c->any_lik = true;
+    if (p[i].prior != p[0].prior) {   // the sweep is compiled per factor kind
+      delete c;
+      return EP_TV_E_ARG;
+    }
   }
+  c->sa.prior = p[0].prior;
   make_layout(c->ih, initial_rows(p, n), c->L);
   c->chunk_rows = c->ih[0].chunk_rows;
   if (ws_bytes < c->L.total) {
@@ -680,6 +701,7 @@ static int advance(ep_tv_ctx* c, int n, int em, bool delta, double tol) {
 int ep_tv_run(ep_tv_ctx* c, int32_t n_sweeps, int32_t em) {
   if (!c || n_sweeps < 0) return EP_TV_E_ARG;
   if (!c->has_obs) return fail(c, EP_TV_E_STATE, "no observation set");
+  if (em && c->sa.prior != PRIOR_L1) return fail(c, EP_TV_E_ARG, "EM is defined for the l1 factor only");
   return advance(c, n_sweeps, em ? 1 : 0, false, 0.0);
 }
 
@@ -701,6 +723,7 @@ static int pull_states(ep_tv_ctx* c) {
 int ep_tv_em_step(ep_tv_ctx* c, int32_t n_ep, double* lambda_out) {
   if (!c || n_ep < 1) return EP_TV_E_ARG;
   if (!c->has_obs) return fail(c, EP_TV_E_STATE, "no observation set");
+  if (c->sa.prior != PRIOR_L1) return fail(c, EP_TV_E_ARG, "EM is defined for the l1 factor only");
   for (int t = 0; t < n_ep; ++t) {
     int rc = one_sweep(c, t == n_ep - 1 ? 1 : 0, false, 0.0);
     if (rc) return rc;
@@ -763,6 +786,7 @@ int ep_tv_solve(ep_tv_ctx* c, int32_t max_sweeps, double tol, int32_t em, float*
                 float* const* d_var, ep_tv_stats* stats) {
   if (!c || max_sweeps < 0) return EP_TV_E_ARG;
   if (!c->has_obs) return fail(c, EP_TV_E_STATE, "no observation set");
+  if (em && c->sa.prior != PRIOR_L1) return fail(c, EP_TV_E_ARG, "EM is defined for the l1 factor only");
   const auto t0 = std::chrono::steady_clock::now();
   const bool use_tol = tol > 0.0;
   const int check_every = kGraphSweeps;
@@ -864,6 +888,30 @@ int ep_tv_tilted_moments(int32_t n, const float* d_m, const float* d_s, float la
                     reinterpret_cast<hipStream_t>(stream)) != hipSuccess)
     return EP_TV_E_HIP;
   return EP_TV_OK;
+}
+
+int ep_tv_tilted_moments_prior(int32_t prior, const double* theta, int32_t n, const float* d_m,
+                               const float* d_s, float* d_rho, float* d_delta, float* d_eabs,
+                               void* stream) {
+  if (!theta || n < 0 || (n > 0 && (!d_m || !d_s || !d_rho || !d_delta || !d_eabs)))
+    return EP_TV_E_ARG;
+  const hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  hipError_t e;
+  if (prior == EP_TV_PRIOR_L1) {
+    if (!(theta[0] >= 0.0) || !std::isfinite(theta[0])) return EP_TV_E_ARG;
+    e = launch_tilted(n, d_m, d_s, (float)theta[0], d_rho, d_delta, d_eabs, s);
+  } else if (prior == EP_TV_PRIOR_MOG2 || prior == EP_TV_PRIOR_BG) {
+    const double om = theta[0], v1 = theta[1];
+    const double v2 = prior == EP_TV_PRIOR_MOG2 ? theta[2] : 0.0;
+    if (!(om > 0.0 && om <= 1.0) || !(v1 > 0.0) || !std::isfinite(v1)) return EP_TV_E_ARG;
+    if (prior == EP_TV_PRIOR_MOG2 && (!(v2 > 0.0) || !std::isfinite(v2))) return EP_TV_E_ARG;
+    const double a2 = 1.0 - om;
+    e = launch_tilted_mixture(n, d_m, d_s, (float)(a2 > 0.0 ? std::log(a2 / om) : -HUGE_VAL),
+                              (float)(v1 - v2), (float)v1, (float)v2, d_rho, d_delta, d_eabs, s);
+  } else {
+    return EP_TV_E_ARG;
+  }
+  return e == hipSuccess ? EP_TV_OK : EP_TV_E_HIP;
 }
 
 int ep_tv_set_timing(ep_tv_ctx* c, int32_t enable) {

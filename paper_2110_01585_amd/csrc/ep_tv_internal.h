@@ -32,7 +32,11 @@ struct InstDev {
   int op, strips, chunks, tile0;
   int ntiles, chunk_rows, npix, pad0;
   float xi, inv_xi, alpha, pad1;
+  float mix_dla, mix_dv, mix_v1, mix_v2;   // mixture factor: log(a2/a1), v1 - v2, v1, v2
 };
+
+// factor kinds (the sweep is compiled once per kind; a context uses one)
+enum { PRIOR_L1 = 0, PRIOR_MOG2 = 1, PRIOR_BG = 2 };
 
 struct InstState {
   double lam, lam_prev;      // current / previous lambda
@@ -67,6 +71,7 @@ struct SweepArgs {
   float* part_dv;
   unsigned* part_clamp;
   unsigned* part_flags;
+  int prior;                 // PRIOR_* of every instance of the context
 };
 
 // Map a block index so that consecutive tiles land on the same XCD (workgroups
@@ -84,6 +89,9 @@ hipError_t launch_tv_sweep(const SweepArgs& a, bool want_delta, hipStream_t s);
 
 hipError_t launch_tilted(int n, const float* m, const float* s, float lam, float* rho, float* del,
                          float* eabs, hipStream_t st);
+hipError_t launch_tilted_mixture(int n, const float* m, const float* s, float dla, float dv,
+                                 float v1, float v2, float* rho, float* del, float* eabs,
+                                 hipStream_t st);
 hipError_t launch_init_cold(float2* const S[5], const float* y_pix, const InstDev* inst,
                             InstState* st, const int4* tiles, int ntiles, hipStream_t s);
 hipError_t launch_finalize(const InstDev* inst, InstState* st, int n, const SweepArgs& a,

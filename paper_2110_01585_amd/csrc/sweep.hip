@@ -64,20 +64,21 @@ struct PairOut {
 // the site update of Eq. (update_qk_x) in the equivalent cancellation-free
 // form tau_i = rho / (s - rho c_i), eta_i = tau_i E_i + delta / s (and i<->j,
 // delta -> -delta); variance clamp of Sec. III-C at 1e8.
-__device__ __forceinline__ PairOut pair_core(float ci, float mi, float cj, float mj, float lam) {
+template <class PR>
+__device__ __forceinline__ PairOut pair_core(float ci, float mi, float cj, float mj, const PR& lam) {
   // no contraction into fused multiply-adds: the update of (i, j) must be the
   // exact mirror of the update of (j, i).  The fused multiply-adds written out
   // map onto each other under the exchange (delta changes sign, s and rho do
   // not), so they keep the mirror exact.
 #pragma clang fp contract(off)
   const float s = ci + cj;
-  const Tilt T = laplace_tilt(mi - mj, s, lam);
+  const Tilt T = lam.tilt(mi - mj, s);
   const float dels = T.delta * frcp(s);
   const float Ei = __builtin_fmaf(dels, ci, mi);
   const float Ej = __builtin_fmaf(-dels, cj, mj);
   PairOut o;
-  o.ti = T.rho * frcp(__builtin_fmaf(-T.rho, ci, s));
-  o.tj = T.rho * frcp(__builtin_fmaf(-T.rho, cj, s));
+  o.ti = T.rho * frcp(lam.den(T, s, ci, cj));
+  o.tj = T.rho * frcp(lam.den(T, s, cj, ci));
   o.ki = o.ti < kPrecFloor;
   o.kj = o.tj < kPrecFloor;
   o.ti = o.ki ? kPrecFloor : o.ti;
@@ -100,9 +101,9 @@ struct Acc {
 };
 
 // Pair inside one lane (V1 on a row, V3/V4 on a column).
-template <int K>
+template <int K, class PR>
 __device__ __forceinline__ void pair_local(Px& P, Px& Q, bool exists, bool cnt_edge, bool cnt_p,
-                                           bool cnt_q, float lam, float alpha, Acc& acc) {
+                                           bool cnt_q, const PR& lam, float alpha, Acc& acc) {
   float ci, mi, cj, mj;
   cavity<K>(P, ci, mi);
   cavity<K>(Q, cj, mj);
@@ -117,8 +118,9 @@ __device__ __forceinline__ void pair_local(Px& P, Px& Q, bool exists, bool cnt_e
 
 // V2 pair: this lane's right pixel R with the next lane's left pixel.
 // exists: the pair (R, next L) exists (evaluated by the owning lane).
+template <class PR>
 __device__ __forceinline__ void pair_v2(Px& L, Px& R, bool exists, bool cnt_edge, bool cnt_r,
-                                        bool cnt_l, float lam, float alpha, Acc& acc, int lane) {
+                                        bool cnt_l, const PR& lam, float alpha, Acc& acc, int lane) {
   float cl, ml;
   cavity<2>(L, cl, ml);
   const float cj = __shfl_down(cl, 1, kWave);
@@ -210,8 +212,9 @@ __device__ __forceinline__ int wrap(int i, int n) {
 // update of its own pixel.  Every wave of the block calls this at the same two
 // points (after its first and after its last row pair), shared boundary or not,
 // so the barriers match.  X: LDS, [2 phases][kWavesPerBlock][kWave].
+template <class PR>
 __device__ __forceinline__ void pair_x4_one(Px& own, bool own_top, float co, float mo, float cp,
-                                            float mp, bool exists, bool own_int, float lam,
+                                            float mp, bool exists, bool own_int, const PR& lam,
                                             float alpha, Acc& acc) {
   const float ci = own_top ? co : cp, mi = own_top ? mo : mp;
   const float cj = own_top ? cp : co, mj = own_top ? mp : mo;
@@ -223,9 +226,10 @@ __device__ __forceinline__ void pair_x4_one(Px& own, bool own_top, float co, flo
   }
 }
 
+template <class PR>
 __device__ __forceinline__ void exchange_v4(float4* X, int phase, int wave, int partner, int lane,
                                             bool shared, Px& oL, Px& oR, bool own_top, bool vL,
-                                            bool vR, bool wL, bool wR, float lam, float alpha,
+                                            bool vR, bool wL, bool wR, const PR& lam, float alpha,
                                             Acc& acc) {
   float cL = 0.f, mL = 0.f, cR = 0.f, mR = 0.f;
   if (shared) {
@@ -279,13 +283,26 @@ __device__ __forceinline__ void finish_row(const SweepArgs& a, long long idx, bo
 //         are final; row r+1 is carried;
 //   up:   pair (r, r+1), then V4 on (r+1, r+2) with row r+2 carried; rows
 //         r+1, r+2 are final; row r is carried.
-template <bool DELTA, bool UP>
+// The factor of an instance: lambda for l1 (it moves under EM), the mixture
+// constants for MoG2 / BG (fixed).
+__device__ __forceinline__ void make_factor(const InstDev&, const InstState& st, L1Factor& f) {
+  f.lam = (float)st.lam;
+}
+__device__ __forceinline__ void make_factor(const InstDev& I, const InstState&, MixtureFactor& f) {
+  f.f.dla = I.mix_dla;
+  f.f.dv = I.mix_dv;
+  f.f.v1 = I.mix_v1;
+  f.f.v2 = I.mix_v2;
+}
+
+template <bool DELTA, bool UP, class PR>
 __device__ __forceinline__ void sweep_tile(const SweepArgs& a, int tile, int wave, int lane,
                                            bool x_start, bool x_end, float4* X) {
   const int4 td = a.tiles[tile];
   const InstDev I = a.inst[td.x];
   const InstState& ST = a.st[td.x];
-  const float lam = (float)ST.lam;
+  PR lam;
+  make_factor(I, ST, lam);
   const float alpha = I.alpha;
   const bool per = I.bnd == BND_PERIODIC;
   const int W = I.W, H = I.H;
@@ -449,7 +466,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, int tile, int wav
 // One wave per tile; consecutive tiles (vertically adjacent chunks of a strip)
 // form a block, whose shared boundaries exchange cavities in LDS instead of
 // recomputing halo rows; neighbouring blocks are mapped to the same XCD.
-template <bool DELTA>
+template <bool DELTA, class PR>
 __global__ __launch_bounds__(kWavesPerBlock * kWave) void k_tv_sweep(SweepArgs a) {
   __shared__ float4 X[2 * kWavesPerBlock * kWave];
   const int wave = threadIdx.x >> 6;
@@ -479,18 +496,19 @@ __global__ __launch_bounds__(kWavesPerBlock * kWave) void k_tv_sweep(SweepArgs a
     sh_dn = t.x == td.x && t.y == td.y && t.z == td.z + 1;
   }
   if (td.z & 1)
-    sweep_tile<DELTA, false>(a, tile, wave, lane, sh_up, sh_dn, X);
+    sweep_tile<DELTA, false, PR>(a, tile, wave, lane, sh_up, sh_dn, X);
   else
-    sweep_tile<DELTA, true>(a, tile, wave, lane, sh_dn, sh_up, X);
+    sweep_tile<DELTA, true, PR>(a, tile, wave, lane, sh_dn, sh_up, X);
 }
 
+template <class PR>
 __global__ __launch_bounds__(256) void k_tilted(int n, const float* __restrict__ m,
-                                                const float* __restrict__ s, float lam,
+                                                const float* __restrict__ s, PR f,
                                                 float* __restrict__ rho, float* __restrict__ del,
                                                 float* __restrict__ eabs) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  const Tilt T = laplace_tilt(m[i], s[i], lam);
+  const Tilt T = f.tilt(m[i], s[i]);
   rho[i] = T.rho;
   del[i] = T.delta;
   eabs[i] = T.eabs;
@@ -499,18 +517,38 @@ __global__ __launch_bounds__(256) void k_tilted(int n, const float* __restrict__
 hipError_t launch_tilted(int n, const float* m, const float* s, float lam, float* rho, float* del,
                          float* eabs, hipStream_t st) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_tilted, dim3((n + 255) / 256), dim3(256), 0, st, n, m, s, lam, rho, del,
-                     eabs);
+  L1Factor f;
+  f.lam = lam;
+  hipLaunchKernelGGL(k_tilted<L1Factor>, dim3((n + 255) / 256), dim3(256), 0, st, n, m, s, f, rho,
+                     del, eabs);
+  return hipGetLastError();
+}
+
+hipError_t launch_tilted_mixture(int n, const float* m, const float* s, float dla, float dv,
+                                 float v1, float v2, float* rho, float* del, float* eabs,
+                                 hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  MixtureFactor f;
+  f.f.dla = dla;
+  f.f.dv = dv;
+  f.f.v1 = v1;
+  f.f.v2 = v2;
+  hipLaunchKernelGGL(k_tilted<MixtureFactor>, dim3((n + 255) / 256), dim3(256), 0, st, n, m, s, f,
+                     rho, del, eabs);
   return hipGetLastError();
 }
 
 hipError_t launch_tv_sweep(const SweepArgs& a, bool want_delta, hipStream_t s) {
   const int blocks = (a.ntiles + kWavesPerBlock - 1) / kWavesPerBlock;
   if (blocks == 0) return hipSuccess;
-  if (want_delta)
-    hipLaunchKernelGGL(k_tv_sweep<true>, dim3(blocks), dim3(kWavesPerBlock * kWave), 0, s, a);
-  else
-    hipLaunchKernelGGL(k_tv_sweep<false>, dim3(blocks), dim3(kWavesPerBlock * kWave), 0, s, a);
+  const dim3 g(blocks), b(kWavesPerBlock * kWave);
+  if (a.prior == PRIOR_L1) {
+    if (want_delta) hipLaunchKernelGGL((k_tv_sweep<true, L1Factor>), g, b, 0, s, a);
+    else hipLaunchKernelGGL((k_tv_sweep<false, L1Factor>), g, b, 0, s, a);
+  } else {
+    if (want_delta) hipLaunchKernelGGL((k_tv_sweep<true, MixtureFactor>), g, b, 0, s, a);
+    else hipLaunchKernelGGL((k_tv_sweep<false, MixtureFactor>), g, b, 0, s, a);
+  }
   return hipGetLastError();
 }
 

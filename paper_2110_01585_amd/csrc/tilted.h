@@ -30,6 +30,7 @@ struct Tilt {
   float rho;    // 1 - S_bar / s
   float delta;  // m_bar - m
   float eabs;   // E|u| under the tilted distribution
+  float omr;    // S_bar / s = 1 - rho, formed without the subtraction (mixture factors)
 };
 
 // K(x) = t G(s) with z = x / sqrt2, t = 2 / (2 + z), s = 2 t - 1: G is a
@@ -113,7 +114,68 @@ __device__ __forceinline__ Tilt laplace_tilt(float m, float s, float lam) {
   T.rho = __builtin_fmaf(-(pp * pm * Ks), Ks, pp * rp * Kp + pm * rm * Km);
   T.delta = __builtin_fmaf(sig, pp * rp - pm * rm, -(ls * (pp - pm)));
   T.eabs = sig * (pp * Kp + pm * Km);
+  T.omr = 0.f;   // not used for this factor
   return T;
 }
+
+// Tilted moments for a two-component Gaussian-mixture factor
+// phi(u) = a1 N(u; 0, v1) + a2 N(u; 0, v2): MoG2-TV (Eq. (MoG2_TV_prior)) and
+// BG-TV (Eq. (BG_TV), v2 = 0 for the point mass).  Each product with the cavity
+// N(u; m, s) is N(m; 0, t_k) N(u; mu_k, sigma_k^2), t_k = s + v_k, with
+// mu_k - m = -m s / t_k and sigma_k^2 = s v_k / t_k; the weights follow from
+// log(w2 / w1) = log(a2 / a1) + log(t1 / t2) / 2 - m^2 (v1 - v2) / (2 t1 t2),
+// in which no two large numbers are subtracted.  With i_k = 1 / t_k:
+//   delta = m_bar - m = -m s (w1 i1 + w2 i2),
+//   rho = 1 - S_bar / s = s (w1 i1 + w2 i2) - w1 w2 m^2 s (i2 - i1)^2,
+//   S_bar / s = w1 v1 i1 + w2 v2 i2 + w1 w2 m^2 s (i2 - i1)^2,
+// the last term being the spread of the component means (law of total
+// variance).  S_bar / s is a sum of non-negative terms; the site update takes
+// it where it needs 1 - rho (a point mass or a narrow component can make rho
+// come within rounding of 1).  Only m^2 and m times an even function of m enter, so the moments
+// of -m mirror those of m exactly.  E|u| is not formed: it serves only the
+// EM of the l1 factor.
+struct MixFactor {
+  float dla;   // log(a2 / a1)
+  float dv;    // v1 - v2
+  float v1, v2;
+};
+
+__device__ __forceinline__ Tilt mixture_tilt(float m, float s, const MixFactor& F) {
+  const float t1 = s + F.v1, t2 = s + F.v2;
+  const float i1 = frcp(t1), i2 = frcp(t2);
+  const float m2 = m * m;
+  const float di = F.dv * i1 * i2;                       // i2 - i1
+  const float d = F.dla + 0.5f * __logf(t1 * i2) - 0.5f * m2 * di;
+  const float g = __expf(-fabsf(d));
+  const float whi = frcp(1.0f + g), wlo = g * whi;
+  const float w1 = d > 0.f ? wlo : whi;
+  const float w2 = d > 0.f ? whi : wlo;
+  const float wi = w1 * i1 + w2 * i2;
+  Tilt T;
+  const float spread = (w1 * w2) * (m2 * s) * (di * di);
+  T.delta = -(m * (s * wi));
+  T.rho = s * wi - spread;
+  T.omr = w1 * (F.v1 * i1) + w2 * (F.v2 * i2) + spread;
+  T.eabs = 0.f;
+  return T;
+}
+
+// The factor kinds as types, so the sweep is compiled once per kind.
+// den(T, s, c_own, c_other) is s - rho c_own = c_other + (1 - rho) c_own, the
+// denominator of the site precision rho / (s - rho c_own) of Eq. (update_qk_x).
+struct L1Factor {
+  float lam;
+  __device__ __forceinline__ Tilt tilt(float m, float s) const { return laplace_tilt(m, s, lam); }
+  __device__ __forceinline__ float den(const Tilt& T, float s, float c_own, float) const {
+    return __builtin_fmaf(-T.rho, c_own, s);
+  }
+};
+struct MixtureFactor {
+  MixFactor f;
+  __device__ __forceinline__ Tilt tilt(float m, float s) const { return mixture_tilt(m, s, f); }
+  __device__ __forceinline__ float den(const Tilt& T, float, float c_own, float c_other) const {
+    return __builtin_fmaf(T.omr, c_own, c_other);
+  }
+};
 
 }  // namespace eptv

@@ -46,6 +46,9 @@ def test_workspace_bytes_and_validation():
     b1 = ep_tv_workspace_bytes([ok])
     b2 = ep_tv_workspace_bytes([ok, ProblemSpec(300, 17)])
     assert b1 >= 128 * 128 * (5 * 8 + 4) and b2 > b1
+    # the mixture factors: BG ignores s2^2
+    ep_tv_workspace_bytes([ProblemSpec(9, 9, prior=N.PRIOR_BG, prior_omega=0.2, prior_s1sq=0.3, prior_s2sq=0.0)])
+    ep_tv_workspace_bytes([ProblemSpec(9, 9, prior=N.PRIOR_MOG2, prior_omega=1.0, prior_s1sq=0.3, prior_s2sq=1e-3)])
     # the largest accepted sizes (16384 on a side) size without error
     big = ep_tv_workspace_bytes([ProblemSpec(16384, 3), ProblemSpec(2, 16384)])
     assert big >= (16384 * 3 + 2 * 16384) * (5 * 8)
@@ -56,7 +59,11 @@ def test_workspace_bytes_and_validation():
            ProblemSpec(8, 8, op=N.OP_BLUR_PERIODIC),
            ProblemSpec(12, 8, op=N.OP_DFT_MASK, mask=np.ones((12, 8), np.uint8)),
            ProblemSpec(8, 8, op=7), ProblemSpec(5, 5, cg_reduce=1.0), ProblemSpec(5, 5, cg_reduce=-0.1),
-           ProblemSpec(16385, 4), ProblemSpec(4, 16385)]
+           ProblemSpec(16385, 4), ProblemSpec(4, 16385), ProblemSpec(5, 5, prior=7),
+           ProblemSpec(5, 5, prior=N.PRIOR_MOG2, prior_omega=0.0),
+           ProblemSpec(5, 5, prior=N.PRIOR_MOG2, prior_omega=1.5),
+           ProblemSpec(5, 5, prior=N.PRIOR_MOG2, prior_s2sq=0.0),
+           ProblemSpec(5, 5, prior=N.PRIOR_BG, prior_s1sq=-1.0)]
     for s in bad:
         with pytest.raises(EPTVError):
             ep_tv_workspace_bytes([s])
