@@ -129,14 +129,15 @@ def problem_from_synthetic(p, prior="l1", estimator="spectral", boundary=None, o
 
 def init_cold(pb: EPProblem) -> EPState:
     """Initialisation line of Algorithm 1: q_{x,0} = N(y, xi I) when y lives in
-    pixel space (denoising, deconvolution); for the masked DFT, whose y are
-    Fourier coefficients, the pixel-space back-projection H^T y takes its place.
+    pixel space (denoising, deconvolution); for the masked DFT and Walsh-Hadamard
+    operators, whose y are transform coefficients, the pixel-space
+    back-projection H^T y takes its place.
     TV sites get variance 1e8 where covered."""
     N = pb.N
     tau = np.zeros((5, N))
     eta = np.zeros((5, N))
     tau[0] = 1.0 / pb.xi
-    y0 = pb.hty if pb.op.kind == ops.DFT else np.asarray(pb.y, dtype=np.float64)
+    y0 = pb.hty if pb.op.kind in (ops.DFT, ops.HADAMARD) else np.asarray(pb.y, dtype=np.float64)
     eta[0] = y0.ravel() / pb.xi
     for k in range(4):
         tau[k + 1, pb.covered[k]] = SITE_INIT_PREC
@@ -234,7 +235,7 @@ def solve(pb: EPProblem, sweeps: int, em: bool, tol: Optional[float] = None,
         |lambda_t / lambda_{t-1} - 1| <= tol (EM only).
     Returns (mu, v, state, info)."""
     st = init_cold(pb) if state is None else state
-    yr = np.asarray(pb.hty if pb.op.kind == ops.DFT else pb.y, dtype=np.float64)
+    yr = np.asarray(pb.hty if pb.op.kind in (ops.DFT, ops.HADAMARD) else pb.y, dtype=np.float64)
     yrange = float(yr.max() - yr.min()) or 1.0
     mu_prev, v_prev = marginals(st)
     done = 0

@@ -11,7 +11,14 @@ Sec. II-A, Eq. (1): y = H x + n, n ~ N(0, xi I).  Three operators:
 * masked orthonormal 2-D DFT (compressive sensing, case (iii) replaced by a
   Fourier sensing matrix): observations are the masked complex coefficients of
   F x.  Treating (Re, Im) of each kept coefficient as two real observations of
-  variance xi gives H^T H x = Re(F^H P F x) and H^T y = Re(F^H P y).
+  variance xi gives H^T H x = Re(F^H P F x) and H^T y = Re(F^H P y);
+* subsampled Paley-ordered 2-D Walsh-Hadamard transform (compressive sensing,
+  case (iii) with the paper's Hadamard sensing matrix, Sec. II-A and the CS
+  experiment of Sec. V): observations are the kept coefficients
+  (W x)(u, v) = sum_{r,c} w_u(r) w_v(c) x(r, c) / sqrt(h w), where w_k is the
+  k-th Walsh function in Paley order, the product of the Rademacher functions
+  selected by the binary digits of k.  W is real and orthonormal, so
+  H^T H = W^T P W is diagonal in the Walsh basis with the mask as eigenvalues.
 
 The blur H and H^T are written as sums of shifted copies (their definition);
 H^T H and its spectrum use the FFT (a library primitive), and tests check the
@@ -26,7 +33,10 @@ it is exact when H^T H is diagonal and otherwise names Monte Carlo estimators
               inverse is circulant and its diagonal is the constant
               c = mean_w 1 / (|H(w)|^2 / xi + d); the site precision is then the
               constant gamma = 1/c - d, and the tilted variance at pixel p is
-              1 / (gamma + tau_c[p]).  Exact when tau_c is constant.
+              1 / (gamma + tau_c[p]).  Exact when tau_c is constant.  For the
+              Walsh-Hadamard operator the same holds with the Walsh basis in
+              place of the Fourier basis (every Walsh function has squared
+              entries 1 / N, like every Fourier mode).
 """
 from __future__ import annotations
 
@@ -35,6 +45,26 @@ import numpy as np
 IDENTITY = "identity"
 BLUR = "blur"
 DFT = "dft"
+HADAMARD = "hadamard"
+
+
+def walsh_paley(n):
+    """n x n matrix of the Walsh functions in Paley order sampled at t = j / n
+    (n a power of two), from their definition: w_k = prod_i r_{i+1}^{k_i} with
+    k_i the binary digits of k and r_{i+1}(t) = sign(sin(2^{i+1} pi t)) the
+    Rademacher functions, which at t = j / n is -1 exactly when binary digit
+    i + 1 after the point of t, bit (m - 1 - i) of j, is one (n = 2^m)."""
+    m = int(round(np.log2(n)))
+    if 1 << m != n:
+        raise ValueError("Walsh matrix size must be a power of two")
+    j = np.arange(n)
+    out = np.ones((n, n))
+    for k in range(n):
+        for i in range(m):
+            if (k >> i) & 1:
+                rad = np.where((j >> (m - 1 - i)) & 1, -1.0, 1.0)
+                out[k] *= rad
+    return out
 
 
 class Operator:
@@ -47,9 +77,21 @@ class Operator:
             kh, kw = self.taps.shape
             if kh % 2 == 0 or kw % 2 == 0:
                 raise ValueError("blur taps must have odd sizes")
-        if kind == DFT and self.mask.shape != self.shape:
+        if kind in (DFT, HADAMARD) and self.mask.shape != self.shape:
             raise ValueError("mask shape mismatch")
         self._spec = None
+        if kind == HADAMARD:
+            self._wr = walsh_paley(self.shape[0])
+            self._wc = walsh_paley(self.shape[1])
+            self._norm = 1.0 / np.sqrt(self.shape[0] * self.shape[1])
+
+    def walsh(self, x):
+        """Orthonormal 2-D Walsh transform (Paley order) of an image."""
+        return self._wr @ x @ self._wc.T * self._norm
+
+    def walsh_t(self, v):
+        """Its transpose (and inverse)."""
+        return self._wr.T @ v @ self._wc * self._norm
 
     # ---------------- definition forms ----------------
     def H(self, x):
@@ -64,6 +106,8 @@ class Operator:
                 for b in range(kw):
                     out += self.taps[a, b] * np.roll(x, (a - kh // 2, b - kw // 2), axis=(0, 1))
             return out
+        if self.kind == HADAMARD:
+            return np.where(self.mask, self.walsh(x), 0.0)
         X = np.fft.fft2(x, norm="ortho")
         return np.where(self.mask, X, 0.0)
 
@@ -79,11 +123,14 @@ class Operator:
                     out += self.taps[a, b] * np.roll(v, (-(a - kh // 2), -(b - kw // 2)), axis=(0, 1))
             return out
         V = np.where(self.mask, v, 0.0)
+        if self.kind == HADAMARD:
+            return self.walsh_t(np.real(V))
         return np.real(np.fft.ifft2(V, norm="ortho"))
 
     # ---------------- spectral forms ----------------
     def spectrum(self):
-        """Eigenvalues |H(w)|^2 of the circulant H^T H, shape (h, w)."""
+        """Eigenvalues |H(w)|^2 of the circulant H^T H, shape (h, w); for the
+        Walsh-Hadamard operator the eigenvalues in the Walsh basis (the mask)."""
         if self._spec is not None:
             return self._spec
         h, w = self.shape
@@ -96,6 +143,8 @@ class Operator:
                 for b in range(kw):
                     pad[(a - kh // 2) % h, (b - kw // 2) % w] += self.taps[a, b]
             spec = np.abs(np.fft.fft2(pad)) ** 2
+        elif self.kind == HADAMARD:
+            spec = self.mask.astype(np.float64)
         else:
             m = self.mask.astype(np.float64)
             # P(-w): index (-r mod h, -c mod w)
@@ -108,7 +157,16 @@ class Operator:
         """H^T H x through the spectrum (FFT); tests pin it to Ht(H(x))."""
         if self.kind == IDENTITY:
             return x.copy()
+        if self.kind == HADAMARD:
+            return self.Ht(self.H(x))
         return np.real(np.fft.ifft2(np.fft.fft2(x) * self.spectrum()))
+
+    def diag_basis_apply(self, v, d):
+        """U^T diag(d) U v for the unitary U that diagonalises H^T H (the DFT,
+        or the Walsh transform): the preconditioner of the mean solve."""
+        if self.kind == HADAMARD:
+            return self.walsh_t(d * self.walsh(v))
+        return np.real(np.fft.ifft2(np.fft.fft2(v) * d))
 
     def Hty(self, y):
         return self.Ht(y)
@@ -130,8 +188,10 @@ def solve_tilted_mean(op: Operator, xi, tau_c, b, x0=None, rtol=1e-12, maxiter=5
     """E = (H^T H / xi + diag(tau_c))^{-1} b by preconditioned conjugate
     gradients (the paper's suggestion for the mean of Eq. (tilted_P_1)).
 
-    The preconditioner is the circulant (H^T H / xi + mean(tau_c) I)^{-1}; it
-    changes the iteration count, not the solution.  Returns (E, iterations)."""
+    The preconditioner is (H^T H / xi + mean(tau_c) I)^{-1}, diagonal in the
+    basis that diagonalises H^T H (circulant for the blur and the DFT, Walsh
+    for the Hadamard operator); it changes the iteration count, not the
+    solution.  Returns (E, iterations)."""
     h, w = op.shape
     if op.kind == IDENTITY:
         return b / (1.0 / xi + tau_c), 0
@@ -143,7 +203,7 @@ def solve_tilted_mean(op: Operator, xi, tau_c, b, x0=None, rtol=1e-12, maxiter=5
         return op.HtH(v) / xi + tau_c * v
 
     def M(v):
-        return np.real(np.fft.ifft2(np.fft.fft2(v) * pre))
+        return op.diag_basis_apply(v, pre)
 
     x = np.zeros((h, w)) if x0 is None else np.array(x0, dtype=np.float64)
     r = b - A(x)

@@ -32,6 +32,7 @@ import numpy as np
 OP_IDENTITY = "identity"
 OP_BLUR = "blur"
 OP_DFT = "dft"
+OP_HADAMARD = "hadamard"
 
 
 def rng_for(config: int, instance: int = 0) -> np.random.Generator:
@@ -151,6 +152,35 @@ def dft_mask(h: int, w: int, frac: float, rng: np.random.Generator) -> np.ndarra
     return m.reshape(h, w)
 
 
+def _bitrev(n: int) -> np.ndarray:
+    m = int(round(math.log2(n)))
+    j = np.arange(n)
+    out = np.zeros(n, dtype=np.int64)
+    for b in range(m):
+        out |= ((j >> b) & 1) << (m - 1 - b)
+    return out
+
+
+def walsh_paley_2d(x: np.ndarray) -> np.ndarray:
+    """Orthonormal 2-D Walsh transform in Paley order (observation model of the
+    Hadamard CS workload): a fast Walsh-Hadamard butterfly along each axis in
+    natural (Sylvester) order, whose row k is Paley row bitreverse(k)."""
+    h, w = x.shape
+    v = np.asarray(x, dtype=np.float64).copy()
+    for axis, n in ((0, h), (1, w)):
+        v = np.moveaxis(v, axis, 0)
+        s = 1
+        while s < n:
+            v = v.reshape(n // (2 * s), 2, s, -1)
+            a, b = v[:, 0].copy(), v[:, 1].copy()
+            v[:, 0], v[:, 1] = a + b, a - b
+            v = v.reshape(n, -1)
+            s *= 2
+        v = v.reshape((n,) + tuple(np.delete(np.array(x.shape), axis)))
+        v = np.moveaxis(v, 0, axis)
+    return v[np.ix_(_bitrev(h), _bitrev(w))] / math.sqrt(h * w)
+
+
 @dataclass
 class Problem:
     """One restoration instance: what a caller hands to a solver."""
@@ -199,6 +229,19 @@ def make_cs(h, w, n_shapes, sigma, frac, rng, mode="paint", lam0=1.0, damping=0.
                                         + 1j * rng.standard_normal((h, w)))
     Y = np.where(mask.astype(bool), X + noise, 0.0 + 0.0j)
     return Problem(name, x, Y, OP_DFT, sigma * sigma / 2.0, lam0, damping, sweeps, em,
+                   mask=mask, meta={"sigma": sigma, "frac": frac})
+
+
+def make_hadamard_cs(h, w, n_shapes, sigma, frac, rng, mode="paint", lam0=1.0, damping=0.5,
+                     sweeps=300, em=True, name="hcs"):
+    """Hadamard CS: a uniform random subset of round(frac h w) Paley-ordered
+    Walsh coefficients (the constant function (0, 0) always kept), real noise
+    of standard deviation sigma on each."""
+    x = piecewise_image(h, w, n_shapes, rng, mode=mode)
+    mask = dft_mask(h, w, frac, rng)
+    Y = walsh_paley_2d(x) + sigma * rng.standard_normal((h, w))
+    Y = np.where(mask.astype(bool), Y, 0.0)
+    return Problem(name, x, Y, OP_HADAMARD, sigma * sigma, lam0, damping, sweeps, em,
                    mask=mask, meta={"sigma": sigma, "frac": frac})
 
 

@@ -257,3 +257,22 @@ def test_em_fixed_point_identity():
     assert info["converged"]
     a_bar = sum(ep.tv_block_update(pb, st, k) for k in (1, 2, 3, 4))
     assert abs(pb.N / a_bar / st.lam - 1) < 1e-9
+
+
+def test_hadamard_full_mask_equals_denoising_of_back_projection():
+    """With every Walsh coefficient kept, H is orthonormal (H^T H = I) and the
+    EP problem is denoising of H^T y with the same noise: the Hadamard path of
+    the oracle (CG solve, spectral variance) must give the identity path's
+    result."""
+    p = syn.make_hadamard_cs(16, 16, 3, 0.05, 1.0, np.random.default_rng(18), lam0=8.0,
+                             sweeps=12, em=False)
+    assert p.mask.all()
+    pb = ep.problem_from_synthetic(p)
+    mu_h, v_h, _, _ = ep.solve(pb, 12, False)
+    q = syn.make_denoise(16, 16, 3, 0.05, np.random.default_rng(0), lam0=8.0, sweeps=12, em=False)
+    q.y = ops.Operator(ops.HADAMARD, p.shape, mask=p.mask).Ht(p.y)
+    q.xi = p.xi
+    pd = ep.problem_from_synthetic(q)
+    mu_d, v_d, _, _ = ep.solve(pd, 12, False)
+    assert np.allclose(mu_h, mu_d, rtol=0, atol=1e-9)
+    assert np.allclose(v_h, v_d, rtol=1e-8, atol=0)
