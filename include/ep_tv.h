@@ -58,7 +58,9 @@ enum {
 enum {
   EP_TV_OP_IDENTITY = 0,       /* denoising: H = I */
   EP_TV_OP_BLUR_PERIODIC = 1,  /* deconvolution: periodic 2-D convolution with given taps */
-  EP_TV_OP_DFT_MASK = 2        /* CS: subset of orthonormal 2-D DFT coefficients */
+  EP_TV_OP_DFT_MASK = 2,       /* CS: subset of orthonormal 2-D DFT coefficients */
+  EP_TV_OP_HADAMARD_MASK = 3   /* CS: subset of orthonormal 2-D Walsh-Hadamard coefficients,
+                                  Paley order along each axis (Sec. II-A case (iii), Sec. V) */
 };
 
 /* Image boundary for the pixel-pair graph.  FREE: pairs inside the image only;
@@ -82,9 +84,11 @@ typedef struct {
   const float* blur_taps;      /* host, blur_h * blur_w row-major, odd sizes <= 17, centred:
                                   (Hx)(r,c) = sum_ab taps[a][b] x(r-a+blur_h/2, c-b+blur_w/2) */
   int32_t blur_h, blur_w;
-  const uint8_t* dft_mask;     /* host, height*width, nonzero = coefficient observed; the DC
-                                  coefficient is always treated as observed */
-  double noise_var;            /* xi > 0, variance of each real observation (CS: of Re and Im) */
+  const uint8_t* dft_mask;     /* host, height*width, nonzero = coefficient observed (DFT_MASK:
+                                  frequency (r, c); HADAMARD_MASK: Paley-ordered Walsh functions
+                                  (r, c) of the rows and columns); the constant coefficient
+                                  (0, 0) is always treated as observed */
+  double noise_var;            /* xi > 0, variance of each real observation (DFT: of Re and Im) */
   double lambda0;              /* > 0: lambda (fixed, or the EM starting value) */
   double damping;              /* in (0, 1]: weight of the new site value in the damped update */
   double cg_tol;               /* CG relative residual ||r||/||b|| for the likelihood site; 0 = 1e-8 */
@@ -154,6 +158,9 @@ int ep_tv_create(const ep_tv_problem* p, int32_t n_problems, void* d_workspace,
  * d_y: host array of n_problems device pointers.  IDENTITY/BLUR: height*width
  *   floats.  DFT_MASK: height*width complex values as interleaved (re, im)
  *   float pairs, the orthonormal 2-D DFT coefficients of x plus noise; entries
+ *   off the mask are ignored.  HADAMARD_MASK: height*width floats, the
+ *   orthonormal 2-D Walsh coefficients of x plus noise, Paley order (entry
+ *   (u, v) belongs to the u-th row and v-th column Walsh functions); entries
  *   off the mask are ignored.  The data is copied; the caller may reuse y. */
 int ep_tv_set_observation(ep_tv_ctx* ctx, const float* const* d_y);
 

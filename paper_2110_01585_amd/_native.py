@@ -23,6 +23,7 @@ EP_TV_E_STATE = -5
 OP_IDENTITY = 0
 OP_BLUR_PERIODIC = 1
 OP_DFT_MASK = 2
+OP_HADAMARD_MASK = 3
 BND_FREE = 0
 BND_PERIODIC = 1
 PRECOND_AUTO = 0

@@ -43,7 +43,8 @@ class ProblemSpec:
     prior_s2sq: float = 1.0
 
 
-_OPS = {"identity": N.OP_IDENTITY, "blur": N.OP_BLUR_PERIODIC, "dft": N.OP_DFT_MASK}
+_OPS = {"identity": N.OP_IDENTITY, "blur": N.OP_BLUR_PERIODIC, "dft": N.OP_DFT_MASK,
+        "hadamard": N.OP_HADAMARD_MASK}
 _BNDS = {"free": N.BND_FREE, "periodic": N.BND_PERIODIC}
 
 

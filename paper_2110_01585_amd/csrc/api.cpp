@@ -98,7 +98,7 @@ void assign_tiles(std::vector<InstHost>& ih, int rows) {
 const char* validate(const ep_tv_problem& p) {
   if (p.height < 1 || p.width < 1 || p.height > 16384 || p.width > 16384)
     return "height and width must be in [1, 16384]";
-  if (p.op < EP_TV_OP_IDENTITY || p.op > EP_TV_OP_DFT_MASK) return "unknown operator";
+  if (p.op < EP_TV_OP_IDENTITY || p.op > EP_TV_OP_HADAMARD_MASK) return "unknown operator";
   if (p.boundary != EP_TV_BND_FREE && p.boundary != EP_TV_BND_PERIODIC) return "unknown boundary";
   if (p.boundary == EP_TV_BND_PERIODIC && (p.height % 2 || p.width % 2 || p.height < 2 || p.width < 2))
     return "periodic boundary needs even height and width";
@@ -131,6 +131,11 @@ const char* validate(const ep_tv_problem& p) {
     if (!p.dft_mask) return "DFT operator needs dft_mask";
     if (!fft_size_ok(p.height) || !fft_size_ok(p.width))
       return "DFT operator needs power-of-two sizes in [4, 4096]";
+  }
+  if (p.op == EP_TV_OP_HADAMARD_MASK) {
+    if (!p.dft_mask) return "Walsh-Hadamard operator needs dft_mask";
+    if (!fft_size_ok(p.height) || !fft_size_ok(p.width))
+      return "Walsh-Hadamard operator needs power-of-two sizes in [4, 4096]";
   }
   return nullptr;
 }
@@ -402,7 +407,7 @@ int ep_tv_create(const ep_tv_problem* p, int32_t n, void* d_ws, size_t ws_bytes,
       c->ih[i].taps.assign(p[i].blur_taps, p[i].blur_taps + (size_t)p[i].blur_h * p[i].blur_w);
       c->ih[i].p.blur_taps = nullptr;
     }
-    if (p[i].op == EP_TV_OP_DFT_MASK) {
+    if (p[i].op == EP_TV_OP_DFT_MASK || p[i].op == EP_TV_OP_HADAMARD_MASK) {
       c->ih[i].mask.assign(p[i].dft_mask, p[i].dft_mask + (size_t)p[i].height * p[i].width);
       c->ih[i].mask[0] = 1;   // DC always observed
       c->ih[i].p.dft_mask = nullptr;
@@ -536,7 +541,7 @@ int ep_tv_set_observation(ep_tv_ctx* c, const float* const* d_y) {
   for (int i = 0; i < c->n; ++i) {
     if (!d_y[i]) return fail(c, EP_TV_E_ARG, "null observation pointer");
     const InstHost& h = c->ih[i];
-    if (h.p.op == EP_TV_OP_DFT_MASK) continue;
+    if (h.p.op == EP_TV_OP_DFT_MASK || h.p.op == EP_TV_OP_HADAMARD_MASK) continue;
     HIPCHK(c, hipMemcpy2DAsync(c->ypix + h.off, sizeof(float) * h.pitch, d_y[i],
                                sizeof(float) * h.p.width, sizeof(float) * h.p.width, h.p.height,
                                hipMemcpyDeviceToDevice, c->stream));

@@ -791,7 +791,7 @@ hipError_t dft_setup(LikCtx& lc, const LikInstInfo* li, int n, size_t fft_bytes,
   size_t used = 0;
   for (size_t k = 0; k < lc.hinst.size(); ++k) {
     const LikInst& L = lc.hinst[k];
-    if (L.op != OP_DFT && L.precond != PRECOND_CIRCULANT) continue;
+    if (L.op == OP_HAD || (L.op != OP_DFT && L.precond != PRECOND_CIRCULANT)) continue;
     const LikInstInfo& I = li[L.inst];
     DftPlan d;
     d.li = (int)k;
@@ -987,6 +987,15 @@ hipError_t rfft_precondition(LikCtx& lc, int update, hipStream_t s) {
 }
 hipError_t rfft_product(LikCtx& lc, hipStream_t s) { return rfft_cg(lc, RFM_PRODUCT, 0, s); }
 
-void dft_destroy(LikCtx& lc) { lc.dft.clear(); }
+void dft_destroy(LikCtx& lc) {
+  lc.dft.clear();
+  lc.wht.clear();
+}
+
+hipError_t launch_dot_tiles(LikCtx& lc, const LikInst& L, const float* pv, hipStream_t s) {
+  hipLaunchKernelGGL(k_dot_tiles, dim3(L.ntiles), dim3(256), 0, s, lc.d_inst, lc.d_tiles, L.tile0,
+                     L.ntiles, pv, lc.planes[LP_Q], lc.part0, lc.part1, lc.d_st);
+  return hipGetLastError();
+}
 
 }  // namespace eptv

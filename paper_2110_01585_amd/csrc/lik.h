@@ -87,6 +87,7 @@ struct LikLayout {
   size_t inst = 0, tiles = 0, part0 = 0, part1 = 0, taps = 0, fft = 0;
   int nlik = 0, ntiles = 0, ntaps = 0;
   size_t fft_bytes = 0;
+  size_t wht = 0, wht_bytes = 0;
 };
 
 // Number of likelihood tiles and taps floats for the layout.
@@ -98,7 +99,7 @@ inline void lik_counts(const LikInstInfo* li, int n, int& nlik, int& ntiles, int
     ++nlik;
     ntiles += ((li[i].W + kLikTW - 1) / kLikTW) * ((li[i].H + kLikTH - 1) / kLikTH);
     if (li[i].op == OP_BLUR) ntaps += li[i].th * li[i].tw + 2 * li[i].th + 2 * li[i].tw;
-    if (li[i].op == OP_DFT) fft_elems = std::max<long long>(fft_elems, (long long)li[i].H * li[i].W);
+    if (li[i].op == OP_DFT || li[i].op == OP_HAD) fft_elems = std::max<long long>(fft_elems, (long long)li[i].H * li[i].W);
   }
 }
 
@@ -125,6 +126,14 @@ void lik_layout(const LikInstInfo* li, int n, long long plane, Take&& take, LikL
   }
   (void)fft_elems;
   L.fft = take(std::max<size_t>(L.fft_bytes, 256));
+  // Walsh-Hadamard instances: a work vector and the reordered mask, N floats each
+  L.wht_bytes = 0;
+  for (int i = 0; i < n; ++i) {
+    if (li[i].op != OP_HAD) continue;
+    const size_t N = (size_t)li[i].H * li[i].W;
+    L.wht_bytes += 2 * ((N * sizeof(float) + 255) / 256 * 256);
+  }
+  L.wht = take(std::max<size_t>(L.wht_bytes, 256));
 }
 
 // FFT work buffers of one instance that uses the FFT (masked DFT operator,
@@ -140,9 +149,19 @@ struct DftPlan {
   uint8_t* mask = nullptr;   // H x W
 };
 
+// Walsh-Hadamard work buffers of one instance with that operator.
+struct WhtPlan {
+  int li = 0;                // index into LikCtx::hinst
+  int logH = 0, logW = 0, logN = 0, lb = 0;   // lb: bits of the LDS group
+  float* work = nullptr;     // N floats, natural order
+  float* eig = nullptr;      // N floats: the mask in natural order
+};
+
 struct LikCtx {
   int nlik = 0, ntiles = 0;
   std::vector<DftPlan> dft;
+  std::vector<WhtPlan> wht;
+  float* whtbuf = nullptr;
   std::vector<LikInst> hinst;
   std::vector<int> inst_of;          // lik index -> instance index
   LikInst* d_inst = nullptr;

@@ -25,6 +25,7 @@
 
 #include "fft.h"
 #include "lik.h"
+#include "wht.h"
 
 namespace eptv {
 
@@ -753,6 +754,7 @@ hipError_t lik_create(LikCtx& lc, const LikInstInfo* li, int n, char* ws, const 
   lc.part1 = reinterpret_cast<double*>(ws + L.part1);
   lc.taps = reinterpret_cast<float*>(ws + L.taps);
   lc.fft = reinterpret_cast<float2*>(ws + L.fft);
+  lc.whtbuf = reinterpret_cast<float*>(ws + L.wht);
   std::vector<float> taps;
   std::vector<int4> tiles;
   for (int i = 0; i < n; ++i) {
@@ -771,7 +773,7 @@ hipError_t lik_create(LikCtx& lc, const LikInstInfo* li, int n, char* ws, const 
     d.cg_reduce2 = I.cg_reduce * I.cg_reduce;
     d.cg_max_iters = I.cg_max_iters;
     d.precond = lik_precond(I.op, I.H, I.W, I.precond_req);
-    d.npart = d.precond == PRECOND_CIRCULANT ? rfft_partials(I.H, I.W) : d.ntiles;
+    d.npart = (d.precond == PRECOND_CIRCULANT && I.op != OP_HAD) ? rfft_partials(I.H, I.W) : d.ntiles;
     if (d.npart > d.ntiles) return hipErrorInvalidValue;   // partial slots are per tile
     lc.max_iters = std::max(lc.max_iters, I.cg_max_iters);
     const int li_idx = (int)lc.hinst.size();
@@ -818,9 +820,11 @@ hipError_t lik_create(LikCtx& lc, const LikInstInfo* li, int n, char* ws, const 
           if (b2 + dd >= 0 && b2 + dd < kw) acc += v[b2] * v[b2 + dd];
         taps.push_back((float)(sep ? acc : 0.0));
       }
-    } else if (I.op == OP_DFT) {
+    } else if (I.op == OP_DFT || I.op == OP_HAD) {
       d.Rr = 0; d.Rc = 0; d.sep = 0; d.kh = 1; d.kw = 1;
-      // H^T H of the masked orthonormal DFT has unit diagonal times the kept fraction
+      // H^T H of a masked orthonormal transform whose basis vectors have
+      // entries of modulus 1 / sqrt(N) (Fourier, Walsh): its diagonal is the
+      // kept fraction
       int kept = 0;
       for (long long q = 0; q < (long long)I.H * I.W; ++q) kept += I.mask[q] ? 1 : 0;
       d.diagA = (float)((double)kept / ((double)I.H * I.W) / I.xi);
@@ -830,7 +834,7 @@ hipError_t lik_create(LikCtx& lc, const LikInstInfo* li, int n, char* ws, const 
   }
   lc.fast = !lc.hinst.empty();
   for (const LikInst& d : lc.hinst) {
-    lc.fast = lc.fast && d.precond == PRECOND_CIRCULANT && d.npart <= d.ntiles;
+    lc.fast = lc.fast && d.precond == PRECOND_CIRCULANT && d.op != OP_HAD && d.npart <= d.ntiles;
   }
   // partial counts per finalisation stage: r.z / r.r (and p.q of masked-DFT
   // instances) come from the real-transform passes in the fast CG, everything
@@ -862,6 +866,7 @@ hipError_t lik_create(LikCtx& lc, const LikInstInfo* li, int n, char* ws, const 
   hipLaunchKernelGGL(k_spectrum_blur, dim3(lc.ntiles), dim3(256), 0, s, A);
   e = hipGetLastError();
   if (e == hipSuccess) e = dft_setup(lc, li, n, L.fft_bytes, s, err);
+  if (e == hipSuccess) e = wht_setup(lc, li, n, L.wht_bytes, s, err);
   if (e != hipSuccess && err.empty()) err = hipGetErrorString(e);
   return e;
 }
@@ -872,7 +877,8 @@ hipError_t lik_set_observation(LikCtx& lc, const float* const* d_y, hipStream_t 
   hipLaunchKernelGGL(k_hty_blur, dim3(lc.ntiles), dim3(256), 0, s, A, lc.ypix);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  return dft_set_observation(lc, d_y, s);
+  if ((e = dft_set_observation(lc, d_y, s)) != hipSuccess) return e;
+  return wht_set_observation(lc, d_y, s);
 }
 
 static hipError_t set_x_invalid(LikCtx& lc, hipStream_t s);
@@ -956,6 +962,10 @@ static hipError_t launch_apply(LikCtx& lc, int mode, hipStream_t s) {
       hipError_t e = dft_apply(lc, mode, s);
       if (e != hipSuccess) return e;
     }
+    if (!lc.wht.empty()) {
+      hipError_t e = wht_apply(lc, mode, s);
+      if (e != hipSuccess) return e;
+    }
     return launch_apply_blur(lc, mode, s);
   });
 }
@@ -982,6 +992,7 @@ hipError_t lik_head(LikCtx& lc, float2* const S[5], hipStream_t s) {
     if ((e = rfft_precondition(lc, 0, s)) != hipSuccess) return e;
   } else {
     if ((e = fft_precondition(lc, s)) != hipSuccess) return e;
+    if ((e = wht_precondition(lc, s)) != hipSuccess) return e;
     hipLaunchKernelGGL(k_precond_dot, g, b, 0, s, make_args(lc));
   }
   return fin(lc, FIN_INIT, s);
@@ -1014,6 +1025,7 @@ hipError_t lik_iterations(LikCtx& lc, int n, hipStream_t s) {
     if ((e = fin(lc, FIN_ALPHA, s)) != hipSuccess) return e;
     hipLaunchKernelGGL(k_cg_update, g, b, 0, s, make_args(lc));
     if ((e = fft_precondition(lc, s)) != hipSuccess) return e;
+    if ((e = wht_precondition(lc, s)) != hipSuccess) return e;
     hipLaunchKernelGGL(k_precond_dot, g, b, 0, s, make_args(lc));
     if ((e = fin(lc, FIN_BETA, s)) != hipSuccess) return e;
     lc.pcur ^= 1;

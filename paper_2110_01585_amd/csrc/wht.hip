@@ -1,0 +1,368 @@
+// Subsampled Paley-ordered 2-D Walsh-Hadamard operator on the device.
+//
+// The orthonormal 2-D Walsh transform of an H x W image in natural (Sylvester)
+// order is the 1-D Walsh-Hadamard transform of length N = H W of its row-major
+// flattening: the Sylvester matrix of order H W is the Kronecker product of
+// those of orders H and W, and with W a power of two the row-major index
+// r W + c splits into the bits of r above those of c.  The Paley order of the
+// observations only relabels coefficients: Paley row k is natural row
+// bitreverse(k) along each axis, which the host applies to the mask and the
+// observation gather applies to y.
+//
+// The transform runs over the bits of the flattened index in groups:
+//   * the low lb = min(log2 N, 12) bits, a contiguous run of up to 4096
+//     elements, in LDS (radix-4 butterflies, one barrier per two bits);
+//   * the remaining bits in groups of at most 4, each thread holding the
+//     2^g elements of one group in registers; consecutive threads take
+//     consecutive low indices, so every load and store is coalesced.
+// H^T H = W^T diag(mask) W: a product is pre-op, forward groups, the mask
+// multiply and the inverse (the same transform) of the last group fused into
+// one pass, the remaining groups again, and the post-op.  Butterflies are
+// unnormalised; the 1 / N of the orthonormal pair is folded into the multiply.
+#include "wht.h"
+
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "fft.h"
+
+namespace eptv {
+
+namespace {
+
+constexpr int kLowBits = 12;      // elements of the LDS group: 4096 floats
+constexpr int kHighBits = 4;      // elements of a register group: at most 16
+constexpr int kThreads = 256;
+
+enum { WSRC_DIRECTION = 0, WSRC_REAL, WSRC_OBS, WSRC_WORK };
+enum { WMUL_NONE = 0, WMUL_MASK, WMUL_PRECOND, WMUL_SCALE };
+enum { WDST_WORK = 0, WDST_Q, WDST_REAL };
+
+struct WhtArgs {
+  int logW, logH, logN, lb;
+  long long off;             // plane offset of pixel (0, 0)
+  int pitch, inst;
+  float inv_xi, scale;
+  // pitched planes
+  const float* z; const float* x; const float* p_in; float* p_out; const float* tauc;
+  const float* real_in; float* real_out; const float* pvec;
+  const InstState* st;
+  int mode0;                 // WSRC_DIRECTION: the vector is x (product for the CG start)
+  const float* obs;          // WSRC_OBS: user coefficients, dense H x W, Paley order
+  const float* eig;          // mask in natural order (0 or 1), compact N
+  float* work;               // compact N
+  int src, mul, dst;
+  int fwd, inv;              // transform before / after the multiply
+  int b;                     // register group: lowest bit
+};
+
+__device__ __forceinline__ long long plane_index(const WhtArgs& a, int n) {
+  const int r = n >> a.logW, c = n & ((1 << a.logW) - 1);
+  return a.off + (long long)r * a.pitch + c;
+}
+
+__device__ __forceinline__ float mul_factor(const WhtArgs& a, int n, float dbar) {
+  if (a.mul == WMUL_MASK) return a.eig[n] * a.scale;
+  if (a.mul == WMUL_PRECOND) return a.scale / (a.eig[n] * a.inv_xi + dbar);
+  return a.scale;   // WMUL_SCALE
+}
+
+__device__ __forceinline__ float load_src(const WhtArgs& a, int n) {
+  if (a.src == WSRC_WORK) return a.work[n];
+  const long long p = plane_index(a, n);
+  if (a.src == WSRC_REAL) return a.real_in[p];
+  if (a.src == WSRC_OBS) {
+    if (a.eig[n] == 0.f) return 0.f;
+    const unsigned r = (unsigned)(n >> a.logW), c = (unsigned)(n & ((1 << a.logW) - 1));
+    const unsigned rp = __brev(r) >> (32 - a.logH), cp = __brev(c) >> (32 - a.logW);
+    return a.obs[(rp << a.logW) + cp];
+  }
+  // WSRC_DIRECTION
+  if (a.mode0) return a.x[p];
+  const InstState& st = a.st[a.inst];
+  const float z = a.z[p];
+  const float v = st.cg_it == 0 ? z : z + (float)st.cg_beta * a.p_in[p];
+  a.p_out[p] = v;
+  return v;
+}
+
+__device__ __forceinline__ void store_dst(const WhtArgs& a, int n, float v) {
+  if (a.dst == WDST_WORK) {
+    a.work[n] = v;
+    return;
+  }
+  const long long p = plane_index(a, n);
+  if (a.dst == WDST_Q) a.real_out[p] = v * a.inv_xi + a.tauc[p] * a.pvec[p];
+  else a.real_out[p] = v;
+}
+
+// In-place unnormalised Walsh-Hadamard transform of X[0, 2^lb) (natural
+// order), lb >= 2.
+__device__ void lds_wht(float* X, int lb) {
+  int s = 0;
+  const int nq = 1 << (lb - 2);
+  for (; s + 2 <= lb; s += 2) {
+    const int S = 1 << s;
+    for (int q = threadIdx.x; q < nq; q += kThreads) {
+      const int i0 = ((q >> s) << (s + 2)) | (q & (S - 1));
+      const float a0 = X[i0], a1 = X[i0 + S], a2 = X[i0 + 2 * S], a3 = X[i0 + 3 * S];
+      const float b0 = a0 + a1, b1 = a0 - a1, b2 = a2 + a3, b3 = a2 - a3;
+      X[i0] = b0 + b2;
+      X[i0 + S] = b1 + b3;
+      X[i0 + 2 * S] = b0 - b2;
+      X[i0 + 3 * S] = b1 - b3;
+    }
+    __syncthreads();
+  }
+  if (s < lb) {   // odd lb: one radix-2 stage
+    const int S = 1 << s;
+    for (int q = threadIdx.x; q < (1 << (lb - 1)); q += kThreads) {
+      const int i0 = ((q >> s) << (s + 1)) | (q & (S - 1));
+      const float a0 = X[i0], a1 = X[i0 + S];
+      X[i0] = a0 + a1;
+      X[i0 + S] = a0 - a1;
+    }
+    __syncthreads();
+  }
+}
+
+// One block per run of 2^lb contiguous flattened indices.
+__global__ __launch_bounds__(kThreads) void k_wht_low(WhtArgs a) {
+  __shared__ float X[1 << kLowBits];
+  const int C = 1 << a.lb;
+  const int n0 = blockIdx.x << a.lb;
+  for (int i = threadIdx.x; i < C; i += kThreads) X[i] = load_src(a, n0 + i);
+  __syncthreads();
+  if (a.fwd) lds_wht(X, a.lb);
+  if (a.mul != WMUL_NONE) {
+    const float dbar = a.mul == WMUL_PRECOND ? (float)a.st[a.inst].dbar : 0.f;
+    for (int i = threadIdx.x; i < C; i += kThreads) X[i] *= mul_factor(a, n0 + i, dbar);
+    __syncthreads();
+  }
+  if (a.inv) lds_wht(X, a.lb);
+  for (int i = threadIdx.x; i < C; i += kThreads) store_dst(a, n0 + i, X[i]);
+}
+
+template <int G>
+__device__ __forceinline__ void reg_wht(float (&v)[1 << G]) {
+  #pragma unroll
+  for (int s = 1; s < (1 << G); s <<= 1) {
+    #pragma unroll
+    for (int i = 0; i < (1 << G); ++i) {
+      if (i & s) continue;
+      const float x = v[i], y = v[i + s];
+      v[i] = x + y;
+      v[i + s] = x - y;
+    }
+  }
+}
+
+// Bits [b, b + G) of the flattened index, in place on the work buffer.
+// N <= 2^24, so element indices fit 32 bits.
+template <int G>
+__global__ __launch_bounds__(kThreads) void k_wht_high(WhtArgs a) {
+  constexpr int M = 1 << G;
+  const int T = 1 << (a.logN - G);
+  const int t = blockIdx.x * kThreads + threadIdx.x;
+  if (t >= T) return;
+  const int n0 = (t & ((1 << a.b) - 1)) | ((t >> a.b) << (a.b + G));
+  const int S = 1 << a.b;
+  float* w = a.work + n0;
+  float v[M];
+  #pragma unroll
+  for (int i = 0; i < M; ++i) v[i] = w[i * S];
+  reg_wht<G>(v);
+  if (a.mul != WMUL_NONE) {
+    const float dbar = a.mul == WMUL_PRECOND ? (float)a.st[a.inst].dbar : 0.f;
+    #pragma unroll
+    for (int i = 0; i < M; ++i) v[i] *= mul_factor(a, n0 + i * S, dbar);
+  }
+  if (a.inv) reg_wht<G>(v);
+  #pragma unroll
+  for (int i = 0; i < M; ++i) w[i * S] = v[i];
+}
+
+// mask in natural order -> spectrum plane (the spectral variance estimator
+// reads the eigenvalues of H^T H from it)
+__global__ void k_wht_spec(const float* __restrict__ eig, float* __restrict__ spec, long long off,
+                           int pitch, int logW, int N) {
+  const int n = blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= N) return;
+  spec[off + (long long)(n >> logW) * pitch + (n & ((1 << logW) - 1))] = eig[n];
+}
+
+int ilog2i(int v) {
+  int l = 0;
+  while ((1 << l) < v) ++l;
+  return l;
+}
+
+hipError_t launch_high(const WhtArgs& a, int g, hipStream_t s) {
+  const int T = 1 << (a.logN - g);
+  const dim3 grid((unsigned)((T + kThreads - 1) / kThreads)), blk(kThreads);
+  switch (g) {
+    case 1: hipLaunchKernelGGL(k_wht_high<1>, grid, blk, 0, s, a); break;
+    case 2: hipLaunchKernelGGL(k_wht_high<2>, grid, blk, 0, s, a); break;
+    case 3: hipLaunchKernelGGL(k_wht_high<3>, grid, blk, 0, s, a); break;
+    case 4: hipLaunchKernelGGL(k_wht_high<4>, grid, blk, 0, s, a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+// src -> W -> multiply -> (W again if two_sided) -> dst, over the bit groups.
+hipError_t run(const WhtPlan& P, WhtArgs a, bool two_sided, hipStream_t s) {
+  a.logW = P.logW; a.logH = P.logH; a.logN = P.logN; a.lb = P.lb;
+  a.eig = P.eig; a.work = P.work;
+  const unsigned nblk = 1u << (P.logN - P.lb);
+  hipError_t e;
+  if (P.logN == P.lb) {   // one LDS pass
+    a.fwd = 1; a.inv = two_sided ? 1 : 0;
+    hipLaunchKernelGGL(k_wht_low, dim3(nblk), dim3(kThreads), 0, s, a);
+    return hipGetLastError();
+  }
+  const int hb = P.logN - P.lb, ng = (hb + kHighBits - 1) / kHighBits;
+  int gb[4], gg[4];
+  for (int k = 0, b = P.lb; k < ng; ++k) {
+    gg[k] = hb / ng + (k < hb % ng ? 1 : 0);
+    gb[k] = b;
+    b += gg[k];
+  }
+  WhtArgs first = a;
+  first.fwd = 1; first.inv = 0; first.mul = WMUL_NONE; first.dst = WDST_WORK;
+  hipLaunchKernelGGL(k_wht_low, dim3(nblk), dim3(kThreads), 0, s, first);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  for (int k = 0; k < ng; ++k) {
+    WhtArgs h = a;
+    h.b = gb[k];
+    const bool last = k == ng - 1;
+    h.mul = last ? a.mul : WMUL_NONE;
+    h.inv = (last && two_sided) ? 1 : 0;
+    if ((e = launch_high(h, gg[k], s)) != hipSuccess) return e;
+  }
+  if (two_sided) {
+    for (int k = ng - 2; k >= 0; --k) {
+      WhtArgs h = a;
+      h.b = gb[k]; h.mul = WMUL_NONE; h.inv = 0;
+      if ((e = launch_high(h, gg[k], s)) != hipSuccess) return e;
+    }
+  }
+  WhtArgs last = a;
+  last.src = WSRC_WORK; last.fwd = two_sided ? 1 : 0; last.inv = 0; last.mul = WMUL_NONE;
+  hipLaunchKernelGGL(k_wht_low, dim3(nblk), dim3(kThreads), 0, s, last);
+  return hipGetLastError();
+}
+
+WhtArgs base(const LikCtx& lc, const LikInst& L) {
+  WhtArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.off = L.off; a.pitch = L.pitch; a.inst = L.inst; a.inv_xi = L.inv_xi;
+  a.st = lc.d_st;
+  a.tauc = lc.planes[LP_TAUC];
+  return a;
+}
+
+}  // namespace
+
+hipError_t wht_setup(LikCtx& lc, const LikInstInfo* li, int n, size_t wht_bytes, hipStream_t s,
+                     std::string& err) {
+  (void)n;
+  lc.wht.clear();
+  char* cur = reinterpret_cast<char*>(lc.whtbuf);
+  size_t used = 0;
+  std::vector<std::vector<float>> host;   // kept until the copies finish
+  for (size_t k = 0; k < lc.hinst.size(); ++k) {
+    const LikInst& L = lc.hinst[k];
+    if (L.op != OP_HAD) continue;
+    const LikInstInfo& I = li[L.inst];
+    WhtPlan P;
+    P.li = (int)k;
+    P.logH = ilog2i(L.H); P.logW = ilog2i(L.W); P.logN = P.logH + P.logW;
+    P.lb = P.logN < kLowBits ? P.logN : kLowBits;
+    const size_t N = (size_t)L.H * L.W;
+    if ((1 << P.logH) != L.H || (1 << P.logW) != L.W || P.logH < 2 || P.logW < 2 ||
+        P.logN > 24) {
+      err = "Walsh-Hadamard operator needs power-of-two sizes in [4, 4096]";
+      return hipErrorInvalidValue;
+    }
+    const size_t bytes = (N * sizeof(float) + 255) / 256 * 256;
+    P.work = reinterpret_cast<float*>(cur + used);
+    P.eig = reinterpret_cast<float*>(cur + used + bytes);
+    used += 2 * bytes;
+    if (used > wht_bytes) {
+      err = "Walsh-Hadamard workspace layout mismatch";
+      return hipErrorInvalidValue;
+    }
+    // mask (Paley order, user layout) -> natural order
+    host.emplace_back(N);
+    std::vector<float>& m = host.back();
+    for (int r = 0; r < L.H; ++r)
+      for (int c = 0; c < L.W; ++c) {
+        int rp = 0, cp = 0;
+        for (int b = 0; b < P.logH; ++b) rp |= ((r >> b) & 1) << (P.logH - 1 - b);
+        for (int b = 0; b < P.logW; ++b) cp |= ((c >> b) & 1) << (P.logW - 1 - b);
+        m[(size_t)r * L.W + c] = I.mask[(size_t)rp * L.W + cp] ? 1.f : 0.f;
+      }
+    hipError_t e = hipMemcpyAsync(P.eig, m.data(), N * sizeof(float), hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_wht_spec, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, P.eig,
+                       lc.planes[LP_SPEC], L.off, L.pitch, P.logW, (int)N);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    lc.wht.push_back(P);
+  }
+  return host.empty() ? hipSuccess : hipStreamSynchronize(s);
+}
+
+hipError_t wht_set_observation(LikCtx& lc, const float* const* d_y, hipStream_t s) {
+  for (const WhtPlan& P : lc.wht) {
+    const LikInst& L = lc.hinst[P.li];
+    // H^T y = W^T (mask y): one transform of the masked, reordered coefficients
+    WhtArgs a = base(lc, L);
+    a.src = WSRC_OBS; a.obs = d_y[L.inst];
+    a.mul = WMUL_SCALE; a.scale = (float)(1.0 / std::sqrt((double)L.H * L.W));
+    a.dst = WDST_REAL; a.real_out = lc.planes[LP_HTY];
+    hipError_t e = run(P, a, false, s);
+    if (e != hipSuccess) return e;
+    // the cold start and the observation range use H^T y as the pixel-space observation
+    e = hipMemcpy2DAsync(lc.ypix + L.off, sizeof(float) * L.pitch, lc.planes[LP_HTY] + L.off,
+                         sizeof(float) * L.pitch, sizeof(float) * L.W, L.H,
+                         hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t wht_apply(LikCtx& lc, int mode, hipStream_t s) {
+  for (const WhtPlan& P : lc.wht) {
+    const LikInst& L = lc.hinst[P.li];
+    float* p_in = lc.planes[lc.pcur ? LP_P1 : LP_P0];
+    float* p_out = lc.planes[lc.pcur ? LP_P0 : LP_P1];
+    WhtArgs a = base(lc, L);
+    a.src = WSRC_DIRECTION; a.mode0 = mode == 0;
+    a.z = lc.planes[LP_Z]; a.x = lc.planes[LP_X]; a.p_in = p_in; a.p_out = p_out;
+    a.mul = WMUL_MASK; a.scale = (float)(1.0 / ((double)L.H * L.W));
+    a.dst = WDST_Q; a.real_out = lc.planes[LP_Q];
+    a.pvec = mode == 0 ? lc.planes[LP_X] : p_out;
+    hipError_t e = run(P, a, true, s);
+    if (e != hipSuccess) return e;
+    if ((e = launch_dot_tiles(lc, L, a.pvec, s)) != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t wht_precondition(LikCtx& lc, hipStream_t s) {
+  for (const WhtPlan& P : lc.wht) {
+    const LikInst& L = lc.hinst[P.li];
+    if (L.precond != PRECOND_CIRCULANT) continue;
+    WhtArgs a = base(lc, L);
+    a.src = WSRC_REAL; a.real_in = lc.planes[LP_R];
+    a.mul = WMUL_PRECOND; a.scale = (float)(1.0 / ((double)L.H * L.W));
+    a.dst = WDST_REAL; a.real_out = lc.planes[LP_Z];
+    hipError_t e = run(P, a, true, s);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+}  // namespace eptv

@@ -49,6 +49,9 @@ def test_workspace_bytes_and_validation():
     # the mixture factors: BG ignores s2^2
     ep_tv_workspace_bytes([ProblemSpec(9, 9, prior=N.PRIOR_BG, prior_omega=0.2, prior_s1sq=0.3, prior_s2sq=0.0)])
     ep_tv_workspace_bytes([ProblemSpec(9, 9, prior=N.PRIOR_MOG2, prior_omega=1.0, prior_s1sq=0.3, prior_s2sq=1e-3)])
+    # the Walsh-Hadamard operator: power-of-two sizes in [4, 4096] with a mask
+    hb = ep_tv_workspace_bytes([ProblemSpec(64, 32, op=N.OP_HADAMARD_MASK, mask=np.ones((64, 32), np.uint8))])
+    assert hb >= 64 * 32 * (5 * 8 + 4 + 2 * 4)
     # the largest accepted sizes (16384 on a side) size without error
     big = ep_tv_workspace_bytes([ProblemSpec(16384, 3), ProblemSpec(2, 16384)])
     assert big >= (16384 * 3 + 2 * 16384) * (5 * 8)
@@ -63,7 +66,11 @@ def test_workspace_bytes_and_validation():
            ProblemSpec(5, 5, prior=N.PRIOR_MOG2, prior_omega=0.0),
            ProblemSpec(5, 5, prior=N.PRIOR_MOG2, prior_omega=1.5),
            ProblemSpec(5, 5, prior=N.PRIOR_MOG2, prior_s2sq=0.0),
-           ProblemSpec(5, 5, prior=N.PRIOR_BG, prior_s1sq=-1.0)]
+           ProblemSpec(5, 5, prior=N.PRIOR_BG, prior_s1sq=-1.0),
+           ProblemSpec(16, 16, op=N.OP_HADAMARD_MASK),
+           ProblemSpec(12, 16, op=N.OP_HADAMARD_MASK, mask=np.ones((12, 16), np.uint8)),
+           ProblemSpec(8192, 4, op=N.OP_HADAMARD_MASK, mask=np.ones((8192, 4), np.uint8)),
+           ProblemSpec(8, 8, op=4)]
     for s in bad:
         with pytest.raises(EPTVError):
             ep_tv_workspace_bytes([s])

@@ -1,0 +1,113 @@
+"""GPU parity of the Hadamard compressive-sensing path (subsampled Paley-ordered
+2-D Walsh-Hadamard operator: the Walsh transform kernels, CG with the
+Walsh-diagonal preconditioner, spectral variance) against the FP64 oracle."""
+import numpy as np
+import pytest
+
+import synthetic as syn
+from oracle import ep as oep
+from oracle import operators as oops
+from tests.gpu_util import MEAN_TOL, VAR_TOL, f32_problem, mean_err, observation_tensor, var_err
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_2110_01585_amd import Context, spec_from_synthetic  # noqa: E402
+from paper_2110_01585_amd import _native as N  # noqa: E402
+
+
+def _run(p, sweeps, em, precond=N.PRECOND_AUTO, graph=False):
+    ctx = Context([spec_from_synthetic(p, cg_precond=precond)])
+    ctx.ep_tv_set_observation([observation_tensor(p, torch)])
+    if graph:
+        ctx.ep_tv_set_option(N.OPT_GRAPH, 1)
+    ctx.ep_tv_run(sweeps, em)
+    mus, vs = ctx.marginals()
+    st = ctx.ep_tv_get_stats()[0]
+    torch.cuda.synchronize()
+    mu, v = mus[0].cpu().numpy().astype(np.float64), vs[0].cpu().numpy().astype(np.float64)
+    ctx.close()
+    return mu, v, st
+
+
+def _check(p, sweeps, em, **kw):
+    print(f"case {p.name} {p.shape} sweeps={sweeps} em={em} {kw}", flush=True)
+    mu, v, st = _run(p, sweeps, em, **kw)
+    pb = oep.problem_from_synthetic(f32_problem(p))
+    mu_o, v_o, ost, info = oep.solve(pb, sweeps, em)
+    e_mu, e_v = mean_err(mu, mu_o), var_err(v, v_o)
+    print(f"  mean err {e_mu:.2e} var err {e_v:.2e} lambda gpu {st['lambda']:.6g} oracle "
+          f"{info['lam']:.6g} cg_last {st['cg_last']} cg_total {st['cg_total']} "
+          f"(oracle last {ost.cg_iters})")
+    assert e_mu <= MEAN_TOL and e_v <= VAR_TOL
+    if em:
+        assert abs(st["lambda"] / info["lam"] - 1) <= 2e-4
+    return st
+
+
+@pytest.mark.parametrize("h,w,sweeps", [(4, 4, 10), (16, 16, 20), (32, 64, 30), (64, 64, 30),
+                                        (64, 128, 30), (128, 128, 40), (4, 256, 20), (256, 8, 20)])
+def test_hadamard_cs_small(h, w, sweeps):
+    """Sizes below, at and above one LDS group (4096 elements), square and thin."""
+    rng = syn.rng_for(90, h * 1000 + w)
+    p = syn.make_hadamard_cs(h, w, max(3, h * w // 2000), 0.01, 0.3, rng, sweeps=sweeps, em=True)
+    _check(p, sweeps, True)
+
+
+def test_hadamard_cs_paper_shape():
+    """The paper's Hadamard CS setting, 128^2 with M / N = 0.3 and noise variance
+    1e-4 (Sec. V), EM from lambda = 1, 100 sweeps, captured launches."""
+    rng = syn.rng_for(91, 0)
+    p = syn.make_hadamard_cs(128, 128, 12, 0.01, 0.3, rng, sweeps=100, em=True)
+    _check(p, 100, True, graph=True)
+
+
+def test_hadamard_cs_jacobi_and_fixed_lambda():
+    rng = syn.rng_for(92, 0)
+    p = syn.make_hadamard_cs(64, 64, 6, 0.02, 0.25, rng, lam0=40.0, sweeps=25, em=False)
+    _check(p, 25, False, precond=N.PRECOND_JACOBI)
+
+
+def test_hadamard_cs_multigroup_256():
+    """256 x 512: the flattened index has 5 bits above the LDS group (two
+    register groups)."""
+    rng = syn.rng_for(93, 0)
+    p = syn.make_hadamard_cs(256, 512, 20, 0.01, 0.3, rng, sweeps=15, em=True)
+    _check(p, 15, True)
+
+
+@pytest.mark.parametrize("h,w", [(1024, 1024), (4096, 4096)])
+def test_hadamard_large_back_projection_and_solve(h, w):
+    """At 1024^2 (two register groups) and 4096^2 (three, the largest size):
+    after two sweeps, the right-hand side of the mean solve is H^T y / xi +
+    eta_c with H^T y from the oracle's Walsh matrices, and the true residual
+    of the CG iterate in (H^T H / xi + diag tau_c) E = b, formed with the
+    oracle's operator, is the residual the device reports, to the bound of
+    FP32 rounding (the solves of the first sweeps stop at the iteration cap)."""
+    rng = syn.rng_for(94, h)
+    p = syn.make_hadamard_cs(h, w, 40, 0.01, 0.3, rng, sweeps=2, em=True)
+    print(f"case hadamard {h}x{w}", flush=True)
+    ctx = Context([spec_from_synthetic(p)])
+    ctx.ep_tv_set_observation([observation_tensor(p, torch)])
+    ctx.ep_tv_run(2, True)
+    st = ctx.ep_tv_get_stats()[0]
+    n_it = st["cg_last"]
+    lik_d = torch.empty(10, h, w, device="cuda")
+    ctx.ep_tv_get_lik_planes(0, lik_d)
+    torch.cuda.synchronize()
+    lik = lik_d.cpu().numpy().astype(np.float64)
+    del lik_d
+    ctx.close()
+    q = f32_problem(p)
+    op = oops.Operator(oops.HADAMARD, p.shape, mask=p.mask)
+    E, tau_c, eta_c, b = lik[0], lik[1], lik[2], lik[3]
+    b_ref = op.Ht(q.y) / q.xi + eta_c
+    e_b = np.max(np.abs(b - b_ref)) / np.max(np.abs(b_ref))
+    res = op.HtH(E) / q.xi + tau_c * E - b
+    rel_res = np.linalg.norm(res) / np.linalg.norm(b)
+    bound = 1e-8 + (2 + n_it) * 2.0 ** -24 * (1.0 / q.xi + np.max(tau_c)) \
+        * np.linalg.norm(E) / np.linalg.norm(b) * np.log2(h * w)
+    print(f"  b err {e_b:.2e} rel residual {rel_res:.2e} device {st['cg_rel_residual']:.2e} "
+          f"(bound {bound:.2e}, {n_it} iterations)")
+    assert e_b <= 1e-5
+    assert abs(rel_res - st["cg_rel_residual"]) <= bound
