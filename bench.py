@@ -14,6 +14,9 @@ Workloads (synthetic, seeded; generators in synthetic.py):
               --launch stream: every kernel launched on the stream)
   denoise128  128^2 denoising, sigma = 0.1, lambda = 10 fixed, damping 0.5
   denoise4096 4096^2 denoising, sigma = 0.1, EM (an HBM-resident probe of the sweep)
+  hcs2048     2048^2 Hadamard compressive sensing: 30 % of the Paley-ordered Walsh
+              coefficients, sigma = 0.01, EM from lambda = 1 (hcs128: the paper's
+              128^2 size)
   batch256    256 instances, square sizes log-uniform in [64, 1024], 50/50 denoising /
               deconvolution, per-instance EM; graph launches, autotuned tile height,
               Jacobi CG (about 40M pixels in one context)
@@ -35,6 +38,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 SWEEP_BYTES_PER_PX = 72        # 5 sites (tau, eta) read + 4 written, float32
 HTH_BYTES_PER_PX = 20          # z, p_in, tau_c read; p_out, q written (float32)
+WHT_BYTES_PER_PX = 24          # the same, plus the mask (float32)
 PMC_FILE = os.path.join(ROOT, "profiles", "pmc_traffic.json")
 
 
@@ -92,6 +96,11 @@ def make_workload(name):
         rng = syn.rng_for(5, 0)
         return syn.make_denoise(4096, 4096, 960, 0.1, rng, mode="paint", lam0=1.0, sweeps=50,
                                 em=True, name="denoise4096"), True
+    if name in ("hcs2048", "hcs128"):
+        size = 2048 if name == "hcs2048" else 128
+        n = max(3, round(150 * size * size / 1024 ** 2))
+        return syn.make_hadamard_cs(size, size, n, 0.01, 0.3, syn.rng_for(6, size), lam0=1.0,
+                                    sweeps=300, em=True, name=name), True
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -107,6 +116,9 @@ def cpu_sample(name, size):
     if name == "denoise4096":
         return syn.make_denoise(size, size, max(3, round(960 * size * size / 4096 ** 2)), 0.1,
                                 syn.rng_for(5, 1), mode="paint", lam0=1.0, sweeps=1, em=True), True
+    if name.startswith("hcs"):
+        return syn.make_hadamard_cs(size, size, max(3, round(150 * size * size / 1024 ** 2)), 0.01,
+                                    0.3, syn.rng_for(6, 1), lam0=1.0, sweeps=1, em=True), True
     return syn.config0(), False
 
 
@@ -214,9 +226,17 @@ def main():
     sweep_avg_s = tm["sweep_ms"] / max(tm["sweep_launches"], 1) / 1e3
     roof_sweep = roofline_entry("k_tv_sweep", SWEEP_BYTES_PER_PX * h * w, sweep_avg_s, args.workload)
     roofline = roof_sweep
+    roof_apply = None
     if p.op == "blur" and tm["apply_launches"] > 0:
         apply_avg_s = tm["apply_ms"] / tm["apply_launches"] / 1e3
         roof_apply = roofline_entry("k_hth_sep", HTH_BYTES_PER_PX * h * w, apply_avg_s, args.workload)
+        if tm["apply_ms"] > tm["sweep_ms"]:
+            roofline = roof_apply
+    if p.op == "hadamard" and tm["apply_launches"] > 0:
+        # the whole product (transform passes, mask, post-op and p.q partials)
+        # against its algorithmic bytes
+        apply_avg_s = tm["apply_ms"] / tm["apply_launches"] / 1e3
+        roof_apply = roofline_entry("wht_product", WHT_BYTES_PER_PX * h * w, apply_avg_s, args.workload)
         if tm["apply_ms"] > tm["sweep_ms"]:
             roofline = roof_apply
 
@@ -230,7 +250,7 @@ def main():
     if not args.no_cpu_baseline:
         print("[bench] timing the oracle on the host", file=sys.stderr, flush=True)
         cpu = cpu_baseline(args.workload, args.cpu_size, args.cpu_sweeps)
-    return emit(args, p, em, h, w, value, dt, roofline, cpu, conv, tm, roof_sweep, tune)
+    return emit(args, p, em, h, w, value, dt, roofline, cpu, conv, tm, roof_sweep, tune, roof_apply)
 
 
 def bench_batch(args, ps, em):
@@ -404,7 +424,7 @@ def inexact_solves(args, em, p, y, dev, torch, net_in, ref):
     return out
 
 
-def emit(args, p, em, h, w, value, dt, roofline, cpu, conv, tm, roof_sweep, tune):
+def emit(args, p, em, h, w, value, dt, roofline, cpu, conv, tm, roof_sweep, tune, roof_apply=None):
     E = edges(h, w)
     line = {
         "metric": "EP factor-updates/s + s to converged 2048^2 deconv, warm-start vs plain, 1 GPU",
@@ -419,7 +439,8 @@ def emit(args, p, em, h, w, value, dt, roofline, cpu, conv, tm, roof_sweep, tune
                           "HIP events on the context's stream over the same sweeps launched on "
                           "the stream right after the timed graph replays (events are not "
                           "recorded inside a replayed graph)"),
-        "roofline": roofline, "roofline_sweep": roof_sweep, "cpu_baseline": cpu, "convergence": conv,
+        "roofline": roofline, "roofline_sweep": roof_sweep, "roofline_apply": roof_apply,
+        "cpu_baseline": cpu, "convergence": conv,
         "timing_ms": {"sweep": tm["sweep_ms"], "likelihood": tm["lik_ms"],
                       "cg_products": tm["apply_ms"], "cg_products_launches": tm["apply_launches"],
                       "cg_preconditioner": tm["precond_ms"],

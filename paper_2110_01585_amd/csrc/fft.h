@@ -29,7 +29,5 @@ hipError_t rfft_precondition(LikCtx& lc, int update, hipStream_t s);
 // p_out by the real transform, with p.q partials at [tile0, tile0 + npart)
 hipError_t rfft_product(LikCtx& lc, hipStream_t s);
 int rfft_partials(int H, int W);
-// per-tile p.q partials of an instance whose product a transform wrote to the q plane
-hipError_t launch_dot_tiles(LikCtx& lc, const LikInst& L, const float* pv, hipStream_t s);
 
 }  // namespace eptv

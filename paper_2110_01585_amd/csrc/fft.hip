@@ -992,10 +992,4 @@ void dft_destroy(LikCtx& lc) {
   lc.wht.clear();
 }
 
-hipError_t launch_dot_tiles(LikCtx& lc, const LikInst& L, const float* pv, hipStream_t s) {
-  hipLaunchKernelGGL(k_dot_tiles, dim3(L.ntiles), dim3(256), 0, s, lc.d_inst, lc.d_tiles, L.tile0,
-                     L.ntiles, pv, lc.planes[LP_Q], lc.part0, lc.part1, lc.d_st);
-  return hipGetLastError();
-}
-
 }  // namespace eptv

@@ -845,6 +845,7 @@ hipError_t lik_create(LikCtx& lc, const LikInstInfo* li, int n, char* ws, const 
     d.fin_count[FIN_SPEC] = d.ntiles;
     d.fin_count[FIN_INIT] = tr;
     d.fin_count[FIN_ALPHA] = (lc.fast && d.op == OP_DFT) ? d.npart : d.ntiles;
+    if (d.op == OP_HAD) d.fin_count[FIN_ALPHA] = wht_partials(d.H, d.W);   // from the last transform pass
     d.fin_count[FIN_BETA] = tr;
   }
   if ((int)taps.size() > L.ntaps || (int)tiles.size() != L.ntiles) {

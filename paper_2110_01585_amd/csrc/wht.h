@@ -12,6 +12,9 @@
 
 namespace eptv {
 
+// p.q partials one product writes (one per LDS block; never more than the
+// instance's likelihood tiles)
+int wht_partials(int H, int W);
 hipError_t wht_setup(LikCtx& lc, const LikInstInfo* li, int n, size_t wht_bytes, hipStream_t s,
                      std::string& err);
 // H^T y into the H^T y plane and the pixel-space observation

@@ -12,7 +12,7 @@
 // The transform runs over the bits of the flattened index in groups:
 //   * the low lb = min(log2 N, 12) bits, a contiguous run of up to 4096
 //     elements, in LDS (radix-4 butterflies, one barrier per two bits);
-//   * the remaining bits in groups of at most 4, each thread holding the
+//   * the remaining bits in groups of at most 5, each thread holding the
 //     2^g elements of one group in registers; consecutive threads take
 //     consecutive low indices, so every load and store is coalesced.
 // H^T H = W^T diag(mask) W: a product is pre-op, forward groups, the mask
@@ -29,10 +29,10 @@
 
 namespace eptv {
 
-namespace {
+namespace wht {
 
 constexpr int kLowBits = 12;      // elements of the LDS group: 4096 floats
-constexpr int kHighBits = 4;      // elements of a register group: at most 16
+constexpr int kHighBits = 5;      // elements of a register group: at most 32
 constexpr int kThreads = 256;
 
 enum { WSRC_DIRECTION = 0, WSRC_REAL, WSRC_OBS, WSRC_WORK };
@@ -55,6 +55,7 @@ struct WhtArgs {
   int src, mul, dst;
   int fwd, inv;              // transform before / after the multiply
   int b;                     // register group: lowest bit
+  double* part;              // WDST_Q: one p.q partial per LDS block
 };
 
 __device__ __forceinline__ long long plane_index(const WhtArgs& a, int n) {
@@ -92,9 +93,7 @@ __device__ __forceinline__ void store_dst(const WhtArgs& a, int n, float v) {
     a.work[n] = v;
     return;
   }
-  const long long p = plane_index(a, n);
-  if (a.dst == WDST_Q) a.real_out[p] = v * a.inv_xi + a.tauc[p] * a.pvec[p];
-  else a.real_out[p] = v;
+  a.real_out[plane_index(a, n)] = v;   // WDST_REAL
 }
 
 // In-place unnormalised Walsh-Hadamard transform of X[0, 2^lb) (natural
@@ -141,7 +140,26 @@ __global__ __launch_bounds__(kThreads) void k_wht_low(WhtArgs a) {
     __syncthreads();
   }
   if (a.inv) lds_wht(X, a.lb);
-  for (int i = threadIdx.x; i < C; i += kThreads) store_dst(a, n0 + i, X[i]);
+  if (a.dst != WDST_Q) {
+    for (int i = threadIdx.x; i < C; i += kThreads) store_dst(a, n0 + i, X[i]);
+    return;
+  }
+  // q = A p with this block's p.q partial (dst is uniform over the block)
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < C; i += kThreads) {
+    const long long p = plane_index(a, n0 + i);
+    const float pv = a.pvec[p];
+    const float qv = X[i] * a.inv_xi + a.tauc[p] * pv;
+    a.real_out[p] = qv;
+    acc += (double)pv * (double)qv;
+  }
+  #pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) acc += __shfl_xor(acc, o);
+  __shared__ double wsum[kThreads / 64];
+  if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0)
+    a.part[blockIdx.x] = a.st[a.inst].cg_done ? 0.0 : (wsum[0] + wsum[1]) + (wsum[2] + wsum[3]);
 }
 
 template <int G>
@@ -206,6 +224,7 @@ hipError_t launch_high(const WhtArgs& a, int g, hipStream_t s) {
     case 2: hipLaunchKernelGGL(k_wht_high<2>, grid, blk, 0, s, a); break;
     case 3: hipLaunchKernelGGL(k_wht_high<3>, grid, blk, 0, s, a); break;
     case 4: hipLaunchKernelGGL(k_wht_high<4>, grid, blk, 0, s, a); break;
+    case 5: hipLaunchKernelGGL(k_wht_high<5>, grid, blk, 0, s, a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -263,7 +282,14 @@ WhtArgs base(const LikCtx& lc, const LikInst& L) {
   return a;
 }
 
-}  // namespace
+}  // namespace wht
+
+using namespace wht;
+
+int wht_partials(int H, int W) {
+  const int logN = ilog2i(H) + ilog2i(W);
+  return 1 << (logN - (logN < kLowBits ? logN : kLowBits));
+}
 
 hipError_t wht_setup(LikCtx& lc, const LikInstInfo* li, int n, size_t wht_bytes, hipStream_t s,
                      std::string& err) {
@@ -344,9 +370,9 @@ hipError_t wht_apply(LikCtx& lc, int mode, hipStream_t s) {
     a.mul = WMUL_MASK; a.scale = (float)(1.0 / ((double)L.H * L.W));
     a.dst = WDST_Q; a.real_out = lc.planes[LP_Q];
     a.pvec = mode == 0 ? lc.planes[LP_X] : p_out;
+    a.part = lc.part0 + L.tile0;
     hipError_t e = run(P, a, true, s);
     if (e != hipSuccess) return e;
-    if ((e = launch_dot_tiles(lc, L, a.pvec, s)) != hipSuccess) return e;
   }
   return hipSuccess;
 }
