@@ -111,3 +111,41 @@ def test_hadamard_large_back_projection_and_solve(h, w):
           f"(bound {bound:.2e}, {n_it} iterations)")
     assert e_b <= 1e-5
     assert abs(rel_res - st["cg_rel_residual"]) <= bound
+
+
+def test_hadamard_in_mixed_batch_graph_equals_direct():
+    """Hadamard instances next to blur, DFT and identity instances in one
+    context (every solve then takes the Jacobi/transform CG with per-instance
+    partials): each instance matches its own oracle run, and graph launches give
+    the same bits as direct launches (iterations after a solve has converged
+    leave it untouched)."""
+    ps = [syn.make_hadamard_cs(64, 32, 5, 0.01, 0.3, syn.rng_for(95, 0), sweeps=20, em=True),
+          syn.make_deconv(40, 56, 5, 0.02, 1.0, syn.rng_for(95, 1), lam0=1.0, sweeps=20, em=True),
+          syn.make_cs(32, 64, 6, 0.01, 0.3, syn.rng_for(95, 2), sweeps=20, em=True),
+          syn.make_hadamard_cs(128, 128, 8, 0.01, 0.3, syn.rng_for(95, 3), sweeps=20, em=True),
+          syn.make_denoise(37, 91, 5, 0.05, syn.rng_for(95, 4), mode="paint", lam0=1.0, sweeps=20,
+                           em=True)]
+    res = []
+    for graph in (False, True):
+        print(f"case mixed batch graph={graph}", flush=True)
+        ctx = Context([spec_from_synthetic(p) for p in ps])
+        ctx.ep_tv_set_option(N.OPT_GRAPH, 1 if graph else 0)
+        ctx.ep_tv_set_observation([observation_tensor(p, torch) for p in ps])
+        ctx.ep_tv_run(20, True)
+        mus, vs = ctx.marginals()
+        st = ctx.ep_tv_get_stats()
+        torch.cuda.synchronize()
+        res.append(([m.cpu().numpy().astype(np.float64) for m in mus],
+                    [v.cpu().numpy().astype(np.float64) for v in vs], st))
+        ctx.close()
+    (ma, va, sa), (mb, vb, sb) = res
+    for i, p in enumerate(ps):
+        assert np.array_equal(ma[i], mb[i]) and np.array_equal(va[i], vb[i]), p.name
+        assert sa[i]["cg_total"] == sb[i]["cg_total"], p.name
+        pb = oep.problem_from_synthetic(f32_problem(p))
+        mu_o, v_o, _, info = oep.solve(pb, 20, True)
+        e_mu, e_v = mean_err(ma[i], mu_o), var_err(va[i], v_o)
+        print(f"  {p.name} {p.shape}: mean err {e_mu:.2e} var err {e_v:.2e} lambda "
+              f"{sa[i]['lambda']:.6g} oracle {info['lam']:.6g}")
+        assert e_mu <= MEAN_TOL and e_v <= VAR_TOL
+        assert abs(sa[i]["lambda"] / info["lam"] - 1) <= 2e-4
