@@ -8,10 +8,12 @@ generators in ``synthetic.py``, which contain no EP arithmetic).
 
 Modules
   tilted     -- moments of the 1-D tilted distributions of the gradient u
-                (Laplace x Gaussian for l1-TV, Gaussian x Gaussian for the
-                l2 check prior), Sec. III-C, Eq. (marginal_tilted_un).
-  operators  -- H, H^T, H^T H for identity / periodic blur / masked DFT,
-                the blur spectrum, and dense matrices for tiny problems.
+                (Laplace x Gaussian for l1-TV, Gaussian-mixture x Gaussian for
+                MoG2-TV and BG-TV, Gaussian x Gaussian for the l2 check
+                prior), Sec. III-C, Eq. (marginal_tilted_un).
+  operators  -- H, H^T, H^T H for identity / periodic blur / masked DFT /
+                subsampled Paley-ordered Walsh-Hadamard, the spectra, and
+                dense matrices for tiny problems.
   ep         -- colour classes (Fig. 1, Eq. (prior1)), site state, the
                 likelihood-site update (Eqs. (tilted_P_1), (update_q0_x)),
                 the TV-site update (Eq. (update_qk_x) with the Gehre-Jin
