@@ -25,8 +25,6 @@
 #include <cstring>
 #include <vector>
 
-#include "fft.h"
-
 namespace eptv {
 
 namespace wht {
