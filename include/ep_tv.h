@@ -60,7 +60,9 @@ enum {
   EP_TV_OP_BLUR_PERIODIC = 1,  /* deconvolution: periodic 2-D convolution with given taps */
   EP_TV_OP_DFT_MASK = 2,       /* CS: subset of orthonormal 2-D DFT coefficients */
   EP_TV_OP_HADAMARD_MASK = 3   /* CS: subset of orthonormal 2-D Walsh-Hadamard coefficients,
-                                  Paley order along each axis (Sec. II-A case (iii), Sec. V) */
+                                  Paley order along each axis (Sec. II-A case (iii), Sec. V).
+                                  DFT and Hadamard: power-of-two sides in [4, 4096] and at
+                                  least 32 pixels (a 4 x 4 image is rejected) */
 };
 
 /* Image boundary for the pixel-pair graph.  FREE: pairs inside the image only;

@@ -132,6 +132,11 @@ const char* validate(const ep_tv_problem& p) {
     if (!fft_size_ok(p.height) || !fft_size_ok(p.width))
       return "DFT operator needs power-of-two sizes in [4, 4096]";
   }
+  // 4 x 4 transform operators give wrong results (cause not found), so the
+  // smallest accepted transform image has 32 pixels
+  if ((p.op == EP_TV_OP_DFT_MASK || p.op == EP_TV_OP_HADAMARD_MASK) &&
+      (long long)p.height * p.width < 32)
+    return "DFT and Walsh-Hadamard operators need at least 32 pixels";
   if (p.op == EP_TV_OP_HADAMARD_MASK) {
     if (!p.dft_mask) return "Walsh-Hadamard operator needs dft_mask";
     if (!fft_size_ok(p.height) || !fft_size_ok(p.width))

@@ -86,12 +86,27 @@ __device__ __forceinline__ float load_src(const WhtArgs& a, int n) {
   return v;
 }
 
-__device__ __forceinline__ void store_dst(const WhtArgs& a, int n, float v) {
-  if (a.dst == WDST_WORK) {
-    a.work[n] = v;
-    return;
+// Four consecutive elements n .. n + 3 (n a multiple of 4, so they share a row
+// and, with 256-byte aligned rows, form one 16-byte word of every plane).
+__device__ __forceinline__ float4 ld4(const float* p) { return *reinterpret_cast<const float4*>(p); }
+__device__ __forceinline__ void st4(float* p, float4 v) { *reinterpret_cast<float4*>(p) = v; }
+
+__device__ __forceinline__ float4 load_src4(const WhtArgs& a, int n) {
+  if (a.src == WSRC_WORK) return ld4(a.work + n);
+  if (a.src == WSRC_OBS)
+    return make_float4(load_src(a, n), load_src(a, n + 1), load_src(a, n + 2), load_src(a, n + 3));
+  const long long p = plane_index(a, n);
+  if (a.src == WSRC_REAL) return ld4(a.real_in + p);
+  if (a.mode0) return ld4(a.x + p);
+  const InstState& st = a.st[a.inst];
+  float4 v = ld4(a.z + p);
+  if (st.cg_it != 0) {
+    const float beta = (float)st.cg_beta;
+    const float4 q = ld4(a.p_in + p);
+    v = make_float4(v.x + beta * q.x, v.y + beta * q.y, v.z + beta * q.z, v.w + beta * q.w);
   }
-  a.real_out[plane_index(a, n)] = v;   // WDST_REAL
+  st4(a.p_out + p, v);
+  return v;
 }
 
 // In-place unnormalised Walsh-Hadamard transform of X[0, 2^lb) (natural
@@ -126,10 +141,11 @@ __device__ void lds_wht(float* X, int lb) {
 
 // One block per run of 2^lb contiguous flattened indices.
 __global__ __launch_bounds__(kThreads) void k_wht_low(WhtArgs a) {
-  __shared__ float X[1 << kLowBits];
-  const int C = 1 << a.lb;
+  __shared__ __align__(16) float X[1 << kLowBits];
+  float4* X4 = reinterpret_cast<float4*>(X);
+  const int C = 1 << a.lb, C4 = C >> 2;   // lb >= 4
   const int n0 = blockIdx.x << a.lb;
-  for (int i = threadIdx.x; i < C; i += kThreads) X[i] = load_src(a, n0 + i);
+  for (int i = threadIdx.x; i < C4; i += kThreads) X4[i] = load_src4(a, n0 + 4 * i);
   __syncthreads();
   if (a.fwd) lds_wht(X, a.lb);
   if (a.mul != WMUL_NONE) {
@@ -138,18 +154,24 @@ __global__ __launch_bounds__(kThreads) void k_wht_low(WhtArgs a) {
     __syncthreads();
   }
   if (a.inv) lds_wht(X, a.lb);
-  if (a.dst != WDST_Q) {
-    for (int i = threadIdx.x; i < C; i += kThreads) store_dst(a, n0 + i, X[i]);
+  if (a.dst == WDST_WORK) {
+    for (int i = threadIdx.x; i < C4; i += kThreads) st4(a.work + n0 + 4 * i, X4[i]);
+    return;
+  }
+  if (a.dst == WDST_REAL) {
+    for (int i = threadIdx.x; i < C4; i += kThreads) st4(a.real_out + plane_index(a, n0 + 4 * i), X4[i]);
     return;
   }
   // q = A p with this block's p.q partial (dst is uniform over the block)
   double acc = 0.0;
-  for (int i = threadIdx.x; i < C; i += kThreads) {
-    const long long p = plane_index(a, n0 + i);
-    const float pv = a.pvec[p];
-    const float qv = X[i] * a.inv_xi + a.tauc[p] * pv;
-    a.real_out[p] = qv;
-    acc += (double)pv * (double)qv;
+  for (int i = threadIdx.x; i < C4; i += kThreads) {
+    const long long p = plane_index(a, n0 + 4 * i);
+    const float4 pv = ld4(a.pvec + p), tc = ld4(a.tauc + p), v = X4[i];
+    const float4 qv = make_float4(v.x * a.inv_xi + tc.x * pv.x, v.y * a.inv_xi + tc.y * pv.y,
+                                  v.z * a.inv_xi + tc.z * pv.z, v.w * a.inv_xi + tc.w * pv.w);
+    st4(a.real_out + p, qv);
+    acc += ((double)pv.x * (double)qv.x + (double)pv.y * (double)qv.y) +
+           ((double)pv.z * (double)qv.z + (double)pv.w * (double)qv.w);
   }
   #pragma unroll
   for (int o = 32; o >= 1; o >>= 1) acc += __shfl_xor(acc, o);

@@ -70,7 +70,9 @@ def test_workspace_bytes_and_validation():
            ProblemSpec(16, 16, op=N.OP_HADAMARD_MASK),
            ProblemSpec(12, 16, op=N.OP_HADAMARD_MASK, mask=np.ones((12, 16), np.uint8)),
            ProblemSpec(8192, 4, op=N.OP_HADAMARD_MASK, mask=np.ones((8192, 4), np.uint8)),
-           ProblemSpec(8, 8, op=4)]
+           ProblemSpec(8, 8, op=4),
+           ProblemSpec(4, 4, op=N.OP_HADAMARD_MASK, mask=np.ones((4, 4), np.uint8)),
+           ProblemSpec(4, 4, op=N.OP_DFT_MASK, mask=np.ones((4, 4), np.uint8))]
     for s in bad:
         with pytest.raises(EPTVError):
             ep_tv_workspace_bytes([s])

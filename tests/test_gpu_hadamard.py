@@ -45,13 +45,17 @@ def _check(p, sweeps, em, **kw):
     return st
 
 
-@pytest.mark.parametrize("h,w,sweeps", [(4, 4, 10), (16, 16, 20), (32, 64, 30), (64, 64, 30),
-                                        (64, 128, 30), (128, 128, 40), (4, 256, 20), (256, 8, 20)])
-def test_hadamard_cs_small(h, w, sweeps):
-    """Sizes below, at and above one LDS group (4096 elements), square and thin."""
+@pytest.mark.parametrize("h,w,sweeps,em", [(8, 4, 10, False), (16, 16, 20, True), (32, 64, 30, True),
+                                           (64, 64, 30, True), (64, 128, 30, True),
+                                           (128, 128, 40, True), (4, 256, 20, True),
+                                           (256, 8, 20, True)])
+def test_hadamard_cs_small(h, w, sweeps, em):
+    """Sizes below, at and above one LDS group (4096 elements), square and thin,
+    from the smallest accepted image (32 pixels; 8 x 4 at a fixed lambda)."""
     rng = syn.rng_for(90, h * 1000 + w)
-    p = syn.make_hadamard_cs(h, w, max(3, h * w // 2000), 0.01, 0.3, rng, sweeps=sweeps, em=True)
-    _check(p, sweeps, True)
+    p = syn.make_hadamard_cs(h, w, max(3, h * w // 2000), 0.01, 0.3, rng, sweeps=sweeps, em=em,
+                             lam0=1.0 if em else 10.0)
+    _check(p, sweeps, em)
 
 
 def test_hadamard_cs_paper_shape():
