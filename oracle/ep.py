@@ -18,8 +18,10 @@ edge of V_k touches keeps the flat site (tau_k, eta_k) = (0, 0).
 
 One sweep t (where the paper is silent, the reading taken is stated at the step):
   1. likelihood site (Eqs. (tilted_P_1), (update_q0_x)), skipped for H = I,
-     where it is exact and constant, and in sweep 1, where the initial
-     q_{x,0} of the initialisation line stands in for it;
+     where it is exact and constant, and in sweep 1 of a cold start, where the
+     initial q_{x,0} of the initialisation line stands in for it
+     (``first_sweep_likelihood=True`` runs it at t = 1 as well, Algorithm 1's
+     loop body taken literally; both orders reach the same fixed point);
   2. for k in the block order (default 1, 2, 3, 4): every edge of V_k in
      parallel -- cavity, tilted moments of u (Eq. (marginal_tilted_un)),
      Gehre-Jin projection back to (x_i, x_j), site update (Eq. (update_qk_x)),
@@ -31,7 +33,9 @@ One sweep t (where the paper is silent, the reading taken is stated at the step)
 Parity pins: tests/test_oracle_ep.py (l2-TV fixed point = dense posterior mean,
 exact single-edge posterior, EM fixed point = marginal-likelihood maximiser on a
 single edge, symmetry invariants, colour-class structure) and
-tests/test_oracle_brute.py (3x3 brute-force posterior marginals).
+tests/test_oracle_brute.py (3x3 brute-force posterior marginals, the transfer
+pass against a direct sum over the joint grid), tests/test_oracle_estimators.py
+(the divergence rule; runaway of the spectral estimator on sparse masks).
 """
 from __future__ import annotations
 
@@ -45,6 +49,15 @@ from .tilted import tilted
 
 SITE_INIT_PREC = 1e-8     # 1 / 1e8: initial TV-site variance 1e8
 PREC_FLOOR = 1e-8         # clamp: site variance negative or above 1e8 -> 1e8
+# Divergence rule (the paper gives none; EP is not guaranteed to converge): a run
+# is declared diverged once the mean of the global approximation right after a
+# likelihood-site update exceeds DIVERGE_FACTOR times the scale of the
+# pixel-space observation (the larger of its range and its largest magnitude)
+# at some pixel (converging runs stay within about twice that scale, from
+# cold on).  The tilted mean E itself is no indicator: where the cavity is
+# flat and the operator leaves a direction unobserved it is huge but carries a
+# vanishing precision.
+DIVERGE_FACTOR = 1e3
 
 
 def colour_classes(h: int, w: int, boundary: str = "free"):
@@ -86,6 +99,7 @@ class EPState:
     cg_iters: int = 0
     history: list = field(default_factory=list)
     warm: bool = False              # sites carry information already: no skipped q0 update
+    lik_mu_absmax: float = 0.0      # max |mu| of the global approximation after the last q0 update
 
 
 class EPProblem:
@@ -94,7 +108,7 @@ class EPProblem:
 
     def __init__(self, y, op: ops.Operator, xi, lam, damping=0.5, prior="l1",
                  boundary="free", order: Sequence[int] = (1, 2, 3, 4),
-                 estimator="spectral", cg_rtol=1e-12):
+                 estimator="spectral", cg_rtol=1e-12, first_sweep_likelihood=False):
         self.op = op
         self.h, self.w = op.shape
         self.N = self.h * self.w
@@ -107,6 +121,7 @@ class EPProblem:
         self.order = tuple(order)
         self.estimator = estimator
         self.cg_rtol = cg_rtol
+        self.first_sweep_likelihood = bool(first_sweep_likelihood)
         self.y = y
         self.hty = op.Hty(y)
         self.edges = colour_classes(self.h, self.w, boundary)
@@ -178,6 +193,7 @@ def likelihood_site_update(pb: EPProblem, st: EPState):
     a = pb.damping
     st.tau[0] = a * tau_new + (1.0 - a) * st.tau[0]
     st.eta[0] = a * eta_new + (1.0 - a) * st.eta[0]
+    st.lik_mu_absmax = float(np.max(np.abs((st.eta[0] + eta_c) / (st.tau[0] + tau_c))))
 
 
 def tv_block_update(pb: EPProblem, st: EPState, k: int) -> float:
@@ -213,7 +229,7 @@ def tv_block_update(pb: EPProblem, st: EPState, k: int) -> float:
 
 def sweep(pb: EPProblem, st: EPState, t: int, em: bool) -> float:
     """Sweep t (1-based).  Returns a_bar_u of the sweep."""
-    if pb.op.kind != ops.IDENTITY and (t > 1 or st.warm):
+    if pb.op.kind != ops.IDENTITY and (t > 1 or st.warm or pb.first_sweep_likelihood):
         likelihood_site_update(pb, st)
     a_bar = 0.0
     for k in pb.order:
@@ -233,17 +249,23 @@ def solve(pb: EPProblem, sweeps: int, em: bool, tol: Optional[float] = None,
         max|mu_t - mu_{t-1}| <= tol * (max y - min y),
         max|v_t / v_{t-1} - 1| <= 10 tol,
         |lambda_t / lambda_{t-1} - 1| <= tol (EM only).
-    Returns (mu, v, state, info)."""
+    Stops as well, with info["diverged"], once the divergence rule holds
+    (DIVERGE_FACTOR).  Returns (mu, v, state, info)."""
     st = init_cold(pb) if state is None else state
     yr = np.asarray(pb.hty if pb.op.kind in (ops.DFT, ops.HADAMARD) else pb.y, dtype=np.float64)
     yrange = float(yr.max() - yr.min()) or 1.0
+    yscale = max(float(yr.max() - yr.min()), float(np.abs(yr).max()))
     mu_prev, v_prev = marginals(st)
     done = 0
     converged = False
+    diverged = False
     for t in range(1, sweeps + 1):
         lam_prev = st.lam
         a_bar = sweep(pb, st, t, em)
         done = t
+        if st.lik_mu_absmax > DIVERGE_FACTOR * yscale:
+            diverged = True
+            break
         mu, v = marginals(st)
         dmu = float(np.max(np.abs(mu - mu_prev))) / yrange
         dv = float(np.max(np.abs(v / v_prev - 1.0)))
@@ -256,5 +278,6 @@ def solve(pb: EPProblem, sweeps: int, em: bool, tol: Optional[float] = None,
             converged = True
             break
     mu, v = marginals(st)
-    info = {"sweeps": done, "lam": st.lam, "converged": converged, "clamp_count": st.clamp_count}
+    info = {"sweeps": done, "lam": st.lam, "converged": converged, "clamp_count": st.clamp_count,
+            "diverged": diverged}
     return mu.reshape(pb.h, pb.w), v.reshape(pb.h, pb.w), st, info

@@ -36,3 +36,48 @@ def test_ep_close_to_exact_posterior_3x3(lam, sig, seed):
     assert info["converged"]
     assert np.all(np.abs(mu - m_ex) <= 0.05 * np.sqrt(v_ex))
     assert np.all(np.abs(v / v_ex - 1) <= 0.10)
+
+
+@pytest.mark.parametrize("cols,G,lam", [(2, 14, 6.0), (3, 7, 10.0)])
+def test_grid_transfer_equals_direct_sum_over_the_joint_grid(cols, G, lam):
+    """The forward-backward transfer over columns must give exactly the moments
+    of a direct sum of the unnormalised posterior over every grid point of the
+    3 x cols image (all G^(3 cols) states, same midpoint grid), so a wrong
+    coupling index, a dropped vertical or horizontal factor or a wrong message
+    order shows up at round-off level."""
+    rng = np.random.default_rng(40 + cols)
+    y = np.array([[0.0, 0.7, 0.2], [0.1, 0.9, 0.3], [0.5, 0.4, 0.8]])[:, :cols] \
+        + 0.05 * rng.normal(size=(3, cols))
+    xi = 0.03
+    m_tr, v_tr = brute._moments_on_grid(y, xi, lam, G)
+    sd = np.sqrt(xi)
+    lo, hi = float(y.min()) - 8.0 * sd, float(y.max()) + 8.0 * sd
+    g = lo + (hi - lo) / G * (np.arange(G) + 0.5)
+    npx = 3 * cols
+    # pixel (r, c) is axis r * cols + c of the joint array
+    logp = np.zeros((G,) * npx)
+    def axis_vec(v, ax):
+        shape = [1] * npx
+        shape[ax] = G
+        return v.reshape(shape)
+    for r in range(3):
+        for c in range(cols):
+            logp = logp + axis_vec(-0.5 * (y[r, c] - g) ** 2 / xi, r * cols + c)
+    for r in range(3):
+        for c in range(cols):
+            for (r2, c2) in ((r + 1, c), (r, c + 1)):
+                if r2 < 3 and c2 < cols:
+                    d = axis_vec(g, r * cols + c) - axis_vec(g, r2 * cols + c2)
+                    logp = logp - lam * np.abs(d)
+    p = np.exp(logp - logp.max())
+    p /= p.sum()
+    for r in range(3):
+        for c in range(cols):
+            ax = r * cols + c
+            marg = p.sum(axis=tuple(a for a in range(npx) if a != ax))
+            m1 = float(np.dot(marg, g))
+            var = float(np.dot(marg, (g - m1) ** 2))
+            assert abs(m_tr[r, c] - m1) <= 1e-12 * (hi - lo)
+            # the transfer forms the variance as m2 - m1^2: round-off relative
+            # to the squared grid extent
+            assert abs(v_tr[r, c] - var) <= 1e-12 * (hi - lo) ** 2

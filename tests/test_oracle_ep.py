@@ -276,3 +276,37 @@ def test_hadamard_full_mask_equals_denoising_of_back_projection():
     mu_d, v_d, _, _ = ep.solve(pd, 12, False)
     assert np.allclose(mu_h, mu_d, rtol=0, atol=1e-9)
     assert np.allclose(v_h, v_d, rtol=1e-8, atol=0)
+
+
+def _order_case(kind, n):
+    rng = syn.rng_for(7, n)
+    if kind == "blur":
+        return syn.make_deconv(n, n, 4, 0.01, 2.0, rng, lam0=10.0)
+    return syn.make_cs(n, n, 4, 0.005, 0.25, rng, lam0=10.0)
+
+
+@pytest.mark.parametrize("kind,n,em", [("blur", 8, False), ("blur", 16, False), ("blur", 8, True),
+                                       ("dft", 8, False), ("dft", 16, False)])
+def test_first_sweep_order_reaches_the_same_fixed_point(kind, n, em):
+    """Reading of the first sweep of a cold start: the oracle lets the initial
+    likelihood factor (mean y, variance xi) stand in for the first likelihood
+    update and runs the first CG in sweep 2; Algorithm 1's loop body taken
+    literally runs the likelihood update at t = 1 as well.  Both orders must
+    converge (FP64, tol 1e-12) to the same EP fixed point, so the reading
+    changes the trajectory of a fixed number of sweeps, not the answer."""
+    p = _order_case(kind, n)
+    runs = []
+    for literal in (False, True):
+        pb = ep.problem_from_synthetic(p)
+        pb.first_sweep_likelihood = literal
+        mu, v, st, info = ep.solve(pb, 3000, em, tol=1e-12, record=True)
+        assert info["converged"] and not info["diverged"]
+        # the literal order really solves for E in sweep 1
+        assert (st.history[0]["cg"] > 0) == literal
+        runs.append((mu, v, info))
+    (mu_a, v_a, ia), (mu_b, v_b, ib) = runs
+    scale = mu_a.max() - mu_a.min()
+    assert np.max(np.abs(mu_a - mu_b)) <= 1e-9 * scale
+    assert np.max(np.abs(v_a / v_b - 1)) <= 1e-9
+    if em:
+        assert abs(ia["lam"] / ib["lam"] - 1) <= 1e-9
