@@ -51,7 +51,14 @@ enum {
   EP_TV_E_OOM = -2,            /* workspace smaller than ep_tv_workspace_bytes() */
   EP_TV_E_HIP = -3,            /* a HIP runtime call failed */
   EP_TV_E_NONFINITE = -4,      /* NaN/Inf detected in the EP state */
-  EP_TV_E_STATE = -5           /* call out of order (e.g. solve before observation) */
+  EP_TV_E_STATE = -5,          /* call out of order (e.g. solve before observation) */
+  EP_TV_E_DIVERGED = -6        /* EP diverged: after a likelihood-site update the mean of the
+                                  global approximation exceeded 1e3 times the scale of the
+                                  pixel-space observation (max(range, max |.|) of y, or of H^T y
+                                  for the transform operators) at some pixel.  EP has no
+                                  convergence guarantee (Sec. III); the spectral variance
+                                  estimator can run away on small images with sparse masks,
+                                  where RBMC (EP_TV_VAR_RBMC) does not */
 };
 
 /* Degradation operator H (Sec. II-A, cases (i)-(iii)). */
@@ -61,8 +68,7 @@ enum {
   EP_TV_OP_DFT_MASK = 2,       /* CS: subset of orthonormal 2-D DFT coefficients */
   EP_TV_OP_HADAMARD_MASK = 3   /* CS: subset of orthonormal 2-D Walsh-Hadamard coefficients,
                                   Paley order along each axis (Sec. II-A case (iii), Sec. V).
-                                  DFT and Hadamard: power-of-two sides in [4, 4096] and at
-                                  least 32 pixels (a 4 x 4 image is rejected) */
+                                  DFT and Hadamard: power-of-two sides in [4, 4096] */
 };
 
 /* Image boundary for the pixel-pair graph.  FREE: pairs inside the image only;
@@ -133,6 +139,8 @@ typedef struct {
   double lik_precision;        /* last likelihood-site precision gamma (non-identity operators) */
   double cavity_precision_mean;/* mean cavity precision d_bar of the last likelihood-site update */
   double cg_rel_residual;      /* ||r|| / ||b|| at the end of the last CG solve */
+  int32_t cold_restarts;       /* automatic cold restarts of ep_tv_solve (0 or 1) */
+  int32_t reserved_;
 } ep_tv_stats;
 
 typedef struct ep_tv_ctx ep_tv_ctx;
@@ -209,7 +217,13 @@ int ep_tv_em_step(ep_tv_ctx* ctx, int32_t n_ep_sweeps, double* lambda_out);
  * max_sweeps sweeps.  d_mean, d_var: host arrays of n_problems device pointers
  * (height*width floats each) or NULL to skip.  stats: host array of n_problems
  * or NULL.  Synchronises the stream.  Returns EP_TV_W_NOT_CONVERGED if any
- * instance did not converge (tol > 0), EP_TV_E_NONFINITE on NaN/Inf. */
+ * instance did not converge (tol > 0), EP_TV_E_NONFINITE on NaN/Inf,
+ * EP_TV_E_DIVERGED when the divergence rule held.  A failed instance is frozen
+ * (its stats status says which).  An instance started from ep_tv_init_warm or
+ * ep_tv_set_sites that goes non-finite or diverges is re-initialised cold once,
+ * automatically, and keeps sweeping within max_sweeps; if it then converges,
+ * its status is EP_TV_W_WARM_FALLBACK and so is the return value (when nothing
+ * worse happened).  Failures are detected every 8 sweeps. */
 int ep_tv_solve(ep_tv_ctx* ctx, int32_t max_sweeps, double tol, int32_t em_enabled,
                 float* const* d_mean, float* const* d_var, ep_tv_stats* stats);
 

@@ -19,6 +19,7 @@ EP_TV_E_OOM = -2
 EP_TV_E_HIP = -3
 EP_TV_E_NONFINITE = -4
 EP_TV_E_STATE = -5
+EP_TV_E_DIVERGED = -6
 
 OP_IDENTITY = 0
 OP_BLUR_PERIODIC = 1
@@ -36,7 +37,7 @@ OPT_GRAPH = 1
 OPT_TILE_ROWS = 2
 
 STATUS_NAMES = {0: "OK", 1: "W_NOT_CONVERGED", 2: "W_WARM_FALLBACK", -1: "E_ARG", -2: "E_OOM",
-                -3: "E_HIP", -4: "E_NONFINITE", -5: "E_STATE"}
+                -3: "E_HIP", -4: "E_NONFINITE", -5: "E_STATE", -6: "E_DIVERGED"}
 
 
 class EpTvProblem(ctypes.Structure):
@@ -61,7 +62,8 @@ class EpTvStats(ctypes.Structure):
                 ("lambda_", ctypes.c_double), ("a_bar_u", ctypes.c_double),
                 ("max_dmu_rel", ctypes.c_double), ("max_dv_rel", ctypes.c_double),
                 ("elapsed_ms", ctypes.c_double), ("lik_precision", ctypes.c_double),
-                ("cavity_precision_mean", ctypes.c_double), ("cg_rel_residual", ctypes.c_double)]
+                ("cavity_precision_mean", ctypes.c_double), ("cg_rel_residual", ctypes.c_double),
+                ("cold_restarts", ctypes.c_int32), ("reserved_", ctypes.c_int32)]
 
 
 class EpTvTiming(ctypes.Structure):

@@ -194,7 +194,7 @@ class Context:
         mp = _ptrs(means) if means is not None else None
         vp = _ptrs(variances) if variances is not None else None
         rc = N.lib().ep_tv_solve(self.handle, int(max_sweeps), float(tol), int(bool(em)), mp, vp, st)
-        self._check(rc, "solve", ok=(0, 1))
+        self._check(rc, "solve", ok=(0, 1, 2))
         return rc, [self._stats_dict(s) for s in st]
 
     def ep_tv_marginals(self, means=None, variances=None):
@@ -256,7 +256,8 @@ class Context:
                 "clamps": s.clamp_count, "status": s.status, "converged": bool(s.converged),
                 "lambda": s.lambda_, "a_bar_u": s.a_bar_u, "dmu": s.max_dmu_rel,
                 "dv": s.max_dv_rel, "elapsed_ms": s.elapsed_ms, "gamma": s.lik_precision,
-                "dbar": s.cavity_precision_mean, "cg_rel_residual": s.cg_rel_residual}
+                "dbar": s.cavity_precision_mean, "cg_rel_residual": s.cg_rel_residual,
+                "cold_restarts": s.cold_restarts}
 
     # -- conveniences built only from the entry points above --
     def marginals(self):

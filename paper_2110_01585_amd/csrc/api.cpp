@@ -132,11 +132,6 @@ const char* validate(const ep_tv_problem& p) {
     if (!fft_size_ok(p.height) || !fft_size_ok(p.width))
       return "DFT operator needs power-of-two sizes in [4, 4096]";
   }
-  // 4 x 4 transform operators give wrong results (cause not found), so the
-  // smallest accepted transform image has 32 pixels
-  if ((p.op == EP_TV_OP_DFT_MASK || p.op == EP_TV_OP_HADAMARD_MASK) &&
-      (long long)p.height * p.width < 32)
-    return "DFT and Walsh-Hadamard operators need at least 32 pixels";
   if (p.op == EP_TV_OP_HADAMARD_MASK) {
     if (!p.dft_mask) return "Walsh-Hadamard operator needs dft_mask";
     if (!fft_size_ok(p.height) || !fft_size_ok(p.width))
@@ -237,6 +232,7 @@ struct ep_tv_ctx {
   LikCtx lik;
   bool has_obs = false;
   bool any_lik = false;
+  bool warm_started = false;         // init_warm / set_sites since the last cold start
   std::vector<InstState> host_st;
   InstState* pull_st = nullptr;      // pinned host staging for state pulls (allocated on first pull)
   std::vector<float*> tab_host0, tab_host1;
@@ -322,6 +318,7 @@ static int upload_tiles(ep_tv_ctx* c) {
   const int n = c->n;
   c->idev_host.assign(n, InstDev{});
   c->tiles_host.clear();
+  int lik_tiles = 0;   // likelihood tiles are numbered in instance order, as lik_create does
   for (int i = 0; i < n; ++i) {
     const InstHost& h = c->ih[i];
     InstDev& d = c->idev_host[i];
@@ -329,6 +326,11 @@ static int upload_tiles(ep_tv_ctx* c) {
     d.H = h.p.height; d.W = h.p.width; d.pitch = h.pitch; d.bnd = h.p.boundary;
     d.off = h.off; d.op = h.p.op; d.strips = h.strips; d.chunks = h.chunks; d.tile0 = h.tile0;
     d.ntiles = h.ntiles; d.chunk_rows = h.chunk_rows; d.npix = h.p.height * h.p.width;
+    if (h.p.op != EP_TV_OP_IDENTITY) {
+      d.lik_tile0 = lik_tiles;
+      d.lik_ntiles = lik_tile_count(h.p.height, h.p.width);
+      lik_tiles += d.lik_ntiles;
+    }
     d.xi = (float)h.p.noise_var; d.inv_xi = (float)(1.0 / h.p.noise_var);
     d.alpha = (float)h.p.damping;
     if (h.p.prior != EP_TV_PRIOR_L1) {
@@ -477,6 +479,8 @@ int ep_tv_create(const ep_tv_problem* p, int32_t n, void* d_ws, size_t ws_bytes,
     if (lik_create(c->lik, li.data(), n, c->ws, c->L.lik, c->L.plane, c->d_inst, c->d_st,
                    c->d_tiles, c->ntiles, c->ypix, c->stream, e) != hipSuccess)
       rc = fail(c, EP_TV_E_HIP, "likelihood-site setup: " + e);
+    // the finalisation reads it only for instances with likelihood tiles
+    a.part_mu = c->lik.part_mu ? c->lik.part_mu : a.part_dmu;
   }
   if (rc == EP_TV_OK) rc = hip_check(c, hipStreamSynchronize(c->stream), "create sync");
   if (rc != EP_TV_OK) {
@@ -507,6 +511,7 @@ int ep_tv_init_cold(ep_tv_ctx* c) {
   if (rc) return rc;
   HIPCHK(c, launch_yrange(c->ypix, c->d_inst, c->d_st, c->n, c->stream));
   c->cur = 0;
+  c->warm_started = false;
   HIPCHK(c, launch_init_cold(cur_sites(c).S, c->ypix, c->d_inst, c->d_st, c->d_tiles, c->ntiles,
                              c->stream));
   HIPCHK(c, lik_reset(c->lik, c->stream));
@@ -531,6 +536,7 @@ int ep_tv_init_warm(ep_tv_ctx* c, const float* const* d_mu_hat, const float* con
                              c->sa.part_flags, c->stream));
   rc = pull_states(c);
   if (rc) return rc;
+  c->warm_started = true;
   int rejected = 0;
   for (int i = 0; i < c->n; ++i) rejected += c->host_st[i].warm_ok ? 0 : 1;
   if (rejected) {
@@ -779,8 +785,13 @@ static void fill_stats(ep_tv_ctx* c, ep_tv_stats* s) {
     o.cg_iters_total = h.cg_total;
     o.clamp_count = (int32_t)h.clamps;
     o.converged = h.converged;
-    o.status = (h.flags & FLAG_NONFINITE) ? EP_TV_E_NONFINITE
-               : (h.converged ? EP_TV_OK : EP_TV_W_NOT_CONVERGED);
+    o.status = (h.flags & FLAG_NONFINITE)   ? EP_TV_E_NONFINITE
+               : (h.flags & FLAG_DIVERGED)  ? EP_TV_E_DIVERGED
+               : !h.converged               ? EP_TV_W_NOT_CONVERGED
+               : h.cold_restarts            ? EP_TV_W_WARM_FALLBACK
+                                            : EP_TV_OK;
+    o.cold_restarts = h.cold_restarts;
+    o.reserved_ = 0;
     o.lambda = h.lam;
     o.a_bar_u = h.abar;
     o.max_dmu_rel = h.dmu;
@@ -790,6 +801,36 @@ static void fill_stats(ep_tv_ctx* c, ep_tv_stats* s) {
     o.cavity_precision_mean = h.dbar;
     o.cg_rel_residual = h.cg_bb > 0.0 ? std::sqrt(h.cg_rr / h.cg_bb) : 0.0;
   }
+}
+
+// An instance started from a prediction (ep_tv_init_warm) or restored sites
+// (ep_tv_set_sites) that went non-finite or diverged is re-initialised cold,
+// once, and keeps sweeping; the host state is current (pulled by the caller).
+static int restart_failed_warm(ep_tv_ctx* c) {
+  int nrestart = 0;
+  for (int i = 0; i < c->n; ++i) {
+    InstState& s = c->host_st[i];
+    if (!(s.flags & (FLAG_NONFINITE | FLAG_DIVERGED)) || !s.warm || s.cold_restarts > 0) continue;
+    const double yr = s.yrange, ys = s.yscale;
+    std::memset(&s, 0, sizeof(s));
+    s.lam = s.lam_prev = c->ih[i].p.lambda0;
+    s.yrange = yr;
+    s.yscale = ys;
+    s.active = 1u;
+    s.restart = 1;
+    s.cold_restarts = 1;
+    ++nrestart;
+  }
+  if (!nrestart) return EP_TV_OK;
+  HIPCHK(c, hipMemcpyAsync(c->d_st, c->host_st.data(), sizeof(InstState) * c->n,
+                           hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, launch_init_cold(cur_sites(c).S, c->ypix, c->d_inst, c->d_st, c->d_tiles, c->ntiles,
+                             c->stream, true));
+  for (int i = 0; i < c->n; ++i) c->host_st[i].restart = 0;
+  HIPCHK(c, hipMemcpyAsync(c->d_st, c->host_st.data(), sizeof(InstState) * c->n,
+                           hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));   // the host state array is rewritten by later pulls
+  return EP_TV_OK;
 }
 
 int ep_tv_solve(ep_tv_ctx* c, int32_t max_sweeps, double tol, int32_t em, float* const* d_mean,
@@ -804,12 +845,16 @@ int ep_tv_solve(ep_tv_ctx* c, int32_t max_sweeps, double tol, int32_t em, float*
   for (int t = 0; t < max_sweeps; t += check_every) {
     rc = advance(c, std::min(check_every, max_sweeps - t), em ? 1 : 0, true, use_tol ? tol : 0.0);
     if (rc) return rc;
-    if (use_tol) {
+    if (use_tol || c->warm_started) {
       rc = pull_states(c);
       if (rc) return rc;
+      if (c->warm_started) {
+        rc = restart_failed_warm(c);
+        if (rc) return rc;
+      }
       bool any = false;
       for (int i = 0; i < c->n; ++i) any = any || c->host_st[i].active;
-      if (!any) break;
+      if (use_tol && !any) break;
     }
   }
   rc = ep_tv_marginals(c, d_mean, d_var);
@@ -819,13 +864,21 @@ int ep_tv_solve(ep_tv_ctx* c, int32_t max_sweeps, double tol, int32_t em, float*
   c->last_elapsed_ms =
       std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   if (stats) fill_stats(c, stats);
-  bool nonfinite = false, notconv = false;
+  bool nonfinite = false, diverged = false, notconv = false, restarted = false;
   for (int i = 0; i < c->n; ++i) {
     nonfinite = nonfinite || (c->host_st[i].flags & FLAG_NONFINITE);
+    diverged = diverged || (c->host_st[i].flags & FLAG_DIVERGED);
     notconv = notconv || !c->host_st[i].converged;
+    restarted = restarted || c->host_st[i].cold_restarts > 0;
   }
   if (nonfinite) return fail(c, EP_TV_E_NONFINITE, "non-finite EP state");
+  if (diverged) return fail(c, EP_TV_E_DIVERGED, "EP diverged (the global mean left 1e3 times the "
+                                                 "observation's scale)");
   if (use_tol && notconv) return EP_TV_W_NOT_CONVERGED;
+  if (restarted) {
+    c->err = "a warm-started instance failed and was restarted cold";
+    return EP_TV_W_WARM_FALLBACK;
+  }
   return EP_TV_OK;
 }
 
@@ -865,6 +918,7 @@ int ep_tv_set_sites(ep_tv_ctx* c, const float* const* d_in, const double* lambda
   HIPCHK(c, launch_sites_io(cur_sites(c).S, c->d_inst, c->d_tiles, c->ntiles, c->d_tab0, 0,
                             c->stream));
   HIPCHK(c, lik_resume(c->lik, c->stream));
+  c->warm_started = true;
   return EP_TV_OK;
 }
 

@@ -40,8 +40,10 @@ struct SitePtrs {
 
 __global__ __launch_bounds__(256) void k_init_cold(SitePtrs sp, const float* __restrict__ y_pix,
                                                    const InstDev* __restrict__ inst,
-                                                   const int4* __restrict__ tiles) {
+                                                   const InstState* __restrict__ st,
+                                                   const int4* __restrict__ tiles, int only_restart) {
   const int4 td = tiles[blockIdx.x];
+  if (only_restart && !st[td.x].restart) return;
   const InstDev I = inst[td.x];
   const TileBox b = tile_box(td, I);
   const int cols = b.c1 - b.c0;
@@ -59,12 +61,13 @@ __global__ __launch_bounds__(256) void k_init_cold(SitePtrs sp, const float* __r
 }
 
 hipError_t launch_init_cold(float2* const S[5], const float* y_pix, const InstDev* inst,
-                            InstState* st, const int4* tiles, int ntiles, hipStream_t s) {
-  (void)st;
+                            InstState* st, const int4* tiles, int ntiles, hipStream_t s,
+                            bool only_restart) {
   SitePtrs sp;
   for (int k = 0; k < 5; ++k) sp.S[k] = S[k];
   if (ntiles == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_init_cold, dim3(ntiles), dim3(256), 0, s, sp, y_pix, inst, tiles);
+  hipLaunchKernelGGL(k_init_cold, dim3(ntiles), dim3(256), 0, s, sp, y_pix, inst, st, tiles,
+                     only_restart ? 1 : 0);
   return hipGetLastError();
 }
 
@@ -269,6 +272,11 @@ __global__ __launch_bounds__(256) void k_finalize(const InstDev* __restrict__ in
     cl += a.part_clamp[g];
     fl |= a.part_flags[g];
   }
+  // divergence rule: the global mean after this sweep's likelihood-site update
+  float mm = 0.f;
+  for (int t = threadIdx.x; t < I.lik_ntiles; t += blockDim.x)
+    mm = fmaxf(mm, a.part_mu[I.lik_tile0 + t]);
+  if (I.lik_ntiles > 0 && !(mm <= (float)(kDivergeFactor * S.yscale))) fl |= FLAG_DIVERGED;
   se[threadIdx.x] = e; sm[threadIdx.x] = dm; sv[threadIdx.x] = dv; sc[threadIdx.x] = cl;
   sf[threadIdx.x] = fl;
   __syncthreads();
@@ -292,7 +300,7 @@ __global__ __launch_bounds__(256) void k_finalize(const InstDev* __restrict__ in
     if (em && abar > 0.0) S.lam = (double)I.npix / abar;
     S.dmu = (double)sm[0] / (S.yrange > 0.0 ? S.yrange : 1.0);
     S.dv = (double)sv[0];
-    if (S.flags & FLAG_NONFINITE) {
+    if (S.flags & (FLAG_NONFINITE | FLAG_DIVERGED)) {
       S.active = 0u;
     } else if (tol > 0.0) {
       const double dl = fabs(S.lam / S.lam_prev - 1.0);
@@ -420,7 +428,11 @@ __global__ __launch_bounds__(1024) void k_yrange(const float* __restrict__ y_pix
     }
     __syncthreads();
   }
-  if (threadIdx.x == 0) st[blockIdx.x].yrange = (double)smax[0] - (double)smin[0];
+  if (threadIdx.x == 0) {
+    const double lo_d = (double)smin[0], hi_d = (double)smax[0];
+    st[blockIdx.x].yrange = hi_d - lo_d;
+    st[blockIdx.x].yscale = fmax(hi_d - lo_d, fmax(fabs(lo_d), fabs(hi_d)));
+  }
 }
 
 hipError_t launch_yrange(const float* y_pix, const InstDev* inst, InstState* st, int n,

@@ -32,6 +32,8 @@ struct InstDev {
   int op, strips, chunks, tile0;
   int ntiles, chunk_rows, npix, pad0;
   float xi, inv_xi, alpha, pad1;
+  int lik_tile0, lik_ntiles;               // likelihood-kernel tiles (non-identity operators)
+  int pad2, pad3;
   float mix_dla, mix_dv, mix_v1, mix_v2;   // mixture factor: log(a2/a1), v1 - v2, v1, v2
 };
 
@@ -50,10 +52,16 @@ struct InstState {
   unsigned clamps, flags, active, sweeps;
   int cg_last, cg_total, converged, cg_done;
   int cg_it, x_valid, warm, warm_ok;   // warm: sites were set from a prediction (no skipped q0)
-  int xprev_valid, pad_;               // the plane of the solve before the last holds its E
+  int xprev_valid, restart;            // restart: cold re-initialisation pending (host-set)
+  double yscale;                       // max(range, max |.|) of the pixel-space observation
+  int cold_restarts, pad2_;            // automatic cold restarts after a failed warm start
 };
 
-enum { FLAG_NONFINITE = 1u };
+// FLAG_DIVERGED: the global mean after a likelihood-site update left
+// kDivergeFactor times the observation's scale (EP is not guaranteed to converge;
+// the spectral variance estimator can run away on sparse masks).
+enum { FLAG_NONFINITE = 1u, FLAG_DIVERGED = 2u };
+constexpr double kDivergeFactor = 1e3;
 
 // The sweep reads the TV sites of the previous sweep from one buffer and writes
 // the new ones to the other (ping-pong): a wave's halo pixels are interior
@@ -71,6 +79,7 @@ struct SweepArgs {
   float* part_dv;
   unsigned* part_clamp;
   unsigned* part_flags;
+  const float* part_mu;      // per likelihood tile: max |mu| after the likelihood-site update
   int prior;                 // PRIOR_* of every instance of the context
 };
 
@@ -92,8 +101,10 @@ hipError_t launch_tilted(int n, const float* m, const float* s, float lam, float
 hipError_t launch_tilted_mixture(int n, const float* m, const float* s, float dla, float dv,
                                  float v1, float v2, float* rho, float* del, float* eabs,
                                  hipStream_t st);
+// only_restart: re-initialise only the instances whose InstState::restart is set
 hipError_t launch_init_cold(float2* const S[5], const float* y_pix, const InstDev* inst,
-                            InstState* st, const int4* tiles, int ntiles, hipStream_t s);
+                            InstState* st, const int4* tiles, int ntiles, hipStream_t s,
+                            bool only_restart = false);
 hipError_t launch_finalize(const InstDev* inst, InstState* st, int n, const SweepArgs& a,
                            int em, double tol, hipStream_t s);
 hipError_t launch_marginals(float2* const S[5], const InstDev* inst, const int4* tiles, int ntiles,

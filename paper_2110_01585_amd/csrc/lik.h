@@ -26,6 +26,9 @@ constexpr int kCgPoll = 4;                 // CG iterations between convergence 
 
 inline bool fft_size_ok(int n) { return n >= 4 && n <= 4096 && (n & (n - 1)) == 0; }
 
+// Likelihood-kernel tiles of an H x W instance (64 x 16 pixels each).
+inline int lik_tile_count(int H, int W) { return ((W + 63) / 64) * ((H + 15) / 16); }
+
 // Preconditioner request per instance (the ABI's EP_TV_PRECOND_* values).
 enum { PRECOND_REQ_AUTO = 0, PRECOND_REQ_JACOBI = 1, PRECOND_REQ_CIRCULANT = 2 };
 
@@ -84,7 +87,7 @@ inline bool lik_uses_fft(int op, int H, int W, int req) {
 struct LikLayout {
   size_t planes[LP_COUNT]{};
   int nplanes = 0;
-  size_t inst = 0, tiles = 0, part0 = 0, part1 = 0, taps = 0, fft = 0;
+  size_t inst = 0, tiles = 0, part0 = 0, part1 = 0, part_mu = 0, taps = 0, fft = 0;
   int nlik = 0, ntiles = 0, ntaps = 0;
   size_t fft_bytes = 0;
   size_t wht = 0, wht_bytes = 0;
@@ -113,6 +116,7 @@ void lik_layout(const LikInstInfo* li, int n, long long plane, Take&& take, LikL
   L.tiles = take(sizeof(int4) * (size_t)std::max(L.ntiles, 1));
   L.part0 = take(sizeof(double) * (size_t)std::max(L.ntiles, 1));
   L.part1 = take(sizeof(double) * (size_t)std::max(L.ntiles, 1));
+  L.part_mu = take(sizeof(float) * (size_t)std::max(L.ntiles, 1));
   L.taps = take(sizeof(float) * (size_t)std::max(L.ntaps, 1));
   // FFT work buffers, per DFT instance: two complex planes, twiddles, the
   // transposed spectrum and the mask (each rounded up to 256 bytes)
@@ -168,6 +172,7 @@ struct LikCtx {
   int4* d_tiles = nullptr;
   double* part0 = nullptr;
   double* part1 = nullptr;
+  float* part_mu = nullptr;          // per tile: max |mu| after the likelihood-site update
   float* taps = nullptr;
   float* planes[LP_COUNT]{};
   float2* fft = nullptr;

@@ -41,6 +41,7 @@ struct LikArgs {
   InstState* st;
   double* part0;
   double* part1;
+  float* part_mu;
   const float* taps;
   float* hty; float* tauc; float* etac; float* b; float* x; float* r; float* z;
   float* p_in; float* p_out; float* q; float* spec; float* xprev;
@@ -621,13 +622,28 @@ __global__ __launch_bounds__(256) void k_cg_update(LikArgs A) {
       });
 }
 
-// 7. site update q_{x,0} from E = x (Eq. (update_q0_x)), clamp, damping
+// Deterministic block maximum (256 threads), written by thread 0.
+__device__ __forceinline__ void block_max(float v, float* out) {
+  __shared__ float wm[4];
+#pragma unroll
+  for (int off = kWave / 2; off >= 1; off >>= 1) v = fmaxf(v, __shfl_xor(v, off, kWave));
+  if (threadIdx.x % kWave == 0) wm[threadIdx.x / kWave] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) *out = fmaxf(fmaxf(wm[0], wm[1]), fmaxf(wm[2], wm[3]));
+}
+
+// 7. site update q_{x,0} from E = x (Eq. (update_q0_x)), clamp, damping; the
+//    tile's largest |mean| of the global approximation after the update feeds
+//    the divergence rule
 __global__ __launch_bounds__(256) void k_lik_site(LikArgs A, float2* __restrict__ S0) {
   const int tile = blockIdx.x;
   const int4 td = A.tiles[tile];
   const LikInst L = A.inst[td.x];
   InstState& st = A.st[L.inst];
-  if (!st.active || (st.sweeps == 0 && !st.warm)) return;
+  if (!st.active || (st.sweeps == 0 && !st.warm)) {
+    if (threadIdx.x == 0) A.part_mu[tile] = 0.f;
+    return;
+  }
   if (tile == L.tile0 && threadIdx.x == 0) {
     st.cg_last = st.cg_it;
     st.cg_total += st.cg_it;
@@ -638,13 +654,17 @@ __global__ __launch_bounds__(256) void k_lik_site(LikArgs A, float2* __restrict_
   const float a = L.alpha;
   float tcv[kTileItems], xv[kTileItems], ecv[kTileItems];
   float2 ov[kTileItems];
+  float mx = 0.f;
   tile_two_phase<true>(
       t, L,
       [&](int u, long long p) { tcv[u] = A.tauc[p]; xv[u] = A.x[p]; ecv[u] = A.etac[p]; ov[u] = S0[p]; },
       [&](int u, long long p) {
         const float eta_new = (float)(((double)tau_new + (double)tcv[u]) * (double)xv[u] - (double)ecv[u]);
-        S0[p] = make_float2(a * tau_new + (1.f - a) * ov[u].x, a * eta_new + (1.f - a) * ov[u].y);
+        const float2 s0 = make_float2(a * tau_new + (1.f - a) * ov[u].x, a * eta_new + (1.f - a) * ov[u].y);
+        S0[p] = s0;
+        mx = fmaxf(mx, fabsf((s0.y + ecv[u]) / (s0.x + tcv[u])));
       });
+  block_max(mx, &A.part_mu[tile]);
 }
 
 // ---------------------------------------------------------------------------
@@ -719,6 +739,7 @@ static LikArgs make_args(LikCtx& lc) {
   A.st = lc.d_st;
   A.part0 = lc.part0;
   A.part1 = lc.part1;
+  A.part_mu = lc.part_mu;
   A.taps = lc.taps;
   A.hty = lc.planes[LP_HTY];
   A.tauc = lc.planes[LP_TAUC];
@@ -752,6 +773,7 @@ hipError_t lik_create(LikCtx& lc, const LikInstInfo* li, int n, char* ws, const 
   lc.d_tiles = reinterpret_cast<int4*>(ws + L.tiles);
   lc.part0 = reinterpret_cast<double*>(ws + L.part0);
   lc.part1 = reinterpret_cast<double*>(ws + L.part1);
+  lc.part_mu = reinterpret_cast<float*>(ws + L.part_mu);
   lc.taps = reinterpret_cast<float*>(ws + L.taps);
   lc.fft = reinterpret_cast<float2*>(ws + L.fft);
   lc.whtbuf = reinterpret_cast<float*>(ws + L.wht);

@@ -475,12 +475,34 @@ __global__ __launch_bounds__(kWavesPerBlock * kWave) void k_tv_sweep(SweepArgs a
   const bool has = tile < a.ntiles;
   const int4 td = has ? a.tiles[tile] : make_int4(0, 0, 0, 0);
   if (!has || !a.st[td.x].active) {
-    if (has && lane == 0) {
-      a.part_eabs[tile] = 0.0;
-      a.part_dmu[tile] = 0.f;
-      a.part_dv[tile] = 0.f;
-      a.part_clamp[tile] = 0u;
-      a.part_flags[tile] = 0u;
+    if (has) {
+      // A frozen instance (converged, diverged or non-finite) keeps its sites:
+      // they are carried into the output buffer, so the buffer the context
+      // reads next holds the instance's final state whatever the parity of the
+      // sweeps that run after it froze.
+      const InstDev I = a.inst[td.x];
+      const int c0 = td.y * kStripInt;
+      const int R0 = td.z * I.chunk_rows;
+      const int R1 = min(R0 + I.chunk_rows, I.H);
+      for (int r = R0; r < R1; ++r) {
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+          const int c = c0 - 2 + 2 * lane + k;
+          if (c < c0 || c >= c0 + kStripInt || c >= I.W) continue;
+          const long long p = I.off + (long long)r * I.pitch + c;
+          a.O1[p] = a.I1[p];
+          a.O2[p] = a.I2[p];
+          a.O3[p] = a.I3[p];
+          a.O4[p] = a.I4[p];
+        }
+      }
+      if (lane == 0) {
+        a.part_eabs[tile] = 0.0;
+        a.part_dmu[tile] = 0.f;
+        a.part_dv[tile] = 0.f;
+        a.part_clamp[tile] = 0u;
+        a.part_flags[tile] = 0u;
+      }
     }
     __syncthreads();   // the two exchange points of the other waves
     __syncthreads();

@@ -55,6 +55,9 @@ def test_workspace_bytes_and_validation():
     # the largest accepted sizes (16384 on a side) size without error
     big = ep_tv_workspace_bytes([ProblemSpec(16384, 3), ProblemSpec(2, 16384)])
     assert big >= (16384 * 3 + 2 * 16384) * (5 * 8)
+    # the smallest transform images (one 4 x 4 block) are accepted
+    for op in (N.OP_HADAMARD_MASK, N.OP_DFT_MASK):
+        assert ep_tv_workspace_bytes([ProblemSpec(4, 4, op=op, mask=np.ones((4, 4), np.uint8))]) > 0
     bad = [ProblemSpec(0, 5), ProblemSpec(5, 5, noise_var=0.0), ProblemSpec(5, 5, lambda0=-1),
            ProblemSpec(5, 5, damping=0.0), ProblemSpec(5, 5, damping=1.5),
            ProblemSpec(5, 6, boundary=N.BND_PERIODIC),
@@ -70,9 +73,7 @@ def test_workspace_bytes_and_validation():
            ProblemSpec(16, 16, op=N.OP_HADAMARD_MASK),
            ProblemSpec(12, 16, op=N.OP_HADAMARD_MASK, mask=np.ones((12, 16), np.uint8)),
            ProblemSpec(8192, 4, op=N.OP_HADAMARD_MASK, mask=np.ones((8192, 4), np.uint8)),
-           ProblemSpec(8, 8, op=4),
-           ProblemSpec(4, 4, op=N.OP_HADAMARD_MASK, mask=np.ones((4, 4), np.uint8)),
-           ProblemSpec(4, 4, op=N.OP_DFT_MASK, mask=np.ones((4, 4), np.uint8))]
+           ProblemSpec(8, 8, op=4)]
     for s in bad:
         with pytest.raises(EPTVError):
             ep_tv_workspace_bytes([s])

@@ -147,10 +147,17 @@ def test_em_step_and_solve_convergence():
     mu = torch.empty(64, 64, device="cuda"); v = torch.empty(64, 64, device="cuda")
     rc, stats = ctx.ep_tv_solve(400, 1e-5, True, [mu], [v])
     assert rc == 0 and stats[0]["converged"], stats
-    mu_o, v_o, _, info = oep.solve(pb, 400, em=True, tol=1e-5)
+    _, _, _, info = oep.solve(pb, 400, em=True, tol=1e-5)
     assert info["converged"]
-    assert mean_err(mu.cpu().numpy(), mu_o) <= 5 * MEAN_TOL
-    assert var_err(v.cpu().numpy(), v_o) <= 5 * VAR_TOL
+    # the stopping sweep is a threshold decision on rounded deltas: the two
+    # sides may stop one sweep apart; the returned state is compared with the
+    # oracle after exactly the device's sweep count, at the parity bar
+    t = stats[0]["sweeps"]
+    assert abs(t - info["sweeps"]) <= 1, (t, info["sweeps"])
+    mu_o, v_o, _, info_t = oep.solve(pb, t, em=True)
+    assert mean_err(mu.cpu().numpy(), mu_o) <= MEAN_TOL
+    assert var_err(v.cpu().numpy(), v_o) <= VAR_TOL
+    assert abs(stats[0]["lambda"] / info_t["lam"] - 1) <= 1e-4
 
 
 def test_invalid_arguments_and_order():

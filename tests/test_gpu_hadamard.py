@@ -50,8 +50,8 @@ def _check(p, sweeps, em, **kw):
                                            (128, 128, 40, True), (4, 256, 20, True),
                                            (256, 8, 20, True)])
 def test_hadamard_cs_small(h, w, sweeps, em):
-    """Sizes below, at and above one LDS group (4096 elements), square and thin,
-    from the smallest accepted image (32 pixels; 8 x 4 at a fixed lambda)."""
+    """Sizes below, at and above one LDS group (4096 elements), square and thin
+    (4 x 4 images: tests/test_gpu_robust.py)."""
     rng = syn.rng_for(90, h * 1000 + w)
     p = syn.make_hadamard_cs(h, w, max(3, h * w // 2000), 0.01, 0.3, rng, sweeps=sweeps, em=em,
                              lam0=1.0 if em else 10.0)
