@@ -330,6 +330,24 @@ typedef struct {
 } ep_tv_tune_result;
 int ep_tv_autotune(ep_tv_ctx* ctx, int32_t repeats, ep_tv_tune_result* out);
 
+/* Denoising without any allocation, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc): the same computation as ep_tv_create for one
+ * EP_TV_OP_IDENTITY instance (l1 prior, lambda0 = lambda), ep_tv_set_observation,
+ * ep_tv_run(n_sweeps, em_enabled) and ep_tv_marginals, run on the same kernels,
+ * with every working buffer in a 24 MiB device array of the library (one per GPU,
+ * held until the process ends) instead of a caller workspace.  It calls no
+ * allocating routine, host or device.
+ * height, width: in [1, 512] (EP_TV_E_ARG beyond); boundary: EP_TV_BND_*;
+ * noise_var > 0, lambda > 0, damping in (0, 1], n_sweeps >= 0.
+ * d_y: device, height*width floats (read); d_mean, d_var: device, height*width
+ * floats each (written).  hip_stream as in ep_tv_create.  Asynchronous.
+ * Calls on one GPU share its array: calls that overlap on one GPU (other
+ * streams or threads) race and give wrong results. */
+int ep_tv_denoise_noalloc(int32_t height, int32_t width, int32_t boundary, double noise_var,
+                          double lambda, double damping, int32_t n_sweeps, int32_t em_enabled,
+                          const float* d_y, float* d_mean, float* d_var, void* hip_stream);
+
 /* Message for the last error on this context ("" if none).  Static to the ctx. */
 const char* ep_tv_last_error(const ep_tv_ctx* ctx);
 

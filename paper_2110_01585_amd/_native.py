@@ -109,6 +109,9 @@ SIGNATURES = {
     "ep_tv_set_option": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int64]),
     "ep_tv_get_option": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64)]),
     "ep_tv_autotune": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.POINTER(EpTvTuneResult)]),
+    "ep_tv_denoise_noalloc": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                             ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                             ctypes.c_int32, ctypes.c_int32, _P, _P, _P, _P]),
     "ep_tv_last_error": (ctypes.c_char_p, [_P]),
     "ep_tv_destroy": (None, [_P]),
     # learned warm start (include/ep_tv_net.h)

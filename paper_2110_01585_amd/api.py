@@ -133,6 +133,27 @@ def ep_tv_tilted_moments(m, s, lam, stream=None):
     return rho, de, ea
 
 
+def ep_tv_denoise_noalloc(y, noise_var, lam, damping, n_sweeps, em, mean, var,
+                          boundary=N.BND_FREE, stream=None):
+    """Forward to ep_tv_denoise_noalloc (no allocation inside the library):
+    y, mean, var are contiguous float32 device tensors of one H x W image."""
+    import torch
+    for t in (y, mean, var):
+        if not (t.is_cuda and t.dtype == torch.float32 and t.is_contiguous()):
+            raise ValueError("expected contiguous float32 CUDA tensors")
+    h, w = y.shape
+    if mean.shape != y.shape or var.shape != y.shape:
+        raise ValueError("mean and var must have the shape of y")
+    s = stream if stream is not None else torch.cuda.current_stream(y.device)
+    rc = N.lib().ep_tv_denoise_noalloc(int(h), int(w), int(boundary), float(noise_var), float(lam),
+                                       float(damping), int(n_sweeps), int(bool(em)), y.data_ptr(),
+                                       mean.data_ptr(), var.data_ptr(),
+                                       ctypes.c_void_p(s.cuda_stream))
+    if rc != 0:
+        raise EPTVError(rc, "ep_tv_denoise_noalloc failed (sizes above 512, or invalid arguments)")
+    return rc
+
+
 class Context:
     """Owns a libeptv context and the torch workspace tensor backing it."""
 
