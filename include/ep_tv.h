@@ -290,6 +290,17 @@ typedef struct {
   double precond_ms;           /* total GPU time of the real-transform preconditioner of the
                                   circulant-preconditioned CG (with the fused x, r update) */
   int32_t precond_launches;
+  /* single kernels of the likelihood-site update (every launch of each): the
+   * three passes of the real 2-D transform (forward row pass with the fused
+   * x, r update; column pass with the filter; inverse row pass with the r.z,
+   * r.r partials), the per-instance finishing (reduction) kernels, and the
+   * remaining element-wise kernels (cavity and right-hand side, spectral sum,
+   * CG start, Jacobi steps, site update) */
+  double rf_fwd_ms;  int32_t rf_fwd_launches;
+  double rf_filt_ms; int32_t rf_filt_launches;
+  double rf_inv_ms;  int32_t rf_inv_launches;
+  double fin_ms;     int32_t fin_launches;
+  double lik_other_ms; int32_t lik_other_launches;
 } ep_tv_timing;
 
 int ep_tv_set_timing(ep_tv_ctx* ctx, int32_t enable);

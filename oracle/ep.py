@@ -100,6 +100,7 @@ class EPState:
     history: list = field(default_factory=list)
     warm: bool = False              # sites carry information already: no skipped q0 update
     lik_mu_absmax: float = 0.0      # max |mu| of the global approximation after the last q0 update
+    rbmc: Optional[ops.RBMCSamples] = None   # RBMC inputs and per-sample CG starts
 
 
 class EPProblem:
@@ -108,7 +109,8 @@ class EPProblem:
 
     def __init__(self, y, op: ops.Operator, xi, lam, damping=0.5, prior="l1",
                  boundary="free", order: Sequence[int] = (1, 2, 3, 4),
-                 estimator="spectral", cg_rtol=1e-12, first_sweep_likelihood=False):
+                 estimator="spectral", cg_rtol=1e-12, first_sweep_likelihood=False,
+                 rbmc_noise=None):
         self.op = op
         self.h, self.w = op.shape
         self.N = self.h * self.w
@@ -122,6 +124,10 @@ class EPProblem:
         self.estimator = estimator
         self.cg_rtol = cg_rtol
         self.first_sweep_likelihood = bool(first_sweep_likelihood)
+        # RBMC estimator: (e1, e2) white noise, Ns images each (operators.RBMCSamples)
+        self.rbmc_noise = rbmc_noise
+        if estimator == "rbmc" and rbmc_noise is None:
+            raise ValueError("the RBMC estimator needs white-noise samples (rbmc_noise)")
         self.y = y
         self.hty = op.Hty(y)
         self.edges = colour_classes(self.h, self.w, boundary)
@@ -133,13 +139,13 @@ class EPProblem:
 
 
 def problem_from_synthetic(p, prior="l1", estimator="spectral", boundary=None, order=(1, 2, 3, 4),
-                           lam=None, damping=None):
+                           lam=None, damping=None, rbmc_noise=None):
     """Build an EPProblem from a synthetic.Problem."""
     op = ops.Operator(p.op, p.shape, taps=p.taps, mask=p.mask)
     return EPProblem(p.y, op, p.xi, p.lam0 if lam is None else lam,
                      damping=p.damping if damping is None else damping, prior=prior,
                      boundary=p.boundary if boundary is None else boundary, order=order,
-                     estimator=estimator)
+                     estimator=estimator, rbmc_noise=rbmc_noise)
 
 
 def init_cold(pb: EPProblem) -> EPState:
@@ -183,7 +189,9 @@ def likelihood_site_update(pb: EPProblem, st: EPState):
     E, it = ops.solve_tilted_mean(pb.op, pb.xi, tau_c.reshape(shape), b, x0=x0, rtol=pb.cg_rtol)
     st.E = E
     st.cg_iters = it
-    V = ops.tilted_variance(pb.op, pb.xi, tau_c.reshape(shape), pb.estimator).ravel()
+    if pb.estimator == "rbmc" and st.rbmc is None:
+        st.rbmc = ops.RBMCSamples(*pb.rbmc_noise)
+    V = ops.tilted_variance(pb.op, pb.xi, tau_c.reshape(shape), pb.estimator, st.rbmc).ravel()
     E = E.ravel()
     tau_new = 1.0 / V - tau_c
     clamp = tau_new < PREC_FLOOR

@@ -37,6 +37,17 @@ it is exact when H^T H is diagonal and otherwise names Monte Carlo estimators
               Walsh-Hadamard operator the same holds with the Walsh basis in
               place of the Fourier basis (every Walsh function has squared
               entries 1 / N, like every Fourier mode).
+* "rbmc":     the simple Rao-Blackwellised Monte Carlo estimator the paper names
+              (Siden, Lindgren, Bolin, Villani 2018).  With Q the precision
+              H^T H / xi + diag(tau_c), Var(x_i) = 1/Q_ii + Var(E[x_i | x_-i]) and
+              E[x_i | x_-i] = -(sum_{j != i} Q_ij x_j) / Q_ii, so
+                v_i = 1/Q_ii + (1/Q_ii^2) (1/Ns) sum_s (sum_{j != i} Q_ij x_j^(s))^2,
+              x^(s) ~ N(0, Q^{-1}) drawn by perturbation-optimisation: solve
+              Q x^(s) = z^(s) with z^(s) = H^T e1^(s) / sqrt(xi) + sqrt(tau_c) e2^(s)
+              ~ N(0, Q), e1^(s) white in observation space (complex for the DFT:
+              real and imaginary parts each N(0, 1)), e2^(s) white in pixel
+              space.  The white noise is an input (the caller draws it); each
+              sample costs one CG solve.  Unbiased for any Ns, v_i >= 1/Q_ii.
 """
 from __future__ import annotations
 
@@ -171,6 +182,12 @@ class Operator:
     def Hty(self, y):
         return self.Ht(y)
 
+    def diag_HtH(self):
+        """Diagonal of H^T H, the same at every pixel for these operators: the
+        mean eigenvalue (every basis function of the diagonalising transform has
+        squared entries 1 / N; for the blur it equals the sum of squared taps)."""
+        return float(np.mean(self.spectrum()))
+
     def dense_HtH(self):
         """Explicit N x N matrix of H^T H (tiny images only)."""
         h, w = self.shape
@@ -227,10 +244,46 @@ def solve_tilted_mean(op: Operator, xi, tau_c, b, x0=None, rtol=1e-12, maxiter=5
     return x, it
 
 
-def tilted_variance(op: Operator, xi, tau_c, estimator="spectral"):
+class RBMCSamples:
+    """White-noise inputs of the RBMC estimator and the per-sample solutions of
+    the last call (the CG starting points of the next one; they change the
+    iteration counts, not the estimate).  e1: (Ns, h, w), complex for the DFT
+    operator; e2: (Ns, h, w)."""
+
+    def __init__(self, e1, e2):
+        self.e1 = np.asarray(e1)
+        self.e2 = np.asarray(e2, dtype=np.float64)
+        if self.e1.shape != self.e2.shape:
+            raise ValueError("e1 and e2 must hold Ns images each")
+        self.ns = self.e2.shape[0]
+        self.x = [None] * self.ns
+        self.cg_iters = 0
+
+
+def rbmc_variance(op: Operator, xi, tau_c, samples: RBMCSamples, rtol=1e-12):
+    """Diagonal of Q^{-1}, Q = H^T H / xi + diag(tau_c), by the RBMC estimator
+    (see the module header)."""
+    qd = op.diag_HtH() / xi + tau_c
+    acc = np.zeros_like(tau_c, dtype=np.float64)
+    samples.cg_iters = 0
+    for s in range(samples.ns):
+        z = op.Ht(samples.e1[s]) / np.sqrt(xi) + np.sqrt(tau_c) * samples.e2[s]
+        x, it = solve_tilted_mean(op, xi, tau_c, z, x0=samples.x[s], rtol=rtol)
+        samples.x[s] = x
+        samples.cg_iters += it
+        off = op.HtH(x) / xi + tau_c * x - qd * x          # sum_{j != i} Q_ij x_j
+        acc += off * off
+    return 1.0 / qd + acc / samples.ns / (qd * qd)
+
+
+def tilted_variance(op: Operator, xi, tau_c, estimator="spectral", rbmc: RBMCSamples = None):
     """Diagonal of (H^T H / xi + diag(tau_c))^{-1}."""
     if op.kind == IDENTITY:
         return 1.0 / (1.0 / xi + tau_c)
+    if estimator == "rbmc":
+        if rbmc is None:
+            raise ValueError("the RBMC estimator needs its white-noise samples")
+        return rbmc_variance(op, xi, tau_c, rbmc)
     if estimator == "exact":
         A = op.dense_HtH() / xi + np.diag(tau_c.ravel())
         return np.diag(np.linalg.inv(A)).reshape(op.shape).copy()

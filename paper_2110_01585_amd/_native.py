@@ -70,7 +70,12 @@ class EpTvTiming(ctypes.Structure):
     _fields_ = [("sweep_ms", ctypes.c_double), ("sweep_launches", ctypes.c_int32),
                 ("lik_ms", ctypes.c_double), ("lik_updates", ctypes.c_int32),
                 ("apply_ms", ctypes.c_double), ("apply_launches", ctypes.c_int32),
-                ("precond_ms", ctypes.c_double), ("precond_launches", ctypes.c_int32)]
+                ("precond_ms", ctypes.c_double), ("precond_launches", ctypes.c_int32),
+                ("rf_fwd_ms", ctypes.c_double), ("rf_fwd_launches", ctypes.c_int32),
+                ("rf_filt_ms", ctypes.c_double), ("rf_filt_launches", ctypes.c_int32),
+                ("rf_inv_ms", ctypes.c_double), ("rf_inv_launches", ctypes.c_int32),
+                ("fin_ms", ctypes.c_double), ("fin_launches", ctypes.c_int32),
+                ("lik_other_ms", ctypes.c_double), ("lik_other_launches", ctypes.c_int32)]
 
 
 class EpTvTuneResult(ctypes.Structure):

@@ -245,10 +245,7 @@ class Context:
     def ep_tv_get_timing(self):
         t = N.EpTvTiming()
         self._check(N.lib().ep_tv_get_timing(self.handle, ctypes.byref(t)), "get_timing")
-        return {"sweep_ms": t.sweep_ms, "sweep_launches": t.sweep_launches, "lik_ms": t.lik_ms,
-                "lik_updates": t.lik_updates, "apply_ms": t.apply_ms,
-                "apply_launches": t.apply_launches, "precond_ms": t.precond_ms,
-                "precond_launches": t.precond_launches}
+        return {name: getattr(t, name) for name, _ in N.EpTvTiming._fields_}
 
     def ep_tv_init_warm(self, mu_hats, var_hats, lambda_scale: float = 1.0,
                         lambda_power: float = 1.0) -> int:

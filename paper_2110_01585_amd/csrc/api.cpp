@@ -583,7 +583,7 @@ static int enqueue_tv(ep_tv_ctx* c, int par, int em, bool delta, double tol, hip
 }
 
 static int one_sweep(ep_tv_ctx* c, int em, bool delta, double tol) {
-  const bool tm = c->timing && c->ev_used + 4 <= 8192;
+  const bool tm = c->timing && c->ev_used + 4 <= kMaxTimingEvents;
   int i0 = 0, i1 = 0;
   if (c->any_lik) {
     if (tm) HIPCHK(c, hipEventRecord(next_event(c, i0), c->stream));
@@ -1003,13 +1003,23 @@ int ep_tv_get_timing(ep_tv_ctx* c, ep_tv_timing* out) {
     out->lik_ms += ms;
     out->lik_updates += 1;
   }
-  double ams = 0.0, pms = 0.0;
-  int an = 0, pn = 0;
-  HIPCHK(c, lik_timing_read(c->lik, ams, an, pms, pn));
-  out->apply_ms = ams;
-  out->apply_launches = an;
-  out->precond_ms = pms;
-  out->precond_launches = pn;
+  double ms[KT_COUNT] = {};
+  int n[KT_COUNT] = {};
+  HIPCHK(c, lik_timing_read(c->lik, ms, n));
+  out->apply_ms = ms[KT_APPLY];
+  out->apply_launches = n[KT_APPLY];
+  out->precond_ms = ms[KT_PRECOND];
+  out->precond_launches = n[KT_PRECOND];
+  out->rf_fwd_ms = ms[KT_RF_FWD];
+  out->rf_fwd_launches = n[KT_RF_FWD];
+  out->rf_filt_ms = ms[KT_RF_FILT];
+  out->rf_filt_launches = n[KT_RF_FILT];
+  out->rf_inv_ms = ms[KT_RF_INV];
+  out->rf_inv_launches = n[KT_RF_INV];
+  out->fin_ms = ms[KT_FIN];
+  out->fin_launches = n[KT_FIN];
+  out->lik_other_ms = ms[KT_OTHER];
+  out->lik_other_launches = n[KT_OTHER];
   return EP_TV_OK;
 }
 

@@ -967,17 +967,21 @@ hipError_t rfft_cg(LikCtx& lc, int mode, int update, hipStream_t s) {
     RfftArgs f = a;
     f.dst = d.B; f.tw = d.twW; f.nrows = d.H / 2; f.logL = d.logW;
     f.apart = lc.part0 + L.tile0; f.acount = L.fin_count[FIN_ALPHA];
-    hipError_t e = launch_rfft<RF_FWD>(d.W, f, s);
+    hipError_t e = lik_timed(lc, KT_RF_FWD, s, [&]() { return launch_rfft<RF_FWD>(d.W, f, s); });
     if (e != hipSuccess) return e;
     RfftArgs g = a;
     g.src = d.B; g.dst = d.B; g.tw = d.twH; g.nrows = Wh; g.logL = d.logH; g.specT = d.specT;
     g.scale = (float)(1.0 / ((double)d.H * d.W));
-    if ((e = launch_rfft<RF_FILT>(d.H, g, s)) != hipSuccess) return e;
+    if ((e = lik_timed(lc, KT_RF_FILT, s, [&]() { return launch_rfft<RF_FILT>(d.H, g, s); })) !=
+        hipSuccess)
+      return e;
     RfftArgs v = a;
     v.src = d.B; v.tw = d.twW; v.nrows = d.H / 2; v.logL = d.logW;
     v.out = lc.planes[mode == RFM_PRECOND ? LP_Z : LP_Q];
     v.part0 = lc.part0; v.part1 = lc.part1; v.part_base = L.tile0;
-    if ((e = launch_rfft<RF_INV>(d.W, v, s)) != hipSuccess) return e;
+    if ((e = lik_timed(lc, KT_RF_INV, s, [&]() { return launch_rfft<RF_INV>(d.W, v, s); })) !=
+        hipSuccess)
+      return e;
   }
   return hipSuccess;
 }

@@ -184,13 +184,49 @@ struct LikCtx {
   int max_iters = kCgMaxIters;       // largest per-instance CG cap
   InstState* hst = nullptr;          // pinned host staging for CG polls (allocated on first poll)
   int n_all = 0;
-  // timing of H^T H applications
+  // kernel timing (event pairs per bucket, KT_*)
   bool timing = false;
   std::vector<hipEvent_t> ev;
   size_t ev_used = 0;
-  std::vector<std::pair<int, int>> ev_apply;     // products with A inside CG
-  std::vector<std::pair<int, int>> ev_precond;   // fast-CG preconditioner (with the x, r update)
+  std::vector<std::pair<int, int>> ev_k[9];
 };
+
+// Timing buckets of the likelihood-site update.  KT_APPLY and KT_PRECOND each
+// bracket a group of launches (the product with A inside CG; the fast CG's
+// whole preconditioner with its x, r update); the others bracket single
+// launches: the three real-transform passes, the per-instance finishing
+// kernels, and everything else (cavity / right-hand side, spectral sum, CG
+// start, Jacobi kernels, site update).
+enum { KT_APPLY = 0, KT_PRECOND, KT_RF_FWD, KT_RF_FILT, KT_RF_INV, KT_FIN, KT_OTHER, KT_COUNT };
+static_assert(KT_COUNT <= 9, "timing buckets");
+constexpr size_t kMaxTimingEvents = 1u << 17;
+
+// Run `body` between two timing events (when timing is on), recording the pair
+// in bucket `kt`.
+template <class F>
+hipError_t lik_timed(LikCtx& lc, int kt, hipStream_t s, F&& body) {
+  const bool tm = lc.timing && lc.ev_used + 2 <= kMaxTimingEvents;
+  int i0 = 0, i1 = 0;
+  if (tm) {
+    while (lc.ev_used + 2 > lc.ev.size()) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) return hipErrorOutOfMemory;
+      lc.ev.push_back(e);
+    }
+    i0 = (int)lc.ev_used++;
+    i1 = (int)lc.ev_used++;
+    const hipError_t e0 = hipEventRecord(lc.ev[i0], s);
+    if (e0 != hipSuccess) return e0;
+  }
+  hipError_t e = body();
+  if (e != hipSuccess) return e;
+  if (tm) {
+    const hipError_t e1 = hipEventRecord(lc.ev[i1], s);
+    if (e1 != hipSuccess) return e1;
+    lc.ev_k[kt].emplace_back(i0, i1);
+  }
+  return hipGetLastError();
+}
 
 hipError_t lik_create(LikCtx& lc, const LikInstInfo* li, int n, char* ws, const LikLayout& L,
                       long long plane, InstDev* d_inst, InstState* d_st, int4* d_tiles, int ntiles,
@@ -209,6 +245,7 @@ hipError_t lik_poll(LikCtx& lc, hipStream_t s, bool& all_done);
 hipError_t lik_tail(LikCtx& lc, float2* S0, hipStream_t s);
 void lik_destroy(LikCtx& lc);
 void lik_timing(LikCtx& lc, bool enable, bool clear);
-hipError_t lik_timing_read(LikCtx& lc, double& ms, int& launches, double& pms, int& plaunches);
+// Total milliseconds and launch counts per bucket (arrays of KT_COUNT).
+hipError_t lik_timing_read(LikCtx& lc, double* ms, int* launches);
 
 }  // namespace eptv

@@ -950,37 +950,10 @@ static hipError_t launch_apply_blur(LikCtx& lc, int mode, hipStream_t s) {
   return hipGetLastError();
 }
 
-// Run `body` between two timing events (when timing is on), recording the pair
-// in `bucket`.
-template <class F>
-static hipError_t timed(LikCtx& lc, std::vector<std::pair<int, int>>& bucket, hipStream_t s, F&& body) {
-  const bool tm = lc.timing && lc.ev_used + 2 <= 16384;
-  int i0 = 0, i1 = 0;
-  if (tm) {
-    while (lc.ev_used + 2 > lc.ev.size()) {
-      hipEvent_t e;
-      if (hipEventCreate(&e) != hipSuccess) return hipErrorOutOfMemory;
-      lc.ev.push_back(e);
-    }
-    i0 = (int)lc.ev_used++;
-    i1 = (int)lc.ev_used++;
-    const hipError_t e0 = hipEventRecord(lc.ev[i0], s);
-    if (e0 != hipSuccess) return e0;
-  }
-  hipError_t e = body();
-  if (e != hipSuccess) return e;
-  if (tm) {
-    const hipError_t e1 = hipEventRecord(lc.ev[i1], s);
-    if (e1 != hipSuccess) return e1;
-    bucket.emplace_back(i0, i1);
-  }
-  return hipGetLastError();
-}
-
 static hipError_t launch_apply(LikCtx& lc, int mode, hipStream_t s) {
   bool any_dft = false;
   for (const LikInst& d : lc.hinst) any_dft = any_dft || d.op == OP_DFT;
-  return timed(lc, lc.ev_apply, s, [&]() -> hipError_t {
+  return lik_timed(lc, KT_APPLY, s, [&]() -> hipError_t {
     if (any_dft) {
       hipError_t e = dft_apply(lc, mode, s);
       if (e != hipSuccess) return e;
@@ -994,8 +967,20 @@ static hipError_t launch_apply(LikCtx& lc, int mode, hipStream_t s) {
 }
 
 static hipError_t fin(LikCtx& lc, int stage, hipStream_t s) {
-  hipLaunchKernelGGL(k_lik_fin, dim3(lc.nlik), dim3(256), 0, s, make_args(lc), stage);
-  return hipGetLastError();
+  return lik_timed(lc, KT_FIN, s, [&]() {
+    hipLaunchKernelGGL(k_lik_fin, dim3(lc.nlik), dim3(256), 0, s, make_args(lc), stage);
+    return hipGetLastError();
+  });
+}
+
+// One element-wise / reduction kernel of the likelihood update on every tile,
+// timed in the KT_OTHER bucket.
+template <class K, class... Args>
+static hipError_t other(LikCtx& lc, hipStream_t s, K kernel, Args... args) {
+  return lik_timed(lc, KT_OTHER, s, [&]() {
+    hipLaunchKernelGGL(kernel, dim3(lc.ntiles), dim3(256), 0, s, args...);
+    return hipGetLastError();
+  });
 }
 
 hipError_t lik_head(LikCtx& lc, float2* const S[5], hipStream_t s) {
@@ -1003,20 +988,22 @@ hipError_t lik_head(LikCtx& lc, float2* const S[5], hipStream_t s) {
   hipError_t e;
   lc.pcur = 0;   // the first iteration sets p = z whatever the p planes hold
   const dim3 g(lc.ntiles), b(256);
-  hipLaunchKernelGGL(k_lik_prep, g, b, 0, s, make_args(lc), S[0], S[1], S[2], S[3], S[4]);
+  if ((e = other(lc, s, k_lik_prep, make_args(lc), (const float2*)S[0], (const float2*)S[1],
+                 (const float2*)S[2], (const float2*)S[3], (const float2*)S[4])) != hipSuccess)
+    return e;
   if ((e = fin(lc, FIN_PREP, s)) != hipSuccess) return e;
-  hipLaunchKernelGGL(k_lik_spec, g, b, 0, s, make_args(lc));
+  if ((e = other(lc, s, k_lik_spec, make_args(lc))) != hipSuccess) return e;
   if ((e = fin(lc, FIN_SPEC, s)) != hipSuccess) return e;
   if ((e = launch_apply(lc, 0, s)) != hipSuccess) return e;
   bool cg_init_needed = !blur_all_sep(lc);
   for (const LikInst& d : lc.hinst) cg_init_needed = cg_init_needed || d.op != OP_BLUR;
-  if (cg_init_needed) hipLaunchKernelGGL(k_cg_init, g, b, 0, s, make_args(lc));
+  if (cg_init_needed && (e = other(lc, s, k_cg_init, make_args(lc))) != hipSuccess) return e;
   if (lc.fast) {
     if ((e = rfft_precondition(lc, 0, s)) != hipSuccess) return e;
   } else {
     if ((e = fft_precondition(lc, s)) != hipSuccess) return e;
     if ((e = wht_precondition(lc, s)) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_precond_dot, g, b, 0, s, make_args(lc));
+    if ((e = other(lc, s, k_precond_dot, make_args(lc))) != hipSuccess) return e;
   }
   return fin(lc, FIN_INIT, s);
 }
@@ -1029,14 +1016,14 @@ hipError_t lik_iterations(LikCtx& lc, int n, hipStream_t s) {
     for (int it = 0; it < n; ++it) {
       // p_out = z + beta p_in and q = A p_out: blur tiles by the direct
       // H^T H kernel, masked-DFT instances by the real transform
-      e = timed(lc, lc.ev_apply, s, [&]() -> hipError_t {
+      e = lik_timed(lc, KT_APPLY, s, [&]() -> hipError_t {
         hipError_t e2 = launch_apply_blur(lc, 1, s);
         return e2 != hipSuccess ? e2 : rfft_product(lc, s);
       });
       if (e != hipSuccess) return e;
       // alpha = r.z / p.q is formed by every workgroup of the first transform
       // pass from the p.q partials, so no finishing kernel runs in between
-      e = timed(lc, lc.ev_precond, s, [&]() { return rfft_precondition(lc, 1, s); });   // with x, r update
+      e = lik_timed(lc, KT_PRECOND, s, [&]() { return rfft_precondition(lc, 1, s); });   // with x, r update
       if (e != hipSuccess) return e;
       if ((e = fin(lc, FIN_BETA, s)) != hipSuccess) return e;
       lc.pcur ^= 1;
@@ -1046,10 +1033,10 @@ hipError_t lik_iterations(LikCtx& lc, int n, hipStream_t s) {
   for (int it = 0; it < n; ++it) {
     if ((e = launch_apply(lc, 1, s)) != hipSuccess) return e;   // p_out = z + beta p_in, q = A p_out
     if ((e = fin(lc, FIN_ALPHA, s)) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_cg_update, g, b, 0, s, make_args(lc));
+    if ((e = other(lc, s, k_cg_update, make_args(lc))) != hipSuccess) return e;
     if ((e = fft_precondition(lc, s)) != hipSuccess) return e;
     if ((e = wht_precondition(lc, s)) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_precond_dot, g, b, 0, s, make_args(lc));
+    if ((e = other(lc, s, k_precond_dot, make_args(lc))) != hipSuccess) return e;
     if ((e = fin(lc, FIN_BETA, s)) != hipSuccess) return e;
     lc.pcur ^= 1;
   }
@@ -1077,8 +1064,7 @@ hipError_t lik_poll(LikCtx& lc, hipStream_t s, bool& all_done) {
 
 hipError_t lik_tail(LikCtx& lc, float2* S0, hipStream_t s) {
   if (lc.nlik == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_lik_site, dim3(lc.ntiles), dim3(256), 0, s, make_args(lc), S0);
-  return hipGetLastError();
+  return other(lc, s, k_lik_site, make_args(lc), S0);
 }
 
 hipError_t lik_update(LikCtx& lc, float2* const S[5], hipStream_t s) {
@@ -1106,8 +1092,7 @@ void lik_timing(LikCtx& lc, bool enable, bool clear) {
   lc.timing = enable;
   if (clear) {
     lc.ev_used = 0;
-    lc.ev_apply.clear();
-    lc.ev_precond.clear();
+    for (auto& b : lc.ev_k) b.clear();
   }
 }
 
@@ -1124,10 +1109,12 @@ static hipError_t sum_events(LikCtx& lc, const std::vector<std::pair<int, int>>&
   return hipSuccess;
 }
 
-hipError_t lik_timing_read(LikCtx& lc, double& ms, int& launches, double& pms, int& plaunches) {
-  hipError_t e = sum_events(lc, lc.ev_apply, ms, launches);
-  if (e != hipSuccess) return e;
-  return sum_events(lc, lc.ev_precond, pms, plaunches);
+hipError_t lik_timing_read(LikCtx& lc, double* ms, int* launches) {
+  for (int k = 0; k < KT_COUNT; ++k) {
+    hipError_t e = sum_events(lc, lc.ev_k[k], ms[k], launches[k]);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 }  // namespace eptv

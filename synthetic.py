@@ -270,25 +270,26 @@ def config2(size: int = 1024, sweeps: int = 300) -> Problem:
                    sweeps=sweeps, em=True, name=f"cs{size}")
 
 
+def config3_instance(i: int, max_sweeps: int = 200, size_lo: int = 64,
+                     size_hi: int = 1024) -> Problem:
+    """Instance i of the batched mix (its own seed, independent of the others)."""
+    rng = rng_for(3, i)
+    s = int(round(math.exp(rng.uniform(math.log(size_lo), math.log(size_hi)))))
+    shapes = max(3, round(60 * s * s / (512 * 512)))
+    sigma = rng.uniform(0.01, 0.1)
+    if rng.random() < 0.5:
+        return make_denoise(s, s, shapes, sigma, rng, mode="paint", lam0=1.0,
+                            sweeps=max_sweeps, em=True, name=f"b{i}_denoise{s}")
+    sb = rng.uniform(1.0, 3.0)
+    return make_deconv(s, s, shapes, sigma, sb, rng, lam0=1.0, sweeps=max_sweeps,
+                       em=True, name=f"b{i}_deconv{s}")
+
+
 def config3_instances(n_instances: int = 256, max_sweeps: int = 200,
                       size_lo: int = 64, size_hi: int = 1024):
     """Batched mix: sizes round(exp(U[ln lo, ln hi])), 50/50 denoise/deconv,
     sigma_b ~ U[1, 3], sigma ~ U[0.01, 0.1], EM from lambda = 1 per instance."""
-    out = []
-    for i in range(n_instances):
-        rng = rng_for(3, i)
-        s = int(round(math.exp(rng.uniform(math.log(size_lo), math.log(size_hi)))))
-        shapes = max(3, round(60 * s * s / (512 * 512)))
-        sigma = rng.uniform(0.01, 0.1)
-        if rng.random() < 0.5:
-            p = make_denoise(s, s, shapes, sigma, rng, mode="paint", lam0=1.0,
-                             sweeps=max_sweeps, em=True, name=f"b{i}_denoise{s}")
-        else:
-            sb = rng.uniform(1.0, 3.0)
-            p = make_deconv(s, s, shapes, sigma, sb, rng, lam0=1.0, sweeps=max_sweeps,
-                            em=True, name=f"b{i}_deconv{s}")
-        out.append(p)
-    return out
+    return [config3_instance(i, max_sweeps, size_lo, size_hi) for i in range(n_instances)]
 
 
 def config4_train(index: int, size: int = 256) -> Problem:
