@@ -295,7 +295,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-warm", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true",
-                    help="skip the tight reference and the oracle comparison")
+                    help="skip the long reference run and the oracle comparison")
     ap.add_argument("--cg-reduce", type=float, default=0.0,
                     help="also time one cold and one warm solve with this opt-in CG residual "
                          "reduction (0: skip)")
@@ -475,25 +475,28 @@ def warm_solves(ctx, args, em, p, y, dev, torch, conv, mu, var):
     print(f"[bench] warm solves: {conv}", file=sys.stderr, flush=True)
 
 
-def accuracy(ctx, args, em, p, dev, torch, conv, cold, warm):
-    """Both results against a cold solve at a 20x tighter tolerance (run until
-    it converges, up to 10,000 sweeps), and the same GPU path against the FP64
-    oracle on the 512^2 member of the workload family (stored oracle run,
-    tests/golden/deconv512.json: 200 sweeps, 400 sampled pixels)."""
+def accuracy(ctx, args, em, p, dev, torch, conv, cold, warm, ref_sweeps=3000):
+    """Both results against the end of a 3000-sweep cold run (10x the sweeps
+    to converge; the FP32 path's change per sweep settles at about 2.9e-6 of
+    the range, so tolerances below 2.5e-6 are never met and a run to a 100x
+    tighter tolerance does not end), with the last sweep's change reported, and
+    the same GPU path against the FP64 oracle on the 512^2 member of the
+    workload family (stored oracle run, tests/golden/deconv512.json: 200
+    sweeps, 400 sampled pixels)."""
     import numpy as np
     h, w = p.shape
     ctx.ep_tv_init_cold()
     mu_r = torch.empty(h, w, device=dev)
     var_r = torch.empty(h, w, device=dev)
-    rc, st_r = ctx.ep_tv_solve(10000, args.tol / 20, em, [mu_r], [var_r])
+    # a tolerance no sweep meets: exactly ref_sweeps sweeps, with the deltas recorded
+    rc, st_r = ctx.ep_tv_solve(ref_sweeps, 1e-12, em, [mu_r], [var_r])
     torch.cuda.synchronize()
     rng = float(mu_r.max() - mu_r.min())
-    conv["tight_tol"] = args.tol / 20
-    conv["tight_sweeps"] = st_r[0]["sweeps"]
-    conv["tight_converged"] = bool(st_r[0]["converged"])
+    conv["reference"] = {"sweeps": st_r[0]["sweeps"], "last_dmu_range_rel": st_r[0]["dmu"],
+                         "last_dv_rel": st_r[0]["dv"], "lambda": st_r[0]["lambda"]}
     for tag, (m_, v_) in (("cold", cold), ("warm", warm)):
-        conv[f"mean_err_{tag}_vs_tight"] = float((m_ - mu_r).abs().max()) / rng
-        conv[f"var_err_{tag}_vs_tight"] = float((v_ / var_r - 1).abs().max())
+        conv[f"mean_err_{tag}_vs_reference"] = float((m_ - mu_r).abs().max()) / rng
+        conv[f"var_err_{tag}_vs_reference"] = float((v_ / var_r - 1).abs().max())
     # the FP32 path against the FP64 oracle at 512^2
     import synthetic as syn
     from paper_2110_01585_amd import _native as N
