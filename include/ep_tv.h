@@ -110,11 +110,32 @@ typedef struct {
                                   trajectory */
   int32_t prior;               /* EP_TV_PRIOR_*; lambda0 is the L1 lambda (still checked > 0
                                   for the mixtures, which do not use it) */
-  int32_t reserved;            /* 0 */
+  int32_t var_estimator;       /* EP_TV_VAR_*: estimator of diag Cov of the likelihood site's
+                                  tilted distribution (non-identity operators) */
   double prior_omega;          /* MOG2 / BG: omega in (0, 1] */
   double prior_s1sq;           /* MOG2: s1^2 > 0; BG: s^2 > 0 */
   double prior_s2sq;           /* MOG2: s2^2 > 0; BG: unused */
+  int32_t rbmc_samples;        /* EP_TV_VAR_RBMC: samples Ns in [1, 64]; otherwise ignored */
+  int32_t reserved;            /* 0 */
 } ep_tv_problem;
+
+/* Estimators of diag Cov_{P_0}, the tilted variances of the likelihood site
+ * (Sec. III-C, Eq. (tilted_P_1); exact for H = I, where the choice is moot).
+ *  SPECTRAL: the cavity precision replaced by its mean d: the covariance is then
+ *    diagonal in the operator's transform basis with constant diagonal
+ *    c = mean_w 1/(|H(w)|^2/xi + d), and the site precision is 1/c - d at every
+ *    pixel.  Exact at constant cavity; one reduction per sweep.  On small images
+ *    with sparse masks it can make EP diverge (EP_TV_E_DIVERGED).
+ *  RBMC: the simple Rao-Blackwellised Monte Carlo estimator (Siden, Lindgren,
+ *    Bolin, Villani 2018) the paper names for general H: with Q = H^T H/xi +
+ *    diag(tau_c), v_i = 1/Q_ii + (1/Q_ii^2) mean_s (sum_{j!=i} Q_ij x_j^(s))^2
+ *    over Ns samples x^(s) ~ N(0, Q^{-1}), each one CG solve of Q x = z with
+ *    z = H^T e1/sqrt(xi) + sqrt(tau_c) e2 (perturbation-optimisation).  The
+ *    white noise (e1, e2) is an input (ep_tv_set_rbmc_noise), fixed for the
+ *    run, so EP converges to a fixed point of one estimator realisation.
+ *    Unbiased, v_i >= 1/Q_ii; costs Ns extra CG solves per sweep; sweeps are
+ *    launched one by one (EP_TV_OPT_GRAPH does not apply). */
+enum { EP_TV_VAR_SPECTRAL = 0, EP_TV_VAR_RBMC = 1 };
 
 /* Preconditioner of the likelihood-site CG.  CIRCULANT is (H^T H / xi + d I)^{-1}
  * with d the mean cavity precision, applied by FFT; it needs power-of-two sizes
@@ -173,6 +194,17 @@ int ep_tv_create(const ep_tv_problem* p, int32_t n_problems, void* d_workspace,
  *   (u, v) belongs to the u-th row and v-th column Walsh functions); entries
  *   off the mask are ignored.  The data is copied; the caller may reuse y. */
 int ep_tv_set_observation(ep_tv_ctx* ctx, const float* const* d_y);
+
+/* White noise of the RBMC estimator (instances with var_estimator = RBMC),
+ * required before the first sweep of such a context and kept until it is set
+ * again.  d_noise: host array of n_problems device pointers (NULL for instances
+ * without RBMC), each rbmc_samples * (K + H*W) floats: for every sample s, e1
+ * in the observation layout of ep_tv_set_observation (K = H*W floats; for
+ * DFT_MASK K = 2*H*W, interleaved (re, im), both parts N(0, 1)), then e2 (H*W
+ * floats, pixel space), all standard normal draws of the caller.  The data is
+ * copied (as H^T e1 and e2); the sample solutions restart from zero.
+ * Asynchronous. */
+int ep_tv_set_rbmc_noise(ep_tv_ctx* ctx, const float* const* d_noise);
 
 /* Re-run the cold initialisation with the stored observations.  Asynchronous. */
 int ep_tv_init_cold(ep_tv_ctx* ctx);

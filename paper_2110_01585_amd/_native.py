@@ -35,6 +35,8 @@ PRIOR_MOG2 = 1
 PRIOR_BG = 2
 OPT_GRAPH = 1
 OPT_TILE_ROWS = 2
+VAR_SPECTRAL = 0
+VAR_RBMC = 1
 
 STATUS_NAMES = {0: "OK", 1: "W_NOT_CONVERGED", 2: "W_WARM_FALLBACK", -1: "E_ARG", -2: "E_OOM",
                 -3: "E_HIP", -4: "E_NONFINITE", -5: "E_STATE", -6: "E_DIVERGED"}
@@ -50,9 +52,10 @@ class EpTvProblem(ctypes.Structure):
                 ("damping", ctypes.c_double), ("cg_tol", ctypes.c_double),
                 ("cg_max_iters", ctypes.c_int32), ("cg_precond", ctypes.c_int32),
                 ("cg_reduce", ctypes.c_double),
-                ("prior", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("prior", ctypes.c_int32), ("var_estimator", ctypes.c_int32),
                 ("prior_omega", ctypes.c_double), ("prior_s1sq", ctypes.c_double),
-                ("prior_s2sq", ctypes.c_double)]
+                ("prior_s2sq", ctypes.c_double),
+                ("rbmc_samples", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class EpTvStats(ctypes.Structure):
@@ -96,6 +99,7 @@ SIGNATURES = {
                                     _P, ctypes.POINTER(_P)]),
     "ep_tv_set_observation": (ctypes.c_int, [_P, _FPP]),
     "ep_tv_init_cold": (ctypes.c_int, [_P]),
+    "ep_tv_set_rbmc_noise": (ctypes.c_int, [_P, _FPP]),
     "ep_tv_run": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32]),
     "ep_tv_em_step": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.POINTER(ctypes.c_double)]),
     "ep_tv_solve": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_double, ctypes.c_int32, _FPP, _FPP,

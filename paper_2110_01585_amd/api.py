@@ -41,6 +41,8 @@ class ProblemSpec:
     prior_omega: float = 1.0
     prior_s1sq: float = 1.0
     prior_s2sq: float = 1.0
+    var_estimator: int = N.VAR_SPECTRAL
+    rbmc_samples: int = 0
 
 
 _OPS = {"identity": N.OP_IDENTITY, "blur": N.OP_BLUR_PERIODIC, "dft": N.OP_DFT_MASK,
@@ -49,8 +51,9 @@ _BNDS = {"free": N.BND_FREE, "periodic": N.BND_PERIODIC}
 
 
 def spec_from_synthetic(p, lam0=None, damping=None, cg_tol=0.0, cg_max_iters=0,
-                        cg_precond=N.PRECOND_AUTO, cg_reduce=0.0) -> ProblemSpec:
-    """ProblemSpec of a synthetic.Problem (same fields, C enums)."""
+                        cg_precond=N.PRECOND_AUTO, cg_reduce=0.0, rbmc_samples=0) -> ProblemSpec:
+    """ProblemSpec of a synthetic.Problem (same fields, C enums); rbmc_samples > 0
+    selects the RBMC variance estimator with that many samples."""
     h, w = p.shape
     return ProblemSpec(h, w, _OPS[p.op], _BNDS[p.boundary], float(p.xi),
                        float(p.lam0 if lam0 is None else lam0),
@@ -58,7 +61,9 @@ def spec_from_synthetic(p, lam0=None, damping=None, cg_tol=0.0, cg_max_iters=0,
                        taps=None if p.taps is None else np.asarray(p.taps, np.float32),
                        mask=None if p.mask is None else np.asarray(p.mask, np.uint8),
                        cg_tol=cg_tol, cg_max_iters=cg_max_iters, cg_precond=cg_precond,
-                       cg_reduce=cg_reduce)
+                       cg_reduce=cg_reduce,
+                       var_estimator=N.VAR_RBMC if rbmc_samples else N.VAR_SPECTRAL,
+                       rbmc_samples=int(rbmc_samples))
 
 
 def _problems(specs: Sequence[ProblemSpec]):
@@ -71,6 +76,7 @@ def _problems(specs: Sequence[ProblemSpec]):
         a.cg_tol, a.cg_max_iters, a.cg_precond = s.cg_tol, s.cg_max_iters, s.cg_precond
         a.cg_reduce = s.cg_reduce
         a.prior, a.prior_omega, a.prior_s1sq, a.prior_s2sq = s.prior, s.prior_omega, s.prior_s1sq, s.prior_s2sq
+        a.var_estimator, a.rbmc_samples = s.var_estimator, s.rbmc_samples
         if s.taps is not None:
             t = np.ascontiguousarray(s.taps, dtype=np.float32)
             keep.append(t)
@@ -198,6 +204,16 @@ class Context:
               for y, s in zip(ys, self.specs)]
         self._y = ys
         return self._check(N.lib().ep_tv_set_observation(self.handle, _ptrs(ys)), "set_observation")
+
+    def ep_tv_set_rbmc_noise(self, noises):
+        """noises: per instance a contiguous float32 device tensor of
+        rbmc_samples * (K + H*W) values (layout in include/ep_tv.h), or None."""
+        for t, s in zip(noises, self.specs):
+            if t is None or s.rbmc_samples == 0 or s.op == N.OP_IDENTITY:
+                continue
+            k = s.height * s.width * (2 if s.op == N.OP_DFT_MASK else 1)
+            self._dev(t, (s.rbmc_samples * (k + s.height * s.width),))
+        return self._check(N.lib().ep_tv_set_rbmc_noise(self.handle, _ptrs(noises)), "set_rbmc_noise")
 
     def ep_tv_init_cold(self):
         return self._check(N.lib().ep_tv_init_cold(self.handle), "init_cold")

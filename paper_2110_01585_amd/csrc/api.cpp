@@ -115,6 +115,10 @@ const char* validate(const ep_tv_problem& p) {
       return "prior_s2sq must be > 0";
   }
   if (p.cg_max_iters < 0 || p.cg_max_iters > 100000) return "cg_max_iters must be in [0, 100000]";
+  if (p.var_estimator != EP_TV_VAR_SPECTRAL && p.var_estimator != EP_TV_VAR_RBMC)
+    return "var_estimator must be one of EP_TV_VAR_*";
+  if (p.var_estimator == EP_TV_VAR_RBMC && (p.rbmc_samples < 1 || p.rbmc_samples > 64))
+    return "rbmc_samples must be in [1, 64]";
   if (p.cg_precond < EP_TV_PRECOND_AUTO || p.cg_precond > EP_TV_PRECOND_CIRCULANT)
     return "cg_precond must be one of EP_TV_PRECOND_*";
   if (p.cg_precond == EP_TV_PRECOND_CIRCULANT && p.op != EP_TV_OP_IDENTITY &&
@@ -138,6 +142,11 @@ const char* validate(const ep_tv_problem& p) {
       return "Walsh-Hadamard operator needs power-of-two sizes in [4, 4096]";
   }
   return nullptr;
+}
+
+// RBMC samples of an instance (0: the spectral estimator, or H = I).
+int rbmc_ns(const ep_tv_problem& p) {
+  return (p.op != EP_TV_OP_IDENTITY && p.var_estimator == EP_TV_VAR_RBMC) ? p.rbmc_samples : 0;
 }
 
 void make_layout(std::vector<InstHost>& ih, int rows, Layout& L) {
@@ -183,6 +192,7 @@ void make_layout(std::vector<InstHost>& ih, int rows, Layout& L) {
     li[i].th = ih[i].p.op == EP_TV_OP_BLUR_PERIODIC ? ih[i].p.blur_h : 0;
     li[i].tw = ih[i].p.op == EP_TV_OP_BLUR_PERIODIC ? ih[i].p.blur_w : 0;
     li[i].precond_req = ih[i].p.cg_precond;
+    li[i].rbmc_ns = rbmc_ns(ih[i].p);
   }
   lik_layout(li.data(), n, L.plane, take, L.lik);
   L.total = cur;
@@ -233,6 +243,7 @@ struct ep_tv_ctx {
   bool has_obs = false;
   bool any_lik = false;
   bool warm_started = false;         // init_warm / set_sites since the last cold start
+  bool rbmc_noise_set = false;       // RBMC contexts: white noise uploaded
   std::vector<InstState> host_st;
   InstState* pull_st = nullptr;      // pinned host staging for state pulls (allocated on first pull)
   std::vector<float*> tab_host0, tab_host1;
@@ -472,6 +483,7 @@ int ep_tv_create(const ep_tv_problem* p, int32_t n, void* d_ws, size_t ws_bytes,
       li[i].th = c->ih[i].p.blur_h;
       li[i].tw = c->ih[i].p.blur_w;
       li[i].mask = c->ih[i].mask.empty() ? nullptr : c->ih[i].mask.data();
+      li[i].rbmc_ns = rbmc_ns(c->ih[i].p);
       li[i].tile0 = c->ih[i].tile0;
       li[i].ntiles = c->ih[i].ntiles;
     }
@@ -560,6 +572,16 @@ int ep_tv_set_observation(ep_tv_ctx* c, const float* const* d_y) {
   HIPCHK(c, lik_set_observation(c->lik, d_y, c->stream));
   c->has_obs = true;
   return ep_tv_init_cold(c);
+}
+
+int ep_tv_set_rbmc_noise(ep_tv_ctx* c, const float* const* d_noise) {
+  if (!c || !d_noise) return EP_TV_E_ARG;
+  if (!c->lik.rbmc_ns_max) return fail(c, EP_TV_E_ARG, "no instance uses the RBMC estimator");
+  for (int i = 0; i < c->n; ++i)
+    if (rbmc_ns(c->ih[i].p) && !d_noise[i]) return fail(c, EP_TV_E_ARG, "null RBMC noise pointer");
+  HIPCHK(c, lik_set_rbmc_noise(c->lik, d_noise, c->stream));
+  c->rbmc_noise_set = true;
+  return EP_TV_OK;
 }
 
 static CurSites sites_at(const ep_tv_ctx* c, int par) {
@@ -692,9 +714,12 @@ static int graph_sweep(ep_tv_ctx* c) {
   return EP_TV_OK;
 }
 
-// Run n sweeps with the given finalisation settings (direct launches or graphs).
+// Run n sweeps with the given finalisation settings (direct launches or graphs;
+// RBMC sample solves are launched directly).
 static int advance(ep_tv_ctx* c, int n, int em, bool delta, double tol) {
-  if (!c->use_graph) {
+  if (c->lik.rbmc_ns_max && !c->rbmc_noise_set)
+    return fail(c, EP_TV_E_STATE, "the RBMC estimator needs ep_tv_set_rbmc_noise first");
+  if (!c->use_graph || c->lik.rbmc_ns_max) {
     for (int t = 0; t < n; ++t) {
       int rc = one_sweep(c, em, delta, tol);
       if (rc) return rc;
@@ -739,6 +764,8 @@ static int pull_states(ep_tv_ctx* c) {
 int ep_tv_em_step(ep_tv_ctx* c, int32_t n_ep, double* lambda_out) {
   if (!c || n_ep < 1) return EP_TV_E_ARG;
   if (!c->has_obs) return fail(c, EP_TV_E_STATE, "no observation set");
+  if (c->lik.rbmc_ns_max && !c->rbmc_noise_set)
+    return fail(c, EP_TV_E_STATE, "the RBMC estimator needs ep_tv_set_rbmc_noise first");
   if (c->sa.prior != PRIOR_L1) return fail(c, EP_TV_E_ARG, "EM is defined for the l1 factor only");
   for (int t = 0; t < n_ep; ++t) {
     int rc = one_sweep(c, t == n_ep - 1 ? 1 : 0, false, 0.0);

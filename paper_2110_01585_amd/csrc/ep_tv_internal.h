@@ -54,7 +54,7 @@ struct InstState {
   int cg_it, x_valid, warm, warm_ok;   // warm: sites were set from a prediction (no skipped q0)
   int xprev_valid, restart;            // restart: cold re-initialisation pending (host-set)
   double yscale;                       // max(range, max |.|) of the pixel-space observation
-  int cold_restarts, pad2_;            // automatic cold restarts after a failed warm start
+  int cold_restarts, xs_valid;         // xs_valid: the RBMC sample solutions hold the last solves
 };
 
 // FLAG_DIVERGED: the global mean after a likelihood-site update left

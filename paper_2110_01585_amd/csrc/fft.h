@@ -14,6 +14,9 @@ namespace eptv {
 hipError_t dft_setup(LikCtx& lc, const LikInstInfo* li, int n, size_t fft_bytes, hipStream_t s,
                      std::string& err);
 hipError_t dft_set_observation(LikCtx& lc, const float* const* d_y, hipStream_t s);
+// H^T v of the masked-DFT instance with likelihood index li (v: interleaved
+// complex observation-space array) into the pixel plane `out`
+hipError_t dft_back_project_inst(LikCtx& lc, int li, const float* v, float* out, hipStream_t s);
 // mode 0: q = A x; mode 1: p_out = z + beta p_in, q = A p_out (with v.q partials)
 hipError_t dft_apply(LikCtx& lc, int mode, hipStream_t s);
 void dft_destroy(LikCtx& lc);

@@ -864,26 +864,40 @@ static hipError_t inverse_from_B(DftPlan& d, FftArgs post, hipStream_t s) {
   return rows(r, s);
 }
 
+// H^T v = Re(F^H diag(mask) v) = Re(IDFT(mask v)) / sqrt(N) of a complex
+// observation-space array v (interleaved re, im) into the pixel plane `out`.
+// The masked array is copied into A (a row pass without stages is a plain
+// copy), transposed into B and inverse-transformed.
+static hipError_t dft_back_project(LikCtx& lc, DftPlan& d, const float* v, float* out, hipStream_t s) {
+  const LikInst& L = lc.hinst[d.li];
+  const double N = (double)d.H * d.W;
+  FftArgs a = base_args(lc, L);
+  a.pre = PRE_OBS; a.obs = v; a.mask = d.mask;
+  a.dst = d.A; a.tw = d.twW; a.nrows = d.H; a.L = d.W; a.logL = 0; a.post = POST_COMPLEX;
+  hipError_t e = rows(a, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_transpose, dim3((d.W + kTrT - 1) / kTrT, (d.H + kTrT - 1) / kTrT), dim3(256), 0, s, d.A,
+                     d.B, d.H, d.W, nullptr, 0);
+  FftArgs post = base_args(lc, L);
+  post.post = POST_REAL;
+  post.real_out = out;
+  post.scale = (float)(1.0 / std::sqrt(N));
+  return inverse_from_B(d, post, s);
+}
+
+hipError_t dft_back_project_inst(LikCtx& lc, int li, const float* v, float* out, hipStream_t s) {
+  for (DftPlan& d : lc.dft)
+    if (d.li == li) return dft_back_project(lc, d, v, out, s);
+  return hipErrorInvalidValue;
+}
+
 hipError_t dft_set_observation(LikCtx& lc, const float* const* d_y, hipStream_t s) {
   for (DftPlan& d : lc.dft) {
     const LikInst& L = lc.hinst[d.li];
     if (L.op != OP_DFT) continue;
-    const double N = (double)d.H * d.W;
-    // H^T y = Re(F^H diag(mask) y) = Re(IDFT(mask y)) / sqrt(N), then y_pix = H^T y.
-    // The masked observation is copied into A (a row pass without stages is a
-    // plain copy), transposed into B and inverse-transformed.
-    FftArgs a = base_args(lc, L);
-    a.pre = PRE_OBS; a.obs = d_y[L.inst]; a.mask = d.mask;
-    a.dst = d.A; a.tw = d.twW; a.nrows = d.H; a.L = d.W; a.logL = 0; a.post = POST_COMPLEX;
-    hipError_t e = rows(a, s);
+    // H^T y, then y_pix = H^T y
+    hipError_t e = dft_back_project(lc, d, d_y[L.inst], lc.planes[LP_HTY], s);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_transpose, dim3((d.W + kTrT - 1) / kTrT, (d.H + kTrT - 1) / kTrT), dim3(256), 0, s, d.A,
-                       d.B, d.H, d.W, nullptr, 0);
-    FftArgs post = base_args(lc, L);
-    post.post = POST_REAL;
-    post.real_out = lc.planes[LP_HTY];
-    post.scale = (float)(1.0 / std::sqrt(N));
-    if ((e = inverse_from_B(d, post, s)) != hipSuccess) return e;
     // the cold start and the observation range use H^T y as the pixel-space observation
     e = hipMemcpy2DAsync(lc.ypix + L.off, sizeof(float) * L.pitch, lc.planes[LP_HTY] + L.off,
                          sizeof(float) * L.pitch, sizeof(float) * L.W, L.H,

@@ -40,6 +40,7 @@ struct LikInstInfo {
   double cg_reduce = 0.0;
   int cg_max_iters = kCgMaxIters;
   int precond_req = PRECOND_REQ_AUTO;
+  int rbmc_ns = 0;           // RBMC samples of the variance estimator (0: spectral)
   const float* taps = nullptr;
   int th = 0, tw = 0;
   const uint8_t* mask = nullptr;
@@ -48,7 +49,7 @@ struct LikInstInfo {
 
 // Device description of one instance with a non-identity operator.
 // stages of the per-instance finishing kernel (index into LikInst::fin_count)
-enum { FIN_PREP = 0, FIN_SPEC, FIN_INIT, FIN_ALPHA, FIN_BETA };
+enum { FIN_PREP = 0, FIN_SPEC, FIN_INIT, FIN_ALPHA, FIN_BETA, FIN_SAMPLE, FIN_COUNT };
 
 struct LikInst {
   int H, W, pitch, op;
@@ -63,11 +64,14 @@ struct LikInst {
   int cg_max_iters;
   int precond;               // PRECOND_JACOBI or PRECOND_CIRCULANT
   int npart;                 // partial-sum slots of the real-transform passes (fast CG)
-  int fin_count[5];          // partial sums each finalisation stage reduces (set on the host)
+  int fin_count[FIN_COUNT];  // partial sums each finalisation stage reduces (set on the host)
+  int rbmc_ns;               // RBMC samples (0: spectral variance estimator)
+  float inv_sqrt_xi;
 };
 
 enum {
-  LP_HTY = 0, LP_TAUC, LP_ETAC, LP_B, LP_X, LP_R, LP_Z, LP_P0, LP_P1, LP_Q, LP_SPEC, LP_XPREV, LP_COUNT
+  LP_HTY = 0, LP_TAUC, LP_ETAC, LP_B, LP_X, LP_R, LP_Z, LP_P0, LP_P1, LP_Q, LP_SPEC, LP_XPREV,
+  LP_ACC, LP_ESAVE, LP_COUNT   // RBMC: sum of squared off-diagonal terms, the mean solve's E
 };
 
 enum { PRECOND_JACOBI = 0, PRECOND_CIRCULANT = 1 };
@@ -87,6 +91,10 @@ inline bool lik_uses_fft(int op, int H, int W, int req) {
 struct LikLayout {
   size_t planes[LP_COUNT]{};
   int nplanes = 0;
+  // RBMC planes, rbmc_ns_max of each: H^T e1 of every sample (unscaled), the
+  // pixel-space noise e2, and the sample's last solution (the next CG start)
+  int rbmc_ns_max = 0;
+  size_t rbmc_g = 0, rbmc_e2 = 0, rbmc_x = 0;
   size_t inst = 0, tiles = 0, part0 = 0, part1 = 0, part_mu = 0, taps = 0, fft = 0;
   int nlik = 0, ntiles = 0, ntaps = 0;
   size_t fft_bytes = 0;
@@ -110,8 +118,16 @@ template <class Take>
 void lik_layout(const LikInstInfo* li, int n, long long plane, Take&& take, LikLayout& L) {
   long long fft_elems = 0;
   lik_counts(li, n, L.nlik, L.ntiles, L.ntaps, fft_elems);
-  L.nplanes = L.nlik ? LP_COUNT : 0;
+  L.rbmc_ns_max = 0;
+  for (int i = 0; i < n; ++i)
+    if (li[i].op != OP_IDENTITY) L.rbmc_ns_max = std::max(L.rbmc_ns_max, li[i].rbmc_ns);
+  L.nplanes = L.nlik ? (L.rbmc_ns_max ? LP_COUNT : LP_ACC) : 0;
   for (int k = 0; k < L.nplanes; ++k) L.planes[k] = take(sizeof(float) * (size_t)plane);
+  if (L.rbmc_ns_max) {
+    L.rbmc_g = take(sizeof(float) * (size_t)plane * L.rbmc_ns_max);
+    L.rbmc_e2 = take(sizeof(float) * (size_t)plane * L.rbmc_ns_max);
+    L.rbmc_x = take(sizeof(float) * (size_t)plane * L.rbmc_ns_max);
+  }
   L.inst = take(sizeof(LikInst) * (size_t)std::max(L.nlik, 1));
   L.tiles = take(sizeof(int4) * (size_t)std::max(L.ntiles, 1));
   L.part0 = take(sizeof(double) * (size_t)std::max(L.ntiles, 1));
@@ -179,7 +195,13 @@ struct LikCtx {
   InstState* d_st = nullptr;
   const InstDev* d_idev = nullptr;
   float* ypix = nullptr;
+  long long plane = 0;               // elements per plane
+  int rbmc_ns_max = 0;               // RBMC: largest sample count of any instance (0: none)
+  float* rbmc_g = nullptr;           // rbmc_ns_max planes each
+  float* rbmc_e2 = nullptr;
+  float* rbmc_x = nullptr;
   int pcur = 0;                      // which p plane holds the current search direction
+  int sample = 0;                    // RBMC sample whose planes the kernels address
   bool fast = false;                 // every instance circulant: CG products and preconditioner by real FFTs
   int max_iters = kCgMaxIters;       // largest per-instance CG cap
   InstState* hst = nullptr;          // pinned host staging for CG polls (allocated on first poll)
@@ -243,6 +265,10 @@ hipError_t lik_head(LikCtx& lc, float2* const S[5], hipStream_t s);
 hipError_t lik_iterations(LikCtx& lc, int n, hipStream_t s);
 hipError_t lik_poll(LikCtx& lc, hipStream_t s, bool& all_done);
 hipError_t lik_tail(LikCtx& lc, float2* S0, hipStream_t s);
+// RBMC: the white noise of every RBMC instance (host array of device pointers,
+// one per instance of the context; NULL for instances without RBMC): H^T e1 and
+// e2 of every sample into the workspace.  The sample solutions restart from 0.
+hipError_t lik_set_rbmc_noise(LikCtx& lc, const float* const* d_noise, hipStream_t s);
 void lik_destroy(LikCtx& lc);
 void lik_timing(LikCtx& lc, bool enable, bool clear);
 // Total milliseconds and launch counts per bucket (arrays of KT_COUNT).

@@ -46,7 +46,23 @@ struct LikArgs {
   float* hty; float* tauc; float* etac; float* b; float* x; float* r; float* z;
   float* p_in; float* p_out; float* q; float* spec; float* xprev;
   int r_from_apply;          // the separable H^T H kernel writes the CG start r = b - A x itself
+  // RBMC: accumulated squared off-diagonal sums, the mean solve's E, and the
+  // planes of the current sample (H^T e1, e2, last solution)
+  float* acc; float* esave;
+  const float* g_s; const float* e2_s; float* xs_s;
+  int sample;
 };
+
+// The likelihood site is updated in this sweep (every sweep but the first of a
+// cold start, on active instances).
+__device__ __forceinline__ bool lik_now(const InstState& st) {
+  return st.active && (st.sweeps > 0 || st.warm);
+}
+
+// Instance L solves for RBMC sample `s` in this sweep.
+__device__ __forceinline__ bool rbmc_now(const LikInst& L, const InstState& st, int s) {
+  return L.rbmc_ns > s && lik_now(st);
+}
 
 // Deterministic block sum of two doubles (256 threads): a butterfly over the
 // 64 lanes of each wave (every lane ends with the same bits, since each step
@@ -239,6 +255,16 @@ __global__ __launch_bounds__(256) void k_lik_fin(LikArgs A, int stage) {
     case FIN_ALPHA:
       if (st.cg_done) break;
       st.cg_alpha = (r0 != 0.0) ? st.cg_rz / r0 : 0.0;
+      break;
+    case FIN_SAMPLE:
+      // start of the CG solve of RBMC sample A.sample: ||b||^2 of its right-hand side
+      if (!rbmc_now(L, st, A.sample)) {
+        st.cg_done = 1;
+        break;
+      }
+      st.cg_bb = r1;
+      st.cg_it = 0;
+      st.cg_done = 0;
       break;
     case FIN_BETA:
       if (st.cg_done) break;
@@ -644,14 +670,43 @@ __global__ __launch_bounds__(256) void k_lik_site(LikArgs A, float2* __restrict_
     if (threadIdx.x == 0) A.part_mu[tile] = 0.f;
     return;
   }
+  const TileXY t = lik_tile(td, L);
+  const float a = L.alpha;
+  if (L.rbmc_ns) {
+    // RBMC: per-pixel tilted variance V = 1/Q_ii + acc / (Ns Q_ii^2), Q_ii = diag
+    // (H^T H)/xi + tau_c; E is the mean solve's, restored into x for the next
+    // sweep's CG start
+    if (tile == L.tile0 && threadIdx.x == 0) st.xs_valid = 1;
+    const double inv_ns = 1.0 / (double)L.rbmc_ns;
+    float tcv[kTileItems], ev[kTileItems], ecv[kTileItems], acv[kTileItems];
+    float2 ov[kTileItems];
+    float mx = 0.f;
+    tile_two_phase<true>(
+        t, L,
+        [&](int u, long long p) {
+          tcv[u] = A.tauc[p]; ev[u] = A.esave[p]; ecv[u] = A.etac[p]; acv[u] = A.acc[p]; ov[u] = S0[p];
+        },
+        [&](int u, long long p) {
+          const double q = (double)L.diagA + (double)tcv[u];
+          const double v = 1.0 / q + (double)acv[u] * inv_ns / (q * q);
+          double tn = 1.0 / v - (double)tcv[u];
+          if (!(tn >= (double)kPrecFloor)) tn = (double)kPrecFloor;
+          const float tau_new = (float)tn;
+          const float eta_new = (float)((tn + (double)tcv[u]) * (double)ev[u] - (double)ecv[u]);
+          const float2 s0 = make_float2(a * tau_new + (1.f - a) * ov[u].x, a * eta_new + (1.f - a) * ov[u].y);
+          S0[p] = s0;
+          A.x[p] = ev[u];
+          mx = fmaxf(mx, fabsf((s0.y + ecv[u]) / (s0.x + tcv[u])));
+        });
+    block_max(mx, &A.part_mu[tile]);
+    return;
+  }
   if (tile == L.tile0 && threadIdx.x == 0) {
     st.cg_last = st.cg_it;
     st.cg_total += st.cg_it;
   }
-  const TileXY t = lik_tile(td, L);
   float tau_new = (float)st.gamma;
   if (!(tau_new >= kPrecFloor)) tau_new = kPrecFloor;
-  const float a = L.alpha;
   float tcv[kTileItems], xv[kTileItems], ecv[kTileItems];
   float2 ov[kTileItems];
   float mx = 0.f;
@@ -665,6 +720,87 @@ __global__ __launch_bounds__(256) void k_lik_site(LikArgs A, float2* __restrict_
         mx = fmaxf(mx, fabsf((s0.y + ecv[u]) / (s0.x + tcv[u])));
       });
   block_max(mx, &A.part_mu[tile]);
+}
+
+// ---------------------------------------------------------------------------
+// RBMC variance estimator (Siden et al. 2018, named for general H in Sec.
+// III-C): after the mean solve, each sample s solves Q x = z with
+// z = H^T e1 / sqrt(xi) + sqrt(tau_c) e2 ~ N(0, Q) (perturbation-optimisation),
+// then sum_{j != i} Q_ij x_j = (Q x)_i - Q_ii x_i = b_i - r_i - Q_ii x_i is
+// squared into acc.  The mean solve's E is kept aside meanwhile.
+
+// 8a. keep E, clear the accumulator
+__global__ __launch_bounds__(256) void k_rbmc_begin(LikArgs A) {
+  const int tile = blockIdx.x;
+  const int4 td = A.tiles[tile];
+  const LikInst L = A.inst[td.x];
+  InstState& st = A.st[L.inst];
+  if (!rbmc_now(L, st, 0)) return;
+  if (tile == L.tile0 && threadIdx.x == 0) {   // the mean solve's iterations
+    st.cg_last = st.cg_it;
+    st.cg_total += st.cg_it;
+  }
+  const TileXY t = lik_tile(td, L);
+  float xv[kTileItems];
+  tile_two_phase<true>(
+      t, L, [&](int u, long long p) { xv[u] = A.x[p]; },
+      [&](int u, long long p) {
+        A.esave[p] = xv[u];
+        A.acc[p] = 0.f;
+      });
+}
+
+// 8b. right-hand side of sample A.sample and its CG start (the sample's last
+//     solution, or 0), with the ||b||^2 partials
+__global__ __launch_bounds__(256) void k_rbmc_rhs(LikArgs A) {
+  const int tile = blockIdx.x;
+  const int4 td = A.tiles[tile];
+  const LikInst L = A.inst[td.x];
+  const InstState& st = A.st[L.inst];
+  double bb = 0.0;
+  if (rbmc_now(L, st, A.sample)) {
+    const TileXY t = lik_tile(td, L);
+    const bool start = st.xs_valid;
+    const float isx = L.inv_sqrt_xi;
+    float gv[kTileItems], ev[kTileItems], tv[kTileItems], xv[kTileItems];
+    tile_two_phase<true>(
+        t, L,
+        [&](int u, long long p) {
+          gv[u] = A.g_s[p]; ev[u] = A.e2_s[p]; tv[u] = A.tauc[p];
+          if (start) xv[u] = A.xs_s[p];
+        },
+        [&](int u, long long p) {
+          const float bv = (float)((double)gv[u] * (double)isx + sqrt((double)tv[u]) * (double)ev[u]);
+          A.b[p] = bv;
+          A.x[p] = start ? xv[u] : 0.f;
+          bb += (double)bv * (double)bv;
+        });
+  }
+  block_sum2(0.0, bb, &A.part0[tile], &A.part1[tile]);
+}
+
+// 8c. after the sample's solve: keep its solution, accumulate the squared
+//     off-diagonal sum
+__global__ __launch_bounds__(256) void k_rbmc_acc(LikArgs A) {
+  const int tile = blockIdx.x;
+  const int4 td = A.tiles[tile];
+  const LikInst L = A.inst[td.x];
+  InstState& st = A.st[L.inst];
+  if (!rbmc_now(L, st, A.sample)) return;
+  if (tile == L.tile0 && threadIdx.x == 0) st.cg_total += st.cg_it;
+  const TileXY t = lik_tile(td, L);
+  float xv[kTileItems], bv[kTileItems], rv[kTileItems], tv[kTileItems], av[kTileItems];
+  tile_two_phase<true>(
+      t, L,
+      [&](int u, long long p) {
+        xv[u] = A.x[p]; bv[u] = A.b[p]; rv[u] = A.r[p]; tv[u] = A.tauc[p]; av[u] = A.acc[p];
+      },
+      [&](int u, long long p) {
+        const double q = (double)L.diagA + (double)tv[u];
+        const double off = (double)bv[u] - (double)rv[u] - q * (double)xv[u];
+        A.xs_s[p] = xv[u];
+        A.acc[p] = (float)((double)av[u] + off * off);
+      });
 }
 
 // ---------------------------------------------------------------------------
@@ -753,13 +889,20 @@ static LikArgs make_args(LikCtx& lc) {
   A.q = lc.planes[LP_Q];
   A.spec = lc.planes[LP_SPEC];
   A.xprev = lc.planes[LP_XPREV];
+  A.acc = lc.planes[LP_ACC];
+  A.esave = lc.planes[LP_ESAVE];
+  A.sample = lc.sample;
+  const size_t off = (size_t)lc.plane * (size_t)lc.sample;
+  A.g_s = lc.rbmc_g ? lc.rbmc_g + off : nullptr;
+  A.e2_s = lc.rbmc_e2 ? lc.rbmc_e2 + off : nullptr;
+  A.xs_s = lc.rbmc_x ? lc.rbmc_x + off : nullptr;
   return A;
 }
 
 hipError_t lik_create(LikCtx& lc, const LikInstInfo* li, int n, char* ws, const LikLayout& L,
                       long long plane, InstDev* d_inst, InstState* d_st, int4* d_tiles, int ntiles,
                       float* ypix, hipStream_t s, std::string& err) {
-  (void)plane; (void)d_tiles; (void)ntiles;
+  (void)d_tiles; (void)ntiles;
   lc = LikCtx();
   lc.n_all = n;
   lc.nlik = L.nlik;
@@ -768,7 +911,15 @@ hipError_t lik_create(LikCtx& lc, const LikInstInfo* li, int n, char* ws, const 
   lc.d_idev = d_inst;
   lc.ypix = ypix;
   if (lc.nlik == 0) return hipSuccess;
-  for (int k = 0; k < LP_COUNT; ++k) lc.planes[k] = reinterpret_cast<float*>(ws + L.planes[k]);
+  for (int k = 0; k < LP_COUNT; ++k)
+    lc.planes[k] = k < L.nplanes ? reinterpret_cast<float*>(ws + L.planes[k]) : nullptr;
+  lc.plane = plane;
+  lc.rbmc_ns_max = L.rbmc_ns_max;
+  if (L.rbmc_ns_max) {
+    lc.rbmc_g = reinterpret_cast<float*>(ws + L.rbmc_g);
+    lc.rbmc_e2 = reinterpret_cast<float*>(ws + L.rbmc_e2);
+    lc.rbmc_x = reinterpret_cast<float*>(ws + L.rbmc_x);
+  }
   lc.d_inst = reinterpret_cast<LikInst*>(ws + L.inst);
   lc.d_tiles = reinterpret_cast<int4*>(ws + L.tiles);
   lc.part0 = reinterpret_cast<double*>(ws + L.part0);
@@ -790,6 +941,8 @@ hipError_t lik_create(LikCtx& lc, const LikInstInfo* li, int n, char* ws, const 
     const int ty = (I.H + kLikTH - 1) / kLikTH;
     d.ntiles = d.tiles_x * ty;
     d.inv_xi = (float)(1.0 / I.xi);
+    d.inv_sqrt_xi = (float)(1.0 / std::sqrt(I.xi));
+    d.rbmc_ns = I.rbmc_ns;
     d.alpha = (float)I.damping;
     d.cg_tol2 = I.cg_tol * I.cg_tol;
     d.cg_reduce2 = I.cg_reduce * I.cg_reduce;
@@ -869,6 +1022,7 @@ hipError_t lik_create(LikCtx& lc, const LikInstInfo* li, int n, char* ws, const 
     d.fin_count[FIN_ALPHA] = (lc.fast && d.op == OP_DFT) ? d.npart : d.ntiles;
     if (d.op == OP_HAD) d.fin_count[FIN_ALPHA] = wht_partials(d.H, d.W);   // from the last transform pass
     d.fin_count[FIN_BETA] = tr;
+    d.fin_count[FIN_SAMPLE] = d.ntiles;
   }
   if ((int)taps.size() > L.ntaps || (int)tiles.size() != L.ntiles) {
     err = "likelihood layout mismatch (taps or tiles)";
@@ -906,6 +1060,50 @@ hipError_t lik_set_observation(LikCtx& lc, const float* const* d_y, hipStream_t 
 
 static hipError_t set_x_invalid(LikCtx& lc, hipStream_t s);
 
+// Floats of one instance's observation: H x W, complex (two floats) for the DFT.
+static long long obs_floats(const LikInst& L) {
+  return (long long)L.H * L.W * (L.op == OP_DFT ? 2 : 1);
+}
+
+hipError_t lik_set_rbmc_noise(LikCtx& lc, const float* const* d_noise, hipStream_t s) {
+  if (lc.nlik == 0 || lc.rbmc_ns_max == 0) return hipSuccess;
+  hipError_t e;
+  for (int k = 0; k < lc.rbmc_ns_max; ++k) {
+    const size_t off = (size_t)lc.plane * (size_t)k;
+    bool any_blur = false;
+    for (int li = 0; li < (int)lc.hinst.size(); ++li) {
+      const LikInst& L = lc.hinst[li];
+      if (L.rbmc_ns <= k) continue;
+      const long long nobs = obs_floats(L), npx = (long long)L.H * L.W;
+      const float* e1 = d_noise[L.inst] + (size_t)k * (size_t)(nobs + npx);
+      const float* e2 = e1 + nobs;
+      // e2: white noise in pixel space, into its pitched plane
+      e = hipMemcpy2DAsync(lc.rbmc_e2 + off + L.off, sizeof(float) * L.pitch, e2,
+                           sizeof(float) * L.W, sizeof(float) * L.W, L.H, hipMemcpyDeviceToDevice, s);
+      if (e != hipSuccess) return e;
+      // H^T e1 (unscaled; 1/sqrt(xi) is applied with every right-hand side)
+      if (L.op == OP_BLUR) {
+        // staged in the q plane (scratch between solves), correlated below
+        e = hipMemcpy2DAsync(lc.planes[LP_Q] + L.off, sizeof(float) * L.pitch, e1,
+                             sizeof(float) * L.W, sizeof(float) * L.W, L.H, hipMemcpyDeviceToDevice, s);
+        any_blur = true;
+      } else if (L.op == OP_DFT) {
+        e = dft_back_project_inst(lc, li, e1, lc.rbmc_g + off, s);
+      } else {
+        e = wht_back_project_inst(lc, li, e1, lc.rbmc_g + off, s);
+      }
+      if (e != hipSuccess) return e;
+    }
+    if (any_blur) {
+      LikArgs A = make_args(lc);
+      A.hty = lc.rbmc_g + off;
+      hipLaunchKernelGGL(k_hty_blur, dim3(lc.ntiles), dim3(256), 0, s, A, (const float*)lc.planes[LP_Q]);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+  }
+  return set_x_invalid(lc, s);
+}
+
 hipError_t lik_reset(LikCtx& lc, hipStream_t s) { return set_x_invalid(lc, s); }
 hipError_t lik_resume(LikCtx& lc, hipStream_t s) { return set_x_invalid(lc, s); }
 
@@ -914,6 +1112,7 @@ __global__ void k_x_invalid(InstState* st, const LikInst* inst, int nlik) {
   if (i < nlik) {
     st[inst[i].inst].x_valid = 0;
     st[inst[i].inst].xprev_valid = 0;
+    st[inst[i].inst].xs_valid = 0;
   }
 }
 
@@ -983,17 +1182,11 @@ static hipError_t other(LikCtx& lc, hipStream_t s, K kernel, Args... args) {
   });
 }
 
-hipError_t lik_head(LikCtx& lc, float2* const S[5], hipStream_t s) {
-  if (lc.nlik == 0) return hipSuccess;
+// CG start for the right-hand side in b and the start in x: q = A x, r = b - q,
+// z = M^{-1} r, r.z and r.r.
+static hipError_t cg_start(LikCtx& lc, hipStream_t s) {
   hipError_t e;
   lc.pcur = 0;   // the first iteration sets p = z whatever the p planes hold
-  const dim3 g(lc.ntiles), b(256);
-  if ((e = other(lc, s, k_lik_prep, make_args(lc), (const float2*)S[0], (const float2*)S[1],
-                 (const float2*)S[2], (const float2*)S[3], (const float2*)S[4])) != hipSuccess)
-    return e;
-  if ((e = fin(lc, FIN_PREP, s)) != hipSuccess) return e;
-  if ((e = other(lc, s, k_lik_spec, make_args(lc))) != hipSuccess) return e;
-  if ((e = fin(lc, FIN_SPEC, s)) != hipSuccess) return e;
   if ((e = launch_apply(lc, 0, s)) != hipSuccess) return e;
   bool cg_init_needed = !blur_all_sep(lc);
   for (const LikInst& d : lc.hinst) cg_init_needed = cg_init_needed || d.op != OP_BLUR;
@@ -1006,6 +1199,20 @@ hipError_t lik_head(LikCtx& lc, float2* const S[5], hipStream_t s) {
     if ((e = other(lc, s, k_precond_dot, make_args(lc))) != hipSuccess) return e;
   }
   return fin(lc, FIN_INIT, s);
+}
+
+hipError_t lik_head(LikCtx& lc, float2* const S[5], hipStream_t s) {
+  if (lc.nlik == 0) return hipSuccess;
+  hipError_t e;
+  lc.sample = 0;
+  lc.pcur = 0;   // the first iteration sets p = z whatever the p planes hold
+  if ((e = other(lc, s, k_lik_prep, make_args(lc), (const float2*)S[0], (const float2*)S[1],
+                 (const float2*)S[2], (const float2*)S[3], (const float2*)S[4])) != hipSuccess)
+    return e;
+  if ((e = fin(lc, FIN_PREP, s)) != hipSuccess) return e;
+  if ((e = other(lc, s, k_lik_spec, make_args(lc))) != hipSuccess) return e;
+  if ((e = fin(lc, FIN_SPEC, s)) != hipSuccess) return e;
+  return cg_start(lc, s);
 }
 
 hipError_t lik_iterations(LikCtx& lc, int n, hipStream_t s) {
@@ -1067,16 +1274,41 @@ hipError_t lik_tail(LikCtx& lc, float2* S0, hipStream_t s) {
   return other(lc, s, k_lik_site, make_args(lc), S0);
 }
 
-hipError_t lik_update(LikCtx& lc, float2* const S[5], hipStream_t s) {
-  if (lc.nlik == 0) return hipSuccess;
-  hipError_t e = lik_head(lc, S, s);
-  if (e != hipSuccess) return e;
+// CG iterations until every instance's solve has stopped (host polls).
+static hipError_t iterate_to_done(LikCtx& lc, hipStream_t s) {
+  hipError_t e;
   for (int it = 0; it < lc.max_iters; it += kCgPoll) {
     if ((e = lik_iterations(lc, kCgPoll, s)) != hipSuccess) return e;
     bool done = false;
     if ((e = lik_poll(lc, s, done)) != hipSuccess) return e;
     if (done) break;
   }
+  return hipSuccess;
+}
+
+// RBMC sample solves after the mean solve (instances with rbmc_ns > 0).
+static hipError_t rbmc_samples(LikCtx& lc, hipStream_t s) {
+  hipError_t e;
+  lc.sample = 0;
+  if ((e = other(lc, s, k_rbmc_begin, make_args(lc))) != hipSuccess) return e;
+  for (int k = 0; k < lc.rbmc_ns_max; ++k) {
+    lc.sample = k;
+    if ((e = other(lc, s, k_rbmc_rhs, make_args(lc))) != hipSuccess) return e;
+    if ((e = fin(lc, FIN_SAMPLE, s)) != hipSuccess) return e;
+    if ((e = cg_start(lc, s)) != hipSuccess) return e;
+    if ((e = iterate_to_done(lc, s)) != hipSuccess) return e;
+    if ((e = other(lc, s, k_rbmc_acc, make_args(lc))) != hipSuccess) return e;
+  }
+  lc.sample = 0;
+  return hipSuccess;
+}
+
+hipError_t lik_update(LikCtx& lc, float2* const S[5], hipStream_t s) {
+  if (lc.nlik == 0) return hipSuccess;
+  hipError_t e = lik_head(lc, S, s);
+  if (e != hipSuccess) return e;
+  if ((e = iterate_to_done(lc, s)) != hipSuccess) return e;
+  if (lc.rbmc_ns_max && (e = rbmc_samples(lc, s)) != hipSuccess) return e;
   return lik_tail(lc, S[0], s);
 }
 

@@ -19,6 +19,9 @@ hipError_t wht_setup(LikCtx& lc, const LikInstInfo* li, int n, size_t wht_bytes,
                      std::string& err);
 // H^T y into the H^T y plane and the pixel-space observation
 hipError_t wht_set_observation(LikCtx& lc, const float* const* d_y, hipStream_t s);
+// H^T v of the Walsh-Hadamard instance with likelihood index li (v: Paley-ordered
+// coefficients) into the pixel plane `out`
+hipError_t wht_back_project_inst(LikCtx& lc, int li, const float* v, float* out, hipStream_t s);
 // mode 0: q = A x; mode 1: p_out = z + beta p_in, q = A p_out; with p.q partials
 hipError_t wht_apply(LikCtx& lc, int mode, hipStream_t s);
 // z = M^{-1} r, M = W^T diag(mask / xi + d_bar) W, for instances whose

@@ -360,15 +360,28 @@ hipError_t wht_setup(LikCtx& lc, const LikInstInfo* li, int n, size_t wht_bytes,
   return host.empty() ? hipSuccess : hipStreamSynchronize(s);
 }
 
+// H^T v = W^T (mask v) of a Paley-ordered coefficient array v into the pixel
+// plane `out`: one transform of the masked, reordered coefficients.
+static hipError_t wht_back_project(LikCtx& lc, const WhtPlan& P, const float* v, float* out,
+                                   hipStream_t s) {
+  const LikInst& L = lc.hinst[P.li];
+  WhtArgs a = base(lc, L);
+  a.src = WSRC_OBS; a.obs = v;
+  a.mul = WMUL_SCALE; a.scale = (float)(1.0 / std::sqrt((double)L.H * L.W));
+  a.dst = WDST_REAL; a.real_out = out;
+  return run(P, a, false, s);
+}
+
+hipError_t wht_back_project_inst(LikCtx& lc, int li, const float* v, float* out, hipStream_t s) {
+  for (const WhtPlan& P : lc.wht)
+    if (P.li == li) return wht_back_project(lc, P, v, out, s);
+  return hipErrorInvalidValue;
+}
+
 hipError_t wht_set_observation(LikCtx& lc, const float* const* d_y, hipStream_t s) {
   for (const WhtPlan& P : lc.wht) {
     const LikInst& L = lc.hinst[P.li];
-    // H^T y = W^T (mask y): one transform of the masked, reordered coefficients
-    WhtArgs a = base(lc, L);
-    a.src = WSRC_OBS; a.obs = d_y[L.inst];
-    a.mul = WMUL_SCALE; a.scale = (float)(1.0 / std::sqrt((double)L.H * L.W));
-    a.dst = WDST_REAL; a.real_out = lc.planes[LP_HTY];
-    hipError_t e = run(P, a, false, s);
+    hipError_t e = wht_back_project(lc, P, d_y[L.inst], lc.planes[LP_HTY], s);
     if (e != hipSuccess) return e;
     // the cold start and the observation range use H^T y as the pixel-space observation
     e = hipMemcpy2DAsync(lc.ypix + L.off, sizeof(float) * L.pitch, lc.planes[LP_HTY] + L.off,

@@ -55,6 +55,16 @@ def test_workspace_bytes_and_validation():
     # the largest accepted sizes (16384 on a side) size without error
     big = ep_tv_workspace_bytes([ProblemSpec(16384, 3), ProblemSpec(2, 16384)])
     assert big >= (16384 * 3 + 2 * 16384) * (5 * 8)
+    # the RBMC estimator: Ns planes of noise, H^T e1 and sample solutions on top
+    blur = dict(op=N.OP_BLUR_PERIODIC, taps=np.ones((3, 3), np.float32) / 9)
+    b_spec = ep_tv_workspace_bytes([ProblemSpec(64, 64, **blur)])
+    b_rbmc = ep_tv_workspace_bytes([ProblemSpec(64, 64, var_estimator=N.VAR_RBMC, rbmc_samples=4, **blur)])
+    assert b_rbmc >= b_spec + 64 * 65 * 4 * (3 * 4 + 2)
+    for bad_rbmc in (ProblemSpec(8, 8, var_estimator=N.VAR_RBMC, rbmc_samples=0, **blur),
+                     ProblemSpec(8, 8, var_estimator=N.VAR_RBMC, rbmc_samples=65, **blur),
+                     ProblemSpec(8, 8, var_estimator=2, **blur)):
+        with pytest.raises(EPTVError):
+            ep_tv_workspace_bytes([bad_rbmc])
     # the smallest transform images (one 4 x 4 block) are accepted
     for op in (N.OP_HADAMARD_MASK, N.OP_DFT_MASK):
         assert ep_tv_workspace_bytes([ProblemSpec(4, 4, op=op, mask=np.ones((4, 4), np.uint8))]) > 0
