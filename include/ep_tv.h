@@ -116,7 +116,11 @@ typedef struct {
   double prior_s1sq;           /* MOG2: s1^2 > 0; BG: s^2 > 0 */
   double prior_s2sq;           /* MOG2: s2^2 > 0; BG: unused */
   int32_t rbmc_samples;        /* EP_TV_VAR_RBMC: samples Ns in [1, 64]; otherwise ignored */
-  int32_t reserved;            /* 0 */
+  int32_t noise_map;           /* 1: non-i.i.d. noise, one variance per pixel, given by
+                                  ep_tv_set_noise_variance (EP_TV_OP_IDENTITY only; Sec. III-C
+                                  notes that the likelihood factor stays exact for denoising:
+                                  q_{x,0} = N(y, diag(xi_i))); 0: i.i.d. noise of variance
+                                  noise_var (which then only sets the range of valid inputs) */
 } ep_tv_problem;
 
 /* Estimators of diag Cov_{P_0}, the tilted variances of the likelihood site
@@ -205,6 +209,13 @@ int ep_tv_set_observation(ep_tv_ctx* ctx, const float* const* d_y);
  * copied (as H^T e1 and e2); the sample solutions restart from zero.
  * Asynchronous. */
 int ep_tv_set_rbmc_noise(ep_tv_ctx* ctx, const float* const* d_noise);
+
+/* Per-pixel noise variances of the instances with noise_map = 1 (required before
+ * their first sweep).  d_var: host array of n_problems device pointers (NULL
+ * for the other instances), each height*width floats > 0 (row-major).  The
+ * data is copied (as precisions); if an observation is set, every instance is
+ * re-initialised cold.  Asynchronous. */
+int ep_tv_set_noise_variance(ep_tv_ctx* ctx, const float* const* d_var);
 
 /* Re-run the cold initialisation with the stored observations.  Asynchronous. */
 int ep_tv_init_cold(ep_tv_ctx* ctx);
@@ -350,7 +361,14 @@ int ep_tv_get_timing(ep_tv_ctx* ctx, ep_tv_timing* out);
  *    tile is 124 interior columns wide).  Smaller heights than the workspace was
  *    sized for (the smaller of 8 and the initial height) return EP_TV_E_ARG.
  * Both synchronise the stream. */
-enum { EP_TV_OPT_GRAPH = 1, EP_TV_OPT_TILE_ROWS = 2 };
+enum { EP_TV_OPT_GRAPH = 1, EP_TV_OPT_TILE_ROWS = 2, EP_TV_OPT_EM_OPTION = 3 };
+/*  EP_TV_OPT_EM_OPTION (1, 2 or 3, default 3): the approximation of a_0 in the
+ *    EM update lambda = N / a_0 (Sec. IV): 3 = Eq. (3rd_alternative_a0), the
+ *    sum over the sweep's edges of the tilted E|u_n|; 2 = Eq. (eq:au), E|u_n|
+ *    under Q(u_n) = N(m_bar_n, S_bar_n), the Gaussian with the tilted moments;
+ *    1 = Eq. (eq:ax), E|x_i - x_j| under the global Q(x) after the sweep
+ *    (an extra pass over the sites).  The paper adopts option 3; 1 and 2 are
+ *    there to compare the estimates of lambda (its Fig. 4). */
 int ep_tv_set_option(ep_tv_ctx* ctx, int32_t option, int64_t value);
 int ep_tv_get_option(ep_tv_ctx* ctx, int32_t option, int64_t* value);
 

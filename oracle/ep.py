@@ -26,9 +26,17 @@ One sweep t (where the paper is silent, the reading taken is stated at the step)
      parallel -- cavity, tilted moments of u (Eq. (marginal_tilted_un)),
      Gehre-Jin projection back to (x_i, x_j), site update (Eq. (update_qk_x)),
      negative-variance clamp, damping;
-  3. EM (Algorithm 2, option 3, Eq. (3rd_alternative_a0)):
-     lambda <- N / a_bar_u, a_bar_u = sum over all edges of the sweep of the
-     tilted E|u_n| at the lambda used in the sweep; N = number of pixels.
+  3. EM (Algorithm 2): lambda <- N / a_0 with N the number of pixels and a_0
+     one of the three approximations of Sec. IV (em_option):
+       3 (default, Eq. (3rd_alternative_a0)): a_bar_u = sum over all edges of
+         the sweep of the tilted E|u_n| at the lambda used in the sweep;
+       2 (Eq. (eq:au)): a_u = sum over the edges of E|u_n| under Q(u_n), the
+         Gaussian with the tilted mean and variance of u_n (the moments that
+         update Q(u_k));
+       1 (Eq. (eq:ax)): a_x = sum over the edges of E|x_i - x_j| under the
+         global Q(x) after the sweep (x_i - x_j ~ N(mu_i - mu_j, v_i + v_j)).
+     All three are folded-normal or tilted means in closed form; the unused
+     ones are kept as diagnostics (EPState.a_x, a_u, a_bar).
 
 Parity pins: tests/test_oracle_ep.py (l2-TV fixed point = dense posterior mean,
 exact single-edge posterior, EM fixed point = marginal-likelihood maximiser on a
@@ -45,7 +53,7 @@ from typing import Optional, Sequence
 import numpy as np
 
 from . import operators as ops
-from .tilted import tilted
+from .tilted import folded_normal_mean, tilted
 
 SITE_INIT_PREC = 1e-8     # 1 / 1e8: initial TV-site variance 1e8
 PREC_FLOOR = 1e-8         # clamp: site variance negative or above 1e8 -> 1e8
@@ -101,6 +109,9 @@ class EPState:
     warm: bool = False              # sites carry information already: no skipped q0 update
     lik_mu_absmax: float = 0.0      # max |mu| of the global approximation after the last q0 update
     rbmc: Optional[ops.RBMCSamples] = None   # RBMC inputs and per-sample CG starts
+    a_bar: float = 0.0              # last sweep's a_0, option 3 (tilted E|u|)
+    a_u: float = 0.0                # option 2 (E|u| under Q(u)), when computed
+    a_x: float = 0.0                # option 1 (E|x_i - x_j| under Q(x)), when computed
 
 
 class EPProblem:
@@ -110,7 +121,7 @@ class EPProblem:
     def __init__(self, y, op: ops.Operator, xi, lam, damping=0.5, prior="l1",
                  boundary="free", order: Sequence[int] = (1, 2, 3, 4),
                  estimator="spectral", cg_rtol=1e-12, first_sweep_likelihood=False,
-                 rbmc_noise=None):
+                 rbmc_noise=None, em_option=3, em_diagnostics=False, noise_var_map=None):
         self.op = op
         self.h, self.w = op.shape
         self.N = self.h * self.w
@@ -128,6 +139,21 @@ class EPProblem:
         self.rbmc_noise = rbmc_noise
         if estimator == "rbmc" and rbmc_noise is None:
             raise ValueError("the RBMC estimator needs white-noise samples (rbmc_noise)")
+        if em_option not in (1, 2, 3):
+            raise ValueError("em_option must be 1, 2 or 3")
+        self.em_option = em_option
+        self.em_diagnostics = bool(em_diagnostics)   # compute all three a_0 every sweep
+        # non-i.i.d. noise (Sec. III-C, after Eq. (tilted_P_1)): a per-pixel noise
+        # variance for denoising, where the likelihood factor stays exact: q_{x,0}
+        # = N(y, diag(xi_i)) and it is never updated
+        self.noise_prec = None
+        if noise_var_map is not None:
+            if op.kind != ops.IDENTITY:
+                raise ValueError("per-pixel noise variances are supported for denoising")
+            nv = np.asarray(noise_var_map, np.float64)
+            if nv.shape != op.shape or not np.all(nv > 0):
+                raise ValueError("noise_var_map must hold one positive variance per pixel")
+            self.noise_prec = (1.0 / nv).ravel()
         self.y = y
         self.hty = op.Hty(y)
         self.edges = colour_classes(self.h, self.w, boundary)
@@ -139,13 +165,13 @@ class EPProblem:
 
 
 def problem_from_synthetic(p, prior="l1", estimator="spectral", boundary=None, order=(1, 2, 3, 4),
-                           lam=None, damping=None, rbmc_noise=None):
+                           lam=None, damping=None, rbmc_noise=None, em_option=3):
     """Build an EPProblem from a synthetic.Problem."""
     op = ops.Operator(p.op, p.shape, taps=p.taps, mask=p.mask)
     return EPProblem(p.y, op, p.xi, p.lam0 if lam is None else lam,
                      damping=p.damping if damping is None else damping, prior=prior,
                      boundary=p.boundary if boundary is None else boundary, order=order,
-                     estimator=estimator, rbmc_noise=rbmc_noise)
+                     estimator=estimator, rbmc_noise=rbmc_noise, em_option=em_option)
 
 
 def init_cold(pb: EPProblem) -> EPState:
@@ -157,9 +183,10 @@ def init_cold(pb: EPProblem) -> EPState:
     N = pb.N
     tau = np.zeros((5, N))
     eta = np.zeros((5, N))
-    tau[0] = 1.0 / pb.xi
+    prec0 = 1.0 / pb.xi if pb.noise_prec is None else pb.noise_prec
+    tau[0] = prec0
     y0 = pb.hty if pb.op.kind in (ops.DFT, ops.HADAMARD) else np.asarray(pb.y, dtype=np.float64)
-    eta[0] = y0.ravel() / pb.xi
+    eta[0] = y0.ravel() * prec0
     for k in range(4):
         tau[k + 1, pb.covered[k]] = SITE_INIT_PREC
     return EPState(tau=tau, eta=eta, lam=pb.lam0)
@@ -218,6 +245,8 @@ def tv_block_update(pb: EPProblem, st: EPState, k: int) -> float:
     m = mi - mj
     s = ci + cj
     m_bar, S_bar, e_abs = tilted(pb.prior, m, s, st.lam)
+    if pb.em_option == 2 or pb.em_diagnostics:
+        st.a_u += float(folded_normal_mean(m_bar, S_bar).sum())
     # Gehre-Jin projection of the tilted moments of u back to (x_i, x_j)
     Ei = mi + (m_bar - m) / s * ci
     Ej = mj - (m_bar - m) / s * cj
@@ -235,18 +264,34 @@ def tv_block_update(pb: EPProblem, st: EPState, k: int) -> float:
     return float(e_abs.sum())
 
 
+def a_x(pb: EPProblem, mu, v):
+    """Option 1 of Sec. IV: sum over all edges of E|x_i - x_j| under N(mu, diag v)."""
+    mu = np.asarray(mu, np.float64).ravel()
+    v = np.asarray(v, np.float64).ravel()
+    tot = 0.0
+    for k in range(4):
+        i, j = pb.edges[k]
+        tot += float(folded_normal_mean(mu[i] - mu[j], v[i] + v[j]).sum())
+    return tot
+
+
 def sweep(pb: EPProblem, st: EPState, t: int, em: bool) -> float:
-    """Sweep t (1-based).  Returns a_bar_u of the sweep."""
+    """Sweep t (1-based).  Returns a_bar_u (option 3) of the sweep."""
     if pb.op.kind != ops.IDENTITY and (t > 1 or st.warm or pb.first_sweep_likelihood):
         likelihood_site_update(pb, st)
     a_bar = 0.0
+    st.a_u = 0.0
     for k in pb.order:
         a_bar += tv_block_update(pb, st, k)
+    st.a_bar = a_bar
+    if pb.em_option == 1 or pb.em_diagnostics:
+        st.a_x = a_x(pb, *marginals(st))
     if em:
         if pb.prior != "l1":
             raise ValueError("EM is defined for the l1-TV prior only")
-        if a_bar > 0.0:              # an image without edges has nothing to re-estimate
-            st.lam = pb.N / a_bar
+        a0 = {1: st.a_x, 2: st.a_u, 3: a_bar}[pb.em_option]
+        if a0 > 0.0:                 # an image without edges has nothing to re-estimate
+            st.lam = pb.N / a0
     return a_bar
 
 

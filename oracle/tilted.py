@@ -179,6 +179,15 @@ def bg_tilted(m, s, theta):
     return mixture_tilted(m, s, (omega, 1.0 - omega), (v, 0.0))
 
 
+def folded_normal_mean(m, var):
+    """E|d| for d ~ N(m, var): m erf(m / sqrt(2 var)) + sqrt(2 var / pi) exp(-m^2 / (2 var))."""
+    m = np.asarray(m, np.float64)
+    var = np.asarray(var, np.float64)
+    sd = np.sqrt(var)
+    erf = np.vectorize(math.erf, otypes=[np.float64])
+    return m * erf(m / (sd * math.sqrt(2.0))) + sd * math.sqrt(2.0 / math.pi) * np.exp(-m * m / (2 * var))
+
+
 def tilted(prior, m, s, theta):
     if prior == "l1":
         return laplace_tilted(m, s, theta)

@@ -26,25 +26,11 @@ import numpy as np
 
 from . import ep
 from . import operators as ops
+from . import tilted as tilted_mod
 
 
-def folded_normal_mean(m, var):
-    """E|d| for d ~ N(m, var): m erf(m / sqrt(2 var)) + sqrt(2 var / pi) exp(-m^2 / (2 var))."""
-    m = np.asarray(m, np.float64)
-    var = np.asarray(var, np.float64)
-    sd = np.sqrt(var)
-    erf = np.vectorize(math.erf)
-    return m * erf(m / (sd * math.sqrt(2.0))) + sd * math.sqrt(2.0 / math.pi) * np.exp(-m * m / (2 * var))
-
-
-def a_x(pb: ep.EPProblem, mu, v):
-    mu = np.asarray(mu, np.float64).ravel()
-    v = np.asarray(v, np.float64).ravel()
-    tot = 0.0
-    for k in range(4):
-        i, j = pb.edges[k]
-        tot += float(folded_normal_mean(mu[i] - mu[j], v[i] + v[j]).sum())
-    return tot
+folded_normal_mean = tilted_mod.folded_normal_mean
+a_x = ep.a_x
 
 
 def lambda_option1(pb: ep.EPProblem, mu, v, scale=1.0, power=1.0):
@@ -67,10 +53,11 @@ def init_warm(pb: ep.EPProblem, mu_hat, v_hat, set_lambda=True, scale=1.0, power
     prec = 1.0 / v
     if pb.op.kind == ops.IDENTITY:
         y = np.asarray(pb.y, np.float64).ravel()
-        tau[0] = 1.0 / pb.xi
-        eta[0] = y / pb.xi
-        rest_tau = np.maximum(prec - 1.0 / pb.xi, c * ep.SITE_INIT_PREC)
-        rest_eta = mu * (1.0 / pb.xi + rest_tau) - y / pb.xi
+        w = 1.0 / pb.xi if pb.noise_prec is None else pb.noise_prec
+        tau[0] = w
+        eta[0] = y * w
+        rest_tau = np.maximum(prec - w, c * ep.SITE_INIT_PREC)
+        rest_eta = mu * (w + rest_tau) - y * w
         share = np.where(c > 0, 1.0 / np.maximum(c, 1.0), 0.0)
         for k in range(4):
             tau[k + 1] = np.where(cov[k], rest_tau * share, 0.0)

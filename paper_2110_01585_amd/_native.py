@@ -35,6 +35,7 @@ PRIOR_MOG2 = 1
 PRIOR_BG = 2
 OPT_GRAPH = 1
 OPT_TILE_ROWS = 2
+OPT_EM_OPTION = 3
 VAR_SPECTRAL = 0
 VAR_RBMC = 1
 
@@ -55,7 +56,7 @@ class EpTvProblem(ctypes.Structure):
                 ("prior", ctypes.c_int32), ("var_estimator", ctypes.c_int32),
                 ("prior_omega", ctypes.c_double), ("prior_s1sq", ctypes.c_double),
                 ("prior_s2sq", ctypes.c_double),
-                ("rbmc_samples", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("rbmc_samples", ctypes.c_int32), ("noise_map", ctypes.c_int32)]
 
 
 class EpTvStats(ctypes.Structure):
@@ -100,6 +101,7 @@ SIGNATURES = {
     "ep_tv_set_observation": (ctypes.c_int, [_P, _FPP]),
     "ep_tv_init_cold": (ctypes.c_int, [_P]),
     "ep_tv_set_rbmc_noise": (ctypes.c_int, [_P, _FPP]),
+    "ep_tv_set_noise_variance": (ctypes.c_int, [_P, _FPP]),
     "ep_tv_run": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32]),
     "ep_tv_em_step": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.POINTER(ctypes.c_double)]),
     "ep_tv_solve": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_double, ctypes.c_int32, _FPP, _FPP,

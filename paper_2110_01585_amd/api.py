@@ -43,6 +43,7 @@ class ProblemSpec:
     prior_s2sq: float = 1.0
     var_estimator: int = N.VAR_SPECTRAL
     rbmc_samples: int = 0
+    noise_map: bool = False      # per-pixel noise variances (identity operator)
 
 
 _OPS = {"identity": N.OP_IDENTITY, "blur": N.OP_BLUR_PERIODIC, "dft": N.OP_DFT_MASK,
@@ -77,6 +78,7 @@ def _problems(specs: Sequence[ProblemSpec]):
         a.cg_reduce = s.cg_reduce
         a.prior, a.prior_omega, a.prior_s1sq, a.prior_s2sq = s.prior, s.prior_omega, s.prior_s1sq, s.prior_s2sq
         a.var_estimator, a.rbmc_samples = s.var_estimator, s.rbmc_samples
+        a.noise_map = 1 if s.noise_map else 0
         if s.taps is not None:
             t = np.ascontiguousarray(s.taps, dtype=np.float32)
             keep.append(t)
@@ -214,6 +216,15 @@ class Context:
             k = s.height * s.width * (2 if s.op == N.OP_DFT_MASK else 1)
             self._dev(t, (s.rbmc_samples * (k + s.height * s.width),))
         return self._check(N.lib().ep_tv_set_rbmc_noise(self.handle, _ptrs(noises)), "set_rbmc_noise")
+
+    def ep_tv_set_noise_variance(self, variances):
+        """variances: per instance a contiguous (H, W) float32 device tensor, or None
+        for instances without a noise map."""
+        vs = [None if v is None else self._dev(v, (s.height, s.width))
+              for v, s in zip(variances, self.specs)]
+        self._noise = vs
+        return self._check(N.lib().ep_tv_set_noise_variance(self.handle, _ptrs(vs)),
+                           "set_noise_variance")
 
     def ep_tv_init_cold(self):
         return self._check(N.lib().ep_tv_init_cold(self.handle), "init_cold")

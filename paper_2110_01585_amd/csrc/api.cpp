@@ -40,7 +40,7 @@ struct Layout {
   long long plane = 0;       // elements per plane (all instances)
   int ntiles = 0;            // tiles at the initial tile height
   int tile_cap = 0;          // tiles at the smallest tile height (sizes the tile arrays)
-  size_t S0 = 0, SB[2][4]{}, ypix = 0, inst = 0, st = 0, tiles = 0;
+  size_t S0 = 0, SB[2][4]{}, ypix = 0, wpix = 0, inst = 0, st = 0, tiles = 0;
   size_t part_e = 0, part_m = 0, part_v = 0, part_c = 0, part_f = 0, tab0 = 0, tab1 = 0;
   LikLayout lik;
   size_t total = 0;
@@ -119,6 +119,9 @@ const char* validate(const ep_tv_problem& p) {
     return "var_estimator must be one of EP_TV_VAR_*";
   if (p.var_estimator == EP_TV_VAR_RBMC && (p.rbmc_samples < 1 || p.rbmc_samples > 64))
     return "rbmc_samples must be in [1, 64]";
+  if (p.noise_map != 0 && p.noise_map != 1) return "noise_map must be 0 or 1";
+  if (p.noise_map && p.op != EP_TV_OP_IDENTITY)
+    return "per-pixel noise variances are supported for the identity operator";
   if (p.cg_precond < EP_TV_PRECOND_AUTO || p.cg_precond > EP_TV_PRECOND_CIRCULANT)
     return "cg_precond must be one of EP_TV_PRECOND_*";
   if (p.cg_precond == EP_TV_PRECOND_CIRCULANT && p.op != EP_TV_OP_IDENTITY &&
@@ -174,6 +177,9 @@ void make_layout(std::vector<InstHost>& ih, int rows, Layout& L) {
   for (int b = 0; b < 2; ++b)
     for (int k = 0; k < 4; ++k) L.SB[b][k] = take(sizeof(float2) * (size_t)L.plane);
   L.ypix = take(sizeof(float) * (size_t)L.plane);
+  bool any_map = false;
+  for (const auto& h : ih) any_map = any_map || h.p.noise_map;
+  L.wpix = any_map ? take(sizeof(float) * (size_t)L.plane) : 0;
   L.inst = take(sizeof(InstDev) * n);
   L.st = take(sizeof(InstState) * n);
   L.tiles = take(sizeof(int4) * (size_t)std::max(tiles, 1));
@@ -233,6 +239,9 @@ struct ep_tv_ctx {
   float2* SB[2][4]{};
   int cur = 0;   // which TV-site buffer holds the current state
   float* ypix = nullptr;
+  float* wpix = nullptr;             // per-pixel noise precisions (noise_map instances)
+  bool any_noise_map = false;
+  bool noise_set = false;
   InstDev* d_inst = nullptr;
   InstState* d_st = nullptr;
   int4* d_tiles = nullptr;
@@ -337,6 +346,7 @@ static int upload_tiles(ep_tv_ctx* c) {
     d.H = h.p.height; d.W = h.p.width; d.pitch = h.pitch; d.bnd = h.p.boundary;
     d.off = h.off; d.op = h.p.op; d.strips = h.strips; d.chunks = h.chunks; d.tile0 = h.tile0;
     d.ntiles = h.ntiles; d.chunk_rows = h.chunk_rows; d.npix = h.p.height * h.p.width;
+    d.wmap = h.p.noise_map ? 1 : 0;
     if (h.p.op != EP_TV_OP_IDENTITY) {
       d.lik_tile0 = lik_tiles;
       d.lik_ntiles = lik_tile_count(h.p.height, h.p.width);
@@ -437,6 +447,7 @@ int ep_tv_create(const ep_tv_problem* p, int32_t n, void* d_ws, size_t ws_bytes,
     }
   }
   c->sa.prior = p[0].prior;
+  c->sa.em_opt = 3;
   make_layout(c->ih, initial_rows(p, n), c->L);
   c->chunk_rows = c->ih[0].chunk_rows;
   if (ws_bytes < c->L.total) {
@@ -449,6 +460,8 @@ int ep_tv_create(const ep_tv_problem* p, int32_t n, void* d_ws, size_t ws_bytes,
   for (int b = 0; b < 2; ++b)
     for (int k = 0; k < 4; ++k) c->SB[b][k] = reinterpret_cast<float2*>(c->ws + c->L.SB[b][k]);
   c->ypix = reinterpret_cast<float*>(c->ws + c->L.ypix);
+  for (int i = 0; i < n; ++i) c->any_noise_map = c->any_noise_map || p[i].noise_map;
+  c->wpix = c->any_noise_map ? reinterpret_cast<float*>(c->ws + c->L.wpix) : nullptr;
   c->d_inst = reinterpret_cast<InstDev*>(c->ws + c->L.inst);
   c->d_st = reinterpret_cast<InstState*>(c->ws + c->L.st);
   c->d_tiles = reinterpret_cast<int4*>(c->ws + c->L.tiles);
@@ -519,13 +532,15 @@ static int reset_states(ep_tv_ctx* c) {
 int ep_tv_init_cold(ep_tv_ctx* c) {
   if (!c) return EP_TV_E_ARG;
   if (!c->has_obs) return fail(c, EP_TV_E_STATE, "no observation set");
+  if (c->any_noise_map && !c->noise_set)
+    return fail(c, EP_TV_E_STATE, "per-pixel noise variances not set (ep_tv_set_noise_variance)");
   int rc = reset_states(c);
   if (rc) return rc;
   HIPCHK(c, launch_yrange(c->ypix, c->d_inst, c->d_st, c->n, c->stream));
   c->cur = 0;
   c->warm_started = false;
   HIPCHK(c, launch_init_cold(cur_sites(c).S, c->ypix, c->d_inst, c->d_st, c->d_tiles, c->ntiles,
-                             c->stream));
+                             c->stream, false, c->wpix));
   HIPCHK(c, lik_reset(c->lik, c->stream));
   return EP_TV_OK;
 }
@@ -545,7 +560,7 @@ int ep_tv_init_warm(ep_tv_ctx* c, const float* const* d_mu_hat, const float* con
   if (rc) return rc;
   HIPCHK(c, launch_init_warm(cur_sites(c).S, c->ypix, c->d_inst, c->d_st, c->n, c->d_tiles, c->ntiles,
                              c->d_tab0, c->d_tab1, lambda_scale, lambda_power, c->sa.part_eabs,
-                             c->sa.part_flags, c->stream));
+                             c->sa.part_flags, c->stream, c->wpix));
   rc = pull_states(c);
   if (rc) return rc;
   c->warm_started = true;
@@ -571,7 +586,20 @@ int ep_tv_set_observation(ep_tv_ctx* c, const float* const* d_y) {
   }
   HIPCHK(c, lik_set_observation(c->lik, d_y, c->stream));
   c->has_obs = true;
+  if (c->any_noise_map && !c->noise_set) return EP_TV_OK;   // cold start once the map is set
   return ep_tv_init_cold(c);
+}
+
+int ep_tv_set_noise_variance(ep_tv_ctx* c, const float* const* d_var) {
+  if (!c || !d_var) return EP_TV_E_ARG;
+  if (!c->any_noise_map) return fail(c, EP_TV_E_ARG, "no instance has noise_map = 1");
+  for (int i = 0; i < c->n; ++i)
+    if (c->ih[i].p.noise_map && !d_var[i]) return fail(c, EP_TV_E_ARG, "null noise-variance pointer");
+  int rc = set_tab(c, const_cast<float* const*>(d_var), c->d_tab1, c->tab_host1);
+  if (rc) return rc;
+  HIPCHK(c, launch_noise_prec(c->wpix, c->d_inst, c->d_tiles, c->ntiles, c->d_tab1, c->stream));
+  c->noise_set = true;
+  return c->has_obs ? ep_tv_init_cold(c) : EP_TV_OK;
 }
 
 int ep_tv_set_rbmc_noise(ep_tv_ctx* c, const float* const* d_noise) {
@@ -600,6 +628,9 @@ static int enqueue_tv(ep_tv_ctx* c, int par, int em, bool delta, double tol, hip
   a.I1 = in[0]; a.I2 = in[1]; a.I3 = in[2]; a.I4 = in[3];
   a.O1 = out[0]; a.O2 = out[1]; a.O3 = out[2]; a.O4 = out[3];
   HIPCHK(c, launch_tv_sweep(a, delta, s));
+  if (em && a.em_opt == 1)
+    HIPCHK(c, launch_em_ax(sites_at(c, par ^ 1).S, c->d_inst, c->d_st, c->d_tiles, c->ntiles,
+                           a.part_eabs, s));
   HIPCHK(c, launch_finalize(c->d_inst, c->d_st, c->n, a, em, tol, s));
   return EP_TV_OK;
 }
@@ -627,6 +658,9 @@ static int one_sweep(ep_tv_ctx* c, int em, bool delta, double tol) {
     HIPCHK(c, hipEventRecord(next_event(c, i1), c->stream));
     c->ev_sweep.emplace_back(i0, i1);
   }
+  if (em && a.em_opt == 1)
+    HIPCHK(c, launch_em_ax(cur_sites(c).S, c->d_inst, c->d_st, c->d_tiles, c->ntiles, a.part_eabs,
+                           c->stream));
   HIPCHK(c, launch_finalize(c->d_inst, c->d_st, c->n, c->sa, em, tol, c->stream));
   return EP_TV_OK;
 }
@@ -719,6 +753,8 @@ static int graph_sweep(ep_tv_ctx* c) {
 static int advance(ep_tv_ctx* c, int n, int em, bool delta, double tol) {
   if (c->lik.rbmc_ns_max && !c->rbmc_noise_set)
     return fail(c, EP_TV_E_STATE, "the RBMC estimator needs ep_tv_set_rbmc_noise first");
+  if (c->any_noise_map && !c->noise_set)
+    return fail(c, EP_TV_E_STATE, "per-pixel noise variances not set (ep_tv_set_noise_variance)");
   if (!c->use_graph || c->lik.rbmc_ns_max) {
     for (int t = 0; t < n; ++t) {
       int rc = one_sweep(c, em, delta, tol);
@@ -766,6 +802,8 @@ int ep_tv_em_step(ep_tv_ctx* c, int32_t n_ep, double* lambda_out) {
   if (!c->has_obs) return fail(c, EP_TV_E_STATE, "no observation set");
   if (c->lik.rbmc_ns_max && !c->rbmc_noise_set)
     return fail(c, EP_TV_E_STATE, "the RBMC estimator needs ep_tv_set_rbmc_noise first");
+  if (c->any_noise_map && !c->noise_set)
+    return fail(c, EP_TV_E_STATE, "per-pixel noise variances not set (ep_tv_set_noise_variance)");
   if (c->sa.prior != PRIOR_L1) return fail(c, EP_TV_E_ARG, "EM is defined for the l1 factor only");
   for (int t = 0; t < n_ep; ++t) {
     int rc = one_sweep(c, t == n_ep - 1 ? 1 : 0, false, 0.0);
@@ -852,7 +890,7 @@ static int restart_failed_warm(ep_tv_ctx* c) {
   HIPCHK(c, hipMemcpyAsync(c->d_st, c->host_st.data(), sizeof(InstState) * c->n,
                            hipMemcpyHostToDevice, c->stream));
   HIPCHK(c, launch_init_cold(cur_sites(c).S, c->ypix, c->d_inst, c->d_st, c->d_tiles, c->ntiles,
-                             c->stream, true));
+                             c->stream, true, c->wpix));
   for (int i = 0; i < c->n; ++i) c->host_st[i].restart = 0;
   HIPCHK(c, hipMemcpyAsync(c->d_st, c->host_st.data(), sizeof(InstState) * c->n,
                            hipMemcpyHostToDevice, c->stream));
@@ -1059,6 +1097,12 @@ int ep_tv_set_option(ep_tv_ctx* c, int32_t option, int64_t value) {
       c->use_graph = value != 0;
       if (!c->use_graph) drop_graphs(c);
       return EP_TV_OK;
+    case EP_TV_OPT_EM_OPTION:
+      if (value < 1 || value > 3) return fail(c, EP_TV_E_ARG, "EM option must be 1, 2 or 3");
+      HIPCHK(c, hipStreamSynchronize(c->stream));
+      c->sa.em_opt = (int)value;
+      drop_graphs(c);
+      return EP_TV_OK;
     case EP_TV_OPT_TILE_ROWS: {
       if (value < 2 || value > 4096 || value % 2)
         return fail(c, EP_TV_E_ARG, "tile rows must be even and in [2, 4096]");
@@ -1078,6 +1122,7 @@ int ep_tv_get_option(ep_tv_ctx* c, int32_t option, int64_t* value) {
   switch (option) {
     case EP_TV_OPT_GRAPH: *value = c->use_graph ? 1 : 0; return EP_TV_OK;
     case EP_TV_OPT_TILE_ROWS: *value = c->chunk_rows; return EP_TV_OK;
+    case EP_TV_OPT_EM_OPTION: *value = c->sa.em_opt; return EP_TV_OK;
     default: return fail(c, EP_TV_E_ARG, "unknown option");
   }
 }

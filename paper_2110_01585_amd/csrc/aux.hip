@@ -41,7 +41,8 @@ struct SitePtrs {
 __global__ __launch_bounds__(256) void k_init_cold(SitePtrs sp, const float* __restrict__ y_pix,
                                                    const InstDev* __restrict__ inst,
                                                    const InstState* __restrict__ st,
-                                                   const int4* __restrict__ tiles, int only_restart) {
+                                                   const int4* __restrict__ tiles, int only_restart,
+                                                   const float* __restrict__ wpix) {
   const int4 td = tiles[blockIdx.x];
   if (only_restart && !st[td.x].restart) return;
   const InstDev I = inst[td.x];
@@ -53,7 +54,8 @@ __global__ __launch_bounds__(256) void k_init_cold(SitePtrs sp, const float* __r
     const int c = b.c0 + i % cols;
     const long long p = I.off + (long long)r * I.pitch + c;
     const float yv = y_pix[p];
-    sp.S[0][p] = make_float2(I.inv_xi, yv * I.inv_xi);
+    const float w = I.wmap ? wpix[p] : I.inv_xi;   // noise precision of the pixel
+    sp.S[0][p] = make_float2(w, yv * w);
 #pragma unroll
     for (int kk = 0; kk < 4; ++kk)
       sp.S[kk + 1][p] = covered(kk, r, c, I) ? make_float2(kSiteInitPrec, 0.f) : make_float2(0.f, 0.f);
@@ -62,12 +64,12 @@ __global__ __launch_bounds__(256) void k_init_cold(SitePtrs sp, const float* __r
 
 hipError_t launch_init_cold(float2* const S[5], const float* y_pix, const InstDev* inst,
                             InstState* st, const int4* tiles, int ntiles, hipStream_t s,
-                            bool only_restart) {
+                            bool only_restart, const float* wpix) {
   SitePtrs sp;
   for (int k = 0; k < 5; ++k) sp.S[k] = S[k];
   if (ntiles == 0) return hipSuccess;
   hipLaunchKernelGGL(k_init_cold, dim3(ntiles), dim3(256), 0, s, sp, y_pix, inst, st, tiles,
-                     only_restart ? 1 : 0);
+                     only_restart ? 1 : 0, wpix);
   return hipGetLastError();
 }
 
@@ -191,7 +193,8 @@ __global__ __launch_bounds__(256) void k_warm_write(SitePtrs sp, const float* __
                                                     const InstState* __restrict__ st,
                                                     const int4* __restrict__ tiles,
                                                     const float* const* __restrict__ mu_tab,
-                                                    const float* const* __restrict__ var_tab) {
+                                                    const float* const* __restrict__ var_tab,
+                                                    const float* __restrict__ wpix) {
   const int4 td = tiles[blockIdx.x];
   if (!st[td.x].warm_ok) return;                 // rejected: the cold sites stay
   const InstDev I = inst[td.x];
@@ -215,9 +218,10 @@ __global__ __launch_bounds__(256) void k_warm_write(SitePtrs sp, const float* __
     float tk, ek;
     if (I.op == OP_IDENTITY) {
       const float yv = y_pix[p];
-      sp.S[0][p] = make_float2(I.inv_xi, yv * I.inv_xi);
-      const float rest = fmaxf(prec - I.inv_xi, (float)cnt * kSiteInitPrec);
-      const float rest_eta = m * (I.inv_xi + rest) - yv * I.inv_xi;
+      const float w = I.wmap ? wpix[p] : I.inv_xi;
+      sp.S[0][p] = make_float2(w, yv * w);
+      const float rest = fmaxf(prec - w, (float)cnt * kSiteInitPrec);
+      const float rest_eta = m * (w + rest) - yv * w;
       const float share = cnt ? 1.f / (float)cnt : 0.f;
       tk = rest * share;
       ek = rest_eta * share;
@@ -236,7 +240,7 @@ hipError_t launch_init_warm(float2* const S[5], const float* y_pix, const InstDe
                             InstState* st, int n, const int4* tiles, int ntiles,
                             const float* const* mu_tab, const float* const* var_tab,
                             double lambda_scale, double lambda_power, double* part_a,
-                            unsigned* part_f, hipStream_t s) {
+                            unsigned* part_f, hipStream_t s, const float* wpix) {
   if (ntiles == 0) return hipSuccess;
   SitePtrs sp;
   for (int k = 0; k < 5; ++k) sp.S[k] = S[k];
@@ -245,7 +249,91 @@ hipError_t launch_init_warm(float2* const S[5], const float* y_pix, const InstDe
   hipLaunchKernelGGL(k_warm_fin, dim3(n), dim3(256), 0, s, inst, st, part_a, part_f, lambda_scale,
                      lambda_power);
   hipLaunchKernelGGL(k_warm_write, dim3(ntiles), dim3(256), 0, s, sp, y_pix, inst, st, tiles, mu_tab,
-                     var_tab);
+                     var_tab, wpix);
+  return hipGetLastError();
+}
+
+// Option 1 of the approximations of a_0: every pixel of the tile adds its edge
+// to the right neighbour and to the lower one (with the wrap-around pairs of a
+// periodic boundary), E|x_i - x_j| under Q(x) = N(mu, diag v).  Block sums in
+// a fixed order.
+__global__ __launch_bounds__(256) void k_em_ax(SitePtrs sp, const InstDev* __restrict__ inst,
+                                               const InstState* __restrict__ st,
+                                               const int4* __restrict__ tiles, double* part) {
+  __shared__ double red[256];
+  const int4 td = tiles[blockIdx.x];
+  const InstDev I = inst[td.x];
+  double acc = 0.0;
+  if (st[td.x].active) {
+    const TileBox b = tile_box(td, I);
+    const bool per = I.bnd == BND_PERIODIC;
+    const int cols = b.c1 - b.c0;
+    const int n = cols * (b.r1 - b.r0);
+    auto moments = [&](int r, int c, double& mu, double& v) {
+      const long long p = I.off + (long long)r * I.pitch + c;
+      double t = 0.0, e = 0.0;
+#pragma unroll
+      for (int k = 0; k < 5; ++k) {
+        const float2 s2 = sp.S[k][p];
+        t += (double)s2.x;
+        e += (double)s2.y;
+      }
+      mu = e / t;
+      v = 1.0 / t;
+    };
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+      const int r = b.r0 + i / cols, c = b.c0 + i % cols;
+      double m0, v0, m1, v1;
+      moments(r, c, m0, v0);
+      if (c + 1 < I.W || (per && I.W > 1)) {
+        moments(r, c + 1 < I.W ? c + 1 : 0, m1, v1);
+        acc += folded_mean(m0 - m1, v0 + v1);
+      }
+      if (r + 1 < I.H || (per && I.H > 1)) {
+        moments(r + 1 < I.H ? r + 1 : 0, c, m1, v1);
+        acc += folded_mean(m0 - m1, v0 + v1);
+      }
+    }
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 128; w >= 1; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+hipError_t launch_em_ax(float2* const S[5], const InstDev* inst, const InstState* st,
+                        const int4* tiles, int ntiles, double* part, hipStream_t s) {
+  SitePtrs sp;
+  for (int k = 0; k < 5; ++k) sp.S[k] = S[k];
+  if (ntiles == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_em_ax, dim3(ntiles), dim3(256), 0, s, sp, inst, st, tiles, part);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void k_noise_prec(float* __restrict__ wpix,
+                                                    const InstDev* __restrict__ inst,
+                                                    const int4* __restrict__ tiles,
+                                                    const float* const* __restrict__ var_tab) {
+  const int4 td = tiles[blockIdx.x];
+  const InstDev I = inst[td.x];
+  const float* v = var_tab[td.x];
+  if (!I.wmap || !v) return;
+  const TileBox b = tile_box(td, I);
+  const int cols = b.c1 - b.c0;
+  const int n = cols * (b.r1 - b.r0);
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    const int r = b.r0 + i / cols, c = b.c0 + i % cols;
+    wpix[I.off + (long long)r * I.pitch + c] = 1.f / v[(long long)r * I.W + c];
+  }
+}
+
+hipError_t launch_noise_prec(float* wpix, const InstDev* inst, const int4* tiles, int ntiles,
+                             const float* const* var_tab, hipStream_t s) {
+  if (ntiles == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_noise_prec, dim3(ntiles), dim3(256), 0, s, wpix, inst, tiles, var_tab);
   return hipGetLastError();
 }
 

@@ -30,7 +30,7 @@ struct InstDev {
   int H, W, pitch, bnd;
   long long off;             // element offset of pixel (0, 0) in every plane
   int op, strips, chunks, tile0;
-  int ntiles, chunk_rows, npix, pad0;
+  int ntiles, chunk_rows, npix, wmap;     // wmap: per-pixel noise precisions (identity operator)
   float xi, inv_xi, alpha, pad1;
   int lik_tile0, lik_ntiles;               // likelihood-kernel tiles (non-identity operators)
   int pad2, pad3;
@@ -81,6 +81,7 @@ struct SweepArgs {
   unsigned* part_flags;
   const float* part_mu;      // per likelihood tile: max |mu| after the likelihood-site update
   int prior;                 // PRIOR_* of every instance of the context
+  int em_opt;                // EM approximation of a_0 (Sec. IV): 1, 2 or 3 (l1 only)
 };
 
 // Map a block index so that consecutive tiles land on the same XCD (workgroups
@@ -101,10 +102,19 @@ hipError_t launch_tilted(int n, const float* m, const float* s, float lam, float
 hipError_t launch_tilted_mixture(int n, const float* m, const float* s, float dla, float dv,
                                  float v1, float v2, float* rho, float* del, float* eabs,
                                  hipStream_t st);
-// only_restart: re-initialise only the instances whose InstState::restart is set
+// only_restart: re-initialise only the instances whose InstState::restart is set.
+// wpix: per-pixel noise precisions of instances with InstDev::wmap (else unused).
 hipError_t launch_init_cold(float2* const S[5], const float* y_pix, const InstDev* inst,
                             InstState* st, const int4* tiles, int ntiles, hipStream_t s,
-                            bool only_restart = false);
+                            bool only_restart = false, const float* wpix = nullptr);
+// Option 1 of the EM approximations of a_0 (Sec. IV): per sweep tile, the sum
+// over the edges owned by its pixels (right and lower neighbour) of
+// E|x_i - x_j| under the global Q(x) of the sites S, into part.
+hipError_t launch_em_ax(float2* const S[5], const InstDev* inst, const InstState* st,
+                        const int4* tiles, int ntiles, double* part, hipStream_t s);
+// 1 / var into the per-pixel noise-precision plane, for the given instances.
+hipError_t launch_noise_prec(float* wpix, const InstDev* inst, const int4* tiles, int ntiles,
+                             const float* const* var_tab, hipStream_t s);
 hipError_t launch_finalize(const InstDev* inst, InstState* st, int n, const SweepArgs& a,
                            int em, double tol, hipStream_t s);
 hipError_t launch_marginals(float2* const S[5], const InstDev* inst, const int4* tiles, int ntiles,
@@ -121,6 +131,6 @@ hipError_t launch_init_warm(float2* const S[5], const float* y_pix, const InstDe
                             InstState* st, int n, const int4* tiles, int ntiles,
                             const float* const* mu_tab, const float* const* var_tab,
                             double lambda_scale, double lambda_power, double* part_a,
-                            unsigned* part_f, hipStream_t s);
+                            unsigned* part_f, hipStream_t s, const float* wpix = nullptr);
 
 }  // namespace eptv

@@ -288,6 +288,9 @@ __device__ __forceinline__ void finish_row(const SweepArgs& a, long long idx, bo
 __device__ __forceinline__ void make_factor(const InstDev&, const InstState& st, L1Factor& f) {
   f.lam = (float)st.lam;
 }
+__device__ __forceinline__ void make_factor(const InstDev&, const InstState& st, L1FactorQu& f) {
+  f.lam = (float)st.lam;
+}
 __device__ __forceinline__ void make_factor(const InstDev& I, const InstState&, MixtureFactor& f) {
   f.f.dla = I.mix_dla;
   f.f.dv = I.mix_dv;
@@ -564,7 +567,11 @@ hipError_t launch_tv_sweep(const SweepArgs& a, bool want_delta, hipStream_t s) {
   const int blocks = (a.ntiles + kWavesPerBlock - 1) / kWavesPerBlock;
   if (blocks == 0) return hipSuccess;
   const dim3 g(blocks), b(kWavesPerBlock * kWave);
-  if (a.prior == PRIOR_L1) {
+  if (a.prior == PRIOR_L1 && a.em_opt == 2) {
+    // EM with option 2: the sweep accumulates E|u| under Q(u) instead
+    if (want_delta) hipLaunchKernelGGL((k_tv_sweep<true, L1FactorQu>), g, b, 0, s, a);
+    else hipLaunchKernelGGL((k_tv_sweep<false, L1FactorQu>), g, b, 0, s, a);
+  } else if (a.prior == PRIOR_L1) {
     if (want_delta) hipLaunchKernelGGL((k_tv_sweep<true, L1Factor>), g, b, 0, s, a);
     else hipLaunchKernelGGL((k_tv_sweep<false, L1Factor>), g, b, 0, s, a);
   } else {

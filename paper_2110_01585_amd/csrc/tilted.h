@@ -170,6 +170,26 @@ struct L1Factor {
     return __builtin_fmaf(-T.rho, c_own, s);
   }
 };
+// The l1 factor with the EM sum of option 2 of Sec. IV in place of option 3:
+// eabs is E|u| under Q(u_n) = N(m_bar, S_bar), the Gaussian with the tilted
+// moments (a folded-normal mean), instead of the tilted E|u| itself.
+struct L1FactorQu {
+  float lam;
+  __device__ __forceinline__ Tilt tilt(float m, float s) const {
+    Tilt T = laplace_tilt(m, s, lam);
+    const float mb = fabsf(m + T.delta);
+    const float Sb = fmaxf(s * (1.0f - T.rho), 0.0f);
+    const float sd = __builtin_amdgcn_sqrtf(Sb);
+    const float kSqrt2OverPi = 0.797884560802865406f;
+    T.eabs = Sb > 0.0f ? sd * kSqrt2OverPi * __expf(-0.5f * mb * mb / Sb) +
+                             mb * erff(mb * 0.707106781186547573f / sd)
+                       : mb;
+    return T;
+  }
+  __device__ __forceinline__ float den(const Tilt& T, float s, float c_own, float) const {
+    return __builtin_fmaf(-T.rho, c_own, s);
+  }
+};
 struct MixtureFactor {
   MixFactor f;
   __device__ __forceinline__ Tilt tilt(float m, float s) const { return mixture_tilt(m, s, f); }
