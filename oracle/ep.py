@@ -167,7 +167,7 @@ class EPProblem:
 def problem_from_synthetic(p, prior="l1", estimator="spectral", boundary=None, order=(1, 2, 3, 4),
                            lam=None, damping=None, rbmc_noise=None, em_option=3):
     """Build an EPProblem from a synthetic.Problem."""
-    op = ops.Operator(p.op, p.shape, taps=p.taps, mask=p.mask)
+    op = ops.Operator(p.op, p.shape, taps=p.taps, mask=p.mask, sense=getattr(p, "sense", None))
     return EPProblem(p.y, op, p.xi, p.lam0 if lam is None else lam,
                      damping=p.damping if damping is None else damping, prior=prior,
                      boundary=p.boundary if boundary is None else boundary, order=order,
@@ -185,7 +185,7 @@ def init_cold(pb: EPProblem) -> EPState:
     eta = np.zeros((5, N))
     prec0 = 1.0 / pb.xi if pb.noise_prec is None else pb.noise_prec
     tau[0] = prec0
-    y0 = pb.hty if pb.op.kind in (ops.DFT, ops.HADAMARD) else np.asarray(pb.y, dtype=np.float64)
+    y0 = pb.hty if pb.op.kind in (ops.DFT, ops.HADAMARD, ops.GAUSS) else np.asarray(pb.y, dtype=np.float64)
     eta[0] = y0.ravel() * prec0
     for k in range(4):
         tau[k + 1, pb.covered[k]] = SITE_INIT_PREC
@@ -305,7 +305,8 @@ def solve(pb: EPProblem, sweeps: int, em: bool, tol: Optional[float] = None,
     Stops as well, with info["diverged"], once the divergence rule holds
     (DIVERGE_FACTOR).  Returns (mu, v, state, info)."""
     st = init_cold(pb) if state is None else state
-    yr = np.asarray(pb.hty if pb.op.kind in (ops.DFT, ops.HADAMARD) else pb.y, dtype=np.float64)
+    yr = np.asarray(pb.hty if pb.op.kind in (ops.DFT, ops.HADAMARD, ops.GAUSS) else pb.y,
+                    dtype=np.float64)
     yrange = float(yr.max() - yr.min()) or 1.0
     yscale = max(float(yr.max() - yr.min()), float(np.abs(yr).max()))
     mu_prev, v_prev = marginals(st)

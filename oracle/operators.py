@@ -12,6 +12,15 @@ Sec. II-A, Eq. (1): y = H x + n, n ~ N(0, xi I).  Three operators:
   Fourier sensing matrix): observations are the masked complex coefficients of
   F x.  Treating (Re, Im) of each kept coefficient as two real observations of
   variance xi gives H^T H x = Re(F^H P F x) and H^T y = Re(F^H P y);
+* dense Gaussian i.i.d. sensing matrix (compressive sensing, case (iii) with
+  the paper's random matrix, Sec. V): H is given (M x N, acting on the image
+  flattened row-major); H^T H is neither diagonal nor circulant, so the
+  likelihood site's mean and variances come from the Woodbury identity the
+  paper names for low-rank H^T H (M < N): with D = diag(tau_c) and
+  S = xi I_M + H D^{-1} H^T = L L^T (Cholesky), Z = L^{-1} H,
+      (H^T H / xi + D)^{-1} = D^{-1} - D^{-1} Z^T Z D^{-1},
+  so v_i = 1/d_i - |z_i|^2 / d_i^2 (z_i column i of Z) and
+  E = D^{-1} (b - Z^T (Z D^{-1} b));
 * subsampled Paley-ordered 2-D Walsh-Hadamard transform (compressive sensing,
   case (iii) with the paper's Hadamard sensing matrix, Sec. II-A and the CS
   experiment of Sec. V): observations are the kept coefficients
@@ -57,6 +66,7 @@ IDENTITY = "identity"
 BLUR = "blur"
 DFT = "dft"
 HADAMARD = "hadamard"
+GAUSS = "gauss"
 
 
 def walsh_paley(n):
@@ -79,9 +89,12 @@ def walsh_paley(n):
 
 
 class Operator:
-    def __init__(self, kind, shape, taps=None, mask=None):
+    def __init__(self, kind, shape, taps=None, mask=None, sense=None):
         self.kind = kind
         self.shape = tuple(shape)
+        self.sense = None if sense is None else np.asarray(sense, dtype=np.float64)
+        if kind == GAUSS and (self.sense is None or self.sense.shape[1] != self.shape[0] * self.shape[1]):
+            raise ValueError("the Gaussian operator needs an M x (h w) sensing matrix")
         self.taps = None if taps is None else np.asarray(taps, dtype=np.float64)
         self.mask = None if mask is None else np.asarray(mask).astype(bool)
         if kind == BLUR:
@@ -110,6 +123,8 @@ class Operator:
         spectrum (h, w) with zeros off the mask."""
         if self.kind == IDENTITY:
             return x.copy()
+        if self.kind == GAUSS:
+            return self.sense @ np.asarray(x, np.float64).ravel()
         if self.kind == BLUR:
             kh, kw = self.taps.shape
             out = np.zeros_like(x)
@@ -126,6 +141,8 @@ class Operator:
         """Adjoint: real image."""
         if self.kind == IDENTITY:
             return np.asarray(v, dtype=np.float64).copy()
+        if self.kind == GAUSS:
+            return (self.sense.T @ np.asarray(v, np.float64)).reshape(self.shape)
         if self.kind == BLUR:
             kh, kw = self.taps.shape
             out = np.zeros_like(v)
@@ -168,7 +185,7 @@ class Operator:
         """H^T H x through the spectrum (FFT); tests pin it to Ht(H(x))."""
         if self.kind == IDENTITY:
             return x.copy()
-        if self.kind == HADAMARD:
+        if self.kind in (HADAMARD, GAUSS):
             return self.Ht(self.H(x))
         return np.real(np.fft.ifft2(np.fft.fft2(x) * self.spectrum()))
 
@@ -201,6 +218,22 @@ class Operator:
         return A
 
 
+def woodbury_moments(op: Operator, xi, tau_c, b):
+    """Mean (H^T H / xi + D)^{-1} b and the diagonal of (H^T H / xi + D)^{-1},
+    D = diag(tau_c), by the Woodbury identity (see the module header); the
+    Cholesky factor and the triangular solve are library routines."""
+    from scipy.linalg import cholesky, solve_triangular
+    H = op.sense
+    d = np.asarray(tau_c, np.float64).ravel()
+    S = xi * np.eye(H.shape[0]) + (H / d) @ H.T
+    L = cholesky(S, lower=True)
+    Z = solve_triangular(L, H, lower=True)
+    v = 1.0 / d - (Z * Z).sum(axis=0) / (d * d)
+    bv = np.asarray(b, np.float64).ravel()
+    E = (bv - Z.T @ (Z @ (bv / d))) / d
+    return E.reshape(op.shape), v.reshape(op.shape)
+
+
 def solve_tilted_mean(op: Operator, xi, tau_c, b, x0=None, rtol=1e-12, maxiter=5000):
     """E = (H^T H / xi + diag(tau_c))^{-1} b by preconditioned conjugate
     gradients (the paper's suggestion for the mean of Eq. (tilted_P_1)).
@@ -212,6 +245,8 @@ def solve_tilted_mean(op: Operator, xi, tau_c, b, x0=None, rtol=1e-12, maxiter=5
     h, w = op.shape
     if op.kind == IDENTITY:
         return b / (1.0 / xi + tau_c), 0
+    if op.kind == GAUSS:
+        return woodbury_moments(op, xi, tau_c, b)[0], 0
     spec = op.spectrum()
     dbar = float(np.mean(tau_c))
     pre = 1.0 / (spec / xi + dbar)
@@ -284,6 +319,9 @@ def tilted_variance(op: Operator, xi, tau_c, estimator="spectral", rbmc: RBMCSam
         if rbmc is None:
             raise ValueError("the RBMC estimator needs its white-noise samples")
         return rbmc_variance(op, xi, tau_c, rbmc)
+    if op.kind == GAUSS or estimator == "woodbury":
+        # exact; the right-hand side does not enter the diagonal
+        return woodbury_moments(op, xi, tau_c, np.zeros(op.shape))[1]
     if estimator == "exact":
         A = op.dense_HtH() / xi + np.diag(tau_c.ravel())
         return np.diag(np.linalg.inv(A)).reshape(op.shape).copy()

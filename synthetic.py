@@ -33,6 +33,7 @@ OP_IDENTITY = "identity"
 OP_BLUR = "blur"
 OP_DFT = "dft"
 OP_HADAMARD = "hadamard"
+OP_GAUSS = "gauss"
 
 
 def rng_for(config: int, instance: int = 0) -> np.random.Generator:
@@ -186,7 +187,8 @@ class Problem:
     """One restoration instance: what a caller hands to a solver."""
     name: str
     x_true: np.ndarray
-    y: np.ndarray                     # real (h, w); complex (h, w) for OP_DFT (0 off-mask)
+    y: np.ndarray                     # real (h, w); complex (h, w) for OP_DFT (0 off-mask);
+                                      # (M,) for OP_GAUSS
     op: str
     xi: float                         # noise variance per real observation
     lam0: float                       # initial (or fixed) lambda
@@ -197,6 +199,7 @@ class Problem:
     mask: Optional[np.ndarray] = None
     boundary: str = "free"
     meta: dict = field(default_factory=dict)
+    sense: Optional[np.ndarray] = None   # OP_GAUSS: M x N sensing matrix (float32 values)
 
     @property
     def shape(self):
@@ -243,6 +246,21 @@ def make_hadamard_cs(h, w, n_shapes, sigma, frac, rng, mode="paint", lam0=1.0, d
     Y = np.where(mask.astype(bool), Y, 0.0)
     return Problem(name, x, Y, OP_HADAMARD, sigma * sigma, lam0, damping, sweeps, em,
                    mask=mask, meta={"sigma": sigma, "frac": frac})
+
+
+def make_gauss_cs(h, w, n_shapes, sigma, frac, rng, mode="paint", lam0=1.0, damping=0.5,
+                  sweeps=100, em=True, name="gcs"):
+    """Compressive sensing with a Gaussian i.i.d. sensing matrix (Sec. II-A case
+    (iii), the CS experiment of Sec. V): M = round(frac h w) rows with entries
+    N(0, 1/M), rounded to float32; y = H vec(x) + noise of standard deviation
+    sigma (x row-major)."""
+    x = piecewise_image(h, w, n_shapes, rng, mode=mode)
+    n = h * w
+    m = max(1, int(round(frac * n)))
+    H = (rng.standard_normal((m, n)) / math.sqrt(m)).astype(np.float32).astype(np.float64)
+    y = H @ x.ravel() + sigma * rng.standard_normal(m)
+    return Problem(name, x, y, OP_GAUSS, sigma * sigma, lam0, damping, sweeps, em, sense=H,
+                   meta={"sigma": sigma, "frac": frac})
 
 
 # --------------------------------------------------------------------------
