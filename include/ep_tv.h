@@ -26,7 +26,7 @@
  *    workspace given to ep_tv_create, which must stay alive and untouched by the
  *    caller until ep_tv_destroy.
  *  - Images are row-major, dense, float32: pixel (r, c) of an H x W image is
- *    element r * W + c.  Pixel arrays passed per instance are given as a host
+ *    element r * W + c.  (EP_TV_OP_GAUSS_CS observations are M floats.)  Pixel arrays passed per instance are given as a host
  *    array of n_problems device pointers.
  *  - All GPU work is enqueued on the HIP stream given to ep_tv_create.  Calls
  *    documented as "asynchronous" return before the GPU has finished; calls
@@ -66,9 +66,15 @@ enum {
   EP_TV_OP_IDENTITY = 0,       /* denoising: H = I */
   EP_TV_OP_BLUR_PERIODIC = 1,  /* deconvolution: periodic 2-D convolution with given taps */
   EP_TV_OP_DFT_MASK = 2,       /* CS: subset of orthonormal 2-D DFT coefficients */
-  EP_TV_OP_HADAMARD_MASK = 3   /* CS: subset of orthonormal 2-D Walsh-Hadamard coefficients,
+  EP_TV_OP_HADAMARD_MASK = 3,  /* CS: subset of orthonormal 2-D Walsh-Hadamard coefficients,
                                   Paley order along each axis (Sec. II-A case (iii), Sec. V).
                                   DFT and Hadamard: power-of-two sides in [4, 4096] */
+  EP_TV_OP_GAUSS_CS = 4        /* CS: a dense M x N sensing matrix (e.g. Gaussian i.i.d.,
+                                  Sec. II-A case (iii), Sec. V) acting on the image flattened
+                                  row-major.  The likelihood site's mean and variances come
+                                  from the Woodbury identity (Sec. III-C: H^T H of rank M < N),
+                                  in FP64 on the matrix cores; N = height*width <= 65536,
+                                  M in [1, 32768] */
 };
 
 /* Image boundary for the pixel-pair graph.  FREE: pairs inside the image only;
@@ -121,6 +127,10 @@ typedef struct {
                                   notes that the likelihood factor stays exact for denoising:
                                   q_{x,0} = N(y, diag(xi_i))); 0: i.i.d. noise of variance
                                   noise_var (which then only sets the range of valid inputs) */
+  const float* sense_matrix;   /* EP_TV_OP_GAUSS_CS: host, sense_rows x (height*width),
+                                  row-major; copied by ep_tv_create */
+  int32_t sense_rows;          /* EP_TV_OP_GAUSS_CS: M */
+  int32_t reserved;            /* 0 */
 } ep_tv_problem;
 
 /* Estimators of diag Cov_{P_0}, the tilted variances of the likelihood site
@@ -344,6 +354,11 @@ typedef struct {
   double rf_inv_ms;  int32_t rf_inv_launches;
   double fin_ms;     int32_t fin_launches;
   double lik_other_ms; int32_t lik_other_launches;
+  /* EP_TV_OP_GAUSS_CS: the FP64 GEMM launches of the Woodbury moments (S = xi I
+   * + H D^-1 H^T, the Cholesky trailing updates, the blocked triangular solve)
+   * and their floating-point operations */
+  double dgemm_ms;   int32_t dgemm_launches;
+  double dgemm_flops;
 } ep_tv_timing;
 
 int ep_tv_set_timing(ep_tv_ctx* ctx, int32_t enable);

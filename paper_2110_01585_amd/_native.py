@@ -25,6 +25,7 @@ OP_IDENTITY = 0
 OP_BLUR_PERIODIC = 1
 OP_DFT_MASK = 2
 OP_HADAMARD_MASK = 3
+OP_GAUSS_CS = 4
 BND_FREE = 0
 BND_PERIODIC = 1
 PRECOND_AUTO = 0
@@ -56,7 +57,9 @@ class EpTvProblem(ctypes.Structure):
                 ("prior", ctypes.c_int32), ("var_estimator", ctypes.c_int32),
                 ("prior_omega", ctypes.c_double), ("prior_s1sq", ctypes.c_double),
                 ("prior_s2sq", ctypes.c_double),
-                ("rbmc_samples", ctypes.c_int32), ("noise_map", ctypes.c_int32)]
+                ("rbmc_samples", ctypes.c_int32), ("noise_map", ctypes.c_int32),
+                ("sense_matrix", ctypes.POINTER(ctypes.c_float)), ("sense_rows", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class EpTvStats(ctypes.Structure):
@@ -79,7 +82,9 @@ class EpTvTiming(ctypes.Structure):
                 ("rf_filt_ms", ctypes.c_double), ("rf_filt_launches", ctypes.c_int32),
                 ("rf_inv_ms", ctypes.c_double), ("rf_inv_launches", ctypes.c_int32),
                 ("fin_ms", ctypes.c_double), ("fin_launches", ctypes.c_int32),
-                ("lik_other_ms", ctypes.c_double), ("lik_other_launches", ctypes.c_int32)]
+                ("lik_other_ms", ctypes.c_double), ("lik_other_launches", ctypes.c_int32),
+                ("dgemm_ms", ctypes.c_double), ("dgemm_launches", ctypes.c_int32),
+                ("dgemm_flops", ctypes.c_double)]
 
 
 class EpTvTuneResult(ctypes.Structure):

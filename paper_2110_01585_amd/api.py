@@ -44,10 +44,11 @@ class ProblemSpec:
     var_estimator: int = N.VAR_SPECTRAL
     rbmc_samples: int = 0
     noise_map: bool = False      # per-pixel noise variances (identity operator)
+    sense: Optional[np.ndarray] = None   # Gaussian CS: M x (H W) sensing matrix
 
 
 _OPS = {"identity": N.OP_IDENTITY, "blur": N.OP_BLUR_PERIODIC, "dft": N.OP_DFT_MASK,
-        "hadamard": N.OP_HADAMARD_MASK}
+        "hadamard": N.OP_HADAMARD_MASK, "gauss": N.OP_GAUSS_CS}
 _BNDS = {"free": N.BND_FREE, "periodic": N.BND_PERIODIC}
 
 
@@ -64,7 +65,9 @@ def spec_from_synthetic(p, lam0=None, damping=None, cg_tol=0.0, cg_max_iters=0,
                        cg_tol=cg_tol, cg_max_iters=cg_max_iters, cg_precond=cg_precond,
                        cg_reduce=cg_reduce,
                        var_estimator=N.VAR_RBMC if rbmc_samples else N.VAR_SPECTRAL,
-                       rbmc_samples=int(rbmc_samples))
+                       rbmc_samples=int(rbmc_samples),
+                       sense=None if getattr(p, "sense", None) is None
+                       else np.asarray(p.sense, np.float32))
 
 
 def _problems(specs: Sequence[ProblemSpec]):
@@ -79,6 +82,11 @@ def _problems(specs: Sequence[ProblemSpec]):
         a.prior, a.prior_omega, a.prior_s1sq, a.prior_s2sq = s.prior, s.prior_omega, s.prior_s1sq, s.prior_s2sq
         a.var_estimator, a.rbmc_samples = s.var_estimator, s.rbmc_samples
         a.noise_map = 1 if s.noise_map else 0
+        if s.sense is not None:
+            hm = np.ascontiguousarray(s.sense, dtype=np.float32)
+            keep.append(hm)
+            a.sense_matrix = hm.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+            a.sense_rows = hm.shape[0]
         if s.taps is not None:
             t = np.ascontiguousarray(s.taps, dtype=np.float32)
             keep.append(t)
@@ -202,8 +210,13 @@ class Context:
 
     # -- entry points --
     def ep_tv_set_observation(self, ys):
-        ys = [self._dev(y, (s.height, s.width) if s.op != N.OP_DFT_MASK else (s.height, s.width, 2))
-              for y, s in zip(ys, self.specs)]
+        def shape(s):
+            if s.op == N.OP_DFT_MASK:
+                return (s.height, s.width, 2)
+            if s.op == N.OP_GAUSS_CS:
+                return (s.sense.shape[0],)
+            return (s.height, s.width)
+        ys = [self._dev(y, shape(s)) for y, s in zip(ys, self.specs)]
         self._y = ys
         return self._check(N.lib().ep_tv_set_observation(self.handle, _ptrs(ys)), "set_observation")
 

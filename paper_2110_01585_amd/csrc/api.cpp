@@ -98,7 +98,14 @@ void assign_tiles(std::vector<InstHost>& ih, int rows) {
 const char* validate(const ep_tv_problem& p) {
   if (p.height < 1 || p.width < 1 || p.height > 16384 || p.width > 16384)
     return "height and width must be in [1, 16384]";
-  if (p.op < EP_TV_OP_IDENTITY || p.op > EP_TV_OP_HADAMARD_MASK) return "unknown operator";
+  if (p.op < EP_TV_OP_IDENTITY || p.op > EP_TV_OP_GAUSS_CS) return "unknown operator";
+  if (p.op == EP_TV_OP_GAUSS_CS) {
+    if (!p.sense_matrix) return "the Gaussian CS operator needs sense_matrix";
+    if (p.sense_rows < 1 || p.sense_rows > 32768) return "sense_rows must be in [1, 32768]";
+    if ((long long)p.height * p.width > 65536) return "the Gaussian CS operator needs at most 65536 pixels";
+    if (p.var_estimator != EP_TV_VAR_SPECTRAL)
+      return "the Gaussian CS operator computes its variances exactly (Woodbury)";
+  }
   if (p.boundary != EP_TV_BND_FREE && p.boundary != EP_TV_BND_PERIODIC) return "unknown boundary";
   if (p.boundary == EP_TV_BND_PERIODIC && (p.height % 2 || p.width % 2 || p.height < 2 || p.width < 2))
     return "periodic boundary needs even height and width";
@@ -199,6 +206,7 @@ void make_layout(std::vector<InstHost>& ih, int rows, Layout& L) {
     li[i].tw = ih[i].p.op == EP_TV_OP_BLUR_PERIODIC ? ih[i].p.blur_w : 0;
     li[i].precond_req = ih[i].p.cg_precond;
     li[i].rbmc_ns = rbmc_ns(ih[i].p);
+    li[i].sense_rows = ih[i].p.op == EP_TV_OP_GAUSS_CS ? ih[i].p.sense_rows : 0;
   }
   lik_layout(li.data(), n, L.plane, take, L.lik);
   L.total = cur;
@@ -497,6 +505,8 @@ int ep_tv_create(const ep_tv_problem* p, int32_t n, void* d_ws, size_t ws_bytes,
       li[i].tw = c->ih[i].p.blur_w;
       li[i].mask = c->ih[i].mask.empty() ? nullptr : c->ih[i].mask.data();
       li[i].rbmc_ns = rbmc_ns(c->ih[i].p);
+      li[i].sense = c->ih[i].p.sense_matrix;
+      li[i].sense_rows = c->ih[i].p.sense_rows;
       li[i].tile0 = c->ih[i].tile0;
       li[i].ntiles = c->ih[i].ntiles;
     }
@@ -579,7 +589,8 @@ int ep_tv_set_observation(ep_tv_ctx* c, const float* const* d_y) {
   for (int i = 0; i < c->n; ++i) {
     if (!d_y[i]) return fail(c, EP_TV_E_ARG, "null observation pointer");
     const InstHost& h = c->ih[i];
-    if (h.p.op == EP_TV_OP_DFT_MASK || h.p.op == EP_TV_OP_HADAMARD_MASK) continue;
+    if (h.p.op == EP_TV_OP_DFT_MASK || h.p.op == EP_TV_OP_HADAMARD_MASK || h.p.op == EP_TV_OP_GAUSS_CS)
+      continue;   // the likelihood setup writes H^T y as the pixel-space observation
     HIPCHK(c, hipMemcpy2DAsync(c->ypix + h.off, sizeof(float) * h.pitch, d_y[i],
                                sizeof(float) * h.p.width, sizeof(float) * h.p.width, h.p.height,
                                hipMemcpyDeviceToDevice, c->stream));
@@ -755,7 +766,7 @@ static int advance(ep_tv_ctx* c, int n, int em, bool delta, double tol) {
     return fail(c, EP_TV_E_STATE, "the RBMC estimator needs ep_tv_set_rbmc_noise first");
   if (c->any_noise_map && !c->noise_set)
     return fail(c, EP_TV_E_STATE, "per-pixel noise variances not set (ep_tv_set_noise_variance)");
-  if (!c->use_graph || c->lik.rbmc_ns_max) {
+  if (!c->use_graph || c->lik.rbmc_ns_max || !c->lik.gauss.empty()) {
     for (int t = 0; t < n; ++t) {
       int rc = one_sweep(c, em, delta, tol);
       if (rc) return rc;
@@ -1085,6 +1096,9 @@ int ep_tv_get_timing(ep_tv_ctx* c, ep_tv_timing* out) {
   out->fin_launches = n[KT_FIN];
   out->lik_other_ms = ms[KT_OTHER];
   out->lik_other_launches = n[KT_OTHER];
+  out->dgemm_ms = ms[KT_DGEMM];
+  out->dgemm_launches = n[KT_DGEMM];
+  out->dgemm_flops = c->lik.dgemm_flops;
   return EP_TV_OK;
 }
 

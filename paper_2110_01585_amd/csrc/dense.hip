@@ -1,0 +1,401 @@
+// Gaussian i.i.d. compressive sensing: Woodbury moments of the likelihood site
+// (see dense.h).  FP64 throughout; the three large products (S = H D^-1 H^T,
+// the Cholesky trailing updates, the blocked triangular solve for Z^T) run on
+// one GEMM kernel built on v_mfma_f64_16x16x4f64.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "dense.h"
+
+namespace eptv {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+constexpr int kDT = 64;   // GEMM output tile and Cholesky block size
+constexpr int kDK = 16;   // K depth staged in LDS per round
+
+// C = beta C + alpha A diag(w) B^T (+ diag on the main diagonal): A is M x K
+// and B is N x K, both with k contiguous; w (length K) may be null.  With
+// `lower`, only the elements n <= m are written (tiles above the diagonal are
+// skipped).  One 64 x 64 output tile per workgroup, 4 waves of 32 x 32, each
+// as 2 x 2 blocks of 16 x 16 MFMA outputs.  MFMA operand layout (16x16x4
+// f64): lane l holds A[l % 16][l / 16] and B[l / 16][l % 16] (k = l / 16); the
+// result element (4 r + l / 16, l % 16) is register r of lane l.
+template <class TA, class TB>
+struct GemmArgs {
+  const TA* A;
+  long long lda;
+  const TB* B;
+  long long ldb;
+  const double* w;
+  double* C;
+  long long ldc;
+  int M, N, K;
+  double alpha, beta, diag;
+  int lower;
+  int nt_n;   // tiles along n
+};
+
+template <class TA, class TB>
+__global__ __launch_bounds__(256) void k_dgemm_nt(GemmArgs<TA, TB> g) {
+  __shared__ double As[kDT][kDK + 1];
+  __shared__ double Bs[kDT][kDK + 1];
+  const int tm = blockIdx.x / g.nt_n, tn = blockIdx.x % g.nt_n;
+  const int m0 = tm * kDT, n0 = tn * kDT;
+  if (g.lower && n0 > m0 + kDT - 1) return;   // whole tile above the diagonal
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+  d4 acc00 = {0, 0, 0, 0}, acc01 = acc00, acc10 = acc00, acc11 = acc00;
+  const int lr = t >> 2, lk = (t & 3) * 4;   // staging: row lr, k lk..lk+3
+  const int am = m0 + lr, bn = n0 + lr;
+  for (int k0 = 0; k0 < g.K; k0 += kDK) {
+    double av[4], bv[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int k = k0 + lk + u;
+      const bool kin = k < g.K;
+      av[u] = (am < g.M && kin) ? (double)g.A[(long long)am * g.lda + k] : 0.0;
+      bv[u] = (bn < g.N && kin) ? (double)g.B[(long long)bn * g.ldb + k] * (g.w ? g.w[k] : 1.0) : 0.0;
+    }
+    __syncthreads();   // the previous round's LDS reads are done
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      As[lr][lk + u] = av[u];
+      Bs[lr][lk + u] = bv[u];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < kDK; kk += 4) {
+      const int r = lane & 15, c = kk + (lane >> 4);
+      const double a0 = As[wm + r][c], a1 = As[wm + 16 + r][c];
+      const double b0 = Bs[wn + r][c], b1 = Bs[wn + 16 + r][c];
+      acc00 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc00, 0, 0, 0);
+      acc01 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc01, 0, 0, 0);
+      acc10 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc10, 0, 0, 0);
+      acc11 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc11, 0, 0, 0);
+    }
+  }
+  const d4* accs[4] = {&acc00, &acc01, &acc10, &acc11};
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int bi = q >> 1, bj = q & 1;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int m = m0 + wm + 16 * bi + 4 * r + (lane >> 4);
+      const int n = n0 + wn + 16 * bj + (lane & 15);
+      if (m < g.M && n < g.N && (!g.lower || n <= m)) {
+        double v = g.alpha * (*accs[q])[r];
+        if (g.beta != 0.0) v += g.beta * g.C[(long long)m * g.ldc + n];
+        if (m == n) v += g.diag;
+        g.C[(long long)m * g.ldc + n] = v;
+      }
+    }
+  }
+}
+
+template <class TA, class TB>
+static hipError_t dgemm(const TA* A, long long lda, const TB* B, long long ldb, const double* w,
+                        double* C, long long ldc, int M, int N, int K, double alpha, double beta,
+                        double diag, bool lower, hipStream_t s) {
+  if (M <= 0 || N <= 0) return hipSuccess;
+  GemmArgs<TA, TB> g;
+  g.A = A; g.lda = lda; g.B = B; g.ldb = ldb; g.w = w; g.C = C; g.ldc = ldc;
+  g.M = M; g.N = N; g.K = K; g.alpha = alpha; g.beta = beta; g.diag = diag;
+  g.lower = lower ? 1 : 0;
+  const int nt_m = (M + kDT - 1) / kDT;
+  g.nt_n = (N + kDT - 1) / kDT;
+  hipLaunchKernelGGL((k_dgemm_nt<TA, TB>), dim3(nt_m * g.nt_n), dim3(256), 0, s, g);
+  return hipGetLastError();
+}
+
+// Cholesky factor of the nb x nb diagonal block at (j0, j0) of S, in place
+// (lower triangle), unblocked in LDS (one workgroup); rows and columns past nb
+// act as the identity.  A non-positive pivot gives NaN, which the sweep then
+// reports as a non-finite state.
+__global__ __launch_bounds__(256) void k_chol_diag(double* S, long long lds, int j0, int nb) {
+  __shared__ double a[kDT][kDT + 1];
+  const int t = threadIdx.x;
+  for (int i = t; i < kDT * kDT; i += 256) {
+    const int r = i / kDT, c = i % kDT;
+    a[r][c] = (r < nb && c < nb) ? S[(long long)(j0 + r) * lds + j0 + c] : (r == c ? 1.0 : 0.0);
+  }
+  __syncthreads();
+  for (int c = 0; c < kDT; ++c) {
+    if (t == 0) a[c][c] = sqrt(a[c][c]);
+    __syncthreads();
+    if (t > c && t < kDT) a[t][c] /= a[c][c];
+    __syncthreads();
+    for (int i = t; i < kDT * kDT; i += 256) {
+      const int r = i / kDT, k = i % kDT;
+      if (k > c && k <= r) a[r][k] -= a[r][c] * a[k][c];
+    }
+    __syncthreads();
+  }
+  for (int i = t; i < kDT * kDT; i += 256) {
+    const int r = i / kDT, c = i % kDT;
+    if (r < nb && c <= r) S[(long long)(j0 + r) * lds + j0 + c] = a[r][c];
+  }
+}
+
+// Rows x of X (nrows x nb, leading dimension ldx) replaced by the solution of
+// x L^T = x_old, L the nb x nb lower-triangular block at L (leading dimension
+// ldl): forward substitution, one row per thread, L in LDS.
+__global__ __launch_bounds__(256) void k_trsm_rows(double* X, long long ldx, int nrows,
+                                                   const double* L, long long ldl, int nb) {
+  __shared__ double Ls[kDT][kDT + 1];
+  const int t = threadIdx.x;
+  for (int i = t; i < kDT * kDT; i += 256) {
+    const int r = i / kDT, c = i % kDT;
+    Ls[r][c] = (r < nb && c <= r) ? L[(long long)r * ldl + c] : (r == c ? 1.0 : 0.0);
+  }
+  __syncthreads();
+  const int row = blockIdx.x * 256 + t;
+  if (row >= nrows) return;
+  double* xr = X + (long long)row * ldx;
+  double x[kDT];
+#pragma unroll
+  for (int c = 0; c < kDT; ++c) x[c] = c < nb ? xr[c] : 0.0;
+#pragma unroll
+  for (int c = 0; c < kDT; ++c) {
+    double sum = x[c];
+#pragma unroll
+    for (int k = 0; k < c; ++k) sum -= x[k] * Ls[c][k];
+    x[c] = sum / Ls[c][c];
+  }
+#pragma unroll
+  for (int c = 0; c < kDT; ++c)
+    if (c < nb) xr[c] = x[c];
+}
+
+// 32 x 32 tiles through LDS: out (cols x rows) = in^T (rows x cols), float.
+__global__ __launch_bounds__(256) void k_transpose_f32(const float* __restrict__ in, float* __restrict__ out,
+                                                       int rows, int cols) {
+  __shared__ float tile[32][33];
+  const int bx = blockIdx.x * 32, by = blockIdx.y * 32;
+  const int tx = threadIdx.x % 32, ty = threadIdx.x / 32;   // 32 x 8
+  for (int j = ty; j < 32; j += 8) {
+    const int r = by + j, c = bx + tx;
+    if (r < rows && c < cols) tile[j][tx] = in[(long long)r * cols + c];
+  }
+  __syncthreads();
+  for (int j = ty; j < 32; j += 8) {
+    const int r = bx + j, c = by + tx;   // out row = in column
+    if (r < cols && c < rows) out[(long long)r * rows + c] = tile[tx][j];
+  }
+}
+
+__global__ __launch_bounds__(256) void k_f32_to_f64(const float* __restrict__ in, double* __restrict__ out,
+                                                    long long n) {
+  const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) out[i] = (double)in[i];
+}
+
+// Wave-level FP64 sum, the same bits on every lane (butterfly).
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = kWave / 2; off >= 1; off >>= 1) v += __shfl_xor(v, off, kWave);
+  return v;
+}
+
+// H^T y: one wave per pixel (row of H^T), FP64 sum; into the H^T y plane and
+// the pixel-space observation (both pitched).
+__global__ __launch_bounds__(256) void k_gauss_hty(const float* __restrict__ HT, const float* __restrict__ y,
+                                                   int M, int N, int W, int pitch, long long off,
+                                                   float* __restrict__ hty, float* __restrict__ ypix) {
+  const int row = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (row >= N) return;
+  const float* h = HT + (long long)row * M;
+  double acc = 0.0;
+  for (int a = lane; a < M; a += kWave) acc += (double)h[a] * (double)y[a];
+  acc = wave_sum(acc);
+  if (lane == 0) {
+    const long long p = off + (long long)(row / W) * pitch + row % W;
+    hty[p] = (float)acc;
+    ypix[p] = (float)acc;
+  }
+}
+
+// Cavity precisions and right-hand side from the pitched planes into flat
+// FP64 vectors; w = 1 / d.
+__global__ __launch_bounds__(256) void k_gauss_gather(const float* __restrict__ tauc,
+                                                      const float* __restrict__ bpl, int N, int W,
+                                                      int pitch, long long off, double* __restrict__ d,
+                                                      double* __restrict__ w, double* __restrict__ b) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= N) return;
+  const long long p = off + (long long)(i / W) * pitch + i % W;
+  const double dv = (double)tauc[p];
+  d[i] = dv;
+  w[i] = 1.0 / dv;
+  b[i] = (double)bpl[p];
+}
+
+// Partial sums of t = Z (b / d) = sum_i Z^T[i, :] b_i / d_i over chunks of
+// kGaussChunk rows: one thread per column a of one chunk.
+__global__ __launch_bounds__(256) void k_gauss_tpart(const double* __restrict__ ZT, const double* __restrict__ b,
+                                                     const double* __restrict__ w, int M, int N,
+                                                     double* __restrict__ tpart) {
+  const int a = blockIdx.x * 256 + threadIdx.x, chunk = blockIdx.y;
+  if (a >= M) return;
+  const int i0 = chunk * kGaussChunk, i1 = min(i0 + kGaussChunk, N);
+  double acc = 0.0;
+  for (int i = i0; i < i1; ++i) acc += ZT[(long long)i * M + a] * (b[i] * w[i]);
+  tpart[(long long)chunk * M + a] = acc;
+}
+
+__global__ __launch_bounds__(256) void k_gauss_tsum(const double* __restrict__ tpart, int M, int nchunk,
+                                                    double* __restrict__ t) {
+  const int a = blockIdx.x * 256 + threadIdx.x;
+  if (a >= M) return;
+  double acc = 0.0;
+  for (int c = 0; c < nchunk; ++c) acc += tpart[(long long)c * M + a];
+  t[a] = acc;
+}
+
+// Per pixel (one wave per row of Z^T): v_i = 1/d_i - |z_i|^2 / d_i^2 and
+// E_i = (b_i - z_i . t) / d_i, into the pitched variance and x planes.
+__global__ __launch_bounds__(256) void k_gauss_moments(const double* __restrict__ ZT, const double* __restrict__ t,
+                                                       const double* __restrict__ d, const double* __restrict__ b,
+                                                       int M, int N, int W, int pitch, long long off,
+                                                       float* __restrict__ var, float* __restrict__ x) {
+  const int row = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (row >= N) return;
+  const double* z = ZT + (long long)row * M;
+  double zz = 0.0, zt = 0.0;
+  for (int a = lane; a < M; a += kWave) {
+    const double v = z[a];
+    zz += v * v;
+    zt += v * t[a];
+  }
+  zz = wave_sum(zz);
+  zt = wave_sum(zt);
+  if (lane == 0) {
+    const double dv = d[row];
+    const long long p = off + (long long)(row / W) * pitch + row % W;
+    var[p] = (float)(1.0 / dv - zz / (dv * dv));
+    x[p] = (float)((b[row] - zt) / dv);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// host side
+
+hipError_t gauss_setup(LikCtx& lc, const LikInstInfo* li, int n, hipStream_t s, std::string& err) {
+  lc.gauss.clear();
+  char* cur = lc.gaussbuf;
+  auto take = [&](size_t bytes) {
+    char* at = cur;
+    cur += (bytes + 255) / 256 * 256;
+    return at;
+  };
+  for (int i = 0; i < n; ++i) {
+    if (li[i].op != OP_GAUSS) continue;
+    GaussPlan P;
+    for (int k = 0; k < (int)lc.hinst.size(); ++k)
+      if (lc.hinst[k].inst == i) P.li = k;
+    P.M = li[i].sense_rows;
+    P.N = li[i].H * li[i].W;
+    const size_t m = (size_t)P.M, nn = (size_t)P.N;
+    P.nchunk = (P.N + kGaussChunk - 1) / kGaussChunk;
+    P.Hm = reinterpret_cast<float*>(take(m * nn * 4));
+    P.HT = reinterpret_cast<float*>(take(m * nn * 4));
+    P.S = reinterpret_cast<double*>(take(m * m * 8));
+    P.ZT = reinterpret_cast<double*>(take(nn * m * 8));
+    P.d = reinterpret_cast<double*>(take(nn * 8));
+    P.w = reinterpret_cast<double*>(take(nn * 8));
+    P.b = reinterpret_cast<double*>(take(nn * 8));
+    P.t = reinterpret_cast<double*>(take(m * 8));
+    P.tpart = reinterpret_cast<double*>(take((size_t)P.nchunk * m * 8));
+    P.y = reinterpret_cast<float*>(take(m * 4));
+    hipError_t e = hipMemcpyAsync(P.Hm, li[i].sense, m * nn * 4, hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) {
+      err = "copy of the sensing matrix";
+      return e;
+    }
+    hipLaunchKernelGGL(k_transpose_f32, dim3((P.N + 31) / 32, (P.M + 31) / 32), dim3(256), 0, s, P.Hm,
+                       P.HT, P.M, P.N);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    lc.gauss.push_back(P);
+  }
+  // the host matrix may go out of scope when ep_tv_create returns
+  return lc.gauss.empty() ? hipSuccess : hipStreamSynchronize(s);
+}
+
+hipError_t gauss_set_observation(LikCtx& lc, const float* const* d_y, hipStream_t s) {
+  for (GaussPlan& P : lc.gauss) {
+    const LikInst& L = lc.hinst[P.li];
+    hipError_t e = hipMemcpyAsync(P.y, d_y[L.inst], sizeof(float) * P.M, hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_gauss_hty, dim3((P.N + 3) / 4), dim3(256), 0, s, P.HT, P.y, P.M, P.N, L.W,
+                       L.pitch, L.off, lc.planes[LP_HTY], lc.ypix);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t gauss_update(LikCtx& lc, const InstState* hst, hipStream_t s) {
+  hipError_t e;
+  for (GaussPlan& P : lc.gauss) {
+    const LikInst& L = lc.hinst[P.li];
+    const InstState& st = hst[L.inst];
+    if (!(st.active && (st.sweeps > 0 || st.warm))) continue;
+    const int M = P.M, N = P.N, nb = (M + kDT - 1) / kDT;
+    const double xi = 1.0 / (double)L.inv_xi;
+    hipLaunchKernelGGL(k_gauss_gather, dim3((N + 255) / 256), dim3(256), 0, s, lc.planes[LP_TAUC],
+                       lc.planes[LP_B], N, L.W, L.pitch, L.off, P.d, P.w, P.b);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    // S = xi I + H D^-1 H^T (lower triangle), then its Cholesky factor in place
+    e = lik_timed(lc, KT_DGEMM, s, [&]() {
+      return dgemm<float, float>(P.Hm, N, P.Hm, N, P.w, P.S, M, M, M, N, 1.0, 0.0, xi, true, s);
+    });
+    if (e != hipSuccess) return e;
+    lc.dgemm_flops += (double)M * (double)(M + kDT) * (double)N;
+    for (int j = 0; j < nb; ++j) {
+      const int j0 = j * kDT, bj = std::min(kDT, M - j0), rest = M - j0 - bj;
+      double* Ljj = P.S + (long long)j0 * M + j0;
+      hipLaunchKernelGGL(k_chol_diag, dim3(1), dim3(256), 0, s, P.S, (long long)M, j0, bj);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+      if (rest <= 0) break;
+      double* panel = P.S + (long long)(j0 + bj) * M + j0;
+      hipLaunchKernelGGL(k_trsm_rows, dim3((rest + 255) / 256), dim3(256), 0, s, panel, (long long)M, rest,
+                         (const double*)Ljj, (long long)M, bj);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+      double* trail = P.S + (long long)(j0 + bj) * M + (j0 + bj);
+      e = lik_timed(lc, KT_DGEMM, s, [&]() {
+        return dgemm<double, double>(panel, M, panel, M, nullptr, trail, M, rest, rest, bj, -1.0, 1.0, 0.0,
+                                     true, s);
+      });
+      if (e != hipSuccess) return e;
+      lc.dgemm_flops += (double)rest * (double)(rest + kDT) * (double)bj;
+    }
+    // Z^T = H^T L^-T by blocks of columns: Z^T[:, j] = (H^T[:, j] - Z^T[:, <j] L[j, <j]^T) L_jj^-T
+    hipLaunchKernelGGL(k_f32_to_f64, dim3((unsigned)(((long long)N * M + 255) / 256)), dim3(256), 0, s, P.HT,
+                       P.ZT, (long long)N * M);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    for (int j = 0; j < nb; ++j) {
+      const int j0 = j * kDT, bj = std::min(kDT, M - j0);
+      if (j0 > 0) {
+        e = lik_timed(lc, KT_DGEMM, s, [&]() {
+          return dgemm<double, double>(P.ZT, M, P.S + (long long)j0 * M, M, nullptr, P.ZT + j0, M, N, bj, j0,
+                                       -1.0, 1.0, 0.0, false, s);
+        });
+        if (e != hipSuccess) return e;
+        lc.dgemm_flops += 2.0 * (double)N * (double)bj * (double)j0;
+      }
+      hipLaunchKernelGGL(k_trsm_rows, dim3((N + 255) / 256), dim3(256), 0, s, P.ZT + j0, (long long)M, N,
+                         (const double*)(P.S + (long long)j0 * M + j0), (long long)M, bj);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    // t = Z (b / d), then v and E per pixel
+    hipLaunchKernelGGL(k_gauss_tpart, dim3((M + 255) / 256, P.nchunk), dim3(256), 0, s, P.ZT, P.b, P.w, M, N,
+                       P.tpart);
+    hipLaunchKernelGGL(k_gauss_tsum, dim3((M + 255) / 256), dim3(256), 0, s, P.tpart, M, P.nchunk, P.t);
+    hipLaunchKernelGGL(k_gauss_moments, dim3((N + 3) / 4), dim3(256), 0, s, P.ZT, P.t, P.d, P.b, M, N, L.W,
+                       L.pitch, L.off, lc.planes[LP_VAR], lc.planes[LP_X]);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+}  // namespace eptv

@@ -23,7 +23,7 @@ constexpr int kWavesPerBlock = 4;
 constexpr float kPrecFloor = 1e-8f;       // clamp: site variance < 0 or > 1e8 -> 1e8
 constexpr float kSiteInitPrec = 1e-8f;    // initial TV-site variance 1e8
 
-enum { OP_IDENTITY = 0, OP_BLUR = 1, OP_DFT = 2, OP_HAD = 3 };
+enum { OP_IDENTITY = 0, OP_BLUR = 1, OP_DFT = 2, OP_HAD = 3, OP_GAUSS = 4 };
 enum { BND_FREE = 0, BND_PERIODIC = 1 };
 
 struct InstDev {

@@ -41,6 +41,8 @@ struct LikInstInfo {
   int cg_max_iters = kCgMaxIters;
   int precond_req = PRECOND_REQ_AUTO;
   int rbmc_ns = 0;           // RBMC samples of the variance estimator (0: spectral)
+  const float* sense = nullptr;   // Gaussian CS: host M x N sensing matrix
+  int sense_rows = 0;
   const float* taps = nullptr;
   int th = 0, tw = 0;
   const uint8_t* mask = nullptr;
@@ -71,7 +73,9 @@ struct LikInst {
 
 enum {
   LP_HTY = 0, LP_TAUC, LP_ETAC, LP_B, LP_X, LP_R, LP_Z, LP_P0, LP_P1, LP_Q, LP_SPEC, LP_XPREV,
-  LP_ACC, LP_ESAVE, LP_COUNT   // RBMC: sum of squared off-diagonal terms, the mean solve's E
+  LP_ACC, LP_ESAVE,            // RBMC: sum of squared off-diagonal terms, the mean solve's E
+  LP_VAR,                      // Gaussian CS: the Woodbury variances
+  LP_COUNT
 };
 
 enum { PRECOND_JACOBI = 0, PRECOND_CIRCULANT = 1 };
@@ -99,7 +103,19 @@ struct LikLayout {
   int nlik = 0, ntiles = 0, ntaps = 0;
   size_t fft_bytes = 0;
   size_t wht = 0, wht_bytes = 0;
+  size_t gauss = 0, gauss_bytes = 0;
 };
+
+// Bytes of the dense buffers of a Gaussian-CS instance (M sensing rows, N
+// pixels), each rounded up to 256 bytes: H and H^T (float), S and Z^T (double),
+// the vectors d, 1/d, b (N), t (M), the partial sums of t and the observation.
+constexpr int kGaussChunk = 256;   // rows per partial sum of t = Z (b / d)
+inline size_t gauss_bytes_of(int M, int N) {
+  auto r = [](size_t b) { return (b + 255) / 256 * 256; };
+  const size_t m = (size_t)M, nn = (size_t)N, nchunk = (nn + kGaussChunk - 1) / kGaussChunk;
+  return 2 * r(m * nn * 4) + r(m * m * 8) + r(nn * m * 8) + 3 * r(nn * 8) + r(m * 8) +
+         r(nchunk * m * 8) + r(m * 4);
+}
 
 // Number of likelihood tiles and taps floats for the layout.
 inline void lik_counts(const LikInstInfo* li, int n, int& nlik, int& ntiles, int& ntaps,
@@ -119,9 +135,12 @@ void lik_layout(const LikInstInfo* li, int n, long long plane, Take&& take, LikL
   long long fft_elems = 0;
   lik_counts(li, n, L.nlik, L.ntiles, L.ntaps, fft_elems);
   L.rbmc_ns_max = 0;
-  for (int i = 0; i < n; ++i)
+  bool any_gauss = false;
+  for (int i = 0; i < n; ++i) {
     if (li[i].op != OP_IDENTITY) L.rbmc_ns_max = std::max(L.rbmc_ns_max, li[i].rbmc_ns);
-  L.nplanes = L.nlik ? (L.rbmc_ns_max ? LP_COUNT : LP_ACC) : 0;
+    any_gauss = any_gauss || li[i].op == OP_GAUSS;
+  }
+  L.nplanes = L.nlik ? ((L.rbmc_ns_max || any_gauss) ? LP_COUNT : LP_ACC) : 0;
   for (int k = 0; k < L.nplanes; ++k) L.planes[k] = take(sizeof(float) * (size_t)plane);
   if (L.rbmc_ns_max) {
     L.rbmc_g = take(sizeof(float) * (size_t)plane * L.rbmc_ns_max);
@@ -154,6 +173,11 @@ void lik_layout(const LikInstInfo* li, int n, long long plane, Take&& take, LikL
     L.wht_bytes += 2 * ((N * sizeof(float) + 255) / 256 * 256);
   }
   L.wht = take(std::max<size_t>(L.wht_bytes, 256));
+  // Gaussian-CS instances: H, H^T, S, Z^T and the vectors of the Woodbury moments
+  L.gauss_bytes = 0;
+  for (int i = 0; i < n; ++i)
+    if (li[i].op == OP_GAUSS) L.gauss_bytes += gauss_bytes_of(li[i].sense_rows, li[i].H * li[i].W);
+  L.gauss = take(std::max<size_t>(L.gauss_bytes, 256));
 }
 
 // FFT work buffers of one instance that uses the FFT (masked DFT operator,
@@ -177,10 +201,30 @@ struct WhtPlan {
   float* eig = nullptr;      // N floats: the mask in natural order
 };
 
+// Device buffers of one Gaussian-CS instance (all in the workspace).
+struct GaussPlan {
+  int li = 0;                  // index into LikCtx::hinst
+  int M = 0, N = 0;            // sensing rows, pixels
+  float* Hm = nullptr;         // M x N, row-major (as given)
+  float* HT = nullptr;         // N x M, its transpose
+  double* S = nullptr;         // M x M (lower triangle used), then its Cholesky factor
+  double* ZT = nullptr;        // N x M
+  double* d = nullptr;         // N: cavity precisions (flat, row-major pixels)
+  double* w = nullptr;         // N: 1 / d
+  double* b = nullptr;         // N: right-hand side
+  double* t = nullptr;         // M
+  double* tpart = nullptr;     // nchunk x M partial sums of t
+  float* y = nullptr;          // M: the observation
+  int nchunk = 0;
+};
+
 struct LikCtx {
   int nlik = 0, ntiles = 0;
   std::vector<DftPlan> dft;
   std::vector<WhtPlan> wht;
+  std::vector<GaussPlan> gauss;
+  char* gaussbuf = nullptr;
+  double dgemm_flops = 0.0;          // flops of the FP64 GEMMs launched while timing
   float* whtbuf = nullptr;
   std::vector<LikInst> hinst;
   std::vector<int> inst_of;          // lik index -> instance index
@@ -218,8 +262,10 @@ struct LikCtx {
 // whole preconditioner with its x, r update); the others bracket single
 // launches: the three real-transform passes, the per-instance finishing
 // kernels, and everything else (cavity / right-hand side, spectral sum, CG
-// start, Jacobi kernels, site update).
-enum { KT_APPLY = 0, KT_PRECOND, KT_RF_FWD, KT_RF_FILT, KT_RF_INV, KT_FIN, KT_OTHER, KT_COUNT };
+// start, Jacobi kernels, site update); KT_DGEMM brackets every FP64 GEMM of the
+// Gaussian-CS Woodbury moments.
+enum { KT_APPLY = 0, KT_PRECOND, KT_RF_FWD, KT_RF_FILT, KT_RF_INV, KT_FIN, KT_OTHER, KT_DGEMM,
+       KT_COUNT };
 static_assert(KT_COUNT <= 9, "timing buckets");
 constexpr size_t kMaxTimingEvents = 1u << 17;
 

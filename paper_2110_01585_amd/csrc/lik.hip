@@ -23,6 +23,7 @@
 #include <cmath>
 #include <cstring>
 
+#include "dense.h"
 #include "fft.h"
 #include "lik.h"
 #include "wht.h"
@@ -51,6 +52,7 @@ struct LikArgs {
   float* acc; float* esave;
   const float* g_s; const float* e2_s; float* xs_s;
   int sample;
+  float* var;                // Gaussian CS: the Woodbury variances
 };
 
 // The likelihood site is updated in this sweep (every sweep but the first of a
@@ -233,7 +235,7 @@ __global__ __launch_bounds__(256) void k_lik_fin(LikArgs A, int stage) {
       st.dbar = r0 / N;
       st.cg_bb = r1;
       st.cg_it = 0;
-      st.cg_done = 0;
+      st.cg_done = L.op == OP_GAUSS ? 1 : 0;   // the dense Woodbury path replaces the CG
       st.xprev_valid = st.x_valid;   // prep has just kept the last solve's E
       st.x_valid = 1;
       break;
@@ -672,6 +674,28 @@ __global__ __launch_bounds__(256) void k_lik_site(LikArgs A, float2* __restrict_
   }
   const TileXY t = lik_tile(td, L);
   const float a = L.alpha;
+  if (L.op == OP_GAUSS) {
+    // Woodbury variances and mean from the dense path
+    float tcv[kTileItems], ev[kTileItems], ecv[kTileItems], vv[kTileItems];
+    float2 ov[kTileItems];
+    float mx = 0.f;
+    tile_two_phase<true>(
+        t, L,
+        [&](int u, long long p) {
+          tcv[u] = A.tauc[p]; ev[u] = A.x[p]; ecv[u] = A.etac[p]; vv[u] = A.var[p]; ov[u] = S0[p];
+        },
+        [&](int u, long long p) {
+          double tn = 1.0 / (double)vv[u] - (double)tcv[u];
+          if (!(tn >= (double)kPrecFloor)) tn = (double)kPrecFloor;
+          const float tau_new = (float)tn;
+          const float eta_new = (float)((tn + (double)tcv[u]) * (double)ev[u] - (double)ecv[u]);
+          const float2 s0 = make_float2(a * tau_new + (1.f - a) * ov[u].x, a * eta_new + (1.f - a) * ov[u].y);
+          S0[p] = s0;
+          mx = fmaxf(mx, fabsf((s0.y + ecv[u]) / (s0.x + tcv[u])));
+        });
+    block_max(mx, &A.part_mu[tile]);
+    return;
+  }
   if (L.rbmc_ns) {
     // RBMC: per-pixel tilted variance V = 1/Q_ii + acc / (Ns Q_ii^2), Q_ii = diag
     // (H^T H)/xi + tau_c; E is the mean solve's, restored into x for the next
@@ -891,6 +915,7 @@ static LikArgs make_args(LikCtx& lc) {
   A.xprev = lc.planes[LP_XPREV];
   A.acc = lc.planes[LP_ACC];
   A.esave = lc.planes[LP_ESAVE];
+  A.var = lc.planes[LP_VAR];
   A.sample = lc.sample;
   const size_t off = (size_t)lc.plane * (size_t)lc.sample;
   A.g_s = lc.rbmc_g ? lc.rbmc_g + off : nullptr;
@@ -947,7 +972,7 @@ hipError_t lik_create(LikCtx& lc, const LikInstInfo* li, int n, char* ws, const 
     d.cg_tol2 = I.cg_tol * I.cg_tol;
     d.cg_reduce2 = I.cg_reduce * I.cg_reduce;
     d.cg_max_iters = I.cg_max_iters;
-    d.precond = lik_precond(I.op, I.H, I.W, I.precond_req);
+    d.precond = I.op == OP_GAUSS ? PRECOND_JACOBI : lik_precond(I.op, I.H, I.W, I.precond_req);
     d.npart = (d.precond == PRECOND_CIRCULANT && I.op != OP_HAD) ? rfft_partials(I.H, I.W) : d.ntiles;
     if (d.npart > d.ntiles) return hipErrorInvalidValue;   // partial slots are per tile
     lc.max_iters = std::max(lc.max_iters, I.cg_max_iters);
@@ -1009,7 +1034,8 @@ hipError_t lik_create(LikCtx& lc, const LikInstInfo* li, int n, char* ws, const 
   }
   lc.fast = !lc.hinst.empty();
   for (const LikInst& d : lc.hinst) {
-    lc.fast = lc.fast && d.precond == PRECOND_CIRCULANT && d.op != OP_HAD && d.npart <= d.ntiles;
+    lc.fast = lc.fast && d.precond == PRECOND_CIRCULANT && d.op != OP_HAD && d.op != OP_GAUSS &&
+              d.npart <= d.ntiles;
   }
   // partial counts per finalisation stage: r.z / r.r (and p.q of masked-DFT
   // instances) come from the real-transform passes in the fast CG, everything
@@ -1044,6 +1070,8 @@ hipError_t lik_create(LikCtx& lc, const LikInstInfo* li, int n, char* ws, const 
   e = hipGetLastError();
   if (e == hipSuccess) e = dft_setup(lc, li, n, L.fft_bytes, s, err);
   if (e == hipSuccess) e = wht_setup(lc, li, n, L.wht_bytes, s, err);
+  lc.gaussbuf = ws + L.gauss;
+  if (e == hipSuccess) e = gauss_setup(lc, li, n, s, err);
   if (e != hipSuccess && err.empty()) err = hipGetErrorString(e);
   return e;
 }
@@ -1055,6 +1083,7 @@ hipError_t lik_set_observation(LikCtx& lc, const float* const* d_y, hipStream_t 
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if ((e = dft_set_observation(lc, d_y, s)) != hipSuccess) return e;
+  if ((e = gauss_set_observation(lc, d_y, s)) != hipSuccess) return e;
   return wht_set_observation(lc, d_y, s);
 }
 
@@ -1309,6 +1338,8 @@ hipError_t lik_update(LikCtx& lc, float2* const S[5], hipStream_t s) {
   if (e != hipSuccess) return e;
   if ((e = iterate_to_done(lc, s)) != hipSuccess) return e;
   if (lc.rbmc_ns_max && (e = rbmc_samples(lc, s)) != hipSuccess) return e;
+  // the host state was pulled by the last CG poll, after this sweep's preparation
+  if (!lc.gauss.empty() && (e = gauss_update(lc, lc.hst, s)) != hipSuccess) return e;
   return lik_tail(lc, S[0], s);
 }
 
@@ -1325,6 +1356,7 @@ void lik_timing(LikCtx& lc, bool enable, bool clear) {
   if (clear) {
     lc.ev_used = 0;
     for (auto& b : lc.ev_k) b.clear();
+    lc.dgemm_flops = 0.0;
   }
 }
 
