@@ -27,6 +27,10 @@ Workloads (synthetic, seeded; generators in synthetic.py):
               coefficients, sigma = 0.01, EM from lambda = 1 (hcs128: 128^2)
   batch256    256 instances, square sizes log-uniform in [64, 1024], 50/50 denoising /
               deconvolution, per-instance EM; Jacobi CG (about 40M pixels)
+  gcs128      128^2 compressive sensing with a Gaussian i.i.d. sensing matrix, M / N = 0.3,
+              sigma = 0.01, EM (the paper's CS setting): Woodbury moments in FP64 on the
+              matrix cores (roofline against the FP64 MFMA peak)
+  rbmc512     512^2 deconvolution with the RBMC variance estimator (8 samples)
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
 """
@@ -44,6 +48,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+FP64_MFMA_PEAK_TFLOPS = 78.6
 # algorithmic bytes per pixel and launch (float32): what the kernel must read
 # and write at least once
 BYTES_PER_PX = {
@@ -107,6 +112,18 @@ def kernel_rooflines(tm, npx, workload, op):
         if tm[f"{k}_launches"] > 0:
             cand[k] = (tm[f"{k}_ms"], tm[f"{k}_launches"])
     entries = {k: roofline_entry(k, npx, ms, n, workload) for k, (ms, n) in cand.items() if n > 0}
+    if tm.get("dgemm_launches", 0) > 0:
+        # the FP64 GEMMs of the Woodbury moments, against the FP64 matrix-core peak
+        t_s = tm["dgemm_ms"] / 1e3
+        ach = tm["dgemm_flops"] / t_s / 1e12
+        entries["dgemm_f64"] = {"bound": "mfma", "achieved": round(ach, 2),
+                                "peak": FP64_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
+                                "frac": round(ach / FP64_MFMA_PEAK_TFLOPS, 4), "traffic": None,
+                                "kernel": "dgemm_f64",
+                                "symbol": "eptv::k_dgemm_nt (v_mfma_f64_16x16x4f64)",
+                                "flops": tm["dgemm_flops"], "launches": tm["dgemm_launches"],
+                                "avg_launch_us": round(tm["dgemm_ms"] * 1e3 / tm["dgemm_launches"], 2),
+                                "total_ms": round(tm["dgemm_ms"], 3)}
     dominant = max(entries, key=lambda k: entries[k]["total_ms"])
     return entries[dominant], entries
 
@@ -136,6 +153,13 @@ def make_workload(name):
         rng = syn.rng_for(5, 0)
         return syn.make_denoise(4096, 4096, 960, 0.1, rng, mode="paint", lam0=1.0, sweeps=50,
                                 em=True, name="denoise4096"), True
+    if name == "gcs128":
+        return syn.make_gauss_cs(128, 128, 12, 0.01, 0.3, syn.rng_for(7, 0), lam0=1.0, sweeps=100,
+                                 em=True, name="gcs128"), True
+    if name == "rbmc512":
+        p = syn.config1(size=512, sweeps=200)
+        p.name = "rbmc512"
+        return p, True
     if name in ("hcs2048", "hcs128"):
         size = 2048 if name == "hcs2048" else 128
         n = max(3, round(150 * size * size / 1024 ** 2))
@@ -264,10 +288,21 @@ def cpu_baseline_sample(name, size, sweeps):
     elif name.startswith("hcs"):
         p, em = syn.make_hadamard_cs(size, size, max(3, round(150 * size * size / 1024 ** 2)), 0.01,
                                      0.3, syn.rng_for(6, 1), lam0=1.0, sweeps=1, em=True), True
+    elif name == "gcs128":
+        size = min(size, 64)
+        p, em = syn.make_gauss_cs(size, size, 3, 0.01, 0.3, syn.rng_for(7, 1), lam0=1.0), True
+    elif name == "rbmc512":
+        size = min(size, 128)
+        p, em = syn.config1(size=size, sweeps=1), True
     else:
         p, em = syn.config0(), False
+    rbmc = None
+    if name == "rbmc512":
+        import numpy as np
+        rng = np.random.default_rng(1)
+        rbmc = (rng.standard_normal((RBMC_SAMPLES,) + p.shape), rng.standard_normal((RBMC_SAMPLES,) + p.shape))
     with threadpool_limits(limits=1):
-        pb = oep.problem_from_synthetic(p)
+        pb = oep.problem_from_synthetic(p, estimator="rbmc" if rbmc else "spectral", rbmc_noise=rbmc)
         t0 = time.perf_counter()
         oep.solve(pb, sweeps, em)
         dt = time.perf_counter() - t0
@@ -320,15 +355,27 @@ def main():
     return bench_sweeps(args, p, em)
 
 
+RBMC_SAMPLES = 8
+
+
 def _ctx(p, dev, graph, **kw):
     import numpy as np
     import torch
     from paper_2110_01585_amd import Context, spec_from_synthetic
     from paper_2110_01585_amd import _native as N
+    rbmc = p.name == "rbmc512"
+    if rbmc:
+        kw["rbmc_samples"] = RBMC_SAMPLES
     ctx = Context([spec_from_synthetic(p, **kw)], device=dev)
     yh = np.stack([p.y.real, p.y.imag], -1) if p.op == "dft" else p.y
     y = torch.tensor(yh, dtype=torch.float32, device=dev).contiguous()
     ctx.ep_tv_set_observation([y])
+    if rbmc:
+        # the estimator's white noise (e1 in pixel space for the blur, then e2), seeded
+        h, w = p.shape
+        g = torch.Generator(device="cpu").manual_seed(12345)
+        noise = torch.randn(RBMC_SAMPLES * 2 * h * w, generator=g).to(dev)
+        ctx.ep_tv_set_rbmc_noise([noise])
     ctx.ep_tv_set_option(N.OPT_GRAPH, 1 if graph else 0)
     return ctx, y
 
@@ -552,7 +599,7 @@ def bench_sweeps(args, p, em):
     ctx.ep_tv_run(max(args.warmup, 2), em)
     tune = ctx.ep_tv_autotune(5)
     print(f"[bench] autotune: {tune}", file=sys.stderr, flush=True)
-    cold_phase = args.cold_phase if p.op == "hadamard" else 0
+    cold_phase = args.cold_phase if p.op == "hadamard" else (20 if p.name == "rbmc512" else 0)
 
     def prime():
         ctx.ep_tv_init_cold()

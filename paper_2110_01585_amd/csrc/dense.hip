@@ -12,8 +12,8 @@ namespace eptv {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 
-constexpr int kDT = 64;   // GEMM output tile and Cholesky block size
-constexpr int kDK = 16;   // K depth staged in LDS per round
+constexpr int kDT = 64;   // Cholesky block size (and the small GEMM tile)
+constexpr int kDK = 32;   // K depth staged in LDS per GEMM round
 
 // C = beta C + alpha A diag(w) B^T (+ diag on the main diagonal): A is M x K
 // and B is N x K, both with k contiguous; w (length K) may be null.  With
@@ -21,7 +21,10 @@ constexpr int kDK = 16;   // K depth staged in LDS per round
 // skipped).  One 64 x 64 output tile per workgroup, 4 waves of 32 x 32, each
 // as 2 x 2 blocks of 16 x 16 MFMA outputs.  MFMA operand layout (16x16x4
 // f64): lane l holds A[l % 16][l / 16] and B[l / 16][l % 16] (k = l / 16); the
-// result element (4 r + l / 16, l % 16) is register r of lane l.
+// result element (4 r + l / 16, l % 16) is register r of lane l.  The next K
+// round's operands are loaded into registers while the current one is
+// multiplied.  A workgroup reads all of A's rows of its tile before it writes
+// C, so C may alias A when the output has a single tile column (N <= 64).
 template <class TA, class TB>
 struct GemmArgs {
   const TA* A;
@@ -39,59 +42,77 @@ struct GemmArgs {
 
 template <class TA, class TB>
 __global__ __launch_bounds__(256) void k_dgemm_nt(GemmArgs<TA, TB> g) {
-  __shared__ double As[kDT][kDK + 1];
-  __shared__ double Bs[kDT][kDK + 1];
+  constexpr int BT = kDT, KD = kDK;
+  constexpr int NB = 2;                       // 16 x 16 MFMA blocks per wave and direction
+  __shared__ double As[BT][KD + 1];
+  __shared__ double Bs[BT][KD + 1];
   const int tm = blockIdx.x / g.nt_n, tn = blockIdx.x % g.nt_n;
-  const int m0 = tm * kDT, n0 = tn * kDT;
-  if (g.lower && n0 > m0 + kDT - 1) return;   // whole tile above the diagonal
+  const int m0 = tm * BT, n0 = tn * BT;
+  if (g.lower && n0 > m0 + BT - 1) return;    // whole tile above the diagonal
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
-  d4 acc00 = {0, 0, 0, 0}, acc01 = acc00, acc10 = acc00, acc11 = acc00;
-  const int lr = t >> 2, lk = (t & 3) * 4;   // staging: row lr, k lk..lk+3
-  const int am = m0 + lr, bn = n0 + lr;
-  for (int k0 = 0; k0 < g.K; k0 += kDK) {
-    double av[4], bv[4];
+  const int wm = (wave >> 1) * (BT / 2), wn = (wave & 1) * (BT / 2);
+  d4 acc[NB][NB];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
+  for (int i = 0; i < NB; ++i)
+#pragma unroll
+    for (int j = 0; j < NB; ++j) acc[i][j] = d4{0, 0, 0, 0};
+  constexpr int kPer = BT * KD / 256;         // staged elements per thread and operand
+  constexpr int kTpr = KD / kPer;             // threads per staged row
+  const int lr = t / kTpr, lk = (t % kTpr) * kPer;
+  const int am = m0 + lr, bn = n0 + lr;
+  const TA* arow = g.A + (long long)am * g.lda;
+  const TB* brow = g.B + (long long)bn * g.ldb;
+  double av[kPer], bv[kPer];
+  auto fetch = [&](int k0) {
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
       const int k = k0 + lk + u;
       const bool kin = k < g.K;
-      av[u] = (am < g.M && kin) ? (double)g.A[(long long)am * g.lda + k] : 0.0;
-      bv[u] = (bn < g.N && kin) ? (double)g.B[(long long)bn * g.ldb + k] * (g.w ? g.w[k] : 1.0) : 0.0;
+      av[u] = (am < g.M && kin) ? (double)arow[k] : 0.0;
+      bv[u] = (bn < g.N && kin) ? (double)brow[k] * (g.w ? g.w[k] : 1.0) : 0.0;
     }
+  };
+  fetch(0);
+  for (int k0 = 0; k0 < g.K; k0 += KD) {
     __syncthreads();   // the previous round's LDS reads are done
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
+    for (int u = 0; u < kPer; ++u) {
       As[lr][lk + u] = av[u];
       Bs[lr][lk + u] = bv[u];
     }
     __syncthreads();
+    if (k0 + KD < g.K) fetch(k0 + KD);
 #pragma unroll
-    for (int kk = 0; kk < kDK; kk += 4) {
+    for (int kk = 0; kk < KD; kk += 4) {
       const int r = lane & 15, c = kk + (lane >> 4);
-      const double a0 = As[wm + r][c], a1 = As[wm + 16 + r][c];
-      const double b0 = Bs[wn + r][c], b1 = Bs[wn + 16 + r][c];
-      acc00 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc00, 0, 0, 0);
-      acc01 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc01, 0, 0, 0);
-      acc10 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc10, 0, 0, 0);
-      acc11 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc11, 0, 0, 0);
-    }
-  }
-  const d4* accs[4] = {&acc00, &acc01, &acc10, &acc11};
+      double a[NB], b[NB];
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int bi = q >> 1, bj = q & 1;
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int m = m0 + wm + 16 * bi + 4 * r + (lane >> 4);
-      const int n = n0 + wn + 16 * bj + (lane & 15);
-      if (m < g.M && n < g.N && (!g.lower || n <= m)) {
-        double v = g.alpha * (*accs[q])[r];
-        if (g.beta != 0.0) v += g.beta * g.C[(long long)m * g.ldc + n];
-        if (m == n) v += g.diag;
-        g.C[(long long)m * g.ldc + n] = v;
+      for (int i = 0; i < NB; ++i) {
+        a[i] = As[wm + 16 * i + r][c];
+        b[i] = Bs[wn + 16 * i + r][c];
       }
+#pragma unroll
+      for (int i = 0; i < NB; ++i)
+#pragma unroll
+        for (int j = 0; j < NB; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
     }
   }
+  __syncthreads();   // every wave's reads of A are done before C (which may alias A) is written
+#pragma unroll
+  for (int bi = 0; bi < NB; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < NB; ++bj)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int m = m0 + wm + 16 * bi + 4 * r + (lane >> 4);
+        const int n = n0 + wn + 16 * bj + (lane & 15);
+        if (m < g.M && n < g.N && (!g.lower || n <= m)) {
+          double v = g.alpha * acc[bi][bj][r];
+          if (g.beta != 0.0) v += g.beta * g.C[(long long)m * g.ldc + n];
+          if (m == n) v += g.diag;
+          g.C[(long long)m * g.ldc + n] = v;
+        }
+      }
 }
 
 template <class TA, class TB>
@@ -111,10 +132,13 @@ static hipError_t dgemm(const TA* A, long long lda, const TB* B, long long ldb, 
 
 // Cholesky factor of the nb x nb diagonal block at (j0, j0) of S, in place
 // (lower triangle), unblocked in LDS (one workgroup); rows and columns past nb
-// act as the identity.  A non-positive pivot gives NaN, which the sweep then
-// reports as a non-finite state.
-__global__ __launch_bounds__(256) void k_chol_diag(double* S, long long lds, int j0, int nb) {
+// act as the identity.  Also writes the inverse of the factor (64 x 64, lower
+// triangular, row-major) to Linv, so that the triangular solves with the block
+// become GEMMs.  A non-positive pivot gives NaN, which the sweep then reports as
+// a non-finite state.
+__global__ __launch_bounds__(256) void k_chol_diag(double* S, long long lds, int j0, int nb, double* Linv) {
   __shared__ double a[kDT][kDT + 1];
+  __shared__ double inv[kDT][kDT + 1];
   const int t = threadIdx.x;
   for (int i = t; i < kDT * kDT; i += 256) {
     const int r = i / kDT, c = i % kDT;
@@ -132,40 +156,27 @@ __global__ __launch_bounds__(256) void k_chol_diag(double* S, long long lds, int
     }
     __syncthreads();
   }
+  // column c of L^-1 by forward substitution, one column per thread
+  if (t < kDT) {
+    const int c = t;
+    for (int r = 0; r < kDT; ++r) {
+      double v;
+      if (r < c) {
+        v = 0.0;
+      } else {
+        double sum = r == c ? 1.0 : 0.0;
+        for (int k = c; k < r; ++k) sum -= a[r][k] * inv[k][c];
+        v = sum / a[r][r];
+      }
+      inv[r][c] = v;
+    }
+  }
+  __syncthreads();
   for (int i = t; i < kDT * kDT; i += 256) {
     const int r = i / kDT, c = i % kDT;
     if (r < nb && c <= r) S[(long long)(j0 + r) * lds + j0 + c] = a[r][c];
+    Linv[i] = inv[r][c];
   }
-}
-
-// Rows x of X (nrows x nb, leading dimension ldx) replaced by the solution of
-// x L^T = x_old, L the nb x nb lower-triangular block at L (leading dimension
-// ldl): forward substitution, one row per thread, L in LDS.
-__global__ __launch_bounds__(256) void k_trsm_rows(double* X, long long ldx, int nrows,
-                                                   const double* L, long long ldl, int nb) {
-  __shared__ double Ls[kDT][kDT + 1];
-  const int t = threadIdx.x;
-  for (int i = t; i < kDT * kDT; i += 256) {
-    const int r = i / kDT, c = i % kDT;
-    Ls[r][c] = (r < nb && c <= r) ? L[(long long)r * ldl + c] : (r == c ? 1.0 : 0.0);
-  }
-  __syncthreads();
-  const int row = blockIdx.x * 256 + t;
-  if (row >= nrows) return;
-  double* xr = X + (long long)row * ldx;
-  double x[kDT];
-#pragma unroll
-  for (int c = 0; c < kDT; ++c) x[c] = c < nb ? xr[c] : 0.0;
-#pragma unroll
-  for (int c = 0; c < kDT; ++c) {
-    double sum = x[c];
-#pragma unroll
-    for (int k = 0; k < c; ++k) sum -= x[k] * Ls[c][k];
-    x[c] = sum / Ls[c][c];
-  }
-#pragma unroll
-  for (int c = 0; c < kDT; ++c)
-    if (c < nb) xr[c] = x[c];
 }
 
 // 32 x 32 tiles through LDS: out (cols x rows) = in^T (rows x cols), float.
@@ -307,6 +318,7 @@ hipError_t gauss_setup(LikCtx& lc, const LikInstInfo* li, int n, hipStream_t s, 
     P.b = reinterpret_cast<double*>(take(nn * 8));
     P.t = reinterpret_cast<double*>(take(m * 8));
     P.tpart = reinterpret_cast<double*>(take((size_t)P.nchunk * m * 8));
+    P.Linv = reinterpret_cast<double*>(take((m + 63) / 64 * 64 * 64 * 8));
     P.y = reinterpret_cast<float*>(take(m * 4));
     hipError_t e = hipMemcpyAsync(P.Hm, li[i].sense, m * nn * 4, hipMemcpyHostToDevice, s);
     if (e != hipSuccess) {
@@ -334,6 +346,37 @@ hipError_t gauss_set_observation(LikCtx& lc, const float* const* d_y, hipStream_
   return hipSuccess;
 }
 
+// Z^T[:, blocks lo..hi) L[lo..hi, lo..hi)^T = R in place (R: the current
+// contents of those columns, already reduced by the columns before lo):
+// split at the middle block, solve the left half, subtract its contribution
+// from the right half (one GEMM over all rows), solve the right half; a single
+// block is one GEMM with the inverse of its diagonal Cholesky block.
+static hipError_t trsm_right(LikCtx& lc, GaussPlan& P, int lo, int hi, hipStream_t s) {
+  const int M = P.M, N = P.N;
+  const int c_lo = lo * kDT, c_hi = std::min(M, hi * kDT);
+  if (hi - lo == 1) {
+    const int bj = c_hi - c_lo;
+    const double* Linv = P.Linv + (long long)lo * kDT * kDT;
+    hipError_t e = lik_timed(lc, KT_DGEMM, s, [&]() {
+      return dgemm<double, double>(P.ZT + c_lo, M, Linv, kDT, nullptr, P.ZT + c_lo, M, N, bj, bj, 1.0, 0.0,
+                                   0.0, false, s);
+    });
+    lc.dgemm_flops += 2.0 * (double)N * (double)bj * (double)bj;
+    return e;
+  }
+  const int mid = (lo + hi) / 2, c_mid = mid * kDT;
+  hipError_t e = trsm_right(lc, P, lo, mid, s);
+  if (e != hipSuccess) return e;
+  // Z^T[:, mid..hi) -= Z^T[:, lo..mid) L[mid..hi, lo..mid)^T
+  e = lik_timed(lc, KT_DGEMM, s, [&]() {
+    return dgemm<double, double>(P.ZT + c_lo, M, P.S + (long long)c_mid * M + c_lo, M, nullptr, P.ZT + c_mid, M,
+                                 N, c_hi - c_mid, c_mid - c_lo, -1.0, 1.0, 0.0, false, s);
+  });
+  if (e != hipSuccess) return e;
+  lc.dgemm_flops += 2.0 * (double)N * (double)(c_hi - c_mid) * (double)(c_mid - c_lo);
+  return trsm_right(lc, P, mid, hi, s);
+}
+
 hipError_t gauss_update(LikCtx& lc, const InstState* hst, hipStream_t s) {
   hipError_t e;
   for (GaussPlan& P : lc.gauss) {
@@ -353,14 +396,18 @@ hipError_t gauss_update(LikCtx& lc, const InstState* hst, hipStream_t s) {
     lc.dgemm_flops += (double)M * (double)(M + kDT) * (double)N;
     for (int j = 0; j < nb; ++j) {
       const int j0 = j * kDT, bj = std::min(kDT, M - j0), rest = M - j0 - bj;
-      double* Ljj = P.S + (long long)j0 * M + j0;
-      hipLaunchKernelGGL(k_chol_diag, dim3(1), dim3(256), 0, s, P.S, (long long)M, j0, bj);
+      double* Linv = P.Linv + (long long)j * kDT * kDT;
+      hipLaunchKernelGGL(k_chol_diag, dim3(1), dim3(256), 0, s, P.S, (long long)M, j0, bj, Linv);
       if ((e = hipGetLastError()) != hipSuccess) return e;
       if (rest <= 0) break;
+      // panel L_ij = S_ij L_jj^-T, in place
       double* panel = P.S + (long long)(j0 + bj) * M + j0;
-      hipLaunchKernelGGL(k_trsm_rows, dim3((rest + 255) / 256), dim3(256), 0, s, panel, (long long)M, rest,
-                         (const double*)Ljj, (long long)M, bj);
-      if ((e = hipGetLastError()) != hipSuccess) return e;
+      e = lik_timed(lc, KT_DGEMM, s, [&]() {
+        return dgemm<double, double>(panel, M, Linv, kDT, nullptr, panel, M, rest, bj, bj, 1.0, 0.0, 0.0,
+                                     false, s);
+      });
+      if (e != hipSuccess) return e;
+      lc.dgemm_flops += 2.0 * (double)rest * (double)bj * (double)bj;
       double* trail = P.S + (long long)(j0 + bj) * M + (j0 + bj);
       e = lik_timed(lc, KT_DGEMM, s, [&]() {
         return dgemm<double, double>(panel, M, panel, M, nullptr, trail, M, rest, rest, bj, -1.0, 1.0, 0.0,
@@ -369,24 +416,12 @@ hipError_t gauss_update(LikCtx& lc, const InstState* hst, hipStream_t s) {
       if (e != hipSuccess) return e;
       lc.dgemm_flops += (double)rest * (double)(rest + kDT) * (double)bj;
     }
-    // Z^T = H^T L^-T by blocks of columns: Z^T[:, j] = (H^T[:, j] - Z^T[:, <j] L[j, <j]^T) L_jj^-T
+    // Z^T = H^T L^-T (Z^T L^T = H^T), recursively over column blocks so that
+    // the large updates are single wide GEMMs
     hipLaunchKernelGGL(k_f32_to_f64, dim3((unsigned)(((long long)N * M + 255) / 256)), dim3(256), 0, s, P.HT,
                        P.ZT, (long long)N * M);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    for (int j = 0; j < nb; ++j) {
-      const int j0 = j * kDT, bj = std::min(kDT, M - j0);
-      if (j0 > 0) {
-        e = lik_timed(lc, KT_DGEMM, s, [&]() {
-          return dgemm<double, double>(P.ZT, M, P.S + (long long)j0 * M, M, nullptr, P.ZT + j0, M, N, bj, j0,
-                                       -1.0, 1.0, 0.0, false, s);
-        });
-        if (e != hipSuccess) return e;
-        lc.dgemm_flops += 2.0 * (double)N * (double)bj * (double)j0;
-      }
-      hipLaunchKernelGGL(k_trsm_rows, dim3((N + 255) / 256), dim3(256), 0, s, P.ZT + j0, (long long)M, N,
-                         (const double*)(P.S + (long long)j0 * M + j0), (long long)M, bj);
-      if ((e = hipGetLastError()) != hipSuccess) return e;
-    }
+    if ((e = trsm_right(lc, P, 0, nb, s)) != hipSuccess) return e;
     // t = Z (b / d), then v and E per pixel
     hipLaunchKernelGGL(k_gauss_tpart, dim3((M + 255) / 256, P.nchunk), dim3(256), 0, s, P.ZT, P.b, P.w, M, N,
                        P.tpart);

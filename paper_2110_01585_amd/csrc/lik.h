@@ -108,13 +108,14 @@ struct LikLayout {
 
 // Bytes of the dense buffers of a Gaussian-CS instance (M sensing rows, N
 // pixels), each rounded up to 256 bytes: H and H^T (float), S and Z^T (double),
-// the vectors d, 1/d, b (N), t (M), the partial sums of t and the observation.
+// the vectors d, 1/d, b (N), t (M), the partial sums of t, the inverses of the
+// diagonal Cholesky blocks and the observation.
 constexpr int kGaussChunk = 256;   // rows per partial sum of t = Z (b / d)
 inline size_t gauss_bytes_of(int M, int N) {
   auto r = [](size_t b) { return (b + 255) / 256 * 256; };
   const size_t m = (size_t)M, nn = (size_t)N, nchunk = (nn + kGaussChunk - 1) / kGaussChunk;
   return 2 * r(m * nn * 4) + r(m * m * 8) + r(nn * m * 8) + 3 * r(nn * 8) + r(m * 8) +
-         r(nchunk * m * 8) + r(m * 4);
+         r(nchunk * m * 8) + r((m + 63) / 64 * 64 * 64 * 8) + r(m * 4);
 }
 
 // Number of likelihood tiles and taps floats for the layout.
@@ -214,6 +215,7 @@ struct GaussPlan {
   double* b = nullptr;         // N: right-hand side
   double* t = nullptr;         // M
   double* tpart = nullptr;     // nchunk x M partial sums of t
+  double* Linv = nullptr;      // ceil(M / 64) blocks of 64 x 64: inverses of the diagonal Cholesky blocks
   float* y = nullptr;          // M: the observation
   int nchunk = 0;
 };
