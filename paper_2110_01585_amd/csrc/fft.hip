@@ -77,13 +77,21 @@ struct Padded {
 };
 
 // ---- in-register DFTs of size 2..16 (radix-2 decimation in time) ----
-// cos and sin of 2 pi k / 16
-__constant__ float kC16[16] = {1.0f, 0.92387953251128674f, 0.70710678118654752f,
-                               0.38268343236508977f, 0.0f, -0.38268343236508977f,
-                               -0.70710678118654752f, -0.92387953251128674f, -1.0f,
-                               -0.92387953251128674f, -0.70710678118654752f,
-                               -0.38268343236508977f, 0.0f, 0.38268343236508977f,
-                               0.70710678118654752f, 0.92387953251128674f};
+// cos(2 pi t / 16); the argument is a compile-time constant once the butterfly
+// loops are unrolled, so the value folds into the instruction
+__device__ constexpr float cos16(int t) {
+  switch (t & 15) {
+    case 0: return 1.0f;
+    case 1: case 15: return 0.92387953251128674f;
+    case 2: case 14: return 0.70710678118654752f;
+    case 3: case 13: return 0.38268343236508977f;
+    case 4: case 12: return 0.0f;
+    case 5: case 11: return -0.38268343236508977f;
+    case 6: case 10: return -0.70710678118654752f;
+    case 7: case 9: return -0.92387953251128674f;
+    default: return -1.0f;
+  }
+}
 
 __device__ constexpr int bitrev_c(int i, int bits) {
   int r = 0;
@@ -91,8 +99,19 @@ __device__ constexpr int bitrev_c(int i, int bits) {
   return r;
 }
 
-template <int R>
-__device__ __forceinline__ void dft_reg(float2 (&v)[R], float sgn) {
+// b e^{s 2 pi i t / 16}, s = +1 for the inverse transform and -1 for the
+// forward one; t < 8.  t = 0 and t = 4 (a multiplication by s i) cost nothing.
+template <bool INV>
+__device__ __forceinline__ float2 rot16(float2 b, int t) {
+  constexpr float sg = INV ? 1.f : -1.f;
+  if (t == 0) return b;
+  if (t == 4) return make_float2(-sg * b.y, sg * b.x);
+  const float c = cos16(t), sn = sg * cos16(t + 12);   // sin(x) = cos(x - pi/2)
+  return make_float2(c * b.x - sn * b.y, c * b.y + sn * b.x);
+}
+
+template <int R, bool INV>
+__device__ __forceinline__ void dft_reg(float2 (&v)[R]) {
   constexpr int bits = R == 2 ? 1 : R == 4 ? 2 : R == 8 ? 3 : 4;
 #pragma unroll
   for (int i = 0; i < R; ++i) {
@@ -109,11 +128,8 @@ __device__ __forceinline__ void dft_reg(float2 (&v)[R], float sgn) {
     for (int k = 0; k < R; k += m) {
 #pragma unroll
       for (int j = 0; j < m / 2; ++j) {
-        // w = e^{sgn 2 pi i j / m} = cos + i sgn sin, index j * 16 / m into the 16-point table
-        const int t = j * (16 / m);
-        const float c = kC16[t], sn = kC16[(t + 12) & 15];   // sin(x) = cos(x - pi/2)
-        const float2 b = v[k + j + m / 2];
-        const float2 tw = make_float2(c * b.x - sgn * sn * b.y, c * b.y + sgn * sn * b.x);
+        // w = e^{s 2 pi i j / m}, index j * 16 / m of the 16-point circle
+        const float2 tw = rot16<INV>(v[k + j + m / 2], j * (16 / m));
         const float2 u = v[k + j];
         v[k + j] = make_float2(u.x + tw.x, u.y + tw.y);
         v[k + j + m / 2] = make_float2(u.x - tw.x, u.y - tw.y);
@@ -125,15 +141,22 @@ __device__ __forceinline__ void dft_reg(float2 (&v)[R], float sgn) {
 // One radix-R Stockham pass over `rows` rows of length L held in LDS, in place:
 // every work item reads its R inputs into registers before the barrier and
 // writes its R outputs after it.  Work item j of a row (j < L/R), k = j mod Ns:
-//   in:  X[j + r L/R],  twiddled by e^{sgn 2 pi i r k / (R Ns)}
+//   in:  X[j + r L/R],  twiddled by e^{s 2 pi i r k / (R Ns)}
 //   out: X[(j - k) R + k + r Ns]
 // R, Ns and L are compile-time, so the index arithmetic is shifts and masks.
-template <int R, int Ns, int L>
-__device__ __forceinline__ void stockham_pass(float2* X, int rows, const float2* __restrict__ tw,
-                                              float sgn) {
+// In the padded index, the r-th input and output of an item sit at fixed
+// offsets from its first ones whenever the unpadded stride is a multiple of 16
+// (or, for the outputs of the first pass, the R outputs lie in one group of
+// 16), so those accesses take immediate offsets.
+template <int R, int Ns, int L, bool INV>
+__device__ __forceinline__ void stockham_pass(float2* X, int rows, const float2* __restrict__ tw) {
   constexpr int kItems = 16 / R;               // work items per thread (rows * L <= 4096)
   constexpr int per_row = L / R;
   constexpr int step = L / (R * Ns);
+  constexpr bool kInFold = per_row % 16 == 0;
+  constexpr int kInStride = per_row + per_row / 16;
+  constexpr bool kOutFold = Ns == 1 || Ns % 16 == 0;
+  constexpr int kOutStride = Ns == 1 ? 1 : Ns + Ns / 16;
   const int total = rows * per_row;
   float2 v[kItems][R];
   int base[kItems];
@@ -145,13 +168,15 @@ __device__ __forceinline__ void stockham_pass(float2* X, int rows, const float2*
       const int row = w / per_row, j = w % per_row;
       const int k = j & (Ns - 1);
       const int rbase = row * L + j;
+      const int pin = pidx(rbase);
+      const int ks = k * step;
 #pragma unroll
       for (int r = 0; r < R; ++r) {
-        float2 x = X[pidx(rbase + r * per_row)];
+        float2 x = X[kInFold ? pin + r * kInStride : pidx(rbase + r * per_row)];
         if (Ns > 1 && r > 0) {
-          float2 t = tw[r * k * step];
-          t.y *= -sgn;        // table holds e^{-2 pi i t / L}; sgn = +1 for the inverse
-          x = cmul(x, t);
+          const float2 t = tw[r * ks];   // e^{-2 pi i r k / (R Ns)}
+          x = INV ? make_float2(x.x * t.x + x.y * t.y, x.y * t.x - x.x * t.y)
+                  : make_float2(x.x * t.x - x.y * t.y, x.y * t.x + x.x * t.y);
         }
         v[it][r] = x;
       }
@@ -162,34 +187,32 @@ __device__ __forceinline__ void stockham_pass(float2* X, int rows, const float2*
 #pragma unroll
   for (int it = 0; it < kItems; ++it) {
     if (base[it] >= 0) {
-      dft_reg<R>(v[it], sgn);
+      dft_reg<R, INV>(v[it]);
+      const int pout = pidx(base[it]);
 #pragma unroll
-      for (int r = 0; r < R; ++r) X[pidx(base[it] + r * Ns)] = v[it][r];
+      for (int r = 0; r < R; ++r)
+        X[kOutFold ? pout + r * kOutStride : pidx(base[it] + r * Ns)] = v[it][r];
     }
   }
   __syncthreads();
 }
 
-// Largest radix of a pass in a workgroup that holds NP points.
-constexpr int max_radix(int NP) { return 16; }
-
-// All passes of a length-L transform: the largest radix while enough points per
+// All passes of a length-L transform: radix 16 while at least 16 points per
 // butterfly remain, then one pass of the remaining radix.
-template <int L, int Ns, int NP>
-__device__ __forceinline__ void fft_passes(float2* X, int rows, const float2* __restrict__ tw,
-                                           float sgn) {
+template <int L, int Ns, bool INV>
+__device__ __forceinline__ void fft_passes(float2* X, int rows, const float2* __restrict__ tw) {
   if constexpr (Ns < L) {
-    constexpr int RM = max_radix(NP);
-    constexpr int R = (L / Ns) >= RM ? RM : (L / Ns);
-    stockham_pass<R, Ns, L>(X, rows, tw, sgn);
-    fft_passes<L, Ns * R, NP>(X, rows, tw, sgn);
+    constexpr int R = (L / Ns) >= 16 ? 16 : (L / Ns);
+    stockham_pass<R, Ns, L, INV>(X, rows, tw);
+    fft_passes<L, Ns * R, INV>(X, rows, tw);
   }
 }
 
-
-// Complex rows per workgroup of the row-transform kernels for length L; the
-// kernels' LDS arrays, their launch grids and the RF_INV partial counts all
-// follow from this one definition.
+// Complex rows per workgroup of the row-transform kernels for length L: 2048
+// points, at most 16 rows (4096-point blocks, one radix-16 item per thread,
+// halve the workgroups in flight and run slower).  The kernels' LDS arrays,
+// their launch grids and the RF_INV partial counts all follow from this one
+// definition.
 constexpr int rows_per_block(int L) { return L >= 2048 ? 1 : (2048 / L > 16 ? 16 : 2048 / L); }
 
 template <int L>
@@ -229,7 +252,12 @@ __global__ __launch_bounds__(256) void k_fft_rows(FftArgs a) {
   }
   __syncthreads();
   // ---- Stockham passes: radix 16 while possible, then 8, 4, 2 ----
-  if (a.logL > 0) fft_passes<L, 1, kRows * L>(X, rows, a.tw, a.inverse ? 1.f : -1.f);
+  if (a.logL > 0) {
+    if (a.inverse)
+      fft_passes<L, 1, true>(X, rows, a.tw);
+    else
+      fft_passes<L, 1, false>(X, rows, a.tw);
+  }
   // ---- store (post-op) ----
   #pragma unroll
   for (int u_ = 0; u_ < (kRows * L + 255) / 256; ++u_) {
@@ -490,9 +518,9 @@ __global__ __launch_bounds__(256) void k_rfft(RfftArgs a) {
   __syncthreads();
   if (!skip) {
     if (STAGE == RF_FWD) {
-      fft_passes<L, 1, kRows * L>(X, rows, a.tw, -1.f);
+      fft_passes<L, 1, false>(X, rows, a.tw);
     } else if (STAGE == RF_FILT) {
-      fft_passes<L, 1, kRows * L>(X, rows, a.tw, -1.f);
+      fft_passes<L, 1, false>(X, rows, a.tw);
       const float dbar = (float)st.dbar;
       #pragma unroll
       for (int u_ = 0; u_ < (kRows * L / 2 + 255) / 256; ++u_) {
@@ -504,14 +532,16 @@ __global__ __launch_bounds__(256) void k_rfft(RfftArgs a) {
 #pragma unroll
         for (int k = 0; k < 2; ++k) {
           const float sp = spv[k] * a.inv_xi;
-          const float m = a.mode == RFM_PRECOND ? a.scale / (sp + dbar) : a.scale * sp;
+          // the preconditioner's filter needs no correctly rounded division
+          const float m = a.mode == RFM_PRECOND ? a.scale * __builtin_amdgcn_rcpf(sp + dbar)
+                                                : a.scale * sp;
           X[pidx(i + k)] = make_float2(X[pidx(i + k)].x * m, X[pidx(i + k)].y * m);
         }
       }
       __syncthreads();
-      fft_passes<L, 1, kRows * L>(X, rows, a.tw, 1.f);
+      fft_passes<L, 1, true>(X, rows, a.tw);
     } else {
-      fft_passes<L, 1, kRows * L>(X, rows, a.tw, 1.f);
+      fft_passes<L, 1, true>(X, rows, a.tw);
     }
   }
   // ---- store ----

@@ -73,7 +73,7 @@ __device__ __forceinline__ PairOut pair_core(float ci, float mi, float cj, float
 #pragma clang fp contract(off)
   const float s = ci + cj;
   const Tilt T = lam.tilt(mi - mj, s);
-  const float dels = T.delta * frcp(s);
+  const float dels = T.dels;
   const float Ei = __builtin_fmaf(dels, ci, mi);
   const float Ej = __builtin_fmaf(-dels, cj, mj);
   PairOut o;
@@ -197,7 +197,7 @@ __device__ __forceinline__ void totals(const Px& p, float& mu, float& v) {
     t += p.t[l];
     e += p.e[l];
   }
-  v = 1.0f / t;
+  v = frcp(t);
   mu = e * v;
 }
 
@@ -258,13 +258,13 @@ __device__ __forceinline__ void finish_row(const SweepArgs& a, long long idx, bo
     if (wL) {
       totals(L, m1, v1);
       dmu = fmaxf(dmu, fabsf(m1 - omL));
-      dv = fmaxf(dv, fabsf(v1 / ovL - 1.f));
+      dv = fmaxf(dv, fabsf((v1 - ovL) * frcp(ovL)));
       if (!(fabsf(m1) < 3.0e38f) || !(v1 > 0.f && v1 < 3.0e38f)) flags |= FLAG_NONFINITE;
     }
     if (wR) {
       totals(R, m1, v1);
       dmu = fmaxf(dmu, fabsf(m1 - omR));
-      dv = fmaxf(dv, fabsf(v1 / ovR - 1.f));
+      dv = fmaxf(dv, fabsf((v1 - ovR) * frcp(ovR)));
       if (!(fabsf(m1) < 3.0e38f) || !(v1 > 0.f && v1 < 3.0e38f)) flags |= FLAG_NONFINITE;
     }
   }

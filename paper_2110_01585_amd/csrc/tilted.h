@@ -29,6 +29,7 @@ __device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x)
 struct Tilt {
   float rho;    // 1 - S_bar / s
   float delta;  // m_bar - m
+  float dels;   // delta / s
   float eabs;   // E|u| under the tilted distribution
   float omr;    // S_bar / s = 1 - rho, formed without the subtraction (mixture factors)
 };
@@ -76,9 +77,10 @@ __device__ __forceinline__ Tilt laplace_tilt(float m, float s, float lam) {
   const float kSqrt2 = 1.41421356237309515f;
   const float kInvSqrt2 = 0.707106781186547573f;
   const float kSqrt2OverPi = 0.797884560802865406f;
-  const float sig = __builtin_amdgcn_sqrtf(s);
+  const float rs = __builtin_amdgcn_rsqf(s);   // 1 / sigma
+  const float sig = s * rs;
   const float ls = lam * s;
-  const float k = kInvSqrt2 * frcp(sig);
+  const float k = kInvSqrt2 * rs;
   const float zp = (ls - m) * k;
   const float zm = (ls + m) * k;
   const float xp = kSqrt2 * zp;
@@ -113,6 +115,7 @@ __device__ __forceinline__ Tilt laplace_tilt(float m, float s, float lam) {
   const float Ks = Kp + Km;
   T.rho = __builtin_fmaf(-(pp * pm * Ks), Ks, pp * rp * Kp + pm * rm * Km);
   T.delta = __builtin_fmaf(sig, pp * rp - pm * rm, -(ls * (pp - pm)));
+  T.dels = T.delta * (rs * rs);
   T.eabs = sig * (pp * Kp + pm * Km);
   T.omr = 0.f;   // not used for this factor
   return T;
@@ -154,6 +157,7 @@ __device__ __forceinline__ Tilt mixture_tilt(float m, float s, const MixFactor& 
   Tilt T;
   const float spread = (w1 * w2) * (m2 * s) * (di * di);
   T.delta = -(m * (s * wi));
+  T.dels = -(m * wi);
   T.rho = s * wi - spread;
   T.omr = w1 * (F.v1 * i1) + w2 * (F.v2 * i2) + spread;
   T.eabs = 0.f;

@@ -168,7 +168,8 @@ def test_deconv2048_one_sweep_step_by_step(monkeypatch):
         i_all, j_all = pb.edges[k - 1]
         pick = rng.choice(i_all.size, 200_000, replace=False)
         sub = types.SimpleNamespace(edges=[(np.zeros(0, int), np.zeros(0, int))] * 4,
-                                    prior=pb.prior, damping=pb.damping)
+                                    prior=pb.prior, damping=pb.damping,
+                                    em_option=pb.em_option, em_diagnostics=False)
         sub.edges[k - 1] = (i_all[pick], j_all[pick])
         tau = np.concatenate([post[:k, 0], pre[k:, 0]])
         eta = np.concatenate([post[:k, 1], pre[k:, 1]])
