@@ -679,7 +679,7 @@ def bench_batch(args, ps, em):
         ctx.ep_tv_init_cold()
         torch.cuda.synchronize()
         t2 = time.perf_counter()
-        rc, st = ctx.ep_tv_solve(min(args.max_sweeps, 200), args.tol, em, None, None)
+        rc, st = ctx.ep_tv_solve(min(args.max_sweeps, 1000), args.tol, em, None, None)
         torch.cuda.synchronize()
         t3 = time.perf_counter()
         sw = [s["sweeps"] for s in st]

@@ -217,3 +217,27 @@ def test_batched_workload_full_size_sampled():
         print(f"sample {p.name} {p.shape}: mean {e_mu:.2e} var {e_v:.2e}")
         assert e_mu <= MEAN_TOL and e_v <= VAR_TOL, p.name
         assert abs(st[i]["lambda"] / info["lam"] - 1) <= 2e-4
+
+
+@pytest.mark.parametrize("index", [6, 13, 15])
+def test_sweeps_to_converged_match_oracle(index):
+    """Batched-workload deconvolution instances that need more than 200 sweeps
+    to meet tol = 5e-6 (EM moves lambda slowly): the device solve stops at the
+    oracle's sweep count (within 3 sweeps, rounding near the threshold), with
+    the same lambda and means.  The sweeps come from the method, not from the
+    device's CG."""
+    p = syn.config3_instance(index)
+    assert "deconv" in p.name
+    c = _ctx([p], graph=True, precond=N.PRECOND_JACOBI)
+    rc, st = c.ep_tv_solve(600, 5e-6, True)
+    outs, _ = _out(c)
+    c.close()
+    mu_o, v_o, _, info = oep.solve(oep.problem_from_synthetic(f32_problem(p)), 600, True, tol=5e-6)
+    s = st[0]
+    print(f"{p.name}: device {s['sweeps']} sweeps, lambda {s['lambda']:.6g}; "
+          f"oracle {info['sweeps']} sweeps, lambda {info['lam']:.6g}")
+    assert s["converged"] and info["converged"]
+    assert s["sweeps"] > 200 and info["sweeps"] > 200
+    assert abs(s["sweeps"] - info["sweeps"]) <= 3
+    assert abs(s["lambda"] / info["lam"] - 1) <= 2e-4
+    assert mean_err(outs[0][0], mu_o) <= MEAN_TOL
