@@ -31,6 +31,9 @@ Workloads (synthetic, seeded; generators in synthetic.py):
               sigma = 0.01, EM (the paper's CS setting): Woodbury moments in FP64 on the
               matrix cores (roofline against the FP64 MFMA peak)
   rbmc512     512^2 deconvolution with the RBMC variance estimator (8 samples)
+  net2048     the warm-start network: a step is one inference on the 2048^2
+              deconvolution observation; also times training steps (forward,
+              backward, Adam) on batches of 16 x 256^2 synthetic targets
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
 """
@@ -347,6 +350,8 @@ def main():
         print("bench.py measures one GPU only: every GPU box here has one GPU and there is no "
               "multi-GPU path (the sharding design is described in DESIGN.md)", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "net2048":
+        return bench_net(args)
     p, em = make_workload(args.workload)
     if isinstance(p, list):
         return bench_batch(args, p, em)
@@ -356,6 +361,85 @@ def main():
 
 
 RBMC_SAMPLES = 8
+BF16_MFMA_PEAK_TFLOPS = 2500.0
+# the warm-start network: 3x3 convolutions 1 -> 32, four 32 -> 32, 32 -> 2
+NET_FLOP_PER_PX = 2 * 9 * (1 * 32 + 4 * 32 * 32 + 32 * 2)
+# bytes each step must move per pixel (input read, output written): the statistics
+# pass over the observation, then per layer: the float
+# observation in, BF16 activations of 32 channels (64 B) between layers, two
+# float outputs
+NET_BYTES_PER_PX = 4 + (4 + 64) + 4 * (64 + 64) + (64 + 8)
+
+
+def bench_net(args):
+    """The warm-start network on its own: inference at 2048^2 (a step), and
+    training steps (forward, backward through all six layers, Adam) on batches
+    of 16 x 256^2, both timed with HIP events on the network's stream."""
+    import numpy as np
+    import torch
+    from paper_2110_01585_amd.net import Net, load_weights
+    dev = torch.device("cuda:0")
+    p, _ = make_workload("deconv2048")
+    h, w = p.shape
+    params, _ = load_weights()
+    net = Net(params, max_batch=1, max_h=h, max_w=w, device=dev)
+    y = torch.tensor(p.y, dtype=torch.float32, device=dev)
+    mu = torch.empty_like(y)
+    var = torch.empty_like(y)
+    st = net.stream
+    for _ in range(max(args.warmup, 1)):
+        net.infer(y, p.xi, mu, var)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(st)
+    for _ in range(args.steps):
+        net.infer(y, p.xi, mu, var)
+    e1.record(st)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    net.close()
+    npx = h * w
+    flops = NET_FLOP_PER_PX * npx
+    nbytes = NET_BYTES_PER_PX * npx
+    # training at the size the network was trained at
+    b, th, tw = 16, 256, 256
+    tnet = Net(params, max_batch=b, max_h=th, max_w=tw, device=dev)
+    g = torch.Generator(device="cpu").manual_seed(7)
+    ty = torch.rand((b, th, tw), generator=g).to(dev)
+    tmu = (ty + 0.01 * torch.randn((b, th, tw), generator=g).to(dev)).contiguous()
+    tvar = torch.full((b, th, tw), 2e-5, device=dev)
+    for _ in range(max(args.warmup, 1)):
+        tnet.train_step(ty, tmu, tvar, 1e-4, 1e-4)
+    torch.cuda.synchronize()
+    e0.record(tnet.stream)
+    for _ in range(args.steps):
+        tnet.train_step(ty, tmu, tvar, 1e-4, 1e-4)
+    e1.record(tnet.stream)
+    torch.cuda.synchronize()
+    tms = e0.elapsed_time(e1) / args.steps
+    tnet.close()
+    tflops = 3 * NET_FLOP_PER_PX * b * th * tw   # forward, input gradient, weight gradient
+    line = {
+        "metric": "warm-start network inferences/s, 2048^2, 1 GPU",
+        "value": 1e3 / ms, "unit": "inferences/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "bf16", "data": "synthetic",
+        "step": "one inference of the 6-layer 3x3 conv net on the 2048^2 deconvolution "
+                "observation (statistics, six BF16-MFMA convolution layers, output map)",
+        "config": {"workload": "net2048", "height": h, "width": w, "channels": 32, "layers": 6},
+        "roofline": {"bound": "hbm", "achieved": round(nbytes / ms / 1e6, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(nbytes / ms / 1e6 / HBM_PEAK_GBS, 4),
+                     "traffic": None, "kernel": "whole inference",
+                     "bytes_per_px": NET_BYTES_PER_PX},
+        "mfma": {"achieved_tflops": round(flops / ms / 1e9, 2), "peak_tflops": BF16_MFMA_PEAK_TFLOPS,
+                 "frac": round(flops / ms / 1e9 / BF16_MFMA_PEAK_TFLOPS, 4),
+                 "flop_per_px": NET_FLOP_PER_PX},
+        "training": {"batch": [b, th, tw], "ms_per_step": round(tms, 3),
+                     "achieved_tflops": round(tflops / tms / 1e9, 2),
+                     "frac_bf16_peak": round(tflops / tms / 1e9 / BF16_MFMA_PEAK_TFLOPS, 4)},
+        "cpu_baseline": None,
+    }
+    print(json.dumps(line), flush=True)
 
 
 def _ctx(p, dev, graph, **kw):

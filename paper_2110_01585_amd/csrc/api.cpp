@@ -546,7 +546,9 @@ int ep_tv_init_cold(ep_tv_ctx* c) {
     return fail(c, EP_TV_E_STATE, "per-pixel noise variances not set (ep_tv_set_noise_variance)");
   int rc = reset_states(c);
   if (rc) return rc;
-  HIPCHK(c, launch_yrange(c->ypix, c->d_inst, c->d_st, c->n, c->stream));
+  // the sweep's per-tile partial arrays serve as the range partials (no sweep runs meanwhile)
+  HIPCHK(c, launch_yrange(c->ypix, c->d_inst, c->d_st, c->n, c->d_tiles, c->ntiles,
+                          c->sa.part_dmu, c->sa.part_dv, c->stream));
   c->cur = 0;
   c->warm_started = false;
   HIPCHK(c, launch_init_cold(cur_sites(c).S, c->ypix, c->d_inst, c->d_st, c->d_tiles, c->ntiles,

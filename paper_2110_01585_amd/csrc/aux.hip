@@ -481,51 +481,84 @@ hipError_t launch_sites_io(float2* const S[5], const InstDev* inst, const int4* 
   return hipGetLastError();
 }
 
-// max - min of the pixel-space observation, one block per instance.
-__global__ __launch_bounds__(1024) void k_yrange(const float* __restrict__ y_pix,
-                                                 const InstDev* __restrict__ inst,
-                                                 InstState* __restrict__ st) {
-  __shared__ float smin[1024], smax[1024];
+// Range and scale of the pixel-space observation, in two steps so that the
+// whole chip reads it: every sweep tile reduces its pixels to a min and a max
+// (partials at the tile's index), then one block per instance reduces its
+// tiles' partials.  Min and max do not depend on the order.
+__device__ __forceinline__ void block_minmax(float& lo, float& hi) {
+#pragma unroll
+  for (int off = kWave / 2; off >= 1; off >>= 1) {
+    lo = fminf(lo, __shfl_xor(lo, off, kWave));
+    hi = fmaxf(hi, __shfl_xor(hi, off, kWave));
+  }
+  __shared__ float wl[4], wh[4];
+  if (threadIdx.x % kWave == 0) {
+    wl[threadIdx.x / kWave] = lo;
+    wh[threadIdx.x / kWave] = hi;
+  }
+  __syncthreads();
+  lo = fminf(fminf(wl[0], wl[1]), fminf(wl[2], wl[3]));
+  hi = fmaxf(fmaxf(wh[0], wh[1]), fmaxf(wh[2], wh[3]));
+}
+
+__global__ __launch_bounds__(256) void k_yrange_tiles(const float* __restrict__ y_pix,
+                                                      const InstDev* __restrict__ inst,
+                                                      const int4* __restrict__ tiles,
+                                                      float* __restrict__ plo,
+                                                      float* __restrict__ phi) {
+  const int tile = blockIdx.x;
+  const int4 td = tiles[tile];
+  const InstDev I = inst[td.x];
+  const int c0 = td.y * kStripInt, c1 = min(c0 + kStripInt, I.W);
+  const int r0 = td.z * I.chunk_rows, r1 = min(r0 + I.chunk_rows, I.H);
+  const int cols = c1 - c0, n = cols * (r1 - r0);
+  float lo = 3.0e38f, hi = -3.0e38f;
+  // up to 8 loads per thread in flight before the first comparison
+  constexpr int kU = 8;
+  for (int i0 = threadIdx.x; i0 < n; i0 += kU * 256) {
+    float v[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int i = i0 + u * 256;
+      const int ii = i < n ? i : i0;   // a repeated pixel leaves min and max unchanged
+      v[u] = y_pix[I.off + (long long)(r0 + ii / cols) * I.pitch + c0 + ii % cols];
+    }
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      lo = fminf(lo, v[u]);
+      hi = fmaxf(hi, v[u]);
+    }
+  }
+  block_minmax(lo, hi);
+  if (threadIdx.x == 0) {
+    plo[tile] = lo;
+    phi[tile] = hi;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_yrange_fin(const InstDev* __restrict__ inst,
+                                                    InstState* __restrict__ st,
+                                                    const float* __restrict__ plo,
+                                                    const float* __restrict__ phi) {
   const InstDev I = inst[blockIdx.x];
   float lo = 3.0e38f, hi = -3.0e38f;
-  // 16 rows per step, all requested before the first comparison; rows past the
-  // last one repeat the step's first row (min and max are unaffected)
-  constexpr int kR = 16;
-  for (int r0 = 0; r0 < I.H; r0 += kR) {
-    for (int c = threadIdx.x; c < I.W; c += blockDim.x) {
-      float v[kR];
-#pragma unroll
-      for (int k = 0; k < kR; ++k) {
-        const int r = r0 + k < I.H ? r0 + k : r0;
-        v[k] = y_pix[I.off + (long long)r * I.pitch + c];
-      }
-#pragma unroll
-      for (int k = 0; k < kR; ++k) {
-        lo = fminf(lo, v[k]);
-        hi = fmaxf(hi, v[k]);
-      }
-    }
+  for (int t = threadIdx.x; t < I.ntiles; t += 256) {
+    lo = fminf(lo, plo[I.tile0 + t]);
+    hi = fmaxf(hi, phi[I.tile0 + t]);
   }
-  smin[threadIdx.x] = lo;
-  smax[threadIdx.x] = hi;
-  __syncthreads();
-  for (int w = 512; w >= 1; w >>= 1) {
-    if ((int)threadIdx.x < w) {
-      smin[threadIdx.x] = fminf(smin[threadIdx.x], smin[threadIdx.x + w]);
-      smax[threadIdx.x] = fmaxf(smax[threadIdx.x], smax[threadIdx.x + w]);
-    }
-    __syncthreads();
-  }
+  block_minmax(lo, hi);
   if (threadIdx.x == 0) {
-    const double lo_d = (double)smin[0], hi_d = (double)smax[0];
+    const double lo_d = (double)lo, hi_d = (double)hi;
     st[blockIdx.x].yrange = hi_d - lo_d;
     st[blockIdx.x].yscale = fmax(hi_d - lo_d, fmax(fabs(lo_d), fabs(hi_d)));
   }
 }
 
 hipError_t launch_yrange(const float* y_pix, const InstDev* inst, InstState* st, int n,
-                         hipStream_t s) {
-  hipLaunchKernelGGL(k_yrange, dim3(n), dim3(1024), 0, s, y_pix, inst, st);
+                         const int4* tiles, int ntiles, float* plo, float* phi, hipStream_t s) {
+  if (n <= 0 || ntiles <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_yrange_tiles, dim3(ntiles), dim3(256), 0, s, y_pix, inst, tiles, plo, phi);
+  hipLaunchKernelGGL(k_yrange_fin, dim3(n), dim3(256), 0, s, inst, st, plo, phi);
   return hipGetLastError();
 }
 

@@ -122,7 +122,7 @@ hipError_t launch_marginals(float2* const S[5], const InstDev* inst, const int4*
 hipError_t launch_sites_io(float2* const S[5], const InstDev* inst, const int4* tiles, int ntiles,
                            float* const* d_tab, int to_user, hipStream_t s);
 hipError_t launch_yrange(const float* y_pix, const InstDev* inst, InstState* st, int n,
-                         hipStream_t s);
+                         const int4* tiles, int ntiles, float* plo, float* phi, hipStream_t s);
 // Warm start from predicted marginals (device pointer tables, one per instance):
 // validates the prediction, computes lambda_0 = scale * (N / a_x)^power (a_x: sum
 // over pairs of the folded-normal mean of x_i - x_j under the prediction) when

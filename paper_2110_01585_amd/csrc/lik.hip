@@ -851,6 +851,18 @@ __global__ __launch_bounds__(256) void k_hty_blur(LikArgs A, const float* __rest
   }
 }
 
+// |K(w)|^2 of a separable kernel u v^T is |U(r)|^2 |V(c)|^2, and each factor
+// is the real transform of the factor's autocorrelation g (symmetric):
+// g(0) + 2 sum_{d>0} g(d) cos(2 pi w d / n), the phase reduced exactly; a
+// power spectrum, so a value rounding has pushed below zero is taken as zero.
+__device__ double autocorr_spectrum(const float* g, int k, int w, int n) {
+  const double two_pi = 6.283185307179586476925;
+  double acc = (double)g[k - 1];
+  for (int d = 1; d < k; ++d)
+    acc += 2.0 * (double)g[k - 1 + d] * cos(two_pi * (double)(((long long)w * d) % n) / n);
+  return fmax(acc, 0.0);
+}
+
 __global__ __launch_bounds__(256) void k_spectrum_blur(LikArgs A) {
   const int tile = blockIdx.x;
   const int4 td = A.tiles[tile];
@@ -859,6 +871,20 @@ __global__ __launch_bounds__(256) void k_spectrum_blur(LikArgs A) {
   const TileXY t = lik_tile(td, L);
   const int cols = t.c1 - t.c0;
   const int n = cols * (t.r1 - t.r0);
+  if (L.sep) {
+    // separable taps: one 1-D spectrum value per tile row and per tile column
+    __shared__ double gr[kLikTH], gc[kLikTW];
+    const int tid = threadIdx.x;
+    if (tid < t.r1 - t.r0) gr[tid] = autocorr_spectrum(A.taps + L.gr_off, L.kh, t.r0 + tid, L.H);
+    else if (tid >= kLikTH && tid - kLikTH < cols)
+      gc[tid - kLikTH] = autocorr_spectrum(A.taps + L.gc_off, L.kw, t.c0 + tid - kLikTH, L.W);
+    __syncthreads();
+    for (int i = tid; i < n; i += blockDim.x) {
+      const int r = i / cols, c = i % cols;
+      A.spec[L.off + (long long)(t.r0 + r) * L.pitch + t.c0 + c] = (float)(gr[r] * gc[c]);
+    }
+    return;
+  }
   const float* k = A.taps + L.k_off;
   const double two_pi = 6.283185307179586476925;
   for (int i = threadIdx.x; i < n; i += blockDim.x) {

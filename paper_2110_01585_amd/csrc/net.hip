@@ -81,39 +81,79 @@ struct NetDev {
   uint16_t* g[2];            // activation gradients (ping-pong)
   float* part;               // weight-gradient partials
   double* loss_part;
+  double2* stats_part;       // per image and stats block: (sum y, sum y^2)
+  double* red_part;          // per chunk of weight-gradient partial blocks and parameter
 };
 
+// partial blocks per image of the statistics pass, chunks of the weight-gradient
+// partial blocks summed in the first reduction step
+constexpr int kStatBlocks = 256;
+constexpr int kRedChunks = 32;
+
 // ---------------------------------------------------------------- image statistics
-__global__ __launch_bounds__(256) void k_stats(const float* __restrict__ y, int H, int W,
-                                               float2* __restrict__ stats) {
-  const int n = blockIdx.x;
+// Mean and standard deviation of each image, in two steps so that the whole
+// chip reads the images: kStatBlocks blocks per image sum contiguous slices
+// (FP64, a wave butterfly and the four wave totals in a fixed order), then one
+// block per image sums those partials in a fixed order.
+__device__ __forceinline__ void block_sum2(double& s1, double& s2) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+    s1 += __shfl_xor(s1, off, 64);
+    s2 += __shfl_xor(s2, off, 64);
+  }
+  __shared__ double a[4], b[4];
+  if ((threadIdx.x & 63) == 0) {
+    a[threadIdx.x >> 6] = s1;
+    b[threadIdx.x >> 6] = s2;
+  }
+  __syncthreads();
+  s1 = (a[0] + a[1]) + (a[2] + a[3]);
+  s2 = (b[0] + b[1]) + (b[2] + b[3]);
+}
+
+__global__ __launch_bounds__(256) void k_stats_part(const float* __restrict__ y, int H, int W,
+                                                    double2* __restrict__ part) {
+  const int n = blockIdx.y;
   const long long np = (long long)H * W;
+  const long long per = (np + kStatBlocks - 1) / kStatBlocks;
+  const long long i0 = (long long)blockIdx.x * per;
+  const long long i1 = i0 + per < np ? i0 + per : np;
   const float* yi = y + (long long)n * np;
   double s1 = 0.0, s2 = 0.0;
-  for (long long i = threadIdx.x; i < np; i += blockDim.x) {
-    const double v = yi[i];
-    s1 += v;
-    s2 += v * v;
-  }
-  __shared__ double a[256], b[256];
-  a[threadIdx.x] = s1;
-  b[threadIdx.x] = s2;
-  __syncthreads();
-  for (int w = 128; w >= 1; w >>= 1) {
-    if ((int)threadIdx.x < w) {
-      a[threadIdx.x] += a[threadIdx.x + w];
-      b[threadIdx.x] += b[threadIdx.x + w];
+  constexpr int kU = 8;   // loads in flight per thread
+  for (long long b = i0 + threadIdx.x; b < i1; b += kU * 256) {
+    float v[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const long long i = b + (long long)u * 256;
+      v[u] = i < i1 ? yi[i] : 0.f;
     }
-    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      s1 += (double)v[u];
+      s2 += (double)v[u] * (double)v[u];
+    }
   }
+  block_sum2(s1, s2);
+  if (threadIdx.x == 0) part[(long long)n * kStatBlocks + blockIdx.x] = make_double2(s1, s2);
+}
+
+__global__ __launch_bounds__(256) void k_stats_fin(const double2* __restrict__ part, int H, int W,
+                                                   float2* __restrict__ stats) {
+  static_assert(kStatBlocks == 256, "one partial per thread");
+  const int n = blockIdx.x;
+  const long long np = (long long)H * W;
+  const double2 p = part[(long long)n * kStatBlocks + threadIdx.x];
+  double s1 = p.x, s2 = p.y;
+  block_sum2(s1, s2);
   if (threadIdx.x == 0) {
-    const double m = a[0] / (double)np;
-    double var = b[0] / (double)np - m * m;
+    const double m = s1 / (double)np;
+    double var = s2 / (double)np - m * m;
     // second pass is not needed at the precision the network uses; guard round-off
     if (var < 0.0) var = 0.0;
-    double s = sqrt(var);
-    if (s < kSFloor) s = kSFloor;
-    stats[n] = make_float2((float)m, (float)s);
+    double sd = sqrt(var);
+    if (sd < kSFloor) sd = kSFloor;
+    stats[n] = make_float2((float)m, (float)sd);
   }
 }
 
@@ -540,13 +580,28 @@ __global__ __launch_bounds__(256) void k_wgrad1(const float* __restrict__ y,
   if (tid < C) pp[kW1 + tid] = bsum;
 }
 
-// fixed-order float64 sum of the per-block partials into the canonical gradient
-__global__ __launch_bounds__(256) void k_reduce(const float* __restrict__ part, int nblocks, int count,
-                                                float* __restrict__ grad_out) {
+// Fixed-order float64 sum of the per-block partials into the canonical
+// gradient, in two steps: chunk c of kRedChunks sums its contiguous range of
+// partial blocks in ascending order, then the chunk sums are added in
+// ascending chunk order.
+__global__ __launch_bounds__(256) void k_reduce_chunks(const float* __restrict__ part, int nblocks,
+                                                       int count, double* __restrict__ red) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= count) return;
+  const int per = (nblocks + kRedChunks - 1) / kRedChunks;
+  const int b0 = blockIdx.y * per, b1 = min(b0 + per, nblocks);
+  double s = 0.0;
+  for (int b = b0; b < b1; ++b) s += part[(long long)b * kPartStride + k];
+  red[(long long)blockIdx.y * count + k] = s;
+}
+
+__global__ __launch_bounds__(256) void k_reduce_fin(const double* __restrict__ red, int count,
+                                                    float* __restrict__ grad_out) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= count) return;
   double s = 0.0;
-  for (int b = 0; b < nblocks; ++b) s += part[(long long)b * kPartStride + k];
+#pragma unroll 8
+  for (int c = 0; c < kRedChunks; ++c) s += red[(long long)c * count + k];
   grad_out[k] = (float)s;
 }
 
@@ -617,7 +672,8 @@ constexpr size_t kAlign = 256;
 size_t rup(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 struct NetLayout {
-  size_t wf, wd, w1r, w6r, grad, am, av, stats, act[5], o, g[2], part, loss_part, loss, total;
+  size_t wf, wd, w1r, w6r, grad, am, av, stats, act[5], o, g[2], part, loss_part, loss, stats_part,
+      red_part, total;
   long long nblk, nloss;
 };
 
@@ -644,6 +700,8 @@ bool net_layout(int max_batch, int max_h, int max_w, NetLayout& L) {
   L.part = take((size_t)L.nblk * kPartStride * 4);
   L.loss_part = take((size_t)L.nloss * 8);
   L.loss = take(8);
+  L.stats_part = take((size_t)max_batch * kStatBlocks * 16);
+  L.red_part = take((size_t)kRedChunks * kStride32 * 8);
   L.total = cur;
   return true;
 }
@@ -676,11 +734,19 @@ hipError_t pack(ep_tv_net* n) {
   return hipGetLastError();
 }
 
+// canonical gradient of `count` parameters from the nblk per-block partials
+void reduce_grad(ep_tv_net* n, int nblk, int count, float* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_reduce_chunks, dim3((count + 255) / 256, kRedChunks), dim3(256), 0, s, n->d.part,
+                     nblk, count, n->d.red_part);
+  hipLaunchKernelGGL(k_reduce_fin, dim3((count + 255) / 256), dim3(256), 0, s, n->d.red_part, count, out);
+}
+
 // forward pass up to a5 (stats, layers 1..5)
 hipError_t forward5(ep_tv_net* n, const float* y, int B, int H, int W) {
   const hipStream_t s = n->stream;
   const long long P = (long long)B * H * W;
-  hipLaunchKernelGGL(k_stats, dim3(B), dim3(256), 0, s, y, H, W, n->d.stats);
+  hipLaunchKernelGGL(k_stats_part, dim3(kStatBlocks, B), dim3(256), 0, s, y, H, W, n->d.stats_part);
+  hipLaunchKernelGGL(k_stats_fin, dim3(B), dim3(256), 0, s, n->d.stats_part, H, W, n->d.stats);
   hipLaunchKernelGGL(k_conv1, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, s, y, n->d.stats, n->d.w1r,
                      n->master + kOffB1, n->d.act[0], B, H, W);
   const dim3 g((W + 63) / 64, (H + 3) / 4, B);
@@ -735,6 +801,8 @@ int ep_tv_net_create(float* d_params, void* d_ws, size_t ws_bytes, int32_t max_b
   d.g[1] = reinterpret_cast<uint16_t*>(ws + L.g[1]);
   d.part = reinterpret_cast<float*>(ws + L.part);
   d.loss_part = reinterpret_cast<double*>(ws + L.loss_part);
+  d.stats_part = reinterpret_cast<double2*>(ws + L.stats_part);
+  d.red_part = reinterpret_cast<double*>(ws + L.red_part);
   n->d_loss = reinterpret_cast<double*>(ws + L.loss);
   int rc = ep_tv_net_sync(n);
   if (rc != EP_TV_OK) {
@@ -790,8 +858,7 @@ int ep_tv_net_loss_grad(ep_tv_net* n, const float* d_y, const float* d_mu_t, con
   const dim3 gc((w + 63) / 64, (h + 3) / 4, batch);
   // layer 6: weight gradient, input gradient (masked by a5)
   hipLaunchKernelGGL(k_wgrad6, gt, dim3(256), 0, s, n->d.act[4], n->d.o, n->d.part, h, w);
-  hipLaunchKernelGGL(k_reduce, dim3((kW6 + 2 + 255) / 256), dim3(256), 0, s, n->d.part, nblk, kW6 + 2,
-                     n->d.grad + kOffW6);
+  reduce_grad(n, nblk, kW6 + 2, n->d.grad + kOffW6, s);
   hipLaunchKernelGGL(k_dgrad6, dim3(nl), dim3(256), 0, s, n->d.o, n->d.w6r, n->d.act[4], n->d.g[0], batch, h,
                      w);
   // layers 5..2: weight gradient from (a_{l-1}, g_l), then g_{l-1} = W_l^T g_l masked by a_{l-1}
@@ -799,16 +866,14 @@ int ep_tv_net_loss_grad(ep_tv_net* n, const float* d_y, const float* d_mu_t, con
   for (int l = 3; l >= 0; --l) {           // l = index of the 32 -> 32 layer (layer l + 2)
     const uint16_t* xin = n->d.act[l];
     hipLaunchKernelGGL(k_wgrad32, gt, dim3(256), 0, s, xin, n->d.g[cur], n->d.part, h, w);
-    hipLaunchKernelGGL(k_reduce, dim3((kStride32 + 255) / 256), dim3(256), 0, s, n->d.part, nblk, kStride32,
-                       n->d.grad + kOff2 + l * kStride32);
+    reduce_grad(n, nblk, kStride32, n->d.grad + kOff2 + l * kStride32, s);
     hipLaunchKernelGGL((k_conv32<EPI_MASK>), gc, dim3(256), 0, s, n->d.g[cur], n->d.wd + l * kW32,
                        (const float*)nullptr, xin, n->d.g[cur ^ 1], h, w);
     cur ^= 1;
   }
   // layer 1
   hipLaunchKernelGGL(k_wgrad1, gt, dim3(256), 0, s, d_y, n->d.stats, n->d.g[cur], n->d.part, h, w);
-  hipLaunchKernelGGL(k_reduce, dim3((kW1 + C + 255) / 256), dim3(256), 0, s, n->d.part, nblk, kW1 + C,
-                     n->d.grad + kOffW1);
+  reduce_grad(n, nblk, kW1 + C, n->d.grad + kOffW1, s);
   NCHK(n, hipGetLastError());
   if (d_grad) NCHK(n, hipMemcpyAsync(d_grad, n->d.grad, kParams * 4, hipMemcpyDeviceToDevice, s));
   n->have_grad = true;

@@ -141,7 +141,9 @@ extern "C" int ep_tv_denoise_noalloc(int32_t height, int32_t width, int32_t boun
   if (hipMemcpy2DAsync(ypix, sizeof(float) * I.pitch, d_y, sizeof(float) * width,
                        sizeof(float) * width, height, hipMemcpyDeviceToDevice, s) != hipSuccess)
     return EP_TV_E_HIP;
-  if (launch_yrange(ypix, d_inst, d_st, 1, s) != hipSuccess) return EP_TV_E_HIP;
+  if (launch_yrange(ypix, d_inst, d_st, 1, d_tiles, I.ntiles, reinterpret_cast<float*>(base + o_pm),
+                    reinterpret_cast<float*>(base + o_pv), s) != hipSuccess)
+    return EP_TV_E_HIP;
   int par = 0;
   float2* S[5] = {S0, SB[0][0], SB[0][1], SB[0][2], SB[0][3]};
   if (launch_init_cold(S, ypix, d_inst, d_st, d_tiles, I.ntiles, s) != hipSuccess) return EP_TV_E_HIP;

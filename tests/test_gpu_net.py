@@ -26,6 +26,11 @@ from paper_2110_01585_amd.net import init_params  # noqa: E402
 # ulp = 2^-8 relative) and propagating through the later layers.
 OUT_TOL = 1e-2        # max |o_gpu - o_oracle| / max |o_oracle|
 GRAD_TOL = 2e-2       # per-tensor relative Frobenius error of the parameter gradient
+# element by element: |g_gpu - g_oracle| <= GRAD_RTOL |g_oracle| + GRAD_ATOL max |g_oracle|
+# (the absolute part covers elements that are sums of terms cancelling to near zero,
+# where one flipped bfloat16 rounding upstream is large relative to the element)
+GRAD_RTOL = 2e-2
+GRAD_ATOL = 5e-3
 LOSS_TOL = 1e-3
 
 
@@ -86,8 +91,11 @@ def test_loss_grad_matches_oracle(b, h, w):
     for li, ((gw, gb), (rw, rb)) in enumerate(zip(onet.unpack(g), onet.unpack(g_ref))):
         for name, a, r in (("W", gw, rw), ("b", gb, rb)):
             e = np.linalg.norm(a - r) / np.linalg.norm(r)
-            print(f"layer {li + 1} {name}: rel err {e:.2e}")
+            scale = np.max(np.abs(r))
+            ew = np.max(np.abs(a - r) / (GRAD_RTOL * np.abs(r) + GRAD_ATOL * scale))
+            print(f"layer {li + 1} {name}: rel err {e:.2e}, element-wise {ew:.2f} of the bound")
             assert e <= GRAD_TOL, (li, name, e)
+            assert ew <= 1.0, (li, name, ew)
     net.close()
 
 
