@@ -116,6 +116,22 @@ __device__ __forceinline__ void pair_local(Px& P, Px& Q, bool exists, bool cnt_e
   }
 }
 
+// Neighbouring lanes' values by DPP wave shifts (one VALU move, no LDS round
+// trip); the lane without a neighbour gets its own value, as with __shfl_down /
+// __shfl_up of one lane.  Called with every lane of the wave active.
+__device__ __forceinline__ int from_next_lane(int v) {
+  return __builtin_amdgcn_update_dpp(v, v, 0x130 /* wave_shl:1 */, 0xf, 0xf, false);
+}
+__device__ __forceinline__ int from_prev_lane(int v) {
+  return __builtin_amdgcn_update_dpp(v, v, 0x138 /* wave_shr:1 */, 0xf, 0xf, false);
+}
+__device__ __forceinline__ float from_next_lane(float v) {
+  return __builtin_bit_cast(float, from_next_lane(__builtin_bit_cast(int, v)));
+}
+__device__ __forceinline__ float from_prev_lane(float v) {
+  return __builtin_bit_cast(float, from_prev_lane(__builtin_bit_cast(int, v)));
+}
+
 // V2 pair: this lane's right pixel R with the next lane's left pixel.
 // exists: the pair (R, next L) exists (evaluated by the owning lane).
 template <class PR>
@@ -123,15 +139,15 @@ __device__ __forceinline__ void pair_v2(Px& L, Px& R, bool exists, bool cnt_edge
                                         bool cnt_l, const PR& lam, float alpha, Acc& acc, int lane) {
   float cl, ml;
   cavity<2>(L, cl, ml);
-  const float cj = __shfl_down(cl, 1, kWave);
-  const float mj = __shfl_down(ml, 1, kWave);
+  const float cj = from_next_lane(cl);
+  const float mj = from_next_lane(ml);
   float ci, mi;
   cavity<2>(R, ci, mi);
   const PairOut o = pair_core(ci, mi, cj, mj, lam);
   // hand the partner's new site back to the lane that owns it
-  const float tj = __shfl_up(o.tj, 1, kWave);
-  const float ej = __shfl_up(o.ej, 1, kWave);
-  const int bits = __shfl_up((exists ? 1 : 0) | (o.kj ? 2 : 0), 1, kWave);
+  const float tj = from_prev_lane(o.tj);
+  const float ej = from_prev_lane(o.ej);
+  const int bits = from_prev_lane((exists ? 1 : 0) | (o.kj ? 2 : 0));
   if (exists) {
     damp<2>(R, o.ti, o.ei, alpha);
     if (cnt_edge) acc.eabs += (double)o.eabs;
@@ -191,9 +207,9 @@ __device__ __forceinline__ void store_row(const SweepArgs& a, long long idx, boo
 }
 
 __device__ __forceinline__ void totals(const Px& p, float& mu, float& v) {
-  float t = 0.f, e = 0.f;
+  float t = p.t[0], e = p.e[0];
 #pragma unroll
-  for (int l = 0; l < 5; ++l) {
+  for (int l = 1; l < 5; ++l) {
     t += p.t[l];
     e += p.e[l];
   }
