@@ -151,6 +151,7 @@ const char* validate(const ep_tv_problem& p) {
     if (!fft_size_ok(p.height) || !fft_size_ok(p.width))
       return "Walsh-Hadamard operator needs power-of-two sizes in [4, 4096]";
   }
+  if (p.reserved != 0) return "reserved must be 0";
   return nullptr;
 }
 
@@ -416,6 +417,7 @@ int ep_tv_workspace_bytes(const ep_tv_problem* p, int32_t n, size_t* bytes) {
   std::vector<InstHost> ih(n);
   for (int i = 0; i < n; ++i) {
     if (validate(p[i])) return EP_TV_E_ARG;
+    if (p[i].prior != p[0].prior) return EP_TV_E_ARG;   // as ep_tv_create
     ih[i].p = p[i];
   }
   Layout L;
