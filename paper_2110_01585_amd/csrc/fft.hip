@@ -148,9 +148,10 @@ __device__ __forceinline__ void dft_reg(float2 (&v)[R]) {
 // offsets from its first ones whenever the unpadded stride is a multiple of 16
 // (or, for the outputs of the first pass, the R outputs lie in one group of
 // 16), so those accesses take immediate offsets.
-template <int R, int Ns, int L, bool INV>
+template <int R, int Ns, int L, bool INV, int NP>
 __device__ __forceinline__ void stockham_pass(float2* X, int rows, const float2* __restrict__ tw) {
-  constexpr int kItems = 16 / R;               // work items per thread (rows * L <= 4096)
+  // work items per thread for NP points in the workgroup (NP <= 4096)
+  constexpr int kItems = NP / R > 256 ? NP / R / 256 : 1;
   constexpr int per_row = L / R;
   constexpr int step = L / (R * Ns);
   constexpr bool kInFold = per_row % 16 == 0;
@@ -197,14 +198,17 @@ __device__ __forceinline__ void stockham_pass(float2* X, int rows, const float2*
   __syncthreads();
 }
 
-// All passes of a length-L transform: radix 16 while at least 16 points per
-// butterfly remain, then one pass of the remaining radix.
-template <int L, int Ns, bool INV>
+// All passes of a length-L transform in a workgroup of NP points: radix 16
+// while at least 16 points per butterfly remain, then one pass of the remaining
+// radix.  (Radix-8 passes, which keep all four waves busy in a 2048-point
+// workgroup where radix-16 passes occupy two, measured slower: one more LDS
+// round trip and barrier per transform.)
+template <int L, int Ns, bool INV, int NP>
 __device__ __forceinline__ void fft_passes(float2* X, int rows, const float2* __restrict__ tw) {
   if constexpr (Ns < L) {
     constexpr int R = (L / Ns) >= 16 ? 16 : (L / Ns);
-    stockham_pass<R, Ns, L, INV>(X, rows, tw);
-    fft_passes<L, Ns * R, INV>(X, rows, tw);
+    stockham_pass<R, Ns, L, INV, NP>(X, rows, tw);
+    fft_passes<L, Ns * R, INV, NP>(X, rows, tw);
   }
 }
 
@@ -254,9 +258,9 @@ __global__ __launch_bounds__(256) void k_fft_rows(FftArgs a) {
   // ---- Stockham passes: radix 16 while possible, then 8, 4, 2 ----
   if (a.logL > 0) {
     if (a.inverse)
-      fft_passes<L, 1, true>(X, rows, a.tw);
+      fft_passes<L, 1, true, kRows * L>(X, rows, a.tw);
     else
-      fft_passes<L, 1, false>(X, rows, a.tw);
+      fft_passes<L, 1, false, kRows * L>(X, rows, a.tw);
   }
   // ---- store (post-op) ----
   #pragma unroll
@@ -518,9 +522,9 @@ __global__ __launch_bounds__(256) void k_rfft(RfftArgs a) {
   __syncthreads();
   if (!skip) {
     if (STAGE == RF_FWD) {
-      fft_passes<L, 1, false>(X, rows, a.tw);
+      fft_passes<L, 1, false, kRows * L>(X, rows, a.tw);
     } else if (STAGE == RF_FILT) {
-      fft_passes<L, 1, false>(X, rows, a.tw);
+      fft_passes<L, 1, false, kRows * L>(X, rows, a.tw);
       const float dbar = (float)st.dbar;
       #pragma unroll
       for (int u_ = 0; u_ < (kRows * L / 2 + 255) / 256; ++u_) {
@@ -539,9 +543,9 @@ __global__ __launch_bounds__(256) void k_rfft(RfftArgs a) {
         }
       }
       __syncthreads();
-      fft_passes<L, 1, true>(X, rows, a.tw);
+      fft_passes<L, 1, true, kRows * L>(X, rows, a.tw);
     } else {
-      fft_passes<L, 1, true>(X, rows, a.tw);
+      fft_passes<L, 1, true, kRows * L>(X, rows, a.tw);
     }
   }
   // ---- store ----
