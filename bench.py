@@ -279,6 +279,18 @@ def cpu_baseline_pool(ps, stride=8, sweeps=2):
             "cpu_count": os.cpu_count(), "cpu_model": cpu_model()}
 
 
+# CPU samples of the secondary workloads (side, sweeps), each about 10-30 s of
+# oracle work on one core and with at least two likelihood-site updates where
+# there is a likelihood site (the first sweep from cold has none): 1024^2
+# denoising (the oracle's per-sweep rate there is within 10 % of its rate at
+# 4096^2, where two sweeps take two minutes), a 1024^2 Hadamard instance (the
+# oracle's dense Walsh products grow as the cube of the side), an 80^2 Gaussian
+# CS instance (the dense Woodbury solve grows as the cube of the pixel count),
+# a 128^2 RBMC instance (8 CG solves per sweep)
+CPU_SAMPLE = {"denoise4096": (1024, 3), "hcs2048": (1024, 3), "gcs128": (80, 3),
+              "rbmc512": (128, 3)}
+
+
 def cpu_baseline_sample(name, size, sweeps):
     """The oracle on the first sweeps of a smaller instance of the same family
     (secondary workloads)."""
@@ -292,8 +304,8 @@ def cpu_baseline_sample(name, size, sweeps):
         p, em = syn.make_hadamard_cs(size, size, max(3, round(150 * size * size / 1024 ** 2)), 0.01,
                                      0.3, syn.rng_for(6, 1), lam0=1.0, sweeps=1, em=True), True
     elif name == "gcs128":
-        size = min(size, 64)
-        p, em = syn.make_gauss_cs(size, size, 3, 0.01, 0.3, syn.rng_for(7, 1), lam0=1.0), True
+        p, em = syn.make_gauss_cs(size, size, max(3, round(12 * size * size / 128 ** 2)), 0.01, 0.3,
+                                  syn.rng_for(7, 1), lam0=1.0), True
     elif name == "rbmc512":
         size = min(size, 128)
         p, em = syn.config1(size=size, sweeps=1), True
@@ -339,8 +351,10 @@ def main():
                          "reduction (0: skip)")
     ap.add_argument("--launch", choices=("graph", "stream"), default="graph",
                     help="replay each sweep's launches as a hipGraph, or launch them one by one")
-    ap.add_argument("--cpu-sweeps", type=int, default=4)
-    ap.add_argument("--cpu-size", type=int, default=256)
+    ap.add_argument("--cpu-sweeps", type=int, default=None,
+                    help="secondary workloads: oracle sweeps of the CPU sample (default per workload)")
+    ap.add_argument("--cpu-size", type=int, default=None,
+                    help="secondary workloads: side of the CPU sample (default per workload)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device copy (counter scaling for rocprofv3)")
     args = ap.parse_args()
@@ -709,7 +723,8 @@ def bench_sweeps(args, p, em):
     roof, kernels = kernel_rooflines(tm, h * w, args.workload, p.op)
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline_sample(args.workload, args.cpu_size, args.cpu_sweeps)
+        size, sweeps = CPU_SAMPLE.get(args.workload, (256, 4))
+        cpu = cpu_baseline_sample(args.workload, args.cpu_size or size, args.cpu_sweeps or sweeps)
     line = {
         "metric": f"EP factor-updates/s, {args.workload}, 1 GPU",
         "value": value, "unit": "factor-updates/s", "n_gpus": 1, "steps": args.steps,
