@@ -131,51 +131,61 @@ static hipError_t dgemm(const TA* A, long long lda, const TB* B, long long ldb, 
 }
 
 // Cholesky factor of the nb x nb diagonal block at (j0, j0) of S, in place
-// (lower triangle), unblocked in LDS (one workgroup); rows and columns past nb
-// act as the identity.  Also writes the inverse of the factor (64 x 64, lower
-// triangular, row-major) to Linv, so that the triangular solves with the block
-// become GEMMs.  A non-positive pivot gives NaN, which the sweep then reports as
-// a non-finite state.
+// (lower triangle), and the inverse of the factor (64 x 64, lower triangular,
+// row-major) into Linv, so that the triangular solves with the block become
+// GEMMs; rows and columns past nb act as the identity.
+// Right-looking on unscaled columns: with A = U D U^T (U unit lower, D the
+// pivots), step c subtracts A[r][c] A[k][c] / D_c from A[r][k] (k > c, r >= k),
+// and the same step eliminates column c from X, the running inverse of U (X = I
+// at the start; X[r][j] -= U[r][c] X[c][j] for r > c, U[r][c] = A[r][c] / D_c).
+// Both read only what steps before c have finished, so one barrier per step
+// suffices: column c + 1 of A and row c + 1 of X are published in LDS (double
+// buffered) by the threads that own them.  At the end L = U D^(1/2), i.e.
+// L[r][k] = A[r][k] / sqrt(D_k), and L^-1 = D^(-1/2) X.  Thread t owns column
+// t % 64, rows t / 64 + 4 q (q < 16), of both A and X, in registers.  A
+// non-positive pivot gives NaN, which the sweep then reports as a non-finite
+// state.
 __global__ __launch_bounds__(256) void k_chol_diag(double* S, long long lds, int j0, int nb, double* Linv) {
-  __shared__ double a[kDT][kDT + 1];
-  __shared__ double inv[kDT][kDT + 1];
-  const int t = threadIdx.x;
-  for (int i = t; i < kDT * kDT; i += 256) {
-    const int r = i / kDT, c = i % kDT;
-    a[r][c] = (r < nb && c < nb) ? S[(long long)(j0 + r) * lds + j0 + c] : (r == c ? 1.0 : 0.0);
+  constexpr int kQ = kDT / 4;
+  __shared__ double col[2][kDT];   // column c of A (unscaled)
+  __shared__ double row[2][kDT];   // row c of X
+  __shared__ double piv[kDT];
+  const int t = threadIdx.x, k = t % kDT, g = t / kDT;
+  double a[kQ], x[kQ];
+#pragma unroll
+  for (int q = 0; q < kQ; ++q) {
+    const int r = g + 4 * q;
+    a[q] = (r < nb && k < nb) ? (r >= k ? S[(long long)(j0 + r) * lds + j0 + k] : 0.0)
+                              : (r == k ? 1.0 : 0.0);
+    x[q] = r == k ? 1.0 : 0.0;
+    if (k == 0) col[0][r] = a[q];
+    if (r == 0) row[0][k] = x[q];
   }
   __syncthreads();
   for (int c = 0; c < kDT; ++c) {
-    if (t == 0) a[c][c] = sqrt(a[c][c]);
-    __syncthreads();
-    if (t > c && t < kDT) a[t][c] /= a[c][c];
-    __syncthreads();
-    for (int i = t; i < kDT * kDT; i += 256) {
-      const int r = i / kDT, k = i % kDT;
-      if (k > c && k <= r) a[r][k] -= a[r][c] * a[k][c];
+    const int b = c & 1;
+    const double d = col[b][c];
+    const double rd = 1.0 / d;
+    const double akc = col[b][k] * rd;   // U[k][c]
+    const double xck = row[b][k];        // X[c][k]
+    if (t == c) piv[c] = d;
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) {
+      const int r = g + 4 * q;
+      const double arc = col[b][r];
+      if (k > c && r >= k) a[q] = __builtin_fma(-arc, akc, a[q]);
+      if (r > c) x[q] = __builtin_fma(-arc * rd, xck, x[q]);
+      if (k == c + 1 && c + 1 < kDT) col[b ^ 1][r] = a[q];
+      if (r == c + 1) row[b ^ 1][k] = x[q];
     }
     __syncthreads();
   }
-  // column c of L^-1 by forward substitution, one column per thread
-  if (t < kDT) {
-    const int c = t;
-    for (int r = 0; r < kDT; ++r) {
-      double v;
-      if (r < c) {
-        v = 0.0;
-      } else {
-        double sum = r == c ? 1.0 : 0.0;
-        for (int k = c; k < r; ++k) sum -= a[r][k] * inv[k][c];
-        v = sum / a[r][r];
-      }
-      inv[r][c] = v;
-    }
-  }
-  __syncthreads();
-  for (int i = t; i < kDT * kDT; i += 256) {
-    const int r = i / kDT, c = i % kDT;
-    if (r < nb && c <= r) S[(long long)(j0 + r) * lds + j0 + c] = a[r][c];
-    Linv[i] = inv[r][c];
+  const double sk = 1.0 / sqrt(piv[k]);
+#pragma unroll
+  for (int q = 0; q < kQ; ++q) {
+    const int r = g + 4 * q;
+    if (r < nb && k < nb && r >= k) S[(long long)(j0 + r) * lds + j0 + k] = a[q] * sk;
+    Linv[r * kDT + k] = x[q] / sqrt(piv[r]);
   }
 }
 
