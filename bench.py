@@ -349,6 +349,8 @@ def main():
     ap.add_argument("--cg-reduce", type=float, default=0.0,
                     help="also time one cold and one warm solve with this opt-in CG residual "
                          "reduction (0: skip)")
+    ap.add_argument("--persistent", type=int, choices=(0, 1), default=0,
+                    help="launch the TV sweep as one resident grid looping over the tile blocks")
     ap.add_argument("--launch", choices=("graph", "stream"), default="graph",
                     help="replay each sweep's launches as a hipGraph, or launch them one by one")
     ap.add_argument("--cpu-sweeps", type=int, default=None,
@@ -500,6 +502,7 @@ def bench_solves(args, p, em):
     dev = torch.device("cuda:0")
     print(f"[bench] workload {args.workload} {h}x{w} op={p.op} em={em}", file=sys.stderr, flush=True)
     ctx, y = _ctx(p, dev, args.launch == "graph")
+    ctx.ep_tv_set_option(N.OPT_PERSISTENT, args.persistent)
     ctx.ep_tv_run(3, em)                      # code objects, graph capture
     tune = ctx.ep_tv_autotune(5)              # sweep tile height (state unchanged)
     print(f"[bench] autotune: {tune}", file=sys.stderr, flush=True)
@@ -694,6 +697,7 @@ def bench_sweeps(args, p, em):
     dev = torch.device("cuda:0")
     print(f"[bench] workload {args.workload} {h}x{w} op={p.op} em={em}", file=sys.stderr, flush=True)
     ctx, y = _ctx(p, dev, args.launch == "graph")
+    ctx.ep_tv_set_option(N.OPT_PERSISTENT, args.persistent)
     ctx.ep_tv_run(max(args.warmup, 2), em)
     tune = ctx.ep_tv_autotune(5)
     print(f"[bench] autotune: {tune}", file=sys.stderr, flush=True)
@@ -754,6 +758,7 @@ def bench_batch(args, ps, em):
     print(f"[bench] workload {args.workload}: {len(ps)} instances, {npx / 1e6:.2f} M pixels, "
           f"{E / 1e6:.2f} M edges per sweep", file=sys.stderr, flush=True)
     ctx = Context([spec_from_synthetic(p, cg_precond=N.PRECOND_JACOBI) for p in ps], device=dev)
+    ctx.ep_tv_set_option(N.OPT_PERSISTENT, args.persistent)
     ctx.ep_tv_set_observation([torch.tensor(p.y, dtype=torch.float32, device=dev) for p in ps])
     tune = ctx.ep_tv_autotune(5)
     print(f"[bench] autotune: {tune}", file=sys.stderr, flush=True)

@@ -376,14 +376,19 @@ int ep_tv_get_timing(ep_tv_ctx* ctx, ep_tv_timing* out);
  *    tile is 124 interior columns wide).  Smaller heights than the workspace was
  *    sized for (the smaller of 8 and the initial height) return EP_TV_E_ARG.
  * Both synchronise the stream. */
-enum { EP_TV_OPT_GRAPH = 1, EP_TV_OPT_TILE_ROWS = 2, EP_TV_OPT_EM_OPTION = 3 };
+enum { EP_TV_OPT_GRAPH = 1, EP_TV_OPT_TILE_ROWS = 2, EP_TV_OPT_EM_OPTION = 3, EP_TV_OPT_PERSISTENT = 4 };
 /*  EP_TV_OPT_EM_OPTION (1, 2 or 3, default 3): the approximation of a_0 in the
  *    EM update lambda = N / a_0 (Sec. IV): 3 = Eq. (3rd_alternative_a0), the
  *    sum over the sweep's edges of the tilted E|u_n|; 2 = Eq. (eq:au), E|u_n|
  *    under Q(u_n) = N(m_bar_n, S_bar_n), the Gaussian with the tilted moments;
  *    1 = Eq. (eq:ax), E|x_i - x_j| under the global Q(x) after the sweep
  *    (an extra pass over the sites).  The paper adopts option 3; 1 and 2 are
- *    there to compare the estimates of lambda (its Fig. 4). */
+ *    there to compare the estimates of lambda (its Fig. 4).
+ *  EP_TV_OPT_PERSISTENT (0 or 1, default 0): launch the fused TV sweep as one
+ *    resident grid (as many workgroups as the device holds at once) whose
+ *    workgroups take the tile blocks of all instances in a fixed round-robin
+ *    order, instead of one workgroup per tile block.  Results are bit-identical
+ *    either way (no workgroup depends on another). */
 int ep_tv_set_option(ep_tv_ctx* ctx, int32_t option, int64_t value);
 int ep_tv_get_option(ep_tv_ctx* ctx, int32_t option, int64_t* value);
 

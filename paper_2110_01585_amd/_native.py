@@ -37,6 +37,7 @@ PRIOR_BG = 2
 OPT_GRAPH = 1
 OPT_TILE_ROWS = 2
 OPT_EM_OPTION = 3
+OPT_PERSISTENT = 4
 VAR_SPECTRAL = 0
 VAR_RBMC = 1
 

@@ -1121,6 +1121,12 @@ int ep_tv_set_option(ep_tv_ctx* c, int32_t option, int64_t value) {
       c->sa.em_opt = (int)value;
       drop_graphs(c);
       return EP_TV_OK;
+    case EP_TV_OPT_PERSISTENT:
+      if (value != 0 && value != 1) return fail(c, EP_TV_E_ARG, "persistent option must be 0 or 1");
+      HIPCHK(c, hipStreamSynchronize(c->stream));
+      c->sa.persistent = (int)value;
+      drop_graphs(c);
+      return EP_TV_OK;
     case EP_TV_OPT_TILE_ROWS: {
       if (value < 2 || value > 4096 || value % 2)
         return fail(c, EP_TV_E_ARG, "tile rows must be even and in [2, 4096]");
@@ -1141,6 +1147,7 @@ int ep_tv_get_option(ep_tv_ctx* c, int32_t option, int64_t* value) {
     case EP_TV_OPT_GRAPH: *value = c->use_graph ? 1 : 0; return EP_TV_OK;
     case EP_TV_OPT_TILE_ROWS: *value = c->chunk_rows; return EP_TV_OK;
     case EP_TV_OPT_EM_OPTION: *value = c->sa.em_opt; return EP_TV_OK;
+    case EP_TV_OPT_PERSISTENT: *value = c->sa.persistent; return EP_TV_OK;
     default: return fail(c, EP_TV_E_ARG, "unknown option");
   }
 }

@@ -82,6 +82,7 @@ struct SweepArgs {
   const float* part_mu;      // per likelihood tile: max |mu| after the likelihood-site update
   int prior;                 // PRIOR_* of every instance of the context
   int em_opt;                // EM approximation of a_0 (Sec. IV): 1, 2 or 3 (l1 only)
+  int persistent;            // 1: one resident grid loops over the tile blocks
 };
 
 // Map a block index so that consecutive tiles land on the same XCD (workgroups

@@ -485,12 +485,11 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, int tile, int wav
 // One wave per tile; consecutive tiles (vertically adjacent chunks of a strip)
 // form a block, whose shared boundaries exchange cavities in LDS instead of
 // recomputing halo rows; neighbouring blocks are mapped to the same XCD.
+// Every path through one tile block passes exactly two barriers.
 template <bool DELTA, class PR>
-__global__ __launch_bounds__(kWavesPerBlock * kWave) void k_tv_sweep(SweepArgs a) {
-  __shared__ float4 X[2 * kWavesPerBlock * kWave];
-  const int wave = threadIdx.x >> 6;
-  const int lane = threadIdx.x & 63;
-  const int tile = xcd_remap(blockIdx.x, gridDim.x) * kWavesPerBlock + wave;
+__device__ __forceinline__ void sweep_block(const SweepArgs& a, int blk, int wave, int lane,
+                                            float4* X) {
+  const int tile = blk * kWavesPerBlock + wave;
   const bool has = tile < a.ntiles;
   const int4 td = has ? a.tiles[tile] : make_int4(0, 0, 0, 0);
   if (!has || !a.st[td.x].active) {
@@ -542,6 +541,21 @@ __global__ __launch_bounds__(kWavesPerBlock * kWave) void k_tv_sweep(SweepArgs a
     sweep_tile<DELTA, true, PR>(a, tile, wave, lane, sh_dn, sh_up, X);
 }
 
+// One block per tile block, or (persistent launch) a resident grid whose
+// blocks take the tile blocks h = blockIdx.x, blockIdx.x + gridDim.x, ...: a
+// static schedule with no dependence between blocks.  With gridDim.x a multiple
+// of 8, block h stays on the XCD that block-index order h would have given it,
+// so the XCD remap keeps neighbouring tile blocks in one L2 either way.
+template <bool DELTA, class PR>
+__global__ __launch_bounds__(kWavesPerBlock * kWave) void k_tv_sweep(SweepArgs a) {
+  __shared__ float4 X[2 * kWavesPerBlock * kWave];
+  const int wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int nblk = (a.ntiles + kWavesPerBlock - 1) / kWavesPerBlock;
+  for (int h = blockIdx.x; h < nblk; h += gridDim.x)
+    sweep_block<DELTA, PR>(a, xcd_remap(h, nblk), wave, lane, X);
+}
+
 template <class PR>
 __global__ __launch_bounds__(256) void k_tilted(int n, const float* __restrict__ m,
                                                 const float* __restrict__ s, PR f,
@@ -579,22 +593,46 @@ hipError_t launch_tilted_mixture(int n, const float* m, const float* s, float dl
   return hipGetLastError();
 }
 
+// Grid of one launch: a block per tile block, or for the persistent launch the
+// blocks the device holds at once (occupancy of this kernel variant times the
+// compute units, a multiple of 8), if fewer.
+template <bool DELTA, class PR>
+static hipError_t launch_sweep_t(const SweepArgs& a, int blocks, hipStream_t s) {
+  int grid = blocks;
+  if (a.persistent) {
+    constexpr int kMaxDev = 64;
+    static int resident[kMaxDev] = {};   // per device and kernel variant, looked up once
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDev) return hipErrorInvalidDevice;
+    if (resident[dev] == 0) {
+      int per_cu = 0, cus = 0;
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_tv_sweep<DELTA, PR>,
+                                                       kWavesPerBlock * kWave, 0);
+      if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+      if (e != hipSuccess) return e;
+      resident[dev] = std::max(8, per_cu * cus / 8 * 8);
+    }
+    grid = std::min(blocks, resident[dev]);
+  }
+  hipLaunchKernelGGL((k_tv_sweep<DELTA, PR>), dim3(grid), dim3(kWavesPerBlock * kWave), 0, s, a);
+  return hipGetLastError();
+}
+
 hipError_t launch_tv_sweep(const SweepArgs& a, bool want_delta, hipStream_t s) {
   const int blocks = (a.ntiles + kWavesPerBlock - 1) / kWavesPerBlock;
   if (blocks == 0) return hipSuccess;
-  const dim3 g(blocks), b(kWavesPerBlock * kWave);
   if (a.prior == PRIOR_L1 && a.em_opt == 2) {
     // EM with option 2: the sweep accumulates E|u| under Q(u) instead
-    if (want_delta) hipLaunchKernelGGL((k_tv_sweep<true, L1FactorQu>), g, b, 0, s, a);
-    else hipLaunchKernelGGL((k_tv_sweep<false, L1FactorQu>), g, b, 0, s, a);
-  } else if (a.prior == PRIOR_L1) {
-    if (want_delta) hipLaunchKernelGGL((k_tv_sweep<true, L1Factor>), g, b, 0, s, a);
-    else hipLaunchKernelGGL((k_tv_sweep<false, L1Factor>), g, b, 0, s, a);
-  } else {
-    if (want_delta) hipLaunchKernelGGL((k_tv_sweep<true, MixtureFactor>), g, b, 0, s, a);
-    else hipLaunchKernelGGL((k_tv_sweep<false, MixtureFactor>), g, b, 0, s, a);
+    return want_delta ? launch_sweep_t<true, L1FactorQu>(a, blocks, s)
+                      : launch_sweep_t<false, L1FactorQu>(a, blocks, s);
   }
-  return hipGetLastError();
+  if (a.prior == PRIOR_L1)
+    return want_delta ? launch_sweep_t<true, L1Factor>(a, blocks, s)
+                      : launch_sweep_t<false, L1Factor>(a, blocks, s);
+  return want_delta ? launch_sweep_t<true, MixtureFactor>(a, blocks, s)
+                    : launch_sweep_t<false, MixtureFactor>(a, blocks, s);
 }
 
 }  // namespace eptv

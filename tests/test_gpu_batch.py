@@ -81,6 +81,47 @@ def test_graph_equals_direct_mixed_solve():
         assert sa[i]["sweeps"] == sb[i]["sweeps"] and sa[i]["cg_total"] == sb[i]["cg_total"]
 
 
+@pytest.mark.parametrize("graph", [False, True])
+def test_persistent_launch_is_bit_identical(graph):
+    """The persistent sweep launch (a resident grid taking the tile blocks in a
+    fixed round-robin order) gives the same bits as one workgroup per tile
+    block: uneven instances of all operator kinds, EM, a solve whose instances
+    freeze at different sweeps, and the full batched generator at reduced
+    sizes."""
+    for ps in (_mixed(), syn.config3_instances(n_instances=24, max_sweeps=20, size_lo=16,
+                                               size_hi=160)):
+        res = []
+        for persistent in (0, 1):
+            c = _ctx(ps, graph=graph, precond=N.PRECOND_JACOBI)
+            c.ep_tv_set_option(N.OPT_PERSISTENT, persistent)
+            assert c.ep_tv_get_option(N.OPT_PERSISTENT) == persistent
+            mus = [torch.empty(*p.shape, device="cuda") for p in ps]
+            vs = [torch.empty(*p.shape, device="cuda") for p in ps]
+            rc, st = c.ep_tv_solve(30, 1e-4, True, mus, vs)
+            torch.cuda.synchronize()
+            res.append(([m.cpu().numpy() for m in mus], [v.cpu().numpy() for v in vs], st))
+            c.close()
+        (ma, va, sa), (mb, vb, sb) = res
+        for i in range(len(ps)):
+            assert np.array_equal(ma[i], mb[i]) and np.array_equal(va[i], vb[i]), ps[i].name
+            assert sa[i]["sweeps"] == sb[i]["sweeps"] and sa[i]["lambda"] == sb[i]["lambda"]
+    # the full batched workload: several times more tile blocks than the device
+    # holds at once, so each workgroup of the persistent grid takes several
+    ps = syn.config3_instances()
+    res = []
+    for persistent in (0, 1):
+        c = _ctx(ps, graph=graph, precond=N.PRECOND_JACOBI)
+        c.ep_tv_set_option(N.OPT_PERSISTENT, persistent)
+        c.ep_tv_run(4, True)
+        outs, st = _out(c)
+        c.close()
+        res.append((outs, st))
+    for i in range(len(ps)):
+        (ma, va), (mb, vb) = res[0][0][i], res[1][0][i]
+        assert np.array_equal(ma, mb) and np.array_equal(va, vb), ps[i].name
+        assert res[0][1][i]["lambda"] == res[1][1][i]["lambda"]
+
+
 def test_graph_equals_direct_fast_cg():
     """Power-of-two blur and masked-DFT instances: every likelihood solve takes
     the real-FFT preconditioned CG.  A replayed graph runs a fixed number of CG
@@ -192,9 +233,10 @@ def test_option_errors():
 def test_batched_workload_full_size_sampled():
     """The full batched workload (256 instances, sizes 64..1024, about 48M
     pixels) in the launch mode the benchmark uses (graph, autotuned tiles,
-    Jacobi CG), 8 sweeps from cold with EM.  The oracle checks the smallest
-    denoising and the smallest deconvolution instance of the batch; every
-    instance must stay finite with non-negative site precisions and lambda > 0."""
+    Jacobi CG), 8 sweeps from cold with EM.  The oracle checks, for each
+    operator, the two smallest instances of the batch and the one nearest to
+    256 x 256 (six instances, 64^2 to about 256^2); every instance must stay
+    finite with non-negative site precisions and lambda > 0."""
     ps = syn.config3_instances()
     npx = sum(p.shape[0] * p.shape[1] for p in ps)
     print(f"batch: {len(ps)} instances, {npx / 1e6:.1f} M pixels")
@@ -206,11 +248,12 @@ def test_batched_workload_full_size_sampled():
     for (mu, v), s in zip(outs, st):
         assert np.isfinite(mu).all() and np.isfinite(v).all() and (v > 0).all()
         assert s["lambda"] > 0 and s["status"] != N.EP_TV_E_NONFINITE and s["sweeps"] == 8
-    picks = {}
-    for i, p in enumerate(ps):
-        if p.op not in picks or p.shape[0] < ps[picks[p.op]].shape[0]:
-            picks[p.op] = i
-    for op, i in picks.items():
+    picks = []
+    for op in sorted({p.op for p in ps}):
+        idx = sorted((i for i, p in enumerate(ps) if p.op == op), key=lambda i: ps[i].shape[0])
+        near = min(idx, key=lambda i: abs(ps[i].shape[0] - 256))
+        picks += sorted({idx[0], idx[1], near})
+    for i in picks:
         p = ps[i]
         mu_o, v_o, _, info = oep.solve(oep.problem_from_synthetic(f32_problem(p)), 8, True)
         e_mu, e_v = mean_err(outs[i][0], mu_o), var_err(outs[i][1], v_o)
