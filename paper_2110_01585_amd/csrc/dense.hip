@@ -25,6 +25,12 @@ constexpr int kDK = 32;   // K depth staged in LDS per GEMM round
 // round's operands are loaded into registers while the current one is
 // multiplied.  A workgroup reads all of A's rows of its tile before it writes
 // C, so C may alias A when the output has a single tile column (N <= 64).
+// The staged tiles are k-major with a swizzle: element (row, k) sits at
+// [k][(row + 16 ((k / 8) % 4)) % 64] of a row of 80, so the MFMA operand reads
+// (16 rows x 4 k per wave) and the staging writes (16 rows x 4 groups of 8 k
+// per wave) both touch each bank pair at most twice, the minimum for 8-byte
+// accesses of 64 lanes.  Operand rows are read as 16-byte words where the
+// leading dimensions and base addresses allow it (`vec`).
 template <class TA, class TB>
 struct GemmArgs {
   const TA* A;
@@ -38,14 +44,34 @@ struct GemmArgs {
   double alpha, beta, diag;
   int lower;
   int nt_n;   // tiles along n
+  int vec;    // rows of A, B (and w) may be read as 16-byte words
 };
+
+__device__ __forceinline__ int swz(int row, int k) { return (row + 16 * ((k >> 3) & 3)) & (kDT - 1); }
+
+// eight consecutive elements as doubles, from a 16-byte aligned address
+__device__ __forceinline__ void load8(const float* p, double (&v)[8]) {
+  const float4 x = *reinterpret_cast<const float4*>(p);
+  const float4 y = *reinterpret_cast<const float4*>(p + 4);
+  v[0] = x.x; v[1] = x.y; v[2] = x.z; v[3] = x.w;
+  v[4] = y.x; v[5] = y.y; v[6] = y.z; v[7] = y.w;
+}
+__device__ __forceinline__ void load8(const double* p, double (&v)[8]) {
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const double2 x = *reinterpret_cast<const double2*>(p + 2 * i);
+    v[2 * i] = x.x;
+    v[2 * i + 1] = x.y;
+  }
+}
 
 template <class TA, class TB>
 __global__ __launch_bounds__(256) void k_dgemm_nt(GemmArgs<TA, TB> g) {
   constexpr int BT = kDT, KD = kDK;
   constexpr int NB = 2;                       // 16 x 16 MFMA blocks per wave and direction
-  __shared__ double As[BT][KD + 1];
-  __shared__ double Bs[BT][KD + 1];
+  constexpr int kRow = BT + 16;
+  __shared__ double As[KD][kRow];
+  __shared__ double Bs[KD][kRow];
   const int tm = blockIdx.x / g.nt_n, tn = blockIdx.x % g.nt_n;
   const int m0 = tm * BT, n0 = tn * BT;
   if (g.lower && n0 > m0 + BT - 1) return;    // whole tile above the diagonal
@@ -62,8 +88,30 @@ __global__ __launch_bounds__(256) void k_dgemm_nt(GemmArgs<TA, TB> g) {
   const int am = m0 + lr, bn = n0 + lr;
   const TA* arow = g.A + (long long)am * g.lda;
   const TB* brow = g.B + (long long)bn * g.ldb;
+  static_assert(kPer == 8, "the staging reads eight consecutive k per thread");
   double av[kPer], bv[kPer];
   auto fetch = [&](int k0) {
+    if (g.vec && k0 + lk + kPer <= g.K) {
+      if (am < g.M) {
+        load8(arow + k0 + lk, av);
+      } else {
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) av[u] = 0.0;
+      }
+      if (bn < g.N) {
+        load8(brow + k0 + lk, bv);
+        if (g.w) {
+          double wv[kPer];
+          load8(g.w + k0 + lk, wv);
+#pragma unroll
+          for (int u = 0; u < kPer; ++u) bv[u] *= wv[u];
+        }
+      } else {
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) bv[u] = 0.0;
+      }
+      return;
+    }
 #pragma unroll
     for (int u = 0; u < kPer; ++u) {
       const int k = k0 + lk + u;
@@ -75,10 +123,11 @@ __global__ __launch_bounds__(256) void k_dgemm_nt(GemmArgs<TA, TB> g) {
   fetch(0);
   for (int k0 = 0; k0 < g.K; k0 += KD) {
     __syncthreads();   // the previous round's LDS reads are done
+    const int sc = swz(lr, lk);   // (lk + u) / 8 == lk / 8
 #pragma unroll
     for (int u = 0; u < kPer; ++u) {
-      As[lr][lk + u] = av[u];
-      Bs[lr][lk + u] = bv[u];
+      As[lk + u][sc] = av[u];
+      Bs[lk + u][sc] = bv[u];
     }
     __syncthreads();
     if (k0 + KD < g.K) fetch(k0 + KD);
@@ -88,8 +137,8 @@ __global__ __launch_bounds__(256) void k_dgemm_nt(GemmArgs<TA, TB> g) {
       double a[NB], b[NB];
 #pragma unroll
       for (int i = 0; i < NB; ++i) {
-        a[i] = As[wm + 16 * i + r][c];
-        b[i] = Bs[wn + 16 * i + r][c];
+        a[i] = As[c][swz(wm + 16 * i + r, c)];
+        b[i] = Bs[c][swz(wn + 16 * i + r, c)];
       }
 #pragma unroll
       for (int i = 0; i < NB; ++i)
@@ -124,6 +173,10 @@ static hipError_t dgemm(const TA* A, long long lda, const TB* B, long long ldb, 
   g.A = A; g.lda = lda; g.B = B; g.ldb = ldb; g.w = w; g.C = C; g.ldc = ldc;
   g.M = M; g.N = N; g.K = K; g.alpha = alpha; g.beta = beta; g.diag = diag;
   g.lower = lower ? 1 : 0;
+  // 16-byte words: every row start aligned (base and leading dimension)
+  auto al = [](const void* p) { return reinterpret_cast<uintptr_t>(p) % 16 == 0; };
+  constexpr long long va = 16 / sizeof(TA), vb = 16 / sizeof(TB);
+  g.vec = al(A) && al(B) && lda % va == 0 && ldb % vb == 0 && (!w || al(w)) ? 1 : 0;
   const int nt_m = (M + kDT - 1) / kDT;
   g.nt_n = (N + kDT - 1) / kDT;
   hipLaunchKernelGGL((k_dgemm_nt<TA, TB>), dim3(nt_m * g.nt_n), dim3(256), 0, s, g);
@@ -206,10 +259,12 @@ __global__ __launch_bounds__(256) void k_transpose_f32(const float* __restrict__
   }
 }
 
+// rows x cols float (contiguous) -> double with leading dimension ld >= cols
 __global__ __launch_bounds__(256) void k_f32_to_f64(const float* __restrict__ in, double* __restrict__ out,
-                                                    long long n) {
+                                                    int rows, int cols, int ld) {
   const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
-  if (i < n) out[i] = (double)in[i];
+  if (i >= (long long)rows * cols) return;
+  out[(i / cols) * ld + i % cols] = (double)in[i];
 }
 
 // Wave-level FP64 sum, the same bits on every lane (butterfly).
@@ -254,14 +309,15 @@ __global__ __launch_bounds__(256) void k_gauss_gather(const float* __restrict__ 
 
 // Partial sums of t = Z (b / d) = sum_i Z^T[i, :] b_i / d_i over chunks of
 // kGaussChunk rows: one thread per column a of one chunk.
-__global__ __launch_bounds__(256) void k_gauss_tpart(const double* __restrict__ ZT, const double* __restrict__ b,
+__global__ __launch_bounds__(256) void k_gauss_tpart(const double* __restrict__ ZT, int ld,
+                                                     const double* __restrict__ b,
                                                      const double* __restrict__ w, int M, int N,
                                                      double* __restrict__ tpart) {
   const int a = blockIdx.x * 256 + threadIdx.x, chunk = blockIdx.y;
   if (a >= M) return;
   const int i0 = chunk * kGaussChunk, i1 = min(i0 + kGaussChunk, N);
   double acc = 0.0;
-  for (int i = i0; i < i1; ++i) acc += ZT[(long long)i * M + a] * (b[i] * w[i]);
+  for (int i = i0; i < i1; ++i) acc += ZT[(long long)i * ld + a] * (b[i] * w[i]);
   tpart[(long long)chunk * M + a] = acc;
 }
 
@@ -276,13 +332,14 @@ __global__ __launch_bounds__(256) void k_gauss_tsum(const double* __restrict__ t
 
 // Per pixel (one wave per row of Z^T): v_i = 1/d_i - |z_i|^2 / d_i^2 and
 // E_i = (b_i - z_i . t) / d_i, into the pitched variance and x planes.
-__global__ __launch_bounds__(256) void k_gauss_moments(const double* __restrict__ ZT, const double* __restrict__ t,
+__global__ __launch_bounds__(256) void k_gauss_moments(const double* __restrict__ ZT, int ld,
+                                                       const double* __restrict__ t,
                                                        const double* __restrict__ d, const double* __restrict__ b,
                                                        int M, int N, int W, int pitch, long long off,
                                                        float* __restrict__ var, float* __restrict__ x) {
   const int row = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
   if (row >= N) return;
-  const double* z = ZT + (long long)row * M;
+  const double* z = ZT + (long long)row * ld;
   double zz = 0.0, zt = 0.0;
   for (int a = lane; a < M; a += kWave) {
     const double v = z[a];
@@ -321,8 +378,9 @@ hipError_t gauss_setup(LikCtx& lc, const LikInstInfo* li, int n, hipStream_t s, 
     P.nchunk = (P.N + kGaussChunk - 1) / kGaussChunk;
     P.Hm = reinterpret_cast<float*>(take(m * nn * 4));
     P.HT = reinterpret_cast<float*>(take(m * nn * 4));
-    P.S = reinterpret_cast<double*>(take(m * m * 8));
-    P.ZT = reinterpret_cast<double*>(take(nn * m * 8));
+    P.ld = gauss_ld(P.M);
+    P.S = reinterpret_cast<double*>(take(m * (size_t)P.ld * 8));
+    P.ZT = reinterpret_cast<double*>(take(nn * (size_t)P.ld * 8));
     P.d = reinterpret_cast<double*>(take(nn * 8));
     P.w = reinterpret_cast<double*>(take(nn * 8));
     P.b = reinterpret_cast<double*>(take(nn * 8));
@@ -362,13 +420,13 @@ hipError_t gauss_set_observation(LikCtx& lc, const float* const* d_y, hipStream_
 // from the right half (one GEMM over all rows), solve the right half; a single
 // block is one GEMM with the inverse of its diagonal Cholesky block.
 static hipError_t trsm_right(LikCtx& lc, GaussPlan& P, int lo, int hi, hipStream_t s) {
-  const int M = P.M, N = P.N;
+  const int M = P.M, N = P.N, ld = P.ld;
   const int c_lo = lo * kDT, c_hi = std::min(M, hi * kDT);
   if (hi - lo == 1) {
     const int bj = c_hi - c_lo;
     const double* Linv = P.Linv + (long long)lo * kDT * kDT;
     hipError_t e = lik_timed(lc, KT_DGEMM, s, [&]() {
-      return dgemm<double, double>(P.ZT + c_lo, M, Linv, kDT, nullptr, P.ZT + c_lo, M, N, bj, bj, 1.0, 0.0,
+      return dgemm<double, double>(P.ZT + c_lo, ld, Linv, kDT, nullptr, P.ZT + c_lo, ld, N, bj, bj, 1.0, 0.0,
                                    0.0, false, s);
     });
     lc.dgemm_flops += 2.0 * (double)N * (double)bj * (double)bj;
@@ -379,8 +437,8 @@ static hipError_t trsm_right(LikCtx& lc, GaussPlan& P, int lo, int hi, hipStream
   if (e != hipSuccess) return e;
   // Z^T[:, mid..hi) -= Z^T[:, lo..mid) L[mid..hi, lo..mid)^T
   e = lik_timed(lc, KT_DGEMM, s, [&]() {
-    return dgemm<double, double>(P.ZT + c_lo, M, P.S + (long long)c_mid * M + c_lo, M, nullptr, P.ZT + c_mid, M,
-                                 N, c_hi - c_mid, c_mid - c_lo, -1.0, 1.0, 0.0, false, s);
+    return dgemm<double, double>(P.ZT + c_lo, ld, P.S + (long long)c_mid * ld + c_lo, ld, nullptr, P.ZT + c_mid,
+                                 ld, N, c_hi - c_mid, c_mid - c_lo, -1.0, 1.0, 0.0, false, s);
   });
   if (e != hipSuccess) return e;
   lc.dgemm_flops += 2.0 * (double)N * (double)(c_hi - c_mid) * (double)(c_mid - c_lo);
@@ -393,34 +451,34 @@ hipError_t gauss_update(LikCtx& lc, const InstState* hst, hipStream_t s) {
     const LikInst& L = lc.hinst[P.li];
     const InstState& st = hst[L.inst];
     if (!(st.active && (st.sweeps > 0 || st.warm))) continue;
-    const int M = P.M, N = P.N, nb = (M + kDT - 1) / kDT;
+    const int M = P.M, N = P.N, ld = P.ld, nb = (M + kDT - 1) / kDT;
     const double xi = 1.0 / (double)L.inv_xi;
     hipLaunchKernelGGL(k_gauss_gather, dim3((N + 255) / 256), dim3(256), 0, s, lc.planes[LP_TAUC],
                        lc.planes[LP_B], N, L.W, L.pitch, L.off, P.d, P.w, P.b);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     // S = xi I + H D^-1 H^T (lower triangle), then its Cholesky factor in place
     e = lik_timed(lc, KT_DGEMM, s, [&]() {
-      return dgemm<float, float>(P.Hm, N, P.Hm, N, P.w, P.S, M, M, M, N, 1.0, 0.0, xi, true, s);
+      return dgemm<float, float>(P.Hm, N, P.Hm, N, P.w, P.S, ld, M, M, N, 1.0, 0.0, xi, true, s);
     });
     if (e != hipSuccess) return e;
     lc.dgemm_flops += (double)M * (double)(M + kDT) * (double)N;
     for (int j = 0; j < nb; ++j) {
       const int j0 = j * kDT, bj = std::min(kDT, M - j0), rest = M - j0 - bj;
       double* Linv = P.Linv + (long long)j * kDT * kDT;
-      hipLaunchKernelGGL(k_chol_diag, dim3(1), dim3(256), 0, s, P.S, (long long)M, j0, bj, Linv);
+      hipLaunchKernelGGL(k_chol_diag, dim3(1), dim3(256), 0, s, P.S, (long long)ld, j0, bj, Linv);
       if ((e = hipGetLastError()) != hipSuccess) return e;
       if (rest <= 0) break;
       // panel L_ij = S_ij L_jj^-T, in place
-      double* panel = P.S + (long long)(j0 + bj) * M + j0;
+      double* panel = P.S + (long long)(j0 + bj) * ld + j0;
       e = lik_timed(lc, KT_DGEMM, s, [&]() {
-        return dgemm<double, double>(panel, M, Linv, kDT, nullptr, panel, M, rest, bj, bj, 1.0, 0.0, 0.0,
+        return dgemm<double, double>(panel, ld, Linv, kDT, nullptr, panel, ld, rest, bj, bj, 1.0, 0.0, 0.0,
                                      false, s);
       });
       if (e != hipSuccess) return e;
       lc.dgemm_flops += 2.0 * (double)rest * (double)bj * (double)bj;
-      double* trail = P.S + (long long)(j0 + bj) * M + (j0 + bj);
+      double* trail = P.S + (long long)(j0 + bj) * ld + (j0 + bj);
       e = lik_timed(lc, KT_DGEMM, s, [&]() {
-        return dgemm<double, double>(panel, M, panel, M, nullptr, trail, M, rest, rest, bj, -1.0, 1.0, 0.0,
+        return dgemm<double, double>(panel, ld, panel, ld, nullptr, trail, ld, rest, rest, bj, -1.0, 1.0, 0.0,
                                      true, s);
       });
       if (e != hipSuccess) return e;
@@ -429,14 +487,14 @@ hipError_t gauss_update(LikCtx& lc, const InstState* hst, hipStream_t s) {
     // Z^T = H^T L^-T (Z^T L^T = H^T), recursively over column blocks so that
     // the large updates are single wide GEMMs
     hipLaunchKernelGGL(k_f32_to_f64, dim3((unsigned)(((long long)N * M + 255) / 256)), dim3(256), 0, s, P.HT,
-                       P.ZT, (long long)N * M);
+                       P.ZT, N, M, ld);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if ((e = trsm_right(lc, P, 0, nb, s)) != hipSuccess) return e;
     // t = Z (b / d), then v and E per pixel
-    hipLaunchKernelGGL(k_gauss_tpart, dim3((M + 255) / 256, P.nchunk), dim3(256), 0, s, P.ZT, P.b, P.w, M, N,
-                       P.tpart);
+    hipLaunchKernelGGL(k_gauss_tpart, dim3((M + 255) / 256, P.nchunk), dim3(256), 0, s, P.ZT, ld, P.b, P.w, M,
+                       N, P.tpart);
     hipLaunchKernelGGL(k_gauss_tsum, dim3((M + 255) / 256), dim3(256), 0, s, P.tpart, M, P.nchunk, P.t);
-    hipLaunchKernelGGL(k_gauss_moments, dim3((N + 3) / 4), dim3(256), 0, s, P.ZT, P.t, P.d, P.b, M, N, L.W,
+    hipLaunchKernelGGL(k_gauss_moments, dim3((N + 3) / 4), dim3(256), 0, s, P.ZT, ld, P.t, P.d, P.b, M, N, L.W,
                        L.pitch, L.off, lc.planes[LP_VAR], lc.planes[LP_X]);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }

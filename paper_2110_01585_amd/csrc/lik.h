@@ -111,10 +111,15 @@ struct LikLayout {
 // the vectors d, 1/d, b (N), t (M), the partial sums of t, the inverses of the
 // diagonal Cholesky blocks and the observation.
 constexpr int kGaussChunk = 256;   // rows per partial sum of t = Z (b / d)
+// Leading dimension of S and Z^T: M rounded up to an even number, so that every
+// row starts on a 16-byte boundary (the GEMM then reads rows as 16-byte words).
+inline int gauss_ld(int M) { return (M + 1) / 2 * 2; }
+
 inline size_t gauss_bytes_of(int M, int N) {
   auto r = [](size_t b) { return (b + 255) / 256 * 256; };
   const size_t m = (size_t)M, nn = (size_t)N, nchunk = (nn + kGaussChunk - 1) / kGaussChunk;
-  return 2 * r(m * nn * 4) + r(m * m * 8) + r(nn * m * 8) + 3 * r(nn * 8) + r(m * 8) +
+  const size_t ld = (size_t)gauss_ld(M);
+  return 2 * r(m * nn * 4) + r(m * ld * 8) + r(nn * ld * 8) + 3 * r(nn * 8) + r(m * 8) +
          r(nchunk * m * 8) + r((m + 63) / 64 * 64 * 64 * 8) + r(m * 4);
 }
 
@@ -208,6 +213,7 @@ struct GaussPlan {
   int M = 0, N = 0;            // sensing rows, pixels
   float* Hm = nullptr;         // M x N, row-major (as given)
   float* HT = nullptr;         // N x M, its transpose
+  int ld = 0;                  // leading dimension of S and ZT (gauss_ld)
   double* S = nullptr;         // M x M (lower triangle used), then its Cholesky factor
   double* ZT = nullptr;        // N x M
   double* d = nullptr;         // N: cavity precisions (flat, row-major pixels)
