@@ -352,18 +352,46 @@ __global__ __launch_bounds__(256) void k_finalize(const InstDev* __restrict__ in
   double e = 0.0;
   float dm = 0.f, dv = 0.f;
   unsigned cl = 0u, fl = 0u;
-  for (int t = threadIdx.x; t < I.ntiles; t += blockDim.x) {
-    const int g = I.tile0 + t;
-    e += a.part_eabs[g];
-    dm = fmaxf(dm, a.part_dmu[g]);
-    dv = fmaxf(dv, a.part_dv[g]);
-    cl += a.part_clamp[g];
-    fl |= a.part_flags[g];
+  // kU partials per thread are requested before the first is folded in (each
+  // thread still takes its partials in ascending order), so their latencies
+  // overlap instead of adding up
+  constexpr int kU = 8;
+  for (int t0 = threadIdx.x; t0 < I.ntiles; t0 += kU * 256) {
+    double ve[kU];
+    float vm[kU], vv[kU];
+    unsigned vc[kU], vf[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int t = t0 + 256 * u;
+      const int g = I.tile0 + (t < I.ntiles ? t : 0);
+      ve[u] = a.part_eabs[g];
+      vm[u] = a.part_dmu[g];
+      vv[u] = a.part_dv[g];
+      vc[u] = a.part_clamp[g];
+      vf[u] = a.part_flags[g];
+    }
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      if (t0 + 256 * u >= I.ntiles) break;
+      e += ve[u];
+      dm = fmaxf(dm, vm[u]);
+      dv = fmaxf(dv, vv[u]);
+      cl += vc[u];
+      fl |= vf[u];
+    }
   }
   // divergence rule: the global mean after this sweep's likelihood-site update
   float mm = 0.f;
-  for (int t = threadIdx.x; t < I.lik_ntiles; t += blockDim.x)
-    mm = fmaxf(mm, a.part_mu[I.lik_tile0 + t]);
+  for (int t0 = threadIdx.x; t0 < I.lik_ntiles; t0 += kU * 256) {
+    float vu[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int t = t0 + 256 * u;
+      vu[u] = t < I.lik_ntiles ? a.part_mu[I.lik_tile0 + t] : 0.f;
+    }
+#pragma unroll
+    for (int u = 0; u < kU; ++u) mm = fmaxf(mm, vu[u]);
+  }
   if (I.lik_ntiles > 0 && !(mm <= (float)(kDivergeFactor * S.yscale))) fl |= FLAG_DIVERGED;
   se[threadIdx.x] = e; sm[threadIdx.x] = dm; sv[threadIdx.x] = dv; sc[threadIdx.x] = cl;
   sf[threadIdx.x] = fl;

@@ -217,6 +217,20 @@ __device__ __forceinline__ void fft_passes(float2* X, int rows, const float2* __
 // halve the workgroups in flight and run slower).  The kernels' LDS arrays,
 // their launch grids and the RF_INV partial counts all follow from this one
 // definition.
+// Entries of the twiddle table the passes of a length-L transform read: one
+// more than the largest index r k L / (R Ns) over the passes' radix R, stride Ns,
+// r < R and k < Ns.
+constexpr int tw_span(int L) {
+  int m = 0;
+  for (int Ns = 1; Ns < L;) {
+    const int R = L / Ns >= 16 ? 16 : L / Ns;
+    const int v = (R - 1) * (Ns - 1) * (L / (R * Ns));
+    m = v > m ? v : m;
+    Ns *= R;
+  }
+  return m + 1;
+}
+
 constexpr int rows_per_block(int L) { return L >= 2048 ? 1 : (2048 / L > 16 ? 16 : 2048 / L); }
 
 template <int L>
@@ -336,7 +350,7 @@ struct RfftArgs {
   const InstState* st;
   InstState* st_w;           // RF_FWD update: block 0 records alpha
   int inst;
-  double* part0;             // RF_INV partials at [part_base + blockIdx.x]
+  double* part0;             // RF_INV partials at [part_base + row block]
   double* part1;
   int part_base;
 };
@@ -368,171 +382,210 @@ __device__ __forceinline__ double cg_alpha(const double* __restrict__ part, int 
   return pq != 0.0 ? rz / pq : 0.0;
 }
 
+// What one thread loads for its workgroup's rows in each stage, all of it
+// before the first LDS store.
+template <int L, int STAGE>
+struct RfftRegs {
+  static constexpr int kPts = rows_per_block(L) * L;
+  static constexpr int N4 = (kPts / 4 + 255) / 256;                          // 4-column words
+  static constexpr int N2 = (kPts / 2 + 255) / 256;                          // complex pairs
+  static constexpr int NH = (rows_per_block(L) * (L / 2 + 1) + 255) / 256;   // half spectrum
+  // RF_FWD: r or z (v), q or p_in (w), x, p of rows 2j (a) and 2j+1 (b)
+  float4 va[STAGE == RF_FWD ? N4 : 1], vb[STAGE == RF_FWD ? N4 : 1];
+  float4 wa[STAGE == RF_FWD ? N4 : 1], wb[STAGE == RF_FWD ? N4 : 1];
+  float4 xa[STAGE == RF_FWD ? N4 : 1], xb[STAGE == RF_FWD ? N4 : 1];
+  float4 pa[STAGE == RF_FWD ? N4 : 1], pb[STAGE == RF_FWD ? N4 : 1];
+  // RF_FILT: two complex values and their two eigenvalues
+  float4 lv[STAGE == RF_FILT ? N2 : 1];
+  float2 sp[STAGE == RF_FILT ? N2 : 1];
+  // RF_INV: (V_a(k), V_b(k))
+  float4 ab[STAGE == RF_INV ? NH : 1];
+};
+
 template <int L, int STAGE>
 __global__ __launch_bounds__(256) void k_rfft(RfftArgs a) {
   constexpr int kRows = rows_per_block(L);
-  __shared__ float2 X[Padded<kRows * L>::value];
+  constexpr int kPts = kRows * L;
+  using Regs = RfftRegs<L, STAGE>;
+  constexpr int N4 = Regs::N4, N2 = Regs::N2, NH = Regs::NH;
+  __shared__ float2 X[Padded<kPts>::value];
+  const int half = L / 2;
   // neighbouring row blocks (which share the cache lines of the transposed
   // half spectrum) run on one XCD
-  const int row0 = xcd_remap(blockIdx.x, gridDim.x) * kRows;
-  const int rows = min(kRows, a.nrows - row0);
-  const int half = L / 2;
+  const int u = xcd_remap(blockIdx.x, gridDim.x);
+  const int row0 = u * kRows, rows = min(kRows, a.nrows - row0);
   const InstState& st = a.st[a.inst];
-  const bool skip = st.cg_done != 0;   // uniform per launch (one instance)
-  // ---- load ----
-  if (STAGE == RF_FWD && !skip) {
-    // The two real rows 2j, 2j+1 of each complex row, as 16-byte words of four
-    // columns (planes and pitches are 64-float aligned, L is a multiple of 4).
-    // Every load is issued before alpha's partials are summed and before the
-    // first store.
-    const bool first = st.cg_it == 0;
-    const float beta = (float)st.cg_beta;
-    const bool upd = a.mode == RFM_PRECOND && a.update;
-    constexpr int NQ4 = (kRows * L / 4 + 255) / 256;   // words per thread and row
-    float4 va[NQ4], vb[NQ4], qa[NQ4], qb[NQ4], xa[NQ4], xb[NQ4], pa[NQ4], pb[NQ4];
+  if (st.cg_done != 0) {   // uniform per launch (one instance)
+    if (STAGE == RF_INV && threadIdx.x == 0) {
+      a.part0[a.part_base + u] = 0.0;
+      a.part1[a.part_base + u] = 0.0;
+    }
+    return;
+  }
+  // The part of the twiddle table the passes read, in LDS: the passes then
+  // issue no global loads, and the table's one load per workgroup overlaps
+  // with the data loads.
+  constexpr int kTw = (tw_span(L) + 1) / 2 * 2;
+  __shared__ float2 T[kTw];
+  for (int i = threadIdx.x; 2 * i < kTw; i += 256)
+    reinterpret_cast<float4*>(T)[i] = reinterpret_cast<const float4*>(a.tw)[i];
+
+  const bool first = st.cg_it == 0;
+  const bool upd = a.mode == RFM_PRECOND && a.update;
+  // RF_FWD: the transformed plane v (r, or z for the new direction), the plane
+  // w it is combined with (q for the update of r, p_in for p = z + beta p_in);
+  // RF_INV: the plane e the result is dotted with (r, or p for q = result + tau_c p)
+  const float* vsrc = a.mode == RFM_PRECOND ? a.r : a.z;
+  const float* wsrc = a.mode == RFM_PRECOND ? a.q : a.p_in;
+  const bool wload = a.mode == RFM_PRECOND ? upd : !first;
+  const float* esrc = a.mode == RFM_PRECOND ? a.r : a.p;
+  // plane index of column i % L of real row 2 (row0 + i / L)
+  auto plane = [&](int i) __attribute__((always_inline)) {
+    return a.off + (long long)(2 * (row0 + i / L)) * a.pitch + i % L;
+  };
+  const float4 zero4 = make_float4(0.f, 0.f, 0.f, 0.f);
+
+  // ---- global loads ----
+  Regs R;
+  {
+    if (STAGE == RF_FWD) {
+      // the two real rows 2j, 2j+1 of each complex row, as 16-byte words of
+      // four columns (planes and pitches are 64-float aligned, L is a multiple of 4)
 #pragma unroll
-    for (int u = 0; u < NQ4; ++u) {
-      const int i = 4 * ((int)threadIdx.x + 256 * u);
-      va[u] = vb[u] = qa[u] = qb[u] = xa[u] = xb[u] = pa[u] = pb[u] = make_float4(0.f, 0.f, 0.f, 0.f);
-      if (i >= rows * L) continue;
-      const long long p = a.off + (long long)(2 * (row0 + i / L)) * a.pitch + i % L;
-      const long long p1 = p + a.pitch;
-      if (a.mode == RFM_PRECOND) {
-        va[u] = *reinterpret_cast<const float4*>(a.r + p);
-        vb[u] = *reinterpret_cast<const float4*>(a.r + p1);
+      for (int q = 0; q < N4; ++q) {
+        const int i = 4 * ((int)threadIdx.x + 256 * q);
+        R.va[q] = R.vb[q] = R.wa[q] = R.wb[q] = R.xa[q] = R.xb[q] = R.pa[q] = R.pb[q] = zero4;
+        if (i >= rows * L) continue;
+        const long long p = plane(i), p1 = p + a.pitch;
+        R.va[q] = *reinterpret_cast<const float4*>(vsrc + p);
+        R.vb[q] = *reinterpret_cast<const float4*>(vsrc + p1);
+        if (wload) {
+          R.wa[q] = *reinterpret_cast<const float4*>(wsrc + p);
+          R.wb[q] = *reinterpret_cast<const float4*>(wsrc + p1);
+        }
         if (upd) {
-          qa[u] = *reinterpret_cast<const float4*>(a.q + p);
-          qb[u] = *reinterpret_cast<const float4*>(a.q + p1);
-          xa[u] = *reinterpret_cast<const float4*>(a.x + p);
-          xb[u] = *reinterpret_cast<const float4*>(a.x + p1);
-          pa[u] = *reinterpret_cast<const float4*>(a.p + p);
-          pb[u] = *reinterpret_cast<const float4*>(a.p + p1);
-        }
-      } else {
-        va[u] = *reinterpret_cast<const float4*>(a.z + p);
-        vb[u] = *reinterpret_cast<const float4*>(a.z + p1);
-        if (!first) {
-          qa[u] = *reinterpret_cast<const float4*>(a.p_in + p);
-          qb[u] = *reinterpret_cast<const float4*>(a.p_in + p1);
+          R.xa[q] = *reinterpret_cast<const float4*>(a.x + p);
+          R.xb[q] = *reinterpret_cast<const float4*>(a.x + p1);
+          R.pa[q] = *reinterpret_cast<const float4*>(a.p + p);
+          R.pb[q] = *reinterpret_cast<const float4*>(a.p + p1);
         }
       }
-    }
-    float alpha = 0.f;
-    if (upd) {
-      const double al = cg_alpha(a.apart, a.acount, st.cg_rz);
-      alpha = (float)al;
-      if (blockIdx.x == 0 && threadIdx.x == 0) a.st_w[a.inst].cg_alpha = al;
-    }
+    } else if (STAGE == RF_FILT) {
+      // two complex values (16 bytes) per load, rows contiguous, and the
+      // filter's eigenvalues for use after the forward transform
 #pragma unroll
-    for (int u = 0; u < NQ4; ++u) {
-      const int i = 4 * ((int)threadIdx.x + 256 * u);
-      if (i >= rows * L) continue;
-      const long long p = a.off + (long long)(2 * (row0 + i / L)) * a.pitch + i % L;
-      const long long p1 = p + a.pitch;
-      const float ra[4] = {va[u].x, va[u].y, va[u].z, va[u].w};
-      const float rb[4] = {vb[u].x, vb[u].y, vb[u].z, vb[u].w};
-      const float sa[4] = {qa[u].x, qa[u].y, qa[u].z, qa[u].w};
-      const float sb[4] = {qb[u].x, qb[u].y, qb[u].z, qb[u].w};
-      float oa[4], ob[4];
-      if (a.mode == RFM_PRECOND) {
-        if (upd) {
-          const float xa4[4] = {xa[u].x, xa[u].y, xa[u].z, xa[u].w};
-          const float xb4[4] = {xb[u].x, xb[u].y, xb[u].z, xb[u].w};
-          const float pa4[4] = {pa[u].x, pa[u].y, pa[u].z, pa[u].w};
-          const float pb4[4] = {pb[u].x, pb[u].y, pb[u].z, pb[u].w};
-          float na[4], nb[4];
-#pragma unroll
-          for (int k = 0; k < 4; ++k) {
-            oa[k] = ra[k] - alpha * sa[k];
-            ob[k] = rb[k] - alpha * sb[k];
-            na[k] = xa4[k] + alpha * pa4[k];
-            nb[k] = xb4[k] + alpha * pb4[k];
-          }
-          *reinterpret_cast<float4*>(a.x + p) = make_float4(na[0], na[1], na[2], na[3]);
-          *reinterpret_cast<float4*>(a.x + p1) = make_float4(nb[0], nb[1], nb[2], nb[3]);
-          *reinterpret_cast<float4*>(a.r + p) = make_float4(oa[0], oa[1], oa[2], oa[3]);
-          *reinterpret_cast<float4*>(a.r + p1) = make_float4(ob[0], ob[1], ob[2], ob[3]);
-        } else {
-#pragma unroll
-          for (int k = 0; k < 4; ++k) {
-            oa[k] = ra[k];
-            ob[k] = rb[k];
-          }
-        }
-      } else {
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          oa[k] = first ? ra[k] : ra[k] + beta * sa[k];
-          ob[k] = first ? rb[k] : rb[k] + beta * sb[k];
-        }
-        *reinterpret_cast<float4*>(a.p + p) = make_float4(oa[0], oa[1], oa[2], oa[3]);
-        *reinterpret_cast<float4*>(a.p + p1) = make_float4(ob[0], ob[1], ob[2], ob[3]);
+      for (int q = 0; q < N2; ++q) {
+        const int i = 2 * ((int)threadIdx.x + 256 * q);
+        R.lv[q] = zero4;
+        R.sp[q] = make_float2(0.f, 0.f);
+        if (i >= rows * L) continue;
+        const long long e = (long long)(row0 + i / L) * L + i % L;
+        R.lv[q] = *reinterpret_cast<const float4*>(a.src + e);
+        R.sp[q] = *reinterpret_cast<const float2*>(a.specT + e);
       }
+    } else {
+      // each stored k <= W/2 once (it fills Z(k) and Z(W-k))
 #pragma unroll
-      for (int k = 0; k < 4; ++k) X[pidx(i + k)] = make_float2(oa[k], ob[k]);
-    }
-  } else if (STAGE == RF_FILT && !skip) {
-    // two complex values (16 bytes) per load; rows are contiguous
-    constexpr int NP2 = (kRows * L / 2 + 255) / 256;
-    float4 lv[NP2];
-#pragma unroll
-    for (int u = 0; u < NP2; ++u) {
-      const int i = 2 * ((int)threadIdx.x + 256 * u);
-      lv[u] = i < rows * L
-                  ? *reinterpret_cast<const float4*>(a.src + (long long)(row0 + i / L) * L + i % L)
-                  : make_float4(0.f, 0.f, 0.f, 0.f);
-    }
-#pragma unroll
-    for (int u = 0; u < NP2; ++u) {
-      const int i = 2 * ((int)threadIdx.x + 256 * u);
-      if (i >= rows * L) continue;
-      X[pidx(i)] = make_float2(lv[u].x, lv[u].y);
-      X[pidx(i + 1)] = make_float2(lv[u].z, lv[u].w);
-    }
-  } else if (STAGE == RF_INV && !skip) {
-    // In chunks of up to 8 elements per thread: every global load of a chunk
-    // is issued before its first LDS store.
-    constexpr int NU = (kRows * L + 255) / 256;
-    constexpr int CH = NU < 8 ? NU : 8;
-#pragma unroll
-    for (int b0 = 0; b0 < NU; b0 += CH) {
-      float2 la[CH], lb[CH];
-#pragma unroll
-      for (int k = 0; k < CH; ++k) {
-        const int i = threadIdx.x + (b0 + k) * 256;
-        la[k] = lb[k] = make_float2(0.f, 0.f);
-        if (b0 + k >= NU || i >= rows * L) continue;
-        const int j = row0 + i / L, c = i % L;
-        const int kk = c <= half ? c : L - c;
-        const float4 ab = *reinterpret_cast<const float4*>(a.src + (long long)kk * a.tld + 2 * j);
-        la[k] = make_float2(ab.x, ab.y);
-        lb[k] = make_float2(ab.z, ab.w);
-      }
-#pragma unroll
-      for (int k = 0; k < CH; ++k) {
-        const int i = threadIdx.x + (b0 + k) * 256;
-        if (b0 + k >= NU || i >= rows * L) continue;
-        const int c = i % L;
-        float2 A = la[k], B = lb[k];
-        if (!(c <= half)) { A.y = -A.y; B.y = -B.y; }
-        X[pidx(i)] = make_float2(A.x - B.y, A.y + B.x);
+      for (int q = 0; q < NH; ++q) {
+        const int i = threadIdx.x + 256 * q;
+        R.ab[q] = zero4;
+        if (i >= rows * (half + 1)) continue;
+        const int j = row0 + i / (half + 1), kk = i % (half + 1);
+        R.ab[q] = *reinterpret_cast<const float4*>(a.src + (long long)kk * a.tld + 2 * j);
       }
     }
   }
-  __syncthreads();
-  if (!skip) {
+  float alpha = 0.f;
+  const float beta = (float)st.cg_beta;
+  if (STAGE == RF_FWD && upd) {
+    // after the data loads are issued, so their latency overlaps
+    const double al = cg_alpha(a.apart, a.acount, st.cg_rz);
+    alpha = (float)al;
+    if (blockIdx.x == 0 && threadIdx.x == 0) a.st_w[a.inst].cg_alpha = al;
+  }
+
+  {
+    // ---- element-wise work and the row data into LDS ----
     if (STAGE == RF_FWD) {
-      fft_passes<L, 1, false, kRows * L>(X, rows, a.tw);
-    } else if (STAGE == RF_FILT) {
-      fft_passes<L, 1, false, kRows * L>(X, rows, a.tw);
-      const float dbar = (float)st.dbar;
-      #pragma unroll
-      for (int u_ = 0; u_ < (kRows * L / 2 + 255) / 256; ++u_) {
-        const int i = 2 * ((int)threadIdx.x + u_ * 256);
+#pragma unroll
+      for (int q = 0; q < N4; ++q) {
+        const int i = 4 * ((int)threadIdx.x + 256 * q);
         if (i >= rows * L) continue;
-        const float2 sp2 =
-            *reinterpret_cast<const float2*>(a.specT + (long long)(row0 + i / L) * L + i % L);
-        const float spv[2] = {sp2.x, sp2.y};
+        const long long p = plane(i), p1 = p + a.pitch;
+        const float ra[4] = {R.va[q].x, R.va[q].y, R.va[q].z, R.va[q].w};
+        const float rb[4] = {R.vb[q].x, R.vb[q].y, R.vb[q].z, R.vb[q].w};
+        const float sa[4] = {R.wa[q].x, R.wa[q].y, R.wa[q].z, R.wa[q].w};
+        const float sb[4] = {R.wb[q].x, R.wb[q].y, R.wb[q].z, R.wb[q].w};
+        float oa[4], ob[4];
+        if (a.mode == RFM_PRECOND) {
+          if (upd) {
+            const float xa4[4] = {R.xa[q].x, R.xa[q].y, R.xa[q].z, R.xa[q].w};
+            const float xb4[4] = {R.xb[q].x, R.xb[q].y, R.xb[q].z, R.xb[q].w};
+            const float pa4[4] = {R.pa[q].x, R.pa[q].y, R.pa[q].z, R.pa[q].w};
+            const float pb4[4] = {R.pb[q].x, R.pb[q].y, R.pb[q].z, R.pb[q].w};
+            float na[4], nb[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+              oa[k] = ra[k] - alpha * sa[k];
+              ob[k] = rb[k] - alpha * sb[k];
+              na[k] = xa4[k] + alpha * pa4[k];
+              nb[k] = xb4[k] + alpha * pb4[k];
+            }
+            *reinterpret_cast<float4*>(a.x + p) = make_float4(na[0], na[1], na[2], na[3]);
+            *reinterpret_cast<float4*>(a.x + p1) = make_float4(nb[0], nb[1], nb[2], nb[3]);
+            *reinterpret_cast<float4*>(a.r + p) = make_float4(oa[0], oa[1], oa[2], oa[3]);
+            *reinterpret_cast<float4*>(a.r + p1) = make_float4(ob[0], ob[1], ob[2], ob[3]);
+          } else {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+              oa[k] = ra[k];
+              ob[k] = rb[k];
+            }
+          }
+        } else {
+#pragma unroll
+          for (int k = 0; k < 4; ++k) {
+            oa[k] = first ? ra[k] : ra[k] + beta * sa[k];
+            ob[k] = first ? rb[k] : rb[k] + beta * sb[k];
+          }
+          *reinterpret_cast<float4*>(a.p + p) = make_float4(oa[0], oa[1], oa[2], oa[3]);
+          *reinterpret_cast<float4*>(a.p + p1) = make_float4(ob[0], ob[1], ob[2], ob[3]);
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) X[pidx(i + k)] = make_float2(oa[k], ob[k]);
+      }
+    } else if (STAGE == RF_FILT) {
+#pragma unroll
+      for (int q = 0; q < N2; ++q) {
+        const int i = 2 * ((int)threadIdx.x + 256 * q);
+        if (i >= rows * L) continue;
+        X[pidx(i)] = make_float2(R.lv[q].x, R.lv[q].y);
+        X[pidx(i + 1)] = make_float2(R.lv[q].z, R.lv[q].w);
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < NH; ++q) {
+        const int i = threadIdx.x + 256 * q;
+        if (i >= rows * (half + 1)) continue;
+        const int jr = i / (half + 1), kk = i % (half + 1);
+        const float4 v = R.ab[q];   // V_a(k) = (v.x, v.y), V_b(k) = (v.z, v.w)
+        X[pidx(jr * L + kk)] = make_float2(v.x - v.w, v.y + v.z);
+        if (kk > 0 && kk < half) X[pidx(jr * L + L - kk)] = make_float2(v.x + v.w, v.z - v.y);
+      }
+    }
+    __syncthreads();
+
+    // ---- passes ----
+    if (STAGE == RF_FWD) {
+      fft_passes<L, 1, false, kPts>(X, rows, T);
+    } else if (STAGE == RF_FILT) {
+      fft_passes<L, 1, false, kPts>(X, rows, T);
+      const float dbar = (float)st.dbar;
+#pragma unroll
+      for (int q = 0; q < N2; ++q) {
+        const int i = 2 * ((int)threadIdx.x + 256 * q);
+        if (i >= rows * L) continue;
+        const float spv[2] = {R.sp[q].x, R.sp[q].y};
 #pragma unroll
         for (int k = 0; k < 2; ++k) {
           const float sp = spv[k] * a.inv_xi;
@@ -543,71 +596,64 @@ __global__ __launch_bounds__(256) void k_rfft(RfftArgs a) {
         }
       }
       __syncthreads();
-      fft_passes<L, 1, true, kRows * L>(X, rows, a.tw);
+      fft_passes<L, 1, true, kPts>(X, rows, T);
     } else {
-      fft_passes<L, 1, true, kRows * L>(X, rows, a.tw);
+      fft_passes<L, 1, true, kPts>(X, rows, T);
     }
-  }
-  // ---- store ----
-  if (STAGE == RF_FWD) {
-    if (skip) return;
-    #pragma unroll
-    for (int u_ = 0; u_ < (kRows * (L / 2 + 1) + 255) / 256; ++u_) {
-      const int i = threadIdx.x + u_ * 256;
-      if (i >= rows * (half + 1)) continue;
-      const int jr = i / (half + 1), k = i % (half + 1);
-      const float2 zk = X[pidx(jr * L + k)];
-      float2 zm = X[pidx(jr * L + ((L - k) & (L - 1)))];
-      zm.y = -zm.y;                                   // conj Z(W - k)
-      const float2 sa = make_float2(0.5f * (zk.x + zm.x), 0.5f * (zk.y + zm.y));
-      const float2 sb = make_float2(0.5f * (zk.y - zm.y), -0.5f * (zk.x - zm.x));   // (Z - conj) / 2i
-      const int j = row0 + jr;
-      *reinterpret_cast<float4*>(a.dst + (long long)k * a.tld + 2 * j) = make_float4(sa.x, sa.y, sb.x, sb.y);
-    }
-  } else if (STAGE == RF_FILT) {
-    if (skip) return;
-    #pragma unroll
-    for (int u_ = 0; u_ < (kRows * L / 2 + 255) / 256; ++u_) {
-      const int i = 2 * ((int)threadIdx.x + u_ * 256);
-      if (i >= rows * L) continue;
-      const float2 v0 = X[pidx(i)], v1 = X[pidx(i + 1)];
-      *reinterpret_cast<float4*>(a.dst + (long long)(row0 + i / L) * L + i % L) =
-          make_float4(v0.x, v0.y, v1.x, v1.y);
-    }
-  } else {
-    double s0 = 0.0, s1 = 0.0;
-    if (!skip) {
-      // rows 2j, 2j+1 as 16-byte words of four columns; r (precondition) or p
-      // and tau_c (product) are loaded before the first store
-      constexpr int NQ4 = (kRows * L / 4 + 255) / 256;
-      float4 ea[NQ4], eb[NQ4], ta[NQ4], tb[NQ4];
+
+    // ---- stores ----
+    if (STAGE == RF_FWD) {
 #pragma unroll
-      for (int u = 0; u < NQ4; ++u) {
-        const int i = 4 * ((int)threadIdx.x + 256 * u);
-        ea[u] = eb[u] = ta[u] = tb[u] = make_float4(0.f, 0.f, 0.f, 0.f);
+      for (int q = 0; q < (kRows * (L / 2 + 1) + 255) / 256; ++q) {
+        const int i = threadIdx.x + q * 256;
+        if (i >= rows * (half + 1)) continue;
+        const int jr = i / (half + 1), k = i % (half + 1);
+        const float2 zk = X[pidx(jr * L + k)];
+        float2 zm = X[pidx(jr * L + ((L - k) & (L - 1)))];
+        zm.y = -zm.y;                                   // conj Z(W - k)
+        const float2 sa = make_float2(0.5f * (zk.x + zm.x), 0.5f * (zk.y + zm.y));
+        const float2 sb = make_float2(0.5f * (zk.y - zm.y), -0.5f * (zk.x - zm.x));   // (Z - conj) / 2i
+        const int j = row0 + jr;
+        *reinterpret_cast<float4*>(a.dst + (long long)k * a.tld + 2 * j) =
+            make_float4(sa.x, sa.y, sb.x, sb.y);
+      }
+    } else if (STAGE == RF_FILT) {
+#pragma unroll
+      for (int q = 0; q < N2; ++q) {
+        const int i = 2 * ((int)threadIdx.x + q * 256);
         if (i >= rows * L) continue;
-        const long long p = a.off + (long long)(2 * (row0 + i / L)) * a.pitch + i % L;
-        const long long p1 = p + a.pitch;
-        if (a.mode == RFM_PRECOND) {
-          ea[u] = *reinterpret_cast<const float4*>(a.r + p);
-          eb[u] = *reinterpret_cast<const float4*>(a.r + p1);
-        } else {
-          ea[u] = *reinterpret_cast<const float4*>(a.p + p);
-          eb[u] = *reinterpret_cast<const float4*>(a.p + p1);
-          ta[u] = *reinterpret_cast<const float4*>(a.tauc + p);
-          tb[u] = *reinterpret_cast<const float4*>(a.tauc + p1);
+        const float2 v0 = X[pidx(i)], v1 = X[pidx(i + 1)];
+        *reinterpret_cast<float4*>(a.dst + (long long)(row0 + i / L) * L + i % L) =
+            make_float4(v0.x, v0.y, v1.x, v1.y);
+      }
+    } else {
+      // r (precondition) or p and tau_c (product), rows 2j and 2j+1 as 16-byte
+      // words of four columns, all loaded before the first store (loaded here,
+      // after the transform: issued with the spectrum they delay its passes)
+      float4 ea[N4], eb[N4], ta[N4], tb[N4];
+#pragma unroll
+      for (int q = 0; q < N4; ++q) {
+        const int i = 4 * ((int)threadIdx.x + 256 * q);
+        ea[q] = eb[q] = ta[q] = tb[q] = zero4;
+        if (i >= rows * L) continue;
+        const long long p = plane(i), p1 = p + a.pitch;
+        ea[q] = *reinterpret_cast<const float4*>(esrc + p);
+        eb[q] = *reinterpret_cast<const float4*>(esrc + p1);
+        if (a.mode != RFM_PRECOND) {
+          ta[q] = *reinterpret_cast<const float4*>(a.tauc + p);
+          tb[q] = *reinterpret_cast<const float4*>(a.tauc + p1);
         }
       }
+      double s0 = 0.0, s1 = 0.0;
 #pragma unroll
-      for (int u = 0; u < NQ4; ++u) {
-        const int i = 4 * ((int)threadIdx.x + 256 * u);
+      for (int q = 0; q < N4; ++q) {
+        const int i = 4 * ((int)threadIdx.x + 256 * q);
         if (i >= rows * L) continue;
-        const long long p = a.off + (long long)(2 * (row0 + i / L)) * a.pitch + i % L;
-        const long long p1 = p + a.pitch;
-        const float va[4] = {ea[u].x, ea[u].y, ea[u].z, ea[u].w};
-        const float vb[4] = {eb[u].x, eb[u].y, eb[u].z, eb[u].w};
-        const float ua[4] = {ta[u].x, ta[u].y, ta[u].z, ta[u].w};
-        const float ub[4] = {tb[u].x, tb[u].y, tb[u].z, tb[u].w};
+        const long long p = plane(i), p1 = p + a.pitch;
+        const float va[4] = {ea[q].x, ea[q].y, ea[q].z, ea[q].w};
+        const float vb[4] = {eb[q].x, eb[q].y, eb[q].z, eb[q].w};
+        const float ua[4] = {ta[q].x, ta[q].y, ta[q].z, ta[q].w};
+        const float ub[4] = {tb[q].x, tb[q].y, tb[q].z, tb[q].w};
         float oa[4], ob[4];
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
@@ -626,23 +672,23 @@ __global__ __launch_bounds__(256) void k_rfft(RfftArgs a) {
         *reinterpret_cast<float4*>(a.out + p) = make_float4(oa[0], oa[1], oa[2], oa[3]);
         *reinterpret_cast<float4*>(a.out + p1) = make_float4(ob[0], ob[1], ob[2], ob[3]);
       }
-    }
-    // deterministic block sum: butterfly over each wave, then the four wave
-    // totals in a fixed order
+      // deterministic block sum: butterfly over each wave, then the four wave
+      // totals in a fixed order
 #pragma unroll
-    for (int off = kWave / 2; off >= 1; off >>= 1) {
-      s0 += __shfl_xor(s0, off, kWave);
-      s1 += __shfl_xor(s1, off, kWave);
-    }
-    __shared__ double sa[4], sb[4];
-    if (threadIdx.x % kWave == 0) {
-      sa[threadIdx.x / kWave] = s0;
-      sb[threadIdx.x / kWave] = s1;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      a.part0[a.part_base + blockIdx.x] = (sa[0] + sa[1]) + (sa[2] + sa[3]);
-      a.part1[a.part_base + blockIdx.x] = (sb[0] + sb[1]) + (sb[2] + sb[3]);
+      for (int off = kWave / 2; off >= 1; off >>= 1) {
+        s0 += __shfl_xor(s0, off, kWave);
+        s1 += __shfl_xor(s1, off, kWave);
+      }
+      __shared__ double sa[4], sb[4];
+      if (threadIdx.x % kWave == 0) {
+        sa[threadIdx.x / kWave] = s0;
+        sb[threadIdx.x / kWave] = s1;
+      }
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        a.part0[a.part_base + u] = (sa[0] + sa[1]) + (sa[2] + sa[3]);
+        a.part1[a.part_base + u] = (sb[0] + sb[1]) + (sb[2] + sb[3]);
+      }
     }
   }
 }
@@ -796,7 +842,8 @@ static hipError_t launch_rfft(int L, const RfftArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
-// Number of partial-sum slots the RF_INV stage of an H x W instance writes.
+// Number of partial-sum slots the RF_INV stage of an H x W instance writes
+// (one per row block).
 int rfft_partials(int H, int W) {
   const int kRows = rows_per_block(W);
   return (H / 2 + kRows - 1) / kRows;
