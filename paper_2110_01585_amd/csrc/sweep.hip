@@ -159,26 +159,23 @@ __device__ __forceinline__ void pair_v2(Px& L, Px& R, bool exists, bool cnt_edge
   }
 }
 
-__device__ __forceinline__ void set_dummy(Px& p) {
-#pragma unroll
-  for (int l = 0; l < 5; ++l) {
-    p.t[l] = 1.0f;
-    p.e[l] = 0.0f;
-  }
-}
-
 struct Raw {
   float4 v[5];  // the five sites of a lane's pixel pair, as loaded
 };
 
-__device__ __forceinline__ void fetch(const SweepArgs& a, long long idx, bool ok, Raw& R) {
+// The five sites of a lane's pixel pair.  idx is always inside the planes: rows
+// and columns beyond a free boundary are read at a clamped position.  Such
+// pixels (and the column right of an odd-width image, read from the row's
+// padding) take part only in pairs that do not exist and are never stored, so
+// what they hold never reaches a result; loading them anyway keeps the loads
+// unconditional and spares a select per value.
+__device__ __forceinline__ void fetch(const SweepArgs& a, long long idx, Raw& R) {
   const float2* S[5] = {a.S0, a.I1, a.I2, a.I3, a.I4};
 #pragma unroll
-  for (int l = 0; l < 5; ++l)
-    R.v[l] = ok ? *reinterpret_cast<const float4*>(S[l] + idx) : make_float4(1.f, 0.f, 1.f, 0.f);
+  for (int l = 0; l < 5; ++l) R.v[l] = *reinterpret_cast<const float4*>(S[l] + idx);
 }
 
-__device__ __forceinline__ void unpack(const Raw& R, bool okR, Px& L, Px& Rt) {
+__device__ __forceinline__ void unpack(const Raw& R, Px& L, Px& Rt) {
 #pragma unroll
   for (int l = 0; l < 5; ++l) {
     L.t[l] = R.v[l].x;
@@ -186,7 +183,6 @@ __device__ __forceinline__ void unpack(const Raw& R, bool okR, Px& L, Px& Rt) {
     Rt.t[l] = R.v[l].z;
     Rt.e[l] = R.v[l].w;
   }
-  if (!okR) set_dummy(Rt);
 }
 
 __device__ __forceinline__ void store_row(const SweepArgs& a, long long idx, bool wL, bool wR,
@@ -337,7 +333,9 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, int tile, int wav
     vL = cl >= 0 && cl < W;
     vR = cr >= 0 && cr < W;
     vN = cl + 2 >= 0 && cl + 2 < W;
-    gcl = cl;
+    // lanes outside the image read the nearest even column inside it (every
+    // lane that stores has vL, so its column is its own)
+    gcl = vL ? cl : (cl < 0 ? 0 : (W - 1) & ~1);
   }
   const bool wL = vL && cl >= c0 && cl < c0 + kStripInt && cl < W;
   const bool wR = vR && cr >= c0 && cr < c0 + kStripInt && cr < W;
@@ -365,28 +363,29 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, int tile, int wav
 
   auto row_ok = [&](int r) { return per || (r >= 0 && r < H); };
   auto row_in = [&](int r) { return r >= R0 && r < R1; };
+  // rows beyond a free boundary are read at the nearest row inside (and never
+  // stored: only rows of the chunk are)
   auto row_idx = [&](int r) {
-    const int g = per ? wrap(r, H) : r;
+    const int g = per ? wrap(r, H) : min(max(r, 0), H - 1);
     return I.off + (long long)g * I.pitch + gcl;
   };
-  // software pipelining: the next row pair is requested before the current one
-  // is processed, so its loads are in flight during the tilted-moment work
-  Raw nb, nc;
-  fetch(a, row_idx(rfirst), row_ok(rfirst) && vL, nb);
-  fetch(a, row_idx(rfirst + 1), row_ok(rfirst + 1) && vL, nc);
+  // Each row pair is loaded when its turn comes: the kernel is held to 168
+  // registers so three waves share a SIMD, and the other waves' tilted-moment
+  // work covers a wave's load latency.  (Requesting the next pair one
+  // iteration ahead needs 40 more registers and leaves two waves per SIMD,
+  // which is slower.)
   for (int it = 0; it < npairs; ++it) {
     const int r = rfirst + it * kStep;
     const bool bv = row_ok(r);
     const bool cv = row_ok(r + 1);
     const bool bint = row_in(r);
     const bool cint = row_in(r + 1);
+    Raw nb, nc;
+    fetch(a, row_idx(r), nb);
+    fetch(a, row_idx(r + 1), nc);
     Px bL, bR, cL, cR;
-    unpack(nb, vR, bL, bR);
-    unpack(nc, vR, cL, cR);
-    if (it + 1 < npairs) {
-      fetch(a, row_idx(r + kStep), row_ok(r + kStep) && vL, nb);
-      fetch(a, row_idx(r + kStep + 1), row_ok(r + kStep + 1) && vL, nc);
-    }
+    unpack(nb, bL, bR);
+    unpack(nc, cL, cR);
     float bomL = 0.f, bovL = 1.f, bomR = 0.f, bovR = 1.f, comL = 0.f, covL = 1.f, comR = 0.f,
           covR = 1.f;
     if (DELTA) {
@@ -545,9 +544,10 @@ __device__ __forceinline__ void sweep_block(const SweepArgs& a, int blk, int wav
 // blocks take the tile blocks h = blockIdx.x, blockIdx.x + gridDim.x, ...: a
 // static schedule with no dependence between blocks.  With gridDim.x a multiple
 // of 8, block h stays on the XCD that block-index order h would have given it,
-// so the XCD remap keeps neighbouring tile blocks in one L2 either way.
+// so the XCD remap keeps neighbouring tile blocks in one L2 either way.  At
+// least three waves per SIMD (at most 168 registers per lane).
 template <bool DELTA, class PR>
-__global__ __launch_bounds__(kWavesPerBlock * kWave) void k_tv_sweep(SweepArgs a) {
+__global__ __launch_bounds__(kWavesPerBlock * kWave, 3) void k_tv_sweep(SweepArgs a) {
   __shared__ float4 X[2 * kWavesPerBlock * kWave];
   const int wave = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
