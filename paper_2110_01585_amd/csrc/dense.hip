@@ -217,20 +217,33 @@ __global__ __launch_bounds__(256) void k_chol_diag(double* S, long long lds, int
   __syncthreads();
   for (int c = 0; c < kDT; ++c) {
     const int b = c & 1;
+    // every LDS read of the step before its first LDS write (the writes go to
+    // the other buffer, which the compiler cannot tell from these), so the
+    // reads are in flight together
+    double arc[kQ];
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) arc[q] = col[b][g + 4 * q];
     const double d = col[b][c];
-    const double rd = 1.0 / d;
-    const double akc = col[b][k] * rd;   // U[k][c]
+    const double ck = col[b][k];
     const double xck = row[b][k];        // X[c][k]
+    const double rd = 1.0 / d;
+    const double akc = ck * rd;          // U[k][c]
     if (t == c) piv[c] = d;
+    const bool kc = k > c;
+    double xn = 0.0;                     // this thread's X[c + 1][k], if it holds row c + 1
 #pragma unroll
     for (int q = 0; q < kQ; ++q) {
       const int r = g + 4 * q;
-      const double arc = col[b][r];
-      if (k > c && r >= k) a[q] = __builtin_fma(-arc, akc, a[q]);
-      if (r > c) x[q] = __builtin_fma(-arc * rd, xck, x[q]);
-      if (k == c + 1 && c + 1 < kDT) col[b ^ 1][r] = a[q];
-      if (r == c + 1) row[b ^ 1][k] = x[q];
+      if (kc && r >= k) a[q] = __builtin_fma(-arc[q], akc, a[q]);
+      if (r > c) x[q] = __builtin_fma(-arc[q] * rd, xck, x[q]);
+      xn = r == c + 1 ? x[q] : xn;
     }
+    // column c + 1 of A and row c + 1 of X, published by their owners
+    if (k == c + 1) {
+#pragma unroll
+      for (int q = 0; q < kQ; ++q) col[b ^ 1][g + 4 * q] = a[q];
+    }
+    if (c + 1 < kDT && ((c + 1 - g) & 3) == 0) row[b ^ 1][k] = xn;
     __syncthreads();
   }
   const double sk = 1.0 / sqrt(piv[k]);
