@@ -363,8 +363,8 @@ def main():
     if args.copy_probe:
         return copy_probe()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: every GPU box here has one GPU and there is no "
-              "multi-GPU path (the sharding design is described in DESIGN.md)", file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU path, so run it "
+              "with --gpus 1", file=sys.stderr)
         sys.exit(2)
     if args.workload == "net2048":
         return bench_net(args)
