@@ -221,6 +221,102 @@ __global__ __launch_bounds__(kThreads) void k_wht_high(WhtArgs a) {
   for (int i = 0; i < M; ++i) w[i * S] = v[i];
 }
 
+// All high bits [lb, logN) at once, hb = logN - lb <= kMidBits, in place on
+// the work buffer: a block takes kMidCols consecutive low indices and every
+// value of the high bits (2^hb x kMidCols elements, 64 KB at hb = 10) into LDS
+// as X[h][l], transforms along h, applies the multiply, and (two-sided)
+// transforms along h again.  This replaces the register groups' separate
+// passes over the high bits (two-sided: four passes become one).  Along h the
+// transform runs in register groups of up to 16 elements (radix 16, 16, 4 at
+// hb = 10), one LDS round trip and barrier per group.  Row h of X starts at
+// kMidCols (h + h / 16): one spare row every 16, so the 16-element groups of
+// the first stage (rows 16 apart in a wave) fall on different banks.
+constexpr int kMidBits = 10;
+constexpr int kMidCols = 16;      // 64-byte runs of each row h
+constexpr int kMidThreads = 1024; // one block per CU at hb = 10: every wave it can hold
+constexpr int kMidRows = (1 << kMidBits) + (1 << kMidBits) / 16;
+
+__device__ __forceinline__ int mid_off(int h, int l) { return kMidCols * (h + (h >> 4)) + l; }
+
+// One register-group stage along h: bits [s, s + G) of h.
+template <int G>
+__device__ __forceinline__ void mid_stage(float* X, int R, int s) {
+  constexpr int M = 1 << G;
+  const int S = 1 << s;
+  for (int q = threadIdx.x; q < (R >> G) * kMidCols; q += kMidThreads) {
+    const int l = q & (kMidCols - 1), b = q / kMidCols;
+    const int h0 = ((b >> s) << (s + G)) | (b & (S - 1));
+    float v[M];
+#pragma unroll
+    for (int i = 0; i < M; ++i) v[i] = X[mid_off(h0 + (i << s), l)];
+    reg_wht<G>(v);
+#pragma unroll
+    for (int i = 0; i < M; ++i) X[mid_off(h0 + (i << s), l)] = v[i];
+  }
+  __syncthreads();
+}
+
+__device__ __forceinline__ void mid_wht(float* X, int hb) {
+  const int R = 1 << hb;
+  for (int s = 0; s < hb;) {
+    const int g = hb - s < 4 ? hb - s : 4;
+    if (g == 4) mid_stage<4>(X, R, s);
+    else if (g == 3) mid_stage<3>(X, R, s);
+    else if (g == 2) mid_stage<2>(X, R, s);
+    else mid_stage<1>(X, R, s);
+    s += g;
+  }
+}
+
+__global__ __launch_bounds__(kMidThreads) void k_wht_mid(WhtArgs a) {
+  __shared__ __align__(16) float X[kMidCols * kMidRows];
+  const int hb = a.logN - a.lb;
+  const int R = 1 << hb;                       // rows h
+  const int n4 = R * (kMidCols / 4);           // float4 words of the tile
+  const int low0 = blockIdx.x * kMidCols;
+  // word i: row h = i / 4, columns l = 4 (i % 4) .. + 3 <-> work[(h << lb) + low0 + l]
+  auto widx = [&](int i) { return ((i >> 2) << a.lb) + low0 + 4 * (i & 3); };
+  auto xw = [&](int i) -> float4& {
+    return *reinterpret_cast<float4*>(X + mid_off(i >> 2, 4 * (i & 3)));
+  };
+  constexpr int kW = (kMidCols << kMidBits) / 4 / kMidThreads;   // words per thread at most
+  float4 ev[kW];
+  const bool need_eig = a.mul == WMUL_MASK || a.mul == WMUL_PRECOND;
+#pragma unroll
+  for (int u = 0; u < kW; ++u) {
+    const int i = threadIdx.x + u * kMidThreads;
+    if (i < n4) {
+      xw(i) = ld4(a.work + widx(i));
+      if (need_eig) ev[u] = ld4(a.eig + widx(i));
+    }
+  }
+  __syncthreads();
+  if (a.fwd) mid_wht(X, hb);
+  if (a.mul != WMUL_NONE) {
+    const float dbar = a.mul == WMUL_PRECOND ? (float)a.st[a.inst].dbar : 0.f;
+#pragma unroll
+    for (int u = 0; u < kW; ++u) {
+      const int i = threadIdx.x + u * kMidThreads;
+      if (i >= n4) continue;
+      const float e4[4] = {ev[u].x, ev[u].y, ev[u].z, ev[u].w};
+      float m[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+        m[k] = a.mul == WMUL_MASK ? e4[k] * a.scale
+             : a.mul == WMUL_PRECOND ? a.scale / (e4[k] * a.inv_xi + dbar) : a.scale;
+      const float4 v = xw(i);
+      xw(i) = make_float4(v.x * m[0], v.y * m[1], v.z * m[2], v.w * m[3]);
+    }
+    __syncthreads();
+  }
+  if (a.inv) mid_wht(X, hb);
+#pragma unroll
+  for (int u = 0; u < kW; ++u) {
+    const int i = threadIdx.x + u * kMidThreads;
+    if (i < n4) st4(a.work + widx(i), xw(i));
+  }
+}
+
 // mask in natural order -> spectrum plane (the spectral variance estimator
 // reads the eigenvalues of H^T H from it)
 __global__ void k_wht_spec(const float* __restrict__ eig, float* __restrict__ spec, long long off,
@@ -262,6 +358,22 @@ hipError_t run(const WhtPlan& P, WhtArgs a, bool two_sided, hipStream_t s) {
     return hipGetLastError();
   }
   const int hb = P.logN - P.lb, ng = (hb + kHighBits - 1) / kHighBits;
+  if (hb <= kMidBits && P.lb >= 4) {
+    // low bits, then every high bit in one LDS pass (multiply and, two-sided,
+    // the inverse included), then the low bits again (two-sided) and the post-op
+    WhtArgs first = a;
+    first.fwd = 1; first.inv = 0; first.mul = WMUL_NONE; first.dst = WDST_WORK;
+    hipLaunchKernelGGL(k_wht_low, dim3(nblk), dim3(kThreads), 0, s, first);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    WhtArgs m = a;
+    m.fwd = 1; m.inv = two_sided ? 1 : 0;
+    hipLaunchKernelGGL(k_wht_mid, dim3((1u << P.lb) / kMidCols), dim3(kMidThreads), 0, s, m);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    WhtArgs last = a;
+    last.src = WSRC_WORK; last.fwd = two_sided ? 1 : 0; last.inv = 0; last.mul = WMUL_NONE;
+    hipLaunchKernelGGL(k_wht_low, dim3(nblk), dim3(kThreads), 0, s, last);
+    return hipGetLastError();
+  }
   int gb[4], gg[4];
   for (int k = 0, b = P.lb; k < ng; ++k) {
     gg[k] = hb / ng + (k < hb % ng ? 1 : 0);
