@@ -82,7 +82,8 @@ def test_hadamard_cs_multigroup_256():
 
 @pytest.mark.parametrize("h,w", [(1024, 1024), (4096, 4096)])
 def test_hadamard_large_back_projection_and_solve(h, w):
-    """At 1024^2 (two register groups) and 4096^2 (three, the largest size):
+    """At 1024^2 (the eight high bits in one LDS pass) and 4096^2 (twelve, in
+    three register groups; the largest size):
     after two sweeps, the right-hand side of the mean solve is H^T y / xi +
     eta_c with H^T y from the oracle's Walsh matrices, and the true residual
     of the CG iterate in (H^T H / xi + diag tau_c) E = b, formed with the
