@@ -255,6 +255,7 @@ struct LikCtx {
   int pcur = 0;                      // which p plane holds the current search direction
   int sample = 0;                    // RBMC sample whose planes the kernels address
   bool fast = false;                 // every instance circulant: CG products and preconditioner by real FFTs
+  bool all_jacobi = false;           // every instance Jacobi: CG step and preconditioner in one pass
   int max_iters = kCgMaxIters;       // largest per-instance CG cap
   InstState* hst = nullptr;          // pinned host staging for CG polls (allocated on first poll)
   int n_all = 0;

@@ -650,6 +650,38 @@ __global__ __launch_bounds__(256) void k_cg_update(LikArgs A) {
       });
 }
 
+// 6b. The CG step and the Jacobi preconditioner in one pass, for contexts whose
+//     every instance is Jacobi-preconditioned: x += alpha p, r -= alpha q,
+//     z = r / diag(A), and partial sums of r.z and r.r (what k_cg_update and
+//     k_precond_dot do, without writing r and reading it back).
+__global__ __launch_bounds__(256) void k_cg_update_jacobi(LikArgs A) {
+  const int tile = blockIdx.x;
+  const int4 td = A.tiles[tile];
+  const LikInst L = A.inst[td.x];
+  const InstState& st = A.st[L.inst];
+  double rz = 0.0, rr = 0.0;
+  if (!st.cg_done) {
+    const float alpha = (float)st.cg_alpha;
+    const TileXY t = lik_tile(td, L);
+    float xv[kTileItems], pv[kTileItems], rv[kTileItems], qv[kTileItems], tv[kTileItems];
+    tile_two_phase<true>(
+        t, L,
+        [&](int u, long long p) {
+          xv[u] = A.x[p]; pv[u] = A.p_out[p]; rv[u] = A.r[p]; qv[u] = A.q[p]; tv[u] = A.tauc[p];
+        },
+        [&](int u, long long p) {
+          const float rn = rv[u] - alpha * qv[u];
+          const float zv = rn / (L.diagA + tv[u]);
+          A.x[p] = xv[u] + alpha * pv[u];
+          A.r[p] = rn;
+          A.z[p] = zv;
+          rz += (double)rn * (double)zv;
+          rr += (double)rn * (double)rn;
+        });
+  }
+  block_sum2(rz, rr, &A.part0[tile], &A.part1[tile]);
+}
+
 // Deterministic block maximum (256 threads), written by thread 0.
 __device__ __forceinline__ void block_max(float v, float* out) {
   __shared__ float wm[4];
@@ -1059,6 +1091,8 @@ hipError_t lik_create(LikCtx& lc, const LikInstInfo* li, int n, char* ws, const 
     lc.inst_of.push_back(i);
   }
   lc.fast = !lc.hinst.empty();
+  lc.all_jacobi = !lc.hinst.empty();
+  for (const LikInst& d : lc.hinst) lc.all_jacobi = lc.all_jacobi && d.precond == PRECOND_JACOBI;
   for (const LikInst& d : lc.hinst) {
     lc.fast = lc.fast && d.precond == PRECOND_CIRCULANT && d.op != OP_HAD && d.op != OP_GAUSS &&
               d.npart <= d.ntiles;
@@ -1295,6 +1329,12 @@ hipError_t lik_iterations(LikCtx& lc, int n, hipStream_t s) {
   for (int it = 0; it < n; ++it) {
     if ((e = launch_apply(lc, 1, s)) != hipSuccess) return e;   // p_out = z + beta p_in, q = A p_out
     if ((e = fin(lc, FIN_ALPHA, s)) != hipSuccess) return e;
+    if (lc.all_jacobi) {
+      if ((e = other(lc, s, k_cg_update_jacobi, make_args(lc))) != hipSuccess) return e;
+      if ((e = fin(lc, FIN_BETA, s)) != hipSuccess) return e;
+      lc.pcur ^= 1;
+      continue;
+    }
     if ((e = other(lc, s, k_cg_update, make_args(lc))) != hipSuccess) return e;
     if ((e = fft_precondition(lc, s)) != hipSuccess) return e;
     if ((e = wht_precondition(lc, s)) != hipSuccess) return e;
