@@ -324,10 +324,8 @@ __global__ __launch_bounds__(256) void k_apply(LikArgs A) {
   const LikInst L = A.inst[td.x];
   const InstState& st = A.st[L.inst];
   if (L.op != OP_BLUR) return;   // masked-DFT tiles: q and partials come from the FFT path
-  if (st.cg_done) {
-    block_sum2(0.0, 0.0, &A.part0[tile], &A.part1[tile]);
-    return;
-  }
+  // a finished solve's partials are not read (every finishing stage skips it)
+  if (st.cg_done) return;
   const TileXY t = lik_tile(td, L);
   const int Rr = L.Rr, Rc = L.Rc;
   const int EH = kLikTH + 2 * Rr, EW = kLikTW + 2 * Rc;
@@ -390,10 +388,8 @@ __global__ __launch_bounds__(256) void k_hth_sep(LikArgs A) {
   const LikInst L = A.inst[td.x];
   const InstState& st = A.st[L.inst];
   if (L.op != OP_BLUR) return;   // masked-DFT tiles: the FFT path writes q and partials
-  if (st.cg_done) {
-    block_sum2(0.0, 0.0, &A.part0[tile], &A.part1[tile]);
-    return;
-  }
+  // a finished solve's partials are not read (every finishing stage skips it)
+  if (st.cg_done) return;
   if (threadIdx.x < NT) {
     const int d = (int)threadIdx.x - RT;       // offset -RT..RT
     gr[threadIdx.x] = (d >= -L.Rr && d <= L.Rr) ? A.taps[L.gr_off + d + L.Rr] : 0.f;
@@ -605,8 +601,9 @@ __global__ __launch_bounds__(256) void k_precond_dot(LikArgs A) {
   const int4 td = A.tiles[tile];
   const LikInst L = A.inst[td.x];
   const InstState& st = A.st[L.inst];
+  if (st.cg_done) return;   // its partials are not read (every finishing stage skips it)
   double rz = 0.0, rr = 0.0;
-  if (!st.cg_done) {
+  {
     const TileXY t = lik_tile(td, L);
     const bool jac = L.precond == PRECOND_JACOBI;
     float rv[kTileItems], wv[kTileItems];   // r, and tau_c (Jacobi) or z
@@ -659,8 +656,9 @@ __global__ __launch_bounds__(256) void k_cg_update_jacobi(LikArgs A) {
   const int4 td = A.tiles[tile];
   const LikInst L = A.inst[td.x];
   const InstState& st = A.st[L.inst];
+  if (st.cg_done) return;   // its partials are not read (every finishing stage skips it)
   double rz = 0.0, rr = 0.0;
-  if (!st.cg_done) {
+  {
     const float alpha = (float)st.cg_alpha;
     const TileXY t = lik_tile(td, L);
     float xv[kTileItems], pv[kTileItems], rv[kTileItems], qv[kTileItems], tv[kTileItems];
