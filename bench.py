@@ -131,17 +131,67 @@ def kernel_rooflines(tm, npx, workload, op):
     return entries[dominant], entries
 
 
-def copy_probe(nbytes=1 << 30, reps=5):
+def copy_probe(nbytes=1 << 30, reps=9):
     """A plain device-to-device copy of known size (for scaling the HBM byte
     counters of rocprofv3)."""
     import torch
     src = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
     dst = torch.empty_like(src)
-    for _ in range(reps):
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(reps + 1)]
+    ev[0].record()
+    for i in range(reps):
         dst.copy_(src)
+        ev[i + 1].record()
     torch.cuda.synchronize()
+    # the copy's own rate: the practical ceiling of a pure streaming kernel
+    # (one read, one write per element) next to the 8 TB/s peak
+    ms = sorted(ev[i].elapsed_time(ev[i + 1]) for i in range(1, reps))
+    med = ms[len(ms) // 2] if ms else float("nan")
     print(json.dumps({"copy_probe_bytes_read": nbytes, "copy_probe_bytes_written": nbytes,
-                      "repetitions": reps}), flush=True)
+                      "repetitions": reps, "median_ms": round(med, 4),
+                      "gbps": round(2 * nbytes / (med * 1e-3) / 1e9, 1)}), flush=True)
+
+
+def stream_probe(h=4096, w=4096, reps=15):
+    """The sweep's access pattern (five float2 site planes read, four written,
+    h x w pixels each, 1.2 GB at 4096^2) with no arithmetic, timed with HIP
+    events on the probe's stream: the rate this pattern reaches on the device,
+    i.e. the practical ceiling for the sweep's fraction of the 8 TB/s peak."""
+    import ctypes
+
+    import torch
+    from paper_2110_01585_amd.build import PROBE_LIB
+    if not os.path.exists(PROBE_LIB):
+        raise RuntimeError(f"{PROBE_LIB} is not built; run __graft_entry__.build() first")
+    lib = ctypes.CDLL(PROBE_LIB)
+    lib.eptv_stream_probe.restype = ctypes.c_int
+    lib.eptv_stream_probe.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_void_p),
+                                      ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                      ctypes.c_void_p]
+    planes = [torch.zeros(h, w, 2, dtype=torch.float32, device="cuda") for _ in range(9)]
+    ins = (ctypes.c_void_p * 5)(*[t.data_ptr() for t in planes[:5]])
+    outs = (ctypes.c_void_p * 4)(*[t.data_ptr() for t in planes[5:]])
+    stream = torch.cuda.current_stream()
+    nbytes = 9 * h * w * 8
+    res = {"pattern": "5 float2 planes read, 4 written (the TV sweep's), no arithmetic",
+           "height": h, "width": w, "bytes_per_launch": nbytes}
+    for name, mode, rows in (("flat", 0, 0), ("march12", 1, 12), ("march48", 1, 48)):
+        def launch():
+            rc = lib.eptv_stream_probe(ins, outs, h, w, mode, rows, ctypes.c_void_p(stream.cuda_stream))
+            if rc != 0:
+                raise RuntimeError(f"eptv_stream_probe failed ({rc})")
+        for _ in range(3):
+            launch()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2 * reps)]
+        for i in range(reps):
+            ev[2 * i].record(stream)
+            launch()
+            ev[2 * i + 1].record(stream)
+        torch.cuda.synchronize()
+        us = sorted(ev[2 * i].elapsed_time(ev[2 * i + 1]) * 1e3 for i in range(reps))[reps // 2]
+        gbs = nbytes / (us * 1e-6) / 1e9
+        res[name] = {"us": round(us, 2), "gbps": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4)}
+    print(json.dumps(res), flush=True)
 
 
 def make_workload(name):
@@ -357,11 +407,16 @@ def main():
                     help="secondary workloads: oracle sweeps of the CPU sample (default per workload)")
     ap.add_argument("--cpu-size", type=int, default=None,
                     help="secondary workloads: side of the CPU sample (default per workload)")
+    ap.add_argument("--stream-probe", action="store_true",
+                    help="only run the streaming probe: the TV sweep's plane accesses without "
+                         "arithmetic (its practical HBM ceiling)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device copy (counter scaling for rocprofv3)")
     args = ap.parse_args()
     if args.copy_probe:
         return copy_probe()
+    if args.stream_probe:
+        return stream_probe()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the library has no multi-GPU path, so run it "
               "with --gpus 1", file=sys.stderr)

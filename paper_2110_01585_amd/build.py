@@ -3,7 +3,8 @@
     python -m paper_2110_01585_amd.build
 
 compiles every source under csrc/ with hipcc into _build/*.o (in parallel) and
-links paper_2110_01585_amd/lib/libeptv.so.  Packed-FP32 instruction selection
+links paper_2110_01585_amd/lib/libeptv.so, then the benchmark's streaming probe
+(probe/stream_probe.hip) into lib/libeptv_probe.so.  Packed-FP32 instruction selection
 is switched off for all device code.
 """
 from __future__ import annotations
@@ -19,6 +20,9 @@ CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(PKG, "_build")
 LIBDIR = os.path.join(PKG, "lib")
 LIB = os.path.join(LIBDIR, "libeptv.so")
+# the benchmark's streaming-bandwidth probe (not part of the EP library)
+PROBE_SRC = os.path.join(PKG, "probe", "stream_probe.hip")
+PROBE_LIB = os.path.join(LIBDIR, "libeptv_probe.so")
 INCLUDE = os.path.join(os.path.dirname(PKG), "include")
 ARCH = os.environ.get("EPTV_ARCH", "gfx950")
 
@@ -62,7 +66,22 @@ def build_library(verbose: bool = False) -> str:
     os.replace(tmp, LIB)
     if verbose:
         print(f"built {LIB}")
+    build_probe(verbose)
     return LIB
+
+
+def build_probe(verbose: bool = False) -> str:
+    """lib/libeptv_probe.so: the streaming-bandwidth probe bench.py --stream-probe runs."""
+    os.makedirs(LIBDIR, exist_ok=True)
+    tmp = PROBE_LIB + ".tmp"
+    cmd = [_hipcc(), PROBE_SRC, "-shared", "-o", tmp] + COMMON
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"hipcc failed on {PROBE_SRC}:\n{r.stdout}\n{r.stderr}")
+    os.replace(tmp, PROBE_LIB)
+    if verbose:
+        print(f"built {PROBE_LIB}")
+    return PROBE_LIB
 
 
 if __name__ == "__main__":
