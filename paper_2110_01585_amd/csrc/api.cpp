@@ -702,12 +702,14 @@ static int build_graphs(ep_tv_ctx* c, int em, bool delta, double tol) {
   Graphs& g = c->g;
   if (g.valid && g.em == em && g.delta == delta && g.tol == tol) return EP_TV_OK;
   drop_graphs(c);
+  if (c->any_lik) HIPCHK(c, lik_poll_word_alloc(c->lik));
   int rc = EP_TV_OK;
   for (int par = 0; par < 2 && rc == EP_TV_OK; ++par) {
     if (c->any_lik) {
       rc = capture(c, &g.head[par], [&](hipStream_t s) -> int {
         HIPCHK(c, lik_head(c->lik, sites_at(c, par).S, s));
         HIPCHK(c, lik_iterations(c->lik, kCgPoll, s));
+        HIPCHK(c, lik_poll_word_launch(c->lik, s));
         return EP_TV_OK;
       });
       if (rc == EP_TV_OK)
@@ -730,6 +732,7 @@ static int build_graphs(ep_tv_ctx* c, int em, bool delta, double tol) {
   if (rc == EP_TV_OK && c->any_lik)
     rc = capture(c, &g.cg, [&](hipStream_t s) -> int {
       HIPCHK(c, lik_iterations(c->lik, kCgPoll, s));
+      HIPCHK(c, lik_poll_word_launch(c->lik, s));
       return EP_TV_OK;
     });
   if (rc != EP_TV_OK) {
@@ -744,18 +747,21 @@ static int build_graphs(ep_tv_ctx* c, int em, bool delta, double tol) {
 }
 
 // One sweep from the graphs: the CG runs kCgPoll iterations per replay until
-// every instance's solve has converged (checked on the host between replays).
+// every instance's solve has converged, which the last kernel of each replay
+// reports in the pinned poll word the host waits on.
 static int graph_sweep(ep_tv_ctx* c) {
   Graphs& g = c->g;
   if (c->any_lik) {
+    unsigned seq = lik_poll_word_seq(c->lik);
     HIPCHK(c, hipGraphLaunch(g.head[c->cur], c->stream));
     int iters = kCgPoll;
     bool done = false;
-    HIPCHK(c, lik_poll(c->lik, c->stream, done));
+    HIPCHK(c, lik_poll_word_wait(c->lik, c->stream, seq, done));
     while (!done && iters < c->lik.max_iters) {
+      seq = lik_poll_word_seq(c->lik);
       HIPCHK(c, hipGraphLaunch(g.cg, c->stream));
       iters += kCgPoll;
-      HIPCHK(c, lik_poll(c->lik, c->stream, done));
+      HIPCHK(c, lik_poll_word_wait(c->lik, c->stream, seq, done));
     }
   }
   HIPCHK(c, hipGraphLaunch(g.tail[c->cur], c->stream));

@@ -258,6 +258,8 @@ struct LikCtx {
   bool all_jacobi = false;           // every instance Jacobi: CG step and preconditioner in one pass
   int max_iters = kCgMaxIters;       // largest per-instance CG cap
   InstState* hst = nullptr;          // pinned host staging for CG polls (allocated on first poll)
+  long long* poll_word = nullptr;    // pinned host word of graph-replay polls (host address)
+  long long* poll_word_dev = nullptr;  // the same word as the device addresses it
   int n_all = 0;
   // kernel timing (event pairs per bucket, KT_*)
   bool timing = false;
@@ -319,6 +321,16 @@ hipError_t lik_update(LikCtx& lc, float2* const S[5], hipStream_t s);
 hipError_t lik_head(LikCtx& lc, float2* const S[5], hipStream_t s);
 hipError_t lik_iterations(LikCtx& lc, int n, hipStream_t s);
 hipError_t lik_poll(LikCtx& lc, hipStream_t s, bool& all_done);
+// The poll of graph replays: lik_poll_word_launch queues (for capture at the end
+// of a run of CG iterations) a kernel that writes {all solves stopped, sequence
+// number + 1} to a pinned host word; the host reads the sequence number before
+// launching such a replay (lik_poll_word_seq) and waits for it to change
+// (lik_poll_word_wait, which spins on the word and falls back to the stream's
+// completion if the stream drains without a new word).
+hipError_t lik_poll_word_alloc(LikCtx& lc);   // before capture: no allocation while capturing
+hipError_t lik_poll_word_launch(LikCtx& lc, hipStream_t s);
+unsigned lik_poll_word_seq(const LikCtx& lc);
+hipError_t lik_poll_word_wait(LikCtx& lc, hipStream_t s, unsigned seq0, bool& all_done);
 hipError_t lik_tail(LikCtx& lc, float2* S0, hipStream_t s);
 // RBMC: the white noise of every RBMC instance (host array of device pointers,
 // one per instance of the context; NULL for instances without RBMC): H^T e1 and

@@ -1362,6 +1362,76 @@ hipError_t lik_poll(LikCtx& lc, hipStream_t s, bool& all_done) {
   return hipSuccess;
 }
 
+// CG poll word for graph replays: the last kernel of a captured run of CG
+// iterations writes to pinned host memory whether every instance's solve has
+// stopped (high half) next to a sequence number one above the one it finds
+// there (low half), so the host waits for the word to change instead of
+// copying the flags back and synchronising the stream.  One thread; the 64-bit
+// system-scope store makes both halves visible to the host at once.
+__global__ void k_cg_poll_word(const LikInst* __restrict__ inst, int nlik,
+                               const InstState* __restrict__ st, long long* word) {
+  int done = 1;
+  for (int j = 0; j < nlik; ++j) done &= st[inst[j].inst].cg_done ? 1 : 0;
+  const long long w = __hip_atomic_load(word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+  const unsigned seq = (unsigned)w + 1u;
+  __hip_atomic_store(word, ((long long)done << 32) | (long long)seq, __ATOMIC_RELEASE,
+                     __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+hipError_t lik_poll_word_alloc(LikCtx& lc) {
+  if (lc.poll_word) return hipSuccess;
+  void* h = nullptr;
+  hipError_t e = hipHostMalloc(&h, 64, hipHostMallocMapped | hipHostMallocCoherent);
+  if (e != hipSuccess) return e;
+  void* d = nullptr;
+  e = hipHostGetDevicePointer(&d, h, 0);
+  if (e != hipSuccess) {
+    (void)hipHostFree(h);
+    return e;
+  }
+  lc.poll_word = static_cast<long long*>(h);
+  lc.poll_word_dev = static_cast<long long*>(d);
+  __atomic_store_n(lc.poll_word, 0LL, __ATOMIC_RELEASE);
+  return hipSuccess;
+}
+
+hipError_t lik_poll_word_launch(LikCtx& lc, hipStream_t s) {
+  if (lc.nlik == 0) return hipSuccess;
+  if (!lc.poll_word_dev) return hipErrorInvalidValue;   // lik_poll_word_alloc first
+  hipLaunchKernelGGL(k_cg_poll_word, dim3(1), dim3(1), 0, s, lc.d_inst, lc.nlik,
+                     (const InstState*)lc.d_st, lc.poll_word_dev);
+  return hipGetLastError();
+}
+
+unsigned lik_poll_word_seq(const LikCtx& lc) {
+  return lc.poll_word ? (unsigned)__atomic_load_n(lc.poll_word, __ATOMIC_ACQUIRE) : 0u;
+}
+
+hipError_t lik_poll_word_wait(LikCtx& lc, hipStream_t s, unsigned seq0, bool& all_done) {
+  all_done = true;
+  if (lc.nlik == 0) return hipSuccess;
+  if (!lc.poll_word) return hipErrorInvalidValue;
+  auto fresh = [&](bool& done) {
+    const long long w = __atomic_load_n(lc.poll_word, __ATOMIC_ACQUIRE);
+    if ((unsigned)w == seq0) return false;
+    done = (w >> 32) != 0;
+    return true;
+  };
+  for (unsigned spin = 1;; ++spin) {
+    if (fresh(all_done)) return hipSuccess;
+    if (spin % 256 == 0) {
+      // the stream has drained without a new word only if the poll kernel
+      // did not run; wait for the stream once and look again before failing
+      const hipError_t q = hipStreamQuery(s);
+      if (q == hipErrorNotReady) continue;
+      if (q != hipSuccess) return q;
+      const hipError_t e = hipStreamSynchronize(s);
+      if (e != hipSuccess) return e;
+      return fresh(all_done) ? hipSuccess : hipErrorUnknown;
+    }
+  }
+}
+
 hipError_t lik_tail(LikCtx& lc, float2* S0, hipStream_t s) {
   if (lc.nlik == 0) return hipSuccess;
   return other(lc, s, k_lik_site, make_args(lc), S0);
@@ -1412,6 +1482,8 @@ void lik_destroy(LikCtx& lc) {
   lc.ev.clear();
   if (lc.hst) (void)hipHostFree(lc.hst);
   lc.hst = nullptr;
+  if (lc.poll_word) (void)hipHostFree(lc.poll_word);
+  lc.poll_word = lc.poll_word_dev = nullptr;
   dft_destroy(lc);
 }
 
