@@ -15,7 +15,7 @@
 // rows 4*(l/16)..+3 of column l%16 of D):
 //   forward / input gradient: D[out channel][pixel] = sum over taps of
 //     W_tap[out][in] x X[in][pixel], A = weights (per-wave registers, all 9 taps),
-//     B = 16 pixels x 8 channels loaded straight from the NHWC tensor;
+//     B = 16 pixels x 8 channels read from the block's input tile staged in LDS;
 //   weight gradient: D[in][out] = sum over pixels X[pixel + tap][in] G[pixel][out],
 //     with both operands transposed through LDS (pixels contiguous).
 // The 1 -> 32 and 32 -> 2 layers are plain float32 FMAs.
@@ -206,69 +206,114 @@ __global__ __launch_bounds__(256) void k_conv1(const float* __restrict__ y,
 // ---------------------------------------------------------------- 32 -> 32 conv on MFMA
 enum { EPI_RELU = 0, EPI_MASK = 1 };
 
-// grid (ceil(W / 64), ceil(H / 4), B), 256 threads: wave w takes image row
-// 4 * blockIdx.y + w, columns 64 * blockIdx.x .. +63 in four groups of 16.
+// grid (ceil(W / 64), ceil(H / 16), B), 256 threads.  A block takes columns
+// 64 * blockIdx.x .. +63 of rows 16 * blockIdx.y .. +15 in four steps of four
+// rows; in each step wave w takes row +w, in four groups of 16 columns.  The
+// weights of all nine taps stay in registers across the steps.  Each step's
+// input tile (rows -1 .. +4 and columns -1 .. +64 around its outputs, zero
+// outside the image: 6 x 66 pixels x 64 bytes) is staged in LDS as 16-byte
+// words ordered [k-slice][row][column], so the 16 lanes of a k-slice read 16
+// consecutive words for each tap instead of gathering them from global memory
+// nine times.
+constexpr int kConvTR = 6, kConvTC = 66;                 // staged tile rows, columns
+constexpr int kConvWords = 4 * kConvTR * kConvTC;        // 16-byte words per tile (1,584, 25,344 bytes)
+constexpr int kConvSteps = 4;                            // four-row steps per block
+static_assert(kConvWords <= 8 * 256, "two staging rounds of four words per thread");
 template <int EPI>
 __global__ __launch_bounds__(256) void k_conv32(const uint16_t* __restrict__ in,
                                                 const uint16_t* __restrict__ wa,
                                                 const float* __restrict__ bias,
                                                 const uint16_t* __restrict__ mask,
                                                 uint16_t* __restrict__ out, int H, int W) {
+  // two tile buffers: a step stages into one while slower waves may still read
+  // the previous step's tile from the other; the barrier after staging step s
+  // is passed only once every wave has finished step s - 1, so step s + 1 can
+  // overwrite that step's buffer
+  __shared__ bf16x8 X[2][kConvWords];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int q = lane >> 4, pl = lane & 15;
   const int n = blockIdx.z;
-  const int r = blockIdx.y * 4 + wave;
   const int c0 = blockIdx.x * 64;
-  bf16x8 A[9][2];
-#pragma unroll
-  for (int t = 0; t < 9; ++t)
-#pragma unroll
-    for (int mb = 0; mb < 2; ++mb) A[t][mb] = ld8(wa + ((t * C + 16 * mb + pl) * C + 8 * q));
-  float bv[2][4];
-#pragma unroll
-  for (int mb = 0; mb < 2; ++mb)
-#pragma unroll
-    for (int i = 0; i < 4; ++i) bv[mb][i] = EPI == EPI_RELU ? bias[16 * mb + 4 * q + i] : 0.f;
   const long long img = (long long)n * H * W;
-  for (int g = 0; g < 4; ++g) {
-    const int c = c0 + 16 * g + pl;
-    if (c0 + 16 * g >= W) break;                  // the whole group is right of the image
-    f4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
+  bf16x8 A[9][2];
+  float bv[2][4];
+  for (int step = 0; step < kConvSteps; ++step) {
+    const int r0 = (blockIdx.y * kConvSteps + step) * 4;
+    if (r0 >= H) break;                           // uniform over the block
+    const int r = r0 + wave;
+    bf16x8* T = X[step & 1];
+    // stage: word w = (tile row, tile column, k-slice) in global order (a tile
+    // row's 66 pixels are contiguous in NHWC), stored at [k-slice][row][column]
+    // in two rounds of four words per thread, each round's loads in flight
+    // together (the weights stay in registers, so the rounds are kept short)
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      const int rr = r + a - 1;
-      const bool rok = r < H && rr >= 0 && rr < H;
+    for (int h = 0; h < 2; ++h) {
+      bf16x8 v[4];
 #pragma unroll
-      for (int b = 0; b < 3; ++b) {
-        const int cc = c + b - 1;
-        const bf16x8 xb = (rok && cc >= 0 && cc < W)
-                              ? ld8(in + (img + (long long)rr * W + cc) * C + 8 * q)
-                              : zero8();
-        acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[3 * a + b][0], xb, acc0, 0, 0, 0);
-        acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[3 * a + b][1], xb, acc1, 0, 0, 0);
+      for (int u = 0; u < 4; ++u) {
+        const int w = (int)threadIdx.x + 256 * (4 * h + u);
+        v[u] = zero8();
+        if (w >= kConvWords) continue;
+        const int tr = w / (4 * kConvTC), rem = w - tr * (4 * kConvTC);
+        const int rr = r0 - 1 + tr, cc = c0 - 1 + (rem >> 2);
+        if (rr >= 0 && rr < H && cc >= 0 && cc < W)
+          v[u] = ld8(in + (img + (long long)rr * W + cc) * C + 8 * (rem & 3));
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int w = (int)threadIdx.x + 256 * (4 * h + u);
+        if (w >= kConvWords) continue;
+        const int tr = w / (4 * kConvTC), rem = w - tr * (4 * kConvTC);
+        T[((rem & 3) * kConvTR + tr) * kConvTC + (rem >> 2)] = v[u];
       }
     }
-    if (r >= H || c >= W) continue;
-    const long long px = img + (long long)r * W + c;
+    if (step == 0) {
 #pragma unroll
-    for (int mb = 0; mb < 2; ++mb) {
-      const f4 acc = mb ? acc1 : acc0;
-      const int ch = 16 * mb + 4 * q;
-      uint16_t h[4];
-      if (EPI == EPI_RELU) {
+      for (int t = 0; t < 9; ++t)
 #pragma unroll
-        for (int i = 0; i < 4; ++i) h[i] = f2bf(fmaxf(acc[i] + bv[mb][i], 0.f));
-      } else {
-        const uint2 mv = *reinterpret_cast<const uint2*>(mask + px * C + ch);
-        const uint16_t m4[4] = {(uint16_t)(mv.x & 0xffff), (uint16_t)(mv.x >> 16),
-                                (uint16_t)(mv.y & 0xffff), (uint16_t)(mv.y >> 16)};
+        for (int mb = 0; mb < 2; ++mb) A[t][mb] = ld8(wa + ((t * C + 16 * mb + pl) * C + 8 * q));
 #pragma unroll
-        for (int i = 0; i < 4; ++i) h[i] = bf_pos(m4[i]) ? f2bf(acc[i]) : (uint16_t)0;
+      for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) bv[mb][i] = EPI == EPI_RELU ? bias[16 * mb + 4 * q + i] : 0.f;
+    }
+    __syncthreads();
+    for (int g = 0; g < 4; ++g) {
+      const int c = c0 + 16 * g + pl;
+      if (c0 + 16 * g >= W) break;                // the whole group is right of the image
+      f4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+          // tap (a, b) of output column c reads tile row wave + a, column 16 g + pl + b
+          const bf16x8 xb = T[(q * kConvTR + wave + a) * kConvTC + 16 * g + pl + b];
+          acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[3 * a + b][0], xb, acc0, 0, 0, 0);
+          acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[3 * a + b][1], xb, acc1, 0, 0, 0);
+        }
       }
-      uint2 v;
-      v.x = h[0] | ((uint32_t)h[1] << 16);
-      v.y = h[2] | ((uint32_t)h[3] << 16);
-      *reinterpret_cast<uint2*>(out + px * C + ch) = v;
+      if (r >= H || c >= W) continue;
+      const long long px = img + (long long)r * W + c;
+#pragma unroll
+      for (int mb = 0; mb < 2; ++mb) {
+        const f4 acc = mb ? acc1 : acc0;
+        const int ch = 16 * mb + 4 * q;
+        uint16_t h[4];
+        if (EPI == EPI_RELU) {
+#pragma unroll
+          for (int i = 0; i < 4; ++i) h[i] = f2bf(fmaxf(acc[i] + bv[mb][i], 0.f));
+        } else {
+          const uint2 mv = *reinterpret_cast<const uint2*>(mask + px * C + ch);
+          const uint16_t m4[4] = {(uint16_t)(mv.x & 0xffff), (uint16_t)(mv.x >> 16),
+                                  (uint16_t)(mv.y & 0xffff), (uint16_t)(mv.y >> 16)};
+#pragma unroll
+          for (int i = 0; i < 4; ++i) h[i] = bf_pos(m4[i]) ? f2bf(acc[i]) : (uint16_t)0;
+        }
+        uint2 v;
+        v.x = h[0] | ((uint32_t)h[1] << 16);
+        v.y = h[2] | ((uint32_t)h[3] << 16);
+        *reinterpret_cast<uint2*>(out + px * C + ch) = v;
+      }
     }
   }
 }
@@ -749,7 +794,7 @@ hipError_t forward5(ep_tv_net* n, const float* y, int B, int H, int W) {
   hipLaunchKernelGGL(k_stats_fin, dim3(B), dim3(256), 0, s, n->d.stats_part, H, W, n->d.stats);
   hipLaunchKernelGGL(k_conv1, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, s, y, n->d.stats, n->d.w1r,
                      n->master + kOffB1, n->d.act[0], B, H, W);
-  const dim3 g((W + 63) / 64, (H + 3) / 4, B);
+  const dim3 g((W + 63) / 64, (H + 4 * kConvSteps - 1) / (4 * kConvSteps), B);
   for (int l = 0; l < 4; ++l)
     hipLaunchKernelGGL((k_conv32<EPI_RELU>), g, dim3(256), 0, s, n->d.act[l], n->d.wf + l * kW32,
                        n->master + kOff2 + l * kStride32 + kW32, (const uint16_t*)nullptr, n->d.act[l + 1],
@@ -855,7 +900,7 @@ int ep_tv_net_loss_grad(ep_tv_net* n, const float* d_y, const float* d_mu_t, con
                      n->d_loss);
   const dim3 gt((w + kTile - 1) / kTile, (h + kTile - 1) / kTile, batch);
   const int nblk = (int)(gt.x * gt.y * gt.z);
-  const dim3 gc((w + 63) / 64, (h + 3) / 4, batch);
+  const dim3 gc((w + 63) / 64, (h + 4 * kConvSteps - 1) / (4 * kConvSteps), batch);
   // layer 6: weight gradient, input gradient (masked by a5)
   hipLaunchKernelGGL(k_wgrad6, gt, dim3(256), 0, s, n->d.act[4], n->d.o, n->d.part, h, w);
   reduce_grad(n, nblk, kW6 + 2, n->d.grad + kOffW6, s);
