@@ -224,6 +224,7 @@ struct Graphs {
   bool delta = false;
   double tol = 0.0;
   hipGraphExec_t head[2]{};    // likelihood head + kCgPoll CG iterations
+  hipGraphExec_t head_short[2]{};  // likelihood head + kCgHeadShort CG iterations
   hipGraphExec_t cg = nullptr; // kCgPoll CG iterations
   hipGraphExec_t tail[2]{};    // likelihood site + TV sweep + finalize (one sweep)
   hipGraphExec_t multi[2]{};   // kGraphSweeps whole sweeps (identity operators only)
@@ -241,6 +242,7 @@ struct ep_tv_ctx {
   int chunk_rows = 0;        // current sweep tile height
   bool use_graph = false;
   Graphs g;
+  int cg_iters_prev = 1 << 30;   // largest CG iteration count of the last graph-replayed sweep
   hipStream_t cap = nullptr; // private stream used only to capture graphs
   hipStream_t stream = nullptr;
   char* ws = nullptr;
@@ -389,7 +391,8 @@ static int upload_tiles(ep_tv_ctx* c) {
 
 static void drop_graphs(ep_tv_ctx* c) {
   Graphs& g = c->g;
-  hipGraphExec_t* all[] = {&g.head[0], &g.head[1], &g.cg, &g.tail[0], &g.tail[1], &g.multi[0], &g.multi[1]};
+  hipGraphExec_t* all[] = {&g.head[0], &g.head[1], &g.head_short[0], &g.head_short[1], &g.cg,
+                           &g.tail[0], &g.tail[1], &g.multi[0], &g.multi[1]};
   for (hipGraphExec_t* e : all)
     if (*e) {
       (void)hipGraphExecDestroy(*e);
@@ -713,6 +716,13 @@ static int build_graphs(ep_tv_ctx* c, int em, bool delta, double tol) {
         return EP_TV_OK;
       });
       if (rc == EP_TV_OK)
+        rc = capture(c, &g.head_short[par], [&](hipStream_t s) -> int {
+          HIPCHK(c, lik_head(c->lik, sites_at(c, par).S, s));
+          HIPCHK(c, lik_iterations(c->lik, kCgHeadShort, s));
+          HIPCHK(c, lik_poll_word_launch(c->lik, s));
+          return EP_TV_OK;
+        });
+      if (rc == EP_TV_OK)
         rc = capture(c, &g.tail[par], [&](hipStream_t s) -> int {
           HIPCHK(c, lik_tail(c->lik, c->S0, s));
           return enqueue_tv(c, par, em, delta, tol, s);
@@ -748,21 +758,27 @@ static int build_graphs(ep_tv_ctx* c, int em, bool delta, double tol) {
 
 // One sweep from the graphs: the CG runs kCgPoll iterations per replay until
 // every instance's solve has converged, which the last kernel of each replay
-// reports in the pinned poll word the host waits on.
+// reports in the pinned poll word the host waits on.  The head replay carries
+// kCgHeadShort iterations instead when the previous sweep's solves all
+// stopped within that many (near the fixed point they need about two), so
+// fewer launches of a finished solve's iterations run.
 static int graph_sweep(ep_tv_ctx* c) {
   Graphs& g = c->g;
   if (c->any_lik) {
     unsigned seq = lik_poll_word_seq(c->lik);
-    HIPCHK(c, hipGraphLaunch(g.head[c->cur], c->stream));
-    int iters = kCgPoll;
+    const bool short_head = c->cg_iters_prev <= kCgHeadShort;
+    HIPCHK(c, hipGraphLaunch(short_head ? g.head_short[c->cur] : g.head[c->cur], c->stream));
+    int iters = short_head ? kCgHeadShort : kCgPoll;
     bool done = false;
-    HIPCHK(c, lik_poll_word_wait(c->lik, c->stream, seq, done));
+    int used = 0;
+    HIPCHK(c, lik_poll_word_wait(c->lik, c->stream, seq, done, used));
     while (!done && iters < c->lik.max_iters) {
       seq = lik_poll_word_seq(c->lik);
       HIPCHK(c, hipGraphLaunch(g.cg, c->stream));
       iters += kCgPoll;
-      HIPCHK(c, lik_poll_word_wait(c->lik, c->stream, seq, done));
+      HIPCHK(c, lik_poll_word_wait(c->lik, c->stream, seq, done, used));
     }
+    c->cg_iters_prev = used;
   }
   HIPCHK(c, hipGraphLaunch(g.tail[c->cur], c->stream));
   c->cur ^= 1;

@@ -23,6 +23,7 @@ constexpr int kMaxRadius = kMaxTaps - 1;   // radius of the combined H^T H kerne
 constexpr int kCgMaxIters = 50;
 constexpr double kCgTol = 1e-8;            // relative residual ||r|| / ||b||
 constexpr int kCgPoll = 4;                 // CG iterations between convergence checks (even)
+constexpr int kCgHeadShort = 2;            // CG iterations of the short head graph (even)
 
 inline bool fft_size_ok(int n) { return n >= 4 && n <= 4096 && (n & (n - 1)) == 0; }
 
@@ -322,15 +323,17 @@ hipError_t lik_head(LikCtx& lc, float2* const S[5], hipStream_t s);
 hipError_t lik_iterations(LikCtx& lc, int n, hipStream_t s);
 hipError_t lik_poll(LikCtx& lc, hipStream_t s, bool& all_done);
 // The poll of graph replays: lik_poll_word_launch queues (for capture at the end
-// of a run of CG iterations) a kernel that writes {all solves stopped, sequence
-// number + 1} to a pinned host word; the host reads the sequence number before
-// launching such a replay (lik_poll_word_seq) and waits for it to change
-// (lik_poll_word_wait, which spins on the word and falls back to the stream's
-// completion if the stream drains without a new word).
+// of a run of CG iterations) a kernel that writes {sequence number + 1, all
+// solves stopped, largest iteration count of the current solves} to a pinned
+// host word; the host reads the sequence number before launching such a replay
+// (lik_poll_word_seq) and waits for it to change (lik_poll_word_wait, which
+// spins on the word and falls back to the stream's completion if the stream
+// drains without a new word).
 hipError_t lik_poll_word_alloc(LikCtx& lc);   // before capture: no allocation while capturing
 hipError_t lik_poll_word_launch(LikCtx& lc, hipStream_t s);
 unsigned lik_poll_word_seq(const LikCtx& lc);
-hipError_t lik_poll_word_wait(LikCtx& lc, hipStream_t s, unsigned seq0, bool& all_done);
+hipError_t lik_poll_word_wait(LikCtx& lc, hipStream_t s, unsigned seq0, bool& all_done,
+                              int& max_iters);
 hipError_t lik_tail(LikCtx& lc, float2* S0, hipStream_t s);
 // RBMC: the white noise of every RBMC instance (host array of device pointers,
 // one per instance of the context; NULL for instances without RBMC): H^T e1 and

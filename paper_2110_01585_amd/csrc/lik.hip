@@ -1363,18 +1363,24 @@ hipError_t lik_poll(LikCtx& lc, hipStream_t s, bool& all_done) {
 }
 
 // CG poll word for graph replays: the last kernel of a captured run of CG
-// iterations writes to pinned host memory whether every instance's solve has
-// stopped (high half) next to a sequence number one above the one it finds
-// there (low half), so the host waits for the word to change instead of
-// copying the flags back and synchronising the stream.  One thread; the 64-bit
-// system-scope store makes both halves visible to the host at once.
+// iterations writes to pinned host memory a sequence number one above the one
+// it finds there (bits 0-31), whether every instance's solve has stopped (bit
+// 32) and the largest iteration count of the instances' current solves (bits
+// 33-62), so the host waits for the word to change instead of copying the flags
+// back and synchronising the stream.  One thread; the 64-bit system-scope store
+// makes all fields visible to the host at once.
 __global__ void k_cg_poll_word(const LikInst* __restrict__ inst, int nlik,
                                const InstState* __restrict__ st, long long* word) {
-  int done = 1;
-  for (int j = 0; j < nlik; ++j) done &= st[inst[j].inst].cg_done ? 1 : 0;
+  long long done = 1, iters = 0;
+  for (int j = 0; j < nlik; ++j) {
+    const InstState& s = st[inst[j].inst];
+    done &= s.cg_done ? 1 : 0;
+    iters = s.cg_it > iters ? s.cg_it : iters;
+  }
+  iters = iters < 0x3fffffff ? iters : 0x3fffffff;
   const long long w = __hip_atomic_load(word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
   const unsigned seq = (unsigned)w + 1u;
-  __hip_atomic_store(word, ((long long)done << 32) | (long long)seq, __ATOMIC_RELEASE,
+  __hip_atomic_store(word, (iters << 33) | (done << 32) | (long long)seq, __ATOMIC_RELEASE,
                      __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
@@ -1407,14 +1413,17 @@ unsigned lik_poll_word_seq(const LikCtx& lc) {
   return lc.poll_word ? (unsigned)__atomic_load_n(lc.poll_word, __ATOMIC_ACQUIRE) : 0u;
 }
 
-hipError_t lik_poll_word_wait(LikCtx& lc, hipStream_t s, unsigned seq0, bool& all_done) {
+hipError_t lik_poll_word_wait(LikCtx& lc, hipStream_t s, unsigned seq0, bool& all_done,
+                              int& max_iters) {
   all_done = true;
+  max_iters = 0;
   if (lc.nlik == 0) return hipSuccess;
   if (!lc.poll_word) return hipErrorInvalidValue;
   auto fresh = [&](bool& done) {
     const long long w = __atomic_load_n(lc.poll_word, __ATOMIC_ACQUIRE);
     if ((unsigned)w == seq0) return false;
-    done = (w >> 32) != 0;
+    done = ((w >> 32) & 1) != 0;
+    max_iters = (int)(w >> 33);
     return true;
   };
   for (unsigned spin = 1;; ++spin) {
