@@ -154,3 +154,31 @@ def test_hadamard_in_mixed_batch_graph_equals_direct():
               f"{sa[i]['lambda']:.6g} oracle {info['lam']:.6g}")
         assert e_mu <= MEAN_TOL and e_v <= VAR_TOL
         assert abs(sa[i]["lambda"] / info["lam"] - 1) <= 2e-4
+
+
+def test_sweeps_to_converged_match_oracle_hadamard():
+    """A 64^2 Hadamard CS instance (30 % of the Walsh coefficients, EM from
+    lambda = 1) needs about 1,900 sweeps to meet tol = 5e-6, and its
+    likelihood site moves by about a quarter of each sweep's change of the
+    marginals, so this case tells apart the two places the rule's change could
+    be measured from: the device solve must stop at the oracle's sweep (within
+    3, rounding near the threshold), with the same lambda and means."""
+    rng = syn.rng_for(77, 64)
+    p = syn.make_hadamard_cs(64, 64, 3, 0.01, 0.3, rng, sweeps=3000, em=True, lam0=1.0)
+    print(f"case {p.name} {p.shape} to convergence", flush=True)
+    ctx = Context([spec_from_synthetic(p)])
+    ctx.ep_tv_set_observation([observation_tensor(p, torch)])
+    ctx.ep_tv_set_option(N.OPT_GRAPH, 1)
+    rc, st = ctx.ep_tv_solve(3000, 5e-6, True)
+    mus, vs = ctx.marginals()
+    torch.cuda.synchronize()
+    mu = mus[0].cpu().numpy().astype(np.float64)
+    ctx.close()
+    mu_o, v_o, _, info = oep.solve(oep.problem_from_synthetic(f32_problem(p)), 3000, True, tol=5e-6)
+    s = st[0]
+    print(f"  device {s['sweeps']} sweeps, lambda {s['lambda']:.6g}; oracle {info['sweeps']} "
+          f"sweeps, lambda {info['lam']:.6g}")
+    assert s["converged"] and info["converged"]
+    assert abs(s["sweeps"] - info["sweeps"]) <= 3
+    assert abs(s["lambda"] / info["lam"] - 1) <= 2e-4
+    assert mean_err(mu, mu_o) <= MEAN_TOL
