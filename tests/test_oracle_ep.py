@@ -310,3 +310,35 @@ def test_first_sweep_order_reaches_the_same_fixed_point(kind, n, em):
     assert np.max(np.abs(v_a / v_b - 1)) <= 1e-9
     if em:
         assert abs(ia["lam"] / ib["lam"] - 1) <= 1e-9
+
+
+def test_convergence_rule_reference_marginal():
+    """The convergence rule's change is the one the colour-class updates make:
+    a sweep that updates the likelihood site records the marginal right after
+    that update, and the recorded history's dmu is measured from it; a sweep
+    that does not (identity operator, first cold sweep) measures from the
+    previous sweep's end.  Checked by recomputing both from the states."""
+    rng = syn.rng_for(95, 0)
+    p = syn.make_deconv(16, 12, 3, 0.05, 1.0, rng, lam0=2.0, sweeps=3, em=False)
+    pb = ep.problem_from_synthetic(p)
+    st = ep.init_cold(pb)
+    yrange = float(pb.y.max() - pb.y.min())
+    mu0, _ = ep.marginals(st)
+    ep.sweep(pb, st, 1, False)                 # first cold sweep: no likelihood update
+    assert st.mid is None
+    mu1, _ = ep.marginals(st)
+    ep.sweep(pb, st, 2, False)
+    assert st.mid is not None
+    mid_mu, _ = st.mid
+    mu2, _ = ep.marginals(st)
+    assert not np.allclose(mid_mu, mu1)         # the likelihood update moved the marginal
+    # solve() from the same start reports the same two changes
+    _, _, st2, info = ep.solve(ep.problem_from_synthetic(p), 2, False, tol=0.0, record=True)
+    h = st2.history
+    assert math.isclose(h[0]["dmu"], float(np.max(np.abs(mu1 - mu0))) / yrange, rel_tol=1e-12)
+    assert math.isclose(h[1]["dmu"], float(np.max(np.abs(mu2 - mid_mu))) / yrange, rel_tol=1e-12)
+    # an identity operator never records one
+    q = syn.make_denoise(10, 9, 3, 0.1, syn.rng_for(95, 1), lam0=3.0, sweeps=2, em=False)
+    sq = ep.init_cold(ep.problem_from_synthetic(q))
+    ep.sweep(ep.problem_from_synthetic(q), sq, 2, False)
+    assert sq.mid is None
