@@ -226,6 +226,7 @@ struct Graphs {
   hipGraphExec_t head[2]{};    // likelihood head + kCgPoll CG iterations
   hipGraphExec_t head_short[2]{};  // likelihood head + kCgHeadShort CG iterations
   hipGraphExec_t cg = nullptr; // kCgPoll CG iterations
+  hipGraphExec_t cg8 = nullptr, cg16 = nullptr;  // 2 and 4 times as many
   hipGraphExec_t tail[2]{};    // likelihood site + TV sweep + finalize (one sweep)
   hipGraphExec_t multi[2]{};   // kGraphSweeps whole sweeps (identity operators only)
 };
@@ -392,7 +393,7 @@ static int upload_tiles(ep_tv_ctx* c) {
 static void drop_graphs(ep_tv_ctx* c) {
   Graphs& g = c->g;
   hipGraphExec_t* all[] = {&g.head[0], &g.head[1], &g.head_short[0], &g.head_short[1], &g.cg,
-                           &g.tail[0], &g.tail[1], &g.multi[0], &g.multi[1]};
+                           &g.cg8, &g.cg16, &g.tail[0], &g.tail[1], &g.multi[0], &g.multi[1]};
   for (hipGraphExec_t* e : all)
     if (*e) {
       (void)hipGraphExecDestroy(*e);
@@ -745,6 +746,18 @@ static int build_graphs(ep_tv_ctx* c, int em, bool delta, double tol) {
       HIPCHK(c, lik_poll_word_launch(c->lik, s));
       return EP_TV_OK;
     });
+  if (rc == EP_TV_OK && c->any_lik)
+    rc = capture(c, &g.cg8, [&](hipStream_t s) -> int {
+      HIPCHK(c, lik_iterations(c->lik, 2 * kCgPoll, s));
+      HIPCHK(c, lik_poll_word_launch(c->lik, s));
+      return EP_TV_OK;
+    });
+  if (rc == EP_TV_OK && c->any_lik)
+    rc = capture(c, &g.cg16, [&](hipStream_t s) -> int {
+      HIPCHK(c, lik_iterations(c->lik, 4 * kCgPoll, s));
+      HIPCHK(c, lik_poll_word_launch(c->lik, s));
+      return EP_TV_OK;
+    });
   if (rc != EP_TV_OK) {
     drop_graphs(c);
     return rc;
@@ -773,9 +786,14 @@ static int graph_sweep(ep_tv_ctx* c) {
     int used = 0;
     HIPCHK(c, lik_poll_word_wait(c->lik, c->stream, seq, done, used));
     while (!done && iters < c->lik.max_iters) {
+      // as many iterations per replay as the previous sweep's solves still
+      // needed at this point (the counts change slowly from sweep to sweep),
+      // so long solves wait on fewer polls
+      const int ahead = c->cg_iters_prev - iters;
+      const int n = ahead >= 4 * kCgPoll ? 4 * kCgPoll : ahead >= 2 * kCgPoll ? 2 * kCgPoll : kCgPoll;
       seq = lik_poll_word_seq(c->lik);
-      HIPCHK(c, hipGraphLaunch(g.cg, c->stream));
-      iters += kCgPoll;
+      HIPCHK(c, hipGraphLaunch(n == 4 * kCgPoll ? g.cg16 : n == 2 * kCgPoll ? g.cg8 : g.cg, c->stream));
+      iters += n;
       HIPCHK(c, lik_poll_word_wait(c->lik, c->stream, seq, done, used));
     }
     c->cg_iters_prev = used;
