@@ -36,6 +36,9 @@ Workloads (synthetic, seeded; generators in synthetic.py):
               backward, Adam) on batches of 16 x 256^2 synthetic targets
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+       python bench.py --stream-probe   (the TV sweep's plane accesses with no arithmetic:
+                                         the rate its access pattern reaches on the device)
+       python bench.py --copy-probe     (a plain 1 GiB copy: rate, and the byte counters' scale)
 """
 from __future__ import annotations
 
