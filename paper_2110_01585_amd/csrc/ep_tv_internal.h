@@ -55,6 +55,7 @@ struct InstState {
   int xprev_valid, restart;            // restart: cold re-initialisation pending (host-set)
   double yscale;                       // max(range, max |.|) of the pixel-space observation
   int cold_restarts, xs_valid;         // xs_valid: the RBMC sample solutions hold the last solves
+  int pc_scaled;                       // this solve's circulant preconditioner is diagonally scaled
 };
 
 // FLAG_DIVERGED: the global mean after a likelihood-site update left

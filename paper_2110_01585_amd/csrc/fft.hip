@@ -347,6 +347,7 @@ struct RfftArgs {
   float* out;                // RF_INV: z (precondition) or q (product)
   const float* specT;        // eigenvalues of H^T H, transposed dense (W x H)
   float inv_xi, scale;
+  float diagA;               // diagonal of H^T H / xi (the scaled preconditioner's a_0)
   const InstState* st;
   InstState* st_w;           // RF_FWD update: block 0 records alpha
   int inst;
@@ -395,6 +396,7 @@ struct RfftRegs {
   float4 wa[STAGE == RF_FWD ? N4 : 1], wb[STAGE == RF_FWD ? N4 : 1];
   float4 xa[STAGE == RF_FWD ? N4 : 1], xb[STAGE == RF_FWD ? N4 : 1];
   float4 pa[STAGE == RF_FWD ? N4 : 1], pb[STAGE == RF_FWD ? N4 : 1];
+  float4 ca[STAGE == RF_FWD ? N4 : 1], cb[STAGE == RF_FWD ? N4 : 1];   // tau_c (scaled preconditioner)
   // RF_FILT: two complex values and their two eigenvalues
   float4 lv[STAGE == RF_FILT ? N2 : 1];
   float2 sp[STAGE == RF_FILT ? N2 : 1];
@@ -432,6 +434,9 @@ __global__ __launch_bounds__(256) void k_rfft(RfftArgs a) {
 
   const bool first = st.cg_it == 0;
   const bool upd = a.mode == RFM_PRECOND && a.update;
+  // diagonally scaled circulant S C^{-1} S, s_i^2 = (a_0 + d_bar) / (a_0 + tau_c,i),
+  // which gives the preconditioner A's diagonal (set per solve; uniform per launch)
+  const bool scaled = a.mode == RFM_PRECOND && st.pc_scaled != 0;
   // RF_FWD: the transformed plane v (r, or z for the new direction), the plane
   // w it is combined with (q for the update of r, p_in for p = z + beta p_in);
   // RF_INV: the plane e the result is dotted with (r, or p for q = result + tau_c p)
@@ -455,6 +460,7 @@ __global__ __launch_bounds__(256) void k_rfft(RfftArgs a) {
       for (int q = 0; q < N4; ++q) {
         const int i = 4 * ((int)threadIdx.x + 256 * q);
         R.va[q] = R.vb[q] = R.wa[q] = R.wb[q] = R.xa[q] = R.xb[q] = R.pa[q] = R.pb[q] = zero4;
+        R.ca[q] = R.cb[q] = zero4;
         if (i >= rows * L) continue;
         const long long p = plane(i), p1 = p + a.pitch;
         R.va[q] = *reinterpret_cast<const float4*>(vsrc + p);
@@ -468,6 +474,10 @@ __global__ __launch_bounds__(256) void k_rfft(RfftArgs a) {
           R.xb[q] = *reinterpret_cast<const float4*>(a.x + p1);
           R.pa[q] = *reinterpret_cast<const float4*>(a.p + p);
           R.pb[q] = *reinterpret_cast<const float4*>(a.p + p1);
+        }
+        if (scaled) {
+          R.ca[q] = *reinterpret_cast<const float4*>(a.tauc + p);
+          R.cb[q] = *reinterpret_cast<const float4*>(a.tauc + p1);
         }
       }
     } else if (STAGE == RF_FILT) {
@@ -550,6 +560,16 @@ __global__ __launch_bounds__(256) void k_rfft(RfftArgs a) {
           }
           *reinterpret_cast<float4*>(a.p + p) = make_float4(oa[0], oa[1], oa[2], oa[3]);
           *reinterpret_cast<float4*>(a.p + p1) = make_float4(ob[0], ob[1], ob[2], ob[3]);
+        }
+        if (scaled) {
+          const float a0 = a.diagA, num = a0 + (float)st.dbar;
+          const float ca4[4] = {R.ca[q].x, R.ca[q].y, R.ca[q].z, R.ca[q].w};
+          const float cb4[4] = {R.cb[q].x, R.cb[q].y, R.cb[q].z, R.cb[q].w};
+#pragma unroll
+          for (int k = 0; k < 4; ++k) {
+            oa[k] *= __builtin_sqrtf(num / (a0 + ca4[k]));
+            ob[k] *= __builtin_sqrtf(num / (a0 + cb4[k]));
+          }
         }
 #pragma unroll
         for (int k = 0; k < 4; ++k) X[pidx(i + k)] = make_float2(oa[k], ob[k]);
@@ -639,7 +659,7 @@ __global__ __launch_bounds__(256) void k_rfft(RfftArgs a) {
         const long long p = plane(i), p1 = p + a.pitch;
         ea[q] = *reinterpret_cast<const float4*>(esrc + p);
         eb[q] = *reinterpret_cast<const float4*>(esrc + p1);
-        if (a.mode != RFM_PRECOND) {
+        if (a.mode != RFM_PRECOND || scaled) {
           ta[q] = *reinterpret_cast<const float4*>(a.tauc + p);
           tb[q] = *reinterpret_cast<const float4*>(a.tauc + p1);
         }
@@ -661,6 +681,11 @@ __global__ __launch_bounds__(256) void k_rfft(RfftArgs a) {
           if (a.mode == RFM_PRECOND) {
             oa[k] = zz.x;
             ob[k] = zz.y;
+            if (scaled) {
+              const float a0 = a.diagA, num = a0 + (float)st.dbar;
+              oa[k] *= __builtin_sqrtf(num / (a0 + ua[k]));
+              ob[k] *= __builtin_sqrtf(num / (a0 + ub[k]));
+            }
             s0 += (double)va[k] * oa[k] + (double)vb[k] * ob[k];
             s1 += (double)va[k] * va[k] + (double)vb[k] * vb[k];
           } else {
@@ -1050,6 +1075,7 @@ hipError_t rfft_cg(LikCtx& lc, int mode, int update, hipStream_t s) {
     RfftArgs a;
     std::memset(&a, 0, sizeof(a));
     a.off = L.off; a.pitch = L.pitch; a.inv_xi = L.inv_xi; a.st = lc.d_st; a.st_w = lc.d_st;
+    a.diagA = L.diagA;
     a.inst = L.inst;
     a.ld = Wh; a.mode = mode; a.update = update;
     a.r = lc.planes[LP_R]; a.z = lc.planes[LP_Z]; a.tauc = lc.planes[LP_TAUC];

@@ -24,6 +24,10 @@ constexpr int kCgMaxIters = 50;
 constexpr double kCgTol = 1e-8;            // relative residual ||r|| / ||b||
 constexpr int kCgPoll = 4;                 // CG iterations between convergence checks (even)
 constexpr int kCgHeadShort = 2;            // CG iterations of the short head graph (even)
+// A blur instance's circulant preconditioner is diagonally scaled for a solve
+// whose predecessor needed more than this many iterations (far from the fixed
+// point, where the cavity precisions vary most and the scaling pays).
+constexpr int kCgScaleAbove = 10;
 
 inline bool fft_size_ok(int n) { return n >= 4 && n <= 4096 && (n & (n - 1)) == 0; }
 

@@ -234,6 +234,7 @@ __global__ __launch_bounds__(256) void k_lik_fin(LikArgs A, int stage) {
       }
       st.dbar = r0 / N;
       st.cg_bb = r1;
+      st.pc_scaled = (L.op == OP_BLUR && st.cg_last > kCgScaleAbove) ? 1 : 0;
       st.cg_it = 0;
       st.cg_done = L.op == OP_GAUSS ? 1 : 0;   // the dense Woodbury path replaces the CG
       st.xprev_valid = st.x_valid;   // prep has just kept the last solve's E
