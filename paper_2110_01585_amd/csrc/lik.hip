@@ -1368,20 +1368,40 @@ hipError_t lik_poll(LikCtx& lc, hipStream_t s, bool& all_done) {
 // it finds there (bits 0-31), whether every instance's solve has stopped (bit
 // 32) and the largest iteration count of the instances' current solves (bits
 // 33-62), so the host waits for the word to change instead of copying the flags
-// back and synchronising the stream.  One thread; the 64-bit system-scope store
-// makes all fields visible to the host at once.
-__global__ void k_cg_poll_word(const LikInst* __restrict__ inst, int nlik,
-                               const InstState* __restrict__ st, long long* word) {
-  long long done = 1, iters = 0;
-  for (int j = 0; j < nlik; ++j) {
+// back and synchronising the stream.  One block of 256 threads reduces the
+// instances' flags and counts (each thread a strided share, then the block);
+// thread 0's 64-bit system-scope store makes all fields visible to the host at
+// once.
+__global__ __launch_bounds__(256) void k_cg_poll_word(const LikInst* __restrict__ inst, int nlik,
+                                                      const InstState* __restrict__ st,
+                                                      long long* word) {
+  int done = 1, iters = 0;
+  for (int j = threadIdx.x; j < nlik; j += blockDim.x) {
     const InstState& s = st[inst[j].inst];
     done &= s.cg_done ? 1 : 0;
-    iters = s.cg_it > iters ? s.cg_it : iters;
+    iters = max(iters, s.cg_it);
   }
-  iters = iters < 0x3fffffff ? iters : 0x3fffffff;
+#pragma unroll
+  for (int off = kWave / 2; off >= 1; off >>= 1) {
+    done &= __shfl_xor(done, off, kWave);
+    iters = max(iters, __shfl_xor(iters, off, kWave));
+  }
+  __shared__ int wd[4], wi[4];
+  if (threadIdx.x % kWave == 0) {
+    wd[threadIdx.x / kWave] = done;
+    wi[threadIdx.x / kWave] = iters;
+  }
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  long long all = 1, most = 0;
+  for (int k = 0; k < 4; ++k) {
+    all &= wd[k];
+    most = wi[k] > most ? wi[k] : most;
+  }
+  most = most < 0x3fffffff ? most : 0x3fffffff;
   const long long w = __hip_atomic_load(word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
   const unsigned seq = (unsigned)w + 1u;
-  __hip_atomic_store(word, (iters << 33) | (done << 32) | (long long)seq, __ATOMIC_RELEASE,
+  __hip_atomic_store(word, (most << 33) | (all << 32) | (long long)seq, __ATOMIC_RELEASE,
                      __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
@@ -1405,7 +1425,7 @@ hipError_t lik_poll_word_alloc(LikCtx& lc) {
 hipError_t lik_poll_word_launch(LikCtx& lc, hipStream_t s) {
   if (lc.nlik == 0) return hipSuccess;
   if (!lc.poll_word_dev) return hipErrorInvalidValue;   // lik_poll_word_alloc first
-  hipLaunchKernelGGL(k_cg_poll_word, dim3(1), dim3(1), 0, s, lc.d_inst, lc.nlik,
+  hipLaunchKernelGGL(k_cg_poll_word, dim3(1), dim3(256), 0, s, lc.d_inst, lc.nlik,
                      (const InstState*)lc.d_st, lc.poll_word_dev);
   return hipGetLastError();
 }
